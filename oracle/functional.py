@@ -1,0 +1,268 @@
+"""Oracle: the nonlocal correlation energy E_c^nl and potential v_nl of a
+density on a periodic orthorhombic grid, plain FP64 NumPy/SciPy.
+
+TEST INFRASTRUCTURE.  Only ``tests/``, the smoke check and the CPU-baseline
+leg of the benchmark may import this module.  It shares no code with the
+HIP product path and never imports it.
+
+The steps follow the paper's order.  Readings of points the paper leaves
+open are marked READING; each has a line in the design notes.
+
+ O1  gradient of n by spectral differentiation (the paper uses finite
+     differences for grad n; READING: spectral, with the Nyquist
+     multiplier set to zero so the derivative matrix is real antisymmetric)
+ O2  LDA correlation energy per electron (READING: Perdew-Wang 1992,
+     spin-unpolarised)
+ O3  q0(n, |grad n|) (READING: the Dion et al. form
+     q0 = k_F - (4 pi/3) eps_c + (-Z_ab/36) |grad n|^2 / (k_F n^2), Z_ab = -0.8491)
+ O4  saturation q0 <- h(q0, q_c), Eqs. (qsat)/(Sat)
+ O5  cubic-spline cardinal functions p_a(q) on the q mesh, Eq. (fofx) and
+     the text after it (READING: natural end conditions; below q_1 the
+     linear continuation of the spline)
+ O6  theta_a(r) = n(r) p_a(q0(r)), after Eq. (Eoffk); points with
+     n < n_min contribute nothing (READING)
+ O7  forward transforms c_a(G) = FFT(theta_a)/N
+ O8  u_a(G) = sum_b phi_ab(|G|) c_b(G), phi_ab(|G|) by a natural cubic
+     spline of the radial k table
+ O9  E_k = (Omega/2) sum_G w_G sum_a Re(c_a(G)^* u_a(G)), Eq. (Eoffk) with
+     the complex conjugate (READING), w_G = 1 on the k3 = 0 and k3 = N3/2
+     planes of the half spectrum and 2 elsewhere
+ O10 u_a(r_i) = sum_G u_a(G) exp(i G.r_i), Eqs. (epsilon)/(epsofk):
+     u_ai = (1/dOmega) dE_k/dtheta_ai
+ O11 Delta E = dOmega sum_i C_s n_i^2 / q0_i^3, Eqs. (DEnl)/(Depsnl)
+ O12 local derivatives dtheta/dn, dtheta/dgrad n (and of e_Delta)
+ O13 v_loc = sum_a u_a dtheta_a/dn + de/dn;  w = sum_a u_a dtheta_a/dgrad n + de/dgrad n
+ O14 v = v_loc - sum_c D_c w_c, Eq. (Vi): the sum over j of
+     w_j . d(grad n_j)/dn_i is the transpose of the (antisymmetric)
+     derivative operator applied to w.
+"""
+from __future__ import annotations
+
+import numpy as np
+from scipy.interpolate import CubicSpline
+
+# Perdew-Wang 1992 paramagnetic correlation (READING for the LDA of q0)
+PW_A, PW_ALPHA1 = 0.031091, 0.21370
+PW_BETA = (7.5957, 3.5876, 1.6382, 0.49294)
+Z_AB = -0.8491
+N_MIN = 1e-30
+
+
+# ---------------------------------------------------------------- O2
+def pw92(n):
+    """eps_c(n) and d eps_c / dn (Hartree)."""
+    n = np.asarray(n, dtype=np.float64)
+    rs = (3.0 / (4.0 * np.pi * n)) ** (1.0 / 3.0)
+    b1, b2, b3, b4 = PW_BETA
+    srs = np.sqrt(rs)
+    P = b1 * srs + b2 * rs + b3 * rs * srs + b4 * rs * rs
+    dP = 0.5 * b1 / srs + b2 + 1.5 * b3 * srs + 2.0 * b4 * rs
+    L = np.log1p(1.0 / (2.0 * PW_A * P))
+    eps = -2.0 * PW_A * (1.0 + PW_ALPHA1 * rs) * L
+    deps_drs = (-2.0 * PW_A * PW_ALPHA1 * L
+                + 2.0 * PW_A * (1.0 + PW_ALPHA1 * rs) * dP / (P * (2.0 * PW_A * P + 1.0)))
+    drs_dn = -rs / (3.0 * n)
+    return eps, deps_drs * drs_dn
+
+
+# ---------------------------------------------------------------- O3
+def q0_unsaturated(n, sigma):
+    """q0 and its partials with respect to n and sigma = |grad n|^2."""
+    n = np.asarray(n, dtype=np.float64)
+    sigma = np.asarray(sigma, dtype=np.float64)
+    kf = (3.0 * np.pi * np.pi * n) ** (1.0 / 3.0)
+    eps, deps = pw92(n)
+    zg = -Z_AB / 36.0
+    q = kf - (4.0 * np.pi / 3.0) * eps + zg * sigma / (kf * n * n)
+    dq_dn = kf / (3.0 * n) - (4.0 * np.pi / 3.0) * deps - (7.0 / 3.0) * zg * sigma / (kf * n ** 3)
+    dq_ds = zg / (kf * n * n)
+    return q, dq_dn, dq_ds
+
+
+# ---------------------------------------------------------------- O4
+def saturate(q, qc, mc):
+    """h(q, q_c) of Eq. (Sat) and dh/dq."""
+    y = np.asarray(q, dtype=np.float64) / qc
+    S = np.zeros_like(y)
+    dS = np.zeros_like(y)   # dS/dy = sum_{m=0}^{mc-1} y^m
+    ym = np.ones_like(y)
+    for m in range(1, mc + 1):
+        dS += ym
+        ym = ym * y
+        S += ym / m
+    big = S > 700.0
+    e = np.exp(-np.where(big, 0.0, S))
+    h = np.where(big, qc, qc * (1.0 - e))
+    dh = np.where(big, 0.0, e * dS)
+    return h, dh
+
+
+# ---------------------------------------------------------------- O5
+class CardinalSplines:
+    """p_a(q), p'_a(q): the natural cubic spline through unit data e_a."""
+
+    def __init__(self, qmesh):
+        self.q = np.asarray(qmesh, dtype=np.float64)
+        self.nq = self.q.size
+        self._spl = CubicSpline(self.q, np.eye(self.nq), bc_type="natural", extrapolate=True)
+        self._d1 = self._spl.derivative(1)
+        self._p1 = self._spl(self.q[0])
+        self._dp1 = self._d1(self.q[0])
+
+    def __call__(self, q):
+        """(p [nq, ...], dp/dq [nq, ...]) for q of any shape."""
+        q = np.asarray(q, dtype=np.float64)
+        flat = q.ravel()
+        p = self._spl(flat)              # [npts, nq]
+        dp = self._d1(flat)
+        low = flat < self.q[0]
+        if np.any(low):                  # linear continuation below q_1
+            p[low] = self._p1[None, :] + (flat[low] - self.q[0])[:, None] * self._dp1[None, :]
+            dp[low] = self._dp1[None, :]
+        return (p.T.reshape((self.nq,) + q.shape), dp.T.reshape((self.nq,) + q.shape))
+
+
+# ---------------------------------------------------------------- O1 / O14
+def wavevectors(shape, cell, half=True):
+    """G_c on the (half) FFT grid with the Nyquist components set to zero."""
+    gs = []
+    for c in range(3):
+        npts, length = shape[c], cell[c]
+        if c == 2 and half:
+            m = np.arange(npts // 2 + 1, dtype=np.float64)
+        else:
+            m = np.fft.fftfreq(npts, d=1.0 / npts)
+        if npts % 2 == 0:
+            m[np.abs(m) == npts // 2] = 0.0
+        gs.append(2.0 * np.pi * m / length)
+    return np.meshgrid(*gs, indexing="ij")
+
+
+def gradient(n, cell):
+    """grad n by spectral differentiation (3 x shape)."""
+    shape = n.shape
+    nh = np.fft.rfftn(n)
+    g = wavevectors(shape, cell)
+    return np.stack([np.fft.irfftn(1j * g[c] * nh, s=shape, axes=(0, 1, 2)) for c in range(3)])
+
+
+def divergence(w, cell):
+    """sum_c D_c w_c with the same derivative operator as ``gradient``."""
+    shape = w.shape[1:]
+    g = wavevectors(shape, cell)
+    acc = np.zeros(tuple(shape[:2]) + (shape[2] // 2 + 1,), dtype=np.complex128)
+    for c in range(3):
+        acc += 1j * g[c] * np.fft.rfftn(w[c])
+    return np.fft.irfftn(acc, s=shape, axes=(0, 1, 2))
+
+
+def gmod_half(shape, cell):
+    """|G| on the half spectrum (Nyquist components kept: the kernel depends
+    only on |G| and both signs of a Nyquist component give the same |G|)."""
+    gs = []
+    for c in range(3):
+        npts, length = shape[c], cell[c]
+        m = np.arange(npts // 2 + 1, dtype=np.float64) if c == 2 else np.fft.fftfreq(npts, d=1.0 / npts)
+        gs.append(2.0 * np.pi * m / length)
+    g1, g2, g3 = np.meshgrid(*gs, indexing="ij")
+    return np.sqrt(g1 * g1 + g2 * g2 + g3 * g3)
+
+
+def half_weights(shape):
+    """w_G of the half spectrum: 1 on k3 = 0 and (N3 even) k3 = N3/2, else 2."""
+    n3h = shape[2] // 2 + 1
+    w = np.full(n3h, 2.0)
+    w[0] = 1.0
+    if shape[2] % 2 == 0:
+        w[-1] = 1.0
+    return w
+
+
+# ---------------------------------------------------------------- O5/O6/O12
+def theta_fields(n, grad, table, n_min=N_MIN):
+    """theta_a, dtheta_a/dn, the scalar g_a with dtheta_a/dgrad n = g_a grad n,
+    and e_Delta with its derivatives; every local quantity of the method."""
+    n = np.asarray(n, dtype=np.float64)
+    sigma = np.sum(grad * grad, axis=0)
+    ok = n >= n_min
+    ns = np.where(ok, n, 1.0)
+    q_raw, dq_dn, dq_ds = q0_unsaturated(ns, np.where(ok, sigma, 0.0))
+    q0, Q = saturate(q_raw, table["qc"], int(table.get("mc", 12)))
+    spl = CardinalSplines(table["qmesh"])
+    p, dp = spl(q0)
+    theta = ns * p
+    dtheta_dn = p + ns * dp * Q * dq_dn
+    g = 2.0 * ns * dp * Q * dq_ds      # dtheta_a/dgrad n = g_a * grad n
+    cs = table["c_soft"]
+    e_delta = cs * ns * ns / q0 ** 3
+    de_dn = 2.0 * cs * ns / q0 ** 3 - 3.0 * cs * ns * ns / q0 ** 4 * Q * dq_dn
+    ge = -6.0 * cs * ns * ns / q0 ** 4 * Q * dq_ds
+    z = ~ok
+    for arr in (theta, dtheta_dn, g):
+        arr[:, z] = 0.0
+    for arr in (e_delta, de_dn, ge):
+        arr[z] = 0.0
+    return dict(q0=np.where(ok, q0, 0.0), theta=theta, dtheta_dn=dtheta_dn, g=g,
+                e_delta=e_delta, de_dn=de_dn, ge=ge)
+
+
+# ---------------------------------------------------------------- O8
+_spline_cache: dict = {}
+
+
+def _table_spline(table):
+    """Natural cubic spline in k of every (a, b) column of the radial table."""
+    key = id(table["phi"])
+    hit = _spline_cache.get(key)
+    if hit is None or hit[0] is not table["phi"]:
+        nq, nk = table["phi"].shape[0], table["phi"].shape[2]
+        k = np.arange(nk) * table["dk"]
+        spl = CubicSpline(k, table["phi"].reshape(nq * nq, nk).T, bc_type="natural")
+        hit = (table["phi"], spl, k[-1])
+        _spline_cache.clear()
+        _spline_cache[key] = hit
+    return hit[1], hit[2]
+
+
+def kernel_at(gmod, table):
+    """phi_ab(|G|) [..., nq, nq] by a natural cubic spline of the radial table,
+    evaluated once per distinct |G| value."""
+    nq = table["phi"].shape[0]
+    spl, kmax = _table_spline(table)
+    if gmod.max() > kmax:
+        raise ValueError("|G| beyond the radial kernel table")
+    uniq, inv = np.unique(gmod.ravel(), return_inverse=True)
+    vals = spl(uniq).reshape(uniq.size, nq, nq)
+    return vals, inv.reshape(gmod.shape)
+
+
+# ---------------------------------------------------------------- O1..O14
+def energy_potential(n, cell, table, n_min=N_MIN, return_parts=False):
+    """(E_k, Delta E, v) for the density n [N1, N2, N3] in the cell (bohr)."""
+    n = np.asarray(n, dtype=np.float64)
+    shape = n.shape
+    N = n.size
+    omega = float(np.prod(cell))
+    dvol = omega / N
+    grad = gradient(n, cell)                                   # O1
+    loc = theta_fields(n, grad, table, n_min)                  # O2-O6, O12
+    theta = loc["theta"]
+    nq = theta.shape[0]
+    chat = np.stack([np.fft.rfftn(theta[a]) for a in range(nq)]) / N     # O7
+    vals, shell = kernel_at(gmod_half(shape, cell), table)
+    uhat = np.zeros_like(chat)
+    for a in range(nq):                                        # O8
+        for b in range(nq):
+            uhat[a] += vals[:, a, b][shell] * chat[b]
+    w = half_weights(shape)
+    ek = 0.5 * omega * np.sum(w * np.sum(np.real(np.conj(chat) * uhat), axis=0))   # O9
+    u = np.stack([np.fft.irfftn(uhat[a], s=shape, axes=(0, 1, 2)) * N for a in range(nq)])       # O10
+    de = dvol * np.sum(loc["e_delta"])                         # O11
+    v_loc = np.sum(u * loc["dtheta_dn"], axis=0) + loc["de_dn"]                  # O13
+    gsc = np.sum(u * loc["g"], axis=0) + loc["ge"]
+    wvec = gsc[None] * grad
+    v = v_loc - divergence(wvec, cell)                         # O14
+    if return_parts:
+        return dict(E_k=ek, dE=de, v=v, u=u, chat=chat, uhat=uhat, grad=grad, v_loc=v_loc,
+                    w=wvec, **loc)
+    return ek, de, v
