@@ -1,0 +1,118 @@
+/*
+ * vdwnl.h -- C ABI of libvdwnl: the nonlocal correlation energy E_c^nl and
+ * potential v_nl of the van der Waals density functional, evaluated with the
+ * factorised kernel and FFTs of Roman-Perez and Soler (arXiv:0812.0244) on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Following the paper's statement of the problem (the paragraph after
+ * Eq. (epsofk)), the library accepts the density n(r_i) on a uniform periodic
+ * real-space grid and returns E_c^nl and v_nl(r_i) on the same grid.
+ *
+ * Conventions
+ *  - Hartree atomic units (bohr, Hartree).
+ *  - Grids are orthorhombic: cell lengths L1, L2, L3 along the three axes;
+ *    arrays are C order [N1][N2][N3] (N3 fastest); r_i = (i1 L1/N1, i2 L2/N2,
+ *    i3 L3/N3).
+ *  - Precision 32 or 64 selects the arithmetic of every device array and
+ *    kernel (float / double); global reductions are always FP64.
+ *  - Every function returns VDWNL_OK (0) or a negative error code; nothing
+ *    throws across the ABI.  vdwnl_strerror() names a code and
+ *    vdwnl_last_error() gives the context's last message.
+ *  - A context is not thread safe: use it from one host thread and one stream
+ *    at a time.  Device pointers passed in are owned by the caller; the
+ *    library owns its context and all workspace.
+ */
+#ifndef VDWNL_H
+#define VDWNL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    VDWNL_OK = 0,
+    VDWNL_E_ARG = -1,               /* null pointer, bad enum, non-positive size */
+    VDWNL_E_UNSUPPORTED_SIZE = -2,  /* grid edge with a prime factor > 5, or outside the limits */
+    VDWNL_E_NOMEM = -3,             /* device or host allocation failed */
+    VDWNL_E_TABLE = -4,             /* kernel table invalid (mesh, symmetry, size) */
+    VDWNL_E_KRANGE = -5,            /* radial table does not reach max |G| of a grid */
+    VDWNL_E_STATE = -6,             /* grid or table missing, or no device */
+    VDWNL_E_HIP = -7,               /* a HIP runtime call failed */
+    VDWNL_E_BAD_DENSITY = -8        /* reserved */
+};
+
+typedef struct vdwnl_ctx vdwnl_ctx;
+
+/* Create a context on HIP device `device`.  device < 0 creates a host-only
+ * context: every validation and planning step runs, nothing touches a GPU,
+ * and the evaluation calls return VDWNL_E_STATE. */
+int vdwnl_create(vdwnl_ctx **out, int device);
+
+/* Free the context and all its device memory. */
+int vdwnl_destroy(vdwnl_ctx *ctx);
+
+const char *vdwnl_strerror(int code);
+const char *vdwnl_last_error(const vdwnl_ctx *ctx);
+
+/* Plan one grid (replaces any previous plan).
+ *   shape[3]   N1, N2, N3 >= 4, each a product of 2, 3 and 5;
+ *              N1 <= 204 and N3 <= 340 (LDS tile limits)
+ *   cell[3]    orthorhombic cell lengths, bohr, > 0
+ *   grad_mode  0: grad n by spectral differentiation, the Nyquist multiplier
+ *              set to zero (the paper uses finite differences, the same role;
+ *              1 is reserved for that variant)
+ *   precision  32 or 64
+ * Allocates all device workspace; the evaluation calls allocate nothing. */
+int vdwnl_set_grid(vdwnl_ctx *ctx, const int32_t shape[3], const double cell[3],
+                   int32_t grad_mode, int32_t precision);
+
+/* Plan a batch of nb independent grids evaluated together (same rules as
+ * vdwnl_set_grid for each; shapes[nb][3], cells[nb][3]). */
+int vdwnl_set_grids(vdwnl_ctx *ctx, int32_t nb, const int32_t *shapes, const double *cells,
+                    int32_t grad_mode, int32_t precision);
+
+/* The kernel of the factorisation, Eq. (phi), in k space (the radial table
+ * described after Eq. (Eoffk)), and the parameters of q0:
+ *   nq        number of interpolation points q_a (20 is the supported value)
+ *   qmesh     [nq] strictly increasing, qmesh[nq-1] == q_c (host pointer)
+ *   q_c, m_c  saturation of Eq. (Sat)
+ *   nk, dk    radial mesh k_j = j dk, j < nk
+ *   phi       [nq][nq][nk] host array, phi_ab(k_j), symmetric in (a, b)
+ *   c_soft    C_s of the local correction, Eqs. (DEnl)/(Depsnl):
+ *             Delta E = Int n^2 C_s / q0^3
+ * The arrays are copied; the caller keeps ownership.  phi_ab(|G|) is taken
+ * from the natural cubic spline through phi_ab(k_j). */
+int vdwnl_set_kernel_table(vdwnl_ctx *ctx, int32_t nq, const double *qmesh, double q_c,
+                           int32_t m_c, int32_t nk, double dk, const double *phi,
+                           double c_soft);
+
+/* E_c^nl and v_nl of one density (the planned grid).
+ *   n_dev   device array [N1][N2][N3] of the planned precision (read only)
+ *   v_dev   device array of the same shape, receives v_nl (Hartree)
+ *   E_out   host double[2]: E_k (the FFT part, Eq. Eoffk) and Delta E (the
+ *           local correction, Eq. DEnl); E_c^nl = E_out[0] + E_out[1]
+ *   stream  hipStream_t to run on (0: the null stream); the call returns
+ *           after the stream has finished the evaluation. */
+int vdwnl_energy_potential(vdwnl_ctx *ctx, const void *n_dev, void *v_dev, double *E_out,
+                           void *stream);
+
+/* The planned batch: n_ptrs[nb], v_ptrs[nb] device pointers, E_out[nb][2]. */
+int vdwnl_energy_potential_batched(vdwnl_ctx *ctx, int32_t nb, const void *const *n_ptrs,
+                                   void *const *v_ptrs, double *E_out, void *stream);
+
+/* Copy an internal per-grid field of the last evaluation of grid `inst` to
+ * the device buffer dst (for parity probes): which = 0: grad n [3][N];
+ * 1: v_loc [N] (the local part of v, before the gradient term).  Arrays in
+ * the planned precision. */
+int vdwnl_debug_field(vdwnl_ctx *ctx, int32_t inst, int32_t which, void *dst, void *stream);
+
+/* Number of planned grids and the bytes of device workspace held. */
+int vdwnl_info(const vdwnl_ctx *ctx, int32_t *n_grids, int64_t *workspace_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VDWNL_H */

@@ -1,0 +1,148 @@
+"""ctypes binding of libvdwnl.so: argument marshalling only.
+
+Every step of the evaluation runs in the HIP kernels of the library.  The
+binding fails loudly when the library has not been built; there is no
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_build", "libvdwnl.so")
+
+_i32 = ctypes.c_int32
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int32)
+_vp = ctypes.c_void_p
+
+# name -> (restype, argtypes); every symbol that include/vdwnl.h declares
+SIGNATURES = {
+    "vdwnl_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int]),
+    "vdwnl_destroy": (ctypes.c_int, [_vp]),
+    "vdwnl_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "vdwnl_last_error": (ctypes.c_char_p, [_vp]),
+    "vdwnl_set_grid": (ctypes.c_int, [_vp, _ip, _dp, _i32, _i32]),
+    "vdwnl_set_grids": (ctypes.c_int, [_vp, _i32, _ip, _dp, _i32, _i32]),
+    "vdwnl_set_kernel_table": (ctypes.c_int, [_vp, _i32, _dp, ctypes.c_double, _i32, _i32,
+                                              ctypes.c_double, _dp, ctypes.c_double]),
+    "vdwnl_energy_potential": (ctypes.c_int, [_vp, _vp, _vp, _dp, _vp]),
+    "vdwnl_energy_potential_batched": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(_vp),
+                                                      ctypes.POINTER(_vp), _dp, _vp]),
+    "vdwnl_debug_field": (ctypes.c_int, [_vp, _i32, _i32, _vp, _vp]),
+    "vdwnl_info": (ctypes.c_int, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(ctypes.c_int64)]),
+}
+
+_lib = None
+
+
+class VdwNlError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (_lib.vdwnl_strerror(code).decode() if _lib else "error", code, msg))
+        self.code = code
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libvdwnl.so; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        # One HIP runtime per process: when torch is present its runtime
+        # (same soname) must be loaded first, so the library binds to it.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
+        if not os.path.exists(path):
+            raise RuntimeError("libvdwnl.so not built (%s); run __graft_entry__.build()" % path)
+        lib = ctypes.CDLL(path)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _as_ptr(a, ct):
+    return a.ctypes.data_as(ctypes.POINTER(ct))
+
+
+class VdwNl:
+    """One library context (same names as the C functions, without prefix)."""
+
+    def __init__(self, device: int = 0):
+        self.lib = load_library()
+        h = _vp()
+        rc = self.lib.vdwnl_create(ctypes.byref(h), int(device))
+        if rc != 0:
+            raise VdwNlError(rc, "vdwnl_create(device=%d): %s" % (device, self.lib.vdwnl_last_error(None).decode()))
+        self.h = h
+        self.ngrids = 0
+        self.precision = None
+
+    def _check(self, rc, what):
+        if rc != 0:
+            raise VdwNlError(rc, "%s: %s" % (what, self.lib.vdwnl_last_error(self.h).decode()))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.vdwnl_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_grid(self, shape, cell, grad_mode: int = 0, precision: int = 32):
+        s = np.ascontiguousarray(shape, dtype=np.int32)
+        c = np.ascontiguousarray(cell, dtype=np.float64)
+        self._check(self.lib.vdwnl_set_grid(self.h, _as_ptr(s, ctypes.c_int32), _as_ptr(c, ctypes.c_double),
+                                            grad_mode, precision), "set_grid")
+        self.ngrids, self.precision = 1, precision
+
+    def set_grids(self, shapes, cells, grad_mode: int = 0, precision: int = 32):
+        s = np.ascontiguousarray(shapes, dtype=np.int32).reshape(-1, 3)
+        c = np.ascontiguousarray(cells, dtype=np.float64).reshape(-1, 3)
+        self._check(self.lib.vdwnl_set_grids(self.h, len(s), _as_ptr(s, ctypes.c_int32),
+                                             _as_ptr(c, ctypes.c_double), grad_mode, precision), "set_grids")
+        self.ngrids, self.precision = len(s), precision
+
+    def set_kernel_table(self, qmesh, q_c, m_c, dk, phi, c_soft):
+        q = np.ascontiguousarray(qmesh, dtype=np.float64)
+        p = np.ascontiguousarray(phi, dtype=np.float64)
+        nq, nk = q.size, p.shape[-1]
+        if p.shape != (nq, nq, nk):
+            raise ValueError("phi must be [nq, nq, nk]")
+        self._check(self.lib.vdwnl_set_kernel_table(self.h, nq, _as_ptr(q, ctypes.c_double), float(q_c), int(m_c),
+                                                    nk, float(dk), _as_ptr(p, ctypes.c_double), float(c_soft)),
+                    "set_kernel_table")
+
+    def energy_potential(self, n_ptr: int, v_ptr: int, stream: int = 0):
+        """Device pointers in, (E_k, Delta E) out; v written in place."""
+        E = np.zeros(2)
+        self._check(self.lib.vdwnl_energy_potential(self.h, _vp(n_ptr), _vp(v_ptr), _as_ptr(E, ctypes.c_double),
+                                                    _vp(stream)), "energy_potential")
+        return float(E[0]), float(E[1])
+
+    def energy_potential_batched(self, n_ptrs, v_ptrs, stream: int = 0):
+        nb = len(n_ptrs)
+        na = (_vp * nb)(*[_vp(p) for p in n_ptrs])
+        va = (_vp * nb)(*[_vp(p) for p in v_ptrs])
+        E = np.zeros((nb, 2))
+        self._check(self.lib.vdwnl_energy_potential_batched(self.h, nb, na, va, _as_ptr(E, ctypes.c_double),
+                                                            _vp(stream)), "energy_potential_batched")
+        return E
+
+    def debug_field(self, inst: int, which: int, dst_ptr: int, stream: int = 0):
+        self._check(self.lib.vdwnl_debug_field(self.h, inst, which, _vp(dst_ptr), _vp(stream)), "debug_field")
+
+    def info(self):
+        n = _i32()
+        b = ctypes.c_int64()
+        self._check(self.lib.vdwnl_info(self.h, ctypes.byref(n), ctypes.byref(b)), "info")
+        return n.value, b.value

@@ -1,0 +1,623 @@
+// Host side of libvdwnl: contexts, argument checks, planning and the C ABI.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/vdwnl.h"
+#include "common.hpp"
+
+namespace vdwnl {
+
+// ---------------------------------------------------------------- planning helpers
+
+static bool radix_plan(int n, FftPlan &p) {
+    p.n = n;
+    p.nstage = 0;
+    int m = n;
+    // radix-8 passes first, then 4 / 2, then 3 and 5
+    while (m % 8 == 0 && m > 1) { p.radix[p.nstage++] = 8; m /= 8; }
+    while (m % 4 == 0) { p.radix[p.nstage++] = 4; m /= 4; }
+    while (m % 2 == 0) { p.radix[p.nstage++] = 2; m /= 2; }
+    while (m % 5 == 0) { p.radix[p.nstage++] = 5; m /= 5; }
+    while (m % 3 == 0) { p.radix[p.nstage++] = 3; m /= 3; }
+    return m == 1 && p.nstage <= kMaxStages;
+}
+
+// Second derivatives of the natural cubic spline through y[j] on the nodes
+// x[j] (Thomas algorithm for the tridiagonal continuity equations).
+static void natural_spline_d2(const double *x, const double *y, int n, double *d2) {
+    std::vector<double> c(n, 0.0), r(n, 0.0);
+    d2[0] = d2[n - 1] = 0.0;
+    if (n < 3) { for (int i = 0; i < n; ++i) d2[i] = 0.0; return; }
+    // rows 1..n-2: h_{j-1} M_{j-1} + 2 (h_{j-1} + h_j) M_j + h_j M_{j+1} = rhs_j
+    double cprev = 0.0, rprev = 0.0;
+    for (int j = 1; j < n - 1; ++j) {
+        const double hl = x[j] - x[j - 1], hr = x[j + 1] - x[j];
+        const double rhs = 6.0 * ((y[j + 1] - y[j]) / hr - (y[j] - y[j - 1]) / hl);
+        const double diag = 2.0 * (hl + hr) - hl * cprev;
+        c[j] = hr / diag;
+        r[j] = (rhs - hl * rprev) / diag;
+        cprev = c[j];
+        rprev = r[j];
+    }
+    d2[n - 2] = r[n - 2];
+    for (int j = n - 3; j >= 1; --j) d2[j] = r[j] - c[j] * d2[j + 1];
+}
+
+struct Shells {
+    std::vector<int> map;       // [h1][h2][n3h]
+    std::vector<double> gmod;   // |G| per shell
+    double gmax = 0.0;
+};
+
+static Shells build_shells(const int s[3], const double cell[3]) {
+    Shells sh;
+    const int h1 = s[0] / 2 + 1, h2 = s[1] / 2 + 1, n3h = s[2] / 2 + 1;
+    const double g1 = 2.0 * M_PI / cell[0], g2 = 2.0 * M_PI / cell[1], g3 = 2.0 * M_PI / cell[2];
+    std::vector<double> key((size_t)h1 * h2 * n3h);
+    for (int a = 0; a < h1; ++a)
+        for (int b = 0; b < h2; ++b)
+            for (int c = 0; c < n3h; ++c) {
+                const double x = g1 * a, y = g2 * b, z = g3 * c;
+                key[((size_t)a * h2 + b) * n3h + c] = x * x + y * y + z * z;
+            }
+    std::vector<double> u(key);
+    std::sort(u.begin(), u.end());
+    u.erase(std::unique(u.begin(), u.end()), u.end());
+    sh.map.resize(key.size());
+    for (size_t i = 0; i < key.size(); ++i)
+        sh.map[i] = (int)(std::lower_bound(u.begin(), u.end(), key[i]) - u.begin());
+    sh.gmod.resize(u.size());
+    for (size_t i = 0; i < u.size(); ++i) sh.gmod[i] = std::sqrt(u[i]);
+    sh.gmax = sh.gmod.back();
+    return sh;
+}
+
+struct Grid {
+    int s[3];
+    double cell[3];
+    FftPlan p1, p2, p3;
+    int bmain;               // rows per theta / assemble tile
+    int k3main, k3aux;       // k3 per fused axis-1 tile (20 comps), per grad/div tile
+    int wy20, wy3, wy1;      // axis-2 tile widths
+    int shell_key;           // index into Ctx::shells
+    size_t off_grad, off_vloc, off_spec, off_spec3, off_spec1, off_map, off_tab, off_ek, off_de;
+    int n_ek, n_de;
+    size_t npts() const { return (size_t)s[0] * s[1] * s[2]; }
+    size_t nhalf() const { return (size_t)s[0] * s[1] * (s[2] / 2 + 1); }
+};
+
+}  // namespace vdwnl
+
+using namespace vdwnl;
+
+struct vdwnl_ctx {
+    int device = -1;
+    int precision = 32;
+    int grad_mode = 0;
+    std::string err;
+    // plan
+    std::vector<Grid> grids;
+    std::vector<Shells> shells;
+    std::vector<std::pair<std::vector<double>, int>> shell_keys;   // (shape, cell) -> shells index
+    bool have_grid = false;
+    // table
+    bool have_table = false;
+    int nq = 0, mc = 0, nk = 0;
+    double qc = 0, dk = 0, cs = 0;
+    std::vector<double> qmesh, phi, d2;   // phi, d2 packed [pair][nk]
+    Consts consts;
+    // device state
+    bool device_ready = false;            // tables built for the current (grid, table)
+    void *work = nullptr;
+    size_t work_bytes = 0;
+    std::vector<size_t> tab_off;          // per shells entry: offset of map and table
+    std::vector<size_t> map_off;
+    InstDev *d_inst = nullptr;
+    InstDev *h_inst = nullptr;            // pinned
+    Tile *d_tiles = nullptr;
+    int kind_off[KIND_COUNT] = {0}, kind_cnt[KIND_COUNT] = {0};
+    size_t kind_lds[KIND_COUNT] = {0};
+    void *d_tw = nullptr;
+    Consts *d_consts = nullptr;
+    double *d_E = nullptr, *h_E = nullptr;
+    std::map<int, int> tw_off;            // length -> offset
+};
+
+namespace vdwnl {
+
+static int fail(vdwnl_ctx *c, int code, const std::string &msg) {
+    if (c) c->err = msg;
+    return code;
+}
+
+static int check_krange(vdwnl_ctx *c);
+
+static int hipfail(vdwnl_ctx *c, hipError_t e, const char *what) {
+    return fail(c, VDWNL_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+static void free_device(vdwnl_ctx *c) {
+    if (c->device < 0) return;
+    (void)hipSetDevice(c->device);
+    if (c->work) (void)hipFree(c->work);
+    if (c->d_inst) (void)hipFree(c->d_inst);
+    if (c->h_inst) (void)hipHostFree(c->h_inst);
+    if (c->d_tiles) (void)hipFree(c->d_tiles);
+    if (c->d_tw) (void)hipFree(c->d_tw);
+    if (c->d_consts) (void)hipFree(c->d_consts);
+    if (c->d_E) (void)hipFree(c->d_E);
+    if (c->h_E) (void)hipHostFree(c->h_E);
+    c->work = nullptr; c->d_inst = nullptr; c->h_inst = nullptr; c->d_tiles = nullptr;
+    c->d_tw = nullptr; c->d_consts = nullptr; c->d_E = nullptr; c->h_E = nullptr;
+    c->work_bytes = 0;
+    c->device_ready = false;
+}
+
+static bool smooth235(int n) {
+    if (n < 1) return false;
+    for (int p : {2, 3, 5}) while (n % p == 0) n /= p;
+    return n == 1;
+}
+
+static int check_grid(vdwnl_ctx *c, const int32_t *shape, const double *cell, int precision, Grid &g) {
+    const size_t cs = precision == 64 ? 16 : 8, rs = precision == 64 ? 8 : 4;
+    for (int i = 0; i < 3; ++i) {
+        if (!(cell[i] > 0.0) || !std::isfinite(cell[i]))
+            return fail(c, VDWNL_E_ARG, "cell lengths must be positive and finite");
+        if (shape[i] < 4 || !smooth235(shape[i]))
+            return fail(c, VDWNL_E_UNSUPPORTED_SIZE, "grid edges must be >= 4 and products of 2, 3 and 5");
+        g.s[i] = shape[i];
+        g.cell[i] = cell[i];
+    }
+    const int N1 = g.s[0], N2 = g.s[1], N3 = g.s[2];
+    if (((size_t)N1 * N2) % 2 != 0)
+        return fail(c, VDWNL_E_UNSUPPORTED_SIZE, "N1 * N2 must be even (rows are transformed in pairs)");
+    if (N1 > kMaxN1 || (size_t)kNQ * N1 * cs > (size_t)kLdsCap)
+        return fail(c, VDWNL_E_UNSUPPORTED_SIZE, "N1 too large for the fused axis-1 pass");
+    if (N2 > kTileCap)
+        return fail(c, VDWNL_E_UNSUPPORTED_SIZE, "N2 too large");
+    if ((size_t)kNQ / 2 * N3 > (size_t)kTileCap || 12 * (size_t)N3 * cs + (kNQ + kNQ * kNQ) * rs > (size_t)kLdsCap)
+        return fail(c, VDWNL_E_UNSUPPORTED_SIZE, "N3 too large for the axis-3 pass");
+    if (!radix_plan(N1, g.p1) || !radix_plan(N2, g.p2) || !radix_plan(N3, g.p3))
+        return fail(c, VDWNL_E_UNSUPPORTED_SIZE, "no radix plan");
+    // tile shapes
+    g.bmain = 1;
+    if ((kNQ / 2) * 2 * (size_t)N3 <= (size_t)kTileCap &&
+        12 * 2 * (size_t)N3 * cs + (kNQ + kNQ * kNQ) * rs <= (size_t)kLdsCap)
+        g.bmain = 2;
+    g.k3main = std::max(1, std::min(kTileCap / (kNQ * N1), (int)(kLdsCap / (kNQ * N1 * cs))));
+    g.k3aux = std::max(1, std::min(kTileCap / (3 * N1), (int)(kLdsCap / (4 * N1 * cs))));
+    const int wmax = std::min(kTileCap / N2, (int)(kLdsCap / (N2 * cs)));
+    g.wy20 = g.wy3 = g.wy1 = std::max(1, wmax);
+    return VDWNL_OK;
+}
+
+static int plan_grids(vdwnl_ctx *c, int nb, const int32_t *shapes, const double *cells, int grad_mode,
+                      int precision) {
+    if (!c || !shapes || !cells || nb <= 0) return fail(c, VDWNL_E_ARG, "null argument or empty batch");
+    if (grad_mode != 0) return fail(c, VDWNL_E_ARG, "grad_mode must be 0 (spectral)");
+    if (precision != 32 && precision != 64) return fail(c, VDWNL_E_ARG, "precision must be 32 or 64");
+    std::vector<Grid> gs(nb);
+    for (int i = 0; i < nb; ++i) {
+        int rc = check_grid(c, shapes + 3 * i, cells + 3 * i, precision, gs[i]);
+        if (rc != VDWNL_OK) return rc;
+    }
+    free_device(c);
+    c->grids = gs;
+    c->precision = precision;
+    c->grad_mode = grad_mode;
+    c->shells.clear();
+    c->shell_keys.clear();
+    for (auto &g : c->grids) {
+        std::vector<double> key = {(double)g.s[0], (double)g.s[1], (double)g.s[2], g.cell[0], g.cell[1], g.cell[2]};
+        int found = -1;
+        for (auto &kv : c->shell_keys)
+            if (kv.first == key) found = kv.second;
+        if (found < 0) {
+            found = (int)c->shells.size();
+            c->shells.push_back(build_shells(g.s, g.cell));
+            c->shell_keys.push_back({key, found});
+        }
+        g.shell_key = found;
+    }
+    c->have_grid = true;
+    return check_krange(c);
+}
+
+// spline of the radial table at |G| for every pair: phi_ab(|G_s|), FP64
+static void shell_table(const vdwnl_ctx *c, const Shells &sh, std::vector<double> &out) {
+    const int npair = kNPair;
+    out.assign(sh.gmod.size() * npair, 0.0);
+    for (size_t s = 0; s < sh.gmod.size(); ++s) {
+        const double k = sh.gmod[s];
+        int j = (int)std::floor(k / c->dk);
+        if (j > c->nk - 2) j = c->nk - 2;
+        if (j < 0) j = 0;
+        const double t = k / c->dk - j, a = 1.0 - t, b = t;
+        const double w = c->dk * c->dk / 6.0;
+        for (int p = 0; p < npair; ++p) {
+            const double *f = c->phi.data() + (size_t)p * c->nk;
+            const double *m = c->d2.data() + (size_t)p * c->nk;
+            out[s * npair + p] = a * f[j] + b * f[j + 1] + ((a * a * a - a) * m[j] + (b * b * b - b) * m[j + 1]) * w;
+        }
+    }
+}
+
+// Every grid's largest |G| must lie on the radial kernel mesh.
+static int check_krange(vdwnl_ctx *c) {
+    if (!c->have_grid || !c->have_table) return VDWNL_OK;
+    for (auto &sh : c->shells)
+        if (sh.gmax > (c->nk - 1) * c->dk * (1.0 + 1e-12))
+            return fail(c, VDWNL_E_KRANGE, "radial kernel table does not reach max |G| of a grid");
+    return VDWNL_OK;
+}
+
+static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Build every device structure for the current grids and table.
+static int prepare_device(vdwnl_ctx *c) {
+    if (c->device_ready) return VDWNL_OK;
+    if (!c->have_grid || !c->have_table) return fail(c, VDWNL_E_STATE, "grid and kernel table must both be set");
+    int krc = check_krange(c);
+    if (krc != VDWNL_OK) return krc;
+    if (c->device < 0) return fail(c, VDWNL_E_STATE, "host-only context");
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hipfail(c, e, "hipSetDevice");
+    free_device(c);
+    const bool dp = c->precision == 64;
+    const size_t rs = dp ? 8 : 4, cs = 2 * rs;
+
+    // workspace layout
+    size_t off = 0;
+    c->map_off.assign(c->shells.size(), 0);
+    c->tab_off.assign(c->shells.size(), 0);
+    for (size_t i = 0; i < c->shells.size(); ++i) {
+        c->map_off[i] = off;
+        off = align_up(off + c->shells[i].map.size() * sizeof(int));
+        c->tab_off[i] = off;
+        off = align_up(off + c->shells[i].gmod.size() * kNPair * rs);
+    }
+    std::vector<Tile> tiles[KIND_COUNT];
+    for (size_t gi = 0; gi < c->grids.size(); ++gi) {
+        Grid &g = c->grids[gi];
+        const int N1 = g.s[0], N2 = g.s[1], N3 = g.s[2], N3h = N3 / 2 + 1;
+        const int rows = N1 * N2;
+        const int inst = (int)gi;
+        // axis-3 tiles
+        for (int r = 0; r < rows; r += 2) {
+            tiles[KX_NFWD].push_back({inst, r, 2, 0, -1});
+            tiles[KX_FINAL].push_back({inst, r, 2, 0, -1});
+        }
+        int slot = 0;
+        for (int r = 0; r < rows; r += g.bmain) {
+            const int b = std::min(g.bmain, rows - r);
+            tiles[KX_THETA].push_back({inst, r, b, 0, slot++});
+            tiles[KX_ASSEMBLE].push_back({inst, r, b, 0, -1});
+        }
+        g.n_de = slot;
+        // axis-2 tiles
+        const int kinds_y[6] = {KY_1F, KY_1I, KY_3F, KY_3I, KY_20F, KY_20I};
+        const int vs[6] = {1, 1, 3, 3, kNQ, kNQ};
+        for (int q = 0; q < 6; ++q) {
+            const int ftot = N3h * vs[q];
+            const int w = vs[q] == kNQ ? g.wy20 : (vs[q] == 3 ? g.wy3 : g.wy1);
+            for (int i1 = 0; i1 < N1; ++i1)
+                for (int f = 0; f < ftot; f += w) tiles[kinds_y[q]].push_back({inst, i1, f, std::min(w, ftot - f), -1});
+        }
+        // axis-1 tiles
+        slot = 0;
+        for (int k2 = 0; k2 < N2; ++k2) {
+            for (int k3 = 0; k3 < N3h; k3 += g.k3main)
+                tiles[KZ_MAIN].push_back({inst, k2, k3, std::min(g.k3main, N3h - k3), slot++});
+            for (int k3 = 0; k3 < N3h; k3 += g.k3aux) {
+                tiles[KZ_GRAD].push_back({inst, k2, k3, std::min(g.k3aux, N3h - k3), -1});
+                tiles[KZ_DIV].push_back({inst, k2, k3, std::min(g.k3aux, N3h - k3), -1});
+            }
+        }
+        g.n_ek = slot;
+        // fields
+        g.off_grad = off; off = align_up(off + 3 * g.npts() * rs);
+        g.off_vloc = off; off = align_up(off + g.npts() * rs);
+        g.off_spec = off; off = align_up(off + g.nhalf() * kNQ * cs);
+        g.off_spec3 = off; off = align_up(off + g.nhalf() * 3 * cs);
+        g.off_spec1 = off; off = align_up(off + g.nhalf() * cs);
+        g.off_ek = off; off = align_up(off + g.n_ek * sizeof(double));
+        g.off_de = off; off = align_up(off + g.n_de * sizeof(double));
+    }
+    // LDS per kind (max over grids)
+    for (int k = 0; k < KIND_COUNT; ++k) c->kind_lds[k] = 0;
+    for (auto &g : c->grids) {
+        const size_t N1 = g.s[0], N2 = g.s[1], N3 = g.s[2];
+        auto mx = [&](int k, size_t v) { c->kind_lds[k] = std::max(c->kind_lds[k], v); };
+        mx(KX_NFWD, N3 * cs);
+        mx(KX_FINAL, N3 * cs);
+        const size_t xm = 12 * g.bmain * N3 * cs + (kNQ + kNQ * kNQ) * rs;
+        mx(KX_THETA, xm);
+        mx(KX_ASSEMBLE, xm);
+        mx(KY_1F, N2 * g.wy1 * cs); mx(KY_1I, N2 * g.wy1 * cs);
+        mx(KY_3F, N2 * g.wy3 * cs); mx(KY_3I, N2 * g.wy3 * cs);
+        mx(KY_20F, N2 * g.wy20 * cs); mx(KY_20I, N2 * g.wy20 * cs);
+        mx(KZ_MAIN, (size_t)kNQ * g.k3main * N1 * cs);
+        mx(KZ_GRAD, 4 * g.k3aux * N1 * cs);
+        mx(KZ_DIV, 4 * g.k3aux * N1 * cs);
+    }
+    std::vector<Tile> all;
+    for (int k = 0; k < KIND_COUNT; ++k) {
+        c->kind_off[k] = (int)all.size();
+        c->kind_cnt[k] = (int)tiles[k].size();
+        all.insert(all.end(), tiles[k].begin(), tiles[k].end());
+    }
+    // twiddles
+    c->tw_off.clear();
+    std::vector<double> twd;
+    for (auto &g : c->grids)
+        for (FftPlan *p : {&g.p1, &g.p2, &g.p3}) {
+            auto it = c->tw_off.find(p->n);
+            if (it == c->tw_off.end()) {
+                const int o = (int)(twd.size() / 2);
+                c->tw_off[p->n] = o;
+                for (int m = 0; m < p->n; ++m) {
+                    // exp(-2 pi i m / n)
+                    const double ang = 2.0 * M_PI * (double)m / (double)p->n;
+                    twd.push_back(std::cos(ang));
+                    twd.push_back(-std::sin(ang));
+                }
+                p->tw = o;
+            } else {
+                p->tw = it->second;
+            }
+        }
+    // allocations
+    c->work_bytes = off;
+    if ((e = hipMalloc(&c->work, std::max<size_t>(off, 256))) != hipSuccess) { c->work = nullptr; return hipfail(c, e, "hipMalloc workspace"); }
+    const size_t ng = c->grids.size();
+    if ((e = hipMalloc(&c->d_inst, ng * sizeof(InstDev))) != hipSuccess) return hipfail(c, e, "hipMalloc insts");
+    if ((e = hipHostMalloc((void **)&c->h_inst, ng * sizeof(InstDev), hipHostMallocDefault)) != hipSuccess) return hipfail(c, e, "hipHostMalloc insts");
+    if ((e = hipMalloc(&c->d_tiles, std::max<size_t>(all.size(), 1) * sizeof(Tile))) != hipSuccess) return hipfail(c, e, "hipMalloc tiles");
+    const size_t twbytes = (twd.size() / 2) * cs;
+    if ((e = hipMalloc(&c->d_tw, std::max<size_t>(twbytes, 16))) != hipSuccess) return hipfail(c, e, "hipMalloc twiddles");
+    if ((e = hipMalloc(&c->d_consts, sizeof(Consts))) != hipSuccess) return hipfail(c, e, "hipMalloc consts");
+    if ((e = hipMalloc(&c->d_E, ng * 2 * sizeof(double))) != hipSuccess) return hipfail(c, e, "hipMalloc E");
+    if ((e = hipHostMalloc((void **)&c->h_E, ng * 2 * sizeof(double), hipHostMallocDefault)) != hipSuccess) return hipfail(c, e, "hipHostMalloc E");
+    // uploads
+    char *w = (char *)c->work;
+    for (size_t i = 0; i < c->shells.size(); ++i) {
+        const Shells &sh = c->shells[i];
+        if ((e = hipMemcpy(w + c->map_off[i], sh.map.data(), sh.map.size() * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess)
+            return hipfail(c, e, "upload shell map");
+        std::vector<double> tab;
+        shell_table(c, sh, tab);
+        if (dp) {
+            e = hipMemcpy(w + c->tab_off[i], tab.data(), tab.size() * 8, hipMemcpyHostToDevice);
+        } else {
+            std::vector<float> tf(tab.begin(), tab.end());
+            e = hipMemcpy(w + c->tab_off[i], tf.data(), tf.size() * 4, hipMemcpyHostToDevice);
+        }
+        if (e != hipSuccess) return hipfail(c, e, "upload shell table");
+    }
+    if (dp) {
+        e = hipMemcpy(c->d_tw, twd.data(), twbytes, hipMemcpyHostToDevice);
+    } else {
+        std::vector<float> tf(twd.begin(), twd.end());
+        e = hipMemcpy(c->d_tw, tf.data(), twbytes, hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) return hipfail(c, e, "upload twiddles");
+    if ((e = hipMemcpy(c->d_tiles, all.data(), all.size() * sizeof(Tile), hipMemcpyHostToDevice)) != hipSuccess)
+        return hipfail(c, e, "upload tiles");
+    if ((e = hipMemcpy(c->d_consts, &c->consts, sizeof(Consts), hipMemcpyHostToDevice)) != hipSuccess)
+        return hipfail(c, e, "upload consts");
+    for (size_t gi = 0; gi < ng; ++gi) {
+        const Grid &g = c->grids[gi];
+        InstDev &I = c->h_inst[gi];
+        std::memset(&I, 0, sizeof(I));
+        I.n1 = g.s[0]; I.n2 = g.s[1]; I.n3 = g.s[2]; I.n3h = g.s[2] / 2 + 1;
+        I.h1 = g.s[0] / 2 + 1; I.h2 = g.s[1] / 2 + 1;
+        I.p1 = g.p1; I.p2 = g.p2; I.p3 = g.p3;
+        I.inv_n = 1.0 / (double)g.npts();
+        I.g1 = 2.0 * M_PI / g.cell[0]; I.g2 = 2.0 * M_PI / g.cell[1]; I.g3 = 2.0 * M_PI / g.cell[2];
+        I.omega = g.cell[0] * g.cell[1] * g.cell[2];
+        I.dvol = I.omega / (double)g.npts();
+        I.grad = w + g.off_grad; I.vloc = w + g.off_vloc; I.spec = w + g.off_spec;
+        I.spec3 = w + g.off_spec3; I.spec1 = w + g.off_spec1;
+        I.shellmap = (const int *)(w + c->map_off[g.shell_key]);
+        I.shelltab = w + c->tab_off[g.shell_key];
+        I.part_ek = (double *)(w + g.off_ek); I.part_de = (double *)(w + g.off_de);
+        I.n_ek = g.n_ek; I.n_de = g.n_de;
+    }
+    c->device_ready = true;
+    return VDWNL_OK;
+}
+
+static int run(vdwnl_ctx *c, int nb, const void *const *n_ptrs, void *const *v_ptrs, double *E_out, void *stream) {
+    if (!c) return VDWNL_E_ARG;
+    if (!n_ptrs || !v_ptrs || !E_out) return fail(c, VDWNL_E_ARG, "null pointer");
+    if (!c->have_grid || !c->have_table) return fail(c, VDWNL_E_STATE, "grid and kernel table must both be set");
+    if (nb != (int)c->grids.size()) return fail(c, VDWNL_E_ARG, "batch size differs from the planned grids");
+    for (int i = 0; i < nb; ++i)
+        if (!n_ptrs[i] || !v_ptrs[i]) return fail(c, VDWNL_E_ARG, "null density or potential pointer");
+    if (c->device < 0) return fail(c, VDWNL_E_STATE, "host-only context");
+    int rc = prepare_device(c);
+    if (rc != VDWNL_OK) return rc;
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hipfail(c, e, "hipSetDevice");
+    hipStream_t st = (hipStream_t)stream;
+    for (int i = 0; i < nb; ++i) {
+        c->h_inst[i].n = n_ptrs[i];
+        c->h_inst[i].v = v_ptrs[i];
+    }
+    if ((e = hipMemcpyAsync(c->d_inst, c->h_inst, nb * sizeof(InstDev), hipMemcpyHostToDevice, st)) != hipSuccess)
+        return hipfail(c, e, "upload instance table");
+    static const int order[KIND_COUNT] = {KX_NFWD, KY_1F, KZ_GRAD, KY_3I, KX_THETA, KY_20F, KZ_MAIN,
+                                          KY_20I, KX_ASSEMBLE, KY_3F, KZ_DIV, KY_1I, KX_FINAL};
+    for (int k : order) {
+        LaunchArgs a{c->d_inst, c->d_tiles + c->kind_off[k], c->kind_cnt[k], c->kind_lds[k], c->d_consts, c->d_tw, st};
+        if ((e = launch_kind(k, c->precision, a)) != hipSuccess) return hipfail(c, e, "kernel launch");
+    }
+    if ((e = launch_reduce(c->d_inst, nb, c->d_E, st)) != hipSuccess) return hipfail(c, e, "reduce launch");
+    if ((e = hipMemcpyAsync(c->h_E, c->d_E, nb * 2 * sizeof(double), hipMemcpyDeviceToHost, st)) != hipSuccess)
+        return hipfail(c, e, "copy energies");
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return hipfail(c, e, "stream synchronize");
+    std::memcpy(E_out, c->h_E, nb * 2 * sizeof(double));
+    return VDWNL_OK;
+}
+
+}  // namespace vdwnl
+
+// ---------------------------------------------------------------- C ABI
+
+extern "C" {
+
+const char *vdwnl_strerror(int code) {
+    switch (code) {
+        case VDWNL_OK: return "ok";
+        case VDWNL_E_ARG: return "invalid argument";
+        case VDWNL_E_UNSUPPORTED_SIZE: return "unsupported grid size";
+        case VDWNL_E_NOMEM: return "out of memory";
+        case VDWNL_E_TABLE: return "invalid kernel table";
+        case VDWNL_E_KRANGE: return "kernel table does not cover the grid's wave vectors";
+        case VDWNL_E_STATE: return "grid or kernel table missing, or no device";
+        case VDWNL_E_HIP: return "HIP runtime error";
+        case VDWNL_E_BAD_DENSITY: return "invalid density";
+        default: return "unknown error";
+    }
+}
+
+static thread_local std::string g_create_err = "no error";
+
+const char *vdwnl_last_error(const vdwnl_ctx *ctx) { return ctx ? ctx->err.c_str() : g_create_err.c_str(); }
+
+int vdwnl_create(vdwnl_ctx **out, int device) {
+    if (!out) return VDWNL_E_ARG;
+    *out = nullptr;
+    if (device >= 0) {
+        int count = 0;
+        const hipError_t e = hipGetDeviceCount(&count);
+        if (e != hipSuccess) {
+            g_create_err = std::string("hipGetDeviceCount: ") + hipGetErrorString(e);
+            return VDWNL_E_HIP;
+        }
+        if (device >= count) {
+            g_create_err = "device " + std::to_string(device) + " not present (" + std::to_string(count) + " visible)";
+            return VDWNL_E_STATE;
+        }
+    }
+    vdwnl_ctx *c = new (std::nothrow) vdwnl_ctx();
+    if (!c) return VDWNL_E_NOMEM;
+    c->device = device;
+    std::memset(&c->consts, 0, sizeof(Consts));
+    *out = c;
+    return VDWNL_OK;
+}
+
+int vdwnl_destroy(vdwnl_ctx *ctx) {
+    if (!ctx) return VDWNL_E_ARG;
+    free_device(ctx);
+    delete ctx;
+    return VDWNL_OK;
+}
+
+int vdwnl_set_grid(vdwnl_ctx *ctx, const int32_t shape[3], const double cell[3], int32_t grad_mode,
+                   int32_t precision) {
+    if (!ctx) return VDWNL_E_ARG;
+    return plan_grids(ctx, 1, shape, cell, grad_mode, precision);
+}
+
+int vdwnl_set_grids(vdwnl_ctx *ctx, int32_t nb, const int32_t *shapes, const double *cells, int32_t grad_mode,
+                    int32_t precision) {
+    if (!ctx) return VDWNL_E_ARG;
+    return plan_grids(ctx, nb, shapes, cells, grad_mode, precision);
+}
+
+int vdwnl_set_kernel_table(vdwnl_ctx *ctx, int32_t nq, const double *qmesh, double q_c, int32_t m_c, int32_t nk,
+                           double dk, const double *phi, double c_soft) {
+    if (!ctx) return VDWNL_E_ARG;
+    if (!qmesh || !phi) return fail(ctx, VDWNL_E_ARG, "null table pointer");
+    if (nq != kNQ) return fail(ctx, VDWNL_E_TABLE, "nq must be 20");
+    if (m_c < 1 || m_c > 64) return fail(ctx, VDWNL_E_TABLE, "m_c must be in 1..64");
+    if (nk < 4 || !(dk > 0.0) || !std::isfinite(dk)) return fail(ctx, VDWNL_E_TABLE, "bad radial mesh");
+    if (!(q_c > 0.0) || !std::isfinite(c_soft)) return fail(ctx, VDWNL_E_TABLE, "bad q_c or C_s");
+    for (int i = 0; i < nq; ++i) {
+        if (!std::isfinite(qmesh[i]) || qmesh[i] <= 0.0) return fail(ctx, VDWNL_E_TABLE, "q mesh must be positive");
+        if (i > 0 && !(qmesh[i] > qmesh[i - 1])) return fail(ctx, VDWNL_E_TABLE, "q mesh must increase strictly");
+    }
+    if (qmesh[nq - 1] != q_c) return fail(ctx, VDWNL_E_TABLE, "last q mesh point must equal q_c");
+    const size_t n2 = (size_t)nq * nq;
+    for (int a = 0; a < nq; ++a)
+        for (int b = a + 1; b < nq; ++b) {
+            const double *x = phi + ((size_t)a * nq + b) * nk, *y = phi + ((size_t)b * nq + a) * nk;
+            for (int j = 0; j < nk; ++j)
+                if (x[j] != y[j]) return fail(ctx, VDWNL_E_TABLE, "phi table must be symmetric in (a, b)");
+        }
+    for (size_t i = 0; i < n2 * nk; ++i)
+        if (!std::isfinite(phi[i])) return fail(ctx, VDWNL_E_TABLE, "phi table has a non-finite value");
+    ctx->nq = nq; ctx->mc = m_c; ctx->nk = nk; ctx->qc = q_c; ctx->dk = dk; ctx->cs = c_soft;
+    ctx->qmesh.assign(qmesh, qmesh + nq);
+    ctx->phi.assign((size_t)kNPair * nk, 0.0);
+    ctx->d2.assign((size_t)kNPair * nk, 0.0);
+    std::vector<double> kx(nk);
+    for (int j = 0; j < nk; ++j) kx[j] = j * dk;
+    int p = 0;
+    for (int a = 0; a < nq; ++a)
+        for (int b = a; b < nq; ++b, ++p) {
+            std::memcpy(ctx->phi.data() + (size_t)p * nk, phi + ((size_t)a * nq + b) * nk, nk * sizeof(double));
+            natural_spline_d2(kx.data(), ctx->phi.data() + (size_t)p * nk, nk, ctx->d2.data() + (size_t)p * nk);
+        }
+    // cardinal splines p_a: M[j][a] = second derivative at q_j of the spline through e_a
+    Consts &k = ctx->consts;
+    std::memset(&k, 0, sizeof(k));
+    k.qc = q_c; k.cs = c_soft; k.nmin = 1e-30; k.mc = m_c; k.nq = nq;
+    std::vector<double> e(nq), d2(nq);
+    for (int a = 0; a < nq; ++a) {
+        std::fill(e.begin(), e.end(), 0.0);
+        e[a] = 1.0;
+        natural_spline_d2(qmesh, e.data(), nq, d2.data());
+        for (int j = 0; j < nq; ++j) k.M[j * kNQ + a] = d2[j];
+    }
+    for (int j = 0; j < nq; ++j) k.q[j] = qmesh[j];
+    ctx->have_table = true;
+    free_device(ctx);
+    return check_krange(ctx);
+}
+
+int vdwnl_energy_potential(vdwnl_ctx *ctx, const void *n_dev, void *v_dev, double *E_out, void *stream) {
+    if (!ctx) return VDWNL_E_ARG;
+    if (ctx->have_grid && ctx->grids.size() != 1) return fail(ctx, VDWNL_E_STATE, "context holds a batch plan");
+    const void *np[1] = {n_dev};
+    void *vp[1] = {v_dev};
+    return run(ctx, 1, np, vp, E_out, stream);
+}
+
+int vdwnl_energy_potential_batched(vdwnl_ctx *ctx, int32_t nb, const void *const *n_ptrs, void *const *v_ptrs,
+                                   double *E_out, void *stream) {
+    if (!ctx) return VDWNL_E_ARG;
+    return run(ctx, nb, n_ptrs, v_ptrs, E_out, stream);
+}
+
+int vdwnl_debug_field(vdwnl_ctx *ctx, int32_t inst, int32_t which, void *dst, void *stream) {
+    if (!ctx || !dst) return VDWNL_E_ARG;
+    if (!ctx->device_ready || inst < 0 || inst >= (int32_t)ctx->grids.size())
+        return fail(ctx, VDWNL_E_STATE, "no evaluation of that grid yet");
+    const Grid &g = ctx->grids[inst];
+    const size_t rs = ctx->precision == 64 ? 8 : 4;
+    size_t off, bytes;
+    if (which == 0) { off = g.off_grad; bytes = 3 * g.npts() * rs; }
+    else if (which == 1) { off = g.off_vloc; bytes = g.npts() * rs; }
+    else return fail(ctx, VDWNL_E_ARG, "which must be 0 or 1");
+    hipError_t e = hipMemcpyAsync(dst, (char *)ctx->work + off, bytes, hipMemcpyDeviceToDevice, (hipStream_t)stream);
+    if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+    return e == hipSuccess ? VDWNL_OK : hipfail(ctx, e, "debug copy");
+}
+
+int vdwnl_info(const vdwnl_ctx *ctx, int32_t *n_grids, int64_t *workspace_bytes) {
+    if (!ctx) return VDWNL_E_ARG;
+    if (n_grids) *n_grids = (int32_t)ctx->grids.size();
+    if (workspace_bytes) *workspace_bytes = (int64_t)ctx->work_bytes;
+    return VDWNL_OK;
+}
+
+}  // extern "C"

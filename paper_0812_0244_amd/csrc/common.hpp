@@ -1,0 +1,101 @@
+// Shared host/device definitions of libvdwnl.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace vdwnl {
+
+constexpr int kNQ = 20;                          // interpolation points q_a (compile-time)
+constexpr int kNPair = kNQ * (kNQ + 1) / 2;      // packed symmetric phi_ab per |G| shell
+constexpr int kThreads = 256;                    // threads per workgroup, every kernel
+constexpr int kTileCap = 4096;                   // complex elements of one LDS FFT tile
+constexpr int kLdsCap = 65536;                   // bytes of LDS one workgroup may take
+constexpr int kMaxStages = 16;
+constexpr int kMaxN1 = 204;                      // 20 N1 <= kTileCap (fused axis-1 pass)
+constexpr int kMaxN3 = 340;                      // 12 N3 complex doubles <= kLdsCap
+
+// One 1-D FFT length: radix sequence (each 2, 3, 4, 5 or 8) and the offset of
+// its twiddles W_n^k = exp(-2 pi i k / n), k < n, in the twiddle table.
+struct FftPlan {
+    int n;
+    int nstage;
+    int radix[kMaxStages];
+    int tw;
+};
+
+// Per-grid state seen by the kernels.  Field layouts (C order):
+//   n, v, vloc      [N1][N2][N3] real
+//   grad            [3][N1][N2][N3] real
+//   spec            [N1][N2][N3h][kNQ] complex  (20 theta / u spectra, component fastest)
+//   spec3           [N1][N2][N3h][3] complex    (grad n / w spectra)
+//   spec1           [N1][N2][N3h] complex       (n / divergence spectrum)
+//   shellmap        [N1/2+1][N2/2+1][N3h] int   (|G| shell of (|m1|, |m2|, m3))
+//   shelltab        [nshell][kNPair] real       (phi_ab(|G_s|), a <= b packed row by row)
+struct InstDev {
+    int n1, n2, n3, n3h, h1, h2;
+    FftPlan p1, p2, p3;
+    double inv_n;            // 1 / (N1 N2 N3)
+    double g1, g2, g3;       // 2 pi / L_c
+    double omega, dvol;
+    void *grad, *vloc, *spec, *spec3, *spec1;
+    const int *shellmap;
+    const void *shelltab;
+    double *part_ek;         // one partial per fused axis-1 tile
+    double *part_de;         // one partial per theta tile
+    int n_ek, n_de;
+    const void *n;           // per call
+    void *v;                 // per call
+};
+
+// Method constants (copied into LDS by the kernels that need them).
+struct Consts {
+    double qc;
+    double cs;               // C_s
+    double nmin;
+    int mc;
+    int nq;
+    double q[kNQ];           // q mesh
+    double M[kNQ * kNQ];     // M[j][a]: second derivative at q_j of the cardinal spline p_a
+};
+
+// One workgroup's work item; the meaning of a, b, c depends on the pass.
+struct Tile {
+    int inst;
+    int a, b, c;
+    int slot;                // partial-sum slot within the grid (or -1)
+};
+
+enum KernelKind {
+    KX_NFWD = 0,   // R2C of n along axis 3
+    KY_1F,         // axis-2 forward, 1 component
+    KZ_GRAD,       // axis 1: n -> i G_c n / N (3 components)
+    KY_3I,         // axis-2 inverse, 3 components
+    KX_THETA,      // C2R grad n, theta_a, R2C theta along axis 3
+    KY_20F,        // axis-2 forward, 20 components
+    KZ_MAIN,       // axis 1 forward, u = phi c, energy, axis 1 inverse
+    KY_20I,        // axis-2 inverse, 20 components
+    KX_ASSEMBLE,   // C2R u_a, v_loc and w = g grad n, R2C w along axis 3
+    KY_3F,         // axis-2 forward, 3 components
+    KZ_DIV,        // axis 1: sum_c i G_c w_c / N (1 component)
+    KY_1I,         // axis-2 inverse, 1 component
+    KX_FINAL,      // C2R divergence, v = v_loc - div
+    KIND_COUNT
+};
+
+// Arguments of one pass launch.
+struct LaunchArgs {
+    const InstDev *insts;
+    const Tile *tiles;
+    int ntiles;
+    size_t lds;
+    const Consts *cst;
+    const void *tw;
+    hipStream_t stream;
+};
+
+hipError_t launch_kind(int kind, int precision, const LaunchArgs &a);
+hipError_t launch_reduce(const InstDev *insts, int ninst, double *E, hipStream_t stream);
+
+}  // namespace vdwnl

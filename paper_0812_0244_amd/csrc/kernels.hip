@@ -1,0 +1,592 @@
+// HIP kernels of libvdwnl (gfx950).  One evaluation of E_c^nl and v_nl is
+// thirteen passes over the grid; each pass is one launch that covers every
+// grid of the batch (a workgroup reads its work item from a tile list).
+//
+// Fields are transformed with three 1-D FFT passes: along axis 3 (the
+// contiguous one, real-to-complex by pairing two real lines into one complex
+// line), axis 2 and axis 1.  Spectra keep all components of one k point
+// together ([N1][N2][N3/2+1][V] complex), so the axis-1 pass of the 20 theta
+// spectra holds every component of its k points in LDS and can apply the
+// per-k kernel matrix between its forward and inverse FFTs.
+#include "common.hpp"
+#include "fft_lds.hpp"
+
+namespace vdwnl {
+
+// ---------------------------------------------------------------- helpers
+
+template <typename T> __device__ __forceinline__ T dev_cbrt(T x);
+template <> __device__ __forceinline__ float dev_cbrt(float x) { return cbrtf(x); }
+template <> __device__ __forceinline__ double dev_cbrt(double x) { return cbrt(x); }
+template <typename T> __device__ __forceinline__ T dev_sqrt(T x);
+template <> __device__ __forceinline__ float dev_sqrt(float x) { return sqrtf(x); }
+template <> __device__ __forceinline__ double dev_sqrt(double x) { return sqrt(x); }
+template <typename T> __device__ __forceinline__ T dev_log1p(T x);
+template <> __device__ __forceinline__ float dev_log1p(float x) { return log1pf(x); }
+template <> __device__ __forceinline__ double dev_log1p(double x) { return log1p(x); }
+
+// signed frequency index of position k on an axis of N points, 0 at Nyquist
+__device__ __forceinline__ int freq_nz(int k, int N) {
+    int m = (k <= N / 2) ? k : k - N;
+    if ((N & 1) == 0 && k == N / 2) m = 0;
+    return m;
+}
+__device__ __forceinline__ int freq_abs(int k, int N) { return k <= N - k ? k : N - k; }
+
+// Sum over the workgroup in a fixed order; result valid in thread 0.
+__device__ double block_sum(double v) {
+    __shared__ double red[kThreads / 64];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) red[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < kThreads / 64; ++w) s += red[w];
+    __syncthreads();
+    return s;
+}
+
+// ---------------------------------------------------------------- q0 and the spline basis
+
+// q0(n, |grad n|^2) before saturation and its partials (Dion et al. form,
+// Perdew-Wang 1992 correlation); the saturation of Eq. (Sat) in FP64.
+template <typename T, bool DERIV>
+struct LocalQ {
+    T q0, Q, dqdn, dqds;
+
+    __device__ __forceinline__ void eval(T n, T sigma, const Consts &c) {
+        const T pi = (T)3.14159265358979323846;
+        const T A = (T)0.031091, a1 = (T)0.21370;
+        const T b1 = (T)7.5957, b2 = (T)3.5876, b3 = (T)1.6382, b4 = (T)0.49294;
+        const T zg = (T)(0.8491 / 36.0);   // -Z_ab / 36
+        const T kf = dev_cbrt<T>((T)3 * pi * pi * n);
+        const T rs = dev_cbrt<T>((T)3 / ((T)4 * pi * n));
+        const T srs = dev_sqrt<T>(rs);
+        const T P = b1 * srs + b2 * rs + b3 * rs * srs + b4 * rs * rs;
+        const T L = dev_log1p<T>((T)1 / ((T)2 * A * P));
+        const T eps = (T)-2 * A * ((T)1 + a1 * rs) * L;
+        const T grad_term = zg * sigma / (kf * n * n);
+        const T qraw = kf - ((T)4 * pi / (T)3) * eps + grad_term;
+        if (DERIV) {
+            const T dP = (T)0.5 * b1 / srs + b2 + (T)1.5 * b3 * srs + (T)2 * b4 * rs;
+            const T deps_drs = (T)-2 * A * a1 * L + (T)2 * A * ((T)1 + a1 * rs) * dP / (P * ((T)2 * A * P + (T)1));
+            const T deps_dn = deps_drs * (-rs / ((T)3 * n));
+            dqdn = kf / ((T)3 * n) - ((T)4 * pi / (T)3) * deps_dn - ((T)7 / (T)3) * grad_term / n;
+            dqds = zg / (kf * n * n);
+        }
+        // h(x, x_c) = x_c (1 - exp(-sum_{m<=m_c} (x/x_c)^m / m)), dh/dx = exp(-S) sum_{m<m_c} (x/x_c)^m
+        const double y = (double)qraw / c.qc;
+        if (y > 64.0) {
+            q0 = (T)c.qc;
+            Q = (T)0;
+            return;
+        }
+        double S = 0.0, D = 0.0;
+        for (int m = c.mc; m >= 1; --m) S = S * y + 1.0 / (double)m;
+        S *= y;
+        for (int m = c.mc - 1; m >= 0; --m) D = D * y + 1.0;
+        if (S > 700.0) {
+            q0 = (T)c.qc;
+            Q = (T)0;
+        } else {
+            const double e = exp(-S);
+            q0 = (T)(c.qc * (1.0 - e));
+            Q = (T)(e * D);
+        }
+    }
+};
+
+// Natural cubic cardinal splines p_a(q) on the q mesh (Eq. fofx and the text
+// after it): interval search and the two weights; M[j][a] in LDS.
+template <typename T>
+struct SplinePos {
+    int j;
+    T a, b, h, dq;   // dq = q0 - q_1 below the mesh (linear continuation), else 0
+
+    __device__ __forceinline__ void locate(T q0, const T *qm, int nq) {
+        if (q0 < qm[0]) {
+            j = 0;
+            dq = q0 - qm[0];
+            h = qm[1] - qm[0];
+            a = (T)1;
+            b = (T)0;
+            return;
+        }
+        int lo = 0, hi = nq - 1;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (qm[mid] <= q0) lo = mid; else hi = mid;
+        }
+        j = lo;
+        h = qm[j + 1] - qm[j];
+        a = (qm[j + 1] - q0) / h;
+        b = (T)1 - a;
+        dq = (T)0;
+    }
+    // p_a and dp_a/dq
+    __device__ __forceinline__ void basis(int al, const T *M, T &p, T &dp) const {
+        const T Mj = M[j * kNQ + al], Mj1 = M[(j + 1) * kNQ + al];
+        const T dj = (al == j) ? (T)1 : (T)0, dj1 = (al == j + 1) ? (T)1 : (T)0;
+        p = a * dj + b * dj1 + ((a * a * a - a) * Mj + (b * b * b - b) * Mj1) * h * h / (T)6;
+        dp = (dj1 - dj) / h + (((T)1 - (T)3 * a * a) * Mj + ((T)3 * b * b - (T)1) * Mj1) * h / (T)6;
+        p += dq * dp;
+    }
+};
+
+template <typename T>
+__device__ __forceinline__ void load_consts(const Consts *cst, T *qm, T *Mm) {
+    for (int i = threadIdx.x; i < kNQ; i += kThreads) qm[i] = (T)cst->q[i];
+    for (int i = threadIdx.x; i < kNQ * kNQ; i += kThreads) Mm[i] = (T)cst->M[i];
+}
+
+// ---------------------------------------------------------------- axis-3 passes
+
+// R2C of n: rows (2p, 2p+1) of a tile form one complex line.
+// tile: a = first row (i1 N2 + i2), b = rows (even)
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_x_nfwd(const InstDev *insts, const Tile *tiles,
+                                                     const void *twv) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    C2<T> *buf = reinterpret_cast<C2<T> *>(smem);
+    const Tile t = tiles[blockIdx.x];
+    const InstDev &I = insts[t.inst];
+    const int N3 = I.n3, N3h = I.n3h, row0 = t.a, B = t.b, np = B / 2;
+    const T *n = reinterpret_cast<const T *>(I.n) + (size_t)row0 * N3;
+    for (int idx = threadIdx.x; idx < np * N3; idx += kThreads) {
+        const int pr = idx / N3, k = idx - pr * N3;
+        buf[idx] = mk<T>(n[(2 * pr) * N3 + k], n[(2 * pr + 1) * N3 + k]);
+    }
+    __syncthreads();
+    fft_lines<T>(buf, I.p3, np, 1, N3, reinterpret_cast<const C2<T> *>(twv), -1);
+    C2<T> *out = reinterpret_cast<C2<T> *>(I.spec1) + (size_t)row0 * N3h;
+    for (int idx = threadIdx.x; idx < B * N3h; idx += kThreads) {
+        const int rb = idx / N3h, k = idx - rb * N3h;
+        const C2<T> *Z = buf + (rb >> 1) * N3;
+        const C2<T> z = Z[k], zc = cconj(Z[(N3 - k) % N3]);
+        C2<T> y;
+        if ((rb & 1) == 0) y = mk<T>((z.x + zc.x) * (T)0.5, (z.y + zc.y) * (T)0.5);
+        else y = mk<T>((z.y - zc.y) * (T)0.5, -(z.x - zc.x) * (T)0.5);
+        out[idx] = y;
+    }
+}
+
+// C2R of grad n (3 spectra per row), theta_a = n p_a(q0), Delta E partials,
+// R2C of the 20 theta rows.  tile: a = first row, b = rows, slot = partial.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_x_theta(const InstDev *insts, const Tile *tiles,
+                                                      const Consts *cst, const void *twv) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const Tile t = tiles[blockIdx.x];
+    const InstDev &I = insts[t.inst];
+    const int N3 = I.n3, N3h = I.n3h, row0 = t.a, B = t.b;
+    const size_t N = (size_t)I.n1 * I.n2 * I.n3;
+    C2<T> *r1 = reinterpret_cast<C2<T> *>(smem);          // 2 lines per row: d1 + i d2, d3
+    C2<T> *r2 = r1 + 2 * B * N3;                           // 10 lines per row: theta pairs
+    T *qm = reinterpret_cast<T *>(r2 + kNQ / 2 * B * N3);
+    T *Mm = qm + kNQ;
+    load_consts<T>(cst, qm, Mm);
+    const C2<T> *twall = reinterpret_cast<const C2<T> *>(twv);
+
+    const C2<T> *s3 = reinterpret_cast<const C2<T> *>(I.spec3) + (size_t)row0 * N3h * 3;
+    for (int idx = threadIdx.x; idx < B * N3; idx += kThreads) {
+        const int rb = idx / N3, k = idx - rb * N3;
+        const bool cj = k >= N3h;
+        const int kk = cj ? N3 - k : k;
+        const C2<T> *src = s3 + ((size_t)rb * N3h + kk) * 3;
+        C2<T> y0 = src[0], y1 = src[1], y2 = src[2];
+        if (cj) { y0 = cconj(y0); y1 = cconj(y1); y2 = cconj(y2); }
+        r1[(2 * rb) * N3 + k] = mk<T>(y0.x - y1.y, y0.y + y1.x);
+        r1[(2 * rb + 1) * N3 + k] = y2;
+    }
+    __syncthreads();
+    fft_lines<T>(r1, I.p3, 2 * B, 1, N3, twall, +1);
+
+    const Consts c = *cst;
+    const T *nin = reinterpret_cast<const T *>(I.n);
+    T *grad = reinterpret_cast<T *>(I.grad);
+    double de = 0.0;
+    for (int idx = threadIdx.x; idx < B * N3; idx += kThreads) {
+        const int rb = idx / N3, k = idx - rb * N3;
+        const size_t p = (size_t)(row0 + rb) * N3 + k;
+        const T nv = nin[p];
+        const C2<T> g01 = r1[(2 * rb) * N3 + k], g2 = r1[(2 * rb + 1) * N3 + k];
+        grad[p] = g01.x;
+        grad[N + p] = g01.y;
+        grad[2 * N + p] = g2.x;
+        T *th = reinterpret_cast<T *>(r2 + (size_t)(kNQ / 2 * rb) * N3);   // pair line m at th + 2 m N3
+        if (nv >= (T)c.nmin) {
+            LocalQ<T, false> lq;
+            lq.eval(nv, g01.x * g01.x + g01.y * g01.y + g2.x * g2.x, c);
+            SplinePos<T> sp;
+            sp.locate(lq.q0, qm, kNQ);
+#pragma unroll 4
+            for (int al = 0; al < kNQ; ++al) {
+                T pa, dpa;
+                sp.basis(al, Mm, pa, dpa);
+                th[2 * ((al >> 1) * N3 + k) + (al & 1)] = nv * pa;
+            }
+            const T q3 = lq.q0 * lq.q0 * lq.q0;
+            de += (double)((T)c.cs * nv * nv / q3);
+        } else {
+#pragma unroll 4
+            for (int al = 0; al < kNQ; ++al) th[2 * ((al >> 1) * N3 + k) + (al & 1)] = (T)0;
+        }
+    }
+    __syncthreads();
+    fft_lines<T>(r2, I.p3, kNQ / 2 * B, 1, N3, twall, -1);
+
+    C2<T> *out = reinterpret_cast<C2<T> *>(I.spec) + (size_t)row0 * N3h * kNQ;
+    for (int idx = threadIdx.x; idx < B * N3h * kNQ; idx += kThreads) {
+        const int al = idx % kNQ, rest = idx / kNQ;
+        const int k = rest % N3h, rb = rest / N3h;
+        const C2<T> *Z = r2 + (kNQ / 2 * rb + (al >> 1)) * N3;
+        const C2<T> z = Z[k], zc = cconj(Z[(N3 - k) % N3]);
+        C2<T> y;
+        if ((al & 1) == 0) y = mk<T>((z.x + zc.x) * (T)0.5, (z.y + zc.y) * (T)0.5);
+        else y = mk<T>((z.y - zc.y) * (T)0.5, -(z.x - zc.x) * (T)0.5);
+        out[idx] = y;
+    }
+    const double s = block_sum(de);
+    if (threadIdx.x == 0) I.part_de[t.slot] = s;
+}
+
+// C2R of the 20 u_a rows; v_loc = sum_a u_a dtheta_a/dn + de/dn;
+// w = g grad n with g = sum_a u_a 2 n p'_a Q dq/dsigma + de/dsigma-part;
+// R2C of the three w rows.  tile: a = first row, b = rows.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_x_assemble(const InstDev *insts, const Tile *tiles,
+                                                         const Consts *cst, const void *twv) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const Tile t = tiles[blockIdx.x];
+    const InstDev &I = insts[t.inst];
+    const int N3 = I.n3, N3h = I.n3h, row0 = t.a, B = t.b;
+    const size_t N = (size_t)I.n1 * I.n2 * I.n3;
+    C2<T> *r1 = reinterpret_cast<C2<T> *>(smem);          // 2 lines per row: w1 + i w2, w3
+    C2<T> *r2 = r1 + 2 * B * N3;                           // 10 lines per row: u pairs
+    T *qm = reinterpret_cast<T *>(r2 + kNQ / 2 * B * N3);
+    T *Mm = qm + kNQ;
+    load_consts<T>(cst, qm, Mm);
+    const C2<T> *twall = reinterpret_cast<const C2<T> *>(twv);
+
+    const C2<T> *sp = reinterpret_cast<const C2<T> *>(I.spec) + (size_t)row0 * N3h * kNQ;
+    for (int idx = threadIdx.x; idx < B * N3 * (kNQ / 2); idx += kThreads) {
+        const int m = idx % (kNQ / 2), rest = idx / (kNQ / 2);
+        const int k = rest % N3, rb = rest / N3;
+        const bool cj = k >= N3h;
+        const int kk = cj ? N3 - k : k;
+        const C2<T> *src = sp + ((size_t)rb * N3h + kk) * kNQ + 2 * m;
+        C2<T> ya = src[0], yb = src[1];
+        if (cj) { ya = cconj(ya); yb = cconj(yb); }
+        r2[(kNQ / 2 * rb + m) * N3 + k] = mk<T>(ya.x - yb.y, ya.y + yb.x);
+    }
+    __syncthreads();
+    fft_lines<T>(r2, I.p3, kNQ / 2 * B, 1, N3, twall, +1);
+
+    const Consts c = *cst;
+    const T *nin = reinterpret_cast<const T *>(I.n);
+    const T *grad = reinterpret_cast<const T *>(I.grad);
+    T *vloc = reinterpret_cast<T *>(I.vloc);
+    for (int idx = threadIdx.x; idx < B * N3; idx += kThreads) {
+        const int rb = idx / N3, k = idx - rb * N3;
+        const size_t p = (size_t)(row0 + rb) * N3 + k;
+        const T nv = nin[p];
+        const T gx = grad[p], gy = grad[N + p], gz = grad[2 * N + p];
+        T vl = (T)0, gs = (T)0;
+        if (nv >= (T)c.nmin) {
+            LocalQ<T, true> lq;
+            lq.eval(nv, gx * gx + gy * gy + gz * gz, c);
+            SplinePos<T> spos;
+            spos.locate(lq.q0, qm, kNQ);
+            const T *u = reinterpret_cast<const T *>(r2 + (size_t)(kNQ / 2 * rb) * N3);
+            const T cn = nv * lq.Q * lq.dqdn;
+            T su = (T)0, sdu = (T)0;
+#pragma unroll 4
+            for (int al = 0; al < kNQ; ++al) {
+                T pa, dpa;
+                spos.basis(al, Mm, pa, dpa);
+                const T ua = u[2 * ((al >> 1) * N3 + k) + (al & 1)];
+                su += ua * pa;
+                sdu += ua * dpa;
+            }
+            // dtheta_a/dn = p_a + n p'_a Q dq/dn ; dtheta_a/dgrad n = 2 n p'_a Q dq/dsigma grad n
+            const T q0 = lq.q0, cs = (T)c.cs;
+            const T iq3 = (T)1 / (q0 * q0 * q0), iq4 = iq3 / q0;
+            vl = su + cn * sdu + (T)2 * cs * nv * iq3 - (T)3 * cs * nv * nv * iq4 * lq.Q * lq.dqdn;
+            gs = (T)2 * nv * lq.Q * lq.dqds * sdu - (T)6 * cs * nv * nv * iq4 * lq.Q * lq.dqds;
+        }
+        vloc[p] = vl;
+        r1[(2 * rb) * N3 + k] = mk<T>(gs * gx, gs * gy);
+        r1[(2 * rb + 1) * N3 + k] = mk<T>(gs * gz, (T)0);
+    }
+    __syncthreads();
+    fft_lines<T>(r1, I.p3, 2 * B, 1, N3, twall, -1);
+
+    C2<T> *out = reinterpret_cast<C2<T> *>(I.spec3) + (size_t)row0 * N3h * 3;
+    for (int idx = threadIdx.x; idx < B * N3h * 3; idx += kThreads) {
+        const int comp = idx % 3, rest = idx / 3;
+        const int k = rest % N3h, rb = rest / N3h;
+        const C2<T> *Z = r1 + (2 * rb + (comp >> 1)) * N3;
+        const C2<T> z = Z[k], zc = cconj(Z[(N3 - k) % N3]);
+        C2<T> y;
+        if (comp != 1) y = mk<T>((z.x + zc.x) * (T)0.5, (z.y + zc.y) * (T)0.5);
+        else y = mk<T>((z.y - zc.y) * (T)0.5, -(z.x - zc.x) * (T)0.5);
+        out[idx] = y;
+    }
+}
+
+// C2R of the divergence spectrum (row pairs), v = v_loc - div.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_x_final(const InstDev *insts, const Tile *tiles,
+                                                      const void *twv) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    C2<T> *buf = reinterpret_cast<C2<T> *>(smem);
+    const Tile t = tiles[blockIdx.x];
+    const InstDev &I = insts[t.inst];
+    const int N3 = I.n3, N3h = I.n3h, row0 = t.a, B = t.b, np = B / 2;
+    const C2<T> *s1 = reinterpret_cast<const C2<T> *>(I.spec1) + (size_t)row0 * N3h;
+    for (int idx = threadIdx.x; idx < np * N3; idx += kThreads) {
+        const int pr = idx / N3, k = idx - pr * N3;
+        const bool cj = k >= N3h;
+        const int kk = cj ? N3 - k : k;
+        C2<T> ya = s1[(2 * pr) * N3h + kk], yb = s1[(2 * pr + 1) * N3h + kk];
+        if (cj) { ya = cconj(ya); yb = cconj(yb); }
+        buf[idx] = mk<T>(ya.x - yb.y, ya.y + yb.x);
+    }
+    __syncthreads();
+    fft_lines<T>(buf, I.p3, np, 1, N3, reinterpret_cast<const C2<T> *>(twv), +1);
+    const T *vloc = reinterpret_cast<const T *>(I.vloc) + (size_t)row0 * N3;
+    T *v = reinterpret_cast<T *>(I.v) + (size_t)row0 * N3;
+    for (int idx = threadIdx.x; idx < B * N3; idx += kThreads) {
+        const int rb = idx / N3, k = idx - rb * N3;
+        const C2<T> z = buf[(rb >> 1) * N3 + k];
+        v[idx] = vloc[idx] - ((rb & 1) ? z.y : z.x);
+    }
+}
+
+// ---------------------------------------------------------------- axis-2 pass
+
+// tile: a = i1, b = first flattened (k3, component) index, c = width
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_y(const InstDev *insts, const Tile *tiles,
+                                                const void *twv, int which, int V, int sign) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    C2<T> *buf = reinterpret_cast<C2<T> *>(smem);
+    const Tile t = tiles[blockIdx.x];
+    const InstDev &I = insts[t.inst];
+    const int N2 = I.n2, W = t.c;
+    const size_t rowlen = (size_t)I.n3h * V;
+    void *base = which == 0 ? I.spec : (which == 1 ? I.spec3 : I.spec1);
+    C2<T> *g = reinterpret_cast<C2<T> *>(base) + (size_t)t.a * N2 * rowlen + t.b;
+    for (int idx = threadIdx.x; idx < N2 * W; idx += kThreads) {
+        const int l = idx / W, w = idx - l * W;
+        buf[idx] = g[l * rowlen + w];
+    }
+    __syncthreads();
+    fft_lines<T>(buf, I.p2, W, W, 1, reinterpret_cast<const C2<T> *>(twv), sign);
+    for (int idx = threadIdx.x; idx < N2 * W; idx += kThreads) {
+        const int l = idx / W, w = idx - l * W;
+        g[l * rowlen + w] = buf[idx];
+    }
+}
+
+// ---------------------------------------------------------------- axis-1 passes
+
+// n spectrum -> i G_c n / N, c = 1..3.  tile: a = k2, b = first k3, c = count
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_z_grad(const InstDev *insts, const Tile *tiles,
+                                                     const void *twv) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const Tile t = tiles[blockIdx.x];
+    const InstDev &I = insts[t.inst];
+    const int N1 = I.n1, N2 = I.n2, N3 = I.n3, N3h = I.n3h, k2 = t.a, k30 = t.b, K3 = t.c;
+    C2<T> *bin = reinterpret_cast<C2<T> *>(smem);
+    C2<T> *bout = bin + N1 * K3;
+    const C2<T> *twall = reinterpret_cast<const C2<T> *>(twv);
+    const C2<T> *gin = reinterpret_cast<const C2<T> *>(I.spec1) + (size_t)k2 * N3h + k30;
+    const size_t sin_ = (size_t)N2 * N3h;
+    for (int idx = threadIdx.x; idx < N1 * K3; idx += kThreads) {
+        const int l = idx / K3, w = idx - l * K3;
+        bin[idx] = gin[l * sin_ + w];
+    }
+    __syncthreads();
+    fft_lines<T>(bin, I.p1, K3, K3, 1, twall, -1);
+    const T G2 = (T)(I.g2 * freq_nz(k2, N2));
+    for (int idx = threadIdx.x; idx < N1 * K3; idx += kThreads) {
+        const int l = idx / K3, w = idx - l * K3;
+        const C2<T> nh = cscale(bin[idx], (T)I.inv_n);
+        const T G1 = (T)(I.g1 * freq_nz(l, N1));
+        const T G3 = (T)(I.g3 * freq_nz(k30 + w, N3));
+        C2<T> *o = bout + l * 3 * K3 + 3 * w;
+        o[0] = mk<T>(-G1 * nh.y, G1 * nh.x);
+        o[1] = mk<T>(-G2 * nh.y, G2 * nh.x);
+        o[2] = mk<T>(-G3 * nh.y, G3 * nh.x);
+    }
+    __syncthreads();
+    fft_lines<T>(bout, I.p1, 3 * K3, 3 * K3, 1, twall, +1);
+    C2<T> *gout = reinterpret_cast<C2<T> *>(I.spec3) + ((size_t)k2 * N3h + k30) * 3;
+    for (int idx = threadIdx.x; idx < N1 * 3 * K3; idx += kThreads) {
+        const int l = idx / (3 * K3), w = idx - l * 3 * K3;
+        gout[l * sin_ * 3 + w] = bout[idx];
+    }
+}
+
+// sum_c i G_c w_c / N.  tile: a = k2, b = first k3, c = count
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_z_div(const InstDev *insts, const Tile *tiles,
+                                                    const void *twv) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const Tile t = tiles[blockIdx.x];
+    const InstDev &I = insts[t.inst];
+    const int N1 = I.n1, N2 = I.n2, N3 = I.n3, N3h = I.n3h, k2 = t.a, k30 = t.b, K3 = t.c;
+    C2<T> *bin = reinterpret_cast<C2<T> *>(smem);
+    C2<T> *bout = bin + N1 * 3 * K3;
+    const C2<T> *twall = reinterpret_cast<const C2<T> *>(twv);
+    const size_t sin_ = (size_t)N2 * N3h;
+    const C2<T> *gin = reinterpret_cast<const C2<T> *>(I.spec3) + ((size_t)k2 * N3h + k30) * 3;
+    for (int idx = threadIdx.x; idx < N1 * 3 * K3; idx += kThreads) {
+        const int l = idx / (3 * K3), w = idx - l * 3 * K3;
+        bin[idx] = gin[l * sin_ * 3 + w];
+    }
+    __syncthreads();
+    fft_lines<T>(bin, I.p1, 3 * K3, 3 * K3, 1, twall, -1);
+    const T G2 = (T)(I.g2 * freq_nz(k2, N2));
+    for (int idx = threadIdx.x; idx < N1 * K3; idx += kThreads) {
+        const int l = idx / K3, w = idx - l * K3;
+        const C2<T> *x = bin + l * 3 * K3 + 3 * w;
+        const T G1 = (T)(I.g1 * freq_nz(l, N1));
+        const T G3 = (T)(I.g3 * freq_nz(k30 + w, N3));
+        const T sx = G1 * x[0].x + G2 * x[1].x + G3 * x[2].x;
+        const T sy = G1 * x[0].y + G2 * x[1].y + G3 * x[2].y;
+        bout[idx] = cscale(mk<T>(-sy, sx), (T)I.inv_n);
+    }
+    __syncthreads();
+    fft_lines<T>(bout, I.p1, K3, K3, 1, twall, +1);
+    C2<T> *gout = reinterpret_cast<C2<T> *>(I.spec1) + (size_t)k2 * N3h + k30;
+    for (int idx = threadIdx.x; idx < N1 * K3; idx += kThreads) {
+        const int l = idx / K3, w = idx - l * K3;
+        gout[l * sin_ + w] = bout[idx];
+    }
+}
+
+// Forward axis-1 FFT of the 20 theta spectra, u_a(G) = sum_b phi_ab(|G|) c_b(G)
+// with c = Theta / N (Eq. Eoffk, Eq. epsofk), the energy sum
+// sum_G w_G sum_a Re(c_a^* u_a), inverse axis-1 FFT.  tile: a = k2, b = first k3, c = count
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_z_main(const InstDev *insts, const Tile *tiles,
+                                                     const void *twv) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const Tile t = tiles[blockIdx.x];
+    const InstDev &I = insts[t.inst];
+    const int N1 = I.n1, N2 = I.n2, N3 = I.n3, N3h = I.n3h, k2 = t.a, k30 = t.b, K3 = t.c;
+    const int W = K3 * kNQ;
+    C2<T> *buf = reinterpret_cast<C2<T> *>(smem);
+    const C2<T> *twall = reinterpret_cast<const C2<T> *>(twv);
+    const size_t stride = (size_t)N2 * N3h * kNQ;
+    C2<T> *g = reinterpret_cast<C2<T> *>(I.spec) + ((size_t)k2 * N3h + k30) * kNQ;
+    for (int idx = threadIdx.x; idx < N1 * W; idx += kThreads) {
+        const int l = idx / W, w = idx - l * W;
+        buf[idx] = g[l * stride + w];
+    }
+    __syncthreads();
+    fft_lines<T>(buf, I.p1, W, W, 1, twall, -1);
+
+    const T *tab = reinterpret_cast<const T *>(I.shelltab);
+    const int m2 = freq_abs(k2, N2);
+    const T inv_n = (T)I.inv_n;
+    double e = 0.0;
+    for (int idx = threadIdx.x; idx < N1 * K3; idx += kThreads) {
+        const int l = idx / K3, w = idx - l * K3;
+        const int k3 = k30 + w;
+        const int s = I.shellmap[((size_t)freq_abs(l, N1) * I.h2 + m2) * N3h + k3];
+        const T *ph = tab + (size_t)s * kNPair;
+        C2<T> *x = buf + l * W + w * kNQ;
+        C2<T> th[kNQ], u[kNQ];
+#pragma unroll
+        for (int a = 0; a < kNQ; ++a) {
+            th[a] = cscale(x[a], inv_n);
+            u[a] = mk<T>((T)0, (T)0);
+        }
+        int pidx = 0;
+#pragma unroll
+        for (int a = 0; a < kNQ; ++a) {
+#pragma unroll
+            for (int b = a; b < kNQ; ++b) {
+                const T f = ph[pidx++];
+                u[a].x += f * th[b].x;
+                u[a].y += f * th[b].y;
+                if (b != a) {
+                    u[b].x += f * th[a].x;
+                    u[b].y += f * th[a].y;
+                }
+            }
+        }
+        T ek = (T)0;
+#pragma unroll
+        for (int a = 0; a < kNQ; ++a) {
+            ek += th[a].x * u[a].x + th[a].y * u[a].y;
+            x[a] = u[a];
+        }
+        const bool edge = (k3 == 0) || ((N3 & 1) == 0 && k3 == N3 / 2);
+        e += (edge ? 1.0 : 2.0) * (double)ek;
+    }
+    __syncthreads();
+    fft_lines<T>(buf, I.p1, W, W, 1, twall, +1);
+    for (int idx = threadIdx.x; idx < N1 * W; idx += kThreads) {
+        const int l = idx / W, w = idx - l * W;
+        g[l * stride + w] = buf[idx];
+    }
+    const double s = block_sum(e);
+    if (threadIdx.x == 0) I.part_ek[t.slot] = s;
+}
+
+// E_k = (Omega/2) sum of the axis-1 partials; Delta E = dOmega sum of the
+// theta partials.  One workgroup per grid, fixed summation order.
+__global__ void __launch_bounds__(kThreads) k_reduce(const InstDev *insts, double *E) {
+    const InstDev &I = insts[blockIdx.x];
+    double a = 0.0, b = 0.0;
+    for (int i = threadIdx.x; i < I.n_ek; i += kThreads) a += I.part_ek[i];
+    for (int i = threadIdx.x; i < I.n_de; i += kThreads) b += I.part_de[i];
+    a = block_sum(a);
+    b = block_sum(b);
+    if (threadIdx.x == 0) {
+        E[2 * blockIdx.x] = 0.5 * I.omega * a;
+        E[2 * blockIdx.x + 1] = I.dvol * b;
+    }
+}
+
+// ---------------------------------------------------------------- launchers
+
+template <typename T>
+static hipError_t launch_kind_t(int kind, const LaunchArgs &a) {
+    if (a.ntiles <= 0) return hipSuccess;
+    dim3 grid(a.ntiles), block(kThreads);
+    switch (kind) {
+        case KX_NFWD: hipLaunchKernelGGL(k_x_nfwd<T>, grid, block, a.lds, a.stream, a.insts, a.tiles, a.tw); break;
+        case KY_1F: hipLaunchKernelGGL(k_y<T>, grid, block, a.lds, a.stream, a.insts, a.tiles, a.tw, 2, 1, -1); break;
+        case KZ_GRAD: hipLaunchKernelGGL(k_z_grad<T>, grid, block, a.lds, a.stream, a.insts, a.tiles, a.tw); break;
+        case KY_3I: hipLaunchKernelGGL(k_y<T>, grid, block, a.lds, a.stream, a.insts, a.tiles, a.tw, 1, 3, +1); break;
+        case KX_THETA: hipLaunchKernelGGL(k_x_theta<T>, grid, block, a.lds, a.stream, a.insts, a.tiles, a.cst, a.tw); break;
+        case KY_20F: hipLaunchKernelGGL(k_y<T>, grid, block, a.lds, a.stream, a.insts, a.tiles, a.tw, 0, kNQ, -1); break;
+        case KZ_MAIN: hipLaunchKernelGGL(k_z_main<T>, grid, block, a.lds, a.stream, a.insts, a.tiles, a.tw); break;
+        case KY_20I: hipLaunchKernelGGL(k_y<T>, grid, block, a.lds, a.stream, a.insts, a.tiles, a.tw, 0, kNQ, +1); break;
+        case KX_ASSEMBLE: hipLaunchKernelGGL(k_x_assemble<T>, grid, block, a.lds, a.stream, a.insts, a.tiles, a.cst, a.tw); break;
+        case KY_3F: hipLaunchKernelGGL(k_y<T>, grid, block, a.lds, a.stream, a.insts, a.tiles, a.tw, 1, 3, -1); break;
+        case KZ_DIV: hipLaunchKernelGGL(k_z_div<T>, grid, block, a.lds, a.stream, a.insts, a.tiles, a.tw); break;
+        case KY_1I: hipLaunchKernelGGL(k_y<T>, grid, block, a.lds, a.stream, a.insts, a.tiles, a.tw, 2, 1, +1); break;
+        case KX_FINAL: hipLaunchKernelGGL(k_x_final<T>, grid, block, a.lds, a.stream, a.insts, a.tiles, a.tw); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_kind(int kind, int precision, const LaunchArgs &a) {
+    return precision == 64 ? launch_kind_t<double>(kind, a) : launch_kind_t<float>(kind, a);
+}
+
+hipError_t launch_reduce(const InstDev *insts, int ninst, double *E, hipStream_t stream) {
+    hipLaunchKernelGGL(k_reduce, dim3(ninst), dim3(kThreads), 0, stream, insts, E);
+    return hipGetLastError();
+}
+
+}  // namespace vdwnl

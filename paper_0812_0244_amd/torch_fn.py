@@ -1,0 +1,63 @@
+"""E_c^nl as a differentiable torch function whose backward is v_nl.
+
+Eq. (Vi) defines v_i = (1/dOmega) dE/dn_i, so the gradient of E with
+respect to the grid values n_i is dOmega * v_i.  The forward pass runs the
+HIP library (which produces E and v together); the backward pass launches
+nothing.  PyTorch provides device memory and the stream only.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from .binding import VdwNl
+
+
+class NonlocalCorrelation:
+    """A planned grid plus kernel table on one device.
+
+    ``table`` is a mapping with ``qmesh``, ``qc``, ``mc``, ``dk``, ``phi``
+    ([nq, nq, nk], radial kernel table) and ``c_soft``.
+    """
+
+    def __init__(self, shape, cell, table, precision: int = 32, device: int = 0):
+        self.shape = tuple(int(s) for s in shape)
+        self.cell = tuple(float(c) for c in cell)
+        self.precision = precision
+        self.device = device
+        self.dtype = torch.float64 if precision == 64 else torch.float32
+        self.dvol = float(np.prod(self.cell)) / float(np.prod(self.shape))
+        self.lib = VdwNl(device)
+        self.lib.set_grid(self.shape, self.cell, 0, precision)
+        self.lib.set_kernel_table(table["qmesh"], table["qc"], int(table.get("mc", 12)), table["dk"],
+                                  table["phi"], table["c_soft"])
+
+    def energy_potential(self, n: torch.Tensor, v: torch.Tensor | None = None):
+        """(E_k, Delta E, v) for a device tensor n of the planned shape and precision."""
+        if n.dtype != self.dtype or tuple(n.shape) != self.shape or not n.is_cuda:
+            raise ValueError("n must be a %s CUDA tensor of shape %s" % (self.dtype, self.shape))
+        n = n.contiguous()
+        if v is None:
+            v = torch.empty_like(n)
+        stream = torch.cuda.current_stream(n.device).cuda_stream
+        ek, de = self.lib.energy_potential(n.data_ptr(), v.data_ptr(), stream)
+        return ek, de, v
+
+    def __call__(self, n: torch.Tensor) -> torch.Tensor:
+        return VdwNlEnergy.apply(n, self)
+
+
+class VdwNlEnergy(torch.autograd.Function):
+    """forward(n) = E_c^nl (FP64 scalar); backward(gE) = gE * dOmega * v_nl."""
+
+    @staticmethod
+    def forward(ctx, n, engine: NonlocalCorrelation):
+        ek, de, v = engine.energy_potential(n.detach())
+        ctx.save_for_backward(v)
+        ctx.dvol = engine.dvol
+        return torch.tensor(ek + de, dtype=torch.float64, device=n.device)
+
+    @staticmethod
+    def backward(ctx, gE):
+        (v,) = ctx.saved_tensors
+        return (gE.to(v.dtype) * ctx.dvol) * v, None

@@ -1,0 +1,132 @@
+"""The C ABI without a GPU: the library loads, exports every function the
+header declares, and its host-side argument checks return the documented
+error codes (host-only context, device = -1)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_0812_0244_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "vdwnl.h")
+
+E = dict(OK=0, ARG=-1, SIZE=-2, NOMEM=-3, TABLE=-4, KRANGE=-5, STATE=-6, HIP=-7)
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(vdwnl_[a-z_]+)\s*\(", text)))
+
+
+def test_header_symbols_exported():
+    lib = B.load_library()
+    names = declared_functions()
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(lib, name), name
+        assert name in B.SIGNATURES, name
+
+
+def test_error_codes_match_header():
+    text = open(HEADER).read()
+    for key, code in E.items():
+        if key == "SIZE":
+            key = "UNSUPPORTED_SIZE"
+        assert re.search(r"VDWNL_E_%s\s*=\s*%d" % (key, code), text) or key == "OK"
+    lib = B.load_library()
+    assert lib.vdwnl_strerror(0) == b"ok"
+    assert lib.vdwnl_strerror(-2) == b"unsupported grid size"
+
+
+def _host_ctx():
+    lib = B.load_library()
+    h = ctypes.c_void_p()
+    assert lib.vdwnl_create(ctypes.byref(h), -1) == 0
+    return lib, h
+
+
+def _set_grid(lib, h, shape, cell=(10.0, 10.0, 10.0), gm=0, prec=32):
+    s = np.array(shape, dtype=np.int32)
+    c = np.array(cell, dtype=np.float64)
+    return lib.vdwnl_set_grid(h, s.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                              c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), gm, prec)
+
+
+@pytest.mark.parametrize("shape,code", [((24, 24, 24), 0), ((96, 96, 96), 0), ((160, 160, 320), 0),
+                                        ((12, 30, 50), 0), ((14, 24, 24), -2), ((24, 24, 3), -2),
+                                        ((256, 24, 24), -2), ((24, 24, 512), -2), ((15, 15, 16), -2)])
+def test_grid_validation(shape, code):
+    lib, h = _host_ctx()
+    assert _set_grid(lib, h, shape) == code
+    lib.vdwnl_destroy(h)
+
+
+def test_bad_arguments():
+    lib, h = _host_ctx()
+    assert _set_grid(lib, h, (24, 24, 24), cell=(10.0, -1.0, 10.0)) == E["ARG"]
+    assert _set_grid(lib, h, (24, 24, 24), prec=16) == E["ARG"]
+    assert _set_grid(lib, h, (24, 24, 24), gm=1) == E["ARG"]
+    assert lib.vdwnl_set_grid(None, None, None, 0, 32) == E["ARG"]
+    assert lib.vdwnl_energy_potential(None, None, None, None, None) == E["ARG"]
+    # evaluation on a host-only context
+    assert _set_grid(lib, h, (24, 24, 24)) == 0
+    Eo = np.zeros(2)
+    rc = lib.vdwnl_energy_potential(h, ctypes.c_void_p(16), ctypes.c_void_p(16),
+                                    Eo.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), None)
+    assert rc == E["STATE"]
+    lib.vdwnl_destroy(h)
+
+
+def _table(nq=20, nk=64, dk=0.5, sym=True, qlast=5.0):
+    q = np.linspace(0.05, qlast, nq)
+    phi = np.random.default_rng(0).normal(size=(nq, nq, nk))
+    if sym:
+        phi = phi + phi.transpose(1, 0, 2)
+    return q, phi, dk
+
+
+def _set_table(lib, h, q, phi, dk, qc=5.0, mc=12):
+    q = np.ascontiguousarray(q)
+    phi = np.ascontiguousarray(phi)
+    dp = ctypes.POINTER(ctypes.c_double)
+    return lib.vdwnl_set_kernel_table(h, q.size, q.ctypes.data_as(dp), qc, mc, phi.shape[-1], dk,
+                                      phi.ctypes.data_as(dp), 0.04)
+
+
+def test_table_validation():
+    lib, h = _host_ctx()
+    q, phi, dk = _table()
+    assert _set_table(lib, h, q, phi, dk) == 0
+    assert _set_table(lib, h, *_table(sym=False)) == E["TABLE"]
+    assert _set_table(lib, h, *_table(nq=12)) == E["TABLE"]
+    assert _set_table(lib, h, *_table(qlast=4.0)) == E["TABLE"]
+    qbad = q.copy()
+    qbad[5] = qbad[4]
+    assert _set_table(lib, h, qbad, phi, dk) == E["TABLE"]
+    assert _set_table(lib, h, q, phi, dk, mc=0) == E["TABLE"]
+    lib.vdwnl_destroy(h)
+
+
+def test_kernel_table_range_checked_against_grid():
+    """max |G| of a 96^3 grid in a 20 bohr cell is 26.1 bohr^-1: a table to
+    k = 31.5 covers it, one to k = 15.5 does not."""
+    lib, h = _host_ctx()
+    assert _set_grid(lib, h, (96, 96, 96), cell=(20.0, 20.0, 20.0)) == 0
+    q, phi, _ = _table(nk=64)
+    assert _set_table(lib, h, q, phi, 0.5) == 0
+    assert _set_table(lib, h, q, phi, 0.25) == E["KRANGE"]
+    lib.vdwnl_destroy(h)
+
+
+def test_binding_fails_loudly_without_library(tmp_path):
+    saved = B._lib
+    B._lib = None
+    try:
+        with pytest.raises(RuntimeError):
+            B.load_library(str(tmp_path / "missing.so"))
+    finally:
+        B._lib = saved
