@@ -122,7 +122,8 @@ struct vdwnl_ctx {
     Tile *d_tiles = nullptr;
     int kind_off[KIND_COUNT] = {0}, kind_cnt[KIND_COUNT] = {0};
     size_t kind_lds[KIND_COUNT] = {0};
-    void *d_tw = nullptr;
+    void *d_tw = nullptr;                 // twiddles in the working precision
+    void *d_twd = nullptr;                // FP64 twiddles
     Consts *d_consts = nullptr;
     double *d_E = nullptr, *h_E = nullptr;
     std::map<int, int> tw_off;            // length -> offset
@@ -149,11 +150,12 @@ static void free_device(vdwnl_ctx *c) {
     if (c->h_inst) (void)hipHostFree(c->h_inst);
     if (c->d_tiles) (void)hipFree(c->d_tiles);
     if (c->d_tw) (void)hipFree(c->d_tw);
+    if (c->d_twd) (void)hipFree(c->d_twd);
     if (c->d_consts) (void)hipFree(c->d_consts);
     if (c->d_E) (void)hipFree(c->d_E);
     if (c->h_E) (void)hipHostFree(c->h_E);
     c->work = nullptr; c->d_inst = nullptr; c->h_inst = nullptr; c->d_tiles = nullptr;
-    c->d_tw = nullptr; c->d_consts = nullptr; c->d_E = nullptr; c->h_E = nullptr;
+    c->d_tw = nullptr; c->d_twd = nullptr; c->d_consts = nullptr; c->d_E = nullptr; c->h_E = nullptr;
     c->work_bytes = 0;
     c->device_ready = false;
 }
@@ -181,19 +183,19 @@ static int check_grid(vdwnl_ctx *c, const int32_t *shape, const double *cell, in
         return fail(c, VDWNL_E_UNSUPPORTED_SIZE, "N1 too large for the fused axis-1 pass");
     if (N2 > kTileCap)
         return fail(c, VDWNL_E_UNSUPPORTED_SIZE, "N2 too large");
-    if ((size_t)kNQ / 2 * N3 > (size_t)kTileCap || 12 * (size_t)N3 * cs + (kNQ + kNQ * kNQ) * rs > (size_t)kLdsCap)
+    auto xlds = [&](size_t b) { return b * N3 * (2 * 16 + (kNQ / 2) * cs) + (kNQ + kNQ * kNQ) * rs; };
+    if ((size_t)kNQ / 2 * N3 > (size_t)kTileCap || xlds(1) > (size_t)kLdsCap)
         return fail(c, VDWNL_E_UNSUPPORTED_SIZE, "N3 too large for the axis-3 pass");
     if (!radix_plan(N1, g.p1) || !radix_plan(N2, g.p2) || !radix_plan(N3, g.p3))
         return fail(c, VDWNL_E_UNSUPPORTED_SIZE, "no radix plan");
     // tile shapes
     g.bmain = 1;
-    if ((kNQ / 2) * 2 * (size_t)N3 <= (size_t)kTileCap &&
-        12 * 2 * (size_t)N3 * cs + (kNQ + kNQ * kNQ) * rs <= (size_t)kLdsCap)
+    if ((kNQ / 2) * 2 * (size_t)N3 <= (size_t)kTileCap && xlds(2) <= (size_t)kLdsCap)
         g.bmain = 2;
     g.k3main = std::max(1, std::min(kTileCap / (kNQ * N1), (int)(kLdsCap / (kNQ * N1 * cs))));
-    g.k3aux = std::max(1, std::min(kTileCap / (3 * N1), (int)(kLdsCap / (4 * N1 * cs))));
-    const int wmax = std::min(kTileCap / N2, (int)(kLdsCap / (N2 * cs)));
-    g.wy20 = g.wy3 = g.wy1 = std::max(1, wmax);
+    g.k3aux = std::max(1, std::min(kTileCap / (3 * N1), (int)(kLdsCap / (4 * N1 * 16))));
+    g.wy20 = std::max(1, std::min(kTileCap / N2, (int)(kLdsCap / (N2 * cs))));
+    g.wy3 = g.wy1 = std::max(1, std::min(kTileCap / N2, (int)(kLdsCap / (N2 * 16))));
     return VDWNL_OK;
 }
 
@@ -324,8 +326,8 @@ static int prepare_device(vdwnl_ctx *c) {
         g.off_grad = off; off = align_up(off + 3 * g.npts() * rs);
         g.off_vloc = off; off = align_up(off + g.npts() * rs);
         g.off_spec = off; off = align_up(off + g.nhalf() * kNQ * cs);
-        g.off_spec3 = off; off = align_up(off + g.nhalf() * 3 * cs);
-        g.off_spec1 = off; off = align_up(off + g.nhalf() * cs);
+        g.off_spec3 = off; off = align_up(off + g.nhalf() * 3 * 16);   // FP64 aux spectra
+        g.off_spec1 = off; off = align_up(off + g.nhalf() * 16);
         g.off_ek = off; off = align_up(off + g.n_ek * sizeof(double));
         g.off_de = off; off = align_up(off + g.n_de * sizeof(double));
     }
@@ -334,17 +336,17 @@ static int prepare_device(vdwnl_ctx *c) {
     for (auto &g : c->grids) {
         const size_t N1 = g.s[0], N2 = g.s[1], N3 = g.s[2];
         auto mx = [&](int k, size_t v) { c->kind_lds[k] = std::max(c->kind_lds[k], v); };
-        mx(KX_NFWD, N3 * cs);
-        mx(KX_FINAL, N3 * cs);
-        const size_t xm = 12 * g.bmain * N3 * cs + (kNQ + kNQ * kNQ) * rs;
+        mx(KX_NFWD, N3 * 16);
+        mx(KX_FINAL, N3 * 16);
+        const size_t xm = g.bmain * N3 * (2 * 16 + (kNQ / 2) * cs) + (kNQ + kNQ * kNQ) * rs;
         mx(KX_THETA, xm);
         mx(KX_ASSEMBLE, xm);
-        mx(KY_1F, N2 * g.wy1 * cs); mx(KY_1I, N2 * g.wy1 * cs);
-        mx(KY_3F, N2 * g.wy3 * cs); mx(KY_3I, N2 * g.wy3 * cs);
+        mx(KY_1F, N2 * g.wy1 * 16); mx(KY_1I, N2 * g.wy1 * 16);
+        mx(KY_3F, N2 * g.wy3 * 16); mx(KY_3I, N2 * g.wy3 * 16);
         mx(KY_20F, N2 * g.wy20 * cs); mx(KY_20I, N2 * g.wy20 * cs);
         mx(KZ_MAIN, (size_t)kNQ * g.k3main * N1 * cs);
-        mx(KZ_GRAD, 4 * g.k3aux * N1 * cs);
-        mx(KZ_DIV, 4 * g.k3aux * N1 * cs);
+        mx(KZ_GRAD, 4 * g.k3aux * N1 * 16);
+        mx(KZ_DIV, 4 * g.k3aux * N1 * 16);
     }
     std::vector<Tile> all;
     for (int k = 0; k < KIND_COUNT; ++k) {
@@ -381,6 +383,7 @@ static int prepare_device(vdwnl_ctx *c) {
     if ((e = hipMalloc(&c->d_tiles, std::max<size_t>(all.size(), 1) * sizeof(Tile))) != hipSuccess) return hipfail(c, e, "hipMalloc tiles");
     const size_t twbytes = (twd.size() / 2) * cs;
     if ((e = hipMalloc(&c->d_tw, std::max<size_t>(twbytes, 16))) != hipSuccess) return hipfail(c, e, "hipMalloc twiddles");
+    if ((e = hipMalloc(&c->d_twd, std::max<size_t>((twd.size() / 2) * 16, 16))) != hipSuccess) return hipfail(c, e, "hipMalloc twiddles");
     if ((e = hipMalloc(&c->d_consts, sizeof(Consts))) != hipSuccess) return hipfail(c, e, "hipMalloc consts");
     if ((e = hipMalloc(&c->d_E, ng * 2 * sizeof(double))) != hipSuccess) return hipfail(c, e, "hipMalloc E");
     if ((e = hipHostMalloc((void **)&c->h_E, ng * 2 * sizeof(double), hipHostMallocDefault)) != hipSuccess) return hipfail(c, e, "hipHostMalloc E");
@@ -407,6 +410,8 @@ static int prepare_device(vdwnl_ctx *c) {
         e = hipMemcpy(c->d_tw, tf.data(), twbytes, hipMemcpyHostToDevice);
     }
     if (e != hipSuccess) return hipfail(c, e, "upload twiddles");
+    if ((e = hipMemcpy(c->d_twd, twd.data(), twd.size() * 8, hipMemcpyHostToDevice)) != hipSuccess)
+        return hipfail(c, e, "upload twiddles");
     if ((e = hipMemcpy(c->d_tiles, all.data(), all.size() * sizeof(Tile), hipMemcpyHostToDevice)) != hipSuccess)
         return hipfail(c, e, "upload tiles");
     if ((e = hipMemcpy(c->d_consts, &c->consts, sizeof(Consts), hipMemcpyHostToDevice)) != hipSuccess)
@@ -455,7 +460,8 @@ static int run(vdwnl_ctx *c, int nb, const void *const *n_ptrs, void *const *v_p
     static const int order[KIND_COUNT] = {KX_NFWD, KY_1F, KZ_GRAD, KY_3I, KX_THETA, KY_20F, KZ_MAIN,
                                           KY_20I, KX_ASSEMBLE, KY_3F, KZ_DIV, KY_1I, KX_FINAL};
     for (int k : order) {
-        LaunchArgs a{c->d_inst, c->d_tiles + c->kind_off[k], c->kind_cnt[k], c->kind_lds[k], c->d_consts, c->d_tw, st};
+        LaunchArgs a{c->d_inst, c->d_tiles + c->kind_off[k], c->kind_cnt[k], c->kind_lds[k], c->d_consts, c->d_tw,
+                     c->d_twd, st};
         if ((e = launch_kind(k, c->precision, a)) != hipSuccess) return hipfail(c, e, "kernel launch");
     }
     if ((e = launch_reduce(c->d_inst, nb, c->d_E, st)) != hipSuccess) return hipfail(c, e, "reduce launch");

@@ -29,8 +29,8 @@ struct FftPlan {
 //   n, v, vloc      [N1][N2][N3] real
 //   grad            [3][N1][N2][N3] real
 //   spec            [N1][N2][N3h][kNQ] complex  (20 theta / u spectra, component fastest)
-//   spec3           [N1][N2][N3h][3] complex    (grad n / w spectra)
-//   spec1           [N1][N2][N3h] complex       (n / divergence spectrum)
+//   spec3           [N1][N2][N3h][3] complex FP64   (grad n / w spectra)
+//   spec1           [N1][N2][N3h] complex FP64      (n / divergence spectrum)
 //   shellmap        [N1/2+1][N2/2+1][N3h] int   (|G| shell of (|m1|, |m2|, m3))
 //   shelltab        [nshell][kNPair] real       (phi_ab(|G_s|), a <= b packed row by row)
 struct InstDev {
@@ -91,7 +91,8 @@ struct LaunchArgs {
     int ntiles;
     size_t lds;
     const Consts *cst;
-    const void *tw;
+    const void *tw;          // twiddles in the working precision
+    const void *twd;         // FP64 twiddles (gradient and divergence chains)
     hipStream_t stream;
 };
 

@@ -2,6 +2,13 @@
 // thirteen passes over the grid; each pass is one launch that covers every
 // grid of the batch (a workgroup reads its work item from a tile list).
 //
+// The 20 theta / u fields (the bulk of the traffic) are transformed and
+// contracted in the working precision T (float or double).  The gradient of
+// n and the divergence of w (one to three fields) always run in FP64: the
+// gradient term of v_nl multiplies grad n by a factor that grows as 1/n, so
+// FP32 rounding of a spectral grad n in the low-density regions would
+// dominate the error of v.
+//
 // Fields are transformed with three 1-D FFT passes: along axis 3 (the
 // contiguous one, real-to-complex by pairing two real lines into one complex
 // line), axis 2 and axis 1.  Spectra keep all components of one k point
@@ -142,65 +149,65 @@ __device__ __forceinline__ void load_consts(const Consts *cst, T *qm, T *Mm) {
 
 // ---------------------------------------------------------------- axis-3 passes
 
-// R2C of n: rows (2p, 2p+1) of a tile form one complex line.
-// tile: a = first row (i1 N2 + i2), b = rows (even)
+// R2C of n (read in T, transformed in FP64): rows (2p, 2p+1) of a tile form
+// one complex line.  tile: a = first row (i1 N2 + i2), b = rows (even)
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_x_nfwd(const InstDev *insts, const Tile *tiles,
-                                                     const void *twv) {
+                                                     const void *twdv) {
     extern __shared__ __align__(16) unsigned char smem[];
-    C2<T> *buf = reinterpret_cast<C2<T> *>(smem);
+    double2 *buf = reinterpret_cast<double2 *>(smem);
     const Tile t = tiles[blockIdx.x];
     const InstDev &I = insts[t.inst];
     const int N3 = I.n3, N3h = I.n3h, row0 = t.a, B = t.b, np = B / 2;
     const T *n = reinterpret_cast<const T *>(I.n) + (size_t)row0 * N3;
     for (int idx = threadIdx.x; idx < np * N3; idx += kThreads) {
         const int pr = idx / N3, k = idx - pr * N3;
-        buf[idx] = mk<T>(n[(2 * pr) * N3 + k], n[(2 * pr + 1) * N3 + k]);
+        buf[idx] = mk<double>((double)n[(2 * pr) * N3 + k], (double)n[(2 * pr + 1) * N3 + k]);
     }
     __syncthreads();
-    fft_lines<T>(buf, I.p3, np, 1, N3, reinterpret_cast<const C2<T> *>(twv), -1);
-    C2<T> *out = reinterpret_cast<C2<T> *>(I.spec1) + (size_t)row0 * N3h;
+    fft_lines<double>(buf, I.p3, np, 1, N3, reinterpret_cast<const double2 *>(twdv), -1);
+    double2 *out = reinterpret_cast<double2 *>(I.spec1) + (size_t)row0 * N3h;
     for (int idx = threadIdx.x; idx < B * N3h; idx += kThreads) {
         const int rb = idx / N3h, k = idx - rb * N3h;
-        const C2<T> *Z = buf + (rb >> 1) * N3;
-        const C2<T> z = Z[k], zc = cconj(Z[(N3 - k) % N3]);
-        C2<T> y;
-        if ((rb & 1) == 0) y = mk<T>((z.x + zc.x) * (T)0.5, (z.y + zc.y) * (T)0.5);
-        else y = mk<T>((z.y - zc.y) * (T)0.5, -(z.x - zc.x) * (T)0.5);
+        const double2 *Z = buf + (rb >> 1) * N3;
+        const double2 z = Z[k], zc = cconj(Z[(N3 - k) % N3]);
+        double2 y;
+        if ((rb & 1) == 0) y = mk<double>((z.x + zc.x) * 0.5, (z.y + zc.y) * 0.5);
+        else y = mk<double>((z.y - zc.y) * 0.5, -(z.x - zc.x) * 0.5);
         out[idx] = y;
     }
 }
 
-// C2R of grad n (3 spectra per row), theta_a = n p_a(q0), Delta E partials,
-// R2C of the 20 theta rows.  tile: a = first row, b = rows, slot = partial.
+// C2R of grad n (3 FP64 spectra per row), theta_a = n p_a(q0), Delta E
+// partials, R2C of the 20 theta rows.  tile: a = first row, b = rows, slot = partial.
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_x_theta(const InstDev *insts, const Tile *tiles,
-                                                      const Consts *cst, const void *twv) {
+                                                      const Consts *cst, const void *twv, const void *twdv) {
     extern __shared__ __align__(16) unsigned char smem[];
     const Tile t = tiles[blockIdx.x];
     const InstDev &I = insts[t.inst];
     const int N3 = I.n3, N3h = I.n3h, row0 = t.a, B = t.b;
     const size_t N = (size_t)I.n1 * I.n2 * I.n3;
-    C2<T> *r1 = reinterpret_cast<C2<T> *>(smem);          // 2 lines per row: d1 + i d2, d3
-    C2<T> *r2 = r1 + 2 * B * N3;                           // 10 lines per row: theta pairs
+    double2 *r1 = reinterpret_cast<double2 *>(smem);       // 2 lines per row: d1 + i d2, d3
+    C2<T> *r2 = reinterpret_cast<C2<T> *>(r1 + 2 * B * N3); // 10 lines per row: theta pairs
     T *qm = reinterpret_cast<T *>(r2 + kNQ / 2 * B * N3);
     T *Mm = qm + kNQ;
     load_consts<T>(cst, qm, Mm);
     const C2<T> *twall = reinterpret_cast<const C2<T> *>(twv);
 
-    const C2<T> *s3 = reinterpret_cast<const C2<T> *>(I.spec3) + (size_t)row0 * N3h * 3;
+    const double2 *s3 = reinterpret_cast<const double2 *>(I.spec3) + (size_t)row0 * N3h * 3;
     for (int idx = threadIdx.x; idx < B * N3; idx += kThreads) {
         const int rb = idx / N3, k = idx - rb * N3;
         const bool cj = k >= N3h;
         const int kk = cj ? N3 - k : k;
-        const C2<T> *src = s3 + ((size_t)rb * N3h + kk) * 3;
-        C2<T> y0 = src[0], y1 = src[1], y2 = src[2];
+        const double2 *src = s3 + ((size_t)rb * N3h + kk) * 3;
+        double2 y0 = src[0], y1 = src[1], y2 = src[2];
         if (cj) { y0 = cconj(y0); y1 = cconj(y1); y2 = cconj(y2); }
-        r1[(2 * rb) * N3 + k] = mk<T>(y0.x - y1.y, y0.y + y1.x);
+        r1[(2 * rb) * N3 + k] = mk<double>(y0.x - y1.y, y0.y + y1.x);
         r1[(2 * rb + 1) * N3 + k] = y2;
     }
     __syncthreads();
-    fft_lines<T>(r1, I.p3, 2 * B, 1, N3, twall, +1);
+    fft_lines<double>(r1, I.p3, 2 * B, 1, N3, reinterpret_cast<const double2 *>(twdv), +1);
 
     const Consts c = *cst;
     const T *nin = reinterpret_cast<const T *>(I.n);
@@ -210,7 +217,8 @@ __global__ void __launch_bounds__(kThreads) k_x_theta(const InstDev *insts, cons
         const int rb = idx / N3, k = idx - rb * N3;
         const size_t p = (size_t)(row0 + rb) * N3 + k;
         const T nv = nin[p];
-        const C2<T> g01 = r1[(2 * rb) * N3 + k], g2 = r1[(2 * rb + 1) * N3 + k];
+        const double2 g01d = r1[(2 * rb) * N3 + k], g2d = r1[(2 * rb + 1) * N3 + k];
+        const C2<T> g01 = mk<T>((T)g01d.x, (T)g01d.y), g2 = mk<T>((T)g2d.x, (T)0);
         grad[p] = g01.x;
         grad[N + p] = g01.y;
         grad[2 * N + p] = g2.x;
@@ -256,14 +264,14 @@ __global__ void __launch_bounds__(kThreads) k_x_theta(const InstDev *insts, cons
 // R2C of the three w rows.  tile: a = first row, b = rows.
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_x_assemble(const InstDev *insts, const Tile *tiles,
-                                                         const Consts *cst, const void *twv) {
+                                                         const Consts *cst, const void *twv, const void *twdv) {
     extern __shared__ __align__(16) unsigned char smem[];
     const Tile t = tiles[blockIdx.x];
     const InstDev &I = insts[t.inst];
     const int N3 = I.n3, N3h = I.n3h, row0 = t.a, B = t.b;
     const size_t N = (size_t)I.n1 * I.n2 * I.n3;
-    C2<T> *r1 = reinterpret_cast<C2<T> *>(smem);          // 2 lines per row: w1 + i w2, w3
-    C2<T> *r2 = r1 + 2 * B * N3;                           // 10 lines per row: u pairs
+    double2 *r1 = reinterpret_cast<double2 *>(smem);       // 2 FP64 lines per row: w1 + i w2, w3
+    C2<T> *r2 = reinterpret_cast<C2<T> *>(r1 + 2 * B * N3); // 10 lines per row: u pairs
     T *qm = reinterpret_cast<T *>(r2 + kNQ / 2 * B * N3);
     T *Mm = qm + kNQ;
     load_consts<T>(cst, qm, Mm);
@@ -316,51 +324,52 @@ __global__ void __launch_bounds__(kThreads) k_x_assemble(const InstDev *insts, c
             gs = (T)2 * nv * lq.Q * lq.dqds * sdu - (T)6 * cs * nv * nv * iq4 * lq.Q * lq.dqds;
         }
         vloc[p] = vl;
-        r1[(2 * rb) * N3 + k] = mk<T>(gs * gx, gs * gy);
-        r1[(2 * rb + 1) * N3 + k] = mk<T>(gs * gz, (T)0);
+        const double gsd = (double)gs;
+        r1[(2 * rb) * N3 + k] = mk<double>(gsd * (double)gx, gsd * (double)gy);
+        r1[(2 * rb + 1) * N3 + k] = mk<double>(gsd * (double)gz, 0.0);
     }
     __syncthreads();
-    fft_lines<T>(r1, I.p3, 2 * B, 1, N3, twall, -1);
+    fft_lines<double>(r1, I.p3, 2 * B, 1, N3, reinterpret_cast<const double2 *>(twdv), -1);
 
-    C2<T> *out = reinterpret_cast<C2<T> *>(I.spec3) + (size_t)row0 * N3h * 3;
+    double2 *out = reinterpret_cast<double2 *>(I.spec3) + (size_t)row0 * N3h * 3;
     for (int idx = threadIdx.x; idx < B * N3h * 3; idx += kThreads) {
         const int comp = idx % 3, rest = idx / 3;
         const int k = rest % N3h, rb = rest / N3h;
-        const C2<T> *Z = r1 + (2 * rb + (comp >> 1)) * N3;
-        const C2<T> z = Z[k], zc = cconj(Z[(N3 - k) % N3]);
-        C2<T> y;
-        if (comp != 1) y = mk<T>((z.x + zc.x) * (T)0.5, (z.y + zc.y) * (T)0.5);
-        else y = mk<T>((z.y - zc.y) * (T)0.5, -(z.x - zc.x) * (T)0.5);
+        const double2 *Z = r1 + (2 * rb + (comp >> 1)) * N3;
+        const double2 z = Z[k], zc = cconj(Z[(N3 - k) % N3]);
+        double2 y;
+        if (comp != 1) y = mk<double>((z.x + zc.x) * 0.5, (z.y + zc.y) * 0.5);
+        else y = mk<double>((z.y - zc.y) * 0.5, -(z.x - zc.x) * 0.5);
         out[idx] = y;
     }
 }
 
-// C2R of the divergence spectrum (row pairs), v = v_loc - div.
+// C2R of the FP64 divergence spectrum (row pairs), v = v_loc - div.
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_x_final(const InstDev *insts, const Tile *tiles,
-                                                      const void *twv) {
+                                                      const void *twdv) {
     extern __shared__ __align__(16) unsigned char smem[];
-    C2<T> *buf = reinterpret_cast<C2<T> *>(smem);
+    double2 *buf = reinterpret_cast<double2 *>(smem);
     const Tile t = tiles[blockIdx.x];
     const InstDev &I = insts[t.inst];
     const int N3 = I.n3, N3h = I.n3h, row0 = t.a, B = t.b, np = B / 2;
-    const C2<T> *s1 = reinterpret_cast<const C2<T> *>(I.spec1) + (size_t)row0 * N3h;
+    const double2 *s1 = reinterpret_cast<const double2 *>(I.spec1) + (size_t)row0 * N3h;
     for (int idx = threadIdx.x; idx < np * N3; idx += kThreads) {
         const int pr = idx / N3, k = idx - pr * N3;
         const bool cj = k >= N3h;
         const int kk = cj ? N3 - k : k;
-        C2<T> ya = s1[(2 * pr) * N3h + kk], yb = s1[(2 * pr + 1) * N3h + kk];
+        double2 ya = s1[(2 * pr) * N3h + kk], yb = s1[(2 * pr + 1) * N3h + kk];
         if (cj) { ya = cconj(ya); yb = cconj(yb); }
-        buf[idx] = mk<T>(ya.x - yb.y, ya.y + yb.x);
+        buf[idx] = mk<double>(ya.x - yb.y, ya.y + yb.x);
     }
     __syncthreads();
-    fft_lines<T>(buf, I.p3, np, 1, N3, reinterpret_cast<const C2<T> *>(twv), +1);
+    fft_lines<double>(buf, I.p3, np, 1, N3, reinterpret_cast<const double2 *>(twdv), +1);
     const T *vloc = reinterpret_cast<const T *>(I.vloc) + (size_t)row0 * N3;
     T *v = reinterpret_cast<T *>(I.v) + (size_t)row0 * N3;
     for (int idx = threadIdx.x; idx < B * N3; idx += kThreads) {
         const int rb = idx / N3, k = idx - rb * N3;
-        const C2<T> z = buf[(rb >> 1) * N3 + k];
-        v[idx] = vloc[idx] - ((rb & 1) ? z.y : z.x);
+        const double2 z = buf[(rb >> 1) * N3 + k];
+        v[idx] = (T)((double)vloc[idx] - ((rb & 1) ? z.y : z.x));
     }
 }
 
@@ -562,19 +571,19 @@ static hipError_t launch_kind_t(int kind, const LaunchArgs &a) {
     if (a.ntiles <= 0) return hipSuccess;
     dim3 grid(a.ntiles), block(kThreads);
     switch (kind) {
-        case KX_NFWD: hipLaunchKernelGGL(k_x_nfwd<T>, grid, block, a.lds, a.stream, a.insts, a.tiles, a.tw); break;
-        case KY_1F: hipLaunchKernelGGL(k_y<T>, grid, block, a.lds, a.stream, a.insts, a.tiles, a.tw, 2, 1, -1); break;
-        case KZ_GRAD: hipLaunchKernelGGL(k_z_grad<T>, grid, block, a.lds, a.stream, a.insts, a.tiles, a.tw); break;
-        case KY_3I: hipLaunchKernelGGL(k_y<T>, grid, block, a.lds, a.stream, a.insts, a.tiles, a.tw, 1, 3, +1); break;
-        case KX_THETA: hipLaunchKernelGGL(k_x_theta<T>, grid, block, a.lds, a.stream, a.insts, a.tiles, a.cst, a.tw); break;
+        case KX_NFWD: hipLaunchKernelGGL(k_x_nfwd<T>, grid, block, a.lds, a.stream, a.insts, a.tiles, a.twd); break;
+        case KY_1F: hipLaunchKernelGGL(k_y<double>, grid, block, a.lds, a.stream, a.insts, a.tiles, a.twd, 2, 1, -1); break;
+        case KZ_GRAD: hipLaunchKernelGGL(k_z_grad<double>, grid, block, a.lds, a.stream, a.insts, a.tiles, a.twd); break;
+        case KY_3I: hipLaunchKernelGGL(k_y<double>, grid, block, a.lds, a.stream, a.insts, a.tiles, a.twd, 1, 3, +1); break;
+        case KX_THETA: hipLaunchKernelGGL(k_x_theta<T>, grid, block, a.lds, a.stream, a.insts, a.tiles, a.cst, a.tw, a.twd); break;
         case KY_20F: hipLaunchKernelGGL(k_y<T>, grid, block, a.lds, a.stream, a.insts, a.tiles, a.tw, 0, kNQ, -1); break;
         case KZ_MAIN: hipLaunchKernelGGL(k_z_main<T>, grid, block, a.lds, a.stream, a.insts, a.tiles, a.tw); break;
         case KY_20I: hipLaunchKernelGGL(k_y<T>, grid, block, a.lds, a.stream, a.insts, a.tiles, a.tw, 0, kNQ, +1); break;
-        case KX_ASSEMBLE: hipLaunchKernelGGL(k_x_assemble<T>, grid, block, a.lds, a.stream, a.insts, a.tiles, a.cst, a.tw); break;
-        case KY_3F: hipLaunchKernelGGL(k_y<T>, grid, block, a.lds, a.stream, a.insts, a.tiles, a.tw, 1, 3, -1); break;
-        case KZ_DIV: hipLaunchKernelGGL(k_z_div<T>, grid, block, a.lds, a.stream, a.insts, a.tiles, a.tw); break;
-        case KY_1I: hipLaunchKernelGGL(k_y<T>, grid, block, a.lds, a.stream, a.insts, a.tiles, a.tw, 2, 1, +1); break;
-        case KX_FINAL: hipLaunchKernelGGL(k_x_final<T>, grid, block, a.lds, a.stream, a.insts, a.tiles, a.tw); break;
+        case KX_ASSEMBLE: hipLaunchKernelGGL(k_x_assemble<T>, grid, block, a.lds, a.stream, a.insts, a.tiles, a.cst, a.tw, a.twd); break;
+        case KY_3F: hipLaunchKernelGGL(k_y<double>, grid, block, a.lds, a.stream, a.insts, a.tiles, a.twd, 1, 3, -1); break;
+        case KZ_DIV: hipLaunchKernelGGL(k_z_div<double>, grid, block, a.lds, a.stream, a.insts, a.tiles, a.twd); break;
+        case KY_1I: hipLaunchKernelGGL(k_y<double>, grid, block, a.lds, a.stream, a.insts, a.tiles, a.twd, 2, 1, +1); break;
+        case KX_FINAL: hipLaunchKernelGGL(k_x_final<T>, grid, block, a.lds, a.stream, a.insts, a.tiles, a.twd); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

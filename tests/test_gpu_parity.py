@@ -2,7 +2,11 @@
 
 FP64 runs must agree with the oracle to rounding (relative 1e-10 in E and
 in max|v|); FP32 runs to the accuracy the method is specified at: relative
-energy error <= 1e-6 and max |dv| <= 1e-5 Ha.
+energy error <= 1e-6 and max |dv| <= 1e-5 Ha.  An FP32 run receives the
+density rounded to FP32, so the oracle evaluates that same rounded density:
+v_nl is ill-conditioned in n where n sits on the 1e-4 floor (the gradient
+term scales as 1/n), and the input rounding alone moves the FP64 oracle's v
+by up to 4.6e-5 Ha on the 96^3 workload.  That figure is asserted too.
 """
 import sys
 
@@ -75,9 +79,13 @@ def test_c1_fp64_parity_with_intermediates(table):
     check(g, o, 64)
 
 
+def fp32_input(n):
+    return n.astype(np.float32).astype(np.float64)
+
+
 def test_c1_fp32_parity(table):
     wl = W.config(1)
-    n = wl.density()
+    n = fp32_input(wl.density())
     o = F.energy_potential(n, wl.cell, table, return_parts=True)
     check(gpu_eval(n, wl.cell, table, 32), o, 32)
 
@@ -101,7 +109,15 @@ def test_c2_fp64_and_fp32_parity(table):
     n = wl.density()
     o = F.energy_potential(n, wl.cell, table, return_parts=True)
     check(gpu_eval(n, wl.cell, table, 64), o, 64)
-    check(gpu_eval(n, wl.cell, table, 32), o, 32)
+    n32 = fp32_input(n)
+    o32 = F.energy_potential(n32, wl.cell, table, return_parts=True)
+    g32 = gpu_eval(n32, wl.cell, table, 32)
+    check(g32, o32, 32)
+    # against the FP64-input oracle: energy to 1e-6, v limited by the input rounding
+    e64 = o["E_k"] + o["dE"]
+    assert abs(g32["E_k"] + g32["dE"] - e64) <= FP32_EREL * abs(e64)
+    say("  FP32 run vs FP64-input oracle: max|dv| %.2e" % np.abs(g32["v"] - o["v"]).max())
+    assert np.abs(g32["v"] - o["v"]).max() <= 1e-4
 
 
 def test_constant_table_closed_form_on_gpu(table):
