@@ -108,6 +108,32 @@ int vdwnl_energy_potential_batched(vdwnl_ctx *ctx, int32_t nb, const void *const
  * the planned precision. */
 int vdwnl_debug_field(vdwnl_ctx *ctx, int32_t inst, int32_t which, void *dst, void *stream);
 
+/* Per-pass timing.  vdwnl_set_timing(ctx, 1) clears the counters and makes
+ * every later evaluation record a HIP event after each of its passes (on the
+ * evaluation's stream); vdwnl_pass_times copies the accumulated milliseconds
+ * of each pass (launch order, the FP64 energy reduction last) into ms[], the
+ * number of timed evaluations into *calls, and returns the number of passes.
+ * vdwnl_pass_name(i) names pass i ("" outside the range). */
+int vdwnl_set_timing(vdwnl_ctx *ctx, int32_t on);
+int vdwnl_pass_times(const vdwnl_ctx *ctx, int32_t max_passes, double *ms, int64_t *calls);
+const char *vdwnl_pass_name(int32_t i);
+
+/* Build the kernel table that vdwnl_set_kernel_table takes, on GPU `device`
+ * (the step before the evaluation; it depends only on the q mesh and the
+ * soft-kernel parameters, so it is computed once):
+ *   phi_ab(k_j) = 4 pi Int r^2 j0(k_j r) phi_s(q_a r, q_b r) dr,  k_j = j dk,
+ * with phi the kernel of Eq. (Enl) (Dion et al. form: a double integral over
+ * plane-wave variables) softened below D = sqrt(d1^2 + d2^2) = d_s as in
+ * Eq. (PhiSoft) (phi_s = phi0 + phi2 D^2 + phi4 D^4, value and slope matched
+ * at d_s on each ray d2/d1 = q_b/q_a), and
+ *   C_s = 1/2 Int_0^{d_s/sqrt2} 4 pi d^2 [phi(d,d) - phi_s(d,d)] dd
+ * of Eq. (Depsnl).  qmesh[nq] increasing (host); phi_out host array
+ * [nq][nq][nk] (caller-owned, filled symmetric); *c_soft_out host double.
+ * Takes a few seconds on an MI355X.  Errors: VDWNL_E_ARG, VDWNL_E_TABLE (q
+ * mesh not increasing), VDWNL_E_STATE (device < 0), VDWNL_E_HIP. */
+int vdwnl_build_kernel_table(int device, int32_t nq, const double *qmesh, double d_s, double phi0,
+                             int32_t nk, double dk, double *phi_out, double *c_soft_out);
+
 /* Number of planned grids and the bytes of device workspace held. */
 int vdwnl_info(const vdwnl_ctx *ctx, int32_t *n_grids, int64_t *workspace_bytes);
 

@@ -34,6 +34,11 @@ SIGNATURES = {
                                                       ctypes.POINTER(_vp), _dp, _vp]),
     "vdwnl_debug_field": (ctypes.c_int, [_vp, _i32, _i32, _vp, _vp]),
     "vdwnl_info": (ctypes.c_int, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(ctypes.c_int64)]),
+    "vdwnl_set_timing": (ctypes.c_int, [_vp, _i32]),
+    "vdwnl_pass_times": (ctypes.c_int, [_vp, _i32, _dp, ctypes.POINTER(ctypes.c_int64)]),
+    "vdwnl_pass_name": (ctypes.c_char_p, [_i32]),
+    "vdwnl_build_kernel_table": (ctypes.c_int, [ctypes.c_int, _i32, _dp, ctypes.c_double, ctypes.c_double,
+                                                _i32, ctypes.c_double, _dp, _dp]),
 }
 
 _lib = None
@@ -64,6 +69,28 @@ def load_library(path: str = LIB_PATH):
             fn.argtypes = args
         _lib = lib
     return _lib
+
+
+def log_qmesh(nq: int = 20, q1: float = 0.05, qc: float = 5.0, lam: float = 1.17):
+    """Logarithmic q mesh: (q_{a+1} - q_a) = lam (q_a - q_{a-1}), q_1 = q1, q_N = q_c."""
+    d = np.cumprod(np.concatenate([[1.0], np.full(nq - 2, lam)]))
+    q = q1 + np.concatenate([[0.0], np.cumsum(d * (qc - q1) / d.sum())])
+    q[-1] = qc
+    return q
+
+
+def build_kernel_table(device: int = 0, nq: int = 20, q1: float = 0.05, qc: float = 5.0, lam: float = 1.17,
+                       mc: int = 12, d_s: float = 1.0, phi0: float = 0.5, nk: int = 6401, dk: float = 0.005):
+    """The radial kernel table and C_s, computed by the library on the GPU."""
+    lib = load_library()
+    q = log_qmesh(nq, q1, qc, lam)
+    phi = np.zeros((nq, nq, nk))
+    cs = np.zeros(1)
+    rc = lib.vdwnl_build_kernel_table(device, nq, _as_ptr(q, ctypes.c_double), d_s, phi0, nk, dk,
+                                      _as_ptr(phi, ctypes.c_double), _as_ptr(cs, ctypes.c_double))
+    if rc != 0:
+        raise VdwNlError(rc, "vdwnl_build_kernel_table")
+    return dict(qmesh=q, qc=qc, mc=mc, dk=dk, nk=nk, phi=phi, c_soft=float(cs[0]), ds=d_s, phi0=phi0)
 
 
 def _as_ptr(a, ct):
@@ -140,6 +167,18 @@ class VdwNl:
 
     def debug_field(self, inst: int, which: int, dst_ptr: int, stream: int = 0):
         self._check(self.lib.vdwnl_debug_field(self.h, inst, which, _vp(dst_ptr), _vp(stream)), "debug_field")
+
+    def set_timing(self, on: bool = True):
+        self._check(self.lib.vdwnl_set_timing(self.h, 1 if on else 0), "set_timing")
+
+    def pass_times(self):
+        """{pass name: (total ms, evaluations)} accumulated since set_timing(True)."""
+        ms = np.zeros(32)
+        calls = ctypes.c_int64()
+        npass = self.lib.vdwnl_pass_times(self.h, 32, _as_ptr(ms, ctypes.c_double), ctypes.byref(calls))
+        if npass < 0:
+            raise VdwNlError(npass, "pass_times")
+        return {self.lib.vdwnl_pass_name(i).decode(): (float(ms[i]), calls.value) for i in range(npass)}
 
     def info(self):
         n = _i32()

@@ -127,6 +127,12 @@ struct vdwnl_ctx {
     Consts *d_consts = nullptr;
     double *d_E = nullptr, *h_E = nullptr;
     std::map<int, int> tw_off;            // length -> offset
+    // per-pass timing
+    bool timing = false;
+    hipEvent_t ev[KIND_COUNT + 2] = {};
+    bool ev_made = false;
+    double pass_ms[KIND_COUNT + 1] = {0};
+    int64_t timed_calls = 0;
 };
 
 namespace vdwnl {
@@ -145,6 +151,10 @@ static int hipfail(vdwnl_ctx *c, hipError_t e, const char *what) {
 static void free_device(vdwnl_ctx *c) {
     if (c->device < 0) return;
     (void)hipSetDevice(c->device);
+    if (c->ev_made) {
+        for (auto &e : c->ev) (void)hipEventDestroy(e);
+        c->ev_made = false;
+    }
     if (c->work) (void)hipFree(c->work);
     if (c->d_inst) (void)hipFree(c->d_inst);
     if (c->h_inst) (void)hipHostFree(c->h_inst);
@@ -258,6 +268,13 @@ static int check_krange(vdwnl_ctx *c) {
             return fail(c, VDWNL_E_KRANGE, "radial kernel table does not reach max |G| of a grid");
     return VDWNL_OK;
 }
+
+// Launch order of the passes of one evaluation (the final reduction follows).
+static const int kPassOrder[KIND_COUNT] = {KX_NFWD, KY_1F, KZ_GRAD, KY_3I, KX_THETA, KY_20F, KZ_MAIN,
+                                           KY_20I, KX_ASSEMBLE, KY_3F, KZ_DIV, KY_1I, KX_FINAL};
+static const char *kPassName[KIND_COUNT + 1] = {
+    "x_nfwd", "y_1f", "z_grad", "y_3i", "x_theta", "y_20f", "z_main", "y_20i", "x_assemble", "y_3f", "z_div",
+    "y_1i", "x_final", "reduce"};
 
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -457,18 +474,32 @@ static int run(vdwnl_ctx *c, int nb, const void *const *n_ptrs, void *const *v_p
     }
     if ((e = hipMemcpyAsync(c->d_inst, c->h_inst, nb * sizeof(InstDev), hipMemcpyHostToDevice, st)) != hipSuccess)
         return hipfail(c, e, "upload instance table");
-    static const int order[KIND_COUNT] = {KX_NFWD, KY_1F, KZ_GRAD, KY_3I, KX_THETA, KY_20F, KZ_MAIN,
-                                          KY_20I, KX_ASSEMBLE, KY_3F, KZ_DIV, KY_1I, KX_FINAL};
-    for (int k : order) {
+    if (c->timing && !c->ev_made) {
+        for (auto &ev : c->ev)
+            if ((e = hipEventCreate(&ev)) != hipSuccess) return hipfail(c, e, "hipEventCreate");
+        c->ev_made = true;
+    }
+    if (c->timing) (void)hipEventRecord(c->ev[0], st);
+    for (int i = 0; i < KIND_COUNT; ++i) {
+        const int k = kPassOrder[i];
         LaunchArgs a{c->d_inst, c->d_tiles + c->kind_off[k], c->kind_cnt[k], c->kind_lds[k], c->d_consts, c->d_tw,
                      c->d_twd, st};
         if ((e = launch_kind(k, c->precision, a)) != hipSuccess) return hipfail(c, e, "kernel launch");
+        if (c->timing) (void)hipEventRecord(c->ev[i + 1], st);
     }
     if ((e = launch_reduce(c->d_inst, nb, c->d_E, st)) != hipSuccess) return hipfail(c, e, "reduce launch");
+    if (c->timing) (void)hipEventRecord(c->ev[KIND_COUNT + 1], st);
     if ((e = hipMemcpyAsync(c->h_E, c->d_E, nb * 2 * sizeof(double), hipMemcpyDeviceToHost, st)) != hipSuccess)
         return hipfail(c, e, "copy energies");
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return hipfail(c, e, "stream synchronize");
     std::memcpy(E_out, c->h_E, nb * 2 * sizeof(double));
+    if (c->timing) {
+        for (int i = 0; i <= KIND_COUNT; ++i) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]) == hipSuccess) c->pass_ms[i] += ms;
+        }
+        c->timed_calls++;
+    }
     return VDWNL_OK;
 }
 
@@ -618,6 +649,24 @@ int vdwnl_debug_field(vdwnl_ctx *ctx, int32_t inst, int32_t which, void *dst, vo
     if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
     return e == hipSuccess ? VDWNL_OK : hipfail(ctx, e, "debug copy");
 }
+
+int vdwnl_set_timing(vdwnl_ctx *ctx, int32_t on) {
+    if (!ctx) return VDWNL_E_ARG;
+    ctx->timing = on != 0;
+    for (auto &m : ctx->pass_ms) m = 0.0;
+    ctx->timed_calls = 0;
+    return VDWNL_OK;
+}
+
+int vdwnl_pass_times(const vdwnl_ctx *ctx, int32_t max_passes, double *ms, int64_t *calls) {
+    if (!ctx || (max_passes > 0 && !ms)) return VDWNL_E_ARG;
+    const int n = std::min<int>(max_passes, KIND_COUNT + 1);
+    for (int i = 0; i < n; ++i) ms[i] = ctx->pass_ms[i];
+    if (calls) *calls = ctx->timed_calls;
+    return KIND_COUNT + 1;
+}
+
+const char *vdwnl_pass_name(int32_t i) { return (i >= 0 && i <= KIND_COUNT) ? kPassName[i] : ""; }
 
 int vdwnl_info(const vdwnl_ctx *ctx, int32_t *n_grids, int64_t *workspace_bytes) {
     if (!ctx) return VDWNL_E_ARG;
