@@ -1,0 +1,213 @@
+#!/usr/bin/env python3
+"""Throughput of the vdW-DF nonlocal correlation path on one MI355X.
+
+Workload: the batched configuration -- 64 independent Gaussian-atom densities
+with cubic grids drawn from {32, 48, 64, 96, 128}^3 (spacing 20/96 bohr,
+4..128 atoms each, seeds 4000..4063), N_q = 20.  A step is one call of the
+whole path (E_c^nl and v_nl of every density) with the densities already in
+HBM; the FP32 batched call is the headline, the FP64 per-density ("plain")
+evaluation of the same densities is timed beside it and the relative energy
+difference between the two is reported.
+
+Prints one JSON line (rank 0).  `--gpus N` with N > 1 exits: this build runs
+on one GPU.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+
+
+def pass_bytes(name, shapes, s):
+    """Algorithmic bytes one launch of a pass moves over all grids: what it
+    must read and write given its inputs and outputs (spectra as N1 N2
+    (N3/2+1) complex values; the gradient/divergence spectra are FP64)."""
+    tot = 0
+    for (n1, n2, n3) in shapes:
+        N = n1 * n2 * n3
+        NH = n1 * n2 * (n3 // 2 + 1)
+        c, d = 2 * s, 16
+        b = {
+            "x_nfwd": N * s + NH * d,
+            "y_1f": 2 * NH * d, "y_1i": 2 * NH * d,
+            "z_grad": 4 * NH * d, "z_div": 4 * NH * d,
+            "y_3i": 6 * NH * d, "y_3f": 6 * NH * d,
+            "x_theta": 3 * NH * d + 4 * N * s + 20 * NH * c,
+            "y_20f": 40 * NH * c, "z_main": 40 * NH * c, "y_20i": 40 * NH * c,
+            "x_assemble": 20 * NH * c + 5 * N * s + 3 * NH * d,
+            "x_final": NH * d + 2 * N * s,
+            "reduce": 0,
+        }[name]
+        tot += b
+    return tot
+
+
+def cpu_baseline(insts, dens, budget_s):
+    """The FP64 oracle on the smallest densities of the batch, until about
+    budget_s seconds of host work; grid points per second."""
+    from oracle import functional as F
+    from oracle import kernel_table as kt
+    table = dict(kt.kernel_table())
+    table["mc"] = 12
+    order = sorted(range(len(insts)), key=lambda i: insts[i].npoints)
+    done, pts, t_used = [], 0, 0.0
+    F.energy_potential(dens[order[0]], insts[order[0]].cell, table)   # warm the table spline
+    for i in order:
+        t0 = time.perf_counter()
+        F.energy_potential(dens[i], insts[i].cell, table)
+        t_used += time.perf_counter() - t0
+        pts += insts[i].npoints
+        done.append(insts[i].shape[0])
+        if t_used > budget_s:
+            break
+    sizes = {}
+    for n in done:
+        sizes[n] = sizes.get(n, 0) + 1
+    sample = "%d of the 64 densities, smallest first (%s), FP64 NumPy oracle, %.1f s" % (
+        len(done), ", ".join("%dx %d^3" % (v, k) for k, v in sorted(sizes.items())), t_used)
+    return dict(value=pts / t_used, unit="grid-points/s", cores=1, kind="oracle", sample=sample)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--fp64-steps", type=int, default=3)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only (this build has no multi-GPU path); use --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_0812_0244_amd.binding import VdwNl, build_kernel_table
+
+    def log(msg):
+        print("[bench] " + msg, file=sys.stderr, flush=True)
+
+    insts = W.batch_instances(64)
+    t0 = time.time()
+    dens = [w.density() for w in insts]
+    shapes = [w.shape for w in insts]
+    cells = [w.cell for w in insts]
+    total = sum(w.npoints for w in insts)
+    log("densities built (%.1f s), %d grids, %d points" % (time.time() - t0, len(insts), total))
+    t0 = time.time()
+    table = build_kernel_table(0)
+    log("kernel table built on the GPU (%.1f s)" % (time.time() - t0))
+
+    # ---- FP32 batched (headline)
+    lib = VdwNl(0)
+    lib.set_grids(shapes, cells, 0, 32)
+    lib.set_kernel_table(table["qmesh"], table["qc"], table["mc"], table["dk"], table["phi"], table["c_soft"])
+    n32 = [torch.from_numpy(d).to("cuda", torch.float32) for d in dens]
+    v32 = [torch.empty_like(x) for x in n32]
+    nptr, vptr = [x.data_ptr() for x in n32], [x.data_ptr() for x in v32]
+    stream = torch.cuda.current_stream().cuda_stream
+    for _ in range(args.warmup):
+        lib.energy_potential_batched(nptr, vptr, stream)
+    lib.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        E32 = lib.energy_potential_batched(nptr, vptr, stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    passes = lib.pass_times()
+    log("fp32 batched: %.3f ms/step" % ms_step)
+    for k, (ms, calls) in passes.items():
+        log("  pass %-10s %8.3f ms/step" % (k, ms / max(calls, 1)))
+
+    # dominant pass and its roofline
+    dom = max((k for k in passes if k != "reduce"), key=lambda k: passes[k][0])
+    dom_ms = passes[dom][0] / max(passes[dom][1], 1)
+    dom_bytes = pass_bytes(dom, shapes, 4)
+    achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
+    path_bytes = sum(pass_bytes(k, shapes, 4) for k in passes)
+
+    # ---- FP64 plain: one context per density, evaluated one after another
+    del lib
+    ctxs, n64, v64 = [], [], []
+    for w, d in zip(insts, dens):
+        c = VdwNl(0)
+        c.set_grid(w.shape, w.cell, 0, 64)
+        c.set_kernel_table(table["qmesh"], table["qc"], table["mc"], table["dk"], table["phi"], table["c_soft"])
+        ctxs.append(c)
+        n64.append(torch.from_numpy(d).to("cuda"))
+        v64.append(torch.empty_like(n64[-1]))
+    E64 = np.zeros((len(insts), 2))
+    for i, c in enumerate(ctxs):
+        E64[i] = c.energy_potential(n64[i].data_ptr(), v64[i].data_ptr(), stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.fp64_steps):
+        for i, c in enumerate(ctxs):
+            E64[i] = c.energy_potential(n64[i].data_ptr(), v64[i].data_ptr(), stream)
+    torch.cuda.synchronize()
+    ms64 = (time.perf_counter() - t0) * 1e3 / args.fp64_steps
+    e32 = E32.sum(axis=1)
+    e64 = E64.sum(axis=1)
+    max_rel = float(np.max(np.abs(e32 - e64) / np.abs(e64)))
+    max_dv = max(float((v32[i].double() - v64[i]).abs().max()) for i in range(len(insts)))
+    log("fp64 plain: %.3f ms/step; max rel E (fp32 batched vs fp64 plain) %.2e; max|dv| %.2e"
+        % (ms64, max_rel, max_dv))
+    del ctxs
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        t0 = time.time()
+        cpu = cpu_baseline(insts, dens, args.cpu_seconds)
+        log("cpu baseline: %.3e pts/s (%.1f s)" % (cpu["value"], time.time() - t0))
+
+    sizes = {}
+    for s in shapes:
+        sizes[str(s[0])] = sizes.get(str(s[0]), 0) + 1
+    out = {
+        "metric": "E_c^nl+v_nl grid-points/s (N_q=20), FP32 batched vs FP64 plain at 1e-6 rel E",
+        "value": total / (ms_step * 1e-3),
+        "unit": "grid-points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "batched: 64 Gaussian-atom densities, cubic grids from {32,48,64,96,128}^3 "
+                        "(spacing 20/96 bohr, seeds 4000-4063), N_q=20, one call per step",
+            "grids_by_edge": sizes,
+            "total_points": total,
+            "precision": "theta/u FFTs and contraction FP32; grad n and divergence chains and "
+                         "reductions FP64",
+        },
+        "fp64_plain": {"ms_per_step": ms64, "value": total / (ms64 * 1e-3),
+                       "max_rel_E_fp32_batched_vs_fp64_plain": max_rel, "max_abs_dv_Ha": max_dv},
+        "passes_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in passes.items()},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                     "path_algorithmic_bytes_per_step": path_bytes,
+                     "path_frac": path_bytes / (ms_step * 1e-3) / 1e9 / PEAK_HBM_GBS},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
