@@ -9,6 +9,7 @@
 
 #include "../../include/vdwnl.h"
 #include "common.hpp"
+#include "fft_fast.hpp"
 
 namespace vdwnl {
 
@@ -97,6 +98,7 @@ using namespace vdwnl;
 
 struct vdwnl_ctx {
     int device = -1;
+    size_t lds_cap = kLdsCap;             // LDS bytes one workgroup may take on this device
     int precision = 32;
     int grad_mode = 0;
     std::string err;
@@ -120,8 +122,11 @@ struct vdwnl_ctx {
     InstDev *d_inst = nullptr;
     InstDev *h_inst = nullptr;            // pinned
     Tile *d_tiles = nullptr;
-    int kind_off[KIND_COUNT] = {0}, kind_cnt[KIND_COUNT] = {0};
-    size_t kind_lds[KIND_COUNT] = {0};
+    struct Launch {
+        int kind, lc, off, cnt;
+        size_t lds;
+    };
+    std::vector<Launch> launches[KIND_COUNT];   // per pass: one launch per FFT length class
     void *d_tw = nullptr;                 // twiddles in the working precision
     void *d_twd = nullptr;                // FP64 twiddles
     Consts *d_consts = nullptr;
@@ -186,26 +191,36 @@ static int check_grid(vdwnl_ctx *c, const int32_t *shape, const double *cell, in
         g.s[i] = shape[i];
         g.cell[i] = cell[i];
     }
-    const int N1 = g.s[0], N2 = g.s[1], N3 = g.s[2];
-    if (((size_t)N1 * N2) % 2 != 0)
+    const size_t N1 = g.s[0], N2 = g.s[1], N3 = g.s[2];
+    if ((N1 * N2) % 2 != 0)
         return fail(c, VDWNL_E_UNSUPPORTED_SIZE, "N1 * N2 must be even (rows are transformed in pairs)");
-    if (N1 > kMaxN1 || (size_t)kNQ * N1 * cs > (size_t)kLdsCap)
+    // LDS of each pass as a function of its tile size (twiddles staged in LDS too)
+    const size_t stage = (size_t)((kThreads / 64) * (64 / kNQ)) * kTabStride * rs;
+    auto zmain = [&](size_t k3) { return (N1 + (kNQ * k3 + 1) * N1) * cs + 16 + stage; };
+    auto zaux = [&](size_t k3) { return (N1 + (4 * k3 + 2) * N1) * 16; };
+    auto xmain = [&](size_t b) { return b * (N3 + 1) * (2 * 16 + (kNQ / 2) * cs) + N3 * (16 + cs) + (kNQ + kNQ * kNQ) * rs; };
+    auto ypass = [&](size_t w, size_t c2) { return (N2 + N2 * (w + 1)) * c2; };
+    const size_t cap = c->lds_cap, pref = std::min<size_t>(c->lds_cap, kLdsCap);
+    if (N1 > (size_t)kMaxN1 || zmain(1) > cap)
         return fail(c, VDWNL_E_UNSUPPORTED_SIZE, "N1 too large for the fused axis-1 pass");
-    if (N2 > kTileCap)
+    if (N2 > (size_t)kTileCap || ypass(1, cs) > cap || ypass(1, 16) > cap)
         return fail(c, VDWNL_E_UNSUPPORTED_SIZE, "N2 too large");
-    auto xlds = [&](size_t b) { return b * N3 * (2 * 16 + (kNQ / 2) * cs) + (kNQ + kNQ * kNQ) * rs; };
-    if ((size_t)kNQ / 2 * N3 > (size_t)kTileCap || xlds(1) > (size_t)kLdsCap)
+    if ((size_t)kNQ / 2 * N3 > (size_t)kTileCap || xmain(1) > cap)
         return fail(c, VDWNL_E_UNSUPPORTED_SIZE, "N3 too large for the axis-3 pass");
-    if (!radix_plan(N1, g.p1) || !radix_plan(N2, g.p2) || !radix_plan(N3, g.p3))
+    if (!radix_plan((int)N1, g.p1) || !radix_plan((int)N2, g.p2) || !radix_plan((int)N3, g.p3))
         return fail(c, VDWNL_E_UNSUPPORTED_SIZE, "no radix plan");
-    // tile shapes
-    g.bmain = 1;
-    if ((kNQ / 2) * 2 * (size_t)N3 <= (size_t)kTileCap && xlds(2) <= (size_t)kLdsCap)
-        g.bmain = 2;
-    g.k3main = std::max(1, std::min(kTileCap / (kNQ * N1), (int)(kLdsCap / (kNQ * N1 * cs))));
-    g.k3aux = std::max(1, std::min(kTileCap / (3 * N1), (int)(kLdsCap / (4 * N1 * 16))));
-    g.wy20 = std::max(1, std::min(kTileCap / N2, (int)(kLdsCap / (N2 * cs))));
-    g.wy3 = g.wy1 = std::max(1, std::min(kTileCap / N2, (int)(kLdsCap / (N2 * 16))));
+    // tile shapes: as large as the FFT tile cap allows while the LDS stays
+    // within 64 KB (two or more workgroups per CU); one unit at least
+    g.bmain = ((kNQ / 2) * 2 * N3 <= (size_t)kTileCap && xmain(2) <= pref) ? 2 : 1;
+    g.k3main = 1;
+    while ((size_t)kNQ * (g.k3main + 1) * N1 <= (size_t)kTileCap && zmain(g.k3main + 1) <= pref) ++g.k3main;
+    g.k3aux = 1;
+    while (3 * (size_t)(g.k3aux + 1) * N1 <= (size_t)kTileCap && zaux(g.k3aux + 1) <= pref) ++g.k3aux;
+    g.wy20 = 1;
+    while ((size_t)(g.wy20 + 1) * N2 <= (size_t)kTileCap && ypass(g.wy20 + 1, cs) <= pref) ++g.wy20;
+    g.wy3 = 1;
+    while ((size_t)(g.wy3 + 1) * N2 <= (size_t)kTileCap && ypass(g.wy3 + 1, 16) <= pref) ++g.wy3;
+    g.wy1 = g.wy3;
     return VDWNL_OK;
 }
 
@@ -244,7 +259,7 @@ static int plan_grids(vdwnl_ctx *c, int nb, const int32_t *shapes, const double 
 // spline of the radial table at |G| for every pair: phi_ab(|G_s|), FP64
 static void shell_table(const vdwnl_ctx *c, const Shells &sh, std::vector<double> &out) {
     const int npair = kNPair;
-    out.assign(sh.gmod.size() * npair, 0.0);
+    out.assign(sh.gmod.size() * kTabStride, 0.0);
     for (size_t s = 0; s < sh.gmod.size(); ++s) {
         const double k = sh.gmod[s];
         int j = (int)std::floor(k / c->dk);
@@ -255,7 +270,7 @@ static void shell_table(const vdwnl_ctx *c, const Shells &sh, std::vector<double
         for (int p = 0; p < npair; ++p) {
             const double *f = c->phi.data() + (size_t)p * c->nk;
             const double *m = c->d2.data() + (size_t)p * c->nk;
-            out[s * npair + p] = a * f[j] + b * f[j + 1] + ((a * a * a - a) * m[j] + (b * b * b - b) * m[j + 1]) * w;
+            out[s * kTabStride + p] = a * f[j] + b * f[j + 1] + ((a * a * a - a) * m[j] + (b * b * b - b) * m[j + 1]) * w;
         }
     }
 }
@@ -299,7 +314,7 @@ static int prepare_device(vdwnl_ctx *c) {
         c->map_off[i] = off;
         off = align_up(off + c->shells[i].map.size() * sizeof(int));
         c->tab_off[i] = off;
-        off = align_up(off + c->shells[i].gmod.size() * kNPair * rs);
+        off = align_up(off + c->shells[i].gmod.size() * kTabStride * rs);
     }
     std::vector<Tile> tiles[KIND_COUNT];
     for (size_t gi = 0; gi < c->grids.size(); ++gi) {
@@ -348,28 +363,42 @@ static int prepare_device(vdwnl_ctx *c) {
         g.off_ek = off; off = align_up(off + g.n_ek * sizeof(double));
         g.off_de = off; off = align_up(off + g.n_de * sizeof(double));
     }
-    // LDS per kind (max over grids)
-    for (int k = 0; k < KIND_COUNT; ++k) c->kind_lds[k] = 0;
-    for (auto &g : c->grids) {
+    // LDS of one tile of each pass for grid g
+    auto lds_of = [&](int k, const Grid &g) -> size_t {
         const size_t N1 = g.s[0], N2 = g.s[1], N3 = g.s[2];
-        auto mx = [&](int k, size_t v) { c->kind_lds[k] = std::max(c->kind_lds[k], v); };
-        mx(KX_NFWD, N3 * 16);
-        mx(KX_FINAL, N3 * 16);
-        const size_t xm = g.bmain * N3 * (2 * 16 + (kNQ / 2) * cs) + (kNQ + kNQ * kNQ) * rs;
-        mx(KX_THETA, xm);
-        mx(KX_ASSEMBLE, xm);
-        mx(KY_1F, N2 * g.wy1 * 16); mx(KY_1I, N2 * g.wy1 * 16);
-        mx(KY_3F, N2 * g.wy3 * 16); mx(KY_3I, N2 * g.wy3 * 16);
-        mx(KY_20F, N2 * g.wy20 * cs); mx(KY_20I, N2 * g.wy20 * cs);
-        mx(KZ_MAIN, (size_t)kNQ * g.k3main * N1 * cs);
-        mx(KZ_GRAD, 4 * g.k3aux * N1 * 16);
-        mx(KZ_DIV, 4 * g.k3aux * N1 * 16);
-    }
+        const size_t xm = g.bmain * (N3 + 1) * (2 * 16 + (kNQ / 2) * cs) + N3 * (16 + cs) + (kNQ + kNQ * kNQ) * rs;
+        switch (k) {
+            case KX_NFWD: case KX_FINAL: return (N3 + (N3 + 1)) * 16;
+            case KX_THETA: case KX_ASSEMBLE: return xm;
+            case KY_1F: case KY_1I: return (N2 + N2 * (g.wy1 + 1)) * 16;
+            case KY_3F: case KY_3I: return (N2 + N2 * (g.wy3 + 1)) * 16;
+            case KY_20F: case KY_20I: return (N2 + N2 * (g.wy20 + 1)) * cs;
+            case KZ_MAIN: return (N1 + (size_t)(kNQ * g.k3main + 1) * N1) * cs + 16 + (size_t)((kThreads / 64) * (64 / kNQ)) * kTabStride * rs;
+            default: return (N1 + (4 * g.k3aux + 2) * N1) * 16;   // KZ_GRAD, KZ_DIV
+        }
+    };
+    // the axis whose FFT a pass performs: 3 for the axis-3 passes, 2, 1
+    auto axis_len = [&](int k, const Grid &g) -> int {
+        switch (k) {
+            case KX_NFWD: case KX_THETA: case KX_ASSEMBLE: case KX_FINAL: return g.s[2];
+            case KY_1F: case KY_1I: case KY_3F: case KY_3I: case KY_20F: case KY_20I: return g.s[1];
+            default: return g.s[0];
+        }
+    };
     std::vector<Tile> all;
     for (int k = 0; k < KIND_COUNT; ++k) {
-        c->kind_off[k] = (int)all.size();
-        c->kind_cnt[k] = (int)tiles[k].size();
-        all.insert(all.end(), tiles[k].begin(), tiles[k].end());
+        c->launches[k].clear();
+        for (int lc = 0; lc < kNumLenClasses; ++lc) {
+            vdwnl_ctx::Launch L{k, lc, (int)all.size(), 0, 0};
+            for (const Tile &tl : tiles[k]) {
+                const Grid &g = c->grids[tl.inst];
+                if (len_class(axis_len(k, g)) != lc) continue;
+                all.push_back(tl);
+                L.lds = std::max(L.lds, lds_of(k, g));
+            }
+            L.cnt = (int)all.size() - L.off;
+            if (L.cnt > 0) c->launches[k].push_back(L);
+        }
     }
     // twiddles
     c->tw_off.clear();
@@ -482,9 +511,10 @@ static int run(vdwnl_ctx *c, int nb, const void *const *n_ptrs, void *const *v_p
     if (c->timing) (void)hipEventRecord(c->ev[0], st);
     for (int i = 0; i < KIND_COUNT; ++i) {
         const int k = kPassOrder[i];
-        LaunchArgs a{c->d_inst, c->d_tiles + c->kind_off[k], c->kind_cnt[k], c->kind_lds[k], c->d_consts, c->d_tw,
-                     c->d_twd, st};
-        if ((e = launch_kind(k, c->precision, a)) != hipSuccess) return hipfail(c, e, "kernel launch");
+        for (const auto &L : c->launches[k]) {
+            LaunchArgs a{c->d_inst, c->d_tiles + L.off, L.cnt, L.lds, c->d_consts, c->d_tw, c->d_twd, st};
+            if ((e = launch_kind(k, L.lc, c->precision, a)) != hipSuccess) return hipfail(c, e, "kernel launch");
+        }
         if (c->timing) (void)hipEventRecord(c->ev[i + 1], st);
     }
     if ((e = launch_reduce(c->d_inst, nb, c->d_E, st)) != hipSuccess) return hipfail(c, e, "reduce launch");
@@ -546,6 +576,11 @@ int vdwnl_create(vdwnl_ctx **out, int device) {
     vdwnl_ctx *c = new (std::nothrow) vdwnl_ctx();
     if (!c) return VDWNL_E_NOMEM;
     c->device = device;
+    if (device >= 0) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.sharedMemPerBlock > 0)
+            c->lds_cap = std::min<size_t>(prop.sharedMemPerBlock, 160 * 1024);
+    }
     std::memset(&c->consts, 0, sizeof(Consts));
     *out = c;
     return VDWNL_OK;

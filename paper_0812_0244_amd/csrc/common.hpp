@@ -9,6 +9,7 @@ namespace vdwnl {
 
 constexpr int kNQ = 20;                          // interpolation points q_a (compile-time)
 constexpr int kNPair = kNQ * (kNQ + 1) / 2;      // packed symmetric phi_ab per |G| shell
+constexpr int kTabStride = (kNPair + 3) / 4 * 4;  // row stride of the shell table (16-byte rows)
 constexpr int kThreads = 256;                    // threads per workgroup, every kernel
 constexpr int kTileCap = 4096;                   // complex elements of one LDS FFT tile
 constexpr int kLdsCap = 65536;                   // bytes of LDS one workgroup may take
@@ -32,7 +33,7 @@ struct FftPlan {
 //   spec3           [N1][N2][N3h][3] complex FP64   (grad n / w spectra)
 //   spec1           [N1][N2][N3h] complex FP64      (n / divergence spectrum)
 //   shellmap        [N1/2+1][N2/2+1][N3h] int   (|G| shell of (|m1|, |m2|, m3))
-//   shelltab        [nshell][kNPair] real       (phi_ab(|G_s|), a <= b packed row by row)
+//   shelltab        [nshell][kTabStride] real   (phi_ab(|G_s|), a <= b packed row by row, padded)
 struct InstDev {
     int n1, n2, n3, n3h, h1, h2;
     FftPlan p1, p2, p3;
@@ -96,7 +97,7 @@ struct LaunchArgs {
     hipStream_t stream;
 };
 
-hipError_t launch_kind(int kind, int precision, const LaunchArgs &a);
+hipError_t launch_kind(int kind, int len_class, int precision, const LaunchArgs &a);
 hipError_t launch_reduce(const InstDev *insts, int ninst, double *E, hipStream_t stream);
 
 }  // namespace vdwnl

@@ -1,0 +1,205 @@
+// Compile-time specialised FFTs of lines held in LDS for the transform lengths
+// the workloads use.  A length L = R_1 R_2 ... is done as Stockham passes of
+// radix R_i (up to 20); each line is owned by a group of TPL lanes inside one
+// wave (TPL = gcd of L / R_i, so every lane has whole butterflies in every
+// pass), so the passes are separated by wave-level ordering only.  The
+// in-register DFTs of composite radix are Cooley-Tukey splits with
+// compile-time twiddles.  Lengths without a specialisation use fft_lines.
+#pragma once
+
+#include "fft_lds.hpp"
+
+namespace vdwnl {
+
+// ---------------------------------------------------------------- compile-time trigonometry
+
+namespace ct {
+constexpr double kPi = 3.14159265358979323846264338327950288;
+constexpr double sin_poly(double x) {   // |x| <= pi/4
+    double x2 = x * x, term = x, sum = x;
+    for (int n = 1; n < 14; ++n) {
+        term *= -x2 / ((2.0 * n) * (2.0 * n + 1.0));
+        sum += term;
+    }
+    return sum;
+}
+constexpr double cos_poly(double x) {
+    double x2 = x * x, term = 1.0, sum = 1.0;
+    for (int n = 1; n < 14; ++n) {
+        term *= -x2 / ((2.0 * n - 1.0) * (2.0 * n));
+        sum += term;
+    }
+    return sum;
+}
+// cos and sin of 2 pi m / n (m, n integers), exact to double rounding
+constexpr double cos2pi(int m, int n) {
+    m %= n;
+    if (m < 0) m += n;
+    // quadrant q with angle = q pi/2 + r, |r| <= pi/4
+    const int q = (4 * m + n / 2) / n;                 // nearest multiple of n/4
+    const double r = 2.0 * kPi * ((double)m / n - (double)q / 4.0);
+    switch (q & 3) {
+        case 0: return cos_poly(r);
+        case 1: return -sin_poly(r);
+        case 2: return -cos_poly(r);
+        default: return sin_poly(r);
+    }
+}
+constexpr double sin2pi(int m, int n) {
+    m %= n;
+    if (m < 0) m += n;
+    const int q = (4 * m + n / 2) / n;
+    const double r = 2.0 * kPi * ((double)m / n - (double)q / 4.0);
+    switch (q & 3) {
+        case 0: return sin_poly(r);
+        case 1: return cos_poly(r);
+        case 2: return -sin_poly(r);
+        default: return -cos_poly(r);
+    }
+}
+constexpr int gcd(int a, int b) { return b == 0 ? a : gcd(b, a % b); }
+}  // namespace ct
+
+// ---------------------------------------------------------------- in-register DFTs
+
+// X_q = sum_r v_r exp(S 2 pi i r q / R), in place
+template <typename T, int R, int S>
+struct Dft {
+    // R = P Q, P the first base radix dividing R
+    static constexpr int P = (R % 4 == 0) ? 4 : (R % 2 == 0) ? 2 : (R % 5 == 0) ? 5 : 3;
+    static constexpr int Q = R / P;
+    __device__ __forceinline__ static void run(C2<T> *v) {
+        C2<T> y[R];
+#pragma unroll
+        for (int n2 = 0; n2 < Q; ++n2) {
+            C2<T> a[P];
+#pragma unroll
+            for (int n1 = 0; n1 < P; ++n1) a[n1] = v[Q * n1 + n2];
+            Dft<T, P, S>::run(a);
+#pragma unroll
+            for (int k1 = 0; k1 < P; ++k1) {
+                const int e = n2 * k1;
+                if (e % R == 0) {
+                    y[n2 * P + k1] = a[k1];
+                } else {
+                    const T c = (T)ct::cos2pi(e, R), s = (T)(S * ct::sin2pi(e, R));
+                    y[n2 * P + k1] = mk<T>(a[k1].x * c - a[k1].y * s, a[k1].x * s + a[k1].y * c);
+                }
+            }
+        }
+#pragma unroll
+        for (int k1 = 0; k1 < P; ++k1) {
+            C2<T> b[Q];
+#pragma unroll
+            for (int n2 = 0; n2 < Q; ++n2) b[n2] = y[n2 * P + k1];
+            Dft<T, Q, S>::run(b);
+#pragma unroll
+            for (int k2 = 0; k2 < Q; ++k2) v[k1 + P * k2] = b[k2];
+        }
+    }
+};
+template <typename T, int S> struct Dft<T, 1, S> { __device__ __forceinline__ static void run(C2<T> *) {} };
+template <typename T, int S> struct Dft<T, 2, S> { __device__ __forceinline__ static void run(C2<T> *v) { dft2<T>(v); } };
+template <typename T, int S> struct Dft<T, 3, S> { __device__ __forceinline__ static void run(C2<T> *v) { dft3<T>(v, (T)S); } };
+template <typename T, int S> struct Dft<T, 4, S> {
+    __device__ __forceinline__ static void run(C2<T> *v) { dft4<T>(v[0], v[1], v[2], v[3], (T)S); }
+};
+template <typename T, int S> struct Dft<T, 5, S> { __device__ __forceinline__ static void run(C2<T> *v) { dft5<T>(v, (T)S); } };
+template <typename T, int S> struct Dft<T, 8, S> { __device__ __forceinline__ static void run(C2<T> *v) { dft8<T>(v, (T)S); } };
+
+// ---------------------------------------------------------------- passes
+
+// Order the wave's LDS accesses: every lane of a line's group is in one wave.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int L, int... RS>
+struct FastPlan {
+    static constexpr int gcd_all() {
+        int g = 0;
+        for (int r : {RS...}) g = ct::gcd(g, L / r);
+        return g;
+    }
+    static constexpr int TPL = gcd_all();
+};
+
+// Pass of radix R after NS points have been combined; lane t of the group
+// owns butterflies j = t + m TPL.  Reads e = j + r L/R, twiddles by
+// W_{NS R}^{r (j % NS)}, writes e = (j - j%NS) R + j%NS + r NS.
+template <typename T, int L, int S, int TPL, int NS, int R, int... RS>
+__device__ __forceinline__ void fast_passes(C2<T> *line, int es, const C2<T> *__restrict__ tw, int t) {
+    constexpr int NB = L / R / TPL;
+    C2<T> v[NB][R];
+#pragma unroll
+    for (int m = 0; m < NB; ++m) {
+        const int j = t + m * TPL;
+        const int kk = j % NS;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            C2<T> a = line[(j + r * (L / R)) * es];
+            if (NS > 1 && r > 0) {
+                C2<T> w = tw[r * kk * (L / (NS * R))];
+                if (S > 0) w.y = -w.y;
+                a = cmul(a, w);
+            }
+            v[m][r] = a;
+        }
+        Dft<T, R, S>::run(v[m]);
+    }
+    wave_sync();
+#pragma unroll
+    for (int m = 0; m < NB; ++m) {
+        const int j = t + m * TPL;
+        const int kk = j % NS;
+#pragma unroll
+        for (int r = 0; r < R; ++r) line[((j - kk) * R + kk + r * NS) * es] = v[m][r];
+    }
+    wave_sync();
+    if constexpr (sizeof...(RS) > 0) fast_passes<T, L, S, TPL, NS * R, RS...>(line, es, tw, t);
+}
+
+template <typename T, int S, int L, int... RS>
+__device__ __forceinline__ void fft_fast(C2<T> *buf, int nl, int es, int ls, const C2<T> *__restrict__ tw) {
+    constexpr int TPL = FastPlan<L, RS...>::TPL;
+    static_assert(64 % TPL == 0, "a line's lanes must sit in one wave");
+    constexpr int G = kThreads / TPL;
+    const int grp = threadIdx.x / TPL, t = threadIdx.x - grp * TPL;
+    for (int l0 = 0; l0 < nl; l0 += G) {
+        const int line = l0 + grp;
+        if (line < nl) fast_passes<T, L, S, TPL, 1, RS...>(buf + line * ls, es, tw, t);
+    }
+    __syncthreads();
+}
+
+// Transform lengths with a specialised plan; a pass kernel is compiled once
+// per length class (index into this list, or kLenGeneric for any other length).
+constexpr int kFastLens[] = {24, 32, 48, 64, 96, 128, 160, 320};
+constexpr int kNumLenClasses = 9;
+constexpr int kLenGeneric = 8;
+
+__host__ __device__ constexpr int len_class(int n) {
+    for (int i = 0; i < kLenGeneric; ++i)
+        if (kFastLens[i] == n) return i;
+    return kLenGeneric;
+}
+
+// Unnormalised DFT (sign S) of nl lines of length p.n, for a length of class LC.
+template <typename T, int S, int LC>
+__device__ __forceinline__ void fft_lc(C2<T> *buf, const FftPlan &p, int nl, int es, int ls,
+                                       const C2<T> *__restrict__ tw) {
+    // radix sequences: lanes per line = gcd(L / R_i), elements per lane <= 20
+    if constexpr (LC == 0) fft_fast<T, S, 24, 4, 3, 2>(buf, nl, es, ls, tw);          // 2 lanes, 12 each
+    else if constexpr (LC == 1) fft_fast<T, S, 32, 8, 4>(buf, nl, es, ls, tw);        // 4 lanes, 8 each
+    else if constexpr (LC == 2) fft_fast<T, S, 48, 4, 4, 3>(buf, nl, es, ls, tw);     // 4 lanes, 12 each
+    else if constexpr (LC == 3) fft_fast<T, S, 64, 8, 8>(buf, nl, es, ls, tw);        // 8 lanes, 8 each
+    else if constexpr (LC == 4) fft_fast<T, S, 96, 4, 4, 2, 3>(buf, nl, es, ls, tw);  // 8 lanes, 12 each
+    else if constexpr (LC == 5) fft_fast<T, S, 128, 8, 4, 4>(buf, nl, es, ls, tw);    // 16 lanes, 8 each
+    else if constexpr (LC == 6) fft_fast<T, S, 160, 4, 4, 2, 5>(buf, nl, es, ls, tw); // 8 lanes, 20 each
+    else if constexpr (LC == 7) fft_fast<T, S, 320, 4, 4, 4, 5>(buf, nl, es, ls, tw); // 16 lanes, 20 each
+    else fft_lines<T>(buf, p, nl, es, ls, tw, S);
+}
+
+}  // namespace vdwnl

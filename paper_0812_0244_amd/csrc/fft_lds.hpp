@@ -151,12 +151,19 @@ __device__ __forceinline__ void fft_pass(C2<T> *buf, int L, int nl, int es, int 
     __syncthreads();
 }
 
-// Unnormalised DFT of every line: sign -1 forward, +1 inverse.  The caller
-// has synchronised after filling buf; on return buf is synchronised again.
+// Copy the twiddles W_L^m, m < L, of plan p from the global table to LDS.
+// The caller synchronises before the first fft_lines that reads them.
+template <typename T>
+__device__ __forceinline__ void load_twiddles(C2<T> *dst, const FftPlan &p, const C2<T> *__restrict__ twall) {
+    for (int i = threadIdx.x; i < p.n; i += kThreads) dst[i] = twall[p.tw + i];
+}
+
+// Unnormalised DFT of every line: sign -1 forward, +1 inverse; tw holds
+// W_L^m, m < L (in LDS).  The caller has synchronised after filling buf; on
+// return buf is synchronised again.
 template <typename T>
 __device__ void fft_lines(C2<T> *buf, const FftPlan &p, int nl, int es, int ls,
-                          const C2<T> *__restrict__ twall, int sign) {
-    const C2<T> *tw = twall + p.tw;
+                          const C2<T> *__restrict__ tw, int sign) {
     const T s = (T)sign;
     int Ns = 1;
     for (int st = 0; st < p.nstage; ++st) {

@@ -16,7 +16,7 @@
 // spectra holds every component of its k points in LDS and can apply the
 // per-k kernel matrix between its forward and inverse FFTs.
 #include "common.hpp"
-#include "fft_lds.hpp"
+#include "fft_fast.hpp"
 
 namespace vdwnl {
 
@@ -151,25 +151,27 @@ __device__ __forceinline__ void load_consts(const Consts *cst, T *qm, T *Mm) {
 
 // R2C of n (read in T, transformed in FP64): rows (2p, 2p+1) of a tile form
 // one complex line.  tile: a = first row (i1 N2 + i2), b = rows (even)
-template <typename T>
+template <typename T, int LC>
 __global__ void __launch_bounds__(kThreads) k_x_nfwd(const InstDev *insts, const Tile *tiles,
                                                      const void *twdv) {
     extern __shared__ __align__(16) unsigned char smem[];
-    double2 *buf = reinterpret_cast<double2 *>(smem);
     const Tile t = tiles[blockIdx.x];
     const InstDev &I = insts[t.inst];
-    const int N3 = I.n3, N3h = I.n3h, row0 = t.a, B = t.b, np = B / 2;
+    const int N3 = I.n3, N3h = I.n3h, row0 = t.a, B = t.b, np = B / 2, ls = N3 + 1;
+    double2 *tw = reinterpret_cast<double2 *>(smem);
+    double2 *buf = tw + N3;
+    load_twiddles<double>(tw, I.p3, reinterpret_cast<const double2 *>(twdv));
     const T *n = reinterpret_cast<const T *>(I.n) + (size_t)row0 * N3;
     for (int idx = threadIdx.x; idx < np * N3; idx += kThreads) {
         const int pr = idx / N3, k = idx - pr * N3;
-        buf[idx] = mk<double>((double)n[(2 * pr) * N3 + k], (double)n[(2 * pr + 1) * N3 + k]);
+        buf[pr * ls + k] = mk<double>((double)n[(2 * pr) * N3 + k], (double)n[(2 * pr + 1) * N3 + k]);
     }
     __syncthreads();
-    fft_lines<double>(buf, I.p3, np, 1, N3, reinterpret_cast<const double2 *>(twdv), -1);
+    fft_lc<double, -1, LC>(buf, I.p3, np, 1, ls, tw);
     double2 *out = reinterpret_cast<double2 *>(I.spec1) + (size_t)row0 * N3h;
     for (int idx = threadIdx.x; idx < B * N3h; idx += kThreads) {
         const int rb = idx / N3h, k = idx - rb * N3h;
-        const double2 *Z = buf + (rb >> 1) * N3;
+        const double2 *Z = buf + (rb >> 1) * ls;
         const double2 z = Z[k], zc = cconj(Z[(N3 - k) % N3]);
         double2 y;
         if ((rb & 1) == 0) y = mk<double>((z.x + zc.x) * 0.5, (z.y + zc.y) * 0.5);
@@ -180,20 +182,23 @@ __global__ void __launch_bounds__(kThreads) k_x_nfwd(const InstDev *insts, const
 
 // C2R of grad n (3 FP64 spectra per row), theta_a = n p_a(q0), Delta E
 // partials, R2C of the 20 theta rows.  tile: a = first row, b = rows, slot = partial.
-template <typename T>
+template <typename T, int LC>
 __global__ void __launch_bounds__(kThreads) k_x_theta(const InstDev *insts, const Tile *tiles,
                                                       const Consts *cst, const void *twv, const void *twdv) {
     extern __shared__ __align__(16) unsigned char smem[];
     const Tile t = tiles[blockIdx.x];
     const InstDev &I = insts[t.inst];
-    const int N3 = I.n3, N3h = I.n3h, row0 = t.a, B = t.b;
+    const int N3 = I.n3, N3h = I.n3h, row0 = t.a, B = t.b, ls = N3 + 1;
     const size_t N = (size_t)I.n1 * I.n2 * I.n3;
-    double2 *r1 = reinterpret_cast<double2 *>(smem);       // 2 lines per row: d1 + i d2, d3
-    C2<T> *r2 = reinterpret_cast<C2<T> *>(r1 + 2 * B * N3); // 10 lines per row: theta pairs
-    T *qm = reinterpret_cast<T *>(r2 + kNQ / 2 * B * N3);
+    double2 *twd = reinterpret_cast<double2 *>(smem);       // FP64 twiddles
+    double2 *r1 = twd + N3;                                   // 2 lines per row: d1 + i d2, d3
+    C2<T> *r2 = reinterpret_cast<C2<T> *>(r1 + 2 * B * ls);  // 10 lines per row: theta pairs
+    C2<T> *tw = r2 + kNQ / 2 * B * ls;                       // twiddles in T
+    T *qm = reinterpret_cast<T *>(tw + N3);
     T *Mm = qm + kNQ;
     load_consts<T>(cst, qm, Mm);
-    const C2<T> *twall = reinterpret_cast<const C2<T> *>(twv);
+    load_twiddles<double>(twd, I.p3, reinterpret_cast<const double2 *>(twdv));
+    load_twiddles<T>(tw, I.p3, reinterpret_cast<const C2<T> *>(twv));
 
     const double2 *s3 = reinterpret_cast<const double2 *>(I.spec3) + (size_t)row0 * N3h * 3;
     for (int idx = threadIdx.x; idx < B * N3; idx += kThreads) {
@@ -203,11 +208,11 @@ __global__ void __launch_bounds__(kThreads) k_x_theta(const InstDev *insts, cons
         const double2 *src = s3 + ((size_t)rb * N3h + kk) * 3;
         double2 y0 = src[0], y1 = src[1], y2 = src[2];
         if (cj) { y0 = cconj(y0); y1 = cconj(y1); y2 = cconj(y2); }
-        r1[(2 * rb) * N3 + k] = mk<double>(y0.x - y1.y, y0.y + y1.x);
-        r1[(2 * rb + 1) * N3 + k] = y2;
+        r1[(2 * rb) * ls + k] = mk<double>(y0.x - y1.y, y0.y + y1.x);
+        r1[(2 * rb + 1) * ls + k] = y2;
     }
     __syncthreads();
-    fft_lines<double>(r1, I.p3, 2 * B, 1, N3, reinterpret_cast<const double2 *>(twdv), +1);
+    fft_lc<double, 1, LC>(r1, I.p3, 2 * B, 1, ls, twd);
 
     const Consts c = *cst;
     const T *nin = reinterpret_cast<const T *>(I.n);
@@ -217,12 +222,12 @@ __global__ void __launch_bounds__(kThreads) k_x_theta(const InstDev *insts, cons
         const int rb = idx / N3, k = idx - rb * N3;
         const size_t p = (size_t)(row0 + rb) * N3 + k;
         const T nv = nin[p];
-        const double2 g01d = r1[(2 * rb) * N3 + k], g2d = r1[(2 * rb + 1) * N3 + k];
+        const double2 g01d = r1[(2 * rb) * ls + k], g2d = r1[(2 * rb + 1) * ls + k];
         const C2<T> g01 = mk<T>((T)g01d.x, (T)g01d.y), g2 = mk<T>((T)g2d.x, (T)0);
         grad[p] = g01.x;
         grad[N + p] = g01.y;
         grad[2 * N + p] = g2.x;
-        T *th = reinterpret_cast<T *>(r2 + (size_t)(kNQ / 2 * rb) * N3);   // pair line m at th + 2 m N3
+        T *th = reinterpret_cast<T *>(r2 + (size_t)(kNQ / 2 * rb) * ls);   // pair line m at th + 2 m ls
         if (nv >= (T)c.nmin) {
             LocalQ<T, false> lq;
             lq.eval(nv, g01.x * g01.x + g01.y * g01.y + g2.x * g2.x, c);
@@ -232,23 +237,23 @@ __global__ void __launch_bounds__(kThreads) k_x_theta(const InstDev *insts, cons
             for (int al = 0; al < kNQ; ++al) {
                 T pa, dpa;
                 sp.basis(al, Mm, pa, dpa);
-                th[2 * ((al >> 1) * N3 + k) + (al & 1)] = nv * pa;
+                th[2 * ((al >> 1) * ls + k) + (al & 1)] = nv * pa;
             }
             const T q3 = lq.q0 * lq.q0 * lq.q0;
             de += (double)((T)c.cs * nv * nv / q3);
         } else {
 #pragma unroll 4
-            for (int al = 0; al < kNQ; ++al) th[2 * ((al >> 1) * N3 + k) + (al & 1)] = (T)0;
+            for (int al = 0; al < kNQ; ++al) th[2 * ((al >> 1) * ls + k) + (al & 1)] = (T)0;
         }
     }
     __syncthreads();
-    fft_lines<T>(r2, I.p3, kNQ / 2 * B, 1, N3, twall, -1);
+    fft_lc<T, -1, LC>(r2, I.p3, kNQ / 2 * B, 1, ls, tw);
 
     C2<T> *out = reinterpret_cast<C2<T> *>(I.spec) + (size_t)row0 * N3h * kNQ;
     for (int idx = threadIdx.x; idx < B * N3h * kNQ; idx += kThreads) {
         const int al = idx % kNQ, rest = idx / kNQ;
         const int k = rest % N3h, rb = rest / N3h;
-        const C2<T> *Z = r2 + (kNQ / 2 * rb + (al >> 1)) * N3;
+        const C2<T> *Z = r2 + (kNQ / 2 * rb + (al >> 1)) * ls;
         const C2<T> z = Z[k], zc = cconj(Z[(N3 - k) % N3]);
         C2<T> y;
         if ((al & 1) == 0) y = mk<T>((z.x + zc.x) * (T)0.5, (z.y + zc.y) * (T)0.5);
@@ -262,20 +267,23 @@ __global__ void __launch_bounds__(kThreads) k_x_theta(const InstDev *insts, cons
 // C2R of the 20 u_a rows; v_loc = sum_a u_a dtheta_a/dn + de/dn;
 // w = g grad n with g = sum_a u_a 2 n p'_a Q dq/dsigma + de/dsigma-part;
 // R2C of the three w rows.  tile: a = first row, b = rows.
-template <typename T>
+template <typename T, int LC>
 __global__ void __launch_bounds__(kThreads) k_x_assemble(const InstDev *insts, const Tile *tiles,
                                                          const Consts *cst, const void *twv, const void *twdv) {
     extern __shared__ __align__(16) unsigned char smem[];
     const Tile t = tiles[blockIdx.x];
     const InstDev &I = insts[t.inst];
-    const int N3 = I.n3, N3h = I.n3h, row0 = t.a, B = t.b;
+    const int N3 = I.n3, N3h = I.n3h, row0 = t.a, B = t.b, ls = N3 + 1;
     const size_t N = (size_t)I.n1 * I.n2 * I.n3;
-    double2 *r1 = reinterpret_cast<double2 *>(smem);       // 2 FP64 lines per row: w1 + i w2, w3
-    C2<T> *r2 = reinterpret_cast<C2<T> *>(r1 + 2 * B * N3); // 10 lines per row: u pairs
-    T *qm = reinterpret_cast<T *>(r2 + kNQ / 2 * B * N3);
+    double2 *twd = reinterpret_cast<double2 *>(smem);       // FP64 twiddles
+    double2 *r1 = twd + N3;                                   // 2 FP64 lines per row: w1 + i w2, w3
+    C2<T> *r2 = reinterpret_cast<C2<T> *>(r1 + 2 * B * ls);  // 10 lines per row: u pairs
+    C2<T> *tw = r2 + kNQ / 2 * B * ls;                       // twiddles in T
+    T *qm = reinterpret_cast<T *>(tw + N3);
     T *Mm = qm + kNQ;
     load_consts<T>(cst, qm, Mm);
-    const C2<T> *twall = reinterpret_cast<const C2<T> *>(twv);
+    load_twiddles<double>(twd, I.p3, reinterpret_cast<const double2 *>(twdv));
+    load_twiddles<T>(tw, I.p3, reinterpret_cast<const C2<T> *>(twv));
 
     const C2<T> *sp = reinterpret_cast<const C2<T> *>(I.spec) + (size_t)row0 * N3h * kNQ;
     for (int idx = threadIdx.x; idx < B * N3 * (kNQ / 2); idx += kThreads) {
@@ -286,10 +294,10 @@ __global__ void __launch_bounds__(kThreads) k_x_assemble(const InstDev *insts, c
         const C2<T> *src = sp + ((size_t)rb * N3h + kk) * kNQ + 2 * m;
         C2<T> ya = src[0], yb = src[1];
         if (cj) { ya = cconj(ya); yb = cconj(yb); }
-        r2[(kNQ / 2 * rb + m) * N3 + k] = mk<T>(ya.x - yb.y, ya.y + yb.x);
+        r2[(kNQ / 2 * rb + m) * ls + k] = mk<T>(ya.x - yb.y, ya.y + yb.x);
     }
     __syncthreads();
-    fft_lines<T>(r2, I.p3, kNQ / 2 * B, 1, N3, twall, +1);
+    fft_lc<T, 1, LC>(r2, I.p3, kNQ / 2 * B, 1, ls, tw);
 
     const Consts c = *cst;
     const T *nin = reinterpret_cast<const T *>(I.n);
@@ -306,14 +314,14 @@ __global__ void __launch_bounds__(kThreads) k_x_assemble(const InstDev *insts, c
             lq.eval(nv, gx * gx + gy * gy + gz * gz, c);
             SplinePos<T> spos;
             spos.locate(lq.q0, qm, kNQ);
-            const T *u = reinterpret_cast<const T *>(r2 + (size_t)(kNQ / 2 * rb) * N3);
+            const T *u = reinterpret_cast<const T *>(r2 + (size_t)(kNQ / 2 * rb) * ls);
             const T cn = nv * lq.Q * lq.dqdn;
             T su = (T)0, sdu = (T)0;
 #pragma unroll 4
             for (int al = 0; al < kNQ; ++al) {
                 T pa, dpa;
                 spos.basis(al, Mm, pa, dpa);
-                const T ua = u[2 * ((al >> 1) * N3 + k) + (al & 1)];
+                const T ua = u[2 * ((al >> 1) * ls + k) + (al & 1)];
                 su += ua * pa;
                 sdu += ua * dpa;
             }
@@ -325,17 +333,17 @@ __global__ void __launch_bounds__(kThreads) k_x_assemble(const InstDev *insts, c
         }
         vloc[p] = vl;
         const double gsd = (double)gs;
-        r1[(2 * rb) * N3 + k] = mk<double>(gsd * (double)gx, gsd * (double)gy);
-        r1[(2 * rb + 1) * N3 + k] = mk<double>(gsd * (double)gz, 0.0);
+        r1[(2 * rb) * ls + k] = mk<double>(gsd * (double)gx, gsd * (double)gy);
+        r1[(2 * rb + 1) * ls + k] = mk<double>(gsd * (double)gz, 0.0);
     }
     __syncthreads();
-    fft_lines<double>(r1, I.p3, 2 * B, 1, N3, reinterpret_cast<const double2 *>(twdv), -1);
+    fft_lc<double, -1, LC>(r1, I.p3, 2 * B, 1, ls, twd);
 
     double2 *out = reinterpret_cast<double2 *>(I.spec3) + (size_t)row0 * N3h * 3;
     for (int idx = threadIdx.x; idx < B * N3h * 3; idx += kThreads) {
         const int comp = idx % 3, rest = idx / 3;
         const int k = rest % N3h, rb = rest / N3h;
-        const double2 *Z = r1 + (2 * rb + (comp >> 1)) * N3;
+        const double2 *Z = r1 + (2 * rb + (comp >> 1)) * ls;
         const double2 z = Z[k], zc = cconj(Z[(N3 - k) % N3]);
         double2 y;
         if (comp != 1) y = mk<double>((z.x + zc.x) * 0.5, (z.y + zc.y) * 0.5);
@@ -345,14 +353,16 @@ __global__ void __launch_bounds__(kThreads) k_x_assemble(const InstDev *insts, c
 }
 
 // C2R of the FP64 divergence spectrum (row pairs), v = v_loc - div.
-template <typename T>
+template <typename T, int LC>
 __global__ void __launch_bounds__(kThreads) k_x_final(const InstDev *insts, const Tile *tiles,
                                                       const void *twdv) {
     extern __shared__ __align__(16) unsigned char smem[];
-    double2 *buf = reinterpret_cast<double2 *>(smem);
     const Tile t = tiles[blockIdx.x];
     const InstDev &I = insts[t.inst];
-    const int N3 = I.n3, N3h = I.n3h, row0 = t.a, B = t.b, np = B / 2;
+    const int N3 = I.n3, N3h = I.n3h, row0 = t.a, B = t.b, np = B / 2, ls = N3 + 1;
+    double2 *tw = reinterpret_cast<double2 *>(smem);
+    double2 *buf = tw + N3;
+    load_twiddles<double>(tw, I.p3, reinterpret_cast<const double2 *>(twdv));
     const double2 *s1 = reinterpret_cast<const double2 *>(I.spec1) + (size_t)row0 * N3h;
     for (int idx = threadIdx.x; idx < np * N3; idx += kThreads) {
         const int pr = idx / N3, k = idx - pr * N3;
@@ -360,15 +370,15 @@ __global__ void __launch_bounds__(kThreads) k_x_final(const InstDev *insts, cons
         const int kk = cj ? N3 - k : k;
         double2 ya = s1[(2 * pr) * N3h + kk], yb = s1[(2 * pr + 1) * N3h + kk];
         if (cj) { ya = cconj(ya); yb = cconj(yb); }
-        buf[idx] = mk<double>(ya.x - yb.y, ya.y + yb.x);
+        buf[pr * ls + k] = mk<double>(ya.x - yb.y, ya.y + yb.x);
     }
     __syncthreads();
-    fft_lines<double>(buf, I.p3, np, 1, N3, reinterpret_cast<const double2 *>(twdv), +1);
+    fft_lc<double, 1, LC>(buf, I.p3, np, 1, ls, tw);
     const T *vloc = reinterpret_cast<const T *>(I.vloc) + (size_t)row0 * N3;
     T *v = reinterpret_cast<T *>(I.v) + (size_t)row0 * N3;
     for (int idx = threadIdx.x; idx < B * N3; idx += kThreads) {
         const int rb = idx / N3, k = idx - rb * N3;
-        const double2 z = buf[(rb >> 1) * N3 + k];
+        const double2 z = buf[(rb >> 1) * ls + k];
         v[idx] = (T)((double)vloc[idx] - ((rb & 1) ? z.y : z.x));
     }
 }
@@ -376,177 +386,210 @@ __global__ void __launch_bounds__(kThreads) k_x_final(const InstDev *insts, cons
 // ---------------------------------------------------------------- axis-2 pass
 
 // tile: a = i1, b = first flattened (k3, component) index, c = width
-template <typename T>
+template <typename T, int S, int LC>
 __global__ void __launch_bounds__(kThreads) k_y(const InstDev *insts, const Tile *tiles,
-                                                const void *twv, int which, int V, int sign) {
+                                                const void *twv, int which, int V) {
     extern __shared__ __align__(16) unsigned char smem[];
-    C2<T> *buf = reinterpret_cast<C2<T> *>(smem);
     const Tile t = tiles[blockIdx.x];
     const InstDev &I = insts[t.inst];
-    const int N2 = I.n2, W = t.c;
+    const int N2 = I.n2, W = t.c, es = W | 1;   // odd element stride: no LDS bank conflicts
+    C2<T> *tw = reinterpret_cast<C2<T> *>(smem);
+    C2<T> *buf = tw + N2;
+    load_twiddles<T>(tw, I.p2, reinterpret_cast<const C2<T> *>(twv));
     const size_t rowlen = (size_t)I.n3h * V;
     void *base = which == 0 ? I.spec : (which == 1 ? I.spec3 : I.spec1);
     C2<T> *g = reinterpret_cast<C2<T> *>(base) + (size_t)t.a * N2 * rowlen + t.b;
     for (int idx = threadIdx.x; idx < N2 * W; idx += kThreads) {
         const int l = idx / W, w = idx - l * W;
-        buf[idx] = g[l * rowlen + w];
+        buf[l * es + w] = g[l * rowlen + w];
     }
     __syncthreads();
-    fft_lines<T>(buf, I.p2, W, W, 1, reinterpret_cast<const C2<T> *>(twv), sign);
+    fft_lc<T, S, LC>(buf, I.p2, W, es, 1, tw);
     for (int idx = threadIdx.x; idx < N2 * W; idx += kThreads) {
         const int l = idx / W, w = idx - l * W;
-        g[l * rowlen + w] = buf[idx];
+        g[l * rowlen + w] = buf[l * es + w];
     }
 }
 
 // ---------------------------------------------------------------- axis-1 passes
 
 // n spectrum -> i G_c n / N, c = 1..3.  tile: a = k2, b = first k3, c = count
-template <typename T>
+template <typename T, int LC>
 __global__ void __launch_bounds__(kThreads) k_z_grad(const InstDev *insts, const Tile *tiles,
                                                      const void *twv) {
     extern __shared__ __align__(16) unsigned char smem[];
     const Tile t = tiles[blockIdx.x];
     const InstDev &I = insts[t.inst];
     const int N1 = I.n1, N2 = I.n2, N3 = I.n3, N3h = I.n3h, k2 = t.a, k30 = t.b, K3 = t.c;
-    C2<T> *bin = reinterpret_cast<C2<T> *>(smem);
-    C2<T> *bout = bin + N1 * K3;
-    const C2<T> *twall = reinterpret_cast<const C2<T> *>(twv);
+    C2<T> *twall = reinterpret_cast<C2<T> *>(smem);
+    const int ei = K3 | 1, eo = (3 * K3) | 1;               // odd element strides
+    C2<T> *bin = twall + N1;
+    C2<T> *bout = bin + N1 * ei;
+    load_twiddles<T>(twall, I.p1, reinterpret_cast<const C2<T> *>(twv));
     const C2<T> *gin = reinterpret_cast<const C2<T> *>(I.spec1) + (size_t)k2 * N3h + k30;
     const size_t sin_ = (size_t)N2 * N3h;
     for (int idx = threadIdx.x; idx < N1 * K3; idx += kThreads) {
         const int l = idx / K3, w = idx - l * K3;
-        bin[idx] = gin[l * sin_ + w];
+        bin[l * ei + w] = gin[l * sin_ + w];
     }
     __syncthreads();
-    fft_lines<T>(bin, I.p1, K3, K3, 1, twall, -1);
+    fft_lc<T, -1, LC>(bin, I.p1, K3, ei, 1, twall);
     const T G2 = (T)(I.g2 * freq_nz(k2, N2));
     for (int idx = threadIdx.x; idx < N1 * K3; idx += kThreads) {
         const int l = idx / K3, w = idx - l * K3;
-        const C2<T> nh = cscale(bin[idx], (T)I.inv_n);
+        const C2<T> nh = cscale(bin[l * ei + w], (T)I.inv_n);
         const T G1 = (T)(I.g1 * freq_nz(l, N1));
         const T G3 = (T)(I.g3 * freq_nz(k30 + w, N3));
-        C2<T> *o = bout + l * 3 * K3 + 3 * w;
+        C2<T> *o = bout + l * eo + 3 * w;
         o[0] = mk<T>(-G1 * nh.y, G1 * nh.x);
         o[1] = mk<T>(-G2 * nh.y, G2 * nh.x);
         o[2] = mk<T>(-G3 * nh.y, G3 * nh.x);
     }
     __syncthreads();
-    fft_lines<T>(bout, I.p1, 3 * K3, 3 * K3, 1, twall, +1);
+    fft_lc<T, 1, LC>(bout, I.p1, 3 * K3, eo, 1, twall);
     C2<T> *gout = reinterpret_cast<C2<T> *>(I.spec3) + ((size_t)k2 * N3h + k30) * 3;
     for (int idx = threadIdx.x; idx < N1 * 3 * K3; idx += kThreads) {
         const int l = idx / (3 * K3), w = idx - l * 3 * K3;
-        gout[l * sin_ * 3 + w] = bout[idx];
+        gout[l * sin_ * 3 + w] = bout[l * eo + w];
     }
 }
 
 // sum_c i G_c w_c / N.  tile: a = k2, b = first k3, c = count
-template <typename T>
+template <typename T, int LC>
 __global__ void __launch_bounds__(kThreads) k_z_div(const InstDev *insts, const Tile *tiles,
                                                     const void *twv) {
     extern __shared__ __align__(16) unsigned char smem[];
     const Tile t = tiles[blockIdx.x];
     const InstDev &I = insts[t.inst];
     const int N1 = I.n1, N2 = I.n2, N3 = I.n3, N3h = I.n3h, k2 = t.a, k30 = t.b, K3 = t.c;
-    C2<T> *bin = reinterpret_cast<C2<T> *>(smem);
-    C2<T> *bout = bin + N1 * 3 * K3;
-    const C2<T> *twall = reinterpret_cast<const C2<T> *>(twv);
+    C2<T> *twall = reinterpret_cast<C2<T> *>(smem);
+    const int ei = (3 * K3) | 1, eo = K3 | 1;               // odd element strides
+    C2<T> *bin = twall + N1;
+    C2<T> *bout = bin + N1 * ei;
+    load_twiddles<T>(twall, I.p1, reinterpret_cast<const C2<T> *>(twv));
     const size_t sin_ = (size_t)N2 * N3h;
     const C2<T> *gin = reinterpret_cast<const C2<T> *>(I.spec3) + ((size_t)k2 * N3h + k30) * 3;
     for (int idx = threadIdx.x; idx < N1 * 3 * K3; idx += kThreads) {
         const int l = idx / (3 * K3), w = idx - l * 3 * K3;
-        bin[idx] = gin[l * sin_ * 3 + w];
+        bin[l * ei + w] = gin[l * sin_ * 3 + w];
     }
     __syncthreads();
-    fft_lines<T>(bin, I.p1, 3 * K3, 3 * K3, 1, twall, -1);
+    fft_lc<T, -1, LC>(bin, I.p1, 3 * K3, ei, 1, twall);
     const T G2 = (T)(I.g2 * freq_nz(k2, N2));
     for (int idx = threadIdx.x; idx < N1 * K3; idx += kThreads) {
         const int l = idx / K3, w = idx - l * K3;
-        const C2<T> *x = bin + l * 3 * K3 + 3 * w;
+        const C2<T> *x = bin + l * ei + 3 * w;
         const T G1 = (T)(I.g1 * freq_nz(l, N1));
         const T G3 = (T)(I.g3 * freq_nz(k30 + w, N3));
         const T sx = G1 * x[0].x + G2 * x[1].x + G3 * x[2].x;
         const T sy = G1 * x[0].y + G2 * x[1].y + G3 * x[2].y;
-        bout[idx] = cscale(mk<T>(-sy, sx), (T)I.inv_n);
+        bout[l * eo + w] = cscale(mk<T>(-sy, sx), (T)I.inv_n);
     }
     __syncthreads();
-    fft_lines<T>(bout, I.p1, K3, K3, 1, twall, +1);
+    fft_lc<T, 1, LC>(bout, I.p1, K3, eo, 1, twall);
     C2<T> *gout = reinterpret_cast<C2<T> *>(I.spec1) + (size_t)k2 * N3h + k30;
     for (int idx = threadIdx.x; idx < N1 * K3; idx += kThreads) {
         const int l = idx / K3, w = idx - l * K3;
-        gout[l * sin_ + w] = bout[idx];
+        gout[l * sin_ + w] = bout[l * eo + w];
     }
 }
 
 // Forward axis-1 FFT of the 20 theta spectra, u_a(G) = sum_b phi_ab(|G|) c_b(G)
 // with c = Theta / N (Eq. Eoffk, Eq. epsofk), the energy sum
 // sum_G w_G sum_a Re(c_a^* u_a), inverse axis-1 FFT.  tile: a = k2, b = first k3, c = count
-template <typename T>
+//
+// Contraction layout: lanes form groups of kNQ (three per wave).  A group takes
+// one item: a k3 of the tile and an |m1|, i.e. the pair of k points
+// (m1, -m1) that share the |G| shell; it stages the shell's packed kernel row
+// in LDS with coalesced 16-byte loads, then lane a forms u_a for both points.
+template <typename T, int LC>
 __global__ void __launch_bounds__(kThreads) k_z_main(const InstDev *insts, const Tile *tiles,
                                                      const void *twv) {
     extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int kGroups = (kThreads / 64) * (64 / kNQ);   // lane groups per workgroup
     const Tile t = tiles[blockIdx.x];
     const InstDev &I = insts[t.inst];
     const int N1 = I.n1, N2 = I.n2, N3 = I.n3, N3h = I.n3h, k2 = t.a, k30 = t.b, K3 = t.c;
-    const int W = K3 * kNQ;
-    C2<T> *buf = reinterpret_cast<C2<T> *>(smem);
-    const C2<T> *twall = reinterpret_cast<const C2<T> *>(twv);
+    const int W = K3 * kNQ, es = W | 1;                      // odd element stride
+    C2<T> *twall = reinterpret_cast<C2<T> *>(smem);
+    C2<T> *buf = twall + N1;
+    const size_t stage_off = ((size_t)(N1 + N1 * es) * sizeof(C2<T>) + 15) & ~(size_t)15;
+    T *stage = reinterpret_cast<T *>(smem + stage_off);       // [kGroups][kTabStride], 16-byte aligned
+    load_twiddles<T>(twall, I.p1, reinterpret_cast<const C2<T> *>(twv));
     const size_t stride = (size_t)N2 * N3h * kNQ;
     C2<T> *g = reinterpret_cast<C2<T> *>(I.spec) + ((size_t)k2 * N3h + k30) * kNQ;
     for (int idx = threadIdx.x; idx < N1 * W; idx += kThreads) {
         const int l = idx / W, w = idx - l * W;
-        buf[idx] = g[l * stride + w];
+        buf[l * es + w] = g[l * stride + w];
     }
     __syncthreads();
-    fft_lines<T>(buf, I.p1, W, W, 1, twall, -1);
+    fft_lc<T, -1, LC>(buf, I.p1, W, es, 1, twall);
 
     const T *tab = reinterpret_cast<const T *>(I.shelltab);
     const int m2 = freq_abs(k2, N2);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int grp = lane / kNQ, al = lane - grp * kNQ;
+    const bool lane_on = grp < 64 / kNQ;
+    const int gid = wave * (64 / kNQ) + grp;
+    T *st = stage + (size_t)(lane_on ? gid : 0) * kTabStride;
+    const int nitems = (N1 / 2 + 1) * K3;
     const T inv_n = (T)I.inv_n;
     double e = 0.0;
-    for (int idx = threadIdx.x; idx < N1 * K3; idx += kThreads) {
-        const int l = idx / K3, w = idx - l * K3;
-        const int k3 = k30 + w;
-        const int s = I.shellmap[((size_t)freq_abs(l, N1) * I.h2 + m2) * N3h + k3];
-        const T *ph = tab + (size_t)s * kNPair;
-        C2<T> *x = buf + l * W + w * kNQ;
-        C2<T> th[kNQ], u[kNQ];
-#pragma unroll
-        for (int a = 0; a < kNQ; ++a) {
-            th[a] = cscale(x[a], inv_n);
-            u[a] = mk<T>((T)0, (T)0);
+    for (int base = 0; base < nitems; base += kGroups) {
+        const int item = base + gid;
+        const bool on = lane_on && item < nitems;
+        int l = 0, lp = -1, k3 = 0;
+        if (on) {
+            const int m1 = item / K3, w = item - m1 * K3;
+            k3 = k30 + w;
+            l = m1;
+            lp = N1 - m1;
+            if (m1 == 0 || lp == m1) lp = -1;     // k1 = 0 and the Nyquist plane stand alone
+            const int s = I.shellmap[((size_t)m1 * I.h2 + m2) * N3h + k3];
+            const float4 *src = reinterpret_cast<const float4 *>(tab + (size_t)s * kTabStride);
+            float4 *dst = reinterpret_cast<float4 *>(st);
+            constexpr int nv = kTabStride * (int)sizeof(T) / 16;
+            for (int v = al; v < nv; v += kNQ) dst[v] = src[v];
         }
-        int pidx = 0;
+        __syncthreads();
+        C2<T> u1 = mk<T>((T)0, (T)0), u2 = mk<T>((T)0, (T)0), own1 = u1, own2 = u1;
+        if (on) {
+            const int w = k3 - k30;
+            const C2<T> *x1 = buf + l * es + w * kNQ;
+            const C2<T> *x2 = buf + (lp >= 0 ? lp : l) * es + w * kNQ;
 #pragma unroll
-        for (int a = 0; a < kNQ; ++a) {
-#pragma unroll
-            for (int b = a; b < kNQ; ++b) {
-                const T f = ph[pidx++];
-                u[a].x += f * th[b].x;
-                u[a].y += f * th[b].y;
-                if (b != a) {
-                    u[b].x += f * th[a].x;
-                    u[b].y += f * th[a].y;
-                }
+            for (int b = 0; b < kNQ; ++b) {
+                // packed index of (min(a,b), max(a,b)) in the row-by-row upper triangle
+                const int lo = al < b ? al : b, hi = al < b ? b : al;
+                const T f = st[lo * kNQ - (lo * (lo - 1)) / 2 + (hi - lo)];
+                const C2<T> t1 = x1[b], t2 = x2[b];
+                u1.x += f * t1.x;
+                u1.y += f * t1.y;
+                u2.x += f * t2.x;
+                u2.y += f * t2.y;
             }
+            own1 = x1[al];
+            own2 = x2[al];
+            const bool edge = (k3 == 0) || ((N3 & 1) == 0 && k3 == N3 / 2);
+            const double wgt = (edge ? 1.0 : 2.0) * (double)inv_n * (double)inv_n;
+            e += wgt * (double)(own1.x * u1.x + own1.y * u1.y);
+            if (lp >= 0) e += wgt * (double)(own2.x * u2.x + own2.y * u2.y);
         }
-        T ek = (T)0;
-#pragma unroll
-        for (int a = 0; a < kNQ; ++a) {
-            ek += th[a].x * u[a].x + th[a].y * u[a].y;
-            x[a] = u[a];
+        __syncthreads();
+        if (on) {
+            const int w = k3 - k30;
+            buf[l * es + w * kNQ + al] = cscale(u1, inv_n);
+            if (lp >= 0) buf[lp * es + w * kNQ + al] = cscale(u2, inv_n);
         }
-        const bool edge = (k3 == 0) || ((N3 & 1) == 0 && k3 == N3 / 2);
-        e += (edge ? 1.0 : 2.0) * (double)ek;
     }
     __syncthreads();
-    fft_lines<T>(buf, I.p1, W, W, 1, twall, +1);
+    fft_lc<T, 1, LC>(buf, I.p1, W, es, 1, twall);
     for (int idx = threadIdx.x; idx < N1 * W; idx += kThreads) {
         const int l = idx / W, w = idx - l * W;
-        g[l * stride + w] = buf[idx];
+        g[l * stride + w] = buf[l * es + w];
     }
-    const double s = block_sum(e);
-    if (threadIdx.x == 0) I.part_ek[t.slot] = s;
+    const double sum = block_sum(e);
+    if (threadIdx.x == 0) I.part_ek[t.slot] = sum;
 }
 
 // E_k = (Omega/2) sum of the axis-1 partials; Delta E = dOmega sum of the
@@ -566,31 +609,58 @@ __global__ void __launch_bounds__(kThreads) k_reduce(const InstDev *insts, doubl
 
 // ---------------------------------------------------------------- launchers
 
-template <typename T>
-static hipError_t launch_kind_t(int kind, const LaunchArgs &a) {
-    if (a.ntiles <= 0) return hipSuccess;
+// Kernels that take more than 64 KB of LDS opt in to the device's limit.
+template <typename K>
+static void allow_lds(K kernel, size_t bytes) {
+    if (bytes > 65536) (void)hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+template <typename T, int LC>
+static hipError_t launch_lc(int kind, const LaunchArgs &a) {
     dim3 grid(a.ntiles), block(kThreads);
+#define VDWNL_LAUNCH(kern, ...)                                                              \
+    do {                                                                                     \
+        allow_lds(kern, a.lds);                                                              \
+        hipLaunchKernelGGL(kern, grid, block, a.lds, a.stream, a.insts, a.tiles, __VA_ARGS__); \
+    } while (0)
     switch (kind) {
-        case KX_NFWD: hipLaunchKernelGGL(k_x_nfwd<T>, grid, block, a.lds, a.stream, a.insts, a.tiles, a.twd); break;
-        case KY_1F: hipLaunchKernelGGL(k_y<double>, grid, block, a.lds, a.stream, a.insts, a.tiles, a.twd, 2, 1, -1); break;
-        case KZ_GRAD: hipLaunchKernelGGL(k_z_grad<double>, grid, block, a.lds, a.stream, a.insts, a.tiles, a.twd); break;
-        case KY_3I: hipLaunchKernelGGL(k_y<double>, grid, block, a.lds, a.stream, a.insts, a.tiles, a.twd, 1, 3, +1); break;
-        case KX_THETA: hipLaunchKernelGGL(k_x_theta<T>, grid, block, a.lds, a.stream, a.insts, a.tiles, a.cst, a.tw, a.twd); break;
-        case KY_20F: hipLaunchKernelGGL(k_y<T>, grid, block, a.lds, a.stream, a.insts, a.tiles, a.tw, 0, kNQ, -1); break;
-        case KZ_MAIN: hipLaunchKernelGGL(k_z_main<T>, grid, block, a.lds, a.stream, a.insts, a.tiles, a.tw); break;
-        case KY_20I: hipLaunchKernelGGL(k_y<T>, grid, block, a.lds, a.stream, a.insts, a.tiles, a.tw, 0, kNQ, +1); break;
-        case KX_ASSEMBLE: hipLaunchKernelGGL(k_x_assemble<T>, grid, block, a.lds, a.stream, a.insts, a.tiles, a.cst, a.tw, a.twd); break;
-        case KY_3F: hipLaunchKernelGGL(k_y<double>, grid, block, a.lds, a.stream, a.insts, a.tiles, a.twd, 1, 3, -1); break;
-        case KZ_DIV: hipLaunchKernelGGL(k_z_div<double>, grid, block, a.lds, a.stream, a.insts, a.tiles, a.twd); break;
-        case KY_1I: hipLaunchKernelGGL(k_y<double>, grid, block, a.lds, a.stream, a.insts, a.tiles, a.twd, 2, 1, +1); break;
-        case KX_FINAL: hipLaunchKernelGGL(k_x_final<T>, grid, block, a.lds, a.stream, a.insts, a.tiles, a.twd); break;
+        case KX_NFWD: VDWNL_LAUNCH((k_x_nfwd<T, LC>), a.twd); break;
+        case KY_1F: VDWNL_LAUNCH((k_y<double, -1, LC>), a.twd, 2, 1); break;
+        case KZ_GRAD: VDWNL_LAUNCH((k_z_grad<double, LC>), a.twd); break;
+        case KY_3I: VDWNL_LAUNCH((k_y<double, 1, LC>), a.twd, 1, 3); break;
+        case KX_THETA: VDWNL_LAUNCH((k_x_theta<T, LC>), a.cst, a.tw, a.twd); break;
+        case KY_20F: VDWNL_LAUNCH((k_y<T, -1, LC>), a.tw, 0, kNQ); break;
+        case KZ_MAIN: VDWNL_LAUNCH((k_z_main<T, LC>), a.tw); break;
+        case KY_20I: VDWNL_LAUNCH((k_y<T, 1, LC>), a.tw, 0, kNQ); break;
+        case KX_ASSEMBLE: VDWNL_LAUNCH((k_x_assemble<T, LC>), a.cst, a.tw, a.twd); break;
+        case KY_3F: VDWNL_LAUNCH((k_y<double, -1, LC>), a.twd, 1, 3); break;
+        case KZ_DIV: VDWNL_LAUNCH((k_z_div<double, LC>), a.twd); break;
+        case KY_1I: VDWNL_LAUNCH((k_y<double, 1, LC>), a.twd, 2, 1); break;
+        case KX_FINAL: VDWNL_LAUNCH((k_x_final<T, LC>), a.twd); break;
         default: return hipErrorInvalidValue;
     }
+#undef VDWNL_LAUNCH
     return hipGetLastError();
 }
 
-hipError_t launch_kind(int kind, int precision, const LaunchArgs &a) {
-    return precision == 64 ? launch_kind_t<double>(kind, a) : launch_kind_t<float>(kind, a);
+template <typename T>
+static hipError_t launch_kind_t(int kind, int lc, const LaunchArgs &a) {
+    if (a.ntiles <= 0) return hipSuccess;
+    switch (lc) {
+        case 0: return launch_lc<T, 0>(kind, a);
+        case 1: return launch_lc<T, 1>(kind, a);
+        case 2: return launch_lc<T, 2>(kind, a);
+        case 3: return launch_lc<T, 3>(kind, a);
+        case 4: return launch_lc<T, 4>(kind, a);
+        case 5: return launch_lc<T, 5>(kind, a);
+        case 6: return launch_lc<T, 6>(kind, a);
+        case 7: return launch_lc<T, 7>(kind, a);
+        default: return launch_lc<T, kLenGeneric>(kind, a);
+    }
+}
+
+hipError_t launch_kind(int kind, int lc, int precision, const LaunchArgs &a) {
+    return precision == 64 ? launch_kind_t<double>(kind, lc, a) : launch_kind_t<float>(kind, lc, a);
 }
 
 hipError_t launch_reduce(const InstDev *insts, int ninst, double *E, hipStream_t stream) {
