@@ -535,52 +535,43 @@ __global__ void __launch_bounds__(kThreads) k_z_main(const InstDev *insts, const
     const int nitems = (N1 / 2 + 1) * K3;
     const T inv_n = (T)I.inv_n;
     double e = 0.0;
-    for (int base = 0; base < nitems; base += kGroups) {
-        const int item = base + gid;
-        const bool on = lane_on && item < nitems;
-        int l = 0, lp = -1, k3 = 0;
-        if (on) {
-            const int m1 = item / K3, w = item - m1 * K3;
-            k3 = k30 + w;
-            l = m1;
-            lp = N1 - m1;
-            if (m1 == 0 || lp == m1) lp = -1;     // k1 = 0 and the Nyquist plane stand alone
-            const int s = I.shellmap[((size_t)m1 * I.h2 + m2) * N3h + k3];
-            const float4 *src = reinterpret_cast<const float4 *>(tab + (size_t)s * kTabStride);
-            float4 *dst = reinterpret_cast<float4 *>(st);
-            constexpr int nv = kTabStride * (int)sizeof(T) / 16;
-            for (int v = al; v < nv; v += kNQ) dst[v] = src[v];
-        }
-        __syncthreads();
-        C2<T> u1 = mk<T>((T)0, (T)0), u2 = mk<T>((T)0, (T)0), own1 = u1, own2 = u1;
-        if (on) {
-            const int w = k3 - k30;
-            const C2<T> *x1 = buf + l * es + w * kNQ;
-            const C2<T> *x2 = buf + (lp >= 0 ? lp : l) * es + w * kNQ;
+    // Each group works through its own items; a group's lanes share one wave,
+    // so staging, reads of theta and writes of u need wave-level ordering only.
+    for (int item = gid; lane_on && item < nitems; item += kGroups) {
+        const int m1 = item / K3, w = item - m1 * K3;
+        const int k3 = k30 + w;
+        const int l = m1;
+        int lp = N1 - m1;
+        if (m1 == 0 || lp == m1) lp = -1;     // k1 = 0 and the Nyquist plane stand alone
+        const int s = I.shellmap[((size_t)m1 * I.h2 + m2) * N3h + k3];
+        const float4 *src = reinterpret_cast<const float4 *>(tab + (size_t)s * kTabStride);
+        float4 *dst = reinterpret_cast<float4 *>(st);
+        constexpr int nv = kTabStride * (int)sizeof(T) / 16;
+        for (int v = al; v < nv; v += kNQ) dst[v] = src[v];
+        wave_sync();
+        C2<T> u1 = mk<T>((T)0, (T)0), u2 = u1;
+        C2<T> *x1 = buf + l * es + w * kNQ;
+        C2<T> *x2 = buf + (lp >= 0 ? lp : l) * es + w * kNQ;
 #pragma unroll
-            for (int b = 0; b < kNQ; ++b) {
-                // packed index of (min(a,b), max(a,b)) in the row-by-row upper triangle
-                const int lo = al < b ? al : b, hi = al < b ? b : al;
-                const T f = st[lo * kNQ - (lo * (lo - 1)) / 2 + (hi - lo)];
-                const C2<T> t1 = x1[b], t2 = x2[b];
-                u1.x += f * t1.x;
-                u1.y += f * t1.y;
-                u2.x += f * t2.x;
-                u2.y += f * t2.y;
-            }
-            own1 = x1[al];
-            own2 = x2[al];
-            const bool edge = (k3 == 0) || ((N3 & 1) == 0 && k3 == N3 / 2);
-            const double wgt = (edge ? 1.0 : 2.0) * (double)inv_n * (double)inv_n;
-            e += wgt * (double)(own1.x * u1.x + own1.y * u1.y);
-            if (lp >= 0) e += wgt * (double)(own2.x * u2.x + own2.y * u2.y);
+        for (int b = 0; b < kNQ; ++b) {
+            // packed index of (min(a,b), max(a,b)) in the row-by-row upper triangle
+            const int lo = al < b ? al : b, hi = al < b ? b : al;
+            const T f = st[lo * kNQ - (lo * (lo - 1)) / 2 + (hi - lo)];
+            const C2<T> t1 = x1[b], t2 = x2[b];
+            u1.x += f * t1.x;
+            u1.y += f * t1.y;
+            u2.x += f * t2.x;
+            u2.y += f * t2.y;
         }
-        __syncthreads();
-        if (on) {
-            const int w = k3 - k30;
-            buf[l * es + w * kNQ + al] = cscale(u1, inv_n);
-            if (lp >= 0) buf[lp * es + w * kNQ + al] = cscale(u2, inv_n);
-        }
+        const C2<T> own1 = x1[al], own2 = x2[al];
+        const bool edge = (k3 == 0) || ((N3 & 1) == 0 && k3 == N3 / 2);
+        const double wgt = (edge ? 1.0 : 2.0) * (double)inv_n * (double)inv_n;
+        e += wgt * (double)(own1.x * u1.x + own1.y * u1.y);
+        if (lp >= 0) e += wgt * (double)(own2.x * u2.x + own2.y * u2.y);
+        wave_sync();
+        x1[al] = cscale(u1, inv_n);
+        if (lp >= 0) x2[al] = cscale(u2, inv_n);
+        wave_sync();
     }
     __syncthreads();
     fft_lc<T, 1, LC>(buf, I.p1, W, es, 1, twall);
