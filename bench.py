@@ -83,6 +83,12 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--lds-budgets", type=str, default=None,
+                    help="x,y20,yaux,z,zaux LDS budgets in bytes (fixes the tiles; no tuning)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain device copy of 1 GiB (reference dispatch for "
+                         "hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only (this build has no multi-GPU path); use --gpus 1",
@@ -109,7 +115,17 @@ def main():
     table = build_kernel_table(0)
     log("kernel table built on the GPU (%.1f s)" % (time.time() - t0))
 
-    # ---- FP32 batched (headline)
+    if args.copy_calibration:
+        # a plain copy of known size: 1 GiB read, 1 GiB written
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("calibration copy: 1 GiB device to device")
+
+    # ---- FP32 batched (headline): tile tuning (setup), then graph replays
     lib = VdwNl(0)
     lib.set_grids(shapes, cells, 0, 32)
     lib.set_kernel_table(table["qmesh"], table["qc"], table["mc"], table["dk"], table["phi"], table["c_soft"])
@@ -117,18 +133,37 @@ def main():
     v32 = [torch.empty_like(x) for x in n32]
     nptr, vptr = [x.data_ptr() for x in n32], [x.data_ptr() for x in v32]
     stream = torch.cuda.current_stream().cuda_stream
+    t0 = time.time()
+    if args.lds_budgets:
+        lib.set_tiling([int(x) for x in args.lds_budgets.split(",")])
+    elif not args.no_autotune:
+        lib.autotune(nptr, vptr, reps=2, stream=stream)
+    tiling = lib.get_tiling()
+    log("tile budgets %s (%.1f s)" % (tiling, time.time() - t0))
     for _ in range(args.warmup):
         lib.energy_potential_batched(nptr, vptr, stream)
-    lib.set_timing(True)
     torch.cuda.synchronize()
+    step_ms = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        E32 = lib.energy_potential_batched(nptr, vptr, stream)
+        ts = time.perf_counter()
+        E32 = lib.energy_potential_batched(nptr, vptr, stream)   # returns after the stream is done
+        step_ms.append((time.perf_counter() - ts) * 1e3)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_step = (t1 - t0) * 1e3 / args.steps
+    med_ms = float(np.median(step_ms))
+    log("fp32 batched (graph replay): %.3f ms/step, median %.3f" % (ms_step, med_ms))
+    # the same steps again with a HIP event after every pass (passes launched
+    # one by one on the same stream): per-pass durations
+    lib.set_timing(True)
+    for _ in range(args.steps):
+        lib.energy_potential_batched(nptr, vptr, stream)
+    torch.cuda.synchronize()
     passes = lib.pass_times()
-    log("fp32 batched: %.3f ms/step" % ms_step)
+    lib.set_timing(False)
+    ev_ms = sum(v[0] for v in passes.values()) / args.steps
+    log("fp32 batched (event-timed launches): %.3f ms/step of passes" % ev_ms)
     for k, (ms, calls) in passes.items():
         log("  pass %-10s %8.3f ms/step" % (k, ms / max(calls, 1)))
 
@@ -184,6 +219,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_step,
+        "median_ms_per_step": med_ms,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -196,10 +232,14 @@ def main():
             "total_points": total,
             "precision": "theta/u FFTs and contraction FP32; grad n and divergence chains and "
                          "reductions FP64",
+            "launch": "one HIP graph per call (13 passes x FFT length classes), tile LDS budgets "
+                      "tuned at setup",
+            "lds_budgets": tiling,
         },
         "fp64_plain": {"ms_per_step": ms64, "value": total / (ms64 * 1e-3),
                        "max_rel_E_fp32_batched_vs_fp64_plain": max_rel, "max_abs_dv_Ha": max_dv},
         "passes_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in passes.items()},
+        "event_timed_ms_per_step": ev_ms,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": None,
                      "path_algorithmic_bytes_per_step": path_bytes,

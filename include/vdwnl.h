@@ -58,13 +58,18 @@ const char *vdwnl_last_error(const vdwnl_ctx *ctx);
 
 /* Plan one grid (replaces any previous plan).
  *   shape[3]   N1, N2, N3 >= 4, each a product of 2, 3 and 5;
- *              N1 <= 204 and N3 <= 340 (LDS tile limits)
+ *              N1 <= 204, N3 <= 408, N2 <= 4096 (one line of each axis must
+ *              fit an LDS tile; a device with less LDS may refuse smaller
+ *              grids), N1 N2 even
  *   cell[3]    orthorhombic cell lengths, bohr, > 0
  *   grad_mode  0: grad n by spectral differentiation, the Nyquist multiplier
  *              set to zero (the paper uses finite differences, the same role;
  *              1 is reserved for that variant)
  *   precision  32 or 64
- * Allocates all device workspace; the evaluation calls allocate nothing. */
+ * Device workspace is allocated at the first evaluation after planning;
+ * later evaluations allocate nothing.  Tile shapes follow one LDS budget per
+ * pass group: a budget set tuned by vdwnl_autotune for the same grid list and
+ * precision in this process is reused, else 64 KB each. */
 int vdwnl_set_grid(vdwnl_ctx *ctx, const int32_t shape[3], const double cell[3],
                    int32_t grad_mode, int32_t precision);
 
@@ -98,7 +103,12 @@ int vdwnl_set_kernel_table(vdwnl_ctx *ctx, int32_t nq, const double *qmesh, doub
 int vdwnl_energy_potential(vdwnl_ctx *ctx, const void *n_dev, void *v_dev, double *E_out,
                            void *stream);
 
-/* The planned batch: n_ptrs[nb], v_ptrs[nb] device pointers, E_out[nb][2]. */
+/* The planned batch: n_ptrs[nb], v_ptrs[nb] device pointers, E_out[nb][2].
+ * The first evaluation after planning captures the whole evaluation (every
+ * pass of every grid, the reduction and the copy of the energies) into a HIP
+ * graph on a private stream; later calls replay it on `stream`.  The graph
+ * reads the density and potential pointers of each call from pinned host
+ * memory when it runs, so any buffers may be passed. */
 int vdwnl_energy_potential_batched(vdwnl_ctx *ctx, int32_t nb, const void *const *n_ptrs,
                                    void *const *v_ptrs, double *E_out, void *stream);
 
@@ -113,10 +123,37 @@ int vdwnl_debug_field(vdwnl_ctx *ctx, int32_t inst, int32_t which, void *dst, vo
  * evaluation's stream); vdwnl_pass_times copies the accumulated milliseconds
  * of each pass (launch order, the FP64 energy reduction last) into ms[], the
  * number of timed evaluations into *calls, and returns the number of passes.
- * vdwnl_pass_name(i) names pass i ("" outside the range). */
+ * vdwnl_pass_name(i) names pass i ("" outside the range).  Timed
+ * evaluations launch their passes one by one (no graph). */
 int vdwnl_set_timing(vdwnl_ctx *ctx, int32_t on);
 int vdwnl_pass_times(const vdwnl_ctx *ctx, int32_t max_passes, double *ms, int64_t *calls);
 const char *vdwnl_pass_name(int32_t i);
+
+/* Graph replay on (default, on != 0) or off (every evaluation launches its
+ * passes one by one; results are identical). */
+int vdwnl_set_graph(vdwnl_ctx *ctx, int32_t on);
+
+/* Tile-shape tuning for the planned grids: evaluates the batch (n_ptrs[nb],
+ * v_ptrs[nb] as for vdwnl_energy_potential_batched; v is overwritten) once
+ * plus `reps` timed times (1..100) for each candidate LDS budget, picks per
+ * pass group the budget with the least time over the group's passes, plans
+ * with it and remembers it for this grid list and precision for the rest of
+ * the process.  Results do not depend on the tile shapes beyond rounding
+ * order.  Returns an error code as the evaluation does. */
+int vdwnl_autotune(vdwnl_ctx *ctx, int32_t nb, const void *const *n_ptrs, void *const *v_ptrs,
+                   int32_t reps, void *stream);
+
+/* LDS budget (bytes) of each pass group in the current plan, in the order
+ * axis-3 (theta, assembly), axis-2 over the 20 spectra, axis-2 over the
+ * gradient / divergence spectra, axis-1 with the contraction, axis-1 of the
+ * gradient / divergence; copies up to max_groups values and returns the
+ * number of groups (5). */
+int vdwnl_get_tiling(const vdwnl_ctx *ctx, int32_t max_groups, int64_t *lds_budget);
+
+/* Set the five LDS budgets (bytes, same order, each in [4096, the device's
+ * LDS per workgroup]) and re-plan the tiles of the planned grids (the
+ * workspace is rebuilt at the next evaluation). */
+int vdwnl_set_tiling(vdwnl_ctx *ctx, int32_t ngroups, const int64_t *lds_budget);
 
 /* Build the kernel table that vdwnl_set_kernel_table takes, on GPU `device`
  * (the step before the evaluation; it depends only on the q mesh and the
@@ -133,6 +170,11 @@ const char *vdwnl_pass_name(int32_t i);
  * mesh not increasing), VDWNL_E_STATE (device < 0), VDWNL_E_HIP. */
 int vdwnl_build_kernel_table(int device, int32_t nq, const double *qmesh, double d_s, double phi0,
                              int32_t nk, double dk, double *phi_out, double *c_soft_out);
+
+/* The kernel phi(d1, d2) of Eq. (Enl) itself, by the generator's double
+ * integral, on GPU `device`: out[i] = phi(d1[i], d2[i]) (Hartree), host
+ * arrays of n values, 0 < d1, d2 <= 460.  E_ARG for other arguments. */
+int vdwnl_kernel_phi(int device, int32_t n, const double *d1, const double *d2, double *out);
 
 /* Number of planned grids and the bytes of device workspace held. */
 int vdwnl_info(const vdwnl_ctx *ctx, int32_t *n_grids, int64_t *workspace_bytes);

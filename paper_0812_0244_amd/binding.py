@@ -39,6 +39,11 @@ SIGNATURES = {
     "vdwnl_pass_name": (ctypes.c_char_p, [_i32]),
     "vdwnl_build_kernel_table": (ctypes.c_int, [ctypes.c_int, _i32, _dp, ctypes.c_double, ctypes.c_double,
                                                 _i32, ctypes.c_double, _dp, _dp]),
+    "vdwnl_kernel_phi": (ctypes.c_int, [ctypes.c_int, _i32, _dp, _dp, _dp]),
+    "vdwnl_set_graph": (ctypes.c_int, [_vp, _i32]),
+    "vdwnl_autotune": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _i32, _vp]),
+    "vdwnl_get_tiling": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(ctypes.c_int64)]),
+    "vdwnl_set_tiling": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(ctypes.c_int64)]),
 }
 
 _lib = None
@@ -77,6 +82,19 @@ def log_qmesh(nq: int = 20, q1: float = 0.05, qc: float = 5.0, lam: float = 1.17
     q = q1 + np.concatenate([[0.0], np.cumsum(d * (qc - q1) / d.sum())])
     q[-1] = qc
     return q
+
+
+def kernel_phi(d1, d2, device: int = 0):
+    """phi(d1, d2) of Eq. (Enl) evaluated on the GPU (host arrays in and out)."""
+    lib = load_library()
+    a = np.ascontiguousarray(np.broadcast_arrays(np.asarray(d1, float), np.asarray(d2, float))[0]).ravel()
+    b = np.ascontiguousarray(np.broadcast_arrays(np.asarray(d1, float), np.asarray(d2, float))[1]).ravel()
+    out = np.zeros(a.size)
+    rc = lib.vdwnl_kernel_phi(int(device), a.size, _as_ptr(a, ctypes.c_double), _as_ptr(b, ctypes.c_double),
+                              _as_ptr(out, ctypes.c_double))
+    if rc != 0:
+        raise VdwNlError(rc, "kernel_phi")
+    return out
 
 
 def build_kernel_table(device: int = 0, nq: int = 20, q1: float = 0.05, qc: float = 5.0, lam: float = 1.17,
@@ -164,6 +182,30 @@ class VdwNl:
         self._check(self.lib.vdwnl_energy_potential_batched(self.h, nb, na, va, _as_ptr(E, ctypes.c_double),
                                                             _vp(stream)), "energy_potential_batched")
         return E
+
+    def set_graph(self, on: bool = True):
+        self._check(self.lib.vdwnl_set_graph(self.h, 1 if on else 0), "set_graph")
+
+    def autotune(self, n_ptrs, v_ptrs, reps: int = 2, stream: int = 0):
+        nb = len(n_ptrs)
+        na = (_vp * nb)(*[_vp(p) for p in n_ptrs])
+        va = (_vp * nb)(*[_vp(p) for p in v_ptrs])
+        self._check(self.lib.vdwnl_autotune(self.h, nb, na, va, int(reps), _vp(stream)), "autotune")
+
+    def set_tiling(self, budgets):
+        """budgets: dict with keys x, y20, yaux, z, zaux (bytes), or a sequence of 5."""
+        if isinstance(budgets, dict):
+            budgets = [budgets[k] for k in ("x", "y20", "yaux", "z", "zaux")]
+        b = (ctypes.c_int64 * 5)(*[int(x) for x in budgets])
+        self._check(self.lib.vdwnl_set_tiling(self.h, 5, b), "set_tiling")
+
+    def get_tiling(self):
+        """LDS budget (bytes) per pass group: x, y20, yaux, z, zaux."""
+        b = (ctypes.c_int64 * 8)()
+        n = self.lib.vdwnl_get_tiling(self.h, 8, b)
+        if n < 0:
+            raise VdwNlError(n, "get_tiling")
+        return dict(zip(("x", "y20", "yaux", "z", "zaux"), [int(b[i]) for i in range(n)]))
 
     def debug_field(self, inst: int, which: int, dst_ptr: int, stream: int = 0):
         self._check(self.lib.vdwnl_debug_field(self.h, inst, which, _vp(dst_ptr), _vp(stream)), "debug_field")

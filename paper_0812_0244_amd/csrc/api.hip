@@ -4,6 +4,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -78,11 +79,15 @@ static Shells build_shells(const int s[3], const double cell[3]) {
     return sh;
 }
 
+// Pass groups whose tile shapes follow one LDS budget each.
+enum TileGroup { TG_X = 0, TG_Y20, TG_YAUX, TG_Z, TG_ZAUX, TG_COUNT };
+
 struct Grid {
     int s[3];
     double cell[3];
     FftPlan p1, p2, p3;
     int bmain;               // rows per theta / assemble tile
+    int bnf;                 // rows per n-forward / final tile (even)
     int k3main, k3aux;       // k3 per fused axis-1 tile (20 comps), per grad/div tile
     int wy20, wy3, wy1;      // axis-2 tile widths
     int shell_key;           // index into Ctx::shells
@@ -102,6 +107,8 @@ struct vdwnl_ctx {
     int precision = 32;
     int grad_mode = 0;
     std::string err;
+    size_t pref[TG_COUNT] = {kLdsCap, kLdsCap, kLdsCap, kLdsCap, kLdsCap};   // LDS budget per pass group
+    std::string plan_key;                 // identifies the batch for the tuned-budget cache
     // plan
     std::vector<Grid> grids;
     std::vector<Shells> shells;
@@ -132,6 +139,11 @@ struct vdwnl_ctx {
     Consts *d_consts = nullptr;
     double *d_E = nullptr, *h_E = nullptr;
     std::map<int, int> tw_off;            // length -> offset
+    // the evaluation captured as a HIP graph (replayed on the caller's stream)
+    bool use_graph = true;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
     // per-pass timing
     bool timing = false;
     hipEvent_t ev[KIND_COUNT + 2] = {};
@@ -153,9 +165,19 @@ static int hipfail(vdwnl_ctx *c, hipError_t e, const char *what) {
     return fail(c, VDWNL_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+static void drop_graph(vdwnl_ctx *c) {
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->gexec = nullptr;
+    c->graph = nullptr;
+}
+
 static void free_device(vdwnl_ctx *c) {
     if (c->device < 0) return;
     (void)hipSetDevice(c->device);
+    drop_graph(c);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    c->cap_stream = nullptr;
     if (c->ev_made) {
         for (auto &e : c->ev) (void)hipEventDestroy(e);
         c->ev_made = false;
@@ -200,7 +222,7 @@ static int check_grid(vdwnl_ctx *c, const int32_t *shape, const double *cell, in
     auto zaux = [&](size_t k3) { return (N1 + (4 * k3 + 2) * N1) * 16; };
     auto xmain = [&](size_t b) { return b * (N3 + 1) * (2 * 16 + (kNQ / 2) * cs) + N3 * (16 + cs) + (kNQ + kNQ * kNQ) * rs; };
     auto ypass = [&](size_t w, size_t c2) { return (N2 + N2 * (w + 1)) * c2; };
-    const size_t cap = c->lds_cap, pref = std::min<size_t>(c->lds_cap, kLdsCap);
+    const size_t cap = c->lds_cap;
     if (N1 > (size_t)kMaxN1 || zmain(1) > cap)
         return fail(c, VDWNL_E_UNSUPPORTED_SIZE, "N1 too large for the fused axis-1 pass");
     if (N2 > (size_t)kTileCap || ypass(1, cs) > cap || ypass(1, 16) > cap)
@@ -209,19 +231,66 @@ static int check_grid(vdwnl_ctx *c, const int32_t *shape, const double *cell, in
         return fail(c, VDWNL_E_UNSUPPORTED_SIZE, "N3 too large for the axis-3 pass");
     if (!radix_plan((int)N1, g.p1) || !radix_plan((int)N2, g.p2) || !radix_plan((int)N3, g.p3))
         return fail(c, VDWNL_E_UNSUPPORTED_SIZE, "no radix plan");
-    // tile shapes: as large as the FFT tile cap allows while the LDS stays
-    // within 64 KB (two or more workgroups per CU); one unit at least
-    g.bmain = ((kNQ / 2) * 2 * N3 <= (size_t)kTileCap && xmain(2) <= pref) ? 2 : 1;
-    g.k3main = 1;
-    while ((size_t)kNQ * (g.k3main + 1) * N1 <= (size_t)kTileCap && zmain(g.k3main + 1) <= pref) ++g.k3main;
-    g.k3aux = 1;
-    while (3 * (size_t)(g.k3aux + 1) * N1 <= (size_t)kTileCap && zaux(g.k3aux + 1) <= pref) ++g.k3aux;
-    g.wy20 = 1;
-    while ((size_t)(g.wy20 + 1) * N2 <= (size_t)kTileCap && ypass(g.wy20 + 1, cs) <= pref) ++g.wy20;
-    g.wy3 = 1;
-    while ((size_t)(g.wy3 + 1) * N2 <= (size_t)kTileCap && ypass(g.wy3 + 1, 16) <= pref) ++g.wy3;
-    g.wy1 = g.wy3;
     return VDWNL_OK;
+}
+
+// Tile shapes of grid g from the LDS budget of each pass group: each tile as
+// large as the FFT tile cap and its group's budget allow (at least one unit).
+static void size_tiles(const vdwnl_ctx *c, Grid &g) {
+    const size_t cs = c->precision == 64 ? 16 : 8, rs = c->precision == 64 ? 8 : 4;
+    const size_t N1 = g.s[0], N2 = g.s[1], N3 = g.s[2];
+    const size_t stage = (size_t)((kThreads / 64) * (64 / kNQ)) * kTabStride * rs;
+    auto zmain = [&](size_t k3) { return (N1 + (kNQ * k3 + 1) * N1) * cs + 16 + stage; };
+    auto zaux = [&](size_t k3) { return (N1 + (4 * k3 + 2) * N1) * 16; };
+    auto xmain = [&](size_t b) { return b * (N3 + 1) * (2 * 16 + (kNQ / 2) * cs) + N3 * (16 + cs) + (kNQ + kNQ * kNQ) * rs; };
+    auto ypass = [&](size_t w, size_t c2) { return (N2 + N2 * (w + 1)) * c2; };
+    // axis-3 tiles: at most one grid point per thread (the local steps run
+    // one point per thread)
+    g.bmain = 1;
+    while ((size_t)(g.bmain + 1) * N3 <= (size_t)kThreads && (kNQ / 2) * (g.bmain + 1) * N3 <= (size_t)kTileCap &&
+           xmain(g.bmain + 1) <= c->pref[TG_X])
+        ++g.bmain;
+    g.bnf = 2;
+    while ((size_t)(g.bnf + 2) * N3 <= (size_t)kThreads) g.bnf += 2;
+    g.k3main = 1;
+    while ((size_t)kNQ * (g.k3main + 1) * N1 <= (size_t)kTileCap && zmain(g.k3main + 1) <= c->pref[TG_Z]) ++g.k3main;
+    g.k3aux = 1;
+    while (3 * (size_t)(g.k3aux + 1) * N1 <= (size_t)kTileCap && zaux(g.k3aux + 1) <= c->pref[TG_ZAUX]) ++g.k3aux;
+    g.wy20 = 1;
+    while ((size_t)(g.wy20 + 1) * N2 <= (size_t)kTileCap && ypass(g.wy20 + 1, cs) <= c->pref[TG_Y20]) ++g.wy20;
+    if (g.wy20 > 1) g.wy20 &= ~1;   // even widths: 16-byte aligned FP32 rows
+    g.wy3 = 1;
+    while ((size_t)(g.wy3 + 1) * N2 <= (size_t)kTileCap && ypass(g.wy3 + 1, 16) <= c->pref[TG_YAUX]) ++g.wy3;
+    g.wy1 = g.wy3;
+}
+
+// Tuned LDS budgets, per process, keyed by precision, LDS size and the exact
+// list of grid shapes and cells.
+static std::mutex g_tuned_mu;
+static std::map<std::string, std::vector<size_t>> g_tuned;
+
+static std::string plan_key(const vdwnl_ctx *c) {
+    std::string k = std::to_string(c->precision) + "/" + std::to_string(c->lds_cap);
+    char buf[128];
+    for (const Grid &g : c->grids) {
+        std::snprintf(buf, sizeof(buf), ";%dx%dx%d@%.17g,%.17g,%.17g", g.s[0], g.s[1], g.s[2], g.cell[0], g.cell[1],
+                      g.cell[2]);
+        k += buf;
+    }
+    return k;
+}
+
+static bool tuned_lookup(const std::string &key, size_t *pref) {
+    std::lock_guard<std::mutex> lk(g_tuned_mu);
+    auto it = g_tuned.find(key);
+    if (it == g_tuned.end()) return false;
+    for (int i = 0; i < TG_COUNT; ++i) pref[i] = it->second[i];
+    return true;
+}
+
+static void tuned_store(const std::string &key, const size_t *pref) {
+    std::lock_guard<std::mutex> lk(g_tuned_mu);
+    g_tuned[key] = std::vector<size_t>(pref, pref + TG_COUNT);
 }
 
 static int plan_grids(vdwnl_ctx *c, int nb, const int32_t *shapes, const double *cells, int grad_mode,
@@ -238,6 +307,11 @@ static int plan_grids(vdwnl_ctx *c, int nb, const int32_t *shapes, const double 
     c->grids = gs;
     c->precision = precision;
     c->grad_mode = grad_mode;
+    // tile budgets: a tuned set for this exact batch if one exists, else defaults
+    c->plan_key = plan_key(c);
+    if (!tuned_lookup(c->plan_key, c->pref))
+        for (auto &p : c->pref) p = std::min<size_t>(c->lds_cap, kLdsCap);
+    for (auto &g : c->grids) size_tiles(c, g);
     c->shells.clear();
     c->shell_keys.clear();
     for (auto &g : c->grids) {
@@ -323,9 +397,10 @@ static int prepare_device(vdwnl_ctx *c) {
         const int rows = N1 * N2;
         const int inst = (int)gi;
         // axis-3 tiles
-        for (int r = 0; r < rows; r += 2) {
-            tiles[KX_NFWD].push_back({inst, r, 2, 0, -1});
-            tiles[KX_FINAL].push_back({inst, r, 2, 0, -1});
+        for (int r = 0; r < rows; r += g.bnf) {
+            const int b = std::min(g.bnf, rows - r);   // even: rows and bnf are
+            tiles[KX_NFWD].push_back({inst, r, b, 0, -1});
+            tiles[KX_FINAL].push_back({inst, r, b, 0, -1});
         }
         int slot = 0;
         for (int r = 0; r < rows; r += g.bmain) {
@@ -343,16 +418,40 @@ static int prepare_device(vdwnl_ctx *c) {
             for (int i1 = 0; i1 < N1; ++i1)
                 for (int f = 0; f < ftot; f += w) tiles[kinds_y[q]].push_back({inst, i1, f, std::min(w, ftot - f), -1});
         }
-        // axis-1 tiles
-        slot = 0;
-        for (int k2 = 0; k2 < N2; ++k2) {
-            for (int k3 = 0; k3 < N3h; k3 += g.k3main)
-                tiles[KZ_MAIN].push_back({inst, k2, k3, std::min(g.k3main, N3h - k3), slot++});
+        // axis-1 tiles.  The fused pass reads one kernel row per |G| shell and
+        // point pair; the columns k2 and N2 - k2 (same |m2|) meet the same
+        // shells, so their tiles are placed 8 apart in the launch (workgroups
+        // go round-robin to the 8 XCDs: same XCD, same L2, about the same time).
+        {
+            std::vector<std::pair<Tile, Tile>> prs;
+            std::vector<Tile> singles;
+            for (int k2 = 0; k2 < N2; ++k2) {
+                const int partner = (N2 - k2) % N2;
+                if (partner < k2) continue;
+                for (int k3 = 0; k3 < N3h; k3 += g.k3main) {
+                    const int cnt = std::min(g.k3main, N3h - k3);
+                    if (partner == k2) singles.push_back({inst, k2, k3, cnt, -1});
+                    else prs.push_back({{inst, k2, k3, cnt, -1}, {inst, partner, k3, cnt, -1}});
+                }
+            }
+            std::vector<Tile> zt;
+            for (size_t b0 = 0; b0 < prs.size(); b0 += 8) {
+                const size_t b1 = std::min(prs.size(), b0 + 8);
+                for (size_t i = b0; i < b1; ++i) zt.push_back(prs[i].first);
+                for (size_t i = b0; i < b1; ++i) zt.push_back(prs[i].second);
+            }
+            zt.insert(zt.end(), singles.begin(), singles.end());
+            slot = 0;
+            for (Tile &tl : zt) {
+                tl.slot = slot++;
+                tiles[KZ_MAIN].push_back(tl);
+            }
+        }
+        for (int k2 = 0; k2 < N2; ++k2)
             for (int k3 = 0; k3 < N3h; k3 += g.k3aux) {
                 tiles[KZ_GRAD].push_back({inst, k2, k3, std::min(g.k3aux, N3h - k3), -1});
                 tiles[KZ_DIV].push_back({inst, k2, k3, std::min(g.k3aux, N3h - k3), -1});
             }
-        }
         g.n_ek = slot;
         // fields
         g.off_grad = off; off = align_up(off + 3 * g.npts() * rs);
@@ -368,7 +467,7 @@ static int prepare_device(vdwnl_ctx *c) {
         const size_t N1 = g.s[0], N2 = g.s[1], N3 = g.s[2];
         const size_t xm = g.bmain * (N3 + 1) * (2 * 16 + (kNQ / 2) * cs) + N3 * (16 + cs) + (kNQ + kNQ * kNQ) * rs;
         switch (k) {
-            case KX_NFWD: case KX_FINAL: return (N3 + (N3 + 1)) * 16;
+            case KX_NFWD: case KX_FINAL: return (N3 + (g.bnf / 2) * (N3 + 1)) * 16;
             case KX_THETA: case KX_ASSEMBLE: return xm;
             case KY_1F: case KY_1I: return (N2 + N2 * (g.wy1 + 1)) * 16;
             case KY_3F: case KY_3I: return (N2 + N2 * (g.wy3 + 1)) * 16;
@@ -400,6 +499,13 @@ static int prepare_device(vdwnl_ctx *c) {
             if (L.cnt > 0) c->launches[k].push_back(L);
         }
     }
+    // kernels whose tiles take more than 64 KB of LDS opt in to it now (not
+    // at launch time: launches may be captured into a graph)
+    for (int k = 0; k < KIND_COUNT; ++k)
+        for (const auto &L : c->launches[k]) {
+            LaunchArgs a{nullptr, nullptr, 0, L.lds, nullptr, nullptr, nullptr, nullptr};
+            if ((e = launch_kind(k, L.lc, c->precision, a)) != hipSuccess) return hipfail(c, e, "kernel LDS limit");
+        }
     // twiddles
     c->tw_off.clear();
     std::vector<double> twd;
@@ -484,30 +590,13 @@ static int prepare_device(vdwnl_ctx *c) {
     return VDWNL_OK;
 }
 
-static int run(vdwnl_ctx *c, int nb, const void *const *n_ptrs, void *const *v_ptrs, double *E_out, void *stream) {
-    if (!c) return VDWNL_E_ARG;
-    if (!n_ptrs || !v_ptrs || !E_out) return fail(c, VDWNL_E_ARG, "null pointer");
-    if (!c->have_grid || !c->have_table) return fail(c, VDWNL_E_STATE, "grid and kernel table must both be set");
-    if (nb != (int)c->grids.size()) return fail(c, VDWNL_E_ARG, "batch size differs from the planned grids");
-    for (int i = 0; i < nb; ++i)
-        if (!n_ptrs[i] || !v_ptrs[i]) return fail(c, VDWNL_E_ARG, "null density or potential pointer");
-    if (c->device < 0) return fail(c, VDWNL_E_STATE, "host-only context");
-    int rc = prepare_device(c);
-    if (rc != VDWNL_OK) return rc;
-    hipError_t e = hipSetDevice(c->device);
-    if (e != hipSuccess) return hipfail(c, e, "hipSetDevice");
-    hipStream_t st = (hipStream_t)stream;
-    for (int i = 0; i < nb; ++i) {
-        c->h_inst[i].n = n_ptrs[i];
-        c->h_inst[i].v = v_ptrs[i];
-    }
+// Enqueue one evaluation on st: the instance table (device pointers of this
+// call's n and v), the thirteen passes, the reduction and the copy of the
+// energies to pinned host memory.  With timing on, events bracket each pass.
+static int enqueue(vdwnl_ctx *c, int nb, hipStream_t st) {
+    hipError_t e;
     if ((e = hipMemcpyAsync(c->d_inst, c->h_inst, nb * sizeof(InstDev), hipMemcpyHostToDevice, st)) != hipSuccess)
         return hipfail(c, e, "upload instance table");
-    if (c->timing && !c->ev_made) {
-        for (auto &ev : c->ev)
-            if ((e = hipEventCreate(&ev)) != hipSuccess) return hipfail(c, e, "hipEventCreate");
-        c->ev_made = true;
-    }
     if (c->timing) (void)hipEventRecord(c->ev[0], st);
     for (int i = 0; i < KIND_COUNT; ++i) {
         const int k = kPassOrder[i];
@@ -521,6 +610,67 @@ static int run(vdwnl_ctx *c, int nb, const void *const *n_ptrs, void *const *v_p
     if (c->timing) (void)hipEventRecord(c->ev[KIND_COUNT + 1], st);
     if ((e = hipMemcpyAsync(c->h_E, c->d_E, nb * 2 * sizeof(double), hipMemcpyDeviceToHost, st)) != hipSuccess)
         return hipfail(c, e, "copy energies");
+    return VDWNL_OK;
+}
+
+// Capture enqueue() once into a graph (on a private stream: the caller's may
+// be the null stream, which cannot be captured).  The graph reads the pinned
+// instance table when it runs, so one graph serves every call.
+static int capture(vdwnl_ctx *c, int nb) {
+    hipError_t e;
+    if (!c->cap_stream && (e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking)) != hipSuccess) {
+        c->cap_stream = nullptr;
+        return hipfail(c, e, "hipStreamCreate");
+    }
+    if ((e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed)) != hipSuccess)
+        return hipfail(c, e, "hipStreamBeginCapture");
+    const int rc = enqueue(c, nb, c->cap_stream);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(c->cap_stream, &g);
+    if (rc != VDWNL_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return hipfail(c, e, "hipStreamEndCapture");
+    c->graph = g;
+    if ((e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0)) != hipSuccess) {
+        c->gexec = nullptr;
+        drop_graph(c);
+        return hipfail(c, e, "hipGraphInstantiate");
+    }
+    return VDWNL_OK;
+}
+
+static int run(vdwnl_ctx *c, int nb, const void *const *n_ptrs, void *const *v_ptrs, double *E_out, void *stream) {
+    if (!c) return VDWNL_E_ARG;
+    if (!n_ptrs || !v_ptrs || !E_out) return fail(c, VDWNL_E_ARG, "null pointer");
+    if (!c->have_grid || !c->have_table) return fail(c, VDWNL_E_STATE, "grid and kernel table must both be set");
+    if (nb != (int)c->grids.size()) return fail(c, VDWNL_E_ARG, "batch size differs from the planned grids");
+    for (int i = 0; i < nb; ++i)
+        if (!n_ptrs[i] || !v_ptrs[i]) return fail(c, VDWNL_E_ARG, "null density or potential pointer");
+    if (c->device < 0) return fail(c, VDWNL_E_STATE, "host-only context");
+    int rc = prepare_device(c);
+    if (rc != VDWNL_OK) return rc;
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hipfail(c, e, "hipSetDevice");
+    hipStream_t st = (hipStream_t)stream;
+    // the previous call has synchronised: the pinned table is free to update
+    for (int i = 0; i < nb; ++i) {
+        c->h_inst[i].n = n_ptrs[i];
+        c->h_inst[i].v = v_ptrs[i];
+    }
+    if (c->timing && !c->ev_made) {
+        for (auto &ev : c->ev)
+            if ((e = hipEventCreate(&ev)) != hipSuccess) return hipfail(c, e, "hipEventCreate");
+        c->ev_made = true;
+    }
+    if (c->use_graph && !c->timing) {
+        if (!c->gexec && (rc = capture(c, nb)) != VDWNL_OK) return rc;
+        if ((e = hipGraphLaunch(c->gexec, st)) != hipSuccess) return hipfail(c, e, "hipGraphLaunch");
+    } else {
+        // per-pass timing: eager launches bracketed by events
+        if ((rc = enqueue(c, nb, st)) != VDWNL_OK) return rc;
+    }
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return hipfail(c, e, "stream synchronize");
     std::memcpy(E_out, c->h_E, nb * 2 * sizeof(double));
     if (c->timing) {
@@ -683,6 +833,84 @@ int vdwnl_debug_field(vdwnl_ctx *ctx, int32_t inst, int32_t which, void *dst, vo
     hipError_t e = hipMemcpyAsync(dst, (char *)ctx->work + off, bytes, hipMemcpyDeviceToDevice, (hipStream_t)stream);
     if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
     return e == hipSuccess ? VDWNL_OK : hipfail(ctx, e, "debug copy");
+}
+
+int vdwnl_set_graph(vdwnl_ctx *ctx, int32_t on) {
+    if (!ctx) return VDWNL_E_ARG;
+    ctx->use_graph = on != 0;
+    return VDWNL_OK;
+}
+
+int vdwnl_autotune(vdwnl_ctx *ctx, int32_t nb, const void *const *n_ptrs, void *const *v_ptrs, int32_t reps,
+                   void *stream) {
+    if (!ctx) return VDWNL_E_ARG;
+    if (!ctx->have_grid || !ctx->have_table) return fail(ctx, VDWNL_E_STATE, "grid and kernel table must both be set");
+    if (reps < 1 || reps > 100) return fail(ctx, VDWNL_E_ARG, "reps must be in 1..100");
+    // candidate budgets; the tile sizing keeps at least one unit per tile, so
+    // a budget below some pass's minimum simply gives that pass its minimum
+    std::vector<size_t> cand;
+    for (size_t b : {16384, 24576, 32768, 49152, 65536, 98304, 131072})
+        if (b <= ctx->lds_cap) cand.push_back(b);
+    const bool timing0 = ctx->timing;
+    std::vector<std::vector<double>> t(cand.size(), std::vector<double>(KIND_COUNT, 0.0));
+    int rc = VDWNL_OK;
+    std::vector<double> E((size_t)nb * 2);
+    for (size_t ci = 0; ci < cand.size() && rc == VDWNL_OK; ++ci) {
+        for (auto &p : ctx->pref) p = cand[ci];
+        for (auto &g : ctx->grids) size_tiles(ctx, g);
+        free_device(ctx);
+        ctx->timing = false;
+        rc = run(ctx, nb, n_ptrs, v_ptrs, E.data(), stream);   // plans and warms up
+        if (rc != VDWNL_OK) break;
+        vdwnl_set_timing(ctx, 1);
+        for (int r = 0; r < reps && rc == VDWNL_OK; ++r) rc = run(ctx, nb, n_ptrs, v_ptrs, E.data(), stream);
+        for (int k = 0; k < KIND_COUNT; ++k) t[ci][k] = ctx->pass_ms[k];
+    }
+    // per group, the budget with the least time over the group's passes
+    // (pass_ms is indexed by position in the launch order)
+    auto pos = [](int kind) {
+        for (int i = 0; i < KIND_COUNT; ++i)
+            if (kPassOrder[i] == kind) return i;
+        return 0;
+    };
+    const std::vector<std::vector<int>> groups = {
+        {KX_THETA, KX_ASSEMBLE}, {KY_20F, KY_20I}, {KY_1F, KY_1I, KY_3F, KY_3I}, {KZ_MAIN}, {KZ_GRAD, KZ_DIV}};
+    size_t best[TG_COUNT];
+    for (int gi = 0; gi < TG_COUNT; ++gi) {
+        double bt = 1e300;
+        best[gi] = std::min<size_t>(ctx->lds_cap, kLdsCap);
+        for (size_t ci = 0; rc == VDWNL_OK && ci < cand.size(); ++ci) {
+            double sum = 0.0;
+            for (int k : groups[gi]) sum += t[ci][pos(k)];
+            if (sum < bt) { bt = sum; best[gi] = cand[ci]; }
+        }
+    }
+    for (int gi = 0; gi < TG_COUNT; ++gi) ctx->pref[gi] = best[gi];
+    for (auto &g : ctx->grids) size_tiles(ctx, g);
+    free_device(ctx);
+    vdwnl_set_timing(ctx, timing0 ? 1 : 0);
+    if (rc != VDWNL_OK) return rc;
+    tuned_store(ctx->plan_key, ctx->pref);
+    return VDWNL_OK;
+}
+
+int vdwnl_set_tiling(vdwnl_ctx *ctx, int32_t ngroups, const int64_t *lds_budget) {
+    if (!ctx || !lds_budget) return VDWNL_E_ARG;
+    if (ngroups != TG_COUNT) return fail(ctx, VDWNL_E_ARG, "expected one budget per pass group (5)");
+    if (!ctx->have_grid) return fail(ctx, VDWNL_E_STATE, "no grid planned");
+    for (int i = 0; i < TG_COUNT; ++i)
+        if (lds_budget[i] < 4096 || (size_t)lds_budget[i] > ctx->lds_cap)
+            return fail(ctx, VDWNL_E_ARG, "LDS budget outside [4096, device LDS per workgroup]");
+    for (int i = 0; i < TG_COUNT; ++i) ctx->pref[i] = (size_t)lds_budget[i];
+    for (auto &g : ctx->grids) size_tiles(ctx, g);
+    free_device(ctx);
+    return VDWNL_OK;
+}
+
+int vdwnl_get_tiling(const vdwnl_ctx *ctx, int32_t max_groups, int64_t *lds_budget) {
+    if (!ctx || (max_groups > 0 && !lds_budget)) return VDWNL_E_ARG;
+    for (int i = 0; i < std::min<int>(max_groups, TG_COUNT); ++i) lds_budget[i] = (int64_t)ctx->pref[i];
+    return TG_COUNT;
 }
 
 int vdwnl_set_timing(vdwnl_ctx *ctx, int32_t on) {

@@ -85,7 +85,8 @@ enum KernelKind {
     KIND_COUNT
 };
 
-// Arguments of one pass launch.
+// Arguments of one pass launch.  ntiles == 0: no launch, only raise the
+// kernel's dynamic LDS limit to lds (done when the launches are planned).
 struct LaunchArgs {
     const InstDev *insts;
     const Tile *tiles;

@@ -17,6 +17,7 @@
 // per-k kernel matrix between its forward and inverse FFTs.
 #include "common.hpp"
 #include "fft_fast.hpp"
+#include "tile_io.hpp"
 
 namespace vdwnl {
 
@@ -62,7 +63,7 @@ template <typename T, bool DERIV>
 struct LocalQ {
     T q0, Q, dqdn, dqds;
 
-    __device__ __forceinline__ void eval(T n, T sigma, const Consts &c) {
+    __device__ __forceinline__ void eval(T n, T sigma, double qc, int mc) {
         const T pi = (T)3.14159265358979323846;
         const T A = (T)0.031091, a1 = (T)0.21370;
         const T b1 = (T)7.5957, b2 = (T)3.5876, b3 = (T)1.6382, b4 = (T)0.49294;
@@ -83,22 +84,22 @@ struct LocalQ {
             dqds = zg / (kf * n * n);
         }
         // h(x, x_c) = x_c (1 - exp(-sum_{m<=m_c} (x/x_c)^m / m)), dh/dx = exp(-S) sum_{m<m_c} (x/x_c)^m
-        const double y = (double)qraw / c.qc;
+        const double y = (double)qraw / qc;
         if (y > 64.0) {
-            q0 = (T)c.qc;
+            q0 = (T)qc;
             Q = (T)0;
             return;
         }
         double S = 0.0, D = 0.0;
-        for (int m = c.mc; m >= 1; --m) S = S * y + 1.0 / (double)m;
+        for (int m = mc; m >= 1; --m) S = S * y + 1.0 / (double)m;
         S *= y;
-        for (int m = c.mc - 1; m >= 0; --m) D = D * y + 1.0;
+        for (int m = mc - 1; m >= 0; --m) D = D * y + 1.0;
         if (S > 700.0) {
-            q0 = (T)c.qc;
+            q0 = (T)qc;
             Q = (T)0;
         } else {
             const double e = exp(-S);
-            q0 = (T)(c.qc * (1.0 - e));
+            q0 = (T)(qc * (1.0 - e));
             Q = (T)(e * D);
         }
     }
@@ -112,24 +113,20 @@ struct SplinePos {
     T a, b, h, dq;   // dq = q0 - q_1 below the mesh (linear continuation), else 0
 
     __device__ __forceinline__ void locate(T q0, const T *qm, int nq) {
-        if (q0 < qm[0]) {
-            j = 0;
-            dq = q0 - qm[0];
-            h = qm[1] - qm[0];
-            a = (T)1;
-            b = (T)0;
-            return;
-        }
+        // one path for every case (the struct then stays in registers)
+        const bool below = q0 < qm[0];
         int lo = 0, hi = nq - 1;
         while (hi - lo > 1) {
             const int mid = (lo + hi) >> 1;
             if (qm[mid] <= q0) lo = mid; else hi = mid;
         }
         j = lo;
-        h = qm[j + 1] - qm[j];
-        a = (qm[j + 1] - q0) / h;
+        const T ql = qm[lo], qh = qm[lo + 1];
+        h = qh - ql;
+        const T aa = (qh - q0) / h;
+        a = below ? (T)1 : aa;
         b = (T)1 - a;
-        dq = (T)0;
+        dq = below ? q0 - ql : (T)0;
     }
     // p_a and dp_a/dq
     __device__ __forceinline__ void basis(int al, const T *M, T &p, T &dp) const {
@@ -157,15 +154,18 @@ __global__ void __launch_bounds__(kThreads) k_x_nfwd(const InstDev *insts, const
     extern __shared__ __align__(16) unsigned char smem[];
     const Tile t = tiles[blockIdx.x];
     const InstDev &I = insts[t.inst];
-    const int N3 = I.n3, N3h = I.n3h, row0 = t.a, B = t.b, np = B / 2, ls = N3 + 1;
+    const int N3 = axis_len<LC>(I.n3), N3h = N3 / 2 + 1, row0 = t.a, B = t.b, np = B / 2, ls = N3 + 1;
     double2 *tw = reinterpret_cast<double2 *>(smem);
     double2 *buf = tw + N3;
-    load_twiddles<double>(tw, I.p3, reinterpret_cast<const double2 *>(twdv));
     const T *n = reinterpret_cast<const T *>(I.n) + (size_t)row0 * N3;
-    for (int idx = threadIdx.x; idx < np * N3; idx += kThreads) {
+    batched<4>(np * N3, [&](int idx) {
         const int pr = idx / N3, k = idx - pr * N3;
-        buf[pr * ls + k] = mk<double>((double)n[(2 * pr) * N3 + k], (double)n[(2 * pr + 1) * N3 + k]);
-    }
+        return mk<double>((double)gld(n)[(2 * pr) * N3 + k], (double)gld(n)[(2 * pr + 1) * N3 + k]);
+    }, [&](int idx, double2 z) {
+        const int pr = idx / N3, k = idx - pr * N3;
+        buf[pr * ls + k] = z;
+    });
+    load_twiddles<double>(tw, I.p3, reinterpret_cast<const double2 *>(twdv));
     __syncthreads();
     fft_lc<double, -1, LC>(buf, I.p3, np, 1, ls, tw);
     double2 *out = reinterpret_cast<double2 *>(I.spec1) + (size_t)row0 * N3h;
@@ -188,7 +188,7 @@ __global__ void __launch_bounds__(kThreads) k_x_theta(const InstDev *insts, cons
     extern __shared__ __align__(16) unsigned char smem[];
     const Tile t = tiles[blockIdx.x];
     const InstDev &I = insts[t.inst];
-    const int N3 = I.n3, N3h = I.n3h, row0 = t.a, B = t.b, ls = N3 + 1;
+    const int N3 = axis_len<LC>(I.n3), N3h = N3 / 2 + 1, row0 = t.a, B = t.b, ls = N3 + 1;
     const size_t N = (size_t)I.n1 * I.n2 * I.n3;
     double2 *twd = reinterpret_cast<double2 *>(smem);       // FP64 twiddles
     double2 *r1 = twd + N3;                                   // 2 lines per row: d1 + i d2, d3
@@ -196,41 +196,47 @@ __global__ void __launch_bounds__(kThreads) k_x_theta(const InstDev *insts, cons
     C2<T> *tw = r2 + kNQ / 2 * B * ls;                       // twiddles in T
     T *qm = reinterpret_cast<T *>(tw + N3);
     T *Mm = qm + kNQ;
+    // density of this thread's first point, fetched first (used after the FFT)
+    const int npt = B * N3;
+    const gptr<const T> nin = gld(reinterpret_cast<const T *>(I.n) + (size_t)row0 * N3);
+    const T n_first = threadIdx.x < npt ? nin[threadIdx.x] : (T)0;
+    const double2 *s3 = reinterpret_cast<const double2 *>(I.spec3) + (size_t)row0 * N3h * 3;
+    struct Three { double2 a, b, c; };
+    batched<2>(B * N3, [&](int idx) {
+        const int rb = idx / N3, k = idx - rb * N3;
+        const int kk = k >= N3h ? N3 - k : k;
+        const double2 *src = s3 + ((size_t)rb * N3h + kk) * 3;
+        const gptr<const double2> g = gld(src);
+        return Three{g[0], g[1], g[2]};
+    }, [&](int idx, Three y) {
+        const int rb = idx / N3, k = idx - rb * N3;
+        if (k >= N3h) { y.a = cconj(y.a); y.b = cconj(y.b); y.c = cconj(y.c); }
+        r1[(2 * rb) * ls + k] = mk<double>(y.a.x - y.b.y, y.a.y + y.b.x);
+        r1[(2 * rb + 1) * ls + k] = y.c;
+    });
     load_consts<T>(cst, qm, Mm);
     load_twiddles<double>(twd, I.p3, reinterpret_cast<const double2 *>(twdv));
     load_twiddles<T>(tw, I.p3, reinterpret_cast<const C2<T> *>(twv));
-
-    const double2 *s3 = reinterpret_cast<const double2 *>(I.spec3) + (size_t)row0 * N3h * 3;
-    for (int idx = threadIdx.x; idx < B * N3; idx += kThreads) {
-        const int rb = idx / N3, k = idx - rb * N3;
-        const bool cj = k >= N3h;
-        const int kk = cj ? N3 - k : k;
-        const double2 *src = s3 + ((size_t)rb * N3h + kk) * 3;
-        double2 y0 = src[0], y1 = src[1], y2 = src[2];
-        if (cj) { y0 = cconj(y0); y1 = cconj(y1); y2 = cconj(y2); }
-        r1[(2 * rb) * ls + k] = mk<double>(y0.x - y1.y, y0.y + y1.x);
-        r1[(2 * rb + 1) * ls + k] = y2;
-    }
     __syncthreads();
     fft_lc<double, 1, LC>(r1, I.p3, 2 * B, 1, ls, twd);
 
-    const Consts c = *cst;
-    const T *nin = reinterpret_cast<const T *>(I.n);
-    T *grad = reinterpret_cast<T *>(I.grad);
+    const double c_qc = cst->qc, c_cs = cst->cs, c_nmin = cst->nmin;
+    const int c_mc = cst->mc;
+    const gptr<T> grad = gst(reinterpret_cast<T *>(I.grad));
     double de = 0.0;
-    for (int idx = threadIdx.x; idx < B * N3; idx += kThreads) {
+    for (int idx = threadIdx.x; idx < npt; idx += kThreads) {
         const int rb = idx / N3, k = idx - rb * N3;
         const size_t p = (size_t)(row0 + rb) * N3 + k;
-        const T nv = nin[p];
+        const T nv = idx == (int)threadIdx.x ? n_first : nin[idx];
         const double2 g01d = r1[(2 * rb) * ls + k], g2d = r1[(2 * rb + 1) * ls + k];
         const C2<T> g01 = mk<T>((T)g01d.x, (T)g01d.y), g2 = mk<T>((T)g2d.x, (T)0);
         grad[p] = g01.x;
         grad[N + p] = g01.y;
         grad[2 * N + p] = g2.x;
         T *th = reinterpret_cast<T *>(r2 + (size_t)(kNQ / 2 * rb) * ls);   // pair line m at th + 2 m ls
-        if (nv >= (T)c.nmin) {
+        if (nv >= (T)c_nmin) {
             LocalQ<T, false> lq;
-            lq.eval(nv, g01.x * g01.x + g01.y * g01.y + g2.x * g2.x, c);
+            lq.eval(nv, g01.x * g01.x + g01.y * g01.y + g2.x * g2.x, c_qc, c_mc);
             SplinePos<T> sp;
             sp.locate(lq.q0, qm, kNQ);
 #pragma unroll 4
@@ -240,7 +246,7 @@ __global__ void __launch_bounds__(kThreads) k_x_theta(const InstDev *insts, cons
                 th[2 * ((al >> 1) * ls + k) + (al & 1)] = nv * pa;
             }
             const T q3 = lq.q0 * lq.q0 * lq.q0;
-            de += (double)((T)c.cs * nv * nv / q3);
+            de += (double)((T)c_cs * nv * nv / q3);
         } else {
 #pragma unroll 4
             for (int al = 0; al < kNQ; ++al) th[2 * ((al >> 1) * ls + k) + (al & 1)] = (T)0;
@@ -273,7 +279,7 @@ __global__ void __launch_bounds__(kThreads) k_x_assemble(const InstDev *insts, c
     extern __shared__ __align__(16) unsigned char smem[];
     const Tile t = tiles[blockIdx.x];
     const InstDev &I = insts[t.inst];
-    const int N3 = I.n3, N3h = I.n3h, row0 = t.a, B = t.b, ls = N3 + 1;
+    const int N3 = axis_len<LC>(I.n3), N3h = N3 / 2 + 1, row0 = t.a, B = t.b, ls = N3 + 1;
     const size_t N = (size_t)I.n1 * I.n2 * I.n3;
     double2 *twd = reinterpret_cast<double2 *>(smem);       // FP64 twiddles
     double2 *r1 = twd + N3;                                   // 2 FP64 lines per row: w1 + i w2, w3
@@ -281,37 +287,50 @@ __global__ void __launch_bounds__(kThreads) k_x_assemble(const InstDev *insts, c
     C2<T> *tw = r2 + kNQ / 2 * B * ls;                       // twiddles in T
     T *qm = reinterpret_cast<T *>(tw + N3);
     T *Mm = qm + kNQ;
+    // n and grad n of this thread's first point, fetched first (used after the FFT)
+    const int npt = B * N3;
+    const size_t p0 = (size_t)row0 * N3;
+    const gptr<const T> nin = gld(reinterpret_cast<const T *>(I.n) + p0);
+    const gptr<const T> grad = gld(reinterpret_cast<const T *>(I.grad) + p0);
+    T n_f = (T)0, gx_f = (T)0, gy_f = (T)0, gz_f = (T)0;
+    if (threadIdx.x < npt) {
+        n_f = nin[threadIdx.x];
+        gx_f = grad[threadIdx.x];
+        gy_f = grad[N + threadIdx.x];
+        gz_f = grad[2 * N + threadIdx.x];
+    }
+    const C2<T> *sp = reinterpret_cast<const C2<T> *>(I.spec) + (size_t)row0 * N3h * kNQ;
+    struct Two { C2<T> a, b; };
+    batched<4>(B * N3 * (kNQ / 2), [&](int idx) {
+        const int m = idx % (kNQ / 2), rest = idx / (kNQ / 2);
+        const int k = rest % N3, rb = rest / N3;
+        const int kk = k >= N3h ? N3 - k : k;
+        const gptr<const C2<T>> g = gld(sp + ((size_t)rb * N3h + kk) * kNQ + 2 * m);
+        return Two{g[0], g[1]};
+    }, [&](int idx, Two y) {
+        const int m = idx % (kNQ / 2), rest = idx / (kNQ / 2);
+        const int k = rest % N3, rb = rest / N3;
+        if (k >= N3h) { y.a = cconj(y.a); y.b = cconj(y.b); }
+        r2[(kNQ / 2 * rb + m) * ls + k] = mk<T>(y.a.x - y.b.y, y.a.y + y.b.x);
+    });
     load_consts<T>(cst, qm, Mm);
     load_twiddles<double>(twd, I.p3, reinterpret_cast<const double2 *>(twdv));
     load_twiddles<T>(tw, I.p3, reinterpret_cast<const C2<T> *>(twv));
-
-    const C2<T> *sp = reinterpret_cast<const C2<T> *>(I.spec) + (size_t)row0 * N3h * kNQ;
-    for (int idx = threadIdx.x; idx < B * N3 * (kNQ / 2); idx += kThreads) {
-        const int m = idx % (kNQ / 2), rest = idx / (kNQ / 2);
-        const int k = rest % N3, rb = rest / N3;
-        const bool cj = k >= N3h;
-        const int kk = cj ? N3 - k : k;
-        const C2<T> *src = sp + ((size_t)rb * N3h + kk) * kNQ + 2 * m;
-        C2<T> ya = src[0], yb = src[1];
-        if (cj) { ya = cconj(ya); yb = cconj(yb); }
-        r2[(kNQ / 2 * rb + m) * ls + k] = mk<T>(ya.x - yb.y, ya.y + yb.x);
-    }
     __syncthreads();
     fft_lc<T, 1, LC>(r2, I.p3, kNQ / 2 * B, 1, ls, tw);
 
-    const Consts c = *cst;
-    const T *nin = reinterpret_cast<const T *>(I.n);
-    const T *grad = reinterpret_cast<const T *>(I.grad);
-    T *vloc = reinterpret_cast<T *>(I.vloc);
-    for (int idx = threadIdx.x; idx < B * N3; idx += kThreads) {
+    const double c_qc = cst->qc, c_cs = cst->cs, c_nmin = cst->nmin;
+    const int c_mc = cst->mc;
+    const gptr<T> vloc = gst(reinterpret_cast<T *>(I.vloc) + p0);
+    for (int idx = threadIdx.x; idx < npt; idx += kThreads) {
         const int rb = idx / N3, k = idx - rb * N3;
-        const size_t p = (size_t)(row0 + rb) * N3 + k;
-        const T nv = nin[p];
-        const T gx = grad[p], gy = grad[N + p], gz = grad[2 * N + p];
+        const bool first = idx == (int)threadIdx.x;
+        const T nv = first ? n_f : nin[idx];
+        const T gx = first ? gx_f : grad[idx], gy = first ? gy_f : grad[N + idx], gz = first ? gz_f : grad[2 * N + idx];
         T vl = (T)0, gs = (T)0;
-        if (nv >= (T)c.nmin) {
+        if (nv >= (T)c_nmin) {
             LocalQ<T, true> lq;
-            lq.eval(nv, gx * gx + gy * gy + gz * gz, c);
+            lq.eval(nv, gx * gx + gy * gy + gz * gz, c_qc, c_mc);
             SplinePos<T> spos;
             spos.locate(lq.q0, qm, kNQ);
             const T *u = reinterpret_cast<const T *>(r2 + (size_t)(kNQ / 2 * rb) * ls);
@@ -326,12 +345,12 @@ __global__ void __launch_bounds__(kThreads) k_x_assemble(const InstDev *insts, c
                 sdu += ua * dpa;
             }
             // dtheta_a/dn = p_a + n p'_a Q dq/dn ; dtheta_a/dgrad n = 2 n p'_a Q dq/dsigma grad n
-            const T q0 = lq.q0, cs = (T)c.cs;
+            const T q0 = lq.q0, cs = (T)c_cs;
             const T iq3 = (T)1 / (q0 * q0 * q0), iq4 = iq3 / q0;
             vl = su + cn * sdu + (T)2 * cs * nv * iq3 - (T)3 * cs * nv * nv * iq4 * lq.Q * lq.dqdn;
             gs = (T)2 * nv * lq.Q * lq.dqds * sdu - (T)6 * cs * nv * nv * iq4 * lq.Q * lq.dqds;
         }
-        vloc[p] = vl;
+        vloc[idx] = vl;
         const double gsd = (double)gs;
         r1[(2 * rb) * ls + k] = mk<double>(gsd * (double)gx, gsd * (double)gy);
         r1[(2 * rb + 1) * ls + k] = mk<double>(gsd * (double)gz, 0.0);
@@ -359,27 +378,32 @@ __global__ void __launch_bounds__(kThreads) k_x_final(const InstDev *insts, cons
     extern __shared__ __align__(16) unsigned char smem[];
     const Tile t = tiles[blockIdx.x];
     const InstDev &I = insts[t.inst];
-    const int N3 = I.n3, N3h = I.n3h, row0 = t.a, B = t.b, np = B / 2, ls = N3 + 1;
+    const int N3 = axis_len<LC>(I.n3), N3h = N3 / 2 + 1, row0 = t.a, B = t.b, np = B / 2, ls = N3 + 1;
     double2 *tw = reinterpret_cast<double2 *>(smem);
     double2 *buf = tw + N3;
-    load_twiddles<double>(tw, I.p3, reinterpret_cast<const double2 *>(twdv));
     const double2 *s1 = reinterpret_cast<const double2 *>(I.spec1) + (size_t)row0 * N3h;
-    for (int idx = threadIdx.x; idx < np * N3; idx += kThreads) {
+    const int npt = B * N3;
+    const gptr<const T> vloc = gld(reinterpret_cast<const T *>(I.vloc) + (size_t)row0 * N3);
+    const T vl_first = threadIdx.x < npt ? vloc[threadIdx.x] : (T)0;
+    struct Two { double2 a, b; };
+    batched<4>(np * N3, [&](int idx) {
         const int pr = idx / N3, k = idx - pr * N3;
-        const bool cj = k >= N3h;
-        const int kk = cj ? N3 - k : k;
-        double2 ya = s1[(2 * pr) * N3h + kk], yb = s1[(2 * pr + 1) * N3h + kk];
-        if (cj) { ya = cconj(ya); yb = cconj(yb); }
-        buf[pr * ls + k] = mk<double>(ya.x - yb.y, ya.y + yb.x);
-    }
+        const int kk = k >= N3h ? N3 - k : k;
+        return Two{gld(s1)[(2 * pr) * N3h + kk], gld(s1)[(2 * pr + 1) * N3h + kk]};
+    }, [&](int idx, Two y) {
+        const int pr = idx / N3, k = idx - pr * N3;
+        if (k >= N3h) { y.a = cconj(y.a); y.b = cconj(y.b); }
+        buf[pr * ls + k] = mk<double>(y.a.x - y.b.y, y.a.y + y.b.x);
+    });
+    load_twiddles<double>(tw, I.p3, reinterpret_cast<const double2 *>(twdv));
     __syncthreads();
     fft_lc<double, 1, LC>(buf, I.p3, np, 1, ls, tw);
-    const T *vloc = reinterpret_cast<const T *>(I.vloc) + (size_t)row0 * N3;
-    T *v = reinterpret_cast<T *>(I.v) + (size_t)row0 * N3;
-    for (int idx = threadIdx.x; idx < B * N3; idx += kThreads) {
+    const gptr<T> v = gst(reinterpret_cast<T *>(I.v) + (size_t)row0 * N3);
+    for (int idx = threadIdx.x; idx < npt; idx += kThreads) {
         const int rb = idx / N3, k = idx - rb * N3;
         const double2 z = buf[(rb >> 1) * ls + k];
-        v[idx] = (T)((double)vloc[idx] - ((rb & 1) ? z.y : z.x));
+        const T vl = idx == (int)threadIdx.x ? vl_first : vloc[idx];
+        v[idx] = (T)((double)vl - ((rb & 1) ? z.y : z.x));
     }
 }
 
@@ -392,23 +416,17 @@ __global__ void __launch_bounds__(kThreads) k_y(const InstDev *insts, const Tile
     extern __shared__ __align__(16) unsigned char smem[];
     const Tile t = tiles[blockIdx.x];
     const InstDev &I = insts[t.inst];
-    const int N2 = I.n2, W = t.c, es = W | 1;   // odd element stride: no LDS bank conflicts
+    const int N2 = axis_len<LC>(I.n2), W = t.c, es = W | 1;   // odd element stride: no LDS bank conflicts
     C2<T> *tw = reinterpret_cast<C2<T> *>(smem);
     C2<T> *buf = tw + N2;
-    load_twiddles<T>(tw, I.p2, reinterpret_cast<const C2<T> *>(twv));
     const size_t rowlen = (size_t)I.n3h * V;
     void *base = which == 0 ? I.spec : (which == 1 ? I.spec3 : I.spec1);
     C2<T> *g = reinterpret_cast<C2<T> *>(base) + (size_t)t.a * N2 * rowlen + t.b;
-    for (int idx = threadIdx.x; idx < N2 * W; idx += kThreads) {
-        const int l = idx / W, w = idx - l * W;
-        buf[l * es + w] = g[l * rowlen + w];
-    }
+    crows_in(buf, es, g, rowlen, N2, W);
+    load_twiddles<T>(tw, I.p2, reinterpret_cast<const C2<T> *>(twv));
     __syncthreads();
     fft_lc<T, S, LC>(buf, I.p2, W, es, 1, tw);
-    for (int idx = threadIdx.x; idx < N2 * W; idx += kThreads) {
-        const int l = idx / W, w = idx - l * W;
-        g[l * rowlen + w] = buf[l * es + w];
-    }
+    crows_out(g, rowlen, buf, es, N2, W);
 }
 
 // ---------------------------------------------------------------- axis-1 passes
@@ -420,18 +438,15 @@ __global__ void __launch_bounds__(kThreads) k_z_grad(const InstDev *insts, const
     extern __shared__ __align__(16) unsigned char smem[];
     const Tile t = tiles[blockIdx.x];
     const InstDev &I = insts[t.inst];
-    const int N1 = I.n1, N2 = I.n2, N3 = I.n3, N3h = I.n3h, k2 = t.a, k30 = t.b, K3 = t.c;
+    const int N1 = axis_len<LC>(I.n1), N2 = I.n2, N3 = I.n3, N3h = I.n3h, k2 = t.a, k30 = t.b, K3 = t.c;
     C2<T> *twall = reinterpret_cast<C2<T> *>(smem);
     const int ei = K3 | 1, eo = (3 * K3) | 1;               // odd element strides
     C2<T> *bin = twall + N1;
     C2<T> *bout = bin + N1 * ei;
-    load_twiddles<T>(twall, I.p1, reinterpret_cast<const C2<T> *>(twv));
     const C2<T> *gin = reinterpret_cast<const C2<T> *>(I.spec1) + (size_t)k2 * N3h + k30;
     const size_t sin_ = (size_t)N2 * N3h;
-    for (int idx = threadIdx.x; idx < N1 * K3; idx += kThreads) {
-        const int l = idx / K3, w = idx - l * K3;
-        bin[l * ei + w] = gin[l * sin_ + w];
-    }
+    crows_in(bin, ei, gin, sin_, N1, K3);
+    load_twiddles<T>(twall, I.p1, reinterpret_cast<const C2<T> *>(twv));
     __syncthreads();
     fft_lc<T, -1, LC>(bin, I.p1, K3, ei, 1, twall);
     const T G2 = (T)(I.g2 * freq_nz(k2, N2));
@@ -448,10 +463,7 @@ __global__ void __launch_bounds__(kThreads) k_z_grad(const InstDev *insts, const
     __syncthreads();
     fft_lc<T, 1, LC>(bout, I.p1, 3 * K3, eo, 1, twall);
     C2<T> *gout = reinterpret_cast<C2<T> *>(I.spec3) + ((size_t)k2 * N3h + k30) * 3;
-    for (int idx = threadIdx.x; idx < N1 * 3 * K3; idx += kThreads) {
-        const int l = idx / (3 * K3), w = idx - l * 3 * K3;
-        gout[l * sin_ * 3 + w] = bout[l * eo + w];
-    }
+    crows_out(gout, sin_ * 3, bout, eo, N1, 3 * K3);
 }
 
 // sum_c i G_c w_c / N.  tile: a = k2, b = first k3, c = count
@@ -461,18 +473,15 @@ __global__ void __launch_bounds__(kThreads) k_z_div(const InstDev *insts, const 
     extern __shared__ __align__(16) unsigned char smem[];
     const Tile t = tiles[blockIdx.x];
     const InstDev &I = insts[t.inst];
-    const int N1 = I.n1, N2 = I.n2, N3 = I.n3, N3h = I.n3h, k2 = t.a, k30 = t.b, K3 = t.c;
+    const int N1 = axis_len<LC>(I.n1), N2 = I.n2, N3 = I.n3, N3h = I.n3h, k2 = t.a, k30 = t.b, K3 = t.c;
     C2<T> *twall = reinterpret_cast<C2<T> *>(smem);
     const int ei = (3 * K3) | 1, eo = K3 | 1;               // odd element strides
     C2<T> *bin = twall + N1;
     C2<T> *bout = bin + N1 * ei;
-    load_twiddles<T>(twall, I.p1, reinterpret_cast<const C2<T> *>(twv));
     const size_t sin_ = (size_t)N2 * N3h;
     const C2<T> *gin = reinterpret_cast<const C2<T> *>(I.spec3) + ((size_t)k2 * N3h + k30) * 3;
-    for (int idx = threadIdx.x; idx < N1 * 3 * K3; idx += kThreads) {
-        const int l = idx / (3 * K3), w = idx - l * 3 * K3;
-        bin[l * ei + w] = gin[l * sin_ * 3 + w];
-    }
+    crows_in(bin, ei, gin, sin_ * 3, N1, 3 * K3);
+    load_twiddles<T>(twall, I.p1, reinterpret_cast<const C2<T> *>(twv));
     __syncthreads();
     fft_lc<T, -1, LC>(bin, I.p1, 3 * K3, ei, 1, twall);
     const T G2 = (T)(I.g2 * freq_nz(k2, N2));
@@ -488,10 +497,7 @@ __global__ void __launch_bounds__(kThreads) k_z_div(const InstDev *insts, const 
     __syncthreads();
     fft_lc<T, 1, LC>(bout, I.p1, K3, eo, 1, twall);
     C2<T> *gout = reinterpret_cast<C2<T> *>(I.spec1) + (size_t)k2 * N3h + k30;
-    for (int idx = threadIdx.x; idx < N1 * K3; idx += kThreads) {
-        const int l = idx / K3, w = idx - l * K3;
-        gout[l * sin_ + w] = bout[l * eo + w];
-    }
+    crows_out(gout, sin_, bout, eo, N1, K3);
 }
 
 // Forward axis-1 FFT of the 20 theta spectra, u_a(G) = sum_b phi_ab(|G|) c_b(G)
@@ -507,48 +513,94 @@ __global__ void __launch_bounds__(kThreads) k_z_main(const InstDev *insts, const
                                                      const void *twv) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int kGroups = (kThreads / 64) * (64 / kNQ);   // lane groups per workgroup
+    constexpr int kChunks = kTabStride * (int)sizeof(T) / 16; // 16-byte chunks of one shell row
+    constexpr int kCpl = (kChunks + kNQ - 1) / kNQ;           // chunks per lane of a group
     const Tile t = tiles[blockIdx.x];
     const InstDev &I = insts[t.inst];
-    const int N1 = I.n1, N2 = I.n2, N3 = I.n3, N3h = I.n3h, k2 = t.a, k30 = t.b, K3 = t.c;
+    const int N1 = axis_len<LC>(I.n1), N2 = I.n2, N3 = I.n3, N3h = I.n3h, k2 = t.a, k30 = t.b, K3 = t.c;
     const int W = K3 * kNQ, es = W | 1;                      // odd element stride
     C2<T> *twall = reinterpret_cast<C2<T> *>(smem);
     C2<T> *buf = twall + N1;
     const size_t stage_off = ((size_t)(N1 + N1 * es) * sizeof(C2<T>) + 15) & ~(size_t)15;
     T *stage = reinterpret_cast<T *>(smem + stage_off);       // [kGroups][kTabStride], 16-byte aligned
-    load_twiddles<T>(twall, I.p1, reinterpret_cast<const C2<T> *>(twv));
     const size_t stride = (size_t)N2 * N3h * kNQ;
     C2<T> *g = reinterpret_cast<C2<T> *>(I.spec) + ((size_t)k2 * N3h + k30) * kNQ;
-    for (int idx = threadIdx.x; idx < N1 * W; idx += kThreads) {
-        const int l = idx / W, w = idx - l * W;
-        buf[l * es + w] = g[l * stride + w];
-    }
-    __syncthreads();
-    fft_lc<T, -1, LC>(buf, I.p1, W, es, 1, twall);
+    crows_in(buf, es, g, stride, N1, W);
+    load_twiddles<T>(twall, I.p1, reinterpret_cast<const C2<T> *>(twv));
 
+    // Contraction bookkeeping.  Group gid takes items gid, gid + kGroups, ...;
+    // an item is (|m1|, k3 of the tile).  The shell row of the first item is
+    // fetched before the forward FFT so its latency hides behind it.
     const T *tab = reinterpret_cast<const T *>(I.shelltab);
     const int m2 = freq_abs(k2, N2);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int grp = lane / kNQ, al = lane - grp * kNQ;
     const bool lane_on = grp < 64 / kNQ;
     const int gid = wave * (64 / kNQ) + grp;
-    T *st = stage + (size_t)(lane_on ? gid : 0) * kTabStride;
     const int nitems = (N1 / 2 + 1) * K3;
+    const int *smap = I.shellmap + (size_t)m2 * N3h + k30;
+    const size_t smap_m1 = (size_t)I.h2 * N3h;
+    auto shell_of = [&](int item) {
+        const int m1 = item / K3;
+        return gld(smap)[m1 * smap_m1 + (item - m1 * K3)];
+    };
+    // the next shell row: chunks al, al + 20, ... of the row (3 per lane in FP32, 6 in FP64)
+    static_assert(kCpl == 3 || kCpl == 6, "shell row chunking");
+    const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    float4 r0 = z4, r1 = z4, r2 = z4, r3 = z4, r4 = z4, r5 = z4;
+    const bool last_on = al + (kCpl - 1) * kNQ < kChunks;
+#define VDWNL_FETCH_ROW(s)                                                                          \
+    do {                                                                                            \
+        const gptr<const float4> src_ = gld(reinterpret_cast<const float4 *>(tab + (size_t)(s) * kTabStride)); \
+        r0 = src_[al];                                                                              \
+        r1 = src_[al + kNQ];                                                                        \
+        if constexpr (kCpl == 3) {                                                                  \
+            if (last_on) r2 = src_[al + 2 * kNQ];                                                   \
+        } else {                                                                                    \
+            r2 = src_[al + 2 * kNQ];                                                                \
+            r3 = src_[al + 3 * kNQ];                                                                \
+            r4 = src_[al + 4 * kNQ];                                                                \
+            if (last_on) r5 = src_[al + 5 * kNQ];                                                   \
+        }                                                                                           \
+    } while (0)
+    int s_next = 0;
+    if (lane_on && gid < nitems) {
+        VDWNL_FETCH_ROW(shell_of(gid));
+        if (gid + kGroups < nitems) s_next = shell_of(gid + kGroups);
+    }
+    __syncthreads();
+    fft_lc<T, -1, LC>(buf, I.p1, W, es, 1, twall);
+
+    T *st = stage + (size_t)(lane_on ? gid : 0) * kTabStride;
     const T inv_n = (T)I.inv_n;
     double e = 0.0;
-    // Each group works through its own items; a group's lanes share one wave,
-    // so staging, reads of theta and writes of u need wave-level ordering only.
+    // A group's lanes share one wave, so staging, reads of theta and writes
+    // of u need wave-level ordering only.
     for (int item = gid; lane_on && item < nitems; item += kGroups) {
+        {
+            float4 *dst = reinterpret_cast<float4 *>(st);
+            dst[al] = r0;
+            dst[al + kNQ] = r1;
+            if constexpr (kCpl == 3) {
+                if (last_on) dst[al + 2 * kNQ] = r2;
+            } else {
+                dst[al + 2 * kNQ] = r2;
+                dst[al + 3 * kNQ] = r3;
+                dst[al + 4 * kNQ] = r4;
+                if (last_on) dst[al + 5 * kNQ] = r5;
+            }
+        }
+        wave_sync();
+        // prefetch: the next item's row (its shell is known), the shell after it
+        if (item + kGroups < nitems) {
+            VDWNL_FETCH_ROW(s_next);
+            if (item + 2 * kGroups < nitems) s_next = shell_of(item + 2 * kGroups);
+        }
         const int m1 = item / K3, w = item - m1 * K3;
         const int k3 = k30 + w;
         const int l = m1;
         int lp = N1 - m1;
         if (m1 == 0 || lp == m1) lp = -1;     // k1 = 0 and the Nyquist plane stand alone
-        const int s = I.shellmap[((size_t)m1 * I.h2 + m2) * N3h + k3];
-        const float4 *src = reinterpret_cast<const float4 *>(tab + (size_t)s * kTabStride);
-        float4 *dst = reinterpret_cast<float4 *>(st);
-        constexpr int nv = kTabStride * (int)sizeof(T) / 16;
-        for (int v = al; v < nv; v += kNQ) dst[v] = src[v];
-        wave_sync();
         C2<T> u1 = mk<T>((T)0, (T)0), u2 = u1;
         C2<T> *x1 = buf + l * es + w * kNQ;
         C2<T> *x2 = buf + (lp >= 0 ? lp : l) * es + w * kNQ;
@@ -575,12 +627,10 @@ __global__ void __launch_bounds__(kThreads) k_z_main(const InstDev *insts, const
     }
     __syncthreads();
     fft_lc<T, 1, LC>(buf, I.p1, W, es, 1, twall);
-    for (int idx = threadIdx.x; idx < N1 * W; idx += kThreads) {
-        const int l = idx / W, w = idx - l * W;
-        g[l * stride + w] = buf[l * es + w];
-    }
+    crows_out(g, stride, buf, es, N1, W);
     const double sum = block_sum(e);
     if (threadIdx.x == 0) I.part_ek[t.slot] = sum;
+#undef VDWNL_FETCH_ROW
 }
 
 // E_k = (Omega/2) sum of the axis-1 partials; Delta E = dOmega sum of the
@@ -605,14 +655,16 @@ template <typename K>
 static void allow_lds(K kernel, size_t bytes) {
     if (bytes > 65536) (void)hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
+// (launch_lc with ntiles == 0 only raises the kernel's LDS limit: done once
+// when the launches are planned, never while a stream is being captured)
 
 template <typename T, int LC>
 static hipError_t launch_lc(int kind, const LaunchArgs &a) {
     dim3 grid(a.ntiles), block(kThreads);
-#define VDWNL_LAUNCH(kern, ...)                                                              \
-    do {                                                                                     \
-        allow_lds(kern, a.lds);                                                              \
-        hipLaunchKernelGGL(kern, grid, block, a.lds, a.stream, a.insts, a.tiles, __VA_ARGS__); \
+#define VDWNL_LAUNCH(kern, ...)                                                                  \
+    do {                                                                                         \
+        if (a.ntiles == 0) allow_lds(kern, a.lds);                                               \
+        else hipLaunchKernelGGL(kern, grid, block, a.lds, a.stream, a.insts, a.tiles, __VA_ARGS__); \
     } while (0)
     switch (kind) {
         case KX_NFWD: VDWNL_LAUNCH((k_x_nfwd<T, LC>), a.twd); break;
@@ -636,7 +688,7 @@ static hipError_t launch_lc(int kind, const LaunchArgs &a) {
 
 template <typename T>
 static hipError_t launch_kind_t(int kind, int lc, const LaunchArgs &a) {
-    if (a.ntiles <= 0) return hipSuccess;
+    if (a.ntiles < 0) return hipErrorInvalidValue;
     switch (lc) {
         case 0: return launch_lc<T, 0>(kind, a);
         case 1: return launch_lc<T, 1>(kind, a);

@@ -8,10 +8,12 @@
 // 2. On each ray d2/d1 = q_b/q_a the soft form of Eq. (PhiSoft) replaces phi
 //    below D = |(d1, d2)| = d_s (value and slope matched at d_s).
 // 3. k_radial integrates 4 pi D^2 j0(kappa D) phi_s(D) exactly for the
-//    piecewise-linear interpolant of D phi_s(D) on the sample mesh (Filon),
-//    so the result is stable for every kappa on the table; beyond the last
-//    sample the r^-6 asymptote -C/(d1^2 d2^2 (d1^2 + d2^2)) continues on a
-//    geometric mesh.
+//    piecewise-quadratic interpolant of g(D) = D phi_s(D) on the sample mesh
+//    (Filon: the linear interpolant plus, per interval, g''/2 (D - a)(D - b)
+//    with g'' from the samples), so the result is stable for every kappa on
+//    the table and the O(h^2) bias of a linear interpolant is removed;
+//    beyond the last sample the r^-6 asymptote
+//    -C/(d1^2 d2^2 (d1^2 + d2^2)) continues on a geometric mesh.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -113,9 +115,10 @@ __global__ void __launch_bounds__(kTile) k_phi(const double *d1, const double *d
 }
 
 // One thread per (ray, kappa): Psi(kappa) / (4 pi) = Int D^2 j0(kappa D) phi_s dD
-// = (1/kappa) Int g(D) sin(kappa D) dD with g = D phi_s, g linear between the
-// samples D_n (ray r: samples [off[r], off[r+1]) of D and g).
-__global__ void k_radial(const double *D, const double *g, const int *off, const double *Qr,
+// = (1/kappa) Int g(D) sin(kappa D) dD with g = D phi_s, between the samples
+// D_n (ray r: samples [off[r], off[r+1]) of D and g) the linear interpolant
+// plus cv_n (D - D_n)(D - D_{n+1}), cv_n = g''/2 on the interval.
+__global__ void k_radial(const double *D, const double *g, const double *cv, const int *off, const double *Qr,
                          int nrays, int nk, double dk, double *out) {
     const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (long)nrays * nk) return;
@@ -127,7 +130,8 @@ __global__ void k_radial(const double *D, const double *g, const int *off, const
         // Int g D dD, exact for linear g on each interval
         for (int n = n0; n + 1 < n1; ++n) {
             const double a = D[n], b = D[n + 1], h = b - a, ga = g[n], sl = (g[n + 1] - g[n]) / h;
-            s += ga * (b * b - a * a) * 0.5 + sl * (h * h * (2.0 * b + a) / 6.0);
+            // Int (D - a)(D - b) D dD = -h^3 (a + b) / 12
+            s += ga * (b * b - a * a) * 0.5 + sl * (h * h * (2.0 * b + a) / 6.0) - cv[n] * h * h * h * (a + b) / 12.0;
         }
         out[idx] = s;
         return;
@@ -141,7 +145,10 @@ __global__ void k_radial(const double *D, const double *g, const int *off, const
         sincos(c, &sc, &cc);
         sincos(e, &se, &ce);
         const double sl = (g[n + 1] - g[n]) / h;
-        s += g[n] * (2.0 / kap) * sc * se + sl * (2.0 / (kap * kap)) * (cc * e * e * e * f3(e) + e * sc * se);
+        // Int (D - a)(D - b) sin(kD) dD = -4 (h/2)^3 f3(e) sin c
+        const double hh = 0.5 * h;
+        s += g[n] * (2.0 / kap) * sc * se + sl * (2.0 / (kap * kap)) * (cc * e * e * e * f3(e) + e * sc * se) -
+             cv[n] * 4.0 * hh * hh * hh * f3(e) * sc;
     }
     out[idx] = s / kap;
 }
@@ -159,7 +166,7 @@ struct HostMesh {
 
 // Composite 8-point Gauss-Legendre: geometric panels (ratio 1.5) from 1e-5 up
 // to 2 pi, panels of width pi/3 up to A, and a C-infinity cutoff
-// 1 - s(t), s(t) = E(t) / (E(t) + E(1-t)), E(t) = exp(-1/t), from 0.35 A to A.
+// 1 - s(t), s(t) = E(t) / (E(t) + E(1-t)), E(t) = exp(-1/t), from 0.3 A to A.
 HostMesh make_mesh(double A) {
     static const double xg[8] = {-0.9602898564975363, -0.7966664774136267, -0.5255324099163290, -0.1834346424956498,
                                  0.1834346424956498, 0.5255324099163290, 0.7966664774136267, 0.9602898564975363};
@@ -170,7 +177,7 @@ HostMesh make_mesh(double A) {
     edges.push_back(2.0 * kPi);
     while (edges.back() < A - 1e-12) edges.push_back(std::min(A, edges.back() + kPi / 3.0));
     HostMesh m;
-    const double a1 = 0.35 * A;
+    const double a1 = 0.3 * A;
     auto E = [](double t) { return t > 0.0 ? std::exp(-1.0 / t) : 0.0; };
     for (size_t p = 0; p + 1 < edges.size(); ++p) {
         const double lo = edges[p], hi = edges[p + 1];
@@ -190,14 +197,18 @@ HostMesh make_mesh(double A) {
     return m;
 }
 
-// upper limits of the a integration: the smallest with A >= 5 max(d1, d2)
-const double kBandA[] = {96.0, 192.0, 384.0, 768.0, 1536.0, 2304.0};
-constexpr int kNBand = 6;
+// upper limits A of the a integration: the smallest with A >= 16 max(d1, d2),
+// at least 192.  The truncation error of the tapered integral grows with d
+// (the integrand varies on the scale a ~ d) and falls with A: about 1e-8
+// relative at A = 16 d and A >= 192, while A = 96 leaves 1e-6..1e-5 at
+// d ~ 7..12.  Beyond d = 144 the last band (|phi| < 1e-8 there).
+const double kBandA[] = {192.0, 384.0, 768.0, 1536.0, 2304.0};
+constexpr int kNBand = 5;
 
 int band_of(double d1, double d2) {
     const double m = std::max(d1, d2);
     for (int b = 0; b < kNBand; ++b)
-        if (kBandA[b] >= 5.0 * m) return b;
+        if (kBandA[b] >= 16.0 * m) return b;
     return kNBand - 1;
 }
 
@@ -209,6 +220,58 @@ struct Ray {
     size_t slope_first;   // 4 extra points at d_s -+ h, -+ 2h
     double phi2 = 0, phi4 = 0;
 };
+
+// phi(P1[i], P2[i]) on the current device, one workgroup per point.
+int eval_phi(const std::vector<double> &P1, const std::vector<double> &P2, const std::vector<int> &PB,
+             std::vector<double> &phi) {
+    std::vector<HostMesh> hm;
+    for (int b = 0; b < kNBand; ++b) hm.push_back(make_mesh(kBandA[b]));
+    const int npts = (int)P1.size();
+    phi.assign(npts, 0.0);
+    if (npts == 0) return VDWNL_OK;
+    {
+        size_t tot = 0;
+        for (auto &m : hm) tot += m.a.size();
+        double *dmesh = nullptr, *dP1 = nullptr, *dP2 = nullptr, *dout = nullptr;
+        int *dPB = nullptr;
+        MeshDev *dmd = nullptr;
+        bool ok = hipMalloc(&dmesh, 4 * tot * sizeof(double)) == hipSuccess &&
+                  hipMalloc(&dP1, npts * sizeof(double)) == hipSuccess &&
+                  hipMalloc(&dP2, npts * sizeof(double)) == hipSuccess &&
+                  hipMalloc(&dout, npts * sizeof(double)) == hipSuccess &&
+                  hipMalloc(&dPB, npts * sizeof(int)) == hipSuccess &&
+                  hipMalloc(&dmd, kNBand * sizeof(MeshDev)) == hipSuccess;
+        if (ok) {
+            std::vector<double> flat(4 * tot);
+            std::vector<MeshDev> md(kNBand);
+            size_t o = 0;
+            for (int b = 0; b < kNBand; ++b) {
+                const size_t n = hm[b].a.size();
+                std::memcpy(&flat[o], hm[b].a.data(), n * 8);
+                std::memcpy(&flat[o + n], hm[b].wa.data(), n * 8);
+                std::memcpy(&flat[o + 2 * n], hm[b].S.data(), n * 8);
+                std::memcpy(&flat[o + 3 * n], hm[b].F.data(), n * 8);
+                md[b] = MeshDev{dmesh + o, dmesh + o + n, dmesh + o + 2 * n, dmesh + o + 3 * n, (int)n};
+                o += 4 * n;
+            }
+            ok = hipMemcpy(dmesh, flat.data(), flat.size() * 8, hipMemcpyHostToDevice) == hipSuccess &&
+                 hipMemcpy(dmd, md.data(), md.size() * sizeof(MeshDev), hipMemcpyHostToDevice) == hipSuccess &&
+                 hipMemcpy(dP1, P1.data(), npts * 8, hipMemcpyHostToDevice) == hipSuccess &&
+                 hipMemcpy(dP2, P2.data(), npts * 8, hipMemcpyHostToDevice) == hipSuccess &&
+                 hipMemcpy(dPB, PB.data(), npts * 4, hipMemcpyHostToDevice) == hipSuccess;
+        }
+        if (ok) {
+            hipLaunchKernelGGL(k_phi, dim3(npts), dim3(kTile), 0, 0, dP1, dP2, dPB, dmd, dout, npts);
+            ok = hipGetLastError() == hipSuccess && hipDeviceSynchronize() == hipSuccess &&
+                 hipMemcpy(phi.data(), dout, npts * 8, hipMemcpyDeviceToHost) == hipSuccess;
+        }
+        for (void *p : {(void *)dmesh, (void *)dP1, (void *)dP2, (void *)dout, (void *)dPB, (void *)dmd})
+            if (p) (void)hipFree(p);
+        if (!ok) return VDWNL_E_HIP;
+    }
+
+    return VDWNL_OK;
+}
 
 }  // namespace
 
@@ -271,57 +334,36 @@ extern "C" int vdwnl_build_kernel_table(int device, int32_t nq, const double *qm
             }
     }
 
-    // ---- meshes and the phi kernel
-    std::vector<HostMesh> hm;
-    for (int b = 0; b < kNBand; ++b) hm.push_back(make_mesh(kBandA[b]));
-    const int npts = (int)P1.size();
-    std::vector<double> phi(npts);
+    // ---- the phi kernel at every point
+    std::vector<double> phi;
     {
-        size_t tot = 0;
-        for (auto &m : hm) tot += m.a.size();
-        double *dmesh = nullptr, *dP1 = nullptr, *dP2 = nullptr, *dout = nullptr;
-        int *dPB = nullptr;
-        MeshDev *dmd = nullptr;
-        bool ok = hipMalloc(&dmesh, 4 * tot * sizeof(double)) == hipSuccess &&
-                  hipMalloc(&dP1, npts * sizeof(double)) == hipSuccess &&
-                  hipMalloc(&dP2, npts * sizeof(double)) == hipSuccess &&
-                  hipMalloc(&dout, npts * sizeof(double)) == hipSuccess &&
-                  hipMalloc(&dPB, npts * sizeof(int)) == hipSuccess &&
-                  hipMalloc(&dmd, kNBand * sizeof(MeshDev)) == hipSuccess;
-        if (ok) {
-            std::vector<double> flat(4 * tot);
-            std::vector<MeshDev> md(kNBand);
-            size_t o = 0;
-            for (int b = 0; b < kNBand; ++b) {
-                const size_t n = hm[b].a.size();
-                std::memcpy(&flat[o], hm[b].a.data(), n * 8);
-                std::memcpy(&flat[o + n], hm[b].wa.data(), n * 8);
-                std::memcpy(&flat[o + 2 * n], hm[b].S.data(), n * 8);
-                std::memcpy(&flat[o + 3 * n], hm[b].F.data(), n * 8);
-                md[b] = MeshDev{dmesh + o, dmesh + o + n, dmesh + o + 2 * n, dmesh + o + 3 * n, (int)n};
-                o += 4 * n;
-            }
-            ok = hipMemcpy(dmesh, flat.data(), flat.size() * 8, hipMemcpyHostToDevice) == hipSuccess &&
-                 hipMemcpy(dmd, md.data(), md.size() * sizeof(MeshDev), hipMemcpyHostToDevice) == hipSuccess &&
-                 hipMemcpy(dP1, P1.data(), npts * 8, hipMemcpyHostToDevice) == hipSuccess &&
-                 hipMemcpy(dP2, P2.data(), npts * 8, hipMemcpyHostToDevice) == hipSuccess &&
-                 hipMemcpy(dPB, PB.data(), npts * 4, hipMemcpyHostToDevice) == hipSuccess;
-        }
-        if (ok) {
-            hipLaunchKernelGGL(k_phi, dim3(npts), dim3(kTile), 0, 0, dP1, dP2, dPB, dmd, dout, npts);
-            ok = hipGetLastError() == hipSuccess && hipDeviceSynchronize() == hipSuccess &&
-                 hipMemcpy(phi.data(), dout, npts * 8, hipMemcpyDeviceToHost) == hipSuccess;
-        }
-        for (void *p : {(void *)dmesh, (void *)dP1, (void *)dP2, (void *)dout, (void *)dPB, (void *)dmd})
-            if (p) (void)hipFree(p);
-        if (!ok) return VDWNL_E_HIP;
+        const int rc = eval_phi(P1, P2, PB, phi);
+        if (rc != VDWNL_OK) return rc;
     }
 
     // ---- soft form per ray, samples of g = D phi_s on [0, X] and the asymptote beyond
-    std::vector<double> Dall, gall, Qr;
+    std::vector<double> Dall, gall, cvall, Qr;
     std::vector<int> off = {0};
     const double hh = 2e-3 * d_s;
+    // g''/2 per interval.  Nodes carry g'' from their own piece (soft
+    // polynomial and asymptote: analytic; sampled kernel: divided differences,
+    // one-sided at the ends of the piece, as phi_s is only C^1 at d_s); an
+    // interval takes the mean of its nodes, or the piece its interior lies in.
+    auto curvatures = [&](size_t b, const std::vector<int> &seg, const std::vector<double> &d2) {
+        const size_t n = Dall.size() - b;
+        for (size_t i = 0; i < n; ++i) {
+            double c = 0.0;
+            if (i + 1 < n) {
+                if (seg[i] == seg[i + 1]) c = 0.25 * (d2[i] + d2[i + 1]);
+                else c = 0.5 * (seg[i + 1] == 2 ? d2[i + 1] : d2[i]);
+            }
+            cvall.push_back(c);
+        }
+    };
     for (auto &r : rays) {
+        const size_t base = Dall.size();
+        std::vector<int> seg;        // 0 soft polynomial, 1 sampled kernel, 2 asymptote
+        std::vector<double> d2;      // g'' at the node
         const double *ps = &phi[r.slope_first];
         const double f = phi[r.first];                                      // phi(d_s) on the ray
         const double fp = (ps[0] - 8.0 * ps[1] + 8.0 * ps[2] - ps[3]) / (12.0 * hh);   // d phi / dD at d_s
@@ -332,16 +374,32 @@ extern "C" int vdwnl_build_kernel_table(int device, int32_t nq, const double *qm
             const double D = i * h1, D2 = D * D;
             Dall.push_back(D);
             gall.push_back(D * (phi0 + r.phi2 * D2 + r.phi4 * D2 * D2));
+            seg.push_back(0);
+            d2.push_back(6.0 * r.phi2 * D + 20.0 * r.phi4 * D2 * D);   // (D phi_s)''
         }
+        const size_t e0 = Dall.size();
         for (size_t i = 0; i < r.D.size(); ++i) {
             Dall.push_back(r.D[i]);
             gall.push_back(r.D[i] * phi[r.first + i]);
+            seg.push_back(1);
+            d2.push_back(0.0);
+        }
+        const size_t ne = Dall.size() - e0;
+        for (size_t i = 0; i < ne && ne >= 3; ++i) {
+            const size_t m = std::min(std::max<size_t>(i, 1), ne - 2) + e0;   // centre of the 3-point stencil
+            const double x0 = Dall[m - 1], x1 = Dall[m], x2 = Dall[m + 1];
+            const double y0 = gall[m - 1], y1 = gall[m], y2 = gall[m + 1];
+            d2[e0 - base + i] = 2.0 * ((y2 - y1) / (x2 - x1) - (y1 - y0) / (x1 - x0)) / (x2 - x0);
         }
         const double coef = kCasym / (r.c * r.c * r.s * r.s);   // phi -> -coef / D^6
         for (double D = r.X * 1.005; D < 200.0 * r.X; D *= 1.005) {
             Dall.push_back(D);
             gall.push_back(-coef / (D * D * D * D * D));
+            seg.push_back(2);
+            const double D2 = D * D;
+            d2.push_back(-30.0 * coef / (D2 * D2 * D2 * D));
         }
+        curvatures(base, seg, d2);
         off.push_back((int)Dall.size());
         Qr.push_back(r.Q);
     }
@@ -350,24 +408,26 @@ extern "C" int vdwnl_build_kernel_table(int device, int32_t nq, const double *qm
     const int nrays = (int)rays.size();
     std::vector<double> psi((size_t)nrays * nk);
     {
-        double *dD = nullptr, *dg = nullptr, *dQ = nullptr, *dout = nullptr;
+        double *dD = nullptr, *dg = nullptr, *dcv = nullptr, *dQ = nullptr, *dout = nullptr;
         int *doff = nullptr;
         bool ok = hipMalloc(&dD, Dall.size() * 8) == hipSuccess && hipMalloc(&dg, gall.size() * 8) == hipSuccess &&
+                  hipMalloc(&dcv, cvall.size() * 8) == hipSuccess &&
                   hipMalloc(&dQ, Qr.size() * 8) == hipSuccess && hipMalloc(&doff, off.size() * 4) == hipSuccess &&
                   hipMalloc(&dout, psi.size() * 8) == hipSuccess;
         if (ok)
             ok = hipMemcpy(dD, Dall.data(), Dall.size() * 8, hipMemcpyHostToDevice) == hipSuccess &&
                  hipMemcpy(dg, gall.data(), gall.size() * 8, hipMemcpyHostToDevice) == hipSuccess &&
+                 hipMemcpy(dcv, cvall.data(), cvall.size() * 8, hipMemcpyHostToDevice) == hipSuccess &&
                  hipMemcpy(dQ, Qr.data(), Qr.size() * 8, hipMemcpyHostToDevice) == hipSuccess &&
                  hipMemcpy(doff, off.data(), off.size() * 4, hipMemcpyHostToDevice) == hipSuccess;
         if (ok) {
             const long tot = (long)nrays * nk;
-            hipLaunchKernelGGL(k_radial, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, 0, dD, dg, doff, dQ, nrays,
+            hipLaunchKernelGGL(k_radial, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, 0, dD, dg, dcv, doff, dQ, nrays,
                                nk, dk, dout);
             ok = hipGetLastError() == hipSuccess && hipDeviceSynchronize() == hipSuccess &&
                  hipMemcpy(psi.data(), dout, psi.size() * 8, hipMemcpyDeviceToHost) == hipSuccess;
         }
-        for (void *p : {(void *)dD, (void *)dg, (void *)dQ, (void *)dout, (void *)doff})
+        for (void *p : {(void *)dD, (void *)dg, (void *)dcv, (void *)dQ, (void *)dout, (void *)doff})
             if (p) (void)hipFree(p);
         if (!ok) return VDWNL_E_HIP;
     }
@@ -393,5 +453,22 @@ extern "C" int vdwnl_build_kernel_table(int device, int32_t nq, const double *qm
         }
         *c_soft_out = 0.5 * acc;
     }
+    return VDWNL_OK;
+}
+
+extern "C" int vdwnl_kernel_phi(int device, int32_t n, const double *d1, const double *d2, double *out) {
+    if (n < 0 || (n > 0 && (!d1 || !d2 || !out))) return VDWNL_E_ARG;
+    for (int i = 0; i < n; ++i)
+        if (!(d1[i] > 0.0) || !(d2[i] > 0.0) || !std::isfinite(d1[i]) || !std::isfinite(d2[i]) ||
+            std::max(d1[i], d2[i]) > kBandA[kNBand - 1] / 5.0)
+            return VDWNL_E_ARG;
+    if (device < 0) return VDWNL_E_STATE;
+    if (hipSetDevice(device) != hipSuccess) return VDWNL_E_HIP;
+    std::vector<double> P1(d1, d1 + n), P2(d2, d2 + n), phi;
+    std::vector<int> PB(n);
+    for (int i = 0; i < n; ++i) PB[i] = band_of(d1[i], d2[i]);
+    const int rc = eval_phi(P1, P2, PB, phi);
+    if (rc != VDWNL_OK) return rc;
+    std::memcpy(out, phi.data(), (size_t)n * sizeof(double));
     return VDWNL_OK;
 }

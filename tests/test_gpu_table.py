@@ -56,3 +56,21 @@ def test_energy_with_either_table(gpu_table, table):
     e2 = sum(F.energy_potential(n, wl.cell, gpu_table)[:2])
     print("  E with oracle table %.12e, with GPU table %.12e" % (e1, e2), flush=True)
     assert abs(e1 - e2) < 3e-6 * abs(e1)
+
+
+def test_kernel_phi_against_oracle():
+    """phi(d1, d2) of Eq. (Enl) from the GPU double integral against the
+    oracle's, on points across the soft, intermediate and asymptotic ranges
+    (both integrals are accurate to about 1e-6 relative for max(d) <= 20)."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from oracle import kernel_table as kt
+    from paper_0812_0244_amd.binding import kernel_phi
+    rng = np.random.default_rng(7)
+    d1 = np.concatenate([np.geomspace(0.01, 20, 40), rng.uniform(0.1, 15, 40)])
+    d2 = np.concatenate([np.geomspace(0.01, 20, 40)[::-1], rng.uniform(0.1, 15, 40)])
+    g = kernel_phi(d1, d2)
+    o = kt.phi(d1, d2)
+    rel = np.abs(g - o) / np.abs(o)
+    print("  max |phi_gpu / phi_oracle - 1| = %.2e" % rel[np.abs(o) > 1e-3 * np.abs(o).max()].max(), flush=True)
+    assert np.all(np.abs(g - o) <= 3e-6 * np.abs(o) + 1e-10)
