@@ -49,6 +49,28 @@ def pass_bytes(name, shapes, s):
     return tot
 
 
+def measured_traffic(kernel, lds_budget_z):
+    """HBM bytes per evaluation of `kernel` from the committed counter summary
+    (profiles/<kernel>_batched64_fp32.md), if it was taken on the kernel
+    sources as they are now and the same tile budget; else None."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "%s_batched64_fp32.md" % kernel)
+    if not os.path.exists(path):
+        return None
+    m = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    h = hashlib.sha256()
+    src = os.path.join(ROOT, "paper_0812_0244_amd", "csrc")
+    for f in ("common.hpp", "fft_lds.hpp", "fft_fast.hpp", "tile_io.hpp", "kernels.hip"):
+        h.update(open(os.path.join(src, f), "rb").read())
+    if rec.get("kernel_sources_sha256") != h.hexdigest() or rec.get("lds_budget_z") != lds_budget_z:
+        return None
+    return float(rec["hbm_bytes_per_evaluation"])
+
+
 def cpu_baseline(insts, dens, budget_s):
     """The FP64 oracle on the smallest densities of the batch, until about
     budget_s seconds of host work; grid points per second."""
@@ -167,7 +189,8 @@ def main():
     for k, (ms, calls) in passes.items():
         log("  pass %-10s %8.3f ms/step" % (k, ms / max(calls, 1)))
 
-    # dominant pass and its roofline
+    # dominant pass and its roofline (bytes and time per step: the pass's
+    # launches over every grid of the batch)
     dom = max((k for k in passes if k != "reduce"), key=lambda k: passes[k][0])
     dom_ms = passes[dom][0] / max(passes[dom][1], 1)
     dom_bytes = pass_bytes(dom, shapes, 4)
@@ -241,7 +264,9 @@ def main():
         "passes_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in passes.items()},
         "event_timed_ms_per_step": ev_ms,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
+                     "traffic": measured_traffic(dom, tiling["z"]) if dom == "z_main" else None,
+                     "algorithmic_bytes": dom_bytes,
                      "path_algorithmic_bytes_per_step": path_bytes,
                      "path_frac": path_bytes / (ms_step * 1e-3) / 1e9 / PEAK_HBM_GBS},
         "cpu_baseline": cpu,
