@@ -137,6 +137,7 @@ struct vdwnl_ctx {
     void *d_tw = nullptr;                 // twiddles in the working precision
     void *d_twd = nullptr;                // FP64 twiddles
     Consts *d_consts = nullptr;
+    int2 *d_cols = nullptr;               // (k2, k3) columns of the fused axis-1 tiles
     double *d_E = nullptr, *h_E = nullptr;
     std::map<int, int> tw_off;            // length -> offset
     // the evaluation captured as a HIP graph (replayed on the caller's stream)
@@ -189,6 +190,8 @@ static void free_device(vdwnl_ctx *c) {
     if (c->d_tw) (void)hipFree(c->d_tw);
     if (c->d_twd) (void)hipFree(c->d_twd);
     if (c->d_consts) (void)hipFree(c->d_consts);
+    if (c->d_cols) (void)hipFree(c->d_cols);
+    c->d_cols = nullptr;
     if (c->d_E) (void)hipFree(c->d_E);
     if (c->h_E) (void)hipHostFree(c->h_E);
     c->work = nullptr; c->d_inst = nullptr; c->h_inst = nullptr; c->d_tiles = nullptr;
@@ -218,7 +221,7 @@ static int check_grid(vdwnl_ctx *c, const int32_t *shape, const double *cell, in
         return fail(c, VDWNL_E_UNSUPPORTED_SIZE, "N1 * N2 must be even (rows are transformed in pairs)");
     // LDS of each pass as a function of its tile size (twiddles staged in LDS too)
     const size_t stage = (size_t)((kThreads / 64) * (64 / kNQ)) * kTabStride * rs;
-    auto zmain = [&](size_t k3) { return (N1 + (kNQ * k3 + 1) * N1) * cs + 16 + stage; };
+    auto zmain = [&](size_t k3) { return (N1 + (kNQ * k3 + 1) * N1) * cs + 16 + stage + (N1 / 2 + 1) * k3 * sizeof(int); };
     auto zaux = [&](size_t k3) { return (N1 + (4 * k3 + 2) * N1) * 16; };
     auto xmain = [&](size_t b) { return b * (N3 + 1) * (2 * 16 + (kNQ / 2) * cs) + N3 * (16 + cs) + (kNQ + kNQ * kNQ) * rs; };
     auto ypass = [&](size_t w, size_t c2) { return (N2 + N2 * (w + 1)) * c2; };
@@ -240,27 +243,31 @@ static void size_tiles(const vdwnl_ctx *c, Grid &g) {
     const size_t cs = c->precision == 64 ? 16 : 8, rs = c->precision == 64 ? 8 : 4;
     const size_t N1 = g.s[0], N2 = g.s[1], N3 = g.s[2];
     const size_t stage = (size_t)((kThreads / 64) * (64 / kNQ)) * kTabStride * rs;
-    auto zmain = [&](size_t k3) { return (N1 + (kNQ * k3 + 1) * N1) * cs + 16 + stage; };
+    auto zmain = [&](size_t k3) { return (N1 + (kNQ * k3 + 1) * N1) * cs + 16 + stage + (N1 / 2 + 1) * k3 * sizeof(int); };
     auto zaux = [&](size_t k3) { return (N1 + (4 * k3 + 2) * N1) * 16; };
     auto xmain = [&](size_t b) { return b * (N3 + 1) * (2 * 16 + (kNQ / 2) * cs) + N3 * (16 + cs) + (kNQ + kNQ * kNQ) * rs; };
     auto ypass = [&](size_t w, size_t c2) { return (N2 + N2 * (w + 1)) * c2; };
+    // complex elements per LDS FFT tile: bounded for the runtime-radix FFT
+    // (its per-thread register arrays), not for the compile-time plans
+    auto cap = [](size_t n) { return len_class((int)n) == kLenGeneric ? (size_t)kTileCap : (size_t)1 << 30; };
     // axis-3 tiles: at most one grid point per thread (the local steps run
     // one point per thread)
     g.bmain = 1;
-    while ((size_t)(g.bmain + 1) * N3 <= (size_t)kThreads && (kNQ / 2) * (g.bmain + 1) * N3 <= (size_t)kTileCap &&
+    while ((size_t)(g.bmain + 1) * N3 <= (size_t)kThreads && (kNQ / 2) * (g.bmain + 1) * N3 <= cap(N3) &&
            xmain(g.bmain + 1) <= c->pref[TG_X])
         ++g.bmain;
     g.bnf = 2;
     while ((size_t)(g.bnf + 2) * N3 <= (size_t)kThreads) g.bnf += 2;
     g.k3main = 1;
-    while ((size_t)kNQ * (g.k3main + 1) * N1 <= (size_t)kTileCap && zmain(g.k3main + 1) <= c->pref[TG_Z]) ++g.k3main;
+    while (g.k3main < kMaxCols && (size_t)kNQ * (g.k3main + 1) * N1 <= cap(N1) && zmain(g.k3main + 1) <= c->pref[TG_Z])
+        ++g.k3main;
     g.k3aux = 1;
-    while (3 * (size_t)(g.k3aux + 1) * N1 <= (size_t)kTileCap && zaux(g.k3aux + 1) <= c->pref[TG_ZAUX]) ++g.k3aux;
+    while (3 * (size_t)(g.k3aux + 1) * N1 <= cap(N1) && zaux(g.k3aux + 1) <= c->pref[TG_ZAUX]) ++g.k3aux;
     g.wy20 = 1;
-    while ((size_t)(g.wy20 + 1) * N2 <= (size_t)kTileCap && ypass(g.wy20 + 1, cs) <= c->pref[TG_Y20]) ++g.wy20;
+    while ((size_t)(g.wy20 + 1) * N2 <= cap(N2) && ypass(g.wy20 + 1, cs) <= c->pref[TG_Y20]) ++g.wy20;
     if (g.wy20 > 1) g.wy20 &= ~1;   // even widths: 16-byte aligned FP32 rows
     g.wy3 = 1;
-    while ((size_t)(g.wy3 + 1) * N2 <= (size_t)kTileCap && ypass(g.wy3 + 1, 16) <= c->pref[TG_YAUX]) ++g.wy3;
+    while ((size_t)(g.wy3 + 1) * N2 <= cap(N2) && ypass(g.wy3 + 1, 16) <= c->pref[TG_YAUX]) ++g.wy3;
     g.wy1 = g.wy3;
 }
 
@@ -367,6 +374,27 @@ static const char *kPassName[KIND_COUNT + 1] = {
 
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Launch order for XCD locality: workgroups go round-robin to the 8 XCDs, so
+// tile i of a launch runs on XCD i % 8.  Reorder a list of tiles so that each
+// XCD receives a contiguous block of it (neighbouring tiles share cache lines
+// at their edges and, in the fused pass, kernel rows): position 8 r + x
+// holds the r-th tile of block x.
+static void xcd_blocks(std::vector<Tile> &t) {
+    const size_t n = t.size();
+    if (n < 16) return;
+    // block sizes differ by at most one, the larger first, so that every
+    // full round of 8 positions takes one tile from each block
+    const size_t base = n / 8, rem = n % 8;
+    std::vector<size_t> start(9, 0);
+    for (size_t x = 0; x < 8; ++x) start[x + 1] = start[x] + base + (x < rem ? 1 : 0);
+    std::vector<Tile> out;
+    out.reserve(n);
+    for (size_t r = 0; r <= base; ++r)
+        for (size_t x = 0; x < 8; ++x)
+            if (start[x] + r < start[x + 1]) out.push_back(t[start[x] + r]);
+    t.swap(out);
+}
+
 // Build every device structure for the current grids and table.
 static int prepare_device(vdwnl_ctx *c) {
     if (c->device_ready) return VDWNL_OK;
@@ -391,11 +419,14 @@ static int prepare_device(vdwnl_ctx *c) {
         off = align_up(off + c->shells[i].gmod.size() * kTabStride * rs);
     }
     std::vector<Tile> tiles[KIND_COUNT];
+    std::vector<int2> zcols;              // columns of the fused axis-1 tiles
     for (size_t gi = 0; gi < c->grids.size(); ++gi) {
         Grid &g = c->grids[gi];
         const int N1 = g.s[0], N2 = g.s[1], N3 = g.s[2], N3h = N3 / 2 + 1;
         const int rows = N1 * N2;
         const int inst = (int)gi;
+        size_t first_tile[KIND_COUNT];
+        for (int k = 0; k < KIND_COUNT; ++k) first_tile[k] = tiles[k].size();
         // axis-3 tiles
         for (int r = 0; r < rows; r += g.bnf) {
             const int b = std::min(g.bnf, rows - r);   // even: rows and bnf are
@@ -418,29 +449,32 @@ static int prepare_device(vdwnl_ctx *c) {
             for (int i1 = 0; i1 < N1; ++i1)
                 for (int f = 0; f < ftot; f += w) tiles[kinds_y[q]].push_back({inst, i1, f, std::min(w, ftot - f), -1});
         }
-        // axis-1 tiles.  The fused pass reads one kernel row per |G| shell and
-        // point pair; the columns k2 and N2 - k2 (same |m2|) meet the same
-        // shells, so their tiles are placed 8 apart in the launch (workgroups
-        // go round-robin to the 8 XCDs: same XCD, same L2, about the same time).
+        // Fused axis-1 tiles: the columns k2 and N2 - k2 (the same |m2|, so
+        // the same |G| shell at every (|m1|, k3)) over a run of consecutive
+        // k3; one staged kernel row then serves four k points.  Columns
+        // k2 = 0 and N2/2 stand alone.
         {
-            std::vector<std::pair<Tile, Tile>> prs;
-            std::vector<Tile> singles;
-            for (int k2 = 0; k2 < N2; ++k2) {
-                const int partner = (N2 - k2) % N2;
-                if (partner < k2) continue;
-                for (int k3 = 0; k3 < N3h; k3 += g.k3main) {
-                    const int cnt = std::min(g.k3main, N3h - k3);
-                    if (partner == k2) singles.push_back({inst, k2, k3, cnt, -1});
-                    else prs.push_back({{inst, k2, k3, cnt, -1}, {inst, partner, k3, cnt, -1}});
+            const int K = std::min(g.k3main, kMaxCols);
+            std::vector<Tile> zt;
+            // (a budget of one column per tile: k2 and N2 - k2 in tiles of their own)
+            for (int k2 = 0; k2 <= N2 / 2; ++k2) {
+                const int k2b = (N2 - k2) % N2;
+                const bool pair = k2b != k2 && K >= 2;
+                for (int side = 0; side < ((k2b != k2 && !pair) ? 2 : 1); ++side) {
+                    const int ka = side == 0 ? k2 : k2b;
+                    const int cp = pair ? 2 : 1;                  // columns per pair
+                    const int P = std::max(1, K / cp);            // pairs per tile (P cp <= K)
+                    for (int k3 = 0; k3 < N3h; k3 += P) {
+                        const int np = std::min(P, N3h - k3);
+                        zt.push_back({inst, (int)zcols.size(), np, cp, -1});
+                        for (int i = 0; i < np; ++i) {
+                            zcols.push_back({ka, k3 + i});
+                            if (pair) zcols.push_back({k2b, k3 + i});
+                        }
+                    }
                 }
             }
-            std::vector<Tile> zt;
-            for (size_t b0 = 0; b0 < prs.size(); b0 += 8) {
-                const size_t b1 = std::min(prs.size(), b0 + 8);
-                for (size_t i = b0; i < b1; ++i) zt.push_back(prs[i].first);
-                for (size_t i = b0; i < b1; ++i) zt.push_back(prs[i].second);
-            }
-            zt.insert(zt.end(), singles.begin(), singles.end());
+            xcd_blocks(zt);
             slot = 0;
             for (Tile &tl : zt) {
                 tl.slot = slot++;
@@ -453,6 +487,13 @@ static int prepare_device(vdwnl_ctx *c) {
                 tiles[KZ_DIV].push_back({inst, k2, k3, std::min(g.k3aux, N3h - k3), -1});
             }
         g.n_ek = slot;
+        // XCD-contiguous order for this grid's tiles of the other passes
+        for (int k = 0; k < KIND_COUNT; ++k) {
+            if (k == KZ_MAIN) continue;
+            std::vector<Tile> mine(tiles[k].begin() + first_tile[k], tiles[k].end());
+            xcd_blocks(mine);
+            std::copy(mine.begin(), mine.end(), tiles[k].begin() + first_tile[k]);
+        }
         // fields
         g.off_grad = off; off = align_up(off + 3 * g.npts() * rs);
         g.off_vloc = off; off = align_up(off + g.npts() * rs);
@@ -472,7 +513,11 @@ static int prepare_device(vdwnl_ctx *c) {
             case KY_1F: case KY_1I: return (N2 + N2 * (g.wy1 + 1)) * 16;
             case KY_3F: case KY_3I: return (N2 + N2 * (g.wy3 + 1)) * 16;
             case KY_20F: case KY_20I: return (N2 + N2 * (g.wy20 + 1)) * cs;
-            case KZ_MAIN: return (N1 + (size_t)(kNQ * g.k3main + 1) * N1) * cs + 16 + (size_t)((kThreads / 64) * (64 / kNQ)) * kTabStride * rs;
+            case KZ_MAIN: {
+                const size_t K = std::min(g.k3main, kMaxCols);
+                return (N1 + (size_t)(kNQ * K + 1) * N1) * cs + 16 + (size_t)((kThreads / 64) * (64 / kNQ)) * kTabStride * rs +
+                       (N1 / 2 + 1) * K * sizeof(int);
+            }
             default: return (N1 + (4 * g.k3aux + 2) * N1) * 16;   // KZ_GRAD, KZ_DIV
         }
     };
@@ -503,7 +548,7 @@ static int prepare_device(vdwnl_ctx *c) {
     // at launch time: launches may be captured into a graph)
     for (int k = 0; k < KIND_COUNT; ++k)
         for (const auto &L : c->launches[k]) {
-            LaunchArgs a{nullptr, nullptr, 0, L.lds, nullptr, nullptr, nullptr, nullptr};
+            LaunchArgs a{nullptr, nullptr, 0, L.lds, nullptr, nullptr, nullptr, nullptr, nullptr};
             if ((e = launch_kind(k, L.lc, c->precision, a)) != hipSuccess) return hipfail(c, e, "kernel LDS limit");
         }
     // twiddles
@@ -537,6 +582,11 @@ static int prepare_device(vdwnl_ctx *c) {
     if ((e = hipMalloc(&c->d_tw, std::max<size_t>(twbytes, 16))) != hipSuccess) return hipfail(c, e, "hipMalloc twiddles");
     if ((e = hipMalloc(&c->d_twd, std::max<size_t>((twd.size() / 2) * 16, 16))) != hipSuccess) return hipfail(c, e, "hipMalloc twiddles");
     if ((e = hipMalloc(&c->d_consts, sizeof(Consts))) != hipSuccess) return hipfail(c, e, "hipMalloc consts");
+    if ((e = hipMalloc(&c->d_cols, std::max<size_t>(zcols.size(), 1) * sizeof(int2))) != hipSuccess)
+        return hipfail(c, e, "hipMalloc columns");
+    if (!zcols.empty() &&
+        (e = hipMemcpy(c->d_cols, zcols.data(), zcols.size() * sizeof(int2), hipMemcpyHostToDevice)) != hipSuccess)
+        return hipfail(c, e, "upload columns");
     if ((e = hipMalloc(&c->d_E, ng * 2 * sizeof(double))) != hipSuccess) return hipfail(c, e, "hipMalloc E");
     if ((e = hipHostMalloc((void **)&c->h_E, ng * 2 * sizeof(double), hipHostMallocDefault)) != hipSuccess) return hipfail(c, e, "hipHostMalloc E");
     // uploads
@@ -601,7 +651,7 @@ static int enqueue(vdwnl_ctx *c, int nb, hipStream_t st) {
     for (int i = 0; i < KIND_COUNT; ++i) {
         const int k = kPassOrder[i];
         for (const auto &L : c->launches[k]) {
-            LaunchArgs a{c->d_inst, c->d_tiles + L.off, L.cnt, L.lds, c->d_consts, c->d_tw, c->d_twd, st};
+            LaunchArgs a{c->d_inst, c->d_tiles + L.off, L.cnt, L.lds, c->d_consts, c->d_tw, c->d_twd, st, c->d_cols};
             if ((e = launch_kind(k, L.lc, c->precision, a)) != hipSuccess) return hipfail(c, e, "kernel launch");
         }
         if (c->timing) (void)hipEventRecord(c->ev[i + 1], st);

@@ -14,6 +14,7 @@ constexpr int kThreads = 256;                    // threads per workgroup, every
 constexpr int kTileCap = 4096;                   // complex elements of one LDS FFT tile
 constexpr int kLdsCap = 65536;                   // bytes of LDS one workgroup may take
 constexpr int kMaxStages = 16;
+constexpr int kMaxCols = 16;                     // (k2, k3) columns per fused axis-1 tile
 constexpr int kMaxN1 = 204;                      // 20 N1 <= kTileCap (fused axis-1 pass)
 constexpr int kMaxN3 = 340;                      // 12 N3 complex doubles <= kLdsCap
 
@@ -96,6 +97,7 @@ struct LaunchArgs {
     const void *tw;          // twiddles in the working precision
     const void *twd;         // FP64 twiddles (gradient and divergence chains)
     hipStream_t stream;
+    const int2 *cols;        // (k2, k3) columns of the fused axis-1 tiles
 };
 
 hipError_t launch_kind(int kind, int len_class, int precision, const LaunchArgs &a);

@@ -68,8 +68,10 @@ struct LocalQ {
         const T A = (T)0.031091, a1 = (T)0.21370;
         const T b1 = (T)7.5957, b2 = (T)3.5876, b3 = (T)1.6382, b4 = (T)0.49294;
         const T zg = (T)(0.8491 / 36.0);   // -Z_ab / 36
-        const T kf = dev_cbrt<T>((T)3 * pi * pi * n);
-        const T rs = dev_cbrt<T>((T)3 / ((T)4 * pi * n));
+        // k_F = (3 pi^2 n)^(1/3), r_s = (3 / (4 pi n))^(1/3): one cube root
+        const T cn = dev_cbrt<T>(n);
+        const T kf = (T)3.0936677262801355 * cn;          // (3 pi^2)^(1/3)
+        const T rs = (T)0.6203504908994001 / cn;          // (3 / (4 pi))^(1/3)
         const T srs = dev_sqrt<T>(rs);
         const T P = b1 * srs + b2 * rs + b3 * rs * srs + b4 * rs * rs;
         const T L = dev_log1p<T>((T)1 / ((T)2 * A * P));
@@ -90,27 +92,40 @@ struct LocalQ {
             Q = (T)0;
             return;
         }
-        double S = 0.0, D = 0.0;
+        double S = 0.0;
         for (int m = mc; m >= 1; --m) S = S * y + 1.0 / (double)m;
         S *= y;
-        for (int m = mc - 1; m >= 0; --m) D = D * y + 1.0;
         if (S > 700.0) {
             q0 = (T)qc;
             Q = (T)0;
         } else {
             const double e = exp(-S);
             q0 = (T)(qc * (1.0 - e));
-            Q = (T)(e * D);
+            if (DERIV) {
+                double D = 0.0;
+                for (int m = mc - 1; m >= 0; --m) D = D * y + 1.0;
+                Q = (T)(e * D);
+            } else {
+                Q = (T)0;
+            }
         }
     }
 };
 
 // Natural cubic cardinal splines p_a(q) on the q mesh (Eq. fofx and the text
-// after it): interval search and the two weights; M[j][a] in LDS.
+// after it), M[j][a] (second derivative at q_j of p_a) in LDS.  On the
+// interval j (a = (q_{j+1} - q)/h, b = 1 - a)
+//   p_a  = a d_aj + b d_a,j+1 + ((a^3 - a) M[j][a] + (b^3 - b) M[j+1][a]) h^2/6
+//   p_a' = (d_a,j+1 - d_aj)/h + ((1 - 3a^2) M[j][a] + (3b^2 - 1) M[j+1][a]) h/6
+// and below q_1 the linear continuation p_a(q_1) + (q - q_1) p_a'(q_1).  Both
+// are written p_a = A0 d_aj + A1 d_a,j+1 + C0 M[j][a] + C1 M[j+1][a] and
+// p_a' = B0 d_aj + B1 d_a,j+1 + D0 M[j][a] + D1 M[j+1][a] with per-point
+// scalars, so sums over a reduce to two dot products with rows of M.
 template <typename T>
-struct SplinePos {
+struct SplineW {
     int j;
-    T a, b, h, dq;   // dq = q0 - q_1 below the mesh (linear continuation), else 0
+    T A0, A1, C0, C1;
+    T B0, B1, D0, D1;
 
     __device__ __forceinline__ void locate(T q0, const T *qm, int nq) {
         // one path for every case (the struct then stays in registers)
@@ -122,19 +137,18 @@ struct SplinePos {
         }
         j = lo;
         const T ql = qm[lo], qh = qm[lo + 1];
-        h = qh - ql;
-        const T aa = (qh - q0) / h;
-        a = below ? (T)1 : aa;
-        b = (T)1 - a;
-        dq = below ? q0 - ql : (T)0;
-    }
-    // p_a and dp_a/dq
-    __device__ __forceinline__ void basis(int al, const T *M, T &p, T &dp) const {
-        const T Mj = M[j * kNQ + al], Mj1 = M[(j + 1) * kNQ + al];
-        const T dj = (al == j) ? (T)1 : (T)0, dj1 = (al == j + 1) ? (T)1 : (T)0;
-        p = a * dj + b * dj1 + ((a * a * a - a) * Mj + (b * b * b - b) * Mj1) * h * h / (T)6;
-        dp = (dj1 - dj) / h + (((T)1 - (T)3 * a * a) * Mj + ((T)3 * b * b - (T)1) * Mj1) * h / (T)6;
-        p += dq * dp;
+        const T h = qh - ql, ih = (T)1 / h;
+        const T a = below ? (T)1 : (qh - q0) * ih;
+        const T b = (T)1 - a;
+        const T dq = below ? q0 - ql : (T)0;
+        B0 = -ih;
+        B1 = ih;
+        D0 = ((T)1 - (T)3 * a * a) * h / (T)6;
+        D1 = ((T)3 * b * b - (T)1) * h / (T)6;
+        A0 = a + dq * B0;
+        A1 = b + dq * B1;
+        C0 = (a * a * a - a) * h * h / (T)6 + dq * D0;
+        C1 = (b * b * b - b) * h * h / (T)6 + dq * D1;
     }
 };
 
@@ -237,13 +251,16 @@ __global__ void __launch_bounds__(kThreads) k_x_theta(const InstDev *insts, cons
         if (nv >= (T)c_nmin) {
             LocalQ<T, false> lq;
             lq.eval(nv, g01.x * g01.x + g01.y * g01.y + g2.x * g2.x, c_qc, c_mc);
-            SplinePos<T> sp;
-            sp.locate(lq.q0, qm, kNQ);
-#pragma unroll 4
+            SplineW<T> sw;
+            sw.locate(lq.q0, qm, kNQ);
+            const T *Mj = Mm + sw.j * kNQ;
+            const T nA0 = nv * sw.A0, nA1 = nv * sw.A1, nC0 = nv * sw.C0, nC1 = nv * sw.C1;
+#pragma unroll
             for (int al = 0; al < kNQ; ++al) {
-                T pa, dpa;
-                sp.basis(al, Mm, pa, dpa);
-                th[2 * ((al >> 1) * ls + k) + (al & 1)] = nv * pa;
+                T v = nC0 * Mj[al] + nC1 * Mj[kNQ + al];
+                v += (al == sw.j) ? nA0 : (T)0;
+                v += (al == sw.j + 1) ? nA1 : (T)0;
+                th[2 * ((al >> 1) * ls + k) + (al & 1)] = v;
             }
             const T q3 = lq.q0 * lq.q0 * lq.q0;
             de += (double)((T)c_cs * nv * nv / q3);
@@ -331,19 +348,23 @@ __global__ void __launch_bounds__(kThreads) k_x_assemble(const InstDev *insts, c
         if (nv >= (T)c_nmin) {
             LocalQ<T, true> lq;
             lq.eval(nv, gx * gx + gy * gy + gz * gz, c_qc, c_mc);
-            SplinePos<T> spos;
-            spos.locate(lq.q0, qm, kNQ);
+            SplineW<T> sw;
+            sw.locate(lq.q0, qm, kNQ);
             const T *u = reinterpret_cast<const T *>(r2 + (size_t)(kNQ / 2 * rb) * ls);
             const T cn = nv * lq.Q * lq.dqdn;
-            T su = (T)0, sdu = (T)0;
-#pragma unroll 4
+            // sum_a u_a p_a and sum_a u_a p_a' through S0 = sum_a u_a M[j][a], S1 = sum_a u_a M[j+1][a]
+            const T *Mj = Mm + sw.j * kNQ;
+            T S0 = (T)0, S1 = (T)0;
+#pragma unroll
             for (int al = 0; al < kNQ; ++al) {
-                T pa, dpa;
-                spos.basis(al, Mm, pa, dpa);
                 const T ua = u[2 * ((al >> 1) * ls + k) + (al & 1)];
-                su += ua * pa;
-                sdu += ua * dpa;
+                S0 += ua * Mj[al];
+                S1 += ua * Mj[kNQ + al];
             }
+            const int j0 = sw.j, j1 = sw.j + 1;
+            const T uj = u[2 * ((j0 >> 1) * ls + k) + (j0 & 1)], uj1 = u[2 * ((j1 >> 1) * ls + k) + (j1 & 1)];
+            const T su = sw.A0 * uj + sw.A1 * uj1 + sw.C0 * S0 + sw.C1 * S1;
+            const T sdu = sw.B0 * uj + sw.B1 * uj1 + sw.D0 * S0 + sw.D1 * S1;
             // dtheta_a/dn = p_a + n p'_a Q dq/dn ; dtheta_a/dgrad n = 2 n p'_a Q dq/dsigma grad n
             const T q0 = lq.q0, cs = (T)c_cs;
             const T iq3 = (T)1 / (q0 * q0 * q0), iq4 = iq3 / q0;
@@ -502,135 +523,209 @@ __global__ void __launch_bounds__(kThreads) k_z_div(const InstDev *insts, const 
 
 // Forward axis-1 FFT of the 20 theta spectra, u_a(G) = sum_b phi_ab(|G|) c_b(G)
 // with c = Theta / N (Eq. Eoffk, Eq. epsofk), the energy sum
-// sum_G w_G sum_a Re(c_a^* u_a), inverse axis-1 FFT.  tile: a = k2, b = first k3, c = count
+// sum_G w_G sum_a Re(c_a^* u_a), inverse axis-1 FFT.
+// tile: a = first entry in the column list, b = number of column pairs P,
+// c = columns per pair (2: k2 and N2 - k2, which meet the same |G| shell at
+// every (|m1|, k3); 1: k2 = 0 or N2/2).  Pair i has k3 = k3_0 + i; the list
+// holds the columns pair by pair.
 //
-// Contraction layout: lanes form groups of kNQ (three per wave).  A group takes
-// one item: a k3 of the tile and an |m1|, i.e. the pair of k points
-// (m1, -m1) that share the |G| shell; it stages the shell's packed kernel row
-// in LDS with coalesced 16-byte loads, then lane a forms u_a for both points.
+// Contraction layout: lanes form groups of kNQ (three per wave).  A group
+// takes one item, a |m1| and a pair, stages that shell's packed kernel row in
+// LDS with coalesced 16-byte loads, and lane a keeps phi_ab, b < 20, in
+// registers while it forms u_a at the pair's points (+-m1 of each column).
+// The row of the group's next item is fetched into registers meanwhile.
 template <typename T, int LC>
-__global__ void __launch_bounds__(kThreads) k_z_main(const InstDev *insts, const Tile *tiles,
+__global__ void __launch_bounds__(kThreads) k_z_main(const InstDev *insts, const Tile *tiles, const int2 *cols,
                                                      const void *twv) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int kGroups = (kThreads / 64) * (64 / kNQ);   // lane groups per workgroup
     constexpr int kChunks = kTabStride * (int)sizeof(T) / 16; // 16-byte chunks of one shell row
     constexpr int kCpl = (kChunks + kNQ - 1) / kNQ;           // chunks per lane of a group
+    constexpr int kEpc = 16 / (int)sizeof(C2<T>);             // complex values per 16-byte chunk
     const Tile t = tiles[blockIdx.x];
     const InstDev &I = insts[t.inst];
-    const int N1 = axis_len<LC>(I.n1), N2 = I.n2, N3 = I.n3, N3h = I.n3h, k2 = t.a, k30 = t.b, K3 = t.c;
-    const int W = K3 * kNQ, es = W | 1;                      // odd element stride
+    const int N1 = axis_len<LC>(I.n1), N2 = I.n2, N3 = I.n3, N3h = I.n3h, P = t.b, CP = t.c, K = P * CP;
+    const int W = K * kNQ, es = W | 1;                       // odd element stride
+    __shared__ int colbase[kMaxCols];                         // offset of each column in a k1 plane
+    __shared__ int colk3[kMaxCols];
     C2<T> *twall = reinterpret_cast<C2<T> *>(smem);
     C2<T> *buf = twall + N1;
     const size_t stage_off = ((size_t)(N1 + N1 * es) * sizeof(C2<T>) + 15) & ~(size_t)15;
     T *stage = reinterpret_cast<T *>(smem + stage_off);       // [kGroups][kTabStride], 16-byte aligned
-    const size_t stride = (size_t)N2 * N3h * kNQ;
-    C2<T> *g = reinterpret_cast<C2<T> *>(I.spec) + ((size_t)k2 * N3h + k30) * kNQ;
-    crows_in(buf, es, g, stride, N1, W);
+    if (threadIdx.x < K) {
+        const int2 cw = cols[t.a + threadIdx.x];
+        colbase[threadIdx.x] = (cw.x * N3h + cw.y) * kNQ;
+        colk3[threadIdx.x] = cw.y;
+    }
+    const int2 c0 = cols[t.a];
+    __syncthreads();
+    const size_t plane = (size_t)N2 * N3h * kNQ;
+    C2<T> *spec = reinterpret_cast<C2<T> *>(I.spec);
+    // 16-byte chunks (l, w, e): plane l, column w, chunk e of the column's 20 values
+    constexpr int kCpc = kNQ / kEpc;                          // chunks per column
+    auto io = [&](bool in) {
+        const int total = N1 * K * kCpc;
+        RowCursor cur(threadIdx.x, K * kCpc);
+        for (int base = threadIdx.x; base < total; base += kUnroll * kThreads) {
+            // held as scalar components (arrays of vector types would go to scratch)
+            T ra[kUnroll], rb[kUnroll], rc[kUnroll], rd[kUnroll];
+            int lo[kUnroll];
+            size_t go[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const int w = cur.w / kCpc, e = cur.w - w * kCpc;
+                lo[u] = base + u * kThreads < total ? cur.l * es + w * kNQ + e * kEpc : -1;
+                go[u] = (size_t)cur.l * plane + colbase[w] + e * kEpc;
+                if (in && lo[u] >= 0) {
+                    if constexpr (kEpc == 2) {
+                        const float4 v = gld(reinterpret_cast<const float4 *>(spec + go[u]))[0];
+                        ra[u] = v.x; rb[u] = v.y; rc[u] = v.z; rd[u] = v.w;
+                    } else {
+                        const C2<T> v = gld(spec + go[u])[0];
+                        ra[u] = v.x; rb[u] = v.y;
+                    }
+                }
+                cur.step();
+            }
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                if (lo[u] < 0) continue;
+                if (in) {
+                    buf[lo[u]] = mk<T>(ra[u], rb[u]);
+                    if constexpr (kEpc == 2) buf[lo[u] + 1] = mk<T>(rc[u], rd[u]);
+                } else if constexpr (kEpc == 2) {
+                    const C2<T> p0 = buf[lo[u]], p1 = buf[lo[u] + 1];
+                    gst(reinterpret_cast<float4 *>(spec + go[u]))[0] = make_float4(p0.x, p0.y, p1.x, p1.y);
+                } else {
+                    gst(spec + go[u])[0] = buf[lo[u]];
+                }
+            }
+        }
+    };
+    io(true);
     load_twiddles<T>(twall, I.p1, reinterpret_cast<const C2<T> *>(twv));
 
-    // Contraction bookkeeping.  Group gid takes items gid, gid + kGroups, ...;
-    // an item is (|m1|, k3 of the tile).  The shell row of the first item is
-    // fetched before the forward FFT so its latency hides behind it.
     const T *tab = reinterpret_cast<const T *>(I.shelltab);
-    const int m2 = freq_abs(k2, N2);
+    const int m2 = freq_abs(c0.x, N2), k30 = c0.y;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int grp = lane / kNQ, al = lane - grp * kNQ;
     const bool lane_on = grp < 64 / kNQ;
     const int gid = wave * (64 / kNQ) + grp;
-    const int nitems = (N1 / 2 + 1) * K3;
-    const int *smap = I.shellmap + (size_t)m2 * N3h + k30;
-    const size_t smap_m1 = (size_t)I.h2 * N3h;
-    auto shell_of = [&](int item) {
-        const int m1 = item / K3;
-        return gld(smap)[m1 * smap_m1 + (item - m1 * K3)];
-    };
-    // the next shell row: chunks al, al + 20, ... of the row (3 per lane in FP32, 6 in FP64)
+    const int nitems = (N1 / 2 + 1) * P;                     // item = |m1| P + pair
+    // shell of every item, into LDS (the loads overlap the forward FFT)
+    int *sidx = reinterpret_cast<int *>(stage + (size_t)kGroups * kTabStride);
+    {
+        const gptr<const int> smap = gld(I.shellmap + (size_t)m2 * N3h + k30);
+        const size_t smap_m1 = (size_t)I.h2 * N3h;
+        for (int i = threadIdx.x; i < nitems; i += kThreads) {
+            const int m1 = i / P;
+            sidx[i] = smap[m1 * smap_m1 + (i - m1 * P)];
+        }
+    }
+    // shell rows two items ahead, in two register sets used by alternate
+    // items: chunks al, al + 20, ... of a row (3 per lane in FP32, 6 in FP64)
     static_assert(kCpl == 3 || kCpl == 6, "shell row chunking");
     const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
-    float4 r0 = z4, r1 = z4, r2 = z4, r3 = z4, r4 = z4, r5 = z4;
+    float4 a0 = z4, a1 = z4, a2 = z4, a3 = z4, a4 = z4, a5 = z4;
+    float4 b0 = z4, b1 = z4, b2 = z4, b3 = z4, b4 = z4, b5 = z4;
     const bool last_on = al + (kCpl - 1) * kNQ < kChunks;
-#define VDWNL_FETCH_ROW(s)                                                                          \
+#define VDWNL_FETCH_ROW(R, s)                                                                       \
     do {                                                                                            \
         const gptr<const float4> src_ = gld(reinterpret_cast<const float4 *>(tab + (size_t)(s) * kTabStride)); \
-        r0 = src_[al];                                                                              \
-        r1 = src_[al + kNQ];                                                                        \
+        R##0 = src_[al];                                                                            \
+        R##1 = src_[al + kNQ];                                                                      \
         if constexpr (kCpl == 3) {                                                                  \
-            if (last_on) r2 = src_[al + 2 * kNQ];                                                   \
+            if (last_on) R##2 = src_[al + 2 * kNQ];                                                 \
         } else {                                                                                    \
-            r2 = src_[al + 2 * kNQ];                                                                \
-            r3 = src_[al + 3 * kNQ];                                                                \
-            r4 = src_[al + 4 * kNQ];                                                                \
-            if (last_on) r5 = src_[al + 5 * kNQ];                                                   \
+            R##2 = src_[al + 2 * kNQ];                                                              \
+            R##3 = src_[al + 3 * kNQ];                                                              \
+            R##4 = src_[al + 4 * kNQ];                                                              \
+            if (last_on) R##5 = src_[al + 5 * kNQ];                                                 \
         }                                                                                           \
     } while (0)
-    int s_next = 0;
-    if (lane_on && gid < nitems) {
-        VDWNL_FETCH_ROW(shell_of(gid));
-        if (gid + kGroups < nitems) s_next = shell_of(gid + kGroups);
-    }
+#define VDWNL_STAGE_ROW(R)                                                                          \
+    do {                                                                                            \
+        float4 *dst_ = reinterpret_cast<float4 *>(st);                                              \
+        dst_[al] = R##0;                                                                            \
+        dst_[al + kNQ] = R##1;                                                                      \
+        if constexpr (kCpl == 3) {                                                                  \
+            if (last_on) dst_[al + 2 * kNQ] = R##2;                                                 \
+        } else {                                                                                    \
+            dst_[al + 2 * kNQ] = R##2;                                                              \
+            dst_[al + 3 * kNQ] = R##3;                                                              \
+            dst_[al + 4 * kNQ] = R##4;                                                              \
+            if (last_on) dst_[al + 5 * kNQ] = R##5;                                                 \
+        }                                                                                           \
+    } while (0)
     __syncthreads();
+    if (lane_on && gid < nitems) VDWNL_FETCH_ROW(a, sidx[gid]);
+    if (lane_on && gid + kGroups < nitems) VDWNL_FETCH_ROW(b, sidx[gid + kGroups]);
     fft_lc<T, -1, LC>(buf, I.p1, W, es, 1, twall);
 
     T *st = stage + (size_t)(lane_on ? gid : 0) * kTabStride;
     const T inv_n = (T)I.inv_n;
+    const double wn = (double)inv_n * (double)inv_n;
     double e = 0.0;
-    // A group's lanes share one wave, so staging, reads of theta and writes
-    // of u need wave-level ordering only.
-    for (int item = gid; lane_on && item < nitems; item += kGroups) {
-        {
-            float4 *dst = reinterpret_cast<float4 *>(st);
-            dst[al] = r0;
-            dst[al + kNQ] = r1;
-            if constexpr (kCpl == 3) {
-                if (last_on) dst[al + 2 * kNQ] = r2;
-            } else {
-                dst[al + 2 * kNQ] = r2;
-                dst[al + 3 * kNQ] = r3;
-                dst[al + 4 * kNQ] = r4;
-                if (last_on) dst[al + 5 * kNQ] = r5;
-            }
+    // u for item it from the staged row (phi_{al, b}: packed index of
+    // (min, max) in the row-by-row upper triangle)
+    auto contract = [&](int it) {
+        T f[kNQ];
+#pragma unroll
+        for (int b = 0; b < kNQ; ++b) {
+            const int lo = al < b ? al : b, hi = al < b ? b : al;
+            f[b] = st[lo * kNQ - (lo * (lo - 1)) / 2 + (hi - lo)];
         }
-        wave_sync();
-        // prefetch: the next item's row (its shell is known), the shell after it
-        if (item + kGroups < nitems) {
-            VDWNL_FETCH_ROW(s_next);
-            if (item + 2 * kGroups < nitems) s_next = shell_of(item + 2 * kGroups);
-        }
-        const int m1 = item / K3, w = item - m1 * K3;
-        const int k3 = k30 + w;
+        const int m1 = it / P, pr = it - m1 * P;
         const int l = m1;
         int lp = N1 - m1;
         if (m1 == 0 || lp == m1) lp = -1;     // k1 = 0 and the Nyquist plane stand alone
-        C2<T> u1 = mk<T>((T)0, (T)0), u2 = u1;
-        C2<T> *x1 = buf + l * es + w * kNQ;
-        C2<T> *x2 = buf + (lp >= 0 ? lp : l) * es + w * kNQ;
+        for (int w = pr * CP; w < (pr + 1) * CP; ++w) {
+            C2<T> u1 = mk<T>((T)0, (T)0), u2 = u1;
+            C2<T> *x1 = buf + l * es + w * kNQ;
+            C2<T> *x2 = buf + (lp >= 0 ? lp : l) * es + w * kNQ;
 #pragma unroll
-        for (int b = 0; b < kNQ; ++b) {
-            // packed index of (min(a,b), max(a,b)) in the row-by-row upper triangle
-            const int lo = al < b ? al : b, hi = al < b ? b : al;
-            const T f = st[lo * kNQ - (lo * (lo - 1)) / 2 + (hi - lo)];
-            const C2<T> t1 = x1[b], t2 = x2[b];
-            u1.x += f * t1.x;
-            u1.y += f * t1.y;
-            u2.x += f * t2.x;
-            u2.y += f * t2.y;
+            for (int b = 0; b < kNQ; ++b) {
+                const C2<T> t1 = x1[b], t2 = x2[b];
+                u1.x += f[b] * t1.x;
+                u1.y += f[b] * t1.y;
+                u2.x += f[b] * t2.x;
+                u2.y += f[b] * t2.y;
+            }
+            const C2<T> own1 = x1[al], own2 = x2[al];
+            const int k3 = colk3[w];
+            const bool edge = (k3 == 0) || ((N3 & 1) == 0 && k3 == N3 / 2);
+            const double wgt = edge ? wn : 2.0 * wn;
+            e += wgt * (double)(own1.x * u1.x + own1.y * u1.y);
+            if (lp >= 0) e += wgt * (double)(own2.x * u2.x + own2.y * u2.y);
+            wave_sync();
+            x1[al] = cscale(u1, inv_n);
+            if (lp >= 0) x2[al] = cscale(u2, inv_n);
+            wave_sync();
         }
-        const C2<T> own1 = x1[al], own2 = x2[al];
-        const bool edge = (k3 == 0) || ((N3 & 1) == 0 && k3 == N3 / 2);
-        const double wgt = (edge ? 1.0 : 2.0) * (double)inv_n * (double)inv_n;
-        e += wgt * (double)(own1.x * u1.x + own1.y * u1.y);
-        if (lp >= 0) e += wgt * (double)(own2.x * u2.x + own2.y * u2.y);
+    };
+    // A group's lanes share one wave, so staging, reads of theta and writes
+    // of u need wave-level ordering only.  Items alternate between the two
+    // register sets; each set is refilled two items ahead.
+    for (int it = gid; lane_on && it < nitems; it += 2 * kGroups) {
+        VDWNL_STAGE_ROW(a);
         wave_sync();
-        x1[al] = cscale(u1, inv_n);
-        if (lp >= 0) x2[al] = cscale(u2, inv_n);
-        wave_sync();
+        if (it + 2 * kGroups < nitems) VDWNL_FETCH_ROW(a, sidx[it + 2 * kGroups]);
+        contract(it);
+        const int it2 = it + kGroups;
+        if (it2 < nitems) {
+            VDWNL_STAGE_ROW(b);
+            wave_sync();
+            if (it2 + 2 * kGroups < nitems) VDWNL_FETCH_ROW(b, sidx[it2 + 2 * kGroups]);
+            contract(it2);
+        }
     }
     __syncthreads();
     fft_lc<T, 1, LC>(buf, I.p1, W, es, 1, twall);
-    crows_out(g, stride, buf, es, N1, W);
+    io(false);
     const double sum = block_sum(e);
     if (threadIdx.x == 0) I.part_ek[t.slot] = sum;
 #undef VDWNL_FETCH_ROW
+#undef VDWNL_STAGE_ROW
 }
 
 // E_k = (Omega/2) sum of the axis-1 partials; Delta E = dOmega sum of the
@@ -673,7 +768,7 @@ static hipError_t launch_lc(int kind, const LaunchArgs &a) {
         case KY_3I: VDWNL_LAUNCH((k_y<double, 1, LC>), a.twd, 1, 3); break;
         case KX_THETA: VDWNL_LAUNCH((k_x_theta<T, LC>), a.cst, a.tw, a.twd); break;
         case KY_20F: VDWNL_LAUNCH((k_y<T, -1, LC>), a.tw, 0, kNQ); break;
-        case KZ_MAIN: VDWNL_LAUNCH((k_z_main<T, LC>), a.tw); break;
+        case KZ_MAIN: VDWNL_LAUNCH((k_z_main<T, LC>), a.cols, a.tw); break;
         case KY_20I: VDWNL_LAUNCH((k_y<T, 1, LC>), a.tw, 0, kNQ); break;
         case KX_ASSEMBLE: VDWNL_LAUNCH((k_x_assemble<T, LC>), a.cst, a.tw, a.twd); break;
         case KY_3F: VDWNL_LAUNCH((k_y<double, -1, LC>), a.twd, 1, 3); break;
