@@ -24,6 +24,13 @@
  *     The double integral is a plain weighted double sum over a quadrature
  *     mesh (nodes a_k, weights w_k) that the caller supplies.
  *
+ *  3. The brute-force real-space double sum of Eq. (Enl) on a periodic grid
+ *     with the soft kernel phi_s of Eq. (PhiSoft), no interpolation in q:
+ *       sum_i sum_j sum_L n_i n_j phi_s(q_i r, q_j r),  r = |r_j - r_i + L|,
+ *     0 < r < rcut, phi_s from a table over (angle, log D) supplied by the
+ *     caller (see oracle/bruteforce.py), plus the continuum limit of the sum
+ *     beyond rcut from the tabulated tail integral of phi_s along each ray.
+ *
  *  2. The radial Fourier transform of a sampled radial function g(D)/D:
  *       out(kappa) = sum_i c_i g_i sin(kappa D_i),  D_i = i dD,
  *     with trapezoid weights c_i (1/2 at both ends); the caller scales it to
@@ -150,3 +157,148 @@ int oracle_radial_sine_sum(int nd, double dD, const double *g,
     }
     return 0;
 }
+
+/* ---------------------------------------------------------------- 3 */
+
+/* cubic Lagrange weights for nodes 0, 1, 2, 3 at position t */
+static void lag4w(double t, double w[4])
+{
+    w[0] = -(t - 1.0) * (t - 2.0) * (t - 3.0) / 6.0;
+    w[1] = t * (t - 2.0) * (t - 3.0) / 2.0;
+    w[2] = -t * (t - 1.0) * (t - 3.0) / 2.0;
+    w[3] = t * (t - 1.0) * (t - 2.0) / 6.0;
+}
+
+/* first of 4 stencil nodes around fractional index x on n nodes, and the
+ * position of x relative to it */
+static int stencil(double x, int n, double *t)
+{
+    int i = (int)floor(x) - 1;
+    if (i < 0) i = 0;
+    if (i > n - 4) i = n - 4;
+    *t = x - i;
+    return i;
+}
+
+typedef struct {
+    int nth, nu;
+    double th0, dth, u0, du, dmax, ds, phi0, casym;
+    const double *tab, *p2, *p4;   /* tab[k * nu + m]: phi at angle th0 + k dth, D = exp(u0 + m du) */
+    const double *cum;             /* cum[k * nu + m]: 4 pi Int_{D_m}^inf D^2 phi_s dD on that ray */
+} soft_table;
+
+/* 4 pi Int_D^inf D'^2 phi_s(D') dD' on the ray of angle th (D >= d_s) */
+static double tail_integral(const soft_table *T, double th, double D)
+{
+    double t, wt[4], s, wu[4];
+    const int k = stencil((th - T->th0) / T->dth, T->nth, &t);
+    lag4w(t, wt);
+    const int m = stencil((log(D) - T->u0) / T->du, T->nu, &s);
+    lag4w(s, wu);
+    double v = 0.0;
+    for (int a = 0; a < 4; ++a) {
+        const double *row = T->cum + (size_t)(k + a) * T->nu + m;
+        v += wt[a] * (wu[0] * row[0] + wu[1] * row[1] + wu[2] * row[2] + wu[3] * row[3]);
+    }
+    return v;
+}
+
+/* phi_s(d1, d2): soft polynomial below d_s (coefficients interpolated in the
+ * angle), the table up to dmax, the asymptote beyond. */
+static double phi_soft(const soft_table *T, double d1, double d2)
+{
+    const double D = sqrt(d1 * d1 + d2 * d2);
+    if (D == 0.0) return T->phi0;
+    const double lo = d1 < d2 ? d1 : d2, hi = d1 < d2 ? d2 : d1;
+    if (D > T->dmax) return -T->casym / (d1 * d1 * d2 * d2 * (d1 * d1 + d2 * d2));
+    const double th = atan2(lo, hi);   /* in [0, pi/4]: phi is symmetric */
+    double t, wt[4];
+    const int k = stencil((th - T->th0) / T->dth, T->nth, &t);
+    lag4w(t, wt);
+    if (D < T->ds) {
+        double p2 = 0.0, p4 = 0.0;
+        for (int a = 0; a < 4; ++a) { p2 += wt[a] * T->p2[k + a]; p4 += wt[a] * T->p4[k + a]; }
+        const double D2 = D * D;
+        return T->phi0 + p2 * D2 + p4 * D2 * D2;
+    }
+    double s, wu[4];
+    const int m = stencil((log(D) - T->u0) / T->du, T->nu, &s);
+    lag4w(s, wu);
+    double v = 0.0;
+    for (int a = 0; a < 4; ++a) {
+        const double *row = T->tab + (size_t)(k + a) * T->nu + m;
+        v += wt[a] * (wu[0] * row[0] + wu[1] * row[1] + wu[2] * row[2] + wu[3] * row[3]);
+    }
+    return v;
+}
+
+/* out[0] = sum over (i, j, L), 0 < r < rcut, of n_i n_j phi_s(q_i r, q_j r);
+ * out[1] = sum_i n_i^2 phi_s(0, 0) (r = 0);
+ * out[2] = the continuum limit beyond rcut:
+ *          sum_{i,j} n_i n_j (1/Omega) Int_{r > rcut} 4 pi r^2 phi_s(q_i r, q_j r) dr
+ *          = sum_{i,j} n_i n_j I(angle, rcut Q) / (Q^3 Omega),  Q = |(q_i, q_j)|,
+ *          with I the tabulated tail integral along the ray (rcut Q >= d_s).
+ * Grid [n1][n2][n3] (C order) in an orthorhombic cell. */
+int oracle_bf_energy(int n1, int n2, int n3, const double *cell, const double *n, const double *q, double rcut,
+                     int nth, double th0, double dth, int nu, double u0, double du, double dmax,
+                     const double *tab, const double *p2, const double *p4, const double *cum, double ds,
+                     double phi0, double casym, double *out)
+{
+    if (n1 < 1 || n2 < 1 || n3 < 1 || nth < 4 || nu < 4 || !(rcut > 0.0)) return -1;
+    soft_table T = {nth, nu, th0, dth, u0, du, dmax, ds, phi0, casym, tab, p2, p4, cum};
+    const int N = n1 * n2 * n3;
+    const double h[3] = {cell[0] / n1, cell[1] / n2, cell[2] / n3};
+    const int na[3] = {(int)ceil(rcut / cell[0]) + 1, (int)ceil(rcut / cell[1]) + 1, (int)ceil(rcut / cell[2]) + 1};
+    const double omega = cell[0] * cell[1] * cell[2];
+    const double r2c = rcut * rcut;
+    double s_pair = 0.0, s_self = 0.0, s_tail = 0.0;
+    #pragma omp parallel for schedule(dynamic, 8) reduction(+ : s_pair, s_self, s_tail)
+    for (int i = 0; i < N; ++i) {
+        const int i1 = i / (n2 * n3), i2 = (i / n3) % n2, i3 = i % n3;
+        const double qi = q[i], ni = n[i];
+        s_self += ni * ni * phi0;
+        for (int j = i; j < N; ++j) {
+            const int j1 = j / (n2 * n3), j2 = (j / n3) % n2, j3 = j % n3;
+            const double qj = q[j], nj = n[j];
+            const double mult = (j == i) ? 1.0 : 2.0;    /* (i, j) and (j, i) */
+            const double dx = (j1 - i1) * h[0], dy = (j2 - i2) * h[1], dz = (j3 - i3) * h[2];
+            double acc = 0.0;
+            for (int a = -na[0]; a <= na[0]; ++a) {
+                const double x = dx + a * cell[0];
+                if (fabs(x) >= rcut) continue;
+                for (int b = -na[1]; b <= na[1]; ++b) {
+                    const double y = dy + b * cell[1];
+                    const double xy = x * x + y * y;
+                    if (xy >= r2c) continue;
+                    for (int c = -na[2]; c <= na[2]; ++c) {
+                        const double z = dz + c * cell[2];
+                        const double r2 = xy + z * z;
+                        if (r2 >= r2c || r2 == 0.0) continue;
+                        const double r = sqrt(r2);
+                        acc += phi_soft(&T, qi * r, qj * r);
+                    }
+                }
+            }
+            s_pair += mult * ni * nj * acc;
+            const double Q = sqrt(qi * qi + qj * qj);
+            const double th = atan2(qi < qj ? qi : qj, qi < qj ? qj : qi);
+            s_tail += mult * ni * nj * tail_integral(&T, th, rcut * Q) / (Q * Q * Q * omega);
+        }
+    }
+    out[0] = s_pair;
+    out[1] = s_self;
+    out[2] = s_tail;
+    return 0;
+}
+
+/* phi_s(d1[p], d2[p]) from the same table (for the factorisation check) */
+int oracle_phi_soft(int npts, const double *d1, const double *d2, int nth, double th0, double dth, int nu,
+                    double u0, double du, double dmax, const double *tab, const double *p2, const double *p4,
+                    double ds, double phi0, double casym, double *out)
+{
+    if (npts < 0 || nth < 4 || nu < 4) return -1;
+    soft_table T = {nth, nu, th0, dth, u0, du, dmax, ds, phi0, casym, tab, p2, p4, 0};
+    for (int p = 0; p < npts; ++p) out[p] = phi_soft(&T, d1[p], d2[p]);
+    return 0;
+}
+
