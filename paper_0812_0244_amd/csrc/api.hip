@@ -221,10 +221,10 @@ static int check_grid(vdwnl_ctx *c, const int32_t *shape, const double *cell, in
         return fail(c, VDWNL_E_UNSUPPORTED_SIZE, "N1 * N2 must be even (rows are transformed in pairs)");
     // LDS of each pass as a function of its tile size (twiddles staged in LDS too)
     const size_t stage = (size_t)((kThreads / 64) * (64 / kNQ)) * kTabStride * rs;
-    auto zmain = [&](size_t k3) { return (N1 + (kNQ * k3 + 1) * N1) * cs + 16 + stage + (N1 / 2 + 1) * k3 * sizeof(int); };
-    auto zaux = [&](size_t k3) { return (N1 + (4 * k3 + 2) * N1) * 16; };
+    auto zmain = [&](size_t k3) { return (N1 + kNQ * k3 * (N1 | 1)) * cs + 16 + stage + (N1 / 2 + 1) * k3 * sizeof(int); };
+    auto zaux = [&](size_t k3) { return (N1 + 4 * k3 * (N1 | 1)) * 16; };
     auto xmain = [&](size_t b) { return b * (N3 + 1) * (2 * 16 + (kNQ / 2) * cs) + N3 * (16 + cs) + (kNQ + kNQ * kNQ) * rs; };
-    auto ypass = [&](size_t w, size_t c2) { return (N2 + N2 * (w + 1)) * c2; };
+    auto ypass = [&](size_t w, size_t c2) { return (N2 + (N2 | 1) * w) * c2; };
     const size_t cap = c->lds_cap;
     if (N1 > (size_t)kMaxN1 || zmain(1) > cap)
         return fail(c, VDWNL_E_UNSUPPORTED_SIZE, "N1 too large for the fused axis-1 pass");
@@ -243,21 +243,25 @@ static void size_tiles(const vdwnl_ctx *c, Grid &g) {
     const size_t cs = c->precision == 64 ? 16 : 8, rs = c->precision == 64 ? 8 : 4;
     const size_t N1 = g.s[0], N2 = g.s[1], N3 = g.s[2];
     const size_t stage = (size_t)((kThreads / 64) * (64 / kNQ)) * kTabStride * rs;
-    auto zmain = [&](size_t k3) { return (N1 + (kNQ * k3 + 1) * N1) * cs + 16 + stage + (N1 / 2 + 1) * k3 * sizeof(int); };
-    auto zaux = [&](size_t k3) { return (N1 + (4 * k3 + 2) * N1) * 16; };
+    auto zmain = [&](size_t k3) { return (N1 + kNQ * k3 * (N1 | 1)) * cs + 16 + stage + (N1 / 2 + 1) * k3 * sizeof(int); };
+    auto zaux = [&](size_t k3) { return (N1 + 4 * k3 * (N1 | 1)) * 16; };
     auto xmain = [&](size_t b) { return b * (N3 + 1) * (2 * 16 + (kNQ / 2) * cs) + N3 * (16 + cs) + (kNQ + kNQ * kNQ) * rs; };
-    auto ypass = [&](size_t w, size_t c2) { return (N2 + N2 * (w + 1)) * c2; };
+    auto ypass = [&](size_t w, size_t c2) { return (N2 + (N2 | 1) * w) * c2; };
     // complex elements per LDS FFT tile: bounded for the runtime-radix FFT
     // (its per-thread register arrays), not for the compile-time plans
     auto cap = [](size_t n) { return len_class((int)n) == kLenGeneric ? (size_t)kTileCap : (size_t)1 << 30; };
-    // axis-3 tiles: at most one grid point per thread (the local steps run
-    // one point per thread)
+    // axis-3 tiles of the theta / assembly passes: at most one grid point
+    // per thread (two measured slower: the local chain needs the VGPRs);
+    // of the n-forward / final passes (FP64, one line per row pair): about
+    // 4096 points, enough lines to occupy every lane
     g.bmain = 1;
     while ((size_t)(g.bmain + 1) * N3 <= (size_t)kThreads && (kNQ / 2) * (g.bmain + 1) * N3 <= cap(N3) &&
            xmain(g.bmain + 1) <= c->pref[TG_X])
         ++g.bmain;
     g.bnf = 2;
-    while ((size_t)(g.bnf + 2) * N3 <= (size_t)kThreads) g.bnf += 2;
+    while ((size_t)(g.bnf + 2) * N3 <= 4096 && (size_t)(g.bnf / 2 + 1) * N3 <= cap(N3) &&
+           (N3 + (size_t)(g.bnf / 2 + 1) * (N3 + 1)) * 16 <= kLdsCap)
+        g.bnf += 2;
     g.k3main = 1;
     while (g.k3main < kMaxCols && (size_t)kNQ * (g.k3main + 1) * N1 <= cap(N1) && zmain(g.k3main + 1) <= c->pref[TG_Z])
         ++g.k3main;
@@ -510,15 +514,15 @@ static int prepare_device(vdwnl_ctx *c) {
         switch (k) {
             case KX_NFWD: case KX_FINAL: return (N3 + (g.bnf / 2) * (N3 + 1)) * 16;
             case KX_THETA: case KX_ASSEMBLE: return xm;
-            case KY_1F: case KY_1I: return (N2 + N2 * (g.wy1 + 1)) * 16;
-            case KY_3F: case KY_3I: return (N2 + N2 * (g.wy3 + 1)) * 16;
-            case KY_20F: case KY_20I: return (N2 + N2 * (g.wy20 + 1)) * cs;
+            case KY_1F: case KY_1I: return (N2 + (N2 | 1) * g.wy1) * 16;
+            case KY_3F: case KY_3I: return (N2 + (N2 | 1) * g.wy3) * 16;
+            case KY_20F: case KY_20I: return (N2 + (N2 | 1) * g.wy20) * cs;
             case KZ_MAIN: {
                 const size_t K = std::min(g.k3main, kMaxCols);
-                return (N1 + (size_t)(kNQ * K + 1) * N1) * cs + 16 + (size_t)((kThreads / 64) * (64 / kNQ)) * kTabStride * rs +
+                return (N1 + (size_t)kNQ * K * (N1 | 1)) * cs + 16 + (size_t)((kThreads / 64) * (64 / kNQ)) * kTabStride * rs +
                        (N1 / 2 + 1) * K * sizeof(int);
             }
-            default: return (N1 + (4 * g.k3aux + 2) * N1) * 16;   // KZ_GRAD, KZ_DIV
+            default: return (N1 + 4 * g.k3aux * (N1 | 1)) * 16;   // KZ_GRAD, KZ_DIV
         }
     };
     // the axis whose FFT a pass performs: 3 for the axis-3 passes, 2, 1

@@ -405,7 +405,6 @@ __global__ void __launch_bounds__(kThreads) k_x_final(const InstDev *insts, cons
     const double2 *s1 = reinterpret_cast<const double2 *>(I.spec1) + (size_t)row0 * N3h;
     const int npt = B * N3;
     const gptr<const T> vloc = gld(reinterpret_cast<const T *>(I.vloc) + (size_t)row0 * N3);
-    const T vl_first = threadIdx.x < npt ? vloc[threadIdx.x] : (T)0;
     struct Two { double2 a, b; };
     batched<4>(np * N3, [&](int idx) {
         const int pr = idx / N3, k = idx - pr * N3;
@@ -420,12 +419,11 @@ __global__ void __launch_bounds__(kThreads) k_x_final(const InstDev *insts, cons
     __syncthreads();
     fft_lc<double, 1, LC>(buf, I.p3, np, 1, ls, tw);
     const gptr<T> v = gst(reinterpret_cast<T *>(I.v) + (size_t)row0 * N3);
-    for (int idx = threadIdx.x; idx < npt; idx += kThreads) {
+    batched<4>(npt, [&](int idx) { return vloc[idx]; }, [&](int idx, T vl) {
         const int rb = idx / N3, k = idx - rb * N3;
         const double2 z = buf[(rb >> 1) * ls + k];
-        const T vl = idx == (int)threadIdx.x ? vl_first : vloc[idx];
         v[idx] = (T)((double)vl - ((rb & 1) ? z.y : z.x));
-    }
+    });
 }
 
 // ---------------------------------------------------------------- axis-2 pass
@@ -437,17 +435,17 @@ __global__ void __launch_bounds__(kThreads) k_y(const InstDev *insts, const Tile
     extern __shared__ __align__(16) unsigned char smem[];
     const Tile t = tiles[blockIdx.x];
     const InstDev &I = insts[t.inst];
-    const int N2 = axis_len<LC>(I.n2), W = t.c, es = W | 1;   // odd element stride: no LDS bank conflicts
+    const int N2 = axis_len<LC>(I.n2), W = t.c, lp = N2 | 1;   // lines contiguous, odd pitch
     C2<T> *tw = reinterpret_cast<C2<T> *>(smem);
     C2<T> *buf = tw + N2;
     const size_t rowlen = (size_t)I.n3h * V;
     void *base = which == 0 ? I.spec : (which == 1 ? I.spec3 : I.spec1);
     C2<T> *g = reinterpret_cast<C2<T> *>(base) + (size_t)t.a * N2 * rowlen + t.b;
-    crows_in(buf, es, g, rowlen, N2, W);
+    rows_in_t(buf, lp, g, rowlen, N2, W);
     load_twiddles<T>(tw, I.p2, reinterpret_cast<const C2<T> *>(twv));
     __syncthreads();
-    fft_lc<T, S, LC>(buf, I.p2, W, es, 1, tw);
-    crows_out(g, rowlen, buf, es, N2, W);
+    fft_lc<T, S, LC>(buf, I.p2, W, 1, lp, tw);
+    rows_out_t(g, rowlen, buf, lp, N2, W);
 }
 
 // ---------------------------------------------------------------- axis-1 passes
@@ -460,31 +458,31 @@ __global__ void __launch_bounds__(kThreads) k_z_grad(const InstDev *insts, const
     const Tile t = tiles[blockIdx.x];
     const InstDev &I = insts[t.inst];
     const int N1 = axis_len<LC>(I.n1), N2 = I.n2, N3 = I.n3, N3h = I.n3h, k2 = t.a, k30 = t.b, K3 = t.c;
+    const int lp = N1 | 1;                                   // lines contiguous, odd pitch
     C2<T> *twall = reinterpret_cast<C2<T> *>(smem);
-    const int ei = K3 | 1, eo = (3 * K3) | 1;               // odd element strides
-    C2<T> *bin = twall + N1;
-    C2<T> *bout = bin + N1 * ei;
+    C2<T> *bin = twall + N1;                                 // K3 lines
+    C2<T> *bout = bin + K3 * lp;                             // 3 K3 lines: (w, c) at line 3 w + c
     const C2<T> *gin = reinterpret_cast<const C2<T> *>(I.spec1) + (size_t)k2 * N3h + k30;
     const size_t sin_ = (size_t)N2 * N3h;
-    crows_in(bin, ei, gin, sin_, N1, K3);
+    rows_in_t(bin, lp, gin, sin_, N1, K3);
     load_twiddles<T>(twall, I.p1, reinterpret_cast<const C2<T> *>(twv));
     __syncthreads();
-    fft_lc<T, -1, LC>(bin, I.p1, K3, ei, 1, twall);
+    fft_lc<T, -1, LC>(bin, I.p1, K3, 1, lp, twall);
     const T G2 = (T)(I.g2 * freq_nz(k2, N2));
     for (int idx = threadIdx.x; idx < N1 * K3; idx += kThreads) {
-        const int l = idx / K3, w = idx - l * K3;
-        const C2<T> nh = cscale(bin[l * ei + w], (T)I.inv_n);
+        const int w = idx / N1, l = idx - w * N1;
+        const C2<T> nh = cscale(bin[w * lp + l], (T)I.inv_n);
         const T G1 = (T)(I.g1 * freq_nz(l, N1));
         const T G3 = (T)(I.g3 * freq_nz(k30 + w, N3));
-        C2<T> *o = bout + l * eo + 3 * w;
+        C2<T> *o = bout + 3 * w * lp + l;
         o[0] = mk<T>(-G1 * nh.y, G1 * nh.x);
-        o[1] = mk<T>(-G2 * nh.y, G2 * nh.x);
-        o[2] = mk<T>(-G3 * nh.y, G3 * nh.x);
+        o[lp] = mk<T>(-G2 * nh.y, G2 * nh.x);
+        o[2 * lp] = mk<T>(-G3 * nh.y, G3 * nh.x);
     }
     __syncthreads();
-    fft_lc<T, 1, LC>(bout, I.p1, 3 * K3, eo, 1, twall);
+    fft_lc<T, 1, LC>(bout, I.p1, 3 * K3, 1, lp, twall);
     C2<T> *gout = reinterpret_cast<C2<T> *>(I.spec3) + ((size_t)k2 * N3h + k30) * 3;
-    crows_out(gout, sin_ * 3, bout, eo, N1, 3 * K3);
+    rows_out_t(gout, sin_ * 3, bout, lp, N1, 3 * K3);
 }
 
 // sum_c i G_c w_c / N.  tile: a = k2, b = first k3, c = count
@@ -495,30 +493,30 @@ __global__ void __launch_bounds__(kThreads) k_z_div(const InstDev *insts, const 
     const Tile t = tiles[blockIdx.x];
     const InstDev &I = insts[t.inst];
     const int N1 = axis_len<LC>(I.n1), N2 = I.n2, N3 = I.n3, N3h = I.n3h, k2 = t.a, k30 = t.b, K3 = t.c;
+    const int lp = N1 | 1;                                   // lines contiguous, odd pitch
     C2<T> *twall = reinterpret_cast<C2<T> *>(smem);
-    const int ei = (3 * K3) | 1, eo = K3 | 1;               // odd element strides
-    C2<T> *bin = twall + N1;
-    C2<T> *bout = bin + N1 * ei;
+    C2<T> *bin = twall + N1;                                 // 3 K3 lines: (w, c) at line 3 w + c
+    C2<T> *bout = bin + 3 * K3 * lp;                         // K3 lines
     const size_t sin_ = (size_t)N2 * N3h;
     const C2<T> *gin = reinterpret_cast<const C2<T> *>(I.spec3) + ((size_t)k2 * N3h + k30) * 3;
-    crows_in(bin, ei, gin, sin_ * 3, N1, 3 * K3);
+    rows_in_t(bin, lp, gin, sin_ * 3, N1, 3 * K3);
     load_twiddles<T>(twall, I.p1, reinterpret_cast<const C2<T> *>(twv));
     __syncthreads();
-    fft_lc<T, -1, LC>(bin, I.p1, 3 * K3, ei, 1, twall);
+    fft_lc<T, -1, LC>(bin, I.p1, 3 * K3, 1, lp, twall);
     const T G2 = (T)(I.g2 * freq_nz(k2, N2));
     for (int idx = threadIdx.x; idx < N1 * K3; idx += kThreads) {
-        const int l = idx / K3, w = idx - l * K3;
-        const C2<T> *x = bin + l * ei + 3 * w;
+        const int w = idx / N1, l = idx - w * N1;
+        const C2<T> *x = bin + 3 * w * lp + l;
         const T G1 = (T)(I.g1 * freq_nz(l, N1));
         const T G3 = (T)(I.g3 * freq_nz(k30 + w, N3));
-        const T sx = G1 * x[0].x + G2 * x[1].x + G3 * x[2].x;
-        const T sy = G1 * x[0].y + G2 * x[1].y + G3 * x[2].y;
-        bout[l * eo + w] = cscale(mk<T>(-sy, sx), (T)I.inv_n);
+        const T sx = G1 * x[0].x + G2 * x[lp].x + G3 * x[2 * lp].x;
+        const T sy = G1 * x[0].y + G2 * x[lp].y + G3 * x[2 * lp].y;
+        bout[w * lp + l] = cscale(mk<T>(-sy, sx), (T)I.inv_n);
     }
     __syncthreads();
-    fft_lc<T, 1, LC>(bout, I.p1, K3, eo, 1, twall);
+    fft_lc<T, 1, LC>(bout, I.p1, K3, 1, lp, twall);
     C2<T> *gout = reinterpret_cast<C2<T> *>(I.spec1) + (size_t)k2 * N3h + k30;
-    crows_out(gout, sin_, bout, eo, N1, K3);
+    rows_out_t(gout, sin_, bout, lp, N1, K3);
 }
 
 // Forward axis-1 FFT of the 20 theta spectra, u_a(G) = sum_b phi_ab(|G|) c_b(G)
@@ -545,12 +543,12 @@ __global__ void __launch_bounds__(kThreads) k_z_main(const InstDev *insts, const
     const Tile t = tiles[blockIdx.x];
     const InstDev &I = insts[t.inst];
     const int N1 = axis_len<LC>(I.n1), N2 = I.n2, N3 = I.n3, N3h = I.n3h, P = t.b, CP = t.c, K = P * CP;
-    const int W = K * kNQ, es = W | 1;                       // odd element stride
+    const int W = K * kNQ, lp = N1 | 1;                      // W lines, contiguous, odd pitch
     __shared__ int colbase[kMaxCols];                         // offset of each column in a k1 plane
     __shared__ int colk3[kMaxCols];
     C2<T> *twall = reinterpret_cast<C2<T> *>(smem);
     C2<T> *buf = twall + N1;
-    const size_t stage_off = ((size_t)(N1 + N1 * es) * sizeof(C2<T>) + 15) & ~(size_t)15;
+    const size_t stage_off = ((size_t)(N1 + W * lp) * sizeof(C2<T>) + 15) & ~(size_t)15;
     T *stage = reinterpret_cast<T *>(smem + stage_off);       // [kGroups][kTabStride], 16-byte aligned
     if (threadIdx.x < K) {
         const int2 cw = cols[t.a + threadIdx.x];
@@ -574,7 +572,7 @@ __global__ void __launch_bounds__(kThreads) k_z_main(const InstDev *insts, const
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
                 const int w = cur.w / kCpc, e = cur.w - w * kCpc;
-                lo[u] = base + u * kThreads < total ? cur.l * es + w * kNQ + e * kEpc : -1;
+                lo[u] = base + u * kThreads < total ? (w * kNQ + e * kEpc) * lp + cur.l : -1;
                 go[u] = (size_t)cur.l * plane + colbase[w] + e * kEpc;
                 if (in && lo[u] >= 0) {
                     if constexpr (kEpc == 2) {
@@ -592,9 +590,9 @@ __global__ void __launch_bounds__(kThreads) k_z_main(const InstDev *insts, const
                 if (lo[u] < 0) continue;
                 if (in) {
                     buf[lo[u]] = mk<T>(ra[u], rb[u]);
-                    if constexpr (kEpc == 2) buf[lo[u] + 1] = mk<T>(rc[u], rd[u]);
+                    if constexpr (kEpc == 2) buf[lo[u] + lp] = mk<T>(rc[u], rd[u]);
                 } else if constexpr (kEpc == 2) {
-                    const C2<T> p0 = buf[lo[u]], p1 = buf[lo[u] + 1];
+                    const C2<T> p0 = buf[lo[u]], p1 = buf[lo[u] + lp];
                     gst(reinterpret_cast<float4 *>(spec + go[u]))[0] = make_float4(p0.x, p0.y, p1.x, p1.y);
                 } else {
                     gst(spec + go[u])[0] = buf[lo[u]];
@@ -660,7 +658,7 @@ __global__ void __launch_bounds__(kThreads) k_z_main(const InstDev *insts, const
     __syncthreads();
     if (lane_on && gid < nitems) VDWNL_FETCH_ROW(a, sidx[gid]);
     if (lane_on && gid + kGroups < nitems) VDWNL_FETCH_ROW(b, sidx[gid + kGroups]);
-    fft_lc<T, -1, LC>(buf, I.p1, W, es, 1, twall);
+    fft_lc<T, -1, LC>(buf, I.p1, W, 1, lp, twall);
 
     T *st = stage + (size_t)(lane_on ? gid : 0) * kTabStride;
     const T inv_n = (T)I.inv_n;
@@ -677,29 +675,29 @@ __global__ void __launch_bounds__(kThreads) k_z_main(const InstDev *insts, const
         }
         const int m1 = it / P, pr = it - m1 * P;
         const int l = m1;
-        int lp = N1 - m1;
-        if (m1 == 0 || lp == m1) lp = -1;     // k1 = 0 and the Nyquist plane stand alone
+        int lq = N1 - m1;
+        if (m1 == 0 || lq == m1) lq = -1;     // k1 = 0 and the Nyquist plane stand alone
         for (int w = pr * CP; w < (pr + 1) * CP; ++w) {
             C2<T> u1 = mk<T>((T)0, (T)0), u2 = u1;
-            C2<T> *x1 = buf + l * es + w * kNQ;
-            C2<T> *x2 = buf + (lp >= 0 ? lp : l) * es + w * kNQ;
+            C2<T> *x1 = buf + w * kNQ * lp + l;                   // component b at x1[b lp]
+            C2<T> *x2 = buf + w * kNQ * lp + (lq >= 0 ? lq : l);
 #pragma unroll
             for (int b = 0; b < kNQ; ++b) {
-                const C2<T> t1 = x1[b], t2 = x2[b];
+                const C2<T> t1 = x1[b * lp], t2 = x2[b * lp];
                 u1.x += f[b] * t1.x;
                 u1.y += f[b] * t1.y;
                 u2.x += f[b] * t2.x;
                 u2.y += f[b] * t2.y;
             }
-            const C2<T> own1 = x1[al], own2 = x2[al];
+            const C2<T> own1 = x1[al * lp], own2 = x2[al * lp];
             const int k3 = colk3[w];
             const bool edge = (k3 == 0) || ((N3 & 1) == 0 && k3 == N3 / 2);
             const double wgt = edge ? wn : 2.0 * wn;
             e += wgt * (double)(own1.x * u1.x + own1.y * u1.y);
-            if (lp >= 0) e += wgt * (double)(own2.x * u2.x + own2.y * u2.y);
+            if (lq >= 0) e += wgt * (double)(own2.x * u2.x + own2.y * u2.y);
             wave_sync();
-            x1[al] = cscale(u1, inv_n);
-            if (lp >= 0) x2[al] = cscale(u2, inv_n);
+            x1[al * lp] = cscale(u1, inv_n);
+            if (lq >= 0) x2[al * lp] = cscale(u2, inv_n);
             wave_sync();
         }
     };
@@ -720,7 +718,7 @@ __global__ void __launch_bounds__(kThreads) k_z_main(const InstDev *insts, const
         }
     }
     __syncthreads();
-    fft_lc<T, 1, LC>(buf, I.p1, W, es, 1, twall);
+    fft_lc<T, 1, LC>(buf, I.p1, W, 1, lp, twall);
     io(false);
     const double sum = block_sum(e);
     if (threadIdx.x == 0) I.part_ek[t.slot] = sum;

@@ -139,6 +139,128 @@ __device__ __forceinline__ void rows_out_c(float2 *__restrict__ g, size_t gstr, 
     }
 }
 
+// Transposed copies: global rows l < nrows of W contiguous elements go to
+// LDS lines w < W with element l at lds[w * lpitch + l] (lines contiguous, for
+// FFTs along l with unit element stride).
+template <int U = kUnroll>
+__device__ __forceinline__ void rows_in_t(float2 *lds, int lpitch, const float2 *__restrict__ g, size_t gstr,
+                                          int nrows, int W) {
+    if (!pairable(g, gstr, W)) {
+        const int total = nrows * W;
+        RowCursor cur(threadIdx.x, W);
+        for (int base = threadIdx.x; base < total; base += U * kThreads) {
+            float rx[U], ry[U];
+            int o[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const bool on = base + u * kThreads < total;
+                if (on) {
+                    const float2 v = gld(g)[(size_t)cur.l * gstr + cur.w];
+                    rx[u] = v.x;
+                    ry[u] = v.y;
+                }
+                o[u] = on ? cur.w * lpitch + cur.l : -1;
+                cur.step();
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (o[u] >= 0) lds[o[u]] = make_float2(rx[u], ry[u]);
+        }
+        return;
+    }
+    const int Wp = W / 2, total = nrows * Wp;
+    const float4 *gp = reinterpret_cast<const float4 *>(g);
+    const size_t gp_str = gstr / 2;
+    RowCursor cur(threadIdx.x, Wp);
+    for (int base = threadIdx.x; base < total; base += U * kThreads) {
+        float4 r[U];
+        int o[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const bool on = base + u * kThreads < total;
+            if (on) r[u] = gld(gp)[(size_t)cur.l * gp_str + cur.w];
+            o[u] = on ? 2 * cur.w * lpitch + cur.l : -1;
+            cur.step();
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (o[u] >= 0) {
+                lds[o[u]] = make_float2(r[u].x, r[u].y);
+                lds[o[u] + lpitch] = make_float2(r[u].z, r[u].w);
+            }
+    }
+}
+
+template <int U = kUnroll>
+__device__ __forceinline__ void rows_out_t(float2 *__restrict__ g, size_t gstr, const float2 *lds, int lpitch,
+                                           int nrows, int W) {
+    if (!pairable(g, gstr, W)) {
+        const int total = nrows * W;
+        RowCursor cur(threadIdx.x, W);
+        for (int base = threadIdx.x; base < total; base += U * kThreads) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (base + u * kThreads < total) gst(g)[(size_t)cur.l * gstr + cur.w] = lds[cur.w * lpitch + cur.l];
+                cur.step();
+            }
+        }
+        return;
+    }
+    const int Wp = W / 2, total = nrows * Wp;
+    float4 *gp = reinterpret_cast<float4 *>(g);
+    const size_t gp_str = gstr / 2;
+    RowCursor cur(threadIdx.x, Wp);
+    for (int base = threadIdx.x; base < total; base += U * kThreads) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (base + u * kThreads < total) {
+                const float2 a = lds[2 * cur.w * lpitch + cur.l], b = lds[(2 * cur.w + 1) * lpitch + cur.l];
+                gst(gp)[(size_t)cur.l * gp_str + cur.w] = make_float4(a.x, a.y, b.x, b.y);
+            }
+            cur.step();
+        }
+    }
+}
+
+template <int U = kUnroll>
+__device__ __forceinline__ void rows_in_t(double2 *lds, int lpitch, const double2 *__restrict__ g, size_t gstr,
+                                          int nrows, int W) {
+    const int total = nrows * W;
+    RowCursor cur(threadIdx.x, W);
+    for (int base = threadIdx.x; base < total; base += U * kThreads) {
+        double rx[U], ry[U];
+        int o[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const bool on = base + u * kThreads < total;
+            if (on) {
+                const double2 v = gld(g)[(size_t)cur.l * gstr + cur.w];
+                rx[u] = v.x;
+                ry[u] = v.y;
+            }
+            o[u] = on ? cur.w * lpitch + cur.l : -1;
+            cur.step();
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (o[u] >= 0) lds[o[u]] = make_double2(rx[u], ry[u]);
+    }
+}
+
+template <int U = kUnroll>
+__device__ __forceinline__ void rows_out_t(double2 *__restrict__ g, size_t gstr, const double2 *lds, int lpitch,
+                                           int nrows, int W) {
+    const int total = nrows * W;
+    RowCursor cur(threadIdx.x, W);
+    for (int base = threadIdx.x; base < total; base += U * kThreads) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (base + u * kThreads < total) gst(g)[(size_t)cur.l * gstr + cur.w] = lds[cur.w * lpitch + cur.l];
+            cur.step();
+        }
+    }
+}
+
 // Complex rows of either precision (FP64 complex is already 16 bytes).
 __device__ __forceinline__ void crows_in(float2 *lds, int lstr, const float2 *g, size_t gstr, int nrows, int W) {
     rows_in_c(lds, lstr, g, gstr, nrows, W);
