@@ -223,7 +223,7 @@ static int check_grid(vdwnl_ctx *c, const int32_t *shape, const double *cell, in
     const size_t stage = (size_t)((kThreads / 64) * (64 / kNQ)) * kTabStride * rs;
     auto zmain = [&](size_t k3) { return (N1 + kNQ * k3 * (N1 | 1)) * cs + 16 + stage + (N1 / 2 + 1) * k3 * sizeof(int); };
     auto zaux = [&](size_t k3) { return (N1 + 4 * k3 * (N1 | 1)) * 16; };
-    auto xmain = [&](size_t b) { return b * (N3 + 1) * (2 * 16 + (kNQ / 2) * cs) + N3 * (16 + cs) + (kNQ + kNQ * kNQ) * rs; };
+    auto xmain = [&](size_t b) { return b * (N3 + 1) * (2 * 16 + (kNQ / 2) * cs) + N3 * (16 + cs) + (kNQ + kNQ * kNQ) * rs + (kMaxMc + 1) * 8; };
     auto ypass = [&](size_t w, size_t c2) { return (N2 + (N2 | 1) * w) * c2; };
     const size_t cap = c->lds_cap;
     if (N1 > (size_t)kMaxN1 || zmain(1) > cap)
@@ -245,7 +245,7 @@ static void size_tiles(const vdwnl_ctx *c, Grid &g) {
     const size_t stage = (size_t)((kThreads / 64) * (64 / kNQ)) * kTabStride * rs;
     auto zmain = [&](size_t k3) { return (N1 + kNQ * k3 * (N1 | 1)) * cs + 16 + stage + (N1 / 2 + 1) * k3 * sizeof(int); };
     auto zaux = [&](size_t k3) { return (N1 + 4 * k3 * (N1 | 1)) * 16; };
-    auto xmain = [&](size_t b) { return b * (N3 + 1) * (2 * 16 + (kNQ / 2) * cs) + N3 * (16 + cs) + (kNQ + kNQ * kNQ) * rs; };
+    auto xmain = [&](size_t b) { return b * (N3 + 1) * (2 * 16 + (kNQ / 2) * cs) + N3 * (16 + cs) + (kNQ + kNQ * kNQ) * rs + (kMaxMc + 1) * 8; };
     auto ypass = [&](size_t w, size_t c2) { return (N2 + (N2 | 1) * w) * c2; };
     // complex elements per LDS FFT tile: bounded for the runtime-radix FFT
     // (its per-thread register arrays), not for the compile-time plans
@@ -510,7 +510,8 @@ static int prepare_device(vdwnl_ctx *c) {
     // LDS of one tile of each pass for grid g
     auto lds_of = [&](int k, const Grid &g) -> size_t {
         const size_t N1 = g.s[0], N2 = g.s[1], N3 = g.s[2];
-        const size_t xm = g.bmain * (N3 + 1) * (2 * 16 + (kNQ / 2) * cs) + N3 * (16 + cs) + (kNQ + kNQ * kNQ) * rs;
+        const size_t xm = g.bmain * (N3 + 1) * (2 * 16 + (kNQ / 2) * cs) + N3 * (16 + cs) + (kNQ + kNQ * kNQ) * rs +
+                          (kMaxMc + 1) * 8;
         switch (k) {
             case KX_NFWD: case KX_FINAL: return (N3 + (g.bnf / 2) * (N3 + 1)) * 16;
             case KX_THETA: case KX_ASSEMBLE: return xm;
@@ -814,7 +815,7 @@ int vdwnl_set_kernel_table(vdwnl_ctx *ctx, int32_t nq, const double *qmesh, doub
     if (!ctx) return VDWNL_E_ARG;
     if (!qmesh || !phi) return fail(ctx, VDWNL_E_ARG, "null table pointer");
     if (nq != kNQ) return fail(ctx, VDWNL_E_TABLE, "nq must be 20");
-    if (m_c < 1 || m_c > 64) return fail(ctx, VDWNL_E_TABLE, "m_c must be in 1..64");
+    if (m_c < 1 || m_c > kMaxMc) return fail(ctx, VDWNL_E_TABLE, "m_c must be in 1..64");
     if (nk < 4 || !(dk > 0.0) || !std::isfinite(dk)) return fail(ctx, VDWNL_E_TABLE, "bad radial mesh");
     if (!(q_c > 0.0) || !std::isfinite(c_soft)) return fail(ctx, VDWNL_E_TABLE, "bad q_c or C_s");
     for (int i = 0; i < nq; ++i) {
@@ -855,6 +856,7 @@ int vdwnl_set_kernel_table(vdwnl_ctx *ctx, int32_t nq, const double *qmesh, doub
         for (int j = 0; j < nq; ++j) k.M[j * kNQ + a] = d2[j];
     }
     for (int j = 0; j < nq; ++j) k.q[j] = qmesh[j];
+    for (int m = 1; m <= kMaxMc; ++m) k.invm[m] = 1.0 / (double)m;
     ctx->have_table = true;
     free_device(ctx);
     return check_krange(ctx);

@@ -14,7 +14,8 @@ constexpr int kThreads = 256;                    // threads per workgroup, every
 constexpr int kTileCap = 4096;                   // complex elements of one LDS FFT tile
 constexpr int kLdsCap = 65536;                   // bytes of LDS one workgroup may take
 constexpr int kMaxStages = 16;
-constexpr int kMaxCols = 16;                     // (k2, k3) columns per fused axis-1 tile
+constexpr int kMaxCols = 16;
+constexpr int kMaxMc = 64;                       // largest m_c of Eq. (Sat)                     // (k2, k3) columns per fused axis-1 tile
 constexpr int kMaxN1 = 204;                      // 20 N1 <= kTileCap (fused axis-1 pass)
 constexpr int kMaxN3 = 340;                      // 12 N3 complex doubles <= kLdsCap
 
@@ -60,6 +61,7 @@ struct Consts {
     int nq;
     double q[kNQ];           // q mesh
     double M[kNQ * kNQ];     // M[j][a]: second derivative at q_j of the cardinal spline p_a
+    double invm[kMaxMc + 1]; // 1/m, m <= m_c (coefficients of the saturation series)
 };
 
 // One workgroup's work item; the meaning of a, b, c depends on the pass.

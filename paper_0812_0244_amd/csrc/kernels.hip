@@ -29,6 +29,10 @@ template <> __device__ __forceinline__ double dev_cbrt(double x) { return cbrt(x
 template <typename T> __device__ __forceinline__ T dev_sqrt(T x);
 template <> __device__ __forceinline__ float dev_sqrt(float x) { return sqrtf(x); }
 template <> __device__ __forceinline__ double dev_sqrt(double x) { return sqrt(x); }
+// 1/x: the hardware reciprocal in FP32 (within 1 ulp), a division in FP64
+template <typename T> __device__ __forceinline__ T rcp(T x);
+template <> __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+template <> __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
 template <typename T> __device__ __forceinline__ T dev_log1p(T x);
 template <> __device__ __forceinline__ float dev_log1p(float x) { return log1pf(x); }
 template <> __device__ __forceinline__ double dev_log1p(double x) { return log1p(x); }
@@ -63,27 +67,29 @@ template <typename T, bool DERIV>
 struct LocalQ {
     T q0, Q, dqdn, dqds;
 
-    __device__ __forceinline__ void eval(T n, T sigma, double qc, int mc) {
+    __device__ __forceinline__ void eval(T n, T sigma, double qc, int mc, const double *invm) {
         const T pi = (T)3.14159265358979323846;
         const T A = (T)0.031091, a1 = (T)0.21370;
         const T b1 = (T)7.5957, b2 = (T)3.5876, b3 = (T)1.6382, b4 = (T)0.49294;
         const T zg = (T)(0.8491 / 36.0);   // -Z_ab / 36
         // k_F = (3 pi^2 n)^(1/3), r_s = (3 / (4 pi n))^(1/3): one cube root
-        const T cn = dev_cbrt<T>(n);
+        const T cn = dev_cbrt<T>(n), icn = rcp<T>(cn), in = rcp<T>(n);
         const T kf = (T)3.0936677262801355 * cn;          // (3 pi^2)^(1/3)
-        const T rs = (T)0.6203504908994001 / cn;          // (3 / (4 pi))^(1/3)
+        const T rs = (T)0.6203504908994001 * icn;         // (3 / (4 pi))^(1/3)
         const T srs = dev_sqrt<T>(rs);
         const T P = b1 * srs + b2 * rs + b3 * rs * srs + b4 * rs * rs;
-        const T L = dev_log1p<T>((T)1 / ((T)2 * A * P));
+        const T iP2A = rcp<T>((T)2 * A * P);
+        const T L = dev_log1p<T>(iP2A);
         const T eps = (T)-2 * A * ((T)1 + a1 * rs) * L;
-        const T grad_term = zg * sigma / (kf * n * n);
+        const T ikfn2 = rcp<T>(kf) * in * in;             // 1 / (k_F n^2)
+        const T grad_term = zg * sigma * ikfn2;
         const T qraw = kf - ((T)4 * pi / (T)3) * eps + grad_term;
         if (DERIV) {
-            const T dP = (T)0.5 * b1 / srs + b2 + (T)1.5 * b3 * srs + (T)2 * b4 * rs;
-            const T deps_drs = (T)-2 * A * a1 * L + (T)2 * A * ((T)1 + a1 * rs) * dP / (P * ((T)2 * A * P + (T)1));
-            const T deps_dn = deps_drs * (-rs / ((T)3 * n));
-            dqdn = kf / ((T)3 * n) - ((T)4 * pi / (T)3) * deps_dn - ((T)7 / (T)3) * grad_term / n;
-            dqds = zg / (kf * n * n);
+            const T dP = (T)0.5 * b1 * rcp<T>(srs) + b2 + (T)1.5 * b3 * srs + (T)2 * b4 * rs;
+            const T deps_drs = (T)-2 * A * a1 * L + (T)2 * A * ((T)1 + a1 * rs) * dP * rcp<T>(P * ((T)2 * A * P + (T)1));
+            const T deps_dn = deps_drs * (-rs * in * ((T)1 / (T)3));
+            dqdn = kf * in * ((T)1 / (T)3) - ((T)4 * pi / (T)3) * deps_dn - ((T)7 / (T)3) * grad_term * in;
+            dqds = zg * ikfn2;
         }
         // h(x, x_c) = x_c (1 - exp(-sum_{m<=m_c} (x/x_c)^m / m)), dh/dx = exp(-S) sum_{m<m_c} (x/x_c)^m
         const double y = (double)qraw / qc;
@@ -93,7 +99,7 @@ struct LocalQ {
             return;
         }
         double S = 0.0;
-        for (int m = mc; m >= 1; --m) S = S * y + 1.0 / (double)m;
+        for (int m = mc; m >= 1; --m) S = S * y + invm[m];
         S *= y;
         if (S > 700.0) {
             q0 = (T)qc;
@@ -137,7 +143,7 @@ struct SplineW {
         }
         j = lo;
         const T ql = qm[lo], qh = qm[lo + 1];
-        const T h = qh - ql, ih = (T)1 / h;
+        const T h = qh - ql, ih = rcp<T>(h);
         const T a = below ? (T)1 : (qh - q0) * ih;
         const T b = (T)1 - a;
         const T dq = below ? q0 - ql : (T)0;
@@ -153,9 +159,10 @@ struct SplineW {
 };
 
 template <typename T>
-__device__ __forceinline__ void load_consts(const Consts *cst, T *qm, T *Mm) {
+__device__ __forceinline__ void load_consts(const Consts *cst, T *qm, T *Mm, double *invm) {
     for (int i = threadIdx.x; i < kNQ; i += kThreads) qm[i] = (T)cst->q[i];
     for (int i = threadIdx.x; i < kNQ * kNQ; i += kThreads) Mm[i] = (T)cst->M[i];
+    for (int i = threadIdx.x; i <= kMaxMc; i += kThreads) invm[i] = cst->invm[i];
 }
 
 // ---------------------------------------------------------------- axis-3 passes
@@ -210,6 +217,7 @@ __global__ void __launch_bounds__(kThreads) k_x_theta(const InstDev *insts, cons
     C2<T> *tw = r2 + kNQ / 2 * B * ls;                       // twiddles in T
     T *qm = reinterpret_cast<T *>(tw + N3);
     T *Mm = qm + kNQ;
+    double *invm = reinterpret_cast<double *>(Mm + kNQ * kNQ);   // 8-byte aligned: every part before is
     // density of this thread's first point, fetched first (used after the FFT)
     const int npt = B * N3;
     const gptr<const T> nin = gld(reinterpret_cast<const T *>(I.n) + (size_t)row0 * N3);
@@ -228,7 +236,7 @@ __global__ void __launch_bounds__(kThreads) k_x_theta(const InstDev *insts, cons
         r1[(2 * rb) * ls + k] = mk<double>(y.a.x - y.b.y, y.a.y + y.b.x);
         r1[(2 * rb + 1) * ls + k] = y.c;
     });
-    load_consts<T>(cst, qm, Mm);
+    load_consts<T>(cst, qm, Mm, invm);
     load_twiddles<double>(twd, I.p3, reinterpret_cast<const double2 *>(twdv));
     load_twiddles<T>(tw, I.p3, reinterpret_cast<const C2<T> *>(twv));
     __syncthreads();
@@ -250,7 +258,7 @@ __global__ void __launch_bounds__(kThreads) k_x_theta(const InstDev *insts, cons
         T *th = reinterpret_cast<T *>(r2 + (size_t)(kNQ / 2 * rb) * ls);   // pair line m at th + 2 m ls
         if (nv >= (T)c_nmin) {
             LocalQ<T, false> lq;
-            lq.eval(nv, g01.x * g01.x + g01.y * g01.y + g2.x * g2.x, c_qc, c_mc);
+            lq.eval(nv, g01.x * g01.x + g01.y * g01.y + g2.x * g2.x, c_qc, c_mc, invm);
             SplineW<T> sw;
             sw.locate(lq.q0, qm, kNQ);
             const T *Mj = Mm + sw.j * kNQ;
@@ -262,8 +270,8 @@ __global__ void __launch_bounds__(kThreads) k_x_theta(const InstDev *insts, cons
                 v += (al == sw.j + 1) ? nA1 : (T)0;
                 th[2 * ((al >> 1) * ls + k) + (al & 1)] = v;
             }
-            const T q3 = lq.q0 * lq.q0 * lq.q0;
-            de += (double)((T)c_cs * nv * nv / q3);
+            const T iq = rcp<T>(lq.q0);
+            de += (double)((T)c_cs * nv * nv * iq * iq * iq);
         } else {
 #pragma unroll 4
             for (int al = 0; al < kNQ; ++al) th[2 * ((al >> 1) * ls + k) + (al & 1)] = (T)0;
@@ -272,16 +280,19 @@ __global__ void __launch_bounds__(kThreads) k_x_theta(const InstDev *insts, cons
     __syncthreads();
     fft_lc<T, -1, LC>(r2, I.p3, kNQ / 2 * B, 1, ls, tw);
 
+    // pair line m of row rb holds theta_{2m} + i theta_{2m+1}: its values at
+    // k and N3 - k give both spectra at k, written together
     C2<T> *out = reinterpret_cast<C2<T> *>(I.spec) + (size_t)row0 * N3h * kNQ;
-    for (int idx = threadIdx.x; idx < B * N3h * kNQ; idx += kThreads) {
-        const int al = idx % kNQ, rest = idx / kNQ;
+    for (int idx = threadIdx.x; idx < B * N3h * (kNQ / 2); idx += kThreads) {
+        const int m = idx % (kNQ / 2), rest = idx / (kNQ / 2);
         const int k = rest % N3h, rb = rest / N3h;
-        const C2<T> *Z = r2 + (kNQ / 2 * rb + (al >> 1)) * ls;
-        const C2<T> z = Z[k], zc = cconj(Z[(N3 - k) % N3]);
-        C2<T> y;
-        if ((al & 1) == 0) y = mk<T>((z.x + zc.x) * (T)0.5, (z.y + zc.y) * (T)0.5);
-        else y = mk<T>((z.y - zc.y) * (T)0.5, -(z.x - zc.x) * (T)0.5);
-        out[idx] = y;
+        const C2<T> *Z = r2 + (kNQ / 2 * rb + m) * ls;
+        const C2<T> z = Z[k], zc = cconj(Z[k == 0 ? 0 : N3 - k]);
+        const T ex = (z.x + zc.x) * (T)0.5, ey = (z.y + zc.y) * (T)0.5;
+        const T ox = (z.y - zc.y) * (T)0.5, oy = -(z.x - zc.x) * (T)0.5;
+        C2<T> *o = out + (size_t)(rb * N3h + k) * kNQ + 2 * m;
+        if constexpr (sizeof(T) == 4) gst(reinterpret_cast<float4 *>(o))[0] = make_float4(ex, ey, ox, oy);
+        else { gst(o)[0] = mk<T>(ex, ey); gst(o)[1] = mk<T>(ox, oy); }
     }
     const double s = block_sum(de);
     if (threadIdx.x == 0) I.part_de[t.slot] = s;
@@ -304,6 +315,7 @@ __global__ void __launch_bounds__(kThreads) k_x_assemble(const InstDev *insts, c
     C2<T> *tw = r2 + kNQ / 2 * B * ls;                       // twiddles in T
     T *qm = reinterpret_cast<T *>(tw + N3);
     T *Mm = qm + kNQ;
+    double *invm = reinterpret_cast<double *>(Mm + kNQ * kNQ);   // 8-byte aligned: every part before is
     // n and grad n of this thread's first point, fetched first (used after the FFT)
     const int npt = B * N3;
     const size_t p0 = (size_t)row0 * N3;
@@ -317,20 +329,22 @@ __global__ void __launch_bounds__(kThreads) k_x_assemble(const InstDev *insts, c
         gz_f = grad[2 * N + threadIdx.x];
     }
     const C2<T> *sp = reinterpret_cast<const C2<T> *>(I.spec) + (size_t)row0 * N3h * kNQ;
+    // u_{2m} + i u_{2m+1} on pair line m: from the spectra at k (< N3/2 + 1)
+    // both the value at k and, by Hermitian symmetry, the value at N3 - k
     struct Two { C2<T> a, b; };
-    batched<4>(B * N3 * (kNQ / 2), [&](int idx) {
+    batched<4>(B * N3h * (kNQ / 2), [&](int idx) {
         const int m = idx % (kNQ / 2), rest = idx / (kNQ / 2);
-        const int k = rest % N3, rb = rest / N3;
-        const int kk = k >= N3h ? N3 - k : k;
-        const gptr<const C2<T>> g = gld(sp + ((size_t)rb * N3h + kk) * kNQ + 2 * m);
+        const int k = rest % N3h, rb = rest / N3h;
+        const gptr<const C2<T>> g = gld(sp + ((size_t)rb * N3h + k) * kNQ + 2 * m);
         return Two{g[0], g[1]};
     }, [&](int idx, Two y) {
         const int m = idx % (kNQ / 2), rest = idx / (kNQ / 2);
-        const int k = rest % N3, rb = rest / N3;
-        if (k >= N3h) { y.a = cconj(y.a); y.b = cconj(y.b); }
-        r2[(kNQ / 2 * rb + m) * ls + k] = mk<T>(y.a.x - y.b.y, y.a.y + y.b.x);
+        const int k = rest % N3h, rb = rest / N3h;
+        C2<T> *line = r2 + (kNQ / 2 * rb + m) * ls;
+        line[k] = mk<T>(y.a.x - y.b.y, y.a.y + y.b.x);
+        if (k != 0 && 2 * k != N3) line[N3 - k] = mk<T>(y.a.x + y.b.y, -y.a.y + y.b.x);   // conj(a) + i conj(b)
     });
-    load_consts<T>(cst, qm, Mm);
+    load_consts<T>(cst, qm, Mm, invm);
     load_twiddles<double>(twd, I.p3, reinterpret_cast<const double2 *>(twdv));
     load_twiddles<T>(tw, I.p3, reinterpret_cast<const C2<T> *>(twv));
     __syncthreads();
@@ -347,7 +361,7 @@ __global__ void __launch_bounds__(kThreads) k_x_assemble(const InstDev *insts, c
         T vl = (T)0, gs = (T)0;
         if (nv >= (T)c_nmin) {
             LocalQ<T, true> lq;
-            lq.eval(nv, gx * gx + gy * gy + gz * gz, c_qc, c_mc);
+            lq.eval(nv, gx * gx + gy * gy + gz * gz, c_qc, c_mc, invm);
             SplineW<T> sw;
             sw.locate(lq.q0, qm, kNQ);
             const T *u = reinterpret_cast<const T *>(r2 + (size_t)(kNQ / 2 * rb) * ls);
@@ -367,7 +381,7 @@ __global__ void __launch_bounds__(kThreads) k_x_assemble(const InstDev *insts, c
             const T sdu = sw.B0 * uj + sw.B1 * uj1 + sw.D0 * S0 + sw.D1 * S1;
             // dtheta_a/dn = p_a + n p'_a Q dq/dn ; dtheta_a/dgrad n = 2 n p'_a Q dq/dsigma grad n
             const T q0 = lq.q0, cs = (T)c_cs;
-            const T iq3 = (T)1 / (q0 * q0 * q0), iq4 = iq3 / q0;
+            const T iq = rcp<T>(q0), iq3 = iq * iq * iq, iq4 = iq3 * iq;
             vl = su + cn * sdu + (T)2 * cs * nv * iq3 - (T)3 * cs * nv * nv * iq4 * lq.Q * lq.dqdn;
             gs = (T)2 * nv * lq.Q * lq.dqds * sdu - (T)6 * cs * nv * nv * iq4 * lq.Q * lq.dqds;
         }
