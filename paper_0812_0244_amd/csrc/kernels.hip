@@ -575,41 +575,57 @@ __global__ void __launch_bounds__(kThreads) k_z_main(const InstDev *insts, const
     C2<T> *spec = reinterpret_cast<C2<T> *>(I.spec);
     // 16-byte chunks (l, w, e): plane l, column w, chunk e of the column's 20 values
     constexpr int kCpc = kNQ / kEpc;                          // chunks per column
+    // 16-byte chunks (l, w, e): plane l, column w, chunk e of the column's 20
+    // values.  Each thread keeps one chunk column (w, e) and steps through the
+    // planes; the loads of kUnroll planes are issued before their stores.
     auto io = [&](bool in) {
-        const int total = N1 * K * kCpc;
-        RowCursor cur(threadIdx.x, K * kCpc);
-        for (int base = threadIdx.x; base < total; base += kUnroll * kThreads) {
-            // held as scalar components (arrays of vector types would go to scratch)
+        const int C = K * kCpc;                               // chunks per plane
+        if (C > kThreads) {                                   // (only tiny N1 with many columns)
+            const int total = N1 * C;
+            for (int i = threadIdx.x; i < total; i += kThreads) {
+                const int l = i / C, c = i - l * C, w = c / kCpc, e = c - w * kCpc;
+                C2<T> *lb = buf + (w * kNQ + e * kEpc) * lp + l;
+                C2<T> *gb = spec + (size_t)l * plane + colbase[w] + e * kEpc;
+#pragma unroll
+                for (int q = 0; q < kEpc; ++q) {
+                    if (in) lb[q * lp] = gld(gb)[q];
+                    else gst(gb)[q] = lb[q * lp];
+                }
+            }
+            return;
+        }
+        const int rps = kThreads / C;                         // planes per step
+        if ((int)threadIdx.x >= rps * C) return;
+        const int r0 = threadIdx.x / C, c = threadIdx.x - r0 * C, w = c / kCpc, e = c - w * kCpc;
+        C2<T> *gb = spec + colbase[w] + e * kEpc;
+        C2<T> *lb = buf + (w * kNQ + e * kEpc) * lp;
+        for (int l0 = r0; l0 < N1; l0 += kUnroll * rps) {
             T ra[kUnroll], rb[kUnroll], rc[kUnroll], rd[kUnroll];
-            int lo[kUnroll];
-            size_t go[kUnroll];
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
-                const int w = cur.w / kCpc, e = cur.w - w * kCpc;
-                lo[u] = base + u * kThreads < total ? (w * kNQ + e * kEpc) * lp + cur.l : -1;
-                go[u] = (size_t)cur.l * plane + colbase[w] + e * kEpc;
-                if (in && lo[u] >= 0) {
+                const int l = l0 + u * rps;
+                if (in && l < N1) {
                     if constexpr (kEpc == 2) {
-                        const float4 v = gld(reinterpret_cast<const float4 *>(spec + go[u]))[0];
+                        const float4 v = gld(reinterpret_cast<const float4 *>(gb + (size_t)l * plane))[0];
                         ra[u] = v.x; rb[u] = v.y; rc[u] = v.z; rd[u] = v.w;
                     } else {
-                        const C2<T> v = gld(spec + go[u])[0];
+                        const C2<T> v = gld(gb + (size_t)l * plane)[0];
                         ra[u] = v.x; rb[u] = v.y;
                     }
                 }
-                cur.step();
             }
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
-                if (lo[u] < 0) continue;
+                const int l = l0 + u * rps;
+                if (l >= N1) continue;
                 if (in) {
-                    buf[lo[u]] = mk<T>(ra[u], rb[u]);
-                    if constexpr (kEpc == 2) buf[lo[u] + lp] = mk<T>(rc[u], rd[u]);
+                    lb[l] = mk<T>(ra[u], rb[u]);
+                    if constexpr (kEpc == 2) lb[lp + l] = mk<T>(rc[u], rd[u]);
                 } else if constexpr (kEpc == 2) {
-                    const C2<T> p0 = buf[lo[u]], p1 = buf[lo[u] + lp];
-                    gst(reinterpret_cast<float4 *>(spec + go[u]))[0] = make_float4(p0.x, p0.y, p1.x, p1.y);
+                    const C2<T> p0 = lb[l], p1 = lb[lp + l];
+                    gst(reinterpret_cast<float4 *>(gb + (size_t)l * plane))[0] = make_float4(p0.x, p0.y, p1.x, p1.y);
                 } else {
-                    gst(spec + go[u])[0] = buf[lo[u]];
+                    gst(gb + (size_t)l * plane)[0] = lb[l];
                 }
             }
         }
@@ -634,59 +650,62 @@ __global__ void __launch_bounds__(kThreads) k_z_main(const InstDev *insts, const
             sidx[i] = smap[m1 * smap_m1 + (i - m1 * P)];
         }
     }
-    // shell rows two items ahead, in two register sets used by alternate
-    // items: chunks al, al + 20, ... of a row (3 per lane in FP32, 6 in FP64)
+    // the next item's shell row in registers: chunks al, al + 20, ... of the
+    // row (3 per lane in FP32, 6 in FP64)
     static_assert(kCpl == 3 || kCpl == 6, "shell row chunking");
     const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
-    float4 a0 = z4, a1 = z4, a2 = z4, a3 = z4, a4 = z4, a5 = z4;
-    float4 b0 = z4, b1 = z4, b2 = z4, b3 = z4, b4 = z4, b5 = z4;
+    float4 r0 = z4, r1 = z4, r2 = z4, r3 = z4, r4 = z4, r5 = z4;
     const bool last_on = al + (kCpl - 1) * kNQ < kChunks;
-#define VDWNL_FETCH_ROW(R, s)                                                                       \
+#define VDWNL_FETCH_ROW(s)                                                                          \
     do {                                                                                            \
         const gptr<const float4> src_ = gld(reinterpret_cast<const float4 *>(tab + (size_t)(s) * kTabStride)); \
-        R##0 = src_[al];                                                                            \
-        R##1 = src_[al + kNQ];                                                                      \
+        r0 = src_[al];                                                                              \
+        r1 = src_[al + kNQ];                                                                        \
         if constexpr (kCpl == 3) {                                                                  \
-            if (last_on) R##2 = src_[al + 2 * kNQ];                                                 \
+            if (last_on) r2 = src_[al + 2 * kNQ];                                                   \
         } else {                                                                                    \
-            R##2 = src_[al + 2 * kNQ];                                                              \
-            R##3 = src_[al + 3 * kNQ];                                                              \
-            R##4 = src_[al + 4 * kNQ];                                                              \
-            if (last_on) R##5 = src_[al + 5 * kNQ];                                                 \
-        }                                                                                           \
-    } while (0)
-#define VDWNL_STAGE_ROW(R)                                                                          \
-    do {                                                                                            \
-        float4 *dst_ = reinterpret_cast<float4 *>(st);                                              \
-        dst_[al] = R##0;                                                                            \
-        dst_[al + kNQ] = R##1;                                                                      \
-        if constexpr (kCpl == 3) {                                                                  \
-            if (last_on) dst_[al + 2 * kNQ] = R##2;                                                 \
-        } else {                                                                                    \
-            dst_[al + 2 * kNQ] = R##2;                                                              \
-            dst_[al + 3 * kNQ] = R##3;                                                              \
-            dst_[al + 4 * kNQ] = R##4;                                                              \
-            if (last_on) dst_[al + 5 * kNQ] = R##5;                                                 \
+            r2 = src_[al + 2 * kNQ];                                                                \
+            r3 = src_[al + 3 * kNQ];                                                                \
+            r4 = src_[al + 4 * kNQ];                                                                \
+            if (last_on) r5 = src_[al + 5 * kNQ];                                                   \
         }                                                                                           \
     } while (0)
     __syncthreads();
-    if (lane_on && gid < nitems) VDWNL_FETCH_ROW(a, sidx[gid]);
-    if (lane_on && gid + kGroups < nitems) VDWNL_FETCH_ROW(b, sidx[gid + kGroups]);
+    if (lane_on && gid < nitems) VDWNL_FETCH_ROW(sidx[gid]);
     fft_lc<T, -1, LC>(buf, I.p1, W, 1, lp, twall);
 
     T *st = stage + (size_t)(lane_on ? gid : 0) * kTabStride;
+    // position of phi_{al, b} in the packed row (row-by-row upper triangle)
+    int foff[kNQ];
+#pragma unroll
+    for (int b = 0; b < kNQ; ++b) {
+        const int lo = al < b ? al : b, hi = al < b ? b : al;
+        foff[b] = lo * kNQ - (lo * (lo - 1)) / 2 + (hi - lo);
+    }
     const T inv_n = (T)I.inv_n;
     const double wn = (double)inv_n * (double)inv_n;
     double e = 0.0;
-    // u for item it from the staged row (phi_{al, b}: packed index of
-    // (min, max) in the row-by-row upper triangle)
-    auto contract = [&](int it) {
+    // A group's lanes share one wave, so staging, reads of theta and writes
+    // of u need wave-level ordering only.
+    for (int it = gid; lane_on && it < nitems; it += kGroups) {
+        {
+            float4 *dst = reinterpret_cast<float4 *>(st);
+            dst[al] = r0;
+            dst[al + kNQ] = r1;
+            if constexpr (kCpl == 3) {
+                if (last_on) dst[al + 2 * kNQ] = r2;
+            } else {
+                dst[al + 2 * kNQ] = r2;
+                dst[al + 3 * kNQ] = r3;
+                dst[al + 4 * kNQ] = r4;
+                if (last_on) dst[al + 5 * kNQ] = r5;
+            }
+        }
+        wave_sync();
+        if (it + kGroups < nitems) VDWNL_FETCH_ROW(sidx[it + kGroups]);   // prefetch the next row
         T f[kNQ];
 #pragma unroll
-        for (int b = 0; b < kNQ; ++b) {
-            const int lo = al < b ? al : b, hi = al < b ? b : al;
-            f[b] = st[lo * kNQ - (lo * (lo - 1)) / 2 + (hi - lo)];
-        }
+        for (int b = 0; b < kNQ; ++b) f[b] = st[foff[b]];
         const int m1 = it / P, pr = it - m1 * P;
         const int l = m1;
         int lq = N1 - m1;
@@ -714,22 +733,6 @@ __global__ void __launch_bounds__(kThreads) k_z_main(const InstDev *insts, const
             if (lq >= 0) x2[al * lp] = cscale(u2, inv_n);
             wave_sync();
         }
-    };
-    // A group's lanes share one wave, so staging, reads of theta and writes
-    // of u need wave-level ordering only.  Items alternate between the two
-    // register sets; each set is refilled two items ahead.
-    for (int it = gid; lane_on && it < nitems; it += 2 * kGroups) {
-        VDWNL_STAGE_ROW(a);
-        wave_sync();
-        if (it + 2 * kGroups < nitems) VDWNL_FETCH_ROW(a, sidx[it + 2 * kGroups]);
-        contract(it);
-        const int it2 = it + kGroups;
-        if (it2 < nitems) {
-            VDWNL_STAGE_ROW(b);
-            wave_sync();
-            if (it2 + 2 * kGroups < nitems) VDWNL_FETCH_ROW(b, sidx[it2 + 2 * kGroups]);
-            contract(it2);
-        }
     }
     __syncthreads();
     fft_lc<T, 1, LC>(buf, I.p1, W, 1, lp, twall);
@@ -737,7 +740,6 @@ __global__ void __launch_bounds__(kThreads) k_z_main(const InstDev *insts, const
     const double sum = block_sum(e);
     if (threadIdx.x == 0) I.part_ek[t.slot] = sum;
 #undef VDWNL_FETCH_ROW
-#undef VDWNL_STAGE_ROW
 }
 
 // E_k = (Omega/2) sum of the axis-1 partials; Delta E = dOmega sum of the
