@@ -8,9 +8,12 @@ HIP product path and never imports it.
 The steps follow the paper's order.  Readings of points the paper leaves
 open are marked READING; each has a line in the design notes.
 
- O1  gradient of n by spectral differentiation (the paper uses finite
-     differences for grad n; READING: spectral, with the Nyquist
-     multiplier set to zero so the derivative matrix is real antisymmetric)
+ O1  gradient of n.  grad_mode 0: spectral differentiation (READING: the
+     Nyquist multiplier set to zero so the derivative matrix is real
+     antisymmetric).  grad_mode m = 1..4: the paper's own choice, finite
+     differences on the same grid (Sec. on the potential, around Eq. (Vi);
+     READING: the central formula with m points on each side of every axis,
+     order 2m, periodic)
  O2  LDA correlation energy per electron (READING: Perdew-Wang 1992,
      spin-unpolarised)
  O3  q0(n, |grad n|) (READING: the Dion et al. form
@@ -156,6 +159,37 @@ def divergence(w, cell):
     return np.fft.irfftn(acc, s=shape, axes=(0, 1, 2))
 
 
+def fd_weights(m):
+    """Weights c_s (s = 1..m) of the central first-derivative formula
+    f'(x) ~ sum_s c_s (f(x + s h) - f(x - s h)) / h.  Expanding the right side
+    in a Taylor series, the coefficient of h^(2k-2) f^(2k-1)(x) is
+    sum_s c_s 2 s^(2k-1) / (2k-1)!; the formula has order 2m when it is 1 for
+    k = 1 and 0 for k = 2..m, an m x m linear system solved here."""
+    s = np.arange(1, m + 1, dtype=np.float64)
+    A = np.array([2.0 * s ** (2 * k - 1) for k in range(1, m + 1)])
+    rhs = np.zeros(m)
+    rhs[0] = 1.0
+    return np.linalg.solve(A, rhs)
+
+
+def gradient_fd(n, cell, m):
+    """grad n by the central differences of ``fd_weights(m)`` on the periodic
+    grid (3 x shape): d_c n_i = sum_s c_s (n_{i + s e_c} - n_{i - s e_c}) / h_c."""
+    shape = n.shape
+    c = fd_weights(m)
+    out = np.zeros((3,) + tuple(shape))
+    for ax in range(3):
+        h = cell[ax] / shape[ax]
+        for s in range(1, m + 1):
+            out[ax] += c[s - 1] / h * (np.roll(n, -s, axis=ax) - np.roll(n, s, axis=ax))
+    return out
+
+
+def divergence_fd(w, cell, m):
+    """sum_c D_c w_c with the derivative operator of ``gradient_fd``."""
+    return sum(gradient_fd(w[c], cell, m)[c] for c in range(3))
+
+
 def gmod_half(shape, cell):
     """|G| on the half spectrum (Nyquist components kept: the kernel depends
     only on |G| and both signs of a Nyquist component give the same |G|)."""
@@ -237,14 +271,20 @@ def kernel_at(gmod, table):
 
 
 # ---------------------------------------------------------------- O1..O14
-def energy_potential(n, cell, table, n_min=N_MIN, return_parts=False):
-    """(E_k, Delta E, v) for the density n [N1, N2, N3] in the cell (bohr)."""
+def energy_potential(n, cell, table, n_min=N_MIN, return_parts=False, grad_mode=0):
+    """(E_k, Delta E, v) for the density n [N1, N2, N3] in the cell (bohr);
+    grad_mode 0: spectral gradient, m = 1..4: central differences of order 2m."""
     n = np.asarray(n, dtype=np.float64)
     shape = n.shape
     N = n.size
     omega = float(np.prod(cell))
     dvol = omega / N
-    grad = gradient(n, cell)                                   # O1
+    if grad_mode not in (0, 1, 2, 3, 4):
+        raise ValueError("grad_mode must be 0 (spectral) or 1..4 (central differences)")
+    if grad_mode == 0:
+        grad = gradient(n, cell)                               # O1
+    else:
+        grad = gradient_fd(n, cell, grad_mode)
     loc = theta_fields(n, grad, table, n_min)                  # O2-O6, O12
     theta = loc["theta"]
     nq = theta.shape[0]
@@ -261,7 +301,10 @@ def energy_potential(n, cell, table, n_min=N_MIN, return_parts=False):
     v_loc = np.sum(u * loc["dtheta_dn"], axis=0) + loc["de_dn"]                  # O13
     gsc = np.sum(u * loc["g"], axis=0) + loc["ge"]
     wvec = gsc[None] * grad
-    v = v_loc - divergence(wvec, cell)                         # O14
+    if grad_mode == 0:
+        v = v_loc - divergence(wvec, cell)                     # O14
+    else:
+        v = v_loc - divergence_fd(wvec, cell, grad_mode)
     if return_parts:
         return dict(E_k=ek, dE=de, v=v, u=u, chat=chat, uhat=uhat, grad=grad, v_loc=v_loc,
                     w=wvec, **loc)
