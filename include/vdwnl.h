@@ -63,8 +63,13 @@ const char *vdwnl_last_error(const vdwnl_ctx *ctx);
  *              grids), N1 N2 even
  *   cell[3]    orthorhombic cell lengths, bohr, > 0
  *   grad_mode  0: grad n by spectral differentiation, the Nyquist multiplier
- *              set to zero (the paper uses finite differences, the same role;
- *              1 is reserved for that variant)
+ *              set to zero.  m = 1..4: the paper's choice, finite differences
+ *              on the same grid (the potential section, around Eq. (Vi)):
+ *              the central formula with m points on each side along every
+ *              axis (order 2m), periodic; its weights d(grad n_j)/dn_i give
+ *              the gradient term of Eq. (Vi) as minus the same stencil's
+ *              divergence.  An edge shorter than 2m + 1 folds coinciding
+ *              neighbours' weights together.
  *   precision  32 or 64
  * Device workspace is allocated at the first evaluation after planning;
  * later evaluations allocate nothing.  Tile shapes follow one LDS budget per
@@ -113,21 +118,27 @@ int vdwnl_energy_potential_batched(vdwnl_ctx *ctx, int32_t nb, const void *const
                                    void *const *v_ptrs, double *E_out, void *stream);
 
 /* Copy an internal per-grid field of the last evaluation of grid `inst` to
- * the device buffer dst (for parity probes): which = 0: grad n [3][N];
- * 1: v_loc [N] (the local part of v, before the gradient term).  Arrays in
- * the planned precision. */
+ * the device buffer dst (for parity probes): which = 0: grad n [3][N] with
+ * the spectral gradient; with finite differences the same buffer holds the
+ * vector field w = sum_a u_a dtheta_a/dgrad n + de/dgrad n of Eq. (Vi) after
+ * an evaluation (grad n is overwritten in place); 1: v_loc [N] (the local
+ * part of v, before the gradient term).  Arrays in the planned precision. */
 int vdwnl_debug_field(vdwnl_ctx *ctx, int32_t inst, int32_t which, void *dst, void *stream);
 
 /* Per-pass timing.  vdwnl_set_timing(ctx, 1) clears the counters and makes
  * every later evaluation record a HIP event after each of its passes (on the
  * evaluation's stream); vdwnl_pass_times copies the accumulated milliseconds
- * of each pass (launch order, the FP64 energy reduction last) into ms[], the
- * number of timed evaluations into *calls, and returns the number of passes.
- * vdwnl_pass_name(i) names pass i ("" outside the range).  Timed
- * evaluations launch their passes one by one (no graph). */
+ * of every pass kind (indexed by kind, the FP64 energy reduction last; kinds
+ * the planned gradient mode does not launch stay 0) into ms[], the number of
+ * timed evaluations into *calls, and returns the number of entries.
+ * vdwnl_pass_name(k) names kind k ("" outside the range); vdwnl_pass_order
+ * writes the kinds the planned mode launches, in launch order, into kinds[]
+ * (at most max_passes) and returns their number.  Timed evaluations launch
+ * their passes one by one (no graph). */
 int vdwnl_set_timing(vdwnl_ctx *ctx, int32_t on);
 int vdwnl_pass_times(const vdwnl_ctx *ctx, int32_t max_passes, double *ms, int64_t *calls);
 const char *vdwnl_pass_name(int32_t i);
+int vdwnl_pass_order(const vdwnl_ctx *ctx, int32_t max_passes, int32_t *kinds);
 
 /* Graph replay on (default, on != 0) or off (every evaluation launches its
  * passes one by one; results are identical). */

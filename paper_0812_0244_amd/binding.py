@@ -37,6 +37,7 @@ SIGNATURES = {
     "vdwnl_set_timing": (ctypes.c_int, [_vp, _i32]),
     "vdwnl_pass_times": (ctypes.c_int, [_vp, _i32, _dp, ctypes.POINTER(ctypes.c_int64)]),
     "vdwnl_pass_name": (ctypes.c_char_p, [_i32]),
+    "vdwnl_pass_order": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(_i32)]),
     "vdwnl_build_kernel_table": (ctypes.c_int, [ctypes.c_int, _i32, _dp, ctypes.c_double, ctypes.c_double,
                                                 _i32, ctypes.c_double, _dp, _dp]),
     "vdwnl_kernel_phi": (ctypes.c_int, [ctypes.c_int, _i32, _dp, _dp, _dp]),
@@ -213,14 +214,25 @@ class VdwNl:
     def set_timing(self, on: bool = True):
         self._check(self.lib.vdwnl_set_timing(self.h, 1 if on else 0), "set_timing")
 
+    def pass_order(self):
+        """Kinds of the passes the planned gradient mode launches, in order."""
+        k = (_i32 * 32)()
+        n = self.lib.vdwnl_pass_order(self.h, 32, k)
+        if n < 0:
+            raise VdwNlError(n, "pass_order")
+        return [int(k[i]) for i in range(n)]
+
     def pass_times(self):
-        """{pass name: (total ms, evaluations)} accumulated since set_timing(True)."""
+        """{pass name: (total ms, evaluations)} accumulated since set_timing(True),
+        for the passes of the planned gradient mode in launch order, then the
+        energy reduction."""
         ms = np.zeros(32)
         calls = ctypes.c_int64()
-        npass = self.lib.vdwnl_pass_times(self.h, 32, _as_ptr(ms, ctypes.c_double), ctypes.byref(calls))
-        if npass < 0:
-            raise VdwNlError(npass, "pass_times")
-        return {self.lib.vdwnl_pass_name(i).decode(): (float(ms[i]), calls.value) for i in range(npass)}
+        nk = self.lib.vdwnl_pass_times(self.h, 32, _as_ptr(ms, ctypes.c_double), ctypes.byref(calls))
+        if nk < 0:
+            raise VdwNlError(nk, "pass_times")
+        kinds = self.pass_order() + [nk - 1]
+        return {self.lib.vdwnl_pass_name(i).decode(): (float(ms[i]), calls.value) for i in kinds}
 
     def info(self):
         n = _i32()

@@ -145,7 +145,7 @@ struct vdwnl_ctx {
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
-    // per-pass timing
+    // per-pass timing (pass_ms by kind, the reduction last; events by launch position)
     bool timing = false;
     hipEvent_t ev[KIND_COUNT + 2] = {};
     bool ev_made = false;
@@ -206,6 +206,15 @@ static bool smooth235(int n) {
     return n == 1;
 }
 
+// LDS of one theta / assembly tile of b rows: the 20 fields' pair lines,
+// twiddles and method constants; with the spectral gradient also the FP64
+// lines of grad n (or w) and FP64 twiddles.
+static size_t xpass_lds(int grad_mode, size_t b, size_t N3, size_t rs) {
+    const size_t cs = 2 * rs;
+    const size_t base = b * (N3 + 1) * (kNQ / 2) * cs + N3 * cs + (kNQ + kNQ * kNQ) * rs + (kMaxMc + 1) * 8;
+    return grad_mode == 0 ? base + b * (N3 + 1) * 2 * 16 + N3 * 16 : base;
+}
+
 static int check_grid(vdwnl_ctx *c, const int32_t *shape, const double *cell, int precision, Grid &g) {
     const size_t cs = precision == 64 ? 16 : 8, rs = precision == 64 ? 8 : 4;
     for (int i = 0; i < 3; ++i) {
@@ -223,7 +232,7 @@ static int check_grid(vdwnl_ctx *c, const int32_t *shape, const double *cell, in
     const size_t stage = (size_t)((kThreads / 64) * (64 / kNQ)) * kTabStride * rs;
     auto zmain = [&](size_t k3) { return (N1 + kNQ * k3 * (N1 | 1)) * cs + 16 + stage + (N1 / 2 + 1) * k3 * sizeof(int); };
     auto zaux = [&](size_t k3) { return (N1 + 4 * k3 * (N1 | 1)) * 16; };
-    auto xmain = [&](size_t b) { return b * (N3 + 1) * (2 * 16 + (kNQ / 2) * cs) + N3 * (16 + cs) + (kNQ + kNQ * kNQ) * rs + (kMaxMc + 1) * 8; };
+    auto xmain = [&](size_t b) { return xpass_lds(0, b, N3, rs); };   // the larger (spectral) layout
     auto ypass = [&](size_t w, size_t c2) { return (N2 + (N2 | 1) * w) * c2; };
     const size_t cap = c->lds_cap;
     if (N1 > (size_t)kMaxN1 || zmain(1) > cap)
@@ -245,7 +254,7 @@ static void size_tiles(const vdwnl_ctx *c, Grid &g) {
     const size_t stage = (size_t)((kThreads / 64) * (64 / kNQ)) * kTabStride * rs;
     auto zmain = [&](size_t k3) { return (N1 + kNQ * k3 * (N1 | 1)) * cs + 16 + stage + (N1 / 2 + 1) * k3 * sizeof(int); };
     auto zaux = [&](size_t k3) { return (N1 + 4 * k3 * (N1 | 1)) * 16; };
-    auto xmain = [&](size_t b) { return b * (N3 + 1) * (2 * 16 + (kNQ / 2) * cs) + N3 * (16 + cs) + (kNQ + kNQ * kNQ) * rs + (kMaxMc + 1) * 8; };
+    auto xmain = [&](size_t b) { return xpass_lds(c->grad_mode, b, N3, rs); };
     auto ypass = [&](size_t w, size_t c2) { return (N2 + (N2 | 1) * w) * c2; };
     // complex elements per LDS FFT tile: bounded for the runtime-radix FFT
     // (its per-thread register arrays), not for the compile-time plans
@@ -307,7 +316,8 @@ static void tuned_store(const std::string &key, const size_t *pref) {
 static int plan_grids(vdwnl_ctx *c, int nb, const int32_t *shapes, const double *cells, int grad_mode,
                       int precision) {
     if (!c || !shapes || !cells || nb <= 0) return fail(c, VDWNL_E_ARG, "null argument or empty batch");
-    if (grad_mode != 0) return fail(c, VDWNL_E_ARG, "grad_mode must be 0 (spectral)");
+    if (grad_mode < 0 || grad_mode > kMaxFd)
+        return fail(c, VDWNL_E_ARG, "grad_mode must be 0 (spectral) or 1..4 (central differences)");
     if (precision != 32 && precision != 64) return fail(c, VDWNL_E_ARG, "precision must be 32 or 64");
     std::vector<Grid> gs(nb);
     for (int i = 0; i < nb; ++i) {
@@ -369,12 +379,31 @@ static int check_krange(vdwnl_ctx *c) {
     return VDWNL_OK;
 }
 
-// Launch order of the passes of one evaluation (the final reduction follows).
-static const int kPassOrder[KIND_COUNT] = {KX_NFWD, KY_1F, KZ_GRAD, KY_3I, KX_THETA, KY_20F, KZ_MAIN,
-                                           KY_20I, KX_ASSEMBLE, KY_3F, KZ_DIV, KY_1I, KX_FINAL};
+// Launch order of the passes of one evaluation (the final reduction follows):
+// spectral gradient (thirteen passes) or finite differences (seven).
+static const int kOrderSpectral[] = {KX_NFWD, KY_1F, KZ_GRAD, KY_3I, KX_THETA, KY_20F, KZ_MAIN,
+                                     KY_20I, KX_ASSEMBLE, KY_3F, KZ_DIV, KY_1I, KX_FINAL};
+static const int kOrderFd[] = {KF_GRAD, KX_THETA_FD, KY_20F, KZ_MAIN, KY_20I, KX_ASSEMBLE_FD, KF_DIV};
 static const char *kPassName[KIND_COUNT + 1] = {
     "x_nfwd", "y_1f", "z_grad", "y_3i", "x_theta", "y_20f", "z_main", "y_20i", "x_assemble", "y_3f", "z_div",
-    "y_1i", "x_final", "reduce"};
+    "y_1i", "x_final", "fd_grad", "x_theta_fd", "x_assemble_fd", "fd_div", "reduce"};
+
+static int pass_order(int grad_mode, const int **order) {
+    if (grad_mode == 0) {
+        *order = kOrderSpectral;
+        return (int)(sizeof(kOrderSpectral) / sizeof(int));
+    }
+    *order = kOrderFd;
+    return (int)(sizeof(kOrderFd) / sizeof(int));
+}
+
+// Weights c_s, s = 1..m, of the central first-derivative formula of order 2m
+// on a unit grid: c_s = (-1)^(s+1) (m!)^2 / (s (m - s)! (m + s)!).
+static void central_weights(int m, double *c) {
+    auto fact = [](int k) { double f = 1.0; for (int i = 2; i <= k; ++i) f *= i; return f; };
+    for (int s = 1; s <= m; ++s)
+        c[s - 1] = ((s % 2) ? 1.0 : -1.0) * fact(m) * fact(m) / (s * fact(m - s) * fact(m + s));
+}
 
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -431,23 +460,24 @@ static int prepare_device(vdwnl_ctx *c) {
         const int inst = (int)gi;
         size_t first_tile[KIND_COUNT];
         for (int k = 0; k < KIND_COUNT; ++k) first_tile[k] = tiles[k].size();
-        // axis-3 tiles
+        // axis-3 tiles (and the stencil passes' runs of lines)
+        const bool fd = c->grad_mode > 0;
         for (int r = 0; r < rows; r += g.bnf) {
             const int b = std::min(g.bnf, rows - r);   // even: rows and bnf are
-            tiles[KX_NFWD].push_back({inst, r, b, 0, -1});
-            tiles[KX_FINAL].push_back({inst, r, b, 0, -1});
+            tiles[fd ? KF_GRAD : KX_NFWD].push_back({inst, r, b, 0, -1});
+            tiles[fd ? KF_DIV : KX_FINAL].push_back({inst, r, b, 0, -1});
         }
         int slot = 0;
         for (int r = 0; r < rows; r += g.bmain) {
             const int b = std::min(g.bmain, rows - r);
-            tiles[KX_THETA].push_back({inst, r, b, 0, slot++});
-            tiles[KX_ASSEMBLE].push_back({inst, r, b, 0, -1});
+            tiles[fd ? KX_THETA_FD : KX_THETA].push_back({inst, r, b, 0, slot++});
+            tiles[fd ? KX_ASSEMBLE_FD : KX_ASSEMBLE].push_back({inst, r, b, 0, -1});
         }
         g.n_de = slot;
         // axis-2 tiles
-        const int kinds_y[6] = {KY_1F, KY_1I, KY_3F, KY_3I, KY_20F, KY_20I};
-        const int vs[6] = {1, 1, 3, 3, kNQ, kNQ};
-        for (int q = 0; q < 6; ++q) {
+        const int kinds_y[6] = {KY_20F, KY_20I, KY_1F, KY_1I, KY_3F, KY_3I};
+        const int vs[6] = {kNQ, kNQ, 1, 1, 3, 3};
+        for (int q = 0; q < (fd ? 2 : 6); ++q) {
             const int ftot = N3h * vs[q];
             const int w = vs[q] == kNQ ? g.wy20 : (vs[q] == 3 ? g.wy3 : g.wy1);
             for (int i1 = 0; i1 < N1; ++i1)
@@ -485,7 +515,7 @@ static int prepare_device(vdwnl_ctx *c) {
                 tiles[KZ_MAIN].push_back(tl);
             }
         }
-        for (int k2 = 0; k2 < N2; ++k2)
+        for (int k2 = 0; k2 < (fd ? 0 : N2); ++k2)
             for (int k3 = 0; k3 < N3h; k3 += g.k3aux) {
                 tiles[KZ_GRAD].push_back({inst, k2, k3, std::min(g.k3aux, N3h - k3), -1});
                 tiles[KZ_DIV].push_back({inst, k2, k3, std::min(g.k3aux, N3h - k3), -1});
@@ -502,19 +532,20 @@ static int prepare_device(vdwnl_ctx *c) {
         g.off_grad = off; off = align_up(off + 3 * g.npts() * rs);
         g.off_vloc = off; off = align_up(off + g.npts() * rs);
         g.off_spec = off; off = align_up(off + g.nhalf() * kNQ * cs);
-        g.off_spec3 = off; off = align_up(off + g.nhalf() * 3 * 16);   // FP64 aux spectra
-        g.off_spec1 = off; off = align_up(off + g.nhalf() * 16);
+        const size_t aux = fd ? 0 : g.nhalf();   // FP64 gradient / divergence spectra
+        g.off_spec3 = off; off = align_up(off + aux * 3 * 16);
+        g.off_spec1 = off; off = align_up(off + aux * 16);
         g.off_ek = off; off = align_up(off + g.n_ek * sizeof(double));
         g.off_de = off; off = align_up(off + g.n_de * sizeof(double));
     }
     // LDS of one tile of each pass for grid g
     auto lds_of = [&](int k, const Grid &g) -> size_t {
         const size_t N1 = g.s[0], N2 = g.s[1], N3 = g.s[2];
-        const size_t xm = g.bmain * (N3 + 1) * (2 * 16 + (kNQ / 2) * cs) + N3 * (16 + cs) + (kNQ + kNQ * kNQ) * rs +
-                          (kMaxMc + 1) * 8;
         switch (k) {
             case KX_NFWD: case KX_FINAL: return (N3 + (g.bnf / 2) * (N3 + 1)) * 16;
-            case KX_THETA: case KX_ASSEMBLE: return xm;
+            case KF_GRAD: case KF_DIV: return 0;
+            case KX_THETA: case KX_ASSEMBLE: case KX_THETA_FD: case KX_ASSEMBLE_FD:
+                return xpass_lds(c->grad_mode, g.bmain, N3, rs);
             case KY_1F: case KY_1I: return (N2 + (N2 | 1) * g.wy1) * 16;
             case KY_3F: case KY_3I: return (N2 + (N2 | 1) * g.wy3) * 16;
             case KY_20F: case KY_20I: return (N2 + (N2 | 1) * g.wy20) * cs;
@@ -529,7 +560,8 @@ static int prepare_device(vdwnl_ctx *c) {
     // the axis whose FFT a pass performs: 3 for the axis-3 passes, 2, 1
     auto axis_len = [&](int k, const Grid &g) -> int {
         switch (k) {
-            case KX_NFWD: case KX_THETA: case KX_ASSEMBLE: case KX_FINAL: return g.s[2];
+            case KX_NFWD: case KX_THETA: case KX_ASSEMBLE: case KX_FINAL: case KX_THETA_FD: case KX_ASSEMBLE_FD:
+                return g.s[2];
             case KY_1F: case KY_1I: case KY_3F: case KY_3I: case KY_20F: case KY_20I: return g.s[1];
             default: return g.s[0];
         }
@@ -541,7 +573,9 @@ static int prepare_device(vdwnl_ctx *c) {
             vdwnl_ctx::Launch L{k, lc, (int)all.size(), 0, 0};
             for (const Tile &tl : tiles[k]) {
                 const Grid &g = c->grids[tl.inst];
-                if (len_class(axis_len(k, g)) != lc) continue;
+                // the stencil passes transform nothing: one launch for every grid
+                const int klc = (k == KF_GRAD || k == KF_DIV) ? 0 : len_class(axis_len(k, g));
+                if (klc != lc) continue;
                 all.push_back(tl);
                 L.lds = std::max(L.lds, lds_of(k, g));
             }
@@ -634,6 +668,13 @@ static int prepare_device(vdwnl_ctx *c) {
         I.g1 = 2.0 * M_PI / g.cell[0]; I.g2 = 2.0 * M_PI / g.cell[1]; I.g3 = 2.0 * M_PI / g.cell[2];
         I.omega = g.cell[0] * g.cell[1] * g.cell[2];
         I.dvol = I.omega / (double)g.npts();
+        I.fdm = c->grad_mode;
+        if (c->grad_mode > 0) {
+            double w[kMaxFd];
+            central_weights(c->grad_mode, w);
+            for (int ax = 0; ax < 3; ++ax)
+                for (int s = 0; s < c->grad_mode; ++s) I.fdc[ax][s] = w[s] * (double)g.s[ax] / g.cell[ax];
+        }
         I.grad = w + g.off_grad; I.vloc = w + g.off_vloc; I.spec = w + g.off_spec;
         I.spec3 = w + g.off_spec3; I.spec1 = w + g.off_spec1;
         I.shellmap = (const int *)(w + c->map_off[g.shell_key]);
@@ -653,8 +694,10 @@ static int enqueue(vdwnl_ctx *c, int nb, hipStream_t st) {
     if ((e = hipMemcpyAsync(c->d_inst, c->h_inst, nb * sizeof(InstDev), hipMemcpyHostToDevice, st)) != hipSuccess)
         return hipfail(c, e, "upload instance table");
     if (c->timing) (void)hipEventRecord(c->ev[0], st);
-    for (int i = 0; i < KIND_COUNT; ++i) {
-        const int k = kPassOrder[i];
+    const int *order;
+    const int npass = pass_order(c->grad_mode, &order);
+    for (int i = 0; i < npass; ++i) {
+        const int k = order[i];
         for (const auto &L : c->launches[k]) {
             LaunchArgs a{c->d_inst, c->d_tiles + L.off, L.cnt, L.lds, c->d_consts, c->d_tw, c->d_twd, st, c->d_cols};
             if ((e = launch_kind(k, L.lc, c->precision, a)) != hipSuccess) return hipfail(c, e, "kernel launch");
@@ -662,7 +705,7 @@ static int enqueue(vdwnl_ctx *c, int nb, hipStream_t st) {
         if (c->timing) (void)hipEventRecord(c->ev[i + 1], st);
     }
     if ((e = launch_reduce(c->d_inst, nb, c->d_E, st)) != hipSuccess) return hipfail(c, e, "reduce launch");
-    if (c->timing) (void)hipEventRecord(c->ev[KIND_COUNT + 1], st);
+    if (c->timing) (void)hipEventRecord(c->ev[npass + 1], st);
     if ((e = hipMemcpyAsync(c->h_E, c->d_E, nb * 2 * sizeof(double), hipMemcpyDeviceToHost, st)) != hipSuccess)
         return hipfail(c, e, "copy energies");
     return VDWNL_OK;
@@ -729,9 +772,12 @@ static int run(vdwnl_ctx *c, int nb, const void *const *n_ptrs, void *const *v_p
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return hipfail(c, e, "stream synchronize");
     std::memcpy(E_out, c->h_E, nb * 2 * sizeof(double));
     if (c->timing) {
-        for (int i = 0; i <= KIND_COUNT; ++i) {
+        const int *order;
+        const int npass = pass_order(c->grad_mode, &order);
+        for (int i = 0; i <= npass; ++i) {
             float ms = 0.f;
-            if (hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]) == hipSuccess) c->pass_ms[i] += ms;
+            if (hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]) == hipSuccess)
+                c->pass_ms[i < npass ? order[i] : KIND_COUNT] += ms;
         }
         c->timed_calls++;
     }
@@ -922,23 +968,21 @@ int vdwnl_autotune(vdwnl_ctx *ctx, int32_t nb, const void *const *n_ptrs, void *
         for (int r = 0; r < reps && rc == VDWNL_OK; ++r) rc = run(ctx, nb, n_ptrs, v_ptrs, E.data(), stream);
         for (int k = 0; k < KIND_COUNT; ++k) t[ci][k] = ctx->pass_ms[k];
     }
-    // per group, the budget with the least time over the group's passes
-    // (pass_ms is indexed by position in the launch order)
-    auto pos = [](int kind) {
-        for (int i = 0; i < KIND_COUNT; ++i)
-            if (kPassOrder[i] == kind) return i;
-        return 0;
-    };
-    const std::vector<std::vector<int>> groups = {
-        {KX_THETA, KX_ASSEMBLE}, {KY_20F, KY_20I}, {KY_1F, KY_1I, KY_3F, KY_3I}, {KZ_MAIN}, {KZ_GRAD, KZ_DIV}};
+    // per group, the budget with the least time over the group's passes (a
+    // group with no pass in this gradient mode keeps the default)
+    const std::vector<std::vector<int>> groups = {{KX_THETA, KX_ASSEMBLE, KX_THETA_FD, KX_ASSEMBLE_FD},
+                                                  {KY_20F, KY_20I},
+                                                  {KY_1F, KY_1I, KY_3F, KY_3I},
+                                                  {KZ_MAIN},
+                                                  {KZ_GRAD, KZ_DIV}};
     size_t best[TG_COUNT];
     for (int gi = 0; gi < TG_COUNT; ++gi) {
         double bt = 1e300;
         best[gi] = std::min<size_t>(ctx->lds_cap, kLdsCap);
         for (size_t ci = 0; rc == VDWNL_OK && ci < cand.size(); ++ci) {
             double sum = 0.0;
-            for (int k : groups[gi]) sum += t[ci][pos(k)];
-            if (sum < bt) { bt = sum; best[gi] = cand[ci]; }
+            for (int k : groups[gi]) sum += t[ci][k];
+            if (sum > 0.0 && sum < bt) { bt = sum; best[gi] = cand[ci]; }
         }
     }
     for (int gi = 0; gi < TG_COUNT; ++gi) ctx->pref[gi] = best[gi];
@@ -986,6 +1030,14 @@ int vdwnl_pass_times(const vdwnl_ctx *ctx, int32_t max_passes, double *ms, int64
 }
 
 const char *vdwnl_pass_name(int32_t i) { return (i >= 0 && i <= KIND_COUNT) ? kPassName[i] : ""; }
+
+int vdwnl_pass_order(const vdwnl_ctx *ctx, int32_t max_passes, int32_t *kinds) {
+    if (!ctx || (max_passes > 0 && !kinds)) return VDWNL_E_ARG;
+    const int *order;
+    const int npass = pass_order(ctx->grad_mode, &order);
+    for (int i = 0; i < std::min<int>(max_passes, npass); ++i) kinds[i] = order[i];
+    return npass;
+}
 
 int vdwnl_info(const vdwnl_ctx *ctx, int32_t *n_grids, int64_t *workspace_bytes) {
     if (!ctx) return VDWNL_E_ARG;

@@ -14,8 +14,9 @@ constexpr int kThreads = 256;                    // threads per workgroup, every
 constexpr int kTileCap = 4096;                   // complex elements of one LDS FFT tile
 constexpr int kLdsCap = 65536;                   // bytes of LDS one workgroup may take
 constexpr int kMaxStages = 16;
-constexpr int kMaxCols = 16;
-constexpr int kMaxMc = 64;                       // largest m_c of Eq. (Sat)                     // (k2, k3) columns per fused axis-1 tile
+constexpr int kMaxCols = 16;                     // (k2, k3) columns per fused axis-1 tile
+constexpr int kMaxMc = 64;                       // largest m_c of Eq. (Sat)
+constexpr int kMaxFd = 4;                        // largest finite-difference half-width
 constexpr int kMaxN1 = 204;                      // 20 N1 <= kTileCap (fused axis-1 pass)
 constexpr int kMaxN3 = 340;                      // 12 N3 complex doubles <= kLdsCap
 
@@ -30,7 +31,8 @@ struct FftPlan {
 
 // Per-grid state seen by the kernels.  Field layouts (C order):
 //   n, v, vloc      [N1][N2][N3] real
-//   grad            [3][N1][N2][N3] real
+//   grad            [3][N1][N2][N3] real  (finite-difference mode: grad n, then
+//                   overwritten in place by the vector field w of the assembly)
 //   spec            [N1][N2][N3h][kNQ] complex  (20 theta / u spectra, component fastest)
 //   spec3           [N1][N2][N3h][3] complex FP64   (grad n / w spectra)
 //   spec1           [N1][N2][N3h] complex FP64      (n / divergence spectrum)
@@ -42,6 +44,8 @@ struct InstDev {
     double inv_n;            // 1 / (N1 N2 N3)
     double g1, g2, g3;       // 2 pi / L_c
     double omega, dvol;
+    int fdm;                 // finite-difference half-width m (0: spectral gradient)
+    double fdc[3][kMaxFd];   // c_s / h_c: weights of the central formula on axis c
     void *grad, *vloc, *spec, *spec3, *spec1;
     const int *shellmap;
     const void *shelltab;
@@ -85,6 +89,12 @@ enum KernelKind {
     KZ_DIV,        // axis 1: sum_c i G_c w_c / N (1 component)
     KY_1I,         // axis-2 inverse, 1 component
     KX_FINAL,      // C2R divergence, v = v_loc - div
+    // finite-difference gradient mode: the stencils replace the gradient and
+    // divergence FFT chains
+    KF_GRAD,       // grad n by central differences
+    KX_THETA_FD,   // theta_a from n and the stored grad n, R2C theta along axis 3
+    KX_ASSEMBLE_FD,// C2R u_a, v_loc and w (stored in place of grad n)
+    KF_DIV,        // v = v_loc - sum_c D_c w_c
     KIND_COUNT
 };
 

@@ -201,9 +201,11 @@ __global__ void __launch_bounds__(kThreads) k_x_nfwd(const InstDev *insts, const
     }
 }
 
-// C2R of grad n (3 FP64 spectra per row), theta_a = n p_a(q0), Delta E
-// partials, R2C of the 20 theta rows.  tile: a = first row, b = rows, slot = partial.
-template <typename T, int LC>
+// theta_a = n p_a(q0), Delta E partials, R2C of the 20 theta rows; grad n
+// from the C2R of its 3 FP64 spectra per row (stored for the assembly), or
+// (FD) read as stored by the finite-difference pass.
+// tile: a = first row, b = rows, slot = partial.
+template <typename T, int LC, bool FD>
 __global__ void __launch_bounds__(kThreads) k_x_theta(const InstDev *insts, const Tile *tiles,
                                                       const Consts *cst, const void *twv, const void *twdv) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -211,36 +213,48 @@ __global__ void __launch_bounds__(kThreads) k_x_theta(const InstDev *insts, cons
     const InstDev &I = insts[t.inst];
     const int N3 = axis_len<LC>(I.n3), N3h = N3 / 2 + 1, row0 = t.a, B = t.b, ls = N3 + 1;
     const size_t N = (size_t)I.n1 * I.n2 * I.n3;
-    double2 *twd = reinterpret_cast<double2 *>(smem);       // FP64 twiddles
-    double2 *r1 = twd + N3;                                   // 2 lines per row: d1 + i d2, d3
-    C2<T> *r2 = reinterpret_cast<C2<T> *>(r1 + 2 * B * ls);  // 10 lines per row: theta pairs
+    double2 *twd = reinterpret_cast<double2 *>(smem);       // FP64 twiddles (spectral gradient)
+    double2 *r1 = twd + (FD ? 0 : N3);                        // 2 lines per row: d1 + i d2, d3
+    C2<T> *r2 = reinterpret_cast<C2<T> *>(r1 + (FD ? 0 : 2 * B * ls));   // 10 lines per row: theta pairs
     C2<T> *tw = r2 + kNQ / 2 * B * ls;                       // twiddles in T
     T *qm = reinterpret_cast<T *>(tw + N3);
     T *Mm = qm + kNQ;
     double *invm = reinterpret_cast<double *>(Mm + kNQ * kNQ);   // 8-byte aligned: every part before is
-    // density of this thread's first point, fetched first (used after the FFT)
+    // density (and FD: grad n) of this thread's first point, fetched first
+    // (used after the FFT or the constants)
     const int npt = B * N3;
-    const gptr<const T> nin = gld(reinterpret_cast<const T *>(I.n) + (size_t)row0 * N3);
+    const size_t p0 = (size_t)row0 * N3;
+    const gptr<const T> nin = gld(reinterpret_cast<const T *>(I.n) + p0);
+    const gptr<const T> gin = gld(reinterpret_cast<const T *>(I.grad) + p0);
     const T n_first = threadIdx.x < npt ? nin[threadIdx.x] : (T)0;
-    const double2 *s3 = reinterpret_cast<const double2 *>(I.spec3) + (size_t)row0 * N3h * 3;
-    struct Three { double2 a, b, c; };
-    batched<2>(B * N3, [&](int idx) {
-        const int rb = idx / N3, k = idx - rb * N3;
-        const int kk = k >= N3h ? N3 - k : k;
-        const double2 *src = s3 + ((size_t)rb * N3h + kk) * 3;
-        const gptr<const double2> g = gld(src);
-        return Three{g[0], g[1], g[2]};
-    }, [&](int idx, Three y) {
-        const int rb = idx / N3, k = idx - rb * N3;
-        if (k >= N3h) { y.a = cconj(y.a); y.b = cconj(y.b); y.c = cconj(y.c); }
-        r1[(2 * rb) * ls + k] = mk<double>(y.a.x - y.b.y, y.a.y + y.b.x);
-        r1[(2 * rb + 1) * ls + k] = y.c;
-    });
+    T gx_f = (T)0, gy_f = (T)0, gz_f = (T)0;
+    if constexpr (FD) {
+        if (threadIdx.x < npt) {
+            gx_f = gin[threadIdx.x];
+            gy_f = gin[N + threadIdx.x];
+            gz_f = gin[2 * N + threadIdx.x];
+        }
+    } else {
+        const double2 *s3 = reinterpret_cast<const double2 *>(I.spec3) + (size_t)row0 * N3h * 3;
+        struct Three { double2 a, b, c; };
+        batched<2>(B * N3, [&](int idx) {
+            const int rb = idx / N3, k = idx - rb * N3;
+            const int kk = k >= N3h ? N3 - k : k;
+            const double2 *src = s3 + ((size_t)rb * N3h + kk) * 3;
+            const gptr<const double2> g = gld(src);
+            return Three{g[0], g[1], g[2]};
+        }, [&](int idx, Three y) {
+            const int rb = idx / N3, k = idx - rb * N3;
+            if (k >= N3h) { y.a = cconj(y.a); y.b = cconj(y.b); y.c = cconj(y.c); }
+            r1[(2 * rb) * ls + k] = mk<double>(y.a.x - y.b.y, y.a.y + y.b.x);
+            r1[(2 * rb + 1) * ls + k] = y.c;
+        });
+        load_twiddles<double>(twd, I.p3, reinterpret_cast<const double2 *>(twdv));
+    }
     load_consts<T>(cst, qm, Mm, invm);
-    load_twiddles<double>(twd, I.p3, reinterpret_cast<const double2 *>(twdv));
     load_twiddles<T>(tw, I.p3, reinterpret_cast<const C2<T> *>(twv));
     __syncthreads();
-    fft_lc<double, 1, LC>(r1, I.p3, 2 * B, 1, ls, twd);
+    if constexpr (!FD) fft_lc<double, 1, LC>(r1, I.p3, 2 * B, 1, ls, twd);
 
     const double c_qc = cst->qc, c_cs = cst->cs, c_nmin = cst->nmin;
     const int c_mc = cst->mc;
@@ -249,12 +263,20 @@ __global__ void __launch_bounds__(kThreads) k_x_theta(const InstDev *insts, cons
     for (int idx = threadIdx.x; idx < npt; idx += kThreads) {
         const int rb = idx / N3, k = idx - rb * N3;
         const size_t p = (size_t)(row0 + rb) * N3 + k;
-        const T nv = idx == (int)threadIdx.x ? n_first : nin[idx];
-        const double2 g01d = r1[(2 * rb) * ls + k], g2d = r1[(2 * rb + 1) * ls + k];
-        const C2<T> g01 = mk<T>((T)g01d.x, (T)g01d.y), g2 = mk<T>((T)g2d.x, (T)0);
-        grad[p] = g01.x;
-        grad[N + p] = g01.y;
-        grad[2 * N + p] = g2.x;
+        const bool first = idx == (int)threadIdx.x;
+        const T nv = first ? n_first : nin[idx];
+        C2<T> g01, g2;
+        if constexpr (FD) {
+            g01 = mk<T>(first ? gx_f : gin[idx], first ? gy_f : gin[N + idx]);
+            g2 = mk<T>(first ? gz_f : gin[2 * N + idx], (T)0);
+        } else {
+            const double2 g01d = r1[(2 * rb) * ls + k], g2d = r1[(2 * rb + 1) * ls + k];
+            g01 = mk<T>((T)g01d.x, (T)g01d.y);
+            g2 = mk<T>((T)g2d.x, (T)0);
+            grad[p] = g01.x;
+            grad[N + p] = g01.y;
+            grad[2 * N + p] = g2.x;
+        }
         T *th = reinterpret_cast<T *>(r2 + (size_t)(kNQ / 2 * rb) * ls);   // pair line m at th + 2 m ls
         if (nv >= (T)c_nmin) {
             LocalQ<T, false> lq;
@@ -300,8 +322,9 @@ __global__ void __launch_bounds__(kThreads) k_x_theta(const InstDev *insts, cons
 
 // C2R of the 20 u_a rows; v_loc = sum_a u_a dtheta_a/dn + de/dn;
 // w = g grad n with g = sum_a u_a 2 n p'_a Q dq/dsigma + de/dsigma-part;
-// R2C of the three w rows.  tile: a = first row, b = rows.
-template <typename T, int LC>
+// R2C of the three w rows, or (FD) w stored in place of grad n.
+// tile: a = first row, b = rows.
+template <typename T, int LC, bool FD>
 __global__ void __launch_bounds__(kThreads) k_x_assemble(const InstDev *insts, const Tile *tiles,
                                                          const Consts *cst, const void *twv, const void *twdv) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -309,9 +332,9 @@ __global__ void __launch_bounds__(kThreads) k_x_assemble(const InstDev *insts, c
     const InstDev &I = insts[t.inst];
     const int N3 = axis_len<LC>(I.n3), N3h = N3 / 2 + 1, row0 = t.a, B = t.b, ls = N3 + 1;
     const size_t N = (size_t)I.n1 * I.n2 * I.n3;
-    double2 *twd = reinterpret_cast<double2 *>(smem);       // FP64 twiddles
-    double2 *r1 = twd + N3;                                   // 2 FP64 lines per row: w1 + i w2, w3
-    C2<T> *r2 = reinterpret_cast<C2<T> *>(r1 + 2 * B * ls);  // 10 lines per row: u pairs
+    double2 *twd = reinterpret_cast<double2 *>(smem);       // FP64 twiddles (spectral gradient)
+    double2 *r1 = twd + (FD ? 0 : N3);                        // 2 FP64 lines per row: w1 + i w2, w3
+    C2<T> *r2 = reinterpret_cast<C2<T> *>(r1 + (FD ? 0 : 2 * B * ls));   // 10 lines per row: u pairs
     C2<T> *tw = r2 + kNQ / 2 * B * ls;                       // twiddles in T
     T *qm = reinterpret_cast<T *>(tw + N3);
     T *Mm = qm + kNQ;
@@ -345,7 +368,7 @@ __global__ void __launch_bounds__(kThreads) k_x_assemble(const InstDev *insts, c
         if (k != 0 && 2 * k != N3) line[N3 - k] = mk<T>(y.a.x + y.b.y, -y.a.y + y.b.x);   // conj(a) + i conj(b)
     });
     load_consts<T>(cst, qm, Mm, invm);
-    load_twiddles<double>(twd, I.p3, reinterpret_cast<const double2 *>(twdv));
+    if constexpr (!FD) load_twiddles<double>(twd, I.p3, reinterpret_cast<const double2 *>(twdv));
     load_twiddles<T>(tw, I.p3, reinterpret_cast<const C2<T> *>(twv));
     __syncthreads();
     fft_lc<T, 1, LC>(r2, I.p3, kNQ / 2 * B, 1, ls, tw);
@@ -387,22 +410,142 @@ __global__ void __launch_bounds__(kThreads) k_x_assemble(const InstDev *insts, c
         }
         vloc[idx] = vl;
         const double gsd = (double)gs;
-        r1[(2 * rb) * ls + k] = mk<double>(gsd * (double)gx, gsd * (double)gy);
-        r1[(2 * rb + 1) * ls + k] = mk<double>(gsd * (double)gz, 0.0);
+        if constexpr (FD) {
+            // w in place of grad n: each point is read and written by its own thread
+            const gptr<T> wout = gst(reinterpret_cast<T *>(I.grad) + p0);
+            wout[idx] = (T)(gsd * (double)gx);
+            wout[N + idx] = (T)(gsd * (double)gy);
+            wout[2 * N + idx] = (T)(gsd * (double)gz);
+        } else {
+            r1[(2 * rb) * ls + k] = mk<double>(gsd * (double)gx, gsd * (double)gy);
+            r1[(2 * rb + 1) * ls + k] = mk<double>(gsd * (double)gz, 0.0);
+        }
     }
-    __syncthreads();
-    fft_lc<double, -1, LC>(r1, I.p3, 2 * B, 1, ls, twd);
+    if constexpr (!FD) {
+        __syncthreads();
+        fft_lc<double, -1, LC>(r1, I.p3, 2 * B, 1, ls, twd);
+        double2 *out = reinterpret_cast<double2 *>(I.spec3) + (size_t)row0 * N3h * 3;
+        for (int idx = threadIdx.x; idx < B * N3h * 3; idx += kThreads) {
+            const int comp = idx % 3, rest = idx / 3;
+            const int k = rest % N3h, rb = rest / N3h;
+            const double2 *Z = r1 + (2 * rb + (comp >> 1)) * ls;
+            const double2 z = Z[k], zc = cconj(Z[(N3 - k) % N3]);
+            double2 y;
+            if (comp != 1) y = mk<double>((z.x + zc.x) * 0.5, (z.y + zc.y) * 0.5);
+            else y = mk<double>((z.y - zc.y) * 0.5, -(z.x - zc.x) * 0.5);
+            out[idx] = y;
+        }
+    }
+}
 
-    double2 *out = reinterpret_cast<double2 *>(I.spec3) + (size_t)row0 * N3h * 3;
-    for (int idx = threadIdx.x; idx < B * N3h * 3; idx += kThreads) {
-        const int comp = idx % 3, rest = idx / 3;
-        const int k = rest % N3h, rb = rest / N3h;
-        const double2 *Z = r1 + (2 * rb + (comp >> 1)) * ls;
-        const double2 z = Z[k], zc = cconj(Z[(N3 - k) % N3]);
-        double2 y;
-        if (comp != 1) y = mk<double>((z.x + zc.x) * 0.5, (z.y + zc.y) * 0.5);
-        else y = mk<double>((z.y - zc.y) * 0.5, -(z.x - zc.x) * 0.5);
-        out[idx] = y;
+// ---------------------------------------------------------------- finite-difference passes
+
+// Central differences on the periodic grid, FP64 arithmetic on values read in
+// T: d_c f_i = sum_s (c_s / h_c) (f_{i + s e_c} - f_{i - s e_c}), s = 1..M.
+// Neighbour indices wrap once (M <= 4 <= every edge).  Tiles are runs of
+// whole axis-3 lines: a = first row (i1 N2 + i2), b = rows.
+struct FdIndex {
+    size_t p, b1, b2, b3;    // the point; the point with i1, i2, i3 set to 0
+    int i1, i2, i3;
+    __device__ __forceinline__ FdIndex(int row, int k, int N2, int N3) {
+        i1 = row / N2;
+        i2 = row - i1 * N2;
+        i3 = k;
+        p = (size_t)row * N3 + k;
+        b1 = p - (size_t)i1 * N2 * N3;
+        b2 = p - (size_t)i2 * N3;
+        b3 = p - (size_t)i3;
+    }
+};
+
+__device__ __forceinline__ int wrap_up(int i, int n) { return i >= n ? i - n : i; }
+__device__ __forceinline__ int wrap_dn(int i, int n) { return i < 0 ? i + n : i; }
+
+template <typename T, int M>
+__device__ __forceinline__ double fd_diff(const gptr<const T> f, size_t base, size_t stride, int i, int n,
+                                          const double *c) {
+    double acc = 0.0;
+#pragma unroll
+    for (int s = 1; s <= M; ++s) {
+        const T a = f[base + (size_t)wrap_up(i + s, n) * stride];
+        const T b = f[base + (size_t)wrap_dn(i - s, n) * stride];
+        acc += c[s - 1] * ((double)a - (double)b);
+    }
+    return acc;
+}
+
+template <typename T, int M>
+__device__ __forceinline__ void fd_grad_tile(const InstDev &I, int row0, int B) {
+    const int N1 = I.n1, N2 = I.n2, N3 = I.n3;
+    const size_t N = (size_t)N1 * N2 * N3, plane = (size_t)N2 * N3;
+    const gptr<const T> n = gld(reinterpret_cast<const T *>(I.n));
+    const gptr<T> g = gst(reinterpret_cast<T *>(I.grad));
+    double c1[M], c2[M], c3[M];
+#pragma unroll
+    for (int s = 0; s < M; ++s) { c1[s] = I.fdc[0][s]; c2[s] = I.fdc[1][s]; c3[s] = I.fdc[2][s]; }
+    const int npt = B * N3;
+#pragma unroll 2
+    for (int idx = threadIdx.x; idx < npt; idx += kThreads) {
+        const int rb = idx / N3;
+        const FdIndex x(row0 + rb, idx - rb * N3, N2, N3);
+        const double d1 = fd_diff<T, M>(n, x.b1, plane, x.i1, N1, c1);
+        const double d2 = fd_diff<T, M>(n, x.b2, (size_t)N3, x.i2, N2, c2);
+        const double d3 = fd_diff<T, M>(n, x.b3, 1, x.i3, N3, c3);
+        g[x.p] = (T)d1;
+        g[N + x.p] = (T)d2;
+        g[2 * N + x.p] = (T)d3;
+    }
+}
+
+// v = v_loc - sum_c D_c w_c, w in the grad n buffer (Eq. (Vi): the sum over j
+// of w_j . d(grad n_j)/dn_i is minus the divergence, the operator being
+// antisymmetric).
+template <typename T, int M>
+__device__ __forceinline__ void fd_div_tile(const InstDev &I, int row0, int B) {
+    const int N1 = I.n1, N2 = I.n2, N3 = I.n3;
+    const size_t N = (size_t)N1 * N2 * N3, plane = (size_t)N2 * N3;
+    const gptr<const T> w = gld(reinterpret_cast<const T *>(I.grad));
+    const gptr<const T> vloc = gld(reinterpret_cast<const T *>(I.vloc));
+    const gptr<T> v = gst(reinterpret_cast<T *>(I.v));
+    double c1[M], c2[M], c3[M];
+#pragma unroll
+    for (int s = 0; s < M; ++s) { c1[s] = I.fdc[0][s]; c2[s] = I.fdc[1][s]; c3[s] = I.fdc[2][s]; }
+    const int npt = B * N3;
+#pragma unroll 2
+    for (int idx = threadIdx.x; idx < npt; idx += kThreads) {
+        const int rb = idx / N3;
+        const FdIndex x(row0 + rb, idx - rb * N3, N2, N3);
+        const double vl = (double)vloc[x.p];
+        const double d1 = fd_diff<T, M>(w, x.b1, plane, x.i1, N1, c1);
+        const double d2 = fd_diff<T, M>(w + N, x.b2, (size_t)N3, x.i2, N2, c2);
+        const double d3 = fd_diff<T, M>(w + 2 * N, x.b3, 1, x.i3, N3, c3);
+        v[x.p] = (T)(vl - (d1 + d2 + d3));
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_fd_grad(const InstDev *insts, const Tile *tiles) {
+    const Tile t = tiles[blockIdx.x];
+    const InstDev &I = insts[t.inst];
+    switch (I.fdm) {
+        case 1: fd_grad_tile<T, 1>(I, t.a, t.b); break;
+        case 2: fd_grad_tile<T, 2>(I, t.a, t.b); break;
+        case 3: fd_grad_tile<T, 3>(I, t.a, t.b); break;
+        case 4: fd_grad_tile<T, 4>(I, t.a, t.b); break;
+        default: break;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_fd_div(const InstDev *insts, const Tile *tiles) {
+    const Tile t = tiles[blockIdx.x];
+    const InstDev &I = insts[t.inst];
+    switch (I.fdm) {
+        case 1: fd_div_tile<T, 1>(I, t.a, t.b); break;
+        case 2: fd_div_tile<T, 2>(I, t.a, t.b); break;
+        case 3: fd_div_tile<T, 3>(I, t.a, t.b); break;
+        case 4: fd_div_tile<T, 4>(I, t.a, t.b); break;
+        default: break;
     }
 }
 
@@ -780,11 +923,13 @@ static hipError_t launch_lc(int kind, const LaunchArgs &a) {
         case KY_1F: VDWNL_LAUNCH((k_y<double, -1, LC>), a.twd, 2, 1); break;
         case KZ_GRAD: VDWNL_LAUNCH((k_z_grad<double, LC>), a.twd); break;
         case KY_3I: VDWNL_LAUNCH((k_y<double, 1, LC>), a.twd, 1, 3); break;
-        case KX_THETA: VDWNL_LAUNCH((k_x_theta<T, LC>), a.cst, a.tw, a.twd); break;
+        case KX_THETA: VDWNL_LAUNCH((k_x_theta<T, LC, false>), a.cst, a.tw, a.twd); break;
+        case KX_THETA_FD: VDWNL_LAUNCH((k_x_theta<T, LC, true>), a.cst, a.tw, a.twd); break;
         case KY_20F: VDWNL_LAUNCH((k_y<T, -1, LC>), a.tw, 0, kNQ); break;
         case KZ_MAIN: VDWNL_LAUNCH((k_z_main<T, LC>), a.cols, a.tw); break;
         case KY_20I: VDWNL_LAUNCH((k_y<T, 1, LC>), a.tw, 0, kNQ); break;
-        case KX_ASSEMBLE: VDWNL_LAUNCH((k_x_assemble<T, LC>), a.cst, a.tw, a.twd); break;
+        case KX_ASSEMBLE: VDWNL_LAUNCH((k_x_assemble<T, LC, false>), a.cst, a.tw, a.twd); break;
+        case KX_ASSEMBLE_FD: VDWNL_LAUNCH((k_x_assemble<T, LC, true>), a.cst, a.tw, a.twd); break;
         case KY_3F: VDWNL_LAUNCH((k_y<double, -1, LC>), a.twd, 1, 3); break;
         case KZ_DIV: VDWNL_LAUNCH((k_z_div<double, LC>), a.twd); break;
         case KY_1I: VDWNL_LAUNCH((k_y<double, 1, LC>), a.twd, 2, 1); break;
@@ -798,6 +943,12 @@ static hipError_t launch_lc(int kind, const LaunchArgs &a) {
 template <typename T>
 static hipError_t launch_kind_t(int kind, int lc, const LaunchArgs &a) {
     if (a.ntiles < 0) return hipErrorInvalidValue;
+    if (kind == KF_GRAD || kind == KF_DIV) {   // no FFT and no LDS: one launch for every grid
+        if (a.ntiles == 0) return hipSuccess;
+        if (kind == KF_GRAD) hipLaunchKernelGGL(k_fd_grad<T>, dim3(a.ntiles), dim3(kThreads), 0, a.stream, a.insts, a.tiles);
+        else hipLaunchKernelGGL(k_fd_div<T>, dim3(a.ntiles), dim3(kThreads), 0, a.stream, a.insts, a.tiles);
+        return hipGetLastError();
+    }
     switch (lc) {
         case 0: return launch_lc<T, 0>(kind, a);
         case 1: return launch_lc<T, 1>(kind, a);

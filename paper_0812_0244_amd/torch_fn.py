@@ -17,10 +17,11 @@ class NonlocalCorrelation:
     """A planned grid plus kernel table on one device.
 
     ``table`` is a mapping with ``qmesh``, ``qc``, ``mc``, ``dk``, ``phi``
-    ([nq, nq, nk], radial kernel table) and ``c_soft``.
+    ([nq, nq, nk], radial kernel table) and ``c_soft``.  ``grad_mode`` 0:
+    spectral gradient; m = 1..4: central differences with m points a side.
     """
 
-    def __init__(self, shape, cell, table, precision: int = 32, device: int = 0):
+    def __init__(self, shape, cell, table, precision: int = 32, device: int = 0, grad_mode: int = 0):
         self.shape = tuple(int(s) for s in shape)
         self.cell = tuple(float(c) for c in cell)
         self.precision = precision
@@ -28,7 +29,8 @@ class NonlocalCorrelation:
         self.dtype = torch.float64 if precision == 64 else torch.float32
         self.dvol = float(np.prod(self.cell)) / float(np.prod(self.shape))
         self.lib = VdwNl(device)
-        self.lib.set_grid(self.shape, self.cell, 0, precision)
+        self.grad_mode = grad_mode
+        self.lib.set_grid(self.shape, self.cell, grad_mode, precision)
         self.lib.set_kernel_table(table["qmesh"], table["qc"], int(table.get("mc", 12)), table["dk"],
                                   table["phi"], table["c_soft"])
 

@@ -69,7 +69,10 @@ def test_bad_arguments():
     lib, h = _host_ctx()
     assert _set_grid(lib, h, (24, 24, 24), cell=(10.0, -1.0, 10.0)) == E["ARG"]
     assert _set_grid(lib, h, (24, 24, 24), prec=16) == E["ARG"]
-    assert _set_grid(lib, h, (24, 24, 24), gm=1) == E["ARG"]
+    assert _set_grid(lib, h, (24, 24, 24), gm=5) == E["ARG"]
+    assert _set_grid(lib, h, (24, 24, 24), gm=-1) == E["ARG"]
+    for gm in (1, 2, 3, 4):          # central differences, m points a side
+        assert _set_grid(lib, h, (24, 24, 24), gm=gm) == 0
     assert lib.vdwnl_set_grid(None, None, None, 0, 32) == E["ARG"]
     assert lib.vdwnl_energy_potential(None, None, None, None, None) == E["ARG"]
     # evaluation on a host-only context
