@@ -28,7 +28,8 @@ PEAK_HBM_GBS = 8000.0
 def pass_bytes(name, shapes, s):
     """Algorithmic bytes one launch of a pass moves over all grids: what it
     must read and write given its inputs and outputs (spectra as N1 N2
-    (N3/2+1) complex values; the gradient/divergence spectra are FP64)."""
+    (N3/2+1) complex values; the gradient chain's spectra are FP64, the
+    divergence chain's in the working precision)."""
     tot = 0
     for (n1, n2, n3) in shapes:
         N = n1 * n2 * n3
@@ -36,13 +37,18 @@ def pass_bytes(name, shapes, s):
         c, d = 2 * s, 16
         b = {
             "x_nfwd": N * s + NH * d,
-            "y_1f": 2 * NH * d, "y_1i": 2 * NH * d,
-            "z_grad": 4 * NH * d, "z_div": 4 * NH * d,
-            "y_3i": 6 * NH * d, "y_3f": 6 * NH * d,
+            "y_1f": 2 * NH * d, "y_1i": 2 * NH * c,
+            "z_grad": 4 * NH * d, "z_div": 4 * NH * c,
+            "y_3i": 6 * NH * d, "y_3f": 6 * NH * c,
             "x_theta": 3 * NH * d + 4 * N * s + 20 * NH * c,
             "y_20f": 40 * NH * c, "z_main": 40 * NH * c, "y_20i": 40 * NH * c,
-            "x_assemble": 20 * NH * c + 5 * N * s + 3 * NH * d,
-            "x_final": NH * d + 2 * N * s,
+            "x_assemble": 20 * NH * c + 5 * N * s + 3 * NH * c,
+            "x_final": NH * c + 2 * N * s,
+            # finite-difference gradient mode
+            "fd_grad": 4 * N * s,
+            "x_theta_fd": 4 * N * s + 20 * NH * c,
+            "x_assemble_fd": 20 * NH * c + 8 * N * s,
+            "fd_div": 5 * N * s,
             "reduce": 0,
         }[name]
         tot += b
@@ -108,6 +114,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--lds-budgets", type=str, default=None,
                     help="x,y20,yaux,z,zaux LDS budgets in bytes (fixes the tiles; no tuning)")
+    ap.add_argument("--fd-mode", type=int, default=3,
+                    help="finite-difference half-width of the second leg (0: skip that leg)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain device copy of 1 GiB (reference dispatch for "
                          "hardware byte counters)")
@@ -197,8 +205,52 @@ def main():
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
     path_bytes = sum(pass_bytes(k, shapes, 4) for k in passes)
 
-    # ---- FP64 plain: one context per density, evaluated one after another
+    # ---- the same workload with the finite-difference gradient (the paper's
+    # own choice; seven passes instead of thirteen), FP32 batched
     del lib
+    fd = None
+    if args.fd_mode > 0:
+        lib = VdwNl(0)
+        lib.set_grids(shapes, cells, args.fd_mode, 32)
+        lib.set_kernel_table(table["qmesh"], table["qc"], table["mc"], table["dk"], table["phi"], table["c_soft"])
+        vfd = [torch.empty_like(x) for x in n32]
+        vfptr = [x.data_ptr() for x in vfd]
+        if args.lds_budgets:
+            lib.set_tiling([int(x) for x in args.lds_budgets.split(",")])
+        elif not args.no_autotune:
+            lib.autotune(nptr, vfptr, reps=2, stream=stream)
+        fd_tiling = lib.get_tiling()
+        for _ in range(args.warmup):
+            lib.energy_potential_batched(nptr, vfptr, stream)
+        torch.cuda.synchronize()
+        fd_ms = []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ts = time.perf_counter()
+            Efd = lib.energy_potential_batched(nptr, vfptr, stream)
+            fd_ms.append((time.perf_counter() - ts) * 1e3)
+        torch.cuda.synchronize()
+        fd_step = (time.perf_counter() - t0) * 1e3 / args.steps
+        lib.set_timing(True)
+        for _ in range(args.steps):
+            lib.energy_potential_batched(nptr, vfptr, stream)
+        torch.cuda.synchronize()
+        fd_passes = lib.pass_times()
+        lib.set_timing(False)
+        del lib
+        log("fp32 batched, finite differences m=%d (graph replay): %.3f ms/step, median %.3f"
+            % (args.fd_mode, fd_step, float(np.median(fd_ms))))
+        for k, (ms, calls) in fd_passes.items():
+            log("  pass %-14s %8.3f ms/step" % (k, ms / max(calls, 1)))
+        fd_bytes = sum(pass_bytes(k, shapes, 4) for k in fd_passes)
+        fd = {"grad_mode": args.fd_mode, "ms_per_step": fd_step, "median_ms_per_step": float(np.median(fd_ms)),
+              "value": total / (fd_step * 1e-3), "unit": "grid-points/s", "lds_budgets": fd_tiling,
+              "passes_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in fd_passes.items()},
+              "path_algorithmic_bytes_per_step": fd_bytes,
+              "path_frac": fd_bytes / (fd_step * 1e-3) / 1e9 / PEAK_HBM_GBS,
+              "E_sum": float(Efd.sum())}
+
+    # ---- FP64 plain: one context per density, evaluated one after another
     ctxs, n64, v64 = [], [], []
     for w, d in zip(insts, dens):
         c = VdwNl(0)
@@ -253,7 +305,7 @@ def main():
                         "(spacing 20/96 bohr, seeds 4000-4063), N_q=20, one call per step",
             "grids_by_edge": sizes,
             "total_points": total,
-            "precision": "theta/u FFTs and contraction FP32; grad n and divergence chains and "
+            "precision": "theta/u FFTs, contraction and divergence chain FP32; grad n chain and "
                          "reductions FP64",
             "launch": "one HIP graph per call (13 passes x FFT length classes), tile LDS budgets "
                       "tuned at setup",
@@ -269,6 +321,7 @@ def main():
                      "algorithmic_bytes": dom_bytes,
                      "path_algorithmic_bytes_per_step": path_bytes,
                      "path_frac": path_bytes / (ms_step * 1e-3) / 1e9 / PEAK_HBM_GBS},
+        "fd_gradient": fd,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -207,12 +207,16 @@ static bool smooth235(int n) {
 }
 
 // LDS of one theta / assembly tile of b rows: the 20 fields' pair lines,
-// twiddles and method constants; with the spectral gradient also the FP64
-// lines of grad n (or w) and FP64 twiddles.
-static size_t xpass_lds(int grad_mode, size_t b, size_t N3, size_t rs) {
+// twiddles and method constants; with the spectral gradient also two lines
+// per row of grad n (FP64, with FP64 twiddles: XL_THETA) or of w (working
+// precision: XL_ASSEMBLE).
+enum XLayout { XL_THETA = 0, XL_ASSEMBLE, XL_FD };
+static size_t xpass_lds(int layout, size_t b, size_t N3, size_t rs) {
     const size_t cs = 2 * rs;
     const size_t base = b * (N3 + 1) * (kNQ / 2) * cs + N3 * cs + (kNQ + kNQ * kNQ) * rs + (kMaxMc + 1) * 8;
-    return grad_mode == 0 ? base + b * (N3 + 1) * 2 * 16 + N3 * 16 : base;
+    if (layout == XL_THETA) return base + b * (N3 + 1) * 2 * 16 + N3 * 16;
+    if (layout == XL_ASSEMBLE) return base + b * (N3 + 1) * 2 * cs;
+    return base;
 }
 
 static int check_grid(vdwnl_ctx *c, const int32_t *shape, const double *cell, int precision, Grid &g) {
@@ -232,7 +236,7 @@ static int check_grid(vdwnl_ctx *c, const int32_t *shape, const double *cell, in
     const size_t stage = (size_t)((kThreads / 64) * (64 / kNQ)) * kTabStride * rs;
     auto zmain = [&](size_t k3) { return (N1 + kNQ * k3 * (N1 | 1)) * cs + 16 + stage + (N1 / 2 + 1) * k3 * sizeof(int); };
     auto zaux = [&](size_t k3) { return (N1 + 4 * k3 * (N1 | 1)) * 16; };
-    auto xmain = [&](size_t b) { return xpass_lds(0, b, N3, rs); };   // the larger (spectral) layout
+    auto xmain = [&](size_t b) { return xpass_lds(XL_THETA, b, N3, rs); };   // the largest layout
     auto ypass = [&](size_t w, size_t c2) { return (N2 + (N2 | 1) * w) * c2; };
     const size_t cap = c->lds_cap;
     if (N1 > (size_t)kMaxN1 || zmain(1) > cap)
@@ -254,7 +258,7 @@ static void size_tiles(const vdwnl_ctx *c, Grid &g) {
     const size_t stage = (size_t)((kThreads / 64) * (64 / kNQ)) * kTabStride * rs;
     auto zmain = [&](size_t k3) { return (N1 + kNQ * k3 * (N1 | 1)) * cs + 16 + stage + (N1 / 2 + 1) * k3 * sizeof(int); };
     auto zaux = [&](size_t k3) { return (N1 + 4 * k3 * (N1 | 1)) * 16; };
-    auto xmain = [&](size_t b) { return xpass_lds(c->grad_mode, b, N3, rs); };
+    auto xmain = [&](size_t b) { return xpass_lds(c->grad_mode ? XL_FD : XL_THETA, b, N3, rs); };
     auto ypass = [&](size_t w, size_t c2) { return (N2 + (N2 | 1) * w) * c2; };
     // complex elements per LDS FFT tile: bounded for the runtime-radix FFT
     // (its per-thread register arrays), not for the compile-time plans
@@ -284,13 +288,13 @@ static void size_tiles(const vdwnl_ctx *c, Grid &g) {
     g.wy1 = g.wy3;
 }
 
-// Tuned LDS budgets, per process, keyed by precision, LDS size and the exact
-// list of grid shapes and cells.
+// Tuned LDS budgets, per process, keyed by precision, gradient mode, LDS size
+// and the exact list of grid shapes and cells.
 static std::mutex g_tuned_mu;
 static std::map<std::string, std::vector<size_t>> g_tuned;
 
 static std::string plan_key(const vdwnl_ctx *c) {
-    std::string k = std::to_string(c->precision) + "/" + std::to_string(c->lds_cap);
+    std::string k = std::to_string(c->precision) + "/" + std::to_string(c->grad_mode) + "/" + std::to_string(c->lds_cap);
     char buf[128];
     for (const Grid &g : c->grids) {
         std::snprintf(buf, sizeof(buf), ";%dx%dx%d@%.17g,%.17g,%.17g", g.s[0], g.s[1], g.s[2], g.cell[0], g.cell[1],
@@ -542,19 +546,25 @@ static int prepare_device(vdwnl_ctx *c) {
     auto lds_of = [&](int k, const Grid &g) -> size_t {
         const size_t N1 = g.s[0], N2 = g.s[1], N3 = g.s[2];
         switch (k) {
-            case KX_NFWD: case KX_FINAL: return (N3 + (g.bnf / 2) * (N3 + 1)) * 16;
+            // the gradient chain in FP64, the divergence chain in the working precision
+            case KX_NFWD: return (N3 + (g.bnf / 2) * (N3 + 1)) * 16;
+            case KX_FINAL: return (N3 + (g.bnf / 2) * (N3 + 1)) * cs;
             case KF_GRAD: case KF_DIV: return 0;
-            case KX_THETA: case KX_ASSEMBLE: case KX_THETA_FD: case KX_ASSEMBLE_FD:
-                return xpass_lds(c->grad_mode, g.bmain, N3, rs);
-            case KY_1F: case KY_1I: return (N2 + (N2 | 1) * g.wy1) * 16;
-            case KY_3F: case KY_3I: return (N2 + (N2 | 1) * g.wy3) * 16;
+            case KX_THETA: return xpass_lds(XL_THETA, g.bmain, N3, rs);
+            case KX_ASSEMBLE: return xpass_lds(XL_ASSEMBLE, g.bmain, N3, rs);
+            case KX_THETA_FD: case KX_ASSEMBLE_FD: return xpass_lds(XL_FD, g.bmain, N3, rs);
+            case KY_1F: return (N2 + (N2 | 1) * g.wy1) * 16;
+            case KY_1I: return (N2 + (N2 | 1) * g.wy1) * cs;
+            case KY_3I: return (N2 + (N2 | 1) * g.wy3) * 16;
+            case KY_3F: return (N2 + (N2 | 1) * g.wy3) * cs;
             case KY_20F: case KY_20I: return (N2 + (N2 | 1) * g.wy20) * cs;
             case KZ_MAIN: {
                 const size_t K = std::min(g.k3main, kMaxCols);
                 return (N1 + (size_t)kNQ * K * (N1 | 1)) * cs + 16 + (size_t)((kThreads / 64) * (64 / kNQ)) * kTabStride * rs +
                        (N1 / 2 + 1) * K * sizeof(int);
             }
-            default: return (N1 + 4 * g.k3aux * (N1 | 1)) * 16;   // KZ_GRAD, KZ_DIV
+            case KZ_DIV: return (N1 + 4 * g.k3aux * (N1 | 1)) * cs;
+            default: return (N1 + 4 * g.k3aux * (N1 | 1)) * 16;   // KZ_GRAD
         }
     };
     // the axis whose FFT a pass performs: 3 for the axis-3 passes, 2, 1

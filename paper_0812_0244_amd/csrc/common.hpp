@@ -34,8 +34,10 @@ struct FftPlan {
 //   grad            [3][N1][N2][N3] real  (finite-difference mode: grad n, then
 //                   overwritten in place by the vector field w of the assembly)
 //   spec            [N1][N2][N3h][kNQ] complex  (20 theta / u spectra, component fastest)
-//   spec3           [N1][N2][N3h][3] complex FP64   (grad n / w spectra)
-//   spec1           [N1][N2][N3h] complex FP64      (n / divergence spectrum)
+//   spec3           [N1][N2][N3h][3] complex        (grad n spectra in FP64; later the
+//                   w spectra in the working precision)
+//   spec1           [N1][N2][N3h] complex           (n spectrum in FP64; later the
+//                   divergence spectrum in the working precision)
 //   shellmap        [N1/2+1][N2/2+1][N3h] int   (|G| shell of (|m1|, |m2|, m3))
 //   shelltab        [nshell][kTabStride] real   (phi_ab(|G_s|), a <= b packed row by row, padded)
 struct InstDev {
@@ -84,7 +86,7 @@ enum KernelKind {
     KY_20F,        // axis-2 forward, 20 components
     KZ_MAIN,       // axis 1 forward, u = phi c, energy, axis 1 inverse
     KY_20I,        // axis-2 inverse, 20 components
-    KX_ASSEMBLE,   // C2R u_a, v_loc and w = g grad n, R2C w along axis 3
+    KX_ASSEMBLE,   // C2R u_a, v_loc and w = g grad n, R2C w along axis 3 (working precision from here)
     KY_3F,         // axis-2 forward, 3 components
     KZ_DIV,        // axis 1: sum_c i G_c w_c / N (1 component)
     KY_1I,         // axis-2 inverse, 1 component

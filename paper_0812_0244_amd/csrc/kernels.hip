@@ -322,19 +322,18 @@ __global__ void __launch_bounds__(kThreads) k_x_theta(const InstDev *insts, cons
 
 // C2R of the 20 u_a rows; v_loc = sum_a u_a dtheta_a/dn + de/dn;
 // w = g grad n with g = sum_a u_a 2 n p'_a Q dq/dsigma + de/dsigma-part;
-// R2C of the three w rows, or (FD) w stored in place of grad n.
-// tile: a = first row, b = rows.
+// R2C of the three w rows (in T: the divergence chain runs in the working
+// precision), or (FD) w stored in place of grad n.  tile: a = first row, b = rows.
 template <typename T, int LC, bool FD>
 __global__ void __launch_bounds__(kThreads) k_x_assemble(const InstDev *insts, const Tile *tiles,
-                                                         const Consts *cst, const void *twv, const void *twdv) {
+                                                         const Consts *cst, const void *twv) {
     extern __shared__ __align__(16) unsigned char smem[];
     const Tile t = tiles[blockIdx.x];
     const InstDev &I = insts[t.inst];
     const int N3 = axis_len<LC>(I.n3), N3h = N3 / 2 + 1, row0 = t.a, B = t.b, ls = N3 + 1;
     const size_t N = (size_t)I.n1 * I.n2 * I.n3;
-    double2 *twd = reinterpret_cast<double2 *>(smem);       // FP64 twiddles (spectral gradient)
-    double2 *r1 = twd + (FD ? 0 : N3);                        // 2 FP64 lines per row: w1 + i w2, w3
-    C2<T> *r2 = reinterpret_cast<C2<T> *>(r1 + (FD ? 0 : 2 * B * ls));   // 10 lines per row: u pairs
+    C2<T> *r1 = reinterpret_cast<C2<T> *>(smem);              // 2 lines per row: w1 + i w2, w3
+    C2<T> *r2 = r1 + (FD ? 0 : 2 * B * ls);                   // 10 lines per row: u pairs
     C2<T> *tw = r2 + kNQ / 2 * B * ls;                       // twiddles in T
     T *qm = reinterpret_cast<T *>(tw + N3);
     T *Mm = qm + kNQ;
@@ -368,7 +367,6 @@ __global__ void __launch_bounds__(kThreads) k_x_assemble(const InstDev *insts, c
         if (k != 0 && 2 * k != N3) line[N3 - k] = mk<T>(y.a.x + y.b.y, -y.a.y + y.b.x);   // conj(a) + i conj(b)
     });
     load_consts<T>(cst, qm, Mm, invm);
-    if constexpr (!FD) load_twiddles<double>(twd, I.p3, reinterpret_cast<const double2 *>(twdv));
     load_twiddles<T>(tw, I.p3, reinterpret_cast<const C2<T> *>(twv));
     __syncthreads();
     fft_lc<T, 1, LC>(r2, I.p3, kNQ / 2 * B, 1, ls, tw);
@@ -409,31 +407,31 @@ __global__ void __launch_bounds__(kThreads) k_x_assemble(const InstDev *insts, c
             gs = (T)2 * nv * lq.Q * lq.dqds * sdu - (T)6 * cs * nv * nv * iq4 * lq.Q * lq.dqds;
         }
         vloc[idx] = vl;
-        const double gsd = (double)gs;
         if constexpr (FD) {
             // w in place of grad n: each point is read and written by its own thread
+            const double gsd = (double)gs;
             const gptr<T> wout = gst(reinterpret_cast<T *>(I.grad) + p0);
             wout[idx] = (T)(gsd * (double)gx);
             wout[N + idx] = (T)(gsd * (double)gy);
             wout[2 * N + idx] = (T)(gsd * (double)gz);
         } else {
-            r1[(2 * rb) * ls + k] = mk<double>(gsd * (double)gx, gsd * (double)gy);
-            r1[(2 * rb + 1) * ls + k] = mk<double>(gsd * (double)gz, 0.0);
+            r1[(2 * rb) * ls + k] = mk<T>(gs * gx, gs * gy);
+            r1[(2 * rb + 1) * ls + k] = mk<T>(gs * gz, (T)0);
         }
     }
     if constexpr (!FD) {
         __syncthreads();
-        fft_lc<double, -1, LC>(r1, I.p3, 2 * B, 1, ls, twd);
-        double2 *out = reinterpret_cast<double2 *>(I.spec3) + (size_t)row0 * N3h * 3;
+        fft_lc<T, -1, LC>(r1, I.p3, 2 * B, 1, ls, tw);
+        C2<T> *out = reinterpret_cast<C2<T> *>(I.spec3) + (size_t)row0 * N3h * 3;
         for (int idx = threadIdx.x; idx < B * N3h * 3; idx += kThreads) {
             const int comp = idx % 3, rest = idx / 3;
             const int k = rest % N3h, rb = rest / N3h;
-            const double2 *Z = r1 + (2 * rb + (comp >> 1)) * ls;
-            const double2 z = Z[k], zc = cconj(Z[(N3 - k) % N3]);
-            double2 y;
-            if (comp != 1) y = mk<double>((z.x + zc.x) * 0.5, (z.y + zc.y) * 0.5);
-            else y = mk<double>((z.y - zc.y) * 0.5, -(z.x - zc.x) * 0.5);
-            out[idx] = y;
+            const C2<T> *Z = r1 + (2 * rb + (comp >> 1)) * ls;
+            const C2<T> z = Z[k], zc = cconj(Z[(N3 - k) % N3]);
+            C2<T> y;
+            if (comp != 1) y = mk<T>((z.x + zc.x) * (T)0.5, (z.y + zc.y) * (T)0.5);
+            else y = mk<T>((z.y - zc.y) * (T)0.5, -(z.x - zc.x) * (T)0.5);
+            gst(out)[idx] = y;
         }
     }
 }
@@ -549,20 +547,20 @@ __global__ void __launch_bounds__(kThreads) k_fd_div(const InstDev *insts, const
     }
 }
 
-// C2R of the FP64 divergence spectrum (row pairs), v = v_loc - div.
+// C2R of the divergence spectrum (row pairs, working precision), v = v_loc - div.
 template <typename T, int LC>
 __global__ void __launch_bounds__(kThreads) k_x_final(const InstDev *insts, const Tile *tiles,
-                                                      const void *twdv) {
+                                                      const void *twv) {
     extern __shared__ __align__(16) unsigned char smem[];
     const Tile t = tiles[blockIdx.x];
     const InstDev &I = insts[t.inst];
     const int N3 = axis_len<LC>(I.n3), N3h = N3 / 2 + 1, row0 = t.a, B = t.b, np = B / 2, ls = N3 + 1;
-    double2 *tw = reinterpret_cast<double2 *>(smem);
-    double2 *buf = tw + N3;
-    const double2 *s1 = reinterpret_cast<const double2 *>(I.spec1) + (size_t)row0 * N3h;
+    C2<T> *tw = reinterpret_cast<C2<T> *>(smem);
+    C2<T> *buf = tw + N3;
+    const C2<T> *s1 = reinterpret_cast<const C2<T> *>(I.spec1) + (size_t)row0 * N3h;
     const int npt = B * N3;
     const gptr<const T> vloc = gld(reinterpret_cast<const T *>(I.vloc) + (size_t)row0 * N3);
-    struct Two { double2 a, b; };
+    struct Two { C2<T> a, b; };
     batched<4>(np * N3, [&](int idx) {
         const int pr = idx / N3, k = idx - pr * N3;
         const int kk = k >= N3h ? N3 - k : k;
@@ -570,16 +568,16 @@ __global__ void __launch_bounds__(kThreads) k_x_final(const InstDev *insts, cons
     }, [&](int idx, Two y) {
         const int pr = idx / N3, k = idx - pr * N3;
         if (k >= N3h) { y.a = cconj(y.a); y.b = cconj(y.b); }
-        buf[pr * ls + k] = mk<double>(y.a.x - y.b.y, y.a.y + y.b.x);
+        buf[pr * ls + k] = mk<T>(y.a.x - y.b.y, y.a.y + y.b.x);
     });
-    load_twiddles<double>(tw, I.p3, reinterpret_cast<const double2 *>(twdv));
+    load_twiddles<T>(tw, I.p3, reinterpret_cast<const C2<T> *>(twv));
     __syncthreads();
-    fft_lc<double, 1, LC>(buf, I.p3, np, 1, ls, tw);
+    fft_lc<T, 1, LC>(buf, I.p3, np, 1, ls, tw);
     const gptr<T> v = gst(reinterpret_cast<T *>(I.v) + (size_t)row0 * N3);
     batched<4>(npt, [&](int idx) { return vloc[idx]; }, [&](int idx, T vl) {
         const int rb = idx / N3, k = idx - rb * N3;
-        const double2 z = buf[(rb >> 1) * ls + k];
-        v[idx] = (T)((double)vl - ((rb & 1) ? z.y : z.x));
+        const C2<T> z = buf[(rb >> 1) * ls + k];
+        v[idx] = vl - ((rb & 1) ? z.y : z.x);
     });
 }
 
@@ -928,12 +926,12 @@ static hipError_t launch_lc(int kind, const LaunchArgs &a) {
         case KY_20F: VDWNL_LAUNCH((k_y<T, -1, LC>), a.tw, 0, kNQ); break;
         case KZ_MAIN: VDWNL_LAUNCH((k_z_main<T, LC>), a.cols, a.tw); break;
         case KY_20I: VDWNL_LAUNCH((k_y<T, 1, LC>), a.tw, 0, kNQ); break;
-        case KX_ASSEMBLE: VDWNL_LAUNCH((k_x_assemble<T, LC, false>), a.cst, a.tw, a.twd); break;
-        case KX_ASSEMBLE_FD: VDWNL_LAUNCH((k_x_assemble<T, LC, true>), a.cst, a.tw, a.twd); break;
-        case KY_3F: VDWNL_LAUNCH((k_y<double, -1, LC>), a.twd, 1, 3); break;
-        case KZ_DIV: VDWNL_LAUNCH((k_z_div<double, LC>), a.twd); break;
-        case KY_1I: VDWNL_LAUNCH((k_y<double, 1, LC>), a.twd, 2, 1); break;
-        case KX_FINAL: VDWNL_LAUNCH((k_x_final<T, LC>), a.twd); break;
+        case KX_ASSEMBLE: VDWNL_LAUNCH((k_x_assemble<T, LC, false>), a.cst, a.tw); break;
+        case KX_ASSEMBLE_FD: VDWNL_LAUNCH((k_x_assemble<T, LC, true>), a.cst, a.tw); break;
+        case KY_3F: VDWNL_LAUNCH((k_y<T, -1, LC>), a.tw, 1, 3); break;
+        case KZ_DIV: VDWNL_LAUNCH((k_z_div<T, LC>), a.tw); break;
+        case KY_1I: VDWNL_LAUNCH((k_y<T, 1, LC>), a.tw, 2, 1); break;
+        case KX_FINAL: VDWNL_LAUNCH((k_x_final<T, LC>), a.tw); break;
         default: return hipErrorInvalidValue;
     }
 #undef VDWNL_LAUNCH
