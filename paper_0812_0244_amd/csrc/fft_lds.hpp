@@ -155,7 +155,12 @@ __device__ __forceinline__ void fft_pass(C2<T> *buf, int L, int nl, int es, int 
 // The caller synchronises before the first fft_lines that reads them.
 template <typename T>
 __device__ __forceinline__ void load_twiddles(C2<T> *dst, const FftPlan &p, const C2<T> *__restrict__ twall) {
-    for (int i = threadIdx.x; i < p.n; i += kThreads) dst[i] = twall[p.tw + i];
+    // the first step's load is unconditional (clamped) and stored last, so it
+    // is not waited for at a branch
+    const int n = p.n;
+    const C2<T> v0 = twall[p.tw + min((int)threadIdx.x, n - 1)];
+    for (int i = threadIdx.x + kThreads; i < n; i += kThreads) dst[i] = twall[p.tw + i];
+    if ((int)threadIdx.x < n) dst[threadIdx.x] = v0;
 }
 
 // Unnormalised DFT of every line: sign -1 forward, +1 inverse; tw holds

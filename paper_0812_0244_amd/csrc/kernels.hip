@@ -158,11 +158,19 @@ struct SplineW {
     }
 };
 
+// q mesh, spline second derivatives and 1/m into LDS; all loads are issued
+// before any store (indices clamped, the stores guarded)
 template <typename T>
 __device__ __forceinline__ void load_consts(const Consts *cst, T *qm, T *Mm, double *invm) {
-    for (int i = threadIdx.x; i < kNQ; i += kThreads) qm[i] = (T)cst->q[i];
-    for (int i = threadIdx.x; i < kNQ * kNQ; i += kThreads) Mm[i] = (T)cst->M[i];
-    for (int i = threadIdx.x; i <= kMaxMc; i += kThreads) invm[i] = cst->invm[i];
+    static_assert(kNQ * kNQ <= 2 * kThreads && kNQ <= kThreads && kMaxMc < kThreads, "one or two steps each");
+    const int i = threadIdx.x, i2 = threadIdx.x + kThreads;
+    const gptr<const double> q = gld(cst->q), M = gld(cst->M), im = gld(cst->invm);
+    const double a = q[min(i, kNQ - 1)], b = M[min(i, kNQ * kNQ - 1)], b2 = M[min(i2, kNQ * kNQ - 1)];
+    const double c = im[min(i, kMaxMc)];
+    if (i < kNQ) qm[i] = (T)a;
+    if (i < kNQ * kNQ) Mm[i] = (T)b;
+    if (i2 < kNQ * kNQ) Mm[i2] = (T)b2;
+    if (i <= kMaxMc) invm[i] = c;
 }
 
 // ---------------------------------------------------------------- axis-3 passes
@@ -226,14 +234,15 @@ __global__ void __launch_bounds__(kThreads) k_x_theta(const InstDev *insts, cons
     const size_t p0 = (size_t)row0 * N3;
     const gptr<const T> nin = gld(reinterpret_cast<const T *>(I.n) + p0);
     const gptr<const T> gin = gld(reinterpret_cast<const T *>(I.grad) + p0);
-    const T n_first = threadIdx.x < npt ? nin[threadIdx.x] : (T)0;
+    // (unconditional loads, clamped to the tile: a load under a branch would
+    // be waited for where the branch joins)
+    const int i_first = min((int)threadIdx.x, npt - 1);
+    const T n_first = nin[i_first];
     T gx_f = (T)0, gy_f = (T)0, gz_f = (T)0;
     if constexpr (FD) {
-        if (threadIdx.x < npt) {
-            gx_f = gin[threadIdx.x];
-            gy_f = gin[N + threadIdx.x];
-            gz_f = gin[2 * N + threadIdx.x];
-        }
+        gx_f = gin[i_first];
+        gy_f = gin[N + i_first];
+        gz_f = gin[2 * N + i_first];
     } else {
         const double2 *s3 = reinterpret_cast<const double2 *>(I.spec3) + (size_t)row0 * N3h * 3;
         struct Three { double2 a, b, c; };
@@ -343,18 +352,16 @@ __global__ void __launch_bounds__(kThreads) k_x_assemble(const InstDev *insts, c
     const size_t p0 = (size_t)row0 * N3;
     const gptr<const T> nin = gld(reinterpret_cast<const T *>(I.n) + p0);
     const gptr<const T> grad = gld(reinterpret_cast<const T *>(I.grad) + p0);
-    T n_f = (T)0, gx_f = (T)0, gy_f = (T)0, gz_f = (T)0;
-    if (threadIdx.x < npt) {
-        n_f = nin[threadIdx.x];
-        gx_f = grad[threadIdx.x];
-        gy_f = grad[N + threadIdx.x];
-        gz_f = grad[2 * N + threadIdx.x];
-    }
+    // (unconditional loads, clamped to the tile: a load under a branch would
+    // be waited for where the branch joins)
+    const int i_first = min((int)threadIdx.x, npt - 1);
+    const T n_f = nin[i_first], gx_f = grad[i_first], gy_f = grad[N + i_first], gz_f = grad[2 * N + i_first];
     const C2<T> *sp = reinterpret_cast<const C2<T> *>(I.spec) + (size_t)row0 * N3h * kNQ;
     // u_{2m} + i u_{2m+1} on pair line m: from the spectra at k (< N3/2 + 1)
     // both the value at k and, by Hermitian symmetry, the value at N3 - k
     struct Two { C2<T> a, b; };
-    batched<4>(B * N3h * (kNQ / 2), [&](int idx) {
+    // about five steps per thread for every length class: one batch of six
+    batched<6>(B * N3h * (kNQ / 2), [&](int idx) {
         const int m = idx % (kNQ / 2), rest = idx / (kNQ / 2);
         const int k = rest % N3h, rb = rest / N3h;
         const gptr<const C2<T>> g = gld(sp + ((size_t)rb * N3h + k) * kNQ + 2 * m);
@@ -705,10 +712,12 @@ __global__ void __launch_bounds__(kThreads) k_z_main(const InstDev *insts, const
     C2<T> *buf = twall + N1;
     const size_t stage_off = ((size_t)(N1 + W * lp) * sizeof(C2<T>) + 15) & ~(size_t)15;
     T *stage = reinterpret_cast<T *>(smem + stage_off);       // [kGroups][kTabStride], 16-byte aligned
-    if (threadIdx.x < K) {
-        const int2 cw = cols[t.a + threadIdx.x];
-        colbase[threadIdx.x] = (cw.x * N3h + cw.y) * kNQ;
-        colk3[threadIdx.x] = cw.y;
+    {
+        const int2 cw = cols[t.a + min((int)threadIdx.x, K - 1)];   // unconditional (clamped) load
+        if (threadIdx.x < K) {
+            colbase[threadIdx.x] = (cw.x * N3h + cw.y) * kNQ;
+            colk3[threadIdx.x] = cw.y;
+        }
     }
     const int2 c0 = cols[t.a];
     __syncthreads();
@@ -738,19 +747,23 @@ __global__ void __launch_bounds__(kThreads) k_z_main(const InstDev *insts, const
         const int rps = kThreads / C;                         // planes per step
         if ((int)threadIdx.x >= rps * C) return;
         const int r0 = threadIdx.x / C, c = threadIdx.x - r0 * C, w = c / kCpc, e = c - w * kCpc;
-        C2<T> *gb = spec + colbase[w] + e * kEpc;
         C2<T> *lb = buf + (w * kNQ + e * kEpc) * lp;
+        // this lane's chunk column; planes l = r0 + s rps, s = j kUnroll + u
+        char *cb = reinterpret_cast<char *>(spec + colbase[w] + e * kEpc);
+        const size_t plane_bytes = plane * sizeof(C2<T>);
         for (int l0 = r0; l0 < N1; l0 += kUnroll * rps) {
             T ra[kUnroll], rb[kUnroll], rc[kUnroll], rd[kUnroll];
+            if (in) {
+                // unconditional loads (a plane past N1 re-reads plane r0, valid here)
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
-                const int l = l0 + u * rps;
-                if (in && l < N1) {
+                for (int u = 0; u < kUnroll; ++u) {
+                    const int l = l0 + u * rps;
+                    const char *src = cb + (size_t)(uint32_t)(l < N1 ? l : r0) * plane_bytes;
                     if constexpr (kEpc == 2) {
-                        const float4 v = gld(reinterpret_cast<const float4 *>(gb + (size_t)l * plane))[0];
+                        const float4 v = gld(reinterpret_cast<const float4 *>(src))[0];
                         ra[u] = v.x; rb[u] = v.y; rc[u] = v.z; rd[u] = v.w;
                     } else {
-                        const C2<T> v = gld(gb + (size_t)l * plane)[0];
+                        const C2<T> v = gld(reinterpret_cast<const C2<T> *>(src))[0];
                         ra[u] = v.x; rb[u] = v.y;
                     }
                 }
@@ -759,14 +772,15 @@ __global__ void __launch_bounds__(kThreads) k_z_main(const InstDev *insts, const
             for (int u = 0; u < kUnroll; ++u) {
                 const int l = l0 + u * rps;
                 if (l >= N1) continue;
+                char *dst = cb + (size_t)(uint32_t)l * plane_bytes;
                 if (in) {
                     lb[l] = mk<T>(ra[u], rb[u]);
                     if constexpr (kEpc == 2) lb[lp + l] = mk<T>(rc[u], rd[u]);
                 } else if constexpr (kEpc == 2) {
                     const C2<T> p0 = lb[l], p1 = lb[lp + l];
-                    gst(reinterpret_cast<float4 *>(gb + (size_t)l * plane))[0] = make_float4(p0.x, p0.y, p1.x, p1.y);
+                    gst(reinterpret_cast<float4 *>(dst))[0] = make_float4(p0.x, p0.y, p1.x, p1.y);
                 } else {
-                    gst(gb + (size_t)l * plane)[0] = lb[l];
+                    gst(reinterpret_cast<C2<T> *>(dst))[0] = lb[l];
                 }
             }
         }
@@ -816,16 +830,21 @@ __global__ void __launch_bounds__(kThreads) k_z_main(const InstDev *insts, const
     fft_lc<T, -1, LC>(buf, I.p1, W, 1, lp, twall);
 
     T *st = stage + (size_t)(lane_on ? gid : 0) * kTabStride;
-    // position of phi_{al, b} in the packed row (row-by-row upper triangle)
+    // position of phi_{al, b} in the packed row (row-by-row upper triangle):
+    // row b, column al for b <= al, else row al, column b; with the row
+    // starts s_r = r kNQ - r (r - 1) / 2 that is s_b - b + al or s_al - al + b
+    // (b is a compile-time constant in the unrolled loop)
+    const int s_al = al * kNQ - (al * (al - 1)) / 2 - al;
     int foff[kNQ];
 #pragma unroll
-    for (int b = 0; b < kNQ; ++b) {
-        const int lo = al < b ? al : b, hi = al < b ? b : al;
-        foff[b] = lo * kNQ - (lo * (lo - 1)) / 2 + (hi - lo);
-    }
+    for (int b = 0; b < kNQ; ++b) foff[b] = b <= al ? (b * kNQ - (b * (b - 1)) / 2 - b) + al : s_al + b;
     const T inv_n = (T)I.inv_n;
     const double wn = (double)inv_n * (double)inv_n;
+    const int cstride = kNQ * lp;                             // LDS elements per column
     double e = 0.0;
+    // item it = m1 P + pr, stepped by kGroups without divisions
+    const int dm = kGroups / P, dr = kGroups - dm * P;
+    int m1 = gid / P, pr = gid - m1 * P;
     // A group's lanes share one wave, so staging, reads of theta and writes
     // of u need wave-level ordering only.
     for (int it = gid; lane_on && it < nitems; it += kGroups) {
@@ -847,14 +866,18 @@ __global__ void __launch_bounds__(kThreads) k_z_main(const InstDev *insts, const
         T f[kNQ];
 #pragma unroll
         for (int b = 0; b < kNQ; ++b) f[b] = st[foff[b]];
-        const int m1 = it / P, pr = it - m1 * P;
         const int l = m1;
         int lq = N1 - m1;
         if (m1 == 0 || lq == m1) lq = -1;     // k1 = 0 and the Nyquist plane stand alone
-        for (int w = pr * CP; w < (pr + 1) * CP; ++w) {
+        const int w0 = __mul24(pr, CP);
+        m1 += dm;
+        pr += dr;
+        if (pr >= P) { pr -= P; ++m1; }
+        for (int w = w0; w < w0 + CP; ++w) {
             C2<T> u1 = mk<T>((T)0, (T)0), u2 = u1;
-            C2<T> *x1 = buf + w * kNQ * lp + l;                   // component b at x1[b lp]
-            C2<T> *x2 = buf + w * kNQ * lp + (lq >= 0 ? lq : l);
+            C2<T> *xc = buf + __mul24(w, cstride);
+            C2<T> *x1 = xc + l;                                   // component b at x1[b lp]
+            C2<T> *x2 = xc + (lq >= 0 ? lq : l);
 #pragma unroll
             for (int b = 0; b < kNQ; ++b) {
                 const C2<T> t1 = x1[b * lp], t2 = x2[b * lp];

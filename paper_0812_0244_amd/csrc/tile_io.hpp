@@ -1,7 +1,11 @@
 // Copies between global memory and LDS tiles.  Each thread issues a batch of
 // U independent loads before it writes any of them to LDS, so a wave keeps
 // U requests per lane in flight instead of waiting on each one; row/column
-// indices advance incrementally (no integer division per element).
+// indices advance incrementally (no integer division per element).  The
+// loads of a batch are unconditional (a load under a branch, even a
+// wave-uniform one, is waited for where the branch joins, so the batch would
+// go out one load at a time): a step past the end of the tile re-reads the
+// tile's first element and its value is dropped.
 #pragma once
 
 #include "fft_fast.hpp"
@@ -57,11 +61,9 @@ __device__ __forceinline__ void rows_in(E *lds, int lstr, const E *__restrict__ 
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const bool on = base + u * kThreads < total;
-            if (on) {
-                const E v = gld(g)[(size_t)cur.l * gstr + cur.w];
-                rx[u] = v.x;
-                ry[u] = v.y;
-            }
+            const E v = gld(g)[on ? (size_t)cur.l * gstr + cur.w : 0];
+            rx[u] = v.x;
+            ry[u] = v.y;
             o[u] = on ? cur.l * lstr + cur.w : -1;
             cur.step();
         }
@@ -106,7 +108,7 @@ __device__ __forceinline__ void rows_in_c(float2 *lds, int lstr, const float2 *_
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const bool on = base + u * kThreads < total;
-            if (on) r[u] = gld(gp)[(size_t)cur.l * gp_str + cur.w];
+            r[u] = gld(gp)[on ? (size_t)cur.l * gp_str + cur.w : 0];
             o[u] = on ? cur.l * lstr + 2 * cur.w : -1;
             cur.step();
         }
@@ -151,14 +153,12 @@ __device__ __forceinline__ void rows_in_t(float2 *lds, int lpitch, const float2 
         for (int base = threadIdx.x; base < total; base += U * kThreads) {
             float rx[U], ry[U];
             int o[U];
-#pragma unroll
+    #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const bool on = base + u * kThreads < total;
-                if (on) {
-                    const float2 v = gld(g)[(size_t)cur.l * gstr + cur.w];
-                    rx[u] = v.x;
-                    ry[u] = v.y;
-                }
+                const float2 v = gld(g)[on ? (size_t)cur.l * gstr + cur.w : 0];
+                rx[u] = v.x;
+                ry[u] = v.y;
                 o[u] = on ? cur.w * lpitch + cur.l : -1;
                 cur.step();
             }
@@ -178,7 +178,7 @@ __device__ __forceinline__ void rows_in_t(float2 *lds, int lpitch, const float2 
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const bool on = base + u * kThreads < total;
-            if (on) r[u] = gld(gp)[(size_t)cur.l * gp_str + cur.w];
+            r[u] = gld(gp)[on ? (size_t)cur.l * gp_str + cur.w : 0];
             o[u] = on ? 2 * cur.w * lpitch + cur.l : -1;
             cur.step();
         }
@@ -233,11 +233,9 @@ __device__ __forceinline__ void rows_in_t(double2 *lds, int lpitch, const double
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const bool on = base + u * kThreads < total;
-            if (on) {
-                const double2 v = gld(g)[(size_t)cur.l * gstr + cur.w];
-                rx[u] = v.x;
-                ry[u] = v.y;
-            }
+            const double2 v = gld(g)[on ? (size_t)cur.l * gstr + cur.w : 0];
+            rx[u] = v.x;
+            ry[u] = v.y;
             o[u] = on ? cur.w * lpitch + cur.l : -1;
             cur.step();
         }
@@ -277,15 +275,15 @@ __device__ __forceinline__ void crows_out(double2 *g, size_t gstr, const double2
 
 // Generic batched loop: for i < total (i = threadIdx.x + k kThreads), the
 // loads of U consecutive iterations (ld(i) -> value) are issued before any
-// of their consumers (st(i, value)) run.
+// of their consumers (st(i, value)) run.  ld is called for every step, past
+// the end with i = total - 1 (it must be a pure load).
 template <int U, typename LD, typename ST>
 __device__ __forceinline__ void batched(int total, LD ld, ST st) {
     using R = decltype(ld(0));
     for (int base = threadIdx.x; base < total; base += U * kThreads) {
         R r[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-            if (base + u * kThreads < total) r[u] = ld(base + u * kThreads);
+        for (int u = 0; u < U; ++u) r[u] = ld(min(base + u * kThreads, total - 1));
 #pragma unroll
         for (int u = 0; u < U; ++u)
             if (base + u * kThreads < total) st(base + u * kThreads, r[u]);
