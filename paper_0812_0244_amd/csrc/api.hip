@@ -903,7 +903,7 @@ int vdwnl_set_kernel_table(vdwnl_ctx *ctx, int32_t nq, const double *qmesh, doub
     // cardinal splines p_a: M[j][a] = second derivative at q_j of the spline through e_a
     Consts &k = ctx->consts;
     std::memset(&k, 0, sizeof(k));
-    k.qc = q_c; k.cs = c_soft; k.nmin = 1e-30; k.mc = m_c; k.nq = nq;
+    k.qc = q_c; k.iqc = 1.0 / q_c; k.cs = c_soft; k.nmin = 1e-30; k.mc = m_c; k.nq = nq;
     std::vector<double> e(nq), d2(nq);
     for (int a = 0; a < nq; ++a) {
         std::fill(e.begin(), e.end(), 0.0);

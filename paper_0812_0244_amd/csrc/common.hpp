@@ -61,6 +61,7 @@ struct InstDev {
 // Method constants (copied into LDS by the kernels that need them).
 struct Consts {
     double qc;
+    double iqc;              // 1 / q_c
     double cs;               // C_s
     double nmin;
     int mc;

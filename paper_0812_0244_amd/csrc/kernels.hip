@@ -32,10 +32,23 @@ template <> __device__ __forceinline__ double dev_sqrt(double x) { return sqrt(x
 // 1/x: the hardware reciprocal in FP32 (within 1 ulp), a division in FP64
 template <typename T> __device__ __forceinline__ T rcp(T x);
 template <> __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-template <> __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+// FP64: the hardware estimate refined by two Newton-Raphson steps
+// r <- r + r (1 - x r) (each doubles the correct bits; within an ulp or so
+// of 1/x for normal x, against about fifteen instructions for a division)
+template <> __device__ __forceinline__ double rcp(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
+}
 template <typename T> __device__ __forceinline__ T dev_log1p(T x);
 template <> __device__ __forceinline__ float dev_log1p(float x) { return log1pf(x); }
 template <> __device__ __forceinline__ double dev_log1p(double x) { return log1p(x); }
+template <typename T> __device__ __forceinline__ T dev_exp(T x);
+template <> __device__ __forceinline__ float dev_exp(float x) { return expf(x); }
+template <> __device__ __forceinline__ double dev_exp(double x) { return exp(x); }
+template <typename T> __device__ __forceinline__ T dev_expm1(T x);
+template <> __device__ __forceinline__ float dev_expm1(float x) { return expm1f(x); }
+template <> __device__ __forceinline__ double dev_expm1(double x) { return expm1(x); }
 
 // signed frequency index of position k on an axis of N points, 0 at Nyquist
 __device__ __forceinline__ int freq_nz(int k, int N) {
@@ -62,12 +75,12 @@ __device__ double block_sum(double v) {
 // ---------------------------------------------------------------- q0 and the spline basis
 
 // q0(n, |grad n|^2) before saturation and its partials (Dion et al. form,
-// Perdew-Wang 1992 correlation); the saturation of Eq. (Sat) in FP64.
+// Perdew-Wang 1992 correlation), then the saturation of Eq. (Sat).
 template <typename T, bool DERIV>
 struct LocalQ {
     T q0, Q, dqdn, dqds;
 
-    __device__ __forceinline__ void eval(T n, T sigma, double qc, int mc, const double *invm) {
+    __device__ __forceinline__ void eval(T n, T sigma, double qc, double iqc, int mc, const T *invm) {
         const T pi = (T)3.14159265358979323846;
         const T A = (T)0.031091, a1 = (T)0.21370;
         const T b1 = (T)7.5957, b2 = (T)3.5876, b3 = (T)1.6382, b4 = (T)0.49294;
@@ -91,26 +104,24 @@ struct LocalQ {
             dqdn = kf * in * ((T)1 / (T)3) - ((T)4 * pi / (T)3) * deps_dn - ((T)7 / (T)3) * grad_term * in;
             dqds = zg * ikfn2;
         }
-        // h(x, x_c) = x_c (1 - exp(-sum_{m<=m_c} (x/x_c)^m / m)), dh/dx = exp(-S) sum_{m<m_c} (x/x_c)^m
-        const double y = (double)qraw / qc;
-        if (y > 64.0) {
-            q0 = (T)qc;
-            Q = (T)0;
-            return;
-        }
-        double S = 0.0;
+        // h(x, x_c) = x_c (1 - exp(-S)), S = sum_{m<=m_c} (x/x_c)^m / m (Horner),
+        // dh/dx = exp(-S) sum_{m<m_c} (x/x_c)^m.  1 - exp(-S) as -expm1(-S)
+        // keeps its relative accuracy for small S.  S from 80 up (exp(-S) <
+        // 2e-35), or overflowing, saturates: h = x_c, dh/dx = 0.  Below that
+        // the derivative series stays under 80 m_c^2: no overflow in FP32.
+        const T y = qraw * (T)iqc;
+        T S = (T)0;
         for (int m = mc; m >= 1; --m) S = S * y + invm[m];
         S *= y;
-        if (S > 700.0) {
+        if (!(S < (T)80)) {
             q0 = (T)qc;
             Q = (T)0;
         } else {
-            const double e = exp(-S);
-            q0 = (T)(qc * (1.0 - e));
+            q0 = (T)(-qc) * dev_expm1<T>(-S);
             if (DERIV) {
-                double D = 0.0;
-                for (int m = mc - 1; m >= 0; --m) D = D * y + 1.0;
-                Q = (T)(e * D);
+                T D = (T)0;
+                for (int m = mc - 1; m >= 0; --m) D = D * y + (T)1;
+                Q = dev_exp<T>(-S) * D;
             } else {
                 Q = (T)0;
             }
@@ -143,25 +154,25 @@ struct SplineW {
         }
         j = lo;
         const T ql = qm[lo], qh = qm[lo + 1];
-        const T h = qh - ql, ih = rcp<T>(h);
+        const T h = qh - ql, ih = rcp<T>(h), h6 = h * (T)(1.0 / 6.0);
         const T a = below ? (T)1 : (qh - q0) * ih;
         const T b = (T)1 - a;
         const T dq = below ? q0 - ql : (T)0;
         B0 = -ih;
         B1 = ih;
-        D0 = ((T)1 - (T)3 * a * a) * h / (T)6;
-        D1 = ((T)3 * b * b - (T)1) * h / (T)6;
+        D0 = ((T)1 - (T)3 * a * a) * h6;
+        D1 = ((T)3 * b * b - (T)1) * h6;
         A0 = a + dq * B0;
         A1 = b + dq * B1;
-        C0 = (a * a * a - a) * h * h / (T)6 + dq * D0;
-        C1 = (b * b * b - b) * h * h / (T)6 + dq * D1;
+        C0 = (a * a * a - a) * h * h6 + dq * D0;
+        C1 = (b * b * b - b) * h * h6 + dq * D1;
     }
 };
 
-// q mesh, spline second derivatives and 1/m into LDS; all loads are issued
-// before any store (indices clamped, the stores guarded)
+// q mesh, spline second derivatives and 1/m into LDS (in T); all loads are
+// issued before any store (indices clamped, the stores guarded)
 template <typename T>
-__device__ __forceinline__ void load_consts(const Consts *cst, T *qm, T *Mm, double *invm) {
+__device__ __forceinline__ void load_consts(const Consts *cst, T *qm, T *Mm, T *invm) {
     static_assert(kNQ * kNQ <= 2 * kThreads && kNQ <= kThreads && kMaxMc < kThreads, "one or two steps each");
     const int i = threadIdx.x, i2 = threadIdx.x + kThreads;
     const gptr<const double> q = gld(cst->q), M = gld(cst->M), im = gld(cst->invm);
@@ -170,7 +181,7 @@ __device__ __forceinline__ void load_consts(const Consts *cst, T *qm, T *Mm, dou
     if (i < kNQ) qm[i] = (T)a;
     if (i < kNQ * kNQ) Mm[i] = (T)b;
     if (i2 < kNQ * kNQ) Mm[i2] = (T)b2;
-    if (i <= kMaxMc) invm[i] = c;
+    if (i <= kMaxMc) invm[i] = (T)c;
 }
 
 // ---------------------------------------------------------------- axis-3 passes
@@ -227,7 +238,7 @@ __global__ void __launch_bounds__(kThreads) k_x_theta(const InstDev *insts, cons
     C2<T> *tw = r2 + kNQ / 2 * B * ls;                       // twiddles in T
     T *qm = reinterpret_cast<T *>(tw + N3);
     T *Mm = qm + kNQ;
-    double *invm = reinterpret_cast<double *>(Mm + kNQ * kNQ);   // 8-byte aligned: every part before is
+    T *invm = Mm + kNQ * kNQ;
     // density (and FD: grad n) of this thread's first point, fetched first
     // (used after the FFT or the constants)
     const int npt = B * N3;
@@ -265,7 +276,7 @@ __global__ void __launch_bounds__(kThreads) k_x_theta(const InstDev *insts, cons
     __syncthreads();
     if constexpr (!FD) fft_lc<double, 1, LC>(r1, I.p3, 2 * B, 1, ls, twd);
 
-    const double c_qc = cst->qc, c_cs = cst->cs, c_nmin = cst->nmin;
+    const double c_qc = cst->qc, c_iqc = cst->iqc, c_cs = cst->cs, c_nmin = cst->nmin;
     const int c_mc = cst->mc;
     const gptr<T> grad = gst(reinterpret_cast<T *>(I.grad));
     double de = 0.0;
@@ -289,18 +300,18 @@ __global__ void __launch_bounds__(kThreads) k_x_theta(const InstDev *insts, cons
         T *th = reinterpret_cast<T *>(r2 + (size_t)(kNQ / 2 * rb) * ls);   // pair line m at th + 2 m ls
         if (nv >= (T)c_nmin) {
             LocalQ<T, false> lq;
-            lq.eval(nv, g01.x * g01.x + g01.y * g01.y + g2.x * g2.x, c_qc, c_mc, invm);
+            lq.eval(nv, g01.x * g01.x + g01.y * g01.y + g2.x * g2.x, c_qc, c_iqc, c_mc, invm);
             SplineW<T> sw;
             sw.locate(lq.q0, qm, kNQ);
             const T *Mj = Mm + sw.j * kNQ;
-            const T nA0 = nv * sw.A0, nA1 = nv * sw.A1, nC0 = nv * sw.C0, nC1 = nv * sw.C1;
+            const T nC0 = nv * sw.C0, nC1 = nv * sw.C1;
 #pragma unroll
-            for (int al = 0; al < kNQ; ++al) {
-                T v = nC0 * Mj[al] + nC1 * Mj[kNQ + al];
-                v += (al == sw.j) ? nA0 : (T)0;
-                v += (al == sw.j + 1) ? nA1 : (T)0;
-                th[2 * ((al >> 1) * ls + k) + (al & 1)] = v;
-            }
+            for (int al = 0; al < kNQ; ++al) th[2 * ((al >> 1) * ls + k) + (al & 1)] = nC0 * Mj[al] + nC1 * Mj[kNQ + al];
+            // the interpolating parts A0 d_aj + A1 d_a,j+1 touch two components:
+            // rewrite those two (same thread, so after the loop's stores)
+            const int j0 = sw.j, j1 = sw.j + 1;
+            th[2 * ((j0 >> 1) * ls + k) + (j0 & 1)] = nC0 * Mj[j0] + nC1 * Mj[kNQ + j0] + nv * sw.A0;
+            th[2 * ((j1 >> 1) * ls + k) + (j1 & 1)] = nC0 * Mj[j1] + nC1 * Mj[kNQ + j1] + nv * sw.A1;
             const T iq = rcp<T>(lq.q0);
             de += (double)((T)c_cs * nv * nv * iq * iq * iq);
         } else {
@@ -312,16 +323,17 @@ __global__ void __launch_bounds__(kThreads) k_x_theta(const InstDev *insts, cons
     fft_lc<T, -1, LC>(r2, I.p3, kNQ / 2 * B, 1, ls, tw);
 
     // pair line m of row rb holds theta_{2m} + i theta_{2m+1}: its values at
-    // k and N3 - k give both spectra at k, written together
+    // k and N3 - k give both spectra at k, written together (item idx =
+    // (rb N3h + k) 10 + m lands at spectrum element 2 idx)
     C2<T> *out = reinterpret_cast<C2<T> *>(I.spec) + (size_t)row0 * N3h * kNQ;
-    for (int idx = threadIdx.x; idx < B * N3h * (kNQ / 2); idx += kThreads) {
-        const int m = idx % (kNQ / 2), rest = idx / (kNQ / 2);
-        const int k = rest % N3h, rb = rest / N3h;
+    Cursor3 cur(threadIdx.x, kNQ / 2, N3h);
+    for (int idx = threadIdx.x; idx < B * N3h * (kNQ / 2); idx += kThreads, cur.step()) {
+        const int m = cur.m, k = cur.k, rb = cur.r;
         const C2<T> *Z = r2 + (kNQ / 2 * rb + m) * ls;
         const C2<T> z = Z[k], zc = cconj(Z[k == 0 ? 0 : N3 - k]);
         const T ex = (z.x + zc.x) * (T)0.5, ey = (z.y + zc.y) * (T)0.5;
         const T ox = (z.y - zc.y) * (T)0.5, oy = -(z.x - zc.x) * (T)0.5;
-        C2<T> *o = out + (size_t)(rb * N3h + k) * kNQ + 2 * m;
+        C2<T> *o = out + 2 * (size_t)idx;
         if constexpr (sizeof(T) == 4) gst(reinterpret_cast<float4 *>(o))[0] = make_float4(ex, ey, ox, oy);
         else { gst(o)[0] = mk<T>(ex, ey); gst(o)[1] = mk<T>(ox, oy); }
     }
@@ -346,7 +358,7 @@ __global__ void __launch_bounds__(kThreads) k_x_assemble(const InstDev *insts, c
     C2<T> *tw = r2 + kNQ / 2 * B * ls;                       // twiddles in T
     T *qm = reinterpret_cast<T *>(tw + N3);
     T *Mm = qm + kNQ;
-    double *invm = reinterpret_cast<double *>(Mm + kNQ * kNQ);   // 8-byte aligned: every part before is
+    T *invm = Mm + kNQ * kNQ;
     // n and grad n of this thread's first point, fetched first (used after the FFT)
     const int npt = B * N3;
     const size_t p0 = (size_t)row0 * N3;
@@ -359,26 +371,44 @@ __global__ void __launch_bounds__(kThreads) k_x_assemble(const InstDev *insts, c
     const C2<T> *sp = reinterpret_cast<const C2<T> *>(I.spec) + (size_t)row0 * N3h * kNQ;
     // u_{2m} + i u_{2m+1} on pair line m: from the spectra at k (< N3/2 + 1)
     // both the value at k and, by Hermitian symmetry, the value at N3 - k
-    struct Two { C2<T> a, b; };
-    // about five steps per thread for every length class: one batch of six
-    batched<6>(B * N3h * (kNQ / 2), [&](int idx) {
-        const int m = idx % (kNQ / 2), rest = idx / (kNQ / 2);
-        const int k = rest % N3h, rb = rest / N3h;
-        const gptr<const C2<T>> g = gld(sp + ((size_t)rb * N3h + k) * kNQ + 2 * m);
-        return Two{g[0], g[1]};
-    }, [&](int idx, Two y) {
-        const int m = idx % (kNQ / 2), rest = idx / (kNQ / 2);
-        const int k = rest % N3h, rb = rest / N3h;
-        C2<T> *line = r2 + (kNQ / 2 * rb + m) * ls;
-        line[k] = mk<T>(y.a.x - y.b.y, y.a.y + y.b.x);
-        if (k != 0 && 2 * k != N3) line[N3 - k] = mk<T>(y.a.x + y.b.y, -y.a.y + y.b.x);   // conj(a) + i conj(b)
-    });
+    // item idx = (rb N3h + k) 10 + m reads spectrum elements 2 idx, 2 idx + 1;
+    // about five steps per thread for every length class: batches of six
+    {
+        constexpr int U = 6;
+        const int total = B * N3h * (kNQ / 2);
+        Cursor3 cur(threadIdx.x, kNQ / 2, N3h);
+        const gptr<const C2<T>> g = gld(sp);
+        for (int base = threadIdx.x; base < total; base += U * kThreads) {
+            C2<T> ya[U], yb[U];
+            int lo[U], kk[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int idx = base + u * kThreads;
+                const bool on = idx < total;
+                const size_t e = on ? 2 * (size_t)idx : 0;   // (unconditional loads)
+                ya[u] = g[e];
+                yb[u] = g[e + 1];
+                lo[u] = on ? (kNQ / 2 * cur.r + cur.m) * ls : -1;
+                kk[u] = cur.k;
+                cur.step();
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (lo[u] < 0) continue;
+                C2<T> *line = r2 + lo[u];
+                const int k = kk[u];
+                const C2<T> a = ya[u], b = yb[u];
+                line[k] = mk<T>(a.x - b.y, a.y + b.x);
+                if (k != 0 && 2 * k != N3) line[N3 - k] = mk<T>(a.x + b.y, -a.y + b.x);   // conj(a) + i conj(b)
+            }
+        }
+    }
     load_consts<T>(cst, qm, Mm, invm);
     load_twiddles<T>(tw, I.p3, reinterpret_cast<const C2<T> *>(twv));
     __syncthreads();
     fft_lc<T, 1, LC>(r2, I.p3, kNQ / 2 * B, 1, ls, tw);
 
-    const double c_qc = cst->qc, c_cs = cst->cs, c_nmin = cst->nmin;
+    const double c_qc = cst->qc, c_iqc = cst->iqc, c_cs = cst->cs, c_nmin = cst->nmin;
     const int c_mc = cst->mc;
     const gptr<T> vloc = gst(reinterpret_cast<T *>(I.vloc) + p0);
     for (int idx = threadIdx.x; idx < npt; idx += kThreads) {
@@ -389,7 +419,7 @@ __global__ void __launch_bounds__(kThreads) k_x_assemble(const InstDev *insts, c
         T vl = (T)0, gs = (T)0;
         if (nv >= (T)c_nmin) {
             LocalQ<T, true> lq;
-            lq.eval(nv, gx * gx + gy * gy + gz * gz, c_qc, c_mc, invm);
+            lq.eval(nv, gx * gx + gy * gy + gz * gz, c_qc, c_iqc, c_mc, invm);
             SplineW<T> sw;
             sw.locate(lq.q0, qm, kNQ);
             const T *u = reinterpret_cast<const T *>(r2 + (size_t)(kNQ / 2 * rb) * ls);

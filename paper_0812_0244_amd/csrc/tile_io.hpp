@@ -48,6 +48,30 @@ struct RowCursor {
     }
 };
 
+// Position (r, k, m) of flat index i = (r K + k) M + m, advanced by kThreads
+// per step (k < K, m < M).
+struct Cursor3 {
+    int m, k, r, M, K, dm, dk, dr;
+    __device__ __forceinline__ Cursor3(int i, int M_, int K_) : M(M_), K(K_) {
+        const int rest = i / M_;
+        m = i - rest * M_;
+        r = rest / K_;
+        k = rest - r * K_;
+        const int q = kThreads / M_;
+        dm = kThreads - q * M_;
+        dr = q / K_;
+        dk = q - dr * K_;
+    }
+    __device__ __forceinline__ void step() {
+        m += dm;
+        const int c = m >= M ? 1 : 0;
+        m -= c * M;
+        k += dk + c;
+        r += dr;
+        if (k >= K) { k -= K; ++r; }
+    }
+};
+
 // lds[l * lstr + w] = g[l * gstr + w], l < nrows, w < W (E: float2 or double2).
 template <typename E, int U = kUnroll>
 __device__ __forceinline__ void rows_in(E *lds, int lstr, const E *__restrict__ g, size_t gstr, int nrows, int W) {
