@@ -40,13 +40,13 @@ def pass_bytes(name, shapes, s):
             "y_1f": 2 * NH * d, "y_1i": 2 * NH * c,
             "z_grad": 4 * NH * d, "z_div": 4 * NH * c,
             "y_3i": 6 * NH * d, "y_3f": 6 * NH * c,
-            "x_theta": 3 * NH * d + 4 * N * s + 20 * NH * c,
+            "x_grad": 3 * NH * d + 3 * N * s,
+            "x_theta": 4 * N * s + 20 * NH * c,
             "y_20f": 40 * NH * c, "z_main": 40 * NH * c, "y_20i": 40 * NH * c,
             "x_assemble": 20 * NH * c + 5 * N * s + 3 * NH * c,
             "x_final": NH * c + 2 * N * s,
             # finite-difference gradient mode
             "fd_grad": 4 * N * s,
-            "x_theta_fd": 4 * N * s + 20 * NH * c,
             "x_assemble_fd": 20 * NH * c + 8 * N * s,
             "fd_div": 5 * N * s,
             "reduce": 0,
@@ -206,7 +206,7 @@ def main():
     path_bytes = sum(pass_bytes(k, shapes, 4) for k in passes)
 
     # ---- the same workload with the finite-difference gradient (the paper's
-    # own choice; seven passes instead of thirteen), FP32 batched
+    # own choice; seven passes instead of fourteen), FP32 batched
     del lib
     fd = None
     if args.fd_mode > 0:
@@ -307,7 +307,7 @@ def main():
             "total_points": total,
             "precision": "theta/u FFTs, contraction and divergence chain FP32; grad n chain and "
                          "reductions FP64",
-            "launch": "one HIP graph per call (13 passes x FFT length classes), tile LDS budgets "
+            "launch": "one HIP graph per call (14 passes x FFT length classes), tile LDS budgets "
                       "tuned at setup",
             "lds_budgets": tiling,
         },

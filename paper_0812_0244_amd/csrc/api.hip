@@ -88,6 +88,7 @@ struct Grid {
     FftPlan p1, p2, p3;
     int bmain;               // rows per theta / assemble tile
     int bnf;                 // rows per n-forward / final tile (even)
+    int bgr;                 // rows per grad n C2R tile (even)
     int k3main, k3aux;       // k3 per fused axis-1 tile (20 comps), per grad/div tile
     int wy20, wy3, wy1;      // axis-2 tile widths
     int shell_key;           // index into Ctx::shells
@@ -207,17 +208,18 @@ static bool smooth235(int n) {
 }
 
 // LDS of one theta / assembly tile of b rows: the 20 fields' pair lines,
-// twiddles and method constants; with the spectral gradient also two lines
-// per row of grad n (FP64, with FP64 twiddles: XL_THETA) or of w (working
-// precision: XL_ASSEMBLE).
-enum XLayout { XL_THETA = 0, XL_ASSEMBLE, XL_FD };
+// twiddles and method constants; the spectral assembly pass also holds two
+// lines per row of w (XL_ASSEMBLE).
+enum XLayout { XL_PLAIN = 0, XL_ASSEMBLE };
 static size_t xpass_lds(int layout, size_t b, size_t N3, size_t rs) {
     const size_t cs = 2 * rs;
     const size_t base = b * (N3 + 1) * (kNQ / 2) * cs + N3 * cs + (kNQ + kNQ * kNQ) * rs + (kMaxMc + 1) * 8;
-    if (layout == XL_THETA) return base + b * (N3 + 1) * 2 * 16 + N3 * 16;
-    if (layout == XL_ASSEMBLE) return base + b * (N3 + 1) * 2 * cs;
-    return base;
+    return layout == XL_ASSEMBLE ? base + b * (N3 + 1) * 2 * cs : base;
 }
+
+// LDS of one grad n C2R tile of b rows (even): 3 FP64 lines per row pair and
+// FP64 twiddles.
+static size_t xgrad_lds(size_t b, size_t N3) { return (N3 + 3 * (b / 2) * (N3 + 1)) * 16; }
 
 static int check_grid(vdwnl_ctx *c, const int32_t *shape, const double *cell, int precision, Grid &g) {
     const size_t cs = precision == 64 ? 16 : 8, rs = precision == 64 ? 8 : 4;
@@ -236,7 +238,7 @@ static int check_grid(vdwnl_ctx *c, const int32_t *shape, const double *cell, in
     const size_t stage = (size_t)((kThreads / 64) * (64 / kNQ)) * kTabStride * rs;
     auto zmain = [&](size_t k3) { return (N1 + kNQ * k3 * (N1 | 1)) * cs + 16 + stage + (N1 / 2 + 1) * k3 * sizeof(int); };
     auto zaux = [&](size_t k3) { return (N1 + 4 * k3 * (N1 | 1)) * 16; };
-    auto xmain = [&](size_t b) { return xpass_lds(XL_THETA, b, N3, rs); };   // the largest layout
+    auto xmain = [&](size_t b) { return xpass_lds(XL_ASSEMBLE, b, N3, rs); };   // the larger layout
     auto ypass = [&](size_t w, size_t c2) { return (N2 + (N2 | 1) * w) * c2; };
     const size_t cap = c->lds_cap;
     if (N1 > (size_t)kMaxN1 || zmain(1) > cap)
@@ -258,7 +260,7 @@ static void size_tiles(const vdwnl_ctx *c, Grid &g) {
     const size_t stage = (size_t)((kThreads / 64) * (64 / kNQ)) * kTabStride * rs;
     auto zmain = [&](size_t k3) { return (N1 + kNQ * k3 * (N1 | 1)) * cs + 16 + stage + (N1 / 2 + 1) * k3 * sizeof(int); };
     auto zaux = [&](size_t k3) { return (N1 + 4 * k3 * (N1 | 1)) * 16; };
-    auto xmain = [&](size_t b) { return xpass_lds(c->grad_mode ? XL_FD : XL_THETA, b, N3, rs); };
+    auto xmain = [&](size_t b) { return xpass_lds(c->grad_mode ? XL_PLAIN : XL_ASSEMBLE, b, N3, rs); };
     auto ypass = [&](size_t w, size_t c2) { return (N2 + (N2 | 1) * w) * c2; };
     // complex elements per LDS FFT tile: bounded for the runtime-radix FFT
     // (its per-thread register arrays), not for the compile-time plans
@@ -275,6 +277,11 @@ static void size_tiles(const vdwnl_ctx *c, Grid &g) {
     while ((size_t)(g.bnf + 2) * N3 <= 4096 && (size_t)(g.bnf / 2 + 1) * N3 <= cap(N3) &&
            (N3 + (size_t)(g.bnf / 2 + 1) * (N3 + 1)) * 16 <= kLdsCap)
         g.bnf += 2;
+    // grad n C2R tiles: up to 4096 points in at most 32 KB of FP64 lines
+    g.bgr = 2;
+    while ((size_t)(g.bgr + 2) * N3 <= 4096 && (size_t)3 * (g.bgr / 2 + 1) * N3 <= cap(N3) &&
+           xgrad_lds(g.bgr + 2, N3) <= 32768)
+        g.bgr += 2;
     g.k3main = 1;
     while (g.k3main < kMaxCols && (size_t)kNQ * (g.k3main + 1) * N1 <= cap(N1) && zmain(g.k3main + 1) <= c->pref[TG_Z])
         ++g.k3main;
@@ -384,13 +391,13 @@ static int check_krange(vdwnl_ctx *c) {
 }
 
 // Launch order of the passes of one evaluation (the final reduction follows):
-// spectral gradient (thirteen passes) or finite differences (seven).
-static const int kOrderSpectral[] = {KX_NFWD, KY_1F, KZ_GRAD, KY_3I, KX_THETA, KY_20F, KZ_MAIN,
-                                     KY_20I, KX_ASSEMBLE, KY_3F, KZ_DIV, KY_1I, KX_FINAL};
-static const int kOrderFd[] = {KF_GRAD, KX_THETA_FD, KY_20F, KZ_MAIN, KY_20I, KX_ASSEMBLE_FD, KF_DIV};
+// spectral gradient (fourteen passes) or finite differences (seven).
+static const int kOrderSpectral[] = {KX_NFWD, KY_1F, KZ_GRAD, KY_3I, KX_GRAD, KX_THETA, KY_20F,
+                                     KZ_MAIN, KY_20I, KX_ASSEMBLE, KY_3F, KZ_DIV, KY_1I, KX_FINAL};
+static const int kOrderFd[] = {KF_GRAD, KX_THETA, KY_20F, KZ_MAIN, KY_20I, KX_ASSEMBLE_FD, KF_DIV};
 static const char *kPassName[KIND_COUNT + 1] = {
     "x_nfwd", "y_1f", "z_grad", "y_3i", "x_theta", "y_20f", "z_main", "y_20i", "x_assemble", "y_3f", "z_div",
-    "y_1i", "x_final", "fd_grad", "x_theta_fd", "x_assemble_fd", "fd_div", "reduce"};
+    "y_1i", "x_final", "fd_grad", "x_grad", "x_assemble_fd", "fd_div", "reduce"};
 
 static int pass_order(int grad_mode, const int **order) {
     if (grad_mode == 0) {
@@ -474,10 +481,12 @@ static int prepare_device(vdwnl_ctx *c) {
         int slot = 0;
         for (int r = 0; r < rows; r += g.bmain) {
             const int b = std::min(g.bmain, rows - r);
-            tiles[fd ? KX_THETA_FD : KX_THETA].push_back({inst, r, b, 0, slot++});
+            tiles[KX_THETA].push_back({inst, r, b, 0, slot++});
             tiles[fd ? KX_ASSEMBLE_FD : KX_ASSEMBLE].push_back({inst, r, b, 0, -1});
         }
         g.n_de = slot;
+        if (!fd)
+            for (int r = 0; r < rows; r += g.bgr) tiles[KX_GRAD].push_back({inst, r, std::min(g.bgr, rows - r), 0, -1});
         // axis-2 tiles
         const int kinds_y[6] = {KY_20F, KY_20I, KY_1F, KY_1I, KY_3F, KY_3I};
         const int vs[6] = {kNQ, kNQ, 1, 1, 3, 3};
@@ -550,9 +559,9 @@ static int prepare_device(vdwnl_ctx *c) {
             case KX_NFWD: return (N3 + (g.bnf / 2) * (N3 + 1)) * 16;
             case KX_FINAL: return (N3 + (g.bnf / 2) * (N3 + 1)) * cs;
             case KF_GRAD: case KF_DIV: return 0;
-            case KX_THETA: return xpass_lds(XL_THETA, g.bmain, N3, rs);
+            case KX_GRAD: return xgrad_lds(g.bgr, N3);
+            case KX_THETA: case KX_ASSEMBLE_FD: return xpass_lds(XL_PLAIN, g.bmain, N3, rs);
             case KX_ASSEMBLE: return xpass_lds(XL_ASSEMBLE, g.bmain, N3, rs);
-            case KX_THETA_FD: case KX_ASSEMBLE_FD: return xpass_lds(XL_FD, g.bmain, N3, rs);
             case KY_1F: return (N2 + (N2 | 1) * g.wy1) * 16;
             case KY_1I: return (N2 + (N2 | 1) * g.wy1) * cs;
             case KY_3I: return (N2 + (N2 | 1) * g.wy3) * 16;
@@ -570,7 +579,7 @@ static int prepare_device(vdwnl_ctx *c) {
     // the axis whose FFT a pass performs: 3 for the axis-3 passes, 2, 1
     auto axis_len = [&](int k, const Grid &g) -> int {
         switch (k) {
-            case KX_NFWD: case KX_THETA: case KX_ASSEMBLE: case KX_FINAL: case KX_THETA_FD: case KX_ASSEMBLE_FD:
+            case KX_NFWD: case KX_THETA: case KX_ASSEMBLE: case KX_FINAL: case KX_GRAD: case KX_ASSEMBLE_FD:
                 return g.s[2];
             case KY_1F: case KY_1I: case KY_3F: case KY_3I: case KY_20F: case KY_20I: return g.s[1];
             default: return g.s[0];
@@ -697,7 +706,7 @@ static int prepare_device(vdwnl_ctx *c) {
 }
 
 // Enqueue one evaluation on st: the instance table (device pointers of this
-// call's n and v), the thirteen passes, the reduction and the copy of the
+// call's n and v), the passes of the gradient mode, the reduction and the copy of the
 // energies to pinned host memory.  With timing on, events bracket each pass.
 static int enqueue(vdwnl_ctx *c, int nb, hipStream_t st) {
     hipError_t e;
@@ -980,7 +989,7 @@ int vdwnl_autotune(vdwnl_ctx *ctx, int32_t nb, const void *const *n_ptrs, void *
     }
     // per group, the budget with the least time over the group's passes (a
     // group with no pass in this gradient mode keeps the default)
-    const std::vector<std::vector<int>> groups = {{KX_THETA, KX_ASSEMBLE, KX_THETA_FD, KX_ASSEMBLE_FD},
+    const std::vector<std::vector<int>> groups = {{KX_THETA, KX_ASSEMBLE, KX_ASSEMBLE_FD},
                                                   {KY_20F, KY_20I},
                                                   {KY_1F, KY_1I, KY_3F, KY_3I},
                                                   {KZ_MAIN},

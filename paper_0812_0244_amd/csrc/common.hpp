@@ -31,7 +31,7 @@ struct FftPlan {
 
 // Per-grid state seen by the kernels.  Field layouts (C order):
 //   n, v, vloc      [N1][N2][N3] real
-//   grad            [3][N1][N2][N3] real  (finite-difference mode: grad n, then
+//   grad            [3][N1][N2][N3] real  (grad n; in the finite-difference mode
 //                   overwritten in place by the vector field w of the assembly)
 //   spec            [N1][N2][N3h][kNQ] complex  (20 theta / u spectra, component fastest)
 //   spec3           [N1][N2][N3h][3] complex        (grad n spectra in FP64; later the
@@ -83,7 +83,7 @@ enum KernelKind {
     KY_1F,         // axis-2 forward, 1 component
     KZ_GRAD,       // axis 1: n -> i G_c n / N (3 components)
     KY_3I,         // axis-2 inverse, 3 components
-    KX_THETA,      // C2R grad n, theta_a, R2C theta along axis 3
+    KX_THETA,      // theta_a from n and the stored grad n, R2C theta along axis 3
     KY_20F,        // axis-2 forward, 20 components
     KZ_MAIN,       // axis 1 forward, u = phi c, energy, axis 1 inverse
     KY_20I,        // axis-2 inverse, 20 components
@@ -95,7 +95,7 @@ enum KernelKind {
     // finite-difference gradient mode: the stencils replace the gradient and
     // divergence FFT chains
     KF_GRAD,       // grad n by central differences
-    KX_THETA_FD,   // theta_a from n and the stored grad n, R2C theta along axis 3
+    KX_GRAD,       // (spectral) C2R of the FP64 grad n spectra along axis 3, grad n stored
     KX_ASSEMBLE_FD,// C2R u_a, v_loc and w (stored in place of grad n)
     KF_DIV,        // v = v_loc - sum_c D_c w_c
     KIND_COUNT

@@ -1,13 +1,13 @@
 // HIP kernels of libvdwnl (gfx950).  One evaluation of E_c^nl and v_nl is
-// thirteen passes over the grid; each pass is one launch that covers every
-// grid of the batch (a workgroup reads its work item from a tile list).
+// fourteen passes over the grid with the spectral gradient, seven with finite
+// differences; each pass is one launch that covers every grid of the batch (a
+// workgroup reads its work item from a tile list).
 //
-// The 20 theta / u fields (the bulk of the traffic) are transformed and
-// contracted in the working precision T (float or double).  The gradient of
-// n and the divergence of w (one to three fields) always run in FP64: the
-// gradient term of v_nl multiplies grad n by a factor that grows as 1/n, so
-// FP32 rounding of a spectral grad n in the low-density regions would
-// dominate the error of v.
+// The 20 theta / u fields (the bulk of the traffic), the local chain and the
+// divergence of w are computed in the working precision T (float or double).
+// The spectral gradient of n always runs in FP64: the gradient term of v_nl
+// multiplies grad n by a factor that grows as 1/n, so FP32 rounding of a
+// spectral grad n in the low-density regions would dominate the error of v.
 //
 // Fields are transformed with three 1-D FFT passes: along axis 3 (the
 // contiguous one, real-to-complex by pairing two real lines into one complex
@@ -220,83 +220,90 @@ __global__ void __launch_bounds__(kThreads) k_x_nfwd(const InstDev *insts, const
     }
 }
 
-// theta_a = n p_a(q0), Delta E partials, R2C of the 20 theta rows; grad n
-// from the C2R of its 3 FP64 spectra per row (stored for the assembly), or
-// (FD) read as stored by the finite-difference pass.
-// tile: a = first row, b = rows, slot = partial.
-template <typename T, int LC, bool FD>
+// C2R of the three FP64 grad n spectra (axis 3), grad n stored in T.  Rows
+// (2p, 2p+1) of a tile make three complex lines: 3p and 3p+1 hold
+// d1 + i d2 of row 2p and of row 2p+1, 3p+2 holds d3 of row 2p + i d3 of row
+// 2p+1 (each real field has a Hermitian spectrum: the half spectrum at k and,
+// conjugated, at N3 - k).  tile: a = first row, b = rows (even).
+template <typename T, int LC>
+__global__ void __launch_bounds__(kThreads) k_x_grad(const InstDev *insts, const Tile *tiles,
+                                                     const void *twdv) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const Tile t = tiles[blockIdx.x];
+    const InstDev &I = insts[t.inst];
+    const int N3 = axis_len<LC>(I.n3), N3h = N3 / 2 + 1, row0 = t.a, B = t.b, np = B / 2, ls = N3 + 1;
+    const size_t N = (size_t)I.n1 * I.n2 * I.n3;
+    double2 *tw = reinterpret_cast<double2 *>(smem);
+    double2 *buf = tw + N3;
+    const double2 *s3 = reinterpret_cast<const double2 *>(I.spec3) + (size_t)row0 * N3h * 3;
+    struct Six { double2 a0, b0, c0, a1, b1, c1; };
+    batched<2>(np * N3, [&](int idx) {
+        const int pr = idx / N3, k = idx - pr * N3;
+        const int kk = k >= N3h ? N3 - k : k;
+        const gptr<const double2> g0 = gld(s3 + ((size_t)(2 * pr) * N3h + kk) * 3);
+        const gptr<const double2> g1 = gld(s3 + ((size_t)(2 * pr + 1) * N3h + kk) * 3);
+        return Six{g0[0], g0[1], g0[2], g1[0], g1[1], g1[2]};
+    }, [&](int idx, Six y) {
+        const int pr = idx / N3, k = idx - pr * N3;
+        if (k >= N3h) {
+            y.a0 = cconj(y.a0); y.b0 = cconj(y.b0); y.c0 = cconj(y.c0);
+            y.a1 = cconj(y.a1); y.b1 = cconj(y.b1); y.c1 = cconj(y.c1);
+        }
+        double2 *L = buf + 3 * pr * ls + k;
+        L[0] = mk<double>(y.a0.x - y.b0.y, y.a0.y + y.b0.x);
+        L[ls] = mk<double>(y.a1.x - y.b1.y, y.a1.y + y.b1.x);
+        L[2 * ls] = mk<double>(y.c0.x - y.c1.y, y.c0.y + y.c1.x);
+    });
+    load_twiddles<double>(tw, I.p3, reinterpret_cast<const double2 *>(twdv));
+    __syncthreads();
+    fft_lc<double, 1, LC>(buf, I.p3, 3 * np, 1, ls, tw);
+    const gptr<T> g = gst(reinterpret_cast<T *>(I.grad) + (size_t)row0 * N3);
+    for (int idx = threadIdx.x; idx < B * N3; idx += kThreads) {
+        const int rb = idx / N3, k = idx - rb * N3, pr = rb >> 1, odd = rb & 1;
+        const double2 z = buf[(3 * pr + odd) * ls + k], z3 = buf[(3 * pr + 2) * ls + k];
+        g[idx] = (T)z.x;
+        g[N + idx] = (T)z.y;
+        g[2 * N + idx] = (T)(odd ? z3.y : z3.x);
+    }
+}
+
+// theta_a = n p_a(q0) from n and the stored grad n, Delta E partials, R2C of
+// the 20 theta rows.  tile: a = first row, b = rows, slot = partial.
+template <typename T, int LC>
 __global__ void __launch_bounds__(kThreads) k_x_theta(const InstDev *insts, const Tile *tiles,
-                                                      const Consts *cst, const void *twv, const void *twdv) {
+                                                      const Consts *cst, const void *twv) {
     extern __shared__ __align__(16) unsigned char smem[];
     const Tile t = tiles[blockIdx.x];
     const InstDev &I = insts[t.inst];
     const int N3 = axis_len<LC>(I.n3), N3h = N3 / 2 + 1, row0 = t.a, B = t.b, ls = N3 + 1;
     const size_t N = (size_t)I.n1 * I.n2 * I.n3;
-    double2 *twd = reinterpret_cast<double2 *>(smem);       // FP64 twiddles (spectral gradient)
-    double2 *r1 = twd + (FD ? 0 : N3);                        // 2 lines per row: d1 + i d2, d3
-    C2<T> *r2 = reinterpret_cast<C2<T> *>(r1 + (FD ? 0 : 2 * B * ls));   // 10 lines per row: theta pairs
+    C2<T> *r2 = reinterpret_cast<C2<T> *>(smem);              // 10 lines per row: theta pairs
     C2<T> *tw = r2 + kNQ / 2 * B * ls;                       // twiddles in T
     T *qm = reinterpret_cast<T *>(tw + N3);
     T *Mm = qm + kNQ;
     T *invm = Mm + kNQ * kNQ;
-    // density (and FD: grad n) of this thread's first point, fetched first
-    // (used after the FFT or the constants)
+    // density and grad n of this thread's first point, fetched first (used
+    // after the constants arrive); unconditional loads, clamped to the tile: a
+    // load under a branch would be waited for where the branch joins
     const int npt = B * N3;
     const size_t p0 = (size_t)row0 * N3;
     const gptr<const T> nin = gld(reinterpret_cast<const T *>(I.n) + p0);
     const gptr<const T> gin = gld(reinterpret_cast<const T *>(I.grad) + p0);
-    // (unconditional loads, clamped to the tile: a load under a branch would
-    // be waited for where the branch joins)
     const int i_first = min((int)threadIdx.x, npt - 1);
-    const T n_first = nin[i_first];
-    T gx_f = (T)0, gy_f = (T)0, gz_f = (T)0;
-    if constexpr (FD) {
-        gx_f = gin[i_first];
-        gy_f = gin[N + i_first];
-        gz_f = gin[2 * N + i_first];
-    } else {
-        const double2 *s3 = reinterpret_cast<const double2 *>(I.spec3) + (size_t)row0 * N3h * 3;
-        struct Three { double2 a, b, c; };
-        batched<2>(B * N3, [&](int idx) {
-            const int rb = idx / N3, k = idx - rb * N3;
-            const int kk = k >= N3h ? N3 - k : k;
-            const double2 *src = s3 + ((size_t)rb * N3h + kk) * 3;
-            const gptr<const double2> g = gld(src);
-            return Three{g[0], g[1], g[2]};
-        }, [&](int idx, Three y) {
-            const int rb = idx / N3, k = idx - rb * N3;
-            if (k >= N3h) { y.a = cconj(y.a); y.b = cconj(y.b); y.c = cconj(y.c); }
-            r1[(2 * rb) * ls + k] = mk<double>(y.a.x - y.b.y, y.a.y + y.b.x);
-            r1[(2 * rb + 1) * ls + k] = y.c;
-        });
-        load_twiddles<double>(twd, I.p3, reinterpret_cast<const double2 *>(twdv));
-    }
+    const T n_first = nin[i_first], gx_f = gin[i_first], gy_f = gin[N + i_first], gz_f = gin[2 * N + i_first];
     load_consts<T>(cst, qm, Mm, invm);
     load_twiddles<T>(tw, I.p3, reinterpret_cast<const C2<T> *>(twv));
     __syncthreads();
-    if constexpr (!FD) fft_lc<double, 1, LC>(r1, I.p3, 2 * B, 1, ls, twd);
 
     const double c_qc = cst->qc, c_iqc = cst->iqc, c_cs = cst->cs, c_nmin = cst->nmin;
     const int c_mc = cst->mc;
-    const gptr<T> grad = gst(reinterpret_cast<T *>(I.grad));
     double de = 0.0;
     for (int idx = threadIdx.x; idx < npt; idx += kThreads) {
         const int rb = idx / N3, k = idx - rb * N3;
-        const size_t p = (size_t)(row0 + rb) * N3 + k;
         const bool first = idx == (int)threadIdx.x;
         const T nv = first ? n_first : nin[idx];
-        C2<T> g01, g2;
-        if constexpr (FD) {
-            g01 = mk<T>(first ? gx_f : gin[idx], first ? gy_f : gin[N + idx]);
-            g2 = mk<T>(first ? gz_f : gin[2 * N + idx], (T)0);
-        } else {
-            const double2 g01d = r1[(2 * rb) * ls + k], g2d = r1[(2 * rb + 1) * ls + k];
-            g01 = mk<T>((T)g01d.x, (T)g01d.y);
-            g2 = mk<T>((T)g2d.x, (T)0);
-            grad[p] = g01.x;
-            grad[N + p] = g01.y;
-            grad[2 * N + p] = g2.x;
-        }
+        const C2<T> g01 = mk<T>(first ? gx_f : gin[idx], first ? gy_f : gin[N + idx]);
+        const C2<T> g2 = mk<T>(first ? gz_f : gin[2 * N + idx], (T)0);
         T *th = reinterpret_cast<T *>(r2 + (size_t)(kNQ / 2 * rb) * ls);   // pair line m at th + 2 m ls
         if (nv >= (T)c_nmin) {
             LocalQ<T, false> lq;
@@ -974,8 +981,8 @@ static hipError_t launch_lc(int kind, const LaunchArgs &a) {
         case KY_1F: VDWNL_LAUNCH((k_y<double, -1, LC>), a.twd, 2, 1); break;
         case KZ_GRAD: VDWNL_LAUNCH((k_z_grad<double, LC>), a.twd); break;
         case KY_3I: VDWNL_LAUNCH((k_y<double, 1, LC>), a.twd, 1, 3); break;
-        case KX_THETA: VDWNL_LAUNCH((k_x_theta<T, LC, false>), a.cst, a.tw, a.twd); break;
-        case KX_THETA_FD: VDWNL_LAUNCH((k_x_theta<T, LC, true>), a.cst, a.tw, a.twd); break;
+        case KX_GRAD: VDWNL_LAUNCH((k_x_grad<T, LC>), a.twd); break;
+        case KX_THETA: VDWNL_LAUNCH((k_x_theta<T, LC>), a.cst, a.tw); break;
         case KY_20F: VDWNL_LAUNCH((k_y<T, -1, LC>), a.tw, 0, kNQ); break;
         case KZ_MAIN: VDWNL_LAUNCH((k_z_main<T, LC>), a.cols, a.tw); break;
         case KY_20I: VDWNL_LAUNCH((k_y<T, 1, LC>), a.tw, 0, kNQ); break;
