@@ -235,8 +235,7 @@ static int check_grid(vdwnl_ctx *c, const int32_t *shape, const double *cell, in
     if ((N1 * N2) % 2 != 0)
         return fail(c, VDWNL_E_UNSUPPORTED_SIZE, "N1 * N2 must be even (rows are transformed in pairs)");
     // LDS of each pass as a function of its tile size (twiddles staged in LDS too)
-    const size_t stage = (size_t)((kThreads / 64) * (64 / kNQ)) * kTabStride * rs;
-    auto zmain = [&](size_t k3) { return (N1 + kNQ * k3 * (N1 | 1)) * cs + 16 + stage + (N1 / 2 + 1) * k3 * sizeof(int); };
+    auto zmain = [&](size_t k3) { return (N1 + kNQ * k3 * (N1 | 1)) * cs + 16 + (N1 / 2 + 1) * k3 * sizeof(int); };
     auto zaux = [&](size_t k3) { return (N1 + 4 * k3 * (N1 | 1)) * 16; };
     auto xmain = [&](size_t b) { return xpass_lds(XL_ASSEMBLE, b, N3, rs); };   // the larger layout
     auto ypass = [&](size_t w, size_t c2) { return (N2 + (N2 | 1) * w) * c2; };
@@ -257,8 +256,7 @@ static int check_grid(vdwnl_ctx *c, const int32_t *shape, const double *cell, in
 static void size_tiles(const vdwnl_ctx *c, Grid &g) {
     const size_t cs = c->precision == 64 ? 16 : 8, rs = c->precision == 64 ? 8 : 4;
     const size_t N1 = g.s[0], N2 = g.s[1], N3 = g.s[2];
-    const size_t stage = (size_t)((kThreads / 64) * (64 / kNQ)) * kTabStride * rs;
-    auto zmain = [&](size_t k3) { return (N1 + kNQ * k3 * (N1 | 1)) * cs + 16 + stage + (N1 / 2 + 1) * k3 * sizeof(int); };
+    auto zmain = [&](size_t k3) { return (N1 + kNQ * k3 * (N1 | 1)) * cs + 16 + (N1 / 2 + 1) * k3 * sizeof(int); };
     auto zaux = [&](size_t k3) { return (N1 + 4 * k3 * (N1 | 1)) * 16; };
     auto xmain = [&](size_t b) { return xpass_lds(c->grad_mode ? XL_PLAIN : XL_ASSEMBLE, b, N3, rs); };
     auto ypass = [&](size_t w, size_t c2) { return (N2 + (N2 | 1) * w) * c2; };
@@ -362,10 +360,10 @@ static int plan_grids(vdwnl_ctx *c, int nb, const int32_t *shapes, const double 
     return check_krange(c);
 }
 
-// spline of the radial table at |G| for every pair: phi_ab(|G_s|), FP64
+// spline of the radial table at |G| for every pair: phi_ab(|G_s|), FP64,
+// stored as the full symmetric matrix of each shell
 static void shell_table(const vdwnl_ctx *c, const Shells &sh, std::vector<double> &out) {
-    const int npair = kNPair;
-    out.assign(sh.gmod.size() * kTabStride, 0.0);
+    out.assign(sh.gmod.size() * kTabRow, 0.0);
     for (size_t s = 0; s < sh.gmod.size(); ++s) {
         const double k = sh.gmod[s];
         int j = (int)std::floor(k / c->dk);
@@ -373,11 +371,15 @@ static void shell_table(const vdwnl_ctx *c, const Shells &sh, std::vector<double
         if (j < 0) j = 0;
         const double t = k / c->dk - j, a = 1.0 - t, b = t;
         const double w = c->dk * c->dk / 6.0;
-        for (int p = 0; p < npair; ++p) {
-            const double *f = c->phi.data() + (size_t)p * c->nk;
-            const double *m = c->d2.data() + (size_t)p * c->nk;
-            out[s * kTabStride + p] = a * f[j] + b * f[j + 1] + ((a * a * a - a) * m[j] + (b * b * b - b) * m[j + 1]) * w;
-        }
+        int p = 0;
+        for (int r = 0; r < kNQ; ++r)
+            for (int q = r; q < kNQ; ++q, ++p) {
+                const double *f = c->phi.data() + (size_t)p * c->nk;
+                const double *m = c->d2.data() + (size_t)p * c->nk;
+                const double v = a * f[j] + b * f[j + 1] + ((a * a * a - a) * m[j] + (b * b * b - b) * m[j + 1]) * w;
+                out[s * kTabRow + r * kNQ + q] = v;
+                out[s * kTabRow + q * kNQ + r] = v;
+            }
     }
 }
 
@@ -460,7 +462,7 @@ static int prepare_device(vdwnl_ctx *c) {
         c->map_off[i] = off;
         off = align_up(off + c->shells[i].map.size() * sizeof(int));
         c->tab_off[i] = off;
-        off = align_up(off + c->shells[i].gmod.size() * kTabStride * rs);
+        off = align_up(off + c->shells[i].gmod.size() * kTabRow * rs);
     }
     std::vector<Tile> tiles[KIND_COUNT];
     std::vector<int2> zcols;              // columns of the fused axis-1 tiles
@@ -569,8 +571,7 @@ static int prepare_device(vdwnl_ctx *c) {
             case KY_20F: case KY_20I: return (N2 + (N2 | 1) * g.wy20) * cs;
             case KZ_MAIN: {
                 const size_t K = std::min(g.k3main, kMaxCols);
-                return (N1 + (size_t)kNQ * K * (N1 | 1)) * cs + 16 + (size_t)((kThreads / 64) * (64 / kNQ)) * kTabStride * rs +
-                       (N1 / 2 + 1) * K * sizeof(int);
+                return (N1 + (size_t)kNQ * K * (N1 | 1)) * cs + 16 + (N1 / 2 + 1) * K * sizeof(int);
             }
             case KZ_DIV: return (N1 + 4 * g.k3aux * (N1 | 1)) * cs;
             default: return (N1 + 4 * g.k3aux * (N1 | 1)) * 16;   // KZ_GRAD

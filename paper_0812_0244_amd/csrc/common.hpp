@@ -8,8 +8,8 @@
 namespace vdwnl {
 
 constexpr int kNQ = 20;                          // interpolation points q_a (compile-time)
-constexpr int kNPair = kNQ * (kNQ + 1) / 2;      // packed symmetric phi_ab per |G| shell
-constexpr int kTabStride = (kNPair + 3) / 4 * 4;  // row stride of the shell table (16-byte rows)
+constexpr int kNPair = kNQ * (kNQ + 1) / 2;      // distinct phi_ab (a <= b) per |G| shell
+constexpr int kTabRow = kNQ * kNQ;               // shell table entries per shell (full matrix)
 constexpr int kThreads = 256;                    // threads per workgroup, every kernel
 constexpr int kTileCap = 4096;                   // complex elements of one LDS FFT tile
 constexpr int kLdsCap = 65536;                   // bytes of LDS one workgroup may take
@@ -39,7 +39,8 @@ struct FftPlan {
 //   spec1           [N1][N2][N3h] complex           (n spectrum in FP64; later the
 //                   divergence spectrum in the working precision)
 //   shellmap        [N1/2+1][N2/2+1][N3h] int   (|G| shell of (|m1|, |m2|, m3))
-//   shelltab        [nshell][kTabStride] real   (phi_ab(|G_s|), a <= b packed row by row, padded)
+//   shelltab        [nshell][kNQ][kNQ] real     (phi_ab(|G_s|), the full symmetric matrix:
+//                   row a of a shell is contiguous for the lane that forms u_a)
 struct InstDev {
     int n1, n2, n3, n3h, h1, h2;
     FftPlan p1, p2, p3;

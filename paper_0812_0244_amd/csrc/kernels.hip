@@ -727,28 +727,26 @@ __global__ void __launch_bounds__(kThreads) k_z_div(const InstDev *insts, const 
 // holds the columns pair by pair.
 //
 // Contraction layout: lanes form groups of kNQ (three per wave).  A group
-// takes one item, a |m1| and a pair, stages that shell's packed kernel row in
-// LDS with coalesced 16-byte loads, and lane a keeps phi_ab, b < 20, in
-// registers while it forms u_a at the pair's points (+-m1 of each column).
-// The row of the group's next item is fetched into registers meanwhile.
+// takes one item, a |m1| and a pair; lane a loads row a of that shell's
+// kernel matrix (kNQ contiguous values, 16-byte loads) into registers and
+// forms u_a at the pair's points (+-m1 of each column).  The rows of the
+// group's next item are loaded meanwhile (two register sets in turn).
 template <typename T, int LC>
 __global__ void __launch_bounds__(kThreads) k_z_main(const InstDev *insts, const Tile *tiles, const int2 *cols,
                                                      const void *twv) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int kGroups = (kThreads / 64) * (64 / kNQ);   // lane groups per workgroup
-    constexpr int kChunks = kTabStride * (int)sizeof(T) / 16; // 16-byte chunks of one shell row
-    constexpr int kCpl = (kChunks + kNQ - 1) / kNQ;           // chunks per lane of a group
     constexpr int kEpc = 16 / (int)sizeof(C2<T>);             // complex values per 16-byte chunk
     const Tile t = tiles[blockIdx.x];
     const InstDev &I = insts[t.inst];
     const int N1 = axis_len<LC>(I.n1), N2 = I.n2, N3 = I.n3, N3h = I.n3h, P = t.b, CP = t.c, K = P * CP;
     const int W = K * kNQ, lp = N1 | 1;                      // W lines, contiguous, odd pitch
+    const int cstride = kNQ * lp;                             // LDS elements per column
     __shared__ int colbase[kMaxCols];                         // offset of each column in a k1 plane
     __shared__ int colk3[kMaxCols];
     C2<T> *twall = reinterpret_cast<C2<T> *>(smem);
     C2<T> *buf = twall + N1;
-    const size_t stage_off = ((size_t)(N1 + W * lp) * sizeof(C2<T>) + 15) & ~(size_t)15;
-    T *stage = reinterpret_cast<T *>(smem + stage_off);       // [kGroups][kTabStride], 16-byte aligned
+    int *sidx = reinterpret_cast<int *>(buf + W * lp);        // shell of every item
     {
         const int2 cw = cols[t.a + min((int)threadIdx.x, K - 1)];   // unconditional (clamped) load
         if (threadIdx.x < K) {
@@ -833,7 +831,6 @@ __global__ void __launch_bounds__(kThreads) k_z_main(const InstDev *insts, const
     const int gid = wave * (64 / kNQ) + grp;
     const int nitems = (N1 / 2 + 1) * P;                     // item = |m1| P + pair
     // shell of every item, into LDS (the loads overlap the forward FFT)
-    int *sidx = reinterpret_cast<int *>(stage + (size_t)kGroups * kTabStride);
     {
         const gptr<const int> smap = gld(I.shellmap + (size_t)m2 * N3h + k30);
         const size_t smap_m1 = (size_t)I.h2 * N3h;
@@ -842,67 +839,42 @@ __global__ void __launch_bounds__(kThreads) k_z_main(const InstDev *insts, const
             sidx[i] = smap[m1 * smap_m1 + (i - m1 * P)];
         }
     }
-    // the next item's shell row in registers: chunks al, al + 20, ... of the
-    // row (3 per lane in FP32, 6 in FP64)
-    static_assert(kCpl == 3 || kCpl == 6, "shell row chunking");
-    const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
-    float4 r0 = z4, r1 = z4, r2 = z4, r3 = z4, r4 = z4, r5 = z4;
-    const bool last_on = al + (kCpl - 1) * kNQ < kChunks;
-#define VDWNL_FETCH_ROW(s)                                                                          \
-    do {                                                                                            \
-        const gptr<const float4> src_ = gld(reinterpret_cast<const float4 *>(tab + (size_t)(s) * kTabStride)); \
-        r0 = src_[al];                                                                              \
-        r1 = src_[al + kNQ];                                                                        \
-        if constexpr (kCpl == 3) {                                                                  \
-            if (last_on) r2 = src_[al + 2 * kNQ];                                                   \
-        } else {                                                                                    \
-            r2 = src_[al + 2 * kNQ];                                                                \
-            r3 = src_[al + 3 * kNQ];                                                                \
-            r4 = src_[al + 4 * kNQ];                                                                \
-            if (last_on) r5 = src_[al + 5 * kNQ];                                                   \
-        }                                                                                           \
-    } while (0)
+    // row al of the shell matrix of an item (index clamped to the last item:
+    // the loads stay unconditional)
+    auto fetch = [&](int item, T *f) {
+        const int sh = sidx[min(item, nitems - 1)];
+        const gptr<const T> src = gld(tab + (size_t)sh * kTabRow + al * kNQ);
+        if constexpr (sizeof(T) == 4) {
+            const gptr<const float4> s4 = (gptr<const float4>)src;
+#pragma unroll
+            for (int q = 0; q < kNQ / 4; ++q) {
+                const float4 v = s4[q];
+                f[4 * q] = v.x; f[4 * q + 1] = v.y; f[4 * q + 2] = v.z; f[4 * q + 3] = v.w;
+            }
+        } else {
+            const gptr<const double2> s2 = (gptr<const double2>)src;
+#pragma unroll
+            for (int q = 0; q < kNQ / 2; ++q) {
+                const double2 v = s2[q];
+                f[2 * q] = v.x; f[2 * q + 1] = v.y;
+            }
+        }
+    };
     __syncthreads();
-    if (lane_on && gid < nitems) VDWNL_FETCH_ROW(sidx[gid]);
+    T fa[kNQ], fb[kNQ];
+    if (lane_on) fetch(gid, fa);
     fft_lc<T, -1, LC>(buf, I.p1, W, 1, lp, twall);
 
-    T *st = stage + (size_t)(lane_on ? gid : 0) * kTabStride;
-    // position of phi_{al, b} in the packed row (row-by-row upper triangle):
-    // row b, column al for b <= al, else row al, column b; with the row
-    // starts s_r = r kNQ - r (r - 1) / 2 that is s_b - b + al or s_al - al + b
-    // (b is a compile-time constant in the unrolled loop)
-    const int s_al = al * kNQ - (al * (al - 1)) / 2 - al;
-    int foff[kNQ];
-#pragma unroll
-    for (int b = 0; b < kNQ; ++b) foff[b] = b <= al ? (b * kNQ - (b * (b - 1)) / 2 - b) + al : s_al + b;
     const T inv_n = (T)I.inv_n;
     const double wn = (double)inv_n * (double)inv_n;
-    const int cstride = kNQ * lp;                             // LDS elements per column
     double e = 0.0;
     // item it = m1 P + pr, stepped by kGroups without divisions
     const int dm = kGroups / P, dr = kGroups - dm * P;
     int m1 = gid / P, pr = gid - m1 * P;
-    // A group's lanes share one wave, so staging, reads of theta and writes
-    // of u need wave-level ordering only.
-    for (int it = gid; lane_on && it < nitems; it += kGroups) {
-        {
-            float4 *dst = reinterpret_cast<float4 *>(st);
-            dst[al] = r0;
-            dst[al + kNQ] = r1;
-            if constexpr (kCpl == 3) {
-                if (last_on) dst[al + 2 * kNQ] = r2;
-            } else {
-                dst[al + 2 * kNQ] = r2;
-                dst[al + 3 * kNQ] = r3;
-                dst[al + 4 * kNQ] = r4;
-                if (last_on) dst[al + 5 * kNQ] = r5;
-            }
-        }
-        wave_sync();
-        if (it + kGroups < nitems) VDWNL_FETCH_ROW(sidx[it + kGroups]);   // prefetch the next row
-        T f[kNQ];
-#pragma unroll
-        for (int b = 0; b < kNQ; ++b) f[b] = st[foff[b]];
+    // u at the points of the current item with the kernel row f; a group's
+    // lanes share one wave, so reads of theta and writes of u need wave-level
+    // ordering only
+    auto process = [&](const T *f) {
         const int l = m1;
         int lq = N1 - m1;
         if (m1 == 0 || lq == m1) lq = -1;     // k1 = 0 and the Nyquist plane stand alone
@@ -934,6 +906,15 @@ __global__ void __launch_bounds__(kThreads) k_z_main(const InstDev *insts, const
             if (lq >= 0) x2[al * lp] = cscale(u2, inv_n);
             wave_sync();
         }
+    };
+    for (int it = gid; lane_on && it < nitems;) {
+        fetch(it + kGroups, fb);               // the next item's row (clamped past the end)
+        process(fa);
+        it += kGroups;
+        if (it >= nitems) break;
+        fetch(it + kGroups, fa);
+        process(fb);
+        it += kGroups;
     }
     __syncthreads();
     fft_lc<T, 1, LC>(buf, I.p1, W, 1, lp, twall);
