@@ -167,7 +167,7 @@ def main():
     if args.lds_budgets:
         lib.set_tiling([int(x) for x in args.lds_budgets.split(",")])
     elif not args.no_autotune:
-        lib.autotune(nptr, vptr, reps=2, stream=stream)
+        lib.autotune(nptr, vptr, reps=5, stream=stream)
     tiling = lib.get_tiling()
     log("tile budgets %s (%.1f s)" % (tiling, time.time() - t0))
     for _ in range(args.warmup):
@@ -218,7 +218,7 @@ def main():
         if args.lds_budgets:
             lib.set_tiling([int(x) for x in args.lds_budgets.split(",")])
         elif not args.no_autotune:
-            lib.autotune(nptr, vfptr, reps=2, stream=stream)
+            lib.autotune(nptr, vfptr, reps=5, stream=stream)
         fd_tiling = lib.get_tiling()
         for _ in range(args.warmup):
             lib.energy_potential_batched(nptr, vfptr, stream)
