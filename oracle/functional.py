@@ -125,20 +125,48 @@ class CardinalSplines:
         return (p.T.reshape((self.nq,) + q.shape), dp.T.reshape((self.nq,) + q.shape))
 
 
-# ---------------------------------------------------------------- O1 / O14
-def wavevectors(shape, cell, half=True):
-    """G_c on the (half) FFT grid with the Nyquist components set to zero."""
-    gs = []
+# ---------------------------------------------------------------- cells
+def lattice(cell):
+    """Rows a_1, a_2, a_3 of the cell (bohr): three orthorhombic lengths or a
+    3 x 3 matrix of cell vectors.  Grid point i sits at sum_c (i_c/N_c) a_c."""
+    c = np.asarray(cell, dtype=np.float64)
+    return np.diag(c) if c.shape == (3,) else c.reshape(3, 3)
+
+
+def reciprocal(cell):
+    """Rows b_1, b_2, b_3 with a_i . b_j = 2 pi delta_ij."""
+    return 2.0 * np.pi * np.linalg.inv(lattice(cell)).T
+
+
+def volume(cell):
+    return float(abs(np.linalg.det(lattice(cell))))
+
+
+def _freqs(shape, half):
+    """Integer frequencies m_c on the (half) FFT grid (Nyquist as -N/2, or
+    +N/2 on the last axis of the half spectrum) and the Nyquist flags."""
+    ms, nyq = [], []
     for c in range(3):
-        npts, length = shape[c], cell[c]
+        npts = shape[c]
         if c == 2 and half:
             m = np.arange(npts // 2 + 1, dtype=np.float64)
         else:
             m = np.fft.fftfreq(npts, d=1.0 / npts)
-        if npts % 2 == 0:
-            m[np.abs(m) == npts // 2] = 0.0
-        gs.append(2.0 * np.pi * m / length)
-    return np.meshgrid(*gs, indexing="ij")
+        ms.append(m)
+        nyq.append((npts % 2 == 0) & (np.abs(m) == npts // 2))
+    return ms, nyq
+
+
+# ---------------------------------------------------------------- O1 / O14
+def wavevectors(shape, cell, half=True):
+    """Cartesian components of G = sum_c m_c b_c on the (half) FFT grid, with
+    a Nyquist index m_c taken as zero (the derivative along that lattice
+    axis vanishes there, so the operator stays real antisymmetric)."""
+    B = reciprocal(cell)
+    ms, nyq = _freqs(shape, half)
+    mz = [np.where(nq, 0.0, m) for m, nq in zip(ms, nyq)]
+    M = np.meshgrid(*mz, indexing="ij")
+    return [M[0] * B[0, x] + M[1] * B[1, x] + M[2] * B[2, x] for x in range(3)]
 
 
 def gradient(n, cell):
@@ -172,34 +200,57 @@ def fd_weights(m):
     return np.linalg.solve(A, rhs)
 
 
-def gradient_fd(n, cell, m):
-    """grad n by the central differences of ``fd_weights(m)`` on the periodic
-    grid (3 x shape): d_c n_i = sum_s c_s (n_{i + s e_c} - n_{i - s e_c}) / h_c."""
-    shape = n.shape
+def _stencil(f, ax, m):
+    """sum_s c_s (f_{i + s e_ax} - f_{i - s e_ax}) on the periodic grid (unit spacing)."""
     c = fd_weights(m)
-    out = np.zeros((3,) + tuple(shape))
-    for ax in range(3):
-        h = cell[ax] / shape[ax]
-        for s in range(1, m + 1):
-            out[ax] += c[s - 1] / h * (np.roll(n, -s, axis=ax) - np.roll(n, s, axis=ax))
+    out = np.zeros_like(f)
+    for s in range(1, m + 1):
+        out += c[s - 1] * (np.roll(f, -s, axis=ax) - np.roll(f, s, axis=ax))
     return out
 
 
+def fd_metric(shape, cell):
+    """W[c][x] = N_c b_c,x / (2 pi): grad n = sum_c W[c] d n/d(i_c), the chain
+    rule from the grid index along lattice axis c to Cartesian x (for an
+    orthorhombic cell W = diag(1 / h_c))."""
+    B = reciprocal(cell)
+    return np.array([shape[c] * B[c] / (2.0 * np.pi) for c in range(3)])
+
+
+def gradient_fd(n, cell, m):
+    """grad n by the central differences of ``fd_weights(m)`` along the three
+    lattice axes of the periodic grid, d_c n_i = sum_s c_s (n_{i + s e_c} -
+    n_{i - s e_c}), combined into Cartesian components with ``fd_metric``
+    (3 x shape)."""
+    W = fd_metric(n.shape, cell)
+    d = [_stencil(n, c, m) for c in range(3)]
+    return np.stack([W[0, x] * d[0] + W[1, x] * d[1] + W[2, x] * d[2] for x in range(3)])
+
+
 def divergence_fd(w, cell, m):
-    """sum_c D_c w_c with the derivative operator of ``gradient_fd``."""
-    return sum(gradient_fd(w[c], cell, m)[c] for c in range(3))
+    """The adjoint of ``gradient_fd`` with the sign flipped: sum_c D_c q_c with
+    q_c = sum_x W[c][x] w_x (D_c antisymmetric)."""
+    W = fd_metric(w.shape[1:], cell)
+    return sum(_stencil(W[c, 0] * w[0] + W[c, 1] * w[1] + W[c, 2] * w[2], c, m) for c in range(3))
 
 
 def gmod_half(shape, cell):
-    """|G| on the half spectrum (Nyquist components kept: the kernel depends
-    only on |G| and both signs of a Nyquist component give the same |G|)."""
-    gs = []
+    """|G| on the half spectrum, |G|^2 = sum_cd m_c m_d (b_c . b_d).  A Nyquist
+    index stands for both signs +-N_c/2, which give different |G| in a
+    non-orthogonal cell (READING): |G|^2 there is the mean over the two, i.e.
+    the cross terms of that axis are dropped.  The multiplier then takes the
+    same value at G and -G, as a real transform needs; in an orthorhombic
+    cell nothing changes (no cross terms)."""
+    B = reciprocal(cell)
+    Mt = B @ B.T
+    ms, nyq = _freqs(shape, True)
+    m = np.meshgrid(*ms, indexing="ij")
+    q = np.meshgrid(*[(~nq).astype(np.float64) for nq in nyq], indexing="ij")
+    g2 = sum(Mt[c, c] * m[c] * m[c] for c in range(3))
     for c in range(3):
-        npts, length = shape[c], cell[c]
-        m = np.arange(npts // 2 + 1, dtype=np.float64) if c == 2 else np.fft.fftfreq(npts, d=1.0 / npts)
-        gs.append(2.0 * np.pi * m / length)
-    g1, g2, g3 = np.meshgrid(*gs, indexing="ij")
-    return np.sqrt(g1 * g1 + g2 * g2 + g3 * g3)
+        for d in range(c + 1, 3):
+            g2 = g2 + 2.0 * Mt[c, d] * m[c] * m[d] * q[c] * q[d]
+    return np.sqrt(np.maximum(g2, 0.0))
 
 
 def half_weights(shape):
@@ -272,12 +323,13 @@ def kernel_at(gmod, table):
 
 # ---------------------------------------------------------------- O1..O14
 def energy_potential(n, cell, table, n_min=N_MIN, return_parts=False, grad_mode=0):
-    """(E_k, Delta E, v) for the density n [N1, N2, N3] in the cell (bohr);
+    """(E_k, Delta E, v) for the density n [N1, N2, N3] in the cell (bohr:
+    three orthorhombic lengths or the 3 x 3 matrix of cell vectors);
     grad_mode 0: spectral gradient, m = 1..4: central differences of order 2m."""
     n = np.asarray(n, dtype=np.float64)
     shape = n.shape
     N = n.size
-    omega = float(np.prod(cell))
+    omega = volume(cell)
     dvol = omega / N
     if grad_mode not in (0, 1, 2, 3, 4):
         raise ValueError("grad_mode must be 0 (spectral) or 1..4 (central differences)")

@@ -1,7 +1,8 @@
 """Seeded synthetic densities for the vdW-DF nonlocal-correlation path.
 
 This module holds no part of the method's arithmetic: it only builds
-electron densities n(r) on periodic orthorhombic grids.  It is the one
+electron densities n(r) on periodic grids (orthorhombic, or general cells
+given by their three cell vectors).  It is the one
 module that both the oracle and the product path (tests, benchmark, the
 force example) use for their inputs.
 
@@ -84,6 +85,65 @@ def density_on_grid(shape, cell, atoms: Atoms, floor: float = FLOOR) -> np.ndarr
                * prof[2][idx[2]][None, None, :])
         n[np.ix_(idx[0], idx[1], idx[2])] += sub
     return n
+
+
+# --------------------------------------------------------------------------
+# general (non-orthogonal) periodic cells
+# --------------------------------------------------------------------------
+
+def lattice_matrix(cell) -> np.ndarray:
+    """3 x 3 matrix whose rows are the cell vectors a_1, a_2, a_3 (bohr):
+    a general cell as given, or the diagonal of three orthorhombic lengths."""
+    c = np.asarray(cell, dtype=np.float64)
+    return np.diag(c) if c.shape == (3,) else c.reshape(3, 3).copy()
+
+
+def random_atoms_lattice(rng: np.random.Generator, natoms: int, lattice) -> Atoms:
+    """As ``random_atoms``, centres uniform in the cell spanned by the rows of
+    ``lattice`` (fractional coordinates uniform in [0, 1))."""
+    amp = rng.uniform(0.5, 2.0, natoms)
+    width = rng.uniform(0.6, 1.2, natoms)
+    frac = rng.uniform(0.0, 1.0, (natoms, 3))
+    return Atoms(amp, width, frac @ lattice_matrix(lattice))
+
+
+def density_on_lattice(shape, lattice, atoms: Atoms, floor: float = FLOOR) -> np.ndarray:
+    """n on the grid r_i = sum_c (i_c / N_c) a_c of a general cell (rows of
+    ``lattice``), FP64, C order.  Images L = sum_c k_c a_c are summed while a
+    Gaussian can reach the cell within IMAGE_CUT widths (|k_c| up to the
+    cut's extent along the reciprocal direction, plus one)."""
+    shape = tuple(int(s) for s in shape)
+    A = lattice_matrix(lattice)
+    recip = np.linalg.inv(A).T                       # rows b_c / (2 pi)
+    u = [np.arange(shape[c]) / shape[c] for c in range(3)]
+    U = np.stack(np.meshgrid(*u, indexing="ij"), axis=-1)
+    r = U @ A                                        # [N1, N2, N3, 3]
+    n = np.full(shape, floor, dtype=np.float64)
+    for a, w, pos in zip(atoms.amp, atoms.width, atoms.pos):
+        kmax = [int(math.ceil(IMAGE_CUT * w * np.linalg.norm(recip[c]))) + 1 for c in range(3)]
+        for k1 in range(-kmax[0], kmax[0] + 1):
+            for k2 in range(-kmax[1], kmax[1] + 1):
+                for k3 in range(-kmax[2], kmax[2] + 1):
+                    d = r - (pos + k1 * A[0] + k2 * A[1] + k3 * A[2])
+                    d2 = np.einsum("...i,...i->...", d, d)
+                    m = d2 < (IMAGE_CUT * w) ** 2
+                    if np.any(m):
+                        n[m] += a * np.exp(-d2[m] / (w * w))
+    return n
+
+
+def triclinic_lattice(lengths=(10.0, 9.0, 11.0), angles_deg=(80.0, 105.0, 70.0)) -> np.ndarray:
+    """Rows a_1, a_2, a_3 of the cell with the given edge lengths and the
+    angles (alpha between a_2 and a_3, beta between a_1 and a_3, gamma
+    between a_1 and a_2), a_1 along x and a_2 in the xy plane."""
+    a, b, c = lengths
+    al, be, ga = (math.radians(x) for x in angles_deg)
+    a1 = np.array([a, 0.0, 0.0])
+    a2 = np.array([b * math.cos(ga), b * math.sin(ga), 0.0])
+    cx = c * math.cos(be)
+    cy = c * (math.cos(al) - math.cos(be) * math.cos(ga)) / math.sin(ga)
+    a3 = np.array([cx, cy, math.sqrt(c * c - cx * cx - cy * cy)])
+    return np.stack([a1, a2, a3])
 
 
 # --------------------------------------------------------------------------
