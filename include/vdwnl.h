@@ -83,6 +83,25 @@ int vdwnl_set_grid(vdwnl_ctx *ctx, const int32_t shape[3], const double cell[3],
 int vdwnl_set_grids(vdwnl_ctx *ctx, int32_t nb, const int32_t *shapes, const double *cells,
                     int32_t grad_mode, int32_t precision);
 
+/* Plan a batch of grids in cells of any shape: lattices[nb][3][3], host,
+ * row c = the cell vector a_c in Cartesian bohr (any orientation; a diagonal
+ * matrix is the orthorhombic case of vdwnl_set_grids, with identical
+ * results).  Grid point i sits at sum_c (i_c / N_c) a_c; the grid is the
+ * uniform real-space grid on which the paper's method takes n and returns
+ * E and v (paragraph after Eq. (epsofk)).  Wave vectors G = sum_c m_c b_c
+ * with the reciprocal vectors a_i . b_j = 2 pi delta_ij; the volume is
+ * |det|.  Where the cell is not orthorhombic, |G| at a Nyquist index (which
+ * stands for both +-N_c/2) is the mean of |G|^2 over the two (the cross
+ * terms of that axis dropped), the kernel table holds one row per distinct
+ * |G| over the whole half spectrum (up to about half the grid's points:
+ * larger tables and a slower fused axis-1 pass than an orthorhombic cell),
+ * and finite differences run along the cell axes, combined into Cartesian
+ * components with (N_c / 2 pi) b_c.  Other rules as vdwnl_set_grid.
+ * Errors: VDWNL_E_ARG (null pointer, non-finite entry, cell vectors that
+ * span no volume), as vdwnl_set_grid otherwise. */
+int vdwnl_set_grids_lattice(vdwnl_ctx *ctx, int32_t nb, const int32_t *shapes, const double *lattices,
+                            int32_t grad_mode, int32_t precision);
+
 /* The kernel of the factorisation, Eq. (phi), in k space (the radial table
  * described after Eq. (Eoffk)), and the parameters of q0:
  *   nq        number of interpolation points q_a (20 is the supported value)
@@ -119,9 +138,11 @@ int vdwnl_energy_potential_batched(vdwnl_ctx *ctx, int32_t nb, const void *const
 
 /* Copy an internal per-grid field of the last evaluation of grid `inst` to
  * the device buffer dst (for parity probes): which = 0: grad n [3][N] with
- * the spectral gradient; with finite differences the same buffer holds the
- * vector field w = sum_a u_a dtheta_a/dgrad n + de/dgrad n of Eq. (Vi) after
- * an evaluation (grad n is overwritten in place); 1: v_loc [N] (the local
+ * the spectral gradient; with finite differences the same buffer holds, after
+ * an evaluation, the components q_c = sum_x W[c][x] w_x (W[c][x] =
+ * N_c b_c,x / (2 pi), N_c / L_c on the diagonal of an orthorhombic cell) of
+ * the vector field w = sum_a u_a dtheta_a/dgrad n + de/dgrad n of Eq. (Vi)
+ * (grad n is overwritten in place); 1: v_loc [N] (the local
  * part of v, before the gradient term).  Arrays in the planned precision. */
 int vdwnl_debug_field(vdwnl_ctx *ctx, int32_t inst, int32_t which, void *dst, void *stream);
 

@@ -27,6 +27,7 @@ SIGNATURES = {
     "vdwnl_last_error": (ctypes.c_char_p, [_vp]),
     "vdwnl_set_grid": (ctypes.c_int, [_vp, _ip, _dp, _i32, _i32]),
     "vdwnl_set_grids": (ctypes.c_int, [_vp, _i32, _ip, _dp, _i32, _i32]),
+    "vdwnl_set_grids_lattice": (ctypes.c_int, [_vp, _i32, _ip, _dp, _i32, _i32]),
     "vdwnl_set_kernel_table": (ctypes.c_int, [_vp, _i32, _dp, ctypes.c_double, _i32, _i32,
                                               ctypes.c_double, _dp, ctypes.c_double]),
     "vdwnl_energy_potential": (ctypes.c_int, [_vp, _vp, _vp, _dp, _vp]),
@@ -145,6 +146,9 @@ class VdwNl:
             pass
 
     def set_grid(self, shape, cell, grad_mode: int = 0, precision: int = 32):
+        """cell: three orthorhombic lengths or a 3 x 3 matrix of cell vectors (rows)."""
+        if np.asarray(cell).shape != (3,):
+            return self.set_grids([shape], [cell], grad_mode, precision)
         s = np.ascontiguousarray(shape, dtype=np.int32)
         c = np.ascontiguousarray(cell, dtype=np.float64)
         self._check(self.lib.vdwnl_set_grid(self.h, _as_ptr(s, ctypes.c_int32), _as_ptr(c, ctypes.c_double),
@@ -152,10 +156,20 @@ class VdwNl:
         self.ngrids, self.precision = 1, precision
 
     def set_grids(self, shapes, cells, grad_mode: int = 0, precision: int = 32):
+        """cells: per grid three orthorhombic lengths, or (any of them) a 3 x 3
+        matrix of cell vectors (rows); a batch with any matrix is planned
+        through vdwnl_set_grids_lattice."""
         s = np.ascontiguousarray(shapes, dtype=np.int32).reshape(-1, 3)
-        c = np.ascontiguousarray(cells, dtype=np.float64).reshape(-1, 3)
-        self._check(self.lib.vdwnl_set_grids(self.h, len(s), _as_ptr(s, ctypes.c_int32),
-                                             _as_ptr(c, ctypes.c_double), grad_mode, precision), "set_grids")
+        cl = [np.asarray(c, dtype=np.float64) for c in cells]
+        if all(c.shape == (3,) for c in cl):
+            c = np.ascontiguousarray(np.stack(cl))
+            rc = self.lib.vdwnl_set_grids(self.h, len(s), _as_ptr(s, ctypes.c_int32), _as_ptr(c, ctypes.c_double),
+                                          grad_mode, precision)
+        else:
+            c = np.ascontiguousarray(np.stack([np.diag(x) if x.shape == (3,) else x.reshape(3, 3) for x in cl]))
+            rc = self.lib.vdwnl_set_grids_lattice(self.h, len(s), _as_ptr(s, ctypes.c_int32),
+                                                  _as_ptr(c, ctypes.c_double), grad_mode, precision)
+        self._check(rc, "set_grids")
         self.ngrids, self.precision = len(s), precision
 
     def set_kernel_table(self, qmesh, q_c, m_c, dk, phi, c_soft):

@@ -51,10 +51,56 @@ static void natural_spline_d2(const double *x, const double *y, int n, double *d
 }
 
 struct Shells {
-    std::vector<int> map;       // [h1][h2][n3h]
+    std::vector<int> map;       // [h1][h2][n3h] (orthorhombic) or [N1][N2][n3h] (general cell)
     std::vector<double> gmod;   // |G| per shell
     double gmax = 0.0;
 };
+
+static Shells shells_from_keys(const std::vector<double> &key) {
+    Shells sh;
+    std::vector<double> u(key);
+    std::sort(u.begin(), u.end());
+    u.erase(std::unique(u.begin(), u.end()), u.end());
+    sh.map.resize(key.size());
+    for (size_t i = 0; i < key.size(); ++i)
+        sh.map[i] = (int)(std::lower_bound(u.begin(), u.end(), key[i]) - u.begin());
+    sh.gmod.resize(u.size());
+    for (size_t i = 0; i < u.size(); ++i) sh.gmod[i] = std::sqrt(std::max(u[i], 0.0));
+    sh.gmax = sh.gmod.back();
+    return sh;
+}
+
+// General cell: |G|^2 = sum_cd m_c m_d (b_c . b_d) at every point of the half
+// spectrum (m_1, m_2 in FFT order, Nyquist -N/2; m_3 = k3).  A Nyquist index
+// stands for both signs +-N_c/2, whose |G| differ when the cell is not
+// orthogonal: |G|^2 there is the mean over the two (the cross terms of that
+// axis dropped), so G and -G always meet the same value.
+static Shells build_shells_general(const int s[3], const double B[3][3]) {
+    double M[3][3];
+    for (int c = 0; c < 3; ++c)
+        for (int d = 0; d < 3; ++d) M[c][d] = B[c][0] * B[d][0] + B[c][1] * B[d][1] + B[c][2] * B[d][2];
+    const int n3h = s[2] / 2 + 1;
+    std::vector<double> key((size_t)s[0] * s[1] * n3h);
+    for (int k1 = 0; k1 < s[0]; ++k1)
+        for (int k2 = 0; k2 < s[1]; ++k2)
+            for (int k3 = 0; k3 < n3h; ++k3) {
+                const int k[3] = {k1, k2, k3};
+                double m[3];
+                bool nyq[3];
+                for (int c = 0; c < 3; ++c) {
+                    const int n = s[c];
+                    const int mc = (c < 2 && k[c] >= (n + 1) / 2) ? k[c] - n : k[c];
+                    m[c] = (double)mc;
+                    nyq[c] = (n % 2 == 0) && (mc == n / 2 || mc == -n / 2);
+                }
+                double g2 = M[0][0] * m[0] * m[0] + M[1][1] * m[1] * m[1] + M[2][2] * m[2] * m[2];
+                for (int c = 0; c < 3; ++c)
+                    for (int d = c + 1; d < 3; ++d)
+                        if (!nyq[c] && !nyq[d]) g2 += 2.0 * M[c][d] * m[c] * m[d];
+                key[((size_t)k1 * s[1] + k2) * n3h + k3] = g2;
+            }
+    return shells_from_keys(key);
+}
 
 static Shells build_shells(const int s[3], const double cell[3]) {
     Shells sh;
@@ -67,16 +113,8 @@ static Shells build_shells(const int s[3], const double cell[3]) {
                 const double x = g1 * a, y = g2 * b, z = g3 * c;
                 key[((size_t)a * h2 + b) * n3h + c] = x * x + y * y + z * z;
             }
-    std::vector<double> u(key);
-    std::sort(u.begin(), u.end());
-    u.erase(std::unique(u.begin(), u.end()), u.end());
-    sh.map.resize(key.size());
-    for (size_t i = 0; i < key.size(); ++i)
-        sh.map[i] = (int)(std::lower_bound(u.begin(), u.end(), key[i]) - u.begin());
-    sh.gmod.resize(u.size());
-    for (size_t i = 0; i < u.size(); ++i) sh.gmod[i] = std::sqrt(u[i]);
-    sh.gmax = sh.gmod.back();
-    return sh;
+    (void)sh;
+    return shells_from_keys(key);
 }
 
 // Pass groups whose tile shapes follow one LDS budget each.
@@ -84,7 +122,10 @@ enum TileGroup { TG_X = 0, TG_Y20, TG_YAUX, TG_Z, TG_ZAUX, TG_COUNT };
 
 struct Grid {
     int s[3];
-    double cell[3];
+    double A[3][3];          // cell vectors a_c (rows, bohr)
+    double B[3][3];          // reciprocal vectors b_c (rows): a_i . b_j = 2 pi delta_ij
+    bool general;            // a_c not all along the axes: full-spectrum shells, no column pairing
+    double cell[3];          // |a_c| (the orthorhombic lengths when !general)
     FftPlan p1, p2, p3;
     int bmain;               // rows per theta / assemble tile
     int bnf;                 // rows per n-forward / final tile (even)
@@ -221,15 +262,38 @@ static size_t xpass_lds(int layout, size_t b, size_t N3, size_t rs) {
 // FP64 twiddles.
 static size_t xgrad_lds(size_t b, size_t N3) { return (N3 + 3 * (b / 2) * (N3 + 1)) * 16; }
 
-static int check_grid(vdwnl_ctx *c, const int32_t *shape, const double *cell, int precision, Grid &g) {
+// lattice: 9 values, rows a_1, a_2, a_3 (bohr)
+static int check_grid(vdwnl_ctx *c, const int32_t *shape, const double *lattice, int precision, Grid &g) {
     const size_t cs = precision == 64 ? 16 : 8, rs = precision == 64 ? 8 : 4;
+    g.general = false;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            g.A[i][j] = lattice[3 * i + j];
+            if (!std::isfinite(g.A[i][j])) return fail(c, VDWNL_E_ARG, "cell vectors must be finite");
+            if (i != j && g.A[i][j] != 0.0) g.general = true;
+        }
     for (int i = 0; i < 3; ++i) {
-        if (!(cell[i] > 0.0) || !std::isfinite(cell[i]))
-            return fail(c, VDWNL_E_ARG, "cell lengths must be positive and finite");
+        g.cell[i] = std::sqrt(g.A[i][0] * g.A[i][0] + g.A[i][1] * g.A[i][1] + g.A[i][2] * g.A[i][2]);
+        if (!g.general && !(g.A[i][i] > 0.0)) return fail(c, VDWNL_E_ARG, "cell lengths must be positive and finite");
         if (shape[i] < 4 || !smooth235(shape[i]))
             return fail(c, VDWNL_E_UNSUPPORTED_SIZE, "grid edges must be >= 4 and products of 2, 3 and 5");
         g.s[i] = shape[i];
-        g.cell[i] = cell[i];
+    }
+    // reciprocal vectors: b_c = 2 pi (a_(c+1) x a_(c+2)) / det A
+    const double(*A)[3] = g.A;
+    const double det = A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) - A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
+                       A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
+    if (!(std::fabs(det) > 1e-9 * g.cell[0] * g.cell[1] * g.cell[2]))
+        return fail(c, VDWNL_E_ARG, "cell vectors must span a volume");
+    if (!g.general) {
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) g.B[i][j] = i == j ? 2.0 * M_PI / g.A[i][i] : 0.0;
+    } else {
+        for (int cidx = 0; cidx < 3; ++cidx) {
+            const double *u = A[(cidx + 1) % 3], *v = A[(cidx + 2) % 3];
+            const double x[3] = {u[1] * v[2] - u[2] * v[1], u[2] * v[0] - u[0] * v[2], u[0] * v[1] - u[1] * v[0]};
+            for (int j = 0; j < 3; ++j) g.B[cidx][j] = 2.0 * M_PI * x[j] / det;
+        }
     }
     const size_t N1 = g.s[0], N2 = g.s[1], N3 = g.s[2];
     if ((N1 * N2) % 2 != 0)
@@ -302,9 +366,12 @@ static std::string plan_key(const vdwnl_ctx *c) {
     std::string k = std::to_string(c->precision) + "/" + std::to_string(c->grad_mode) + "/" + std::to_string(c->lds_cap);
     char buf[128];
     for (const Grid &g : c->grids) {
-        std::snprintf(buf, sizeof(buf), ";%dx%dx%d@%.17g,%.17g,%.17g", g.s[0], g.s[1], g.s[2], g.cell[0], g.cell[1],
-                      g.cell[2]);
+        std::snprintf(buf, sizeof(buf), ";%dx%dx%d@", g.s[0], g.s[1], g.s[2]);
         k += buf;
+        for (int i = 0; i < 9; ++i) {
+            std::snprintf(buf, sizeof(buf), "%.17g,", g.A[i / 3][i % 3]);
+            k += buf;
+        }
     }
     return k;
 }
@@ -322,6 +389,7 @@ static void tuned_store(const std::string &key, const size_t *pref) {
     g_tuned[key] = std::vector<size_t>(pref, pref + TG_COUNT);
 }
 
+// cells: nb x 9 values (rows a_1, a_2, a_3 of each grid's cell)
 static int plan_grids(vdwnl_ctx *c, int nb, const int32_t *shapes, const double *cells, int grad_mode,
                       int precision) {
     if (!c || !shapes || !cells || nb <= 0) return fail(c, VDWNL_E_ARG, "null argument or empty batch");
@@ -330,7 +398,7 @@ static int plan_grids(vdwnl_ctx *c, int nb, const int32_t *shapes, const double 
     if (precision != 32 && precision != 64) return fail(c, VDWNL_E_ARG, "precision must be 32 or 64");
     std::vector<Grid> gs(nb);
     for (int i = 0; i < nb; ++i) {
-        int rc = check_grid(c, shapes + 3 * i, cells + 3 * i, precision, gs[i]);
+        int rc = check_grid(c, shapes + 3 * i, cells + 9 * i, precision, gs[i]);
         if (rc != VDWNL_OK) return rc;
     }
     free_device(c);
@@ -345,13 +413,15 @@ static int plan_grids(vdwnl_ctx *c, int nb, const int32_t *shapes, const double 
     c->shells.clear();
     c->shell_keys.clear();
     for (auto &g : c->grids) {
-        std::vector<double> key = {(double)g.s[0], (double)g.s[1], (double)g.s[2], g.cell[0], g.cell[1], g.cell[2]};
+        std::vector<double> key = {(double)g.s[0], (double)g.s[1], (double)g.s[2]};
+        for (int i = 0; i < 9; ++i) key.push_back(g.A[i / 3][i % 3]);
         int found = -1;
         for (auto &kv : c->shell_keys)
             if (kv.first == key) found = kv.second;
         if (found < 0) {
             found = (int)c->shells.size();
-            c->shells.push_back(build_shells(g.s, g.cell));
+            double diag[3] = {g.A[0][0], g.A[1][1], g.A[2][2]};
+            c->shells.push_back(g.general ? build_shells_general(g.s, g.B) : build_shells(g.s, diag));
             c->shell_keys.push_back({key, found});
         }
         g.shell_key = found;
@@ -506,8 +576,9 @@ static int prepare_device(vdwnl_ctx *c) {
             const int K = std::min(g.k3main, kMaxCols);
             std::vector<Tile> zt;
             // (a budget of one column per tile: k2 and N2 - k2 in tiles of their own)
-            for (int k2 = 0; k2 <= N2 / 2; ++k2) {
-                const int k2b = (N2 - k2) % N2;
+            // (general cells: every column alone, k2 over the whole axis)
+            for (int k2 = 0; k2 <= (g.general ? N2 - 1 : N2 / 2); ++k2) {
+                const int k2b = g.general ? k2 : (N2 - k2) % N2;
                 const bool pair = k2b != k2 && K >= 2;
                 for (int side = 0; side < ((k2b != k2 && !pair) ? 2 : 1); ++side) {
                     const int ka = side == 0 ? k2 : k2b;
@@ -571,7 +642,7 @@ static int prepare_device(vdwnl_ctx *c) {
             case KY_20F: case KY_20I: return (N2 + (N2 | 1) * g.wy20) * cs;
             case KZ_MAIN: {
                 const size_t K = std::min(g.k3main, kMaxCols);
-                return (N1 + (size_t)kNQ * K * (N1 | 1)) * cs + 16 + (N1 / 2 + 1) * K * sizeof(int);
+                return (N1 + (size_t)kNQ * K * (N1 | 1)) * cs + 16 + (g.general ? N1 : N1 / 2 + 1) * K * sizeof(int);
             }
             case KZ_DIV: return (N1 + 4 * g.k3aux * (N1 | 1)) * cs;
             default: return (N1 + 4 * g.k3aux * (N1 | 1)) * 16;   // KZ_GRAD
@@ -685,15 +756,25 @@ static int prepare_device(vdwnl_ctx *c) {
         I.h1 = g.s[0] / 2 + 1; I.h2 = g.s[1] / 2 + 1;
         I.p1 = g.p1; I.p2 = g.p2; I.p3 = g.p3;
         I.inv_n = 1.0 / (double)g.npts();
-        I.g1 = 2.0 * M_PI / g.cell[0]; I.g2 = 2.0 * M_PI / g.cell[1]; I.g3 = 2.0 * M_PI / g.cell[2];
-        I.omega = g.cell[0] * g.cell[1] * g.cell[2];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) I.B[i][j] = g.B[i][j];
+        I.general = g.general ? 1 : 0;
+        {
+            const double(*A)[3] = g.A;
+            I.omega = g.general ? std::fabs(A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) -
+                                            A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
+                                            A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]))
+                                : A[0][0] * A[1][1] * A[2][2];
+        }
         I.dvol = I.omega / (double)g.npts();
         I.fdm = c->grad_mode;
         if (c->grad_mode > 0) {
-            double w[kMaxFd];
-            central_weights(c->grad_mode, w);
-            for (int ax = 0; ax < 3; ++ax)
-                for (int s = 0; s < c->grad_mode; ++s) I.fdc[ax][s] = w[s] * (double)g.s[ax] / g.cell[ax];
+            central_weights(c->grad_mode, I.fdc);
+            // W[c][x] = N_c b_c,x / (2 pi) (orthorhombic: N_c / L_c on the diagonal)
+            for (int cc = 0; cc < 3; ++cc)
+                for (int x = 0; x < 3; ++x)
+                    I.fdW[cc][x] = g.general ? (double)g.s[cc] * g.B[cc][x] / (2.0 * M_PI)
+                                             : (cc == x ? (double)g.s[cc] / g.A[cc][cc] : 0.0);
         }
         I.grad = w + g.off_grad; I.vloc = w + g.off_vloc; I.spec = w + g.off_spec;
         I.spec3 = w + g.off_spec3; I.spec1 = w + g.off_spec1;
@@ -864,16 +945,34 @@ int vdwnl_destroy(vdwnl_ctx *ctx) {
     return VDWNL_OK;
 }
 
+// three orthorhombic lengths per grid -> the diagonal cell matrices
+static std::vector<double> diagonal_cells(int nb, const double *cells) {
+    std::vector<double> lat((size_t)9 * std::max(nb, 0), 0.0);
+    for (int i = 0; i < nb; ++i)
+        for (int c = 0; c < 3; ++c) lat[9 * i + 4 * c] = cells[3 * i + c];
+    return lat;
+}
+
 int vdwnl_set_grid(vdwnl_ctx *ctx, const int32_t shape[3], const double cell[3], int32_t grad_mode,
                    int32_t precision) {
     if (!ctx) return VDWNL_E_ARG;
-    return plan_grids(ctx, 1, shape, cell, grad_mode, precision);
+    if (!shape || !cell) return fail(ctx, VDWNL_E_ARG, "null argument or empty batch");
+    const std::vector<double> lat = diagonal_cells(1, cell);
+    return plan_grids(ctx, 1, shape, lat.data(), grad_mode, precision);
 }
 
 int vdwnl_set_grids(vdwnl_ctx *ctx, int32_t nb, const int32_t *shapes, const double *cells, int32_t grad_mode,
                     int32_t precision) {
     if (!ctx) return VDWNL_E_ARG;
-    return plan_grids(ctx, nb, shapes, cells, grad_mode, precision);
+    if (!shapes || !cells || nb <= 0) return fail(ctx, VDWNL_E_ARG, "null argument or empty batch");
+    const std::vector<double> lat = diagonal_cells(nb, cells);
+    return plan_grids(ctx, nb, shapes, lat.data(), grad_mode, precision);
+}
+
+int vdwnl_set_grids_lattice(vdwnl_ctx *ctx, int32_t nb, const int32_t *shapes, const double *lattices,
+                            int32_t grad_mode, int32_t precision) {
+    if (!ctx) return VDWNL_E_ARG;
+    return plan_grids(ctx, nb, shapes, lattices, grad_mode, precision);
 }
 
 int vdwnl_set_kernel_table(vdwnl_ctx *ctx, int32_t nq, const double *qmesh, double q_c, int32_t m_c, int32_t nk,

@@ -31,24 +31,28 @@ struct FftPlan {
 
 // Per-grid state seen by the kernels.  Field layouts (C order):
 //   n, v, vloc      [N1][N2][N3] real
-//   grad            [3][N1][N2][N3] real  (grad n; in the finite-difference mode
-//                   overwritten in place by the vector field w of the assembly)
+//   grad            [3][N1][N2][N3] real  (grad n, Cartesian components; in the
+//                   finite-difference mode overwritten in place by the lattice
+//                   components q_c = sum_x W[c][x] w_x of the assembly's vector field)
 //   spec            [N1][N2][N3h][kNQ] complex  (20 theta / u spectra, component fastest)
 //   spec3           [N1][N2][N3h][3] complex        (grad n spectra in FP64; later the
 //                   w spectra in the working precision)
 //   spec1           [N1][N2][N3h] complex           (n spectrum in FP64; later the
 //                   divergence spectrum in the working precision)
-//   shellmap        [N1/2+1][N2/2+1][N3h] int   (|G| shell of (|m1|, |m2|, m3))
+//   shellmap        [N1/2+1][N2/2+1][N3h] int   (|G| shell of (|m1|, |m2|, m3)); in a
+//                   general (non-orthogonal) cell [N1][N2][N3h] over the whole half spectrum
 //   shelltab        [nshell][kNQ][kNQ] real     (phi_ab(|G_s|), the full symmetric matrix:
 //                   row a of a shell is contiguous for the lane that forms u_a)
 struct InstDev {
     int n1, n2, n3, n3h, h1, h2;
     FftPlan p1, p2, p3;
     double inv_n;            // 1 / (N1 N2 N3)
-    double g1, g2, g3;       // 2 pi / L_c
+    double B[3][3];          // reciprocal vectors b_c (rows, Cartesian): G = sum_c m_c b_c
+    int general;             // non-orthogonal cell: shells over the whole half spectrum
     double omega, dvol;
     int fdm;                 // finite-difference half-width m (0: spectral gradient)
-    double fdc[3][kMaxFd];   // c_s / h_c: weights of the central formula on axis c
+    double fdc[kMaxFd];      // weights c_s of the central formula (unit spacing)
+    double fdW[3][3];        // W[c][x] = N_c b_c,x / (2 pi): grad n = sum_c W[c] d_c n
     void *grad, *vloc, *spec, *spec3, *spec1;
     const int *shellmap;
     const void *shelltab;

@@ -58,6 +58,16 @@ __device__ __forceinline__ int freq_nz(int k, int N) {
 }
 __device__ __forceinline__ int freq_abs(int k, int N) { return k <= N - k ? k : N - k; }
 
+// Cartesian components of G = m1 b_1 + m2 b_2 + m3 b_3 (the frequencies with
+// Nyquist taken as zero); in an orthorhombic cell the off-diagonal b_c,x are
+// zero and each component is the single product m_c b_c,c exactly.
+template <typename T>
+__device__ __forceinline__ void cart_g(const InstDev &I, double m1, double m2, double m3, T &gx, T &gy, T &gz) {
+    gx = (T)(m1 * I.B[0][0] + m2 * I.B[1][0] + m3 * I.B[2][0]);
+    gy = (T)(m1 * I.B[0][1] + m2 * I.B[1][1] + m3 * I.B[2][1]);
+    gz = (T)(m1 * I.B[0][2] + m2 * I.B[1][2] + m3 * I.B[2][2]);
+}
+
 // Sum over the workgroup in a fixed order; result valid in thread 0.
 __device__ double block_sum(double v) {
     __shared__ double red[kThreads / 64];
@@ -452,12 +462,14 @@ __global__ void __launch_bounds__(kThreads) k_x_assemble(const InstDev *insts, c
         }
         vloc[idx] = vl;
         if constexpr (FD) {
-            // w in place of grad n: each point is read and written by its own thread
+            // the lattice components q_c = sum_x W[c][x] w_x of w in place of
+            // grad n (each point is read and written by its own thread)
             const double gsd = (double)gs;
+            const double wx = gsd * (double)gx, wy = gsd * (double)gy, wz = gsd * (double)gz;
             const gptr<T> wout = gst(reinterpret_cast<T *>(I.grad) + p0);
-            wout[idx] = (T)(gsd * (double)gx);
-            wout[N + idx] = (T)(gsd * (double)gy);
-            wout[2 * N + idx] = (T)(gsd * (double)gz);
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                wout[c * N + idx] = (T)(I.fdW[c][0] * wx + I.fdW[c][1] * wy + I.fdW[c][2] * wz);
         } else {
             r1[(2 * rb) * ls + k] = mk<T>(gs * gx, gs * gy);
             r1[(2 * rb + 1) * ls + k] = mk<T>(gs * gz, (T)0);
@@ -483,7 +495,8 @@ __global__ void __launch_bounds__(kThreads) k_x_assemble(const InstDev *insts, c
 // ---------------------------------------------------------------- finite-difference passes
 
 // Central differences on the periodic grid, FP64 arithmetic on values read in
-// T: d_c f_i = sum_s (c_s / h_c) (f_{i + s e_c} - f_{i - s e_c}), s = 1..M.
+// T: d_c f_i = sum_s c_s (f_{i + s e_c} - f_{i - s e_c}), s = 1..M, along the
+// grid (lattice) axis c; grad n = sum_c W[c] d_c n with W[c][x] = N_c b_c,x / (2 pi).
 // Neighbour indices wrap once (M <= 4 <= every edge).  Tiles are runs of
 // whole axis-3 lines: a = first row (i1 N2 + i2), b = rows.
 struct FdIndex {
@@ -522,25 +535,25 @@ __device__ __forceinline__ void fd_grad_tile(const InstDev &I, int row0, int B) 
     const size_t N = (size_t)N1 * N2 * N3, plane = (size_t)N2 * N3;
     const gptr<const T> n = gld(reinterpret_cast<const T *>(I.n));
     const gptr<T> g = gst(reinterpret_cast<T *>(I.grad));
-    double c1[M], c2[M], c3[M];
+    double c[M];
 #pragma unroll
-    for (int s = 0; s < M; ++s) { c1[s] = I.fdc[0][s]; c2[s] = I.fdc[1][s]; c3[s] = I.fdc[2][s]; }
+    for (int s = 0; s < M; ++s) c[s] = I.fdc[s];
     const int npt = B * N3;
 #pragma unroll 2
     for (int idx = threadIdx.x; idx < npt; idx += kThreads) {
         const int rb = idx / N3;
         const FdIndex x(row0 + rb, idx - rb * N3, N2, N3);
-        const double d1 = fd_diff<T, M>(n, x.b1, plane, x.i1, N1, c1);
-        const double d2 = fd_diff<T, M>(n, x.b2, (size_t)N3, x.i2, N2, c2);
-        const double d3 = fd_diff<T, M>(n, x.b3, 1, x.i3, N3, c3);
-        g[x.p] = (T)d1;
-        g[N + x.p] = (T)d2;
-        g[2 * N + x.p] = (T)d3;
+        const double d1 = fd_diff<T, M>(n, x.b1, plane, x.i1, N1, c);
+        const double d2 = fd_diff<T, M>(n, x.b2, (size_t)N3, x.i2, N2, c);
+        const double d3 = fd_diff<T, M>(n, x.b3, 1, x.i3, N3, c);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) g[a * N + x.p] = (T)(I.fdW[0][a] * d1 + I.fdW[1][a] * d2 + I.fdW[2][a] * d3);
     }
 }
 
-// v = v_loc - sum_c D_c w_c, w in the grad n buffer (Eq. (Vi): the sum over j
-// of w_j . d(grad n_j)/dn_i is minus the divergence, the operator being
+// v = v_loc - sum_c d_c q_c, q_c = sum_x W[c][x] w_x in the grad n buffer
+// (Eq. (Vi): the sum over j of w_j . d(grad n_j)/dn_i is the transpose of the
+// gradient operator applied to w, minus the same stencils since they are
 // antisymmetric).
 template <typename T, int M>
 __device__ __forceinline__ void fd_div_tile(const InstDev &I, int row0, int B) {
@@ -549,18 +562,18 @@ __device__ __forceinline__ void fd_div_tile(const InstDev &I, int row0, int B) {
     const gptr<const T> w = gld(reinterpret_cast<const T *>(I.grad));
     const gptr<const T> vloc = gld(reinterpret_cast<const T *>(I.vloc));
     const gptr<T> v = gst(reinterpret_cast<T *>(I.v));
-    double c1[M], c2[M], c3[M];
+    double c[M];
 #pragma unroll
-    for (int s = 0; s < M; ++s) { c1[s] = I.fdc[0][s]; c2[s] = I.fdc[1][s]; c3[s] = I.fdc[2][s]; }
+    for (int s = 0; s < M; ++s) c[s] = I.fdc[s];
     const int npt = B * N3;
 #pragma unroll 2
     for (int idx = threadIdx.x; idx < npt; idx += kThreads) {
         const int rb = idx / N3;
         const FdIndex x(row0 + rb, idx - rb * N3, N2, N3);
         const double vl = (double)vloc[x.p];
-        const double d1 = fd_diff<T, M>(w, x.b1, plane, x.i1, N1, c1);
-        const double d2 = fd_diff<T, M>(w + N, x.b2, (size_t)N3, x.i2, N2, c2);
-        const double d3 = fd_diff<T, M>(w + 2 * N, x.b3, 1, x.i3, N3, c3);
+        const double d1 = fd_diff<T, M>(w, x.b1, plane, x.i1, N1, c);
+        const double d2 = fd_diff<T, M>(w + N, x.b2, (size_t)N3, x.i2, N2, c);
+        const double d3 = fd_diff<T, M>(w + 2 * N, x.b3, 1, x.i3, N3, c);
         v[x.p] = (T)(vl - (d1 + d2 + d3));
     }
 }
@@ -667,12 +680,12 @@ __global__ void __launch_bounds__(kThreads) k_z_grad(const InstDev *insts, const
     load_twiddles<T>(twall, I.p1, reinterpret_cast<const C2<T> *>(twv));
     __syncthreads();
     fft_lc<T, -1, LC>(bin, I.p1, K3, 1, lp, twall);
-    const T G2 = (T)(I.g2 * freq_nz(k2, N2));
+    const double m2 = (double)freq_nz(k2, N2);
     for (int idx = threadIdx.x; idx < N1 * K3; idx += kThreads) {
         const int w = idx / N1, l = idx - w * N1;
         const C2<T> nh = cscale(bin[w * lp + l], (T)I.inv_n);
-        const T G1 = (T)(I.g1 * freq_nz(l, N1));
-        const T G3 = (T)(I.g3 * freq_nz(k30 + w, N3));
+        T G1, G2, G3;
+        cart_g<T>(I, (double)freq_nz(l, N1), m2, (double)freq_nz(k30 + w, N3), G1, G2, G3);
         C2<T> *o = bout + 3 * w * lp + l;
         o[0] = mk<T>(-G1 * nh.y, G1 * nh.x);
         o[lp] = mk<T>(-G2 * nh.y, G2 * nh.x);
@@ -702,12 +715,12 @@ __global__ void __launch_bounds__(kThreads) k_z_div(const InstDev *insts, const 
     load_twiddles<T>(twall, I.p1, reinterpret_cast<const C2<T> *>(twv));
     __syncthreads();
     fft_lc<T, -1, LC>(bin, I.p1, 3 * K3, 1, lp, twall);
-    const T G2 = (T)(I.g2 * freq_nz(k2, N2));
+    const double m2 = (double)freq_nz(k2, N2);
     for (int idx = threadIdx.x; idx < N1 * K3; idx += kThreads) {
         const int w = idx / N1, l = idx - w * N1;
         const C2<T> *x = bin + 3 * w * lp + l;
-        const T G1 = (T)(I.g1 * freq_nz(l, N1));
-        const T G3 = (T)(I.g3 * freq_nz(k30 + w, N3));
+        T G1, G2, G3;
+        cart_g<T>(I, (double)freq_nz(l, N1), m2, (double)freq_nz(k30 + w, N3), G1, G2, G3);
         const T sx = G1 * x[0].x + G2 * x[lp].x + G3 * x[2 * lp].x;
         const T sy = G1 * x[0].y + G2 * x[lp].y + G3 * x[2 * lp].y;
         bout[w * lp + l] = cscale(mk<T>(-sy, sx), (T)I.inv_n);
@@ -824,16 +837,20 @@ __global__ void __launch_bounds__(kThreads) k_z_main(const InstDev *insts, const
     load_twiddles<T>(twall, I.p1, reinterpret_cast<const C2<T> *>(twv));
 
     const T *tab = reinterpret_cast<const T *>(I.shelltab);
-    const int m2 = freq_abs(c0.x, N2), k30 = c0.y;
+    // orthorhombic cell: item = |m1| P + pair, the +-m1 points share a shell;
+    // general cell: item = k1 P + pair over the whole axis, a shell each
+    const bool general = I.general != 0;
+    const int k30 = c0.y;
+    const int m2 = general ? c0.x : freq_abs(c0.x, N2);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int grp = lane / kNQ, al = lane - grp * kNQ;
     const bool lane_on = grp < 64 / kNQ;
     const int gid = wave * (64 / kNQ) + grp;
-    const int nitems = (N1 / 2 + 1) * P;                     // item = |m1| P + pair
+    const int nitems = (general ? N1 : N1 / 2 + 1) * P;
     // shell of every item, into LDS (the loads overlap the forward FFT)
     {
         const gptr<const int> smap = gld(I.shellmap + (size_t)m2 * N3h + k30);
-        const size_t smap_m1 = (size_t)I.h2 * N3h;
+        const size_t smap_m1 = (size_t)(general ? N2 : I.h2) * N3h;
         for (int i = threadIdx.x; i < nitems; i += kThreads) {
             const int m1 = i / P;
             sidx[i] = smap[m1 * smap_m1 + (i - m1 * P)];
@@ -877,7 +894,7 @@ __global__ void __launch_bounds__(kThreads) k_z_main(const InstDev *insts, const
     auto process = [&](const T *f) {
         const int l = m1;
         int lq = N1 - m1;
-        if (m1 == 0 || lq == m1) lq = -1;     // k1 = 0 and the Nyquist plane stand alone
+        if (general || m1 == 0 || lq == m1) lq = -1;   // k1 = 0 and the Nyquist plane stand alone
         const int w0 = __mul24(pr, CP);
         m1 += dm;
         pr += dr;

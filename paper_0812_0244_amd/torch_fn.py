@@ -23,11 +23,13 @@ class NonlocalCorrelation:
 
     def __init__(self, shape, cell, table, precision: int = 32, device: int = 0, grad_mode: int = 0):
         self.shape = tuple(int(s) for s in shape)
-        self.cell = tuple(float(c) for c in cell)
+        c = np.asarray(cell, dtype=np.float64)
+        self.cell = tuple(float(x) for x in c) if c.shape == (3,) else c.reshape(3, 3).copy()
         self.precision = precision
         self.device = device
         self.dtype = torch.float64 if precision == 64 else torch.float32
-        self.dvol = float(np.prod(self.cell)) / float(np.prod(self.shape))
+        vol = float(np.prod(c)) if c.shape == (3,) else abs(float(np.linalg.det(c.reshape(3, 3))))
+        self.dvol = vol / float(np.prod(self.shape))
         self.lib = VdwNl(device)
         self.grad_mode = grad_mode
         self.lib.set_grid(self.shape, self.cell, grad_mode, precision)

@@ -133,3 +133,28 @@ def test_binding_fails_loudly_without_library(tmp_path):
             B.load_library(str(tmp_path / "missing.so"))
     finally:
         B._lib = saved
+
+
+def test_lattice_planning_checks():
+    """Cells given by their vectors: a triclinic cell plans, a singular or
+    non-finite one is rejected; a diagonal matrix plans like the lengths."""
+    lib, h = _host_ctx()
+    s = np.array([20, 18, 24], dtype=np.int32)
+    ip = ctypes.POINTER(ctypes.c_int32)
+    dp = ctypes.POINTER(ctypes.c_double)
+
+    def plan(cell):
+        c = np.ascontiguousarray(np.asarray(cell, dtype=np.float64).reshape(-1))
+        return lib.vdwnl_set_grids_lattice(h, 1, s.ctypes.data_as(ip), c.ctypes.data_as(dp), 0, 32)
+
+    tri = np.array([[8.0, 0.0, 0.0], [3.05, 6.85, 0.0], [-2.2, 1.9, 7.9]])
+    assert plan(tri) == 0
+    assert plan(np.diag([8.0, 9.0, 10.0])) == 0
+    flat = tri.copy()
+    flat[2] = flat[0] + flat[1]                  # a_3 in the plane of a_1, a_2
+    assert plan(flat) == E["ARG"]
+    nan = tri.copy()
+    nan[1, 2] = np.nan
+    assert plan(nan) == E["ARG"]
+    assert lib.vdwnl_set_grids_lattice(h, 1, s.ctypes.data_as(ip), None, 0, 32) == E["ARG"]
+    lib.vdwnl_destroy(h)

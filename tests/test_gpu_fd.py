@@ -5,8 +5,9 @@ oracle, through the C ABI.
 Same bars as the spectral mode: FP64 to rounding (relative 1e-10 in each
 energy part and in max|v|), FP32 at relative energy error <= 1e-6 and
 max|dv| <= 1e-5 Ha against the oracle of the FP32-rounded density.  The
-intermediates are compared too: the vector field w of Eq. (Vi) (which the
-library stores in place of grad n in this mode) and v_loc.
+intermediates are compared too: the vector field w of Eq. (Vi) (whose
+lattice components q_c = sum_x W[c][x] w_x the library stores in place of
+grad n in this mode) and v_loc.
 """
 import sys
 
@@ -74,7 +75,9 @@ def test_c1_fp64_fd_parity_with_intermediates(table, m):
     o = F.energy_potential(n, wl.cell, table, return_parts=True, grad_mode=m)
     g = gpu_eval(n, wl.cell, table, 64, m, debug=True)
     np.testing.assert_allclose(g["v_loc"], o["v_loc"], rtol=0, atol=1e-10 * np.abs(o["v_loc"]).max())
-    np.testing.assert_allclose(g["w"], o["w"], rtol=0, atol=1e-10 * np.abs(o["w"]).max())
+    # the buffer holds the lattice components q_c = sum_x W[c][x] w_x of w
+    q = np.einsum("cx,x...->c...", F.fd_metric(n.shape, wl.cell), o["w"])
+    np.testing.assert_allclose(g["w"], q, rtol=0, atol=1e-10 * np.abs(q).max())
     check(g, o, 64)
 
 
