@@ -174,8 +174,15 @@ struct vdwnl_ctx {
     struct Launch {
         int kind, lc, off, cnt;
         size_t lds;
+        int group;
     };
-    std::vector<Launch> launches[KIND_COUNT];   // per pass: one launch per FFT length class
+    // per pass: one launch per group of grids (grids whose three axes fall in
+    // the same FFT length classes); the groups' chains of passes are
+    // independent of each other
+    std::vector<Launch> launches[KIND_COUNT];
+    int ngroups = 0;
+    std::vector<hipStream_t> chain_streams;   // one per group (graph capture)
+    std::vector<hipEvent_t> chain_events;     // fork (index 0) and one join per group
     void *d_tw = nullptr;                 // twiddles in the working precision
     void *d_twd = nullptr;                // FP64 twiddles
     Consts *d_consts = nullptr;
@@ -221,6 +228,10 @@ static void free_device(vdwnl_ctx *c) {
     drop_graph(c);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     c->cap_stream = nullptr;
+    for (auto s : c->chain_streams) (void)hipStreamDestroy(s);
+    c->chain_streams.clear();
+    for (auto ev : c->chain_events) (void)hipEventDestroy(ev);
+    c->chain_events.clear();
     if (c->ev_made) {
         for (auto &e : c->ev) (void)hipEventDestroy(e);
         c->ev_made = false;
@@ -657,16 +668,31 @@ static int prepare_device(vdwnl_ctx *c) {
             default: return g.s[0];
         }
     };
+    // groups: grids with the same length classes on all three axes (every
+    // pass of a group is then one launch).  (Dealing a group with a large
+    // share of the points into sub-groups measured no faster.)
+    std::vector<int> group_of(c->grids.size());
+    {
+        std::vector<int> keys;
+        for (size_t gi = 0; gi < c->grids.size(); ++gi) {
+            const Grid &g = c->grids[gi];
+            const int key = (len_class(g.s[0]) * kNumLenClasses + len_class(g.s[1])) * kNumLenClasses + len_class(g.s[2]);
+            auto it = std::find(keys.begin(), keys.end(), key);
+            group_of[gi] = (int)(it - keys.begin());
+            if (it == keys.end()) keys.push_back(key);
+        }
+        c->ngroups = (int)keys.size();
+    }
     std::vector<Tile> all;
     for (int k = 0; k < KIND_COUNT; ++k) {
         c->launches[k].clear();
-        for (int lc = 0; lc < kNumLenClasses; ++lc) {
-            vdwnl_ctx::Launch L{k, lc, (int)all.size(), 0, 0};
+        for (int grp = 0; grp < c->ngroups; ++grp) {
+            vdwnl_ctx::Launch L{k, 0, (int)all.size(), 0, 0, grp};
             for (const Tile &tl : tiles[k]) {
+                if (group_of[tl.inst] != grp) continue;
                 const Grid &g = c->grids[tl.inst];
-                // the stencil passes transform nothing: one launch for every grid
-                const int klc = (k == KF_GRAD || k == KF_DIV) ? 0 : len_class(axis_len(k, g));
-                if (klc != lc) continue;
+                // the stencil passes transform nothing (class 0 for any grid)
+                L.lc = (k == KF_GRAD || k == KF_DIV) ? 0 : len_class(axis_len(k, g));
                 all.push_back(tl);
                 L.lds = std::max(L.lds, lds_of(k, g));
             }
@@ -790,20 +816,44 @@ static int prepare_device(vdwnl_ctx *c) {
 // Enqueue one evaluation on st: the instance table (device pointers of this
 // call's n and v), the passes of the gradient mode, the reduction and the copy of the
 // energies to pinned host memory.  With timing on, events bracket each pass.
-static int enqueue(vdwnl_ctx *c, int nb, hipStream_t st) {
+// With chains (graph capture of a batch of several groups) each group's
+// passes go to a stream of its own, forked from st and joined back before
+// the reduction: the groups' chains are independent, so a pass of one group
+// can run beside a pass of another.  Otherwise the passes go in order on st.
+static int enqueue(vdwnl_ctx *c, int nb, hipStream_t st, bool chains = false) {
     hipError_t e;
     if ((e = hipMemcpyAsync(c->d_inst, c->h_inst, nb * sizeof(InstDev), hipMemcpyHostToDevice, st)) != hipSuccess)
         return hipfail(c, e, "upload instance table");
     if (c->timing) (void)hipEventRecord(c->ev[0], st);
     const int *order;
     const int npass = pass_order(c->grad_mode, &order);
-    for (int i = 0; i < npass; ++i) {
-        const int k = order[i];
-        for (const auto &L : c->launches[k]) {
-            LaunchArgs a{c->d_inst, c->d_tiles + L.off, L.cnt, L.lds, c->d_consts, c->d_tw, c->d_twd, st, c->d_cols};
-            if ((e = launch_kind(k, L.lc, c->precision, a)) != hipSuccess) return hipfail(c, e, "kernel launch");
+    auto launch = [&](const vdwnl_ctx::Launch &L, hipStream_t s) -> int {
+        LaunchArgs a{c->d_inst, c->d_tiles + L.off, L.cnt, L.lds, c->d_consts, c->d_tw, c->d_twd, s, c->d_cols};
+        const hipError_t le = launch_kind(L.kind, L.lc, c->precision, a);
+        return le == hipSuccess ? VDWNL_OK : hipfail(c, le, "kernel launch");
+    };
+    if (chains) {
+        if ((e = hipEventRecord(c->chain_events[0], st)) != hipSuccess) return hipfail(c, e, "fork event");
+        for (int grp = 0; grp < c->ngroups; ++grp) {
+            hipStream_t cs = c->chain_streams[grp];
+            if ((e = hipStreamWaitEvent(cs, c->chain_events[0], 0)) != hipSuccess) return hipfail(c, e, "fork wait");
+            for (int i = 0; i < npass; ++i)
+                for (const auto &L : c->launches[order[i]])
+                    if (L.group == grp) {
+                        const int rc = launch(L, cs);
+                        if (rc != VDWNL_OK) return rc;
+                    }
+            if ((e = hipEventRecord(c->chain_events[1 + grp], cs)) != hipSuccess) return hipfail(c, e, "join event");
+            if ((e = hipStreamWaitEvent(st, c->chain_events[1 + grp], 0)) != hipSuccess) return hipfail(c, e, "join wait");
         }
-        if (c->timing) (void)hipEventRecord(c->ev[i + 1], st);
+    } else {
+        for (int i = 0; i < npass; ++i) {
+            for (const auto &L : c->launches[order[i]]) {
+                const int rc = launch(L, st);
+                if (rc != VDWNL_OK) return rc;
+            }
+            if (c->timing) (void)hipEventRecord(c->ev[i + 1], st);
+        }
     }
     if ((e = launch_reduce(c->d_inst, nb, c->d_E, st)) != hipSuccess) return hipfail(c, e, "reduce launch");
     if (c->timing) (void)hipEventRecord(c->ev[npass + 1], st);
@@ -821,9 +871,21 @@ static int capture(vdwnl_ctx *c, int nb) {
         c->cap_stream = nullptr;
         return hipfail(c, e, "hipStreamCreate");
     }
+    // streams and events of the groups' chains (created once; default priority)
+    const bool chains = c->ngroups > 1;
+    while (chains && (int)c->chain_streams.size() < c->ngroups) {
+        hipStream_t s = nullptr;
+        if ((e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) != hipSuccess) return hipfail(c, e, "hipStreamCreate");
+        c->chain_streams.push_back(s);
+    }
+    while (chains && (int)c->chain_events.size() < c->ngroups + 1) {
+        hipEvent_t ev = nullptr;
+        if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return hipfail(c, e, "hipEventCreate");
+        c->chain_events.push_back(ev);
+    }
     if ((e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed)) != hipSuccess)
         return hipfail(c, e, "hipStreamBeginCapture");
-    const int rc = enqueue(c, nb, c->cap_stream);
+    const int rc = enqueue(c, nb, c->cap_stream, chains);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(c->cap_stream, &g);
     if (rc != VDWNL_OK) {

@@ -918,10 +918,13 @@ __global__ void __launch_bounds__(kThreads) k_z_main(const InstDev *insts, const
             const double wgt = edge ? wn : 2.0 * wn;
             e += wgt * (double)(own1.x * u1.x + own1.y * u1.y);
             if (lq >= 0) e += wgt * (double)(own2.x * u2.x + own2.y * u2.y);
+            // every lane of the group has read theta at these points before
+            // any lane overwrites its component with u; the next column or
+            // item reads other points (each k point belongs to one item), so
+            // no ordering is needed after the writes
             wave_sync();
             x1[al * lp] = cscale(u1, inv_n);
             if (lq >= 0) x2[al * lp] = cscale(u2, inv_n);
-            wave_sync();
         }
     };
     for (int it = gid; lane_on && it < nitems;) {
