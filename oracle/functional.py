@@ -1,5 +1,5 @@
 """Oracle: the nonlocal correlation energy E_c^nl and potential v_nl of a
-density on a periodic orthorhombic grid, plain FP64 NumPy/SciPy.
+density on a periodic grid (a cell of any shape), plain FP64 NumPy/SciPy.
 
 TEST INFRASTRUCTURE.  Only ``tests/``, the smoke check and the CPU-baseline
 leg of the benchmark may import this module.  It shares no code with the
@@ -38,6 +38,13 @@ open are marked READING; each has a line in the design notes.
  O14 v = v_loc - sum_c D_c w_c, Eq. (Vi): the sum over j of
      w_j . d(grad n_j)/dn_i is the transpose of the (antisymmetric)
      derivative operator applied to w.
+ O15 (xc_energy_potential only) the semilocal terms of Eq. (Exc):
+     E_x^GGA (READING: the Zhang-Yang revPBE exchange, i.e. the PBE
+     enhancement factor with kappa = 1.245) and E_c^LDA (the Perdew-Wang
+     1992 LDA of O2).  Their energy densities depend on n and |grad n|^2
+     only, so their derivatives add to v_loc and w of O13 and pass through
+     the same gradient adjoint O14, as the paper does for the semilocal
+     terms (Sec. on the potential, around Eq. (Vi)).
 """
 from __future__ import annotations
 
@@ -66,6 +73,37 @@ def pw92(n):
                 + 2.0 * PW_A * (1.0 + PW_ALPHA1 * rs) * dP / (P * (2.0 * PW_A * P + 1.0)))
     drs_dn = -rs / (3.0 * n)
     return eps, deps_drs * drs_dn
+
+
+# ---------------------------------------------------------------- O15
+# revPBE exchange (READING): e_x = n eps_x^unif(n) F_x(s), eps_x^unif =
+# -3 k_F / (4 pi), s^2 = sigma / (4 k_F^2 n^2),
+# F_x = 1 + kappa - kappa / (1 + mu s^2 / kappa); mu = beta pi^2 / 3 of PBE
+REVPBE_KAPPA = 1.245
+PBE_MU = 0.066725 * np.pi ** 2 / 3.0
+
+
+def exchange_gga(n, sigma):
+    """e_x per volume and its partials with respect to n and sigma = |grad n|^2."""
+    n = np.asarray(n, dtype=np.float64)
+    sigma = np.asarray(sigma, dtype=np.float64)
+    kf = (3.0 * np.pi * np.pi * n) ** (1.0 / 3.0)
+    e_unif = -3.0 * kf * n / (4.0 * np.pi)                  # n eps_x^unif
+    ds2_dsigma = 1.0 / (4.0 * kf * kf * n * n)
+    s2 = sigma * ds2_dsigma
+    den = 1.0 + PBE_MU * s2 / REVPBE_KAPPA
+    fx = 1.0 + REVPBE_KAPPA - REVPBE_KAPPA / den
+    dfx = PBE_MU / (den * den)                               # dF_x / ds^2
+    # d e_unif/dn = (4/3) e_unif / n;  d s^2/dn = -(8/3) s^2 / n
+    de_dn = (4.0 / 3.0) * e_unif / n * fx - (8.0 / 3.0) * e_unif * dfx * s2 / n
+    de_ds = e_unif * dfx * ds2_dsigma
+    return e_unif * fx, de_dn, de_ds
+
+
+def correlation_lda(n):
+    """e_c = n eps_c(n) per volume (O2) and de_c/dn."""
+    eps, deps = pw92(n)
+    return n * eps, eps + n * deps
 
 
 # ---------------------------------------------------------------- O3
@@ -326,6 +364,22 @@ def energy_potential(n, cell, table, n_min=N_MIN, return_parts=False, grad_mode=
     """(E_k, Delta E, v) for the density n [N1, N2, N3] in the cell (bohr:
     three orthorhombic lengths or the 3 x 3 matrix of cell vectors);
     grad_mode 0: spectral gradient, m = 1..4: central differences of order 2m."""
+    parts = _evaluate(n, cell, table, n_min, grad_mode, semilocal=False)
+    if return_parts:
+        return parts
+    return parts["E_k"], parts["dE"], parts["v"]
+
+
+def xc_energy_potential(n, cell, table, n_min=N_MIN, return_parts=False, grad_mode=0):
+    """The whole functional of Eq. (Exc): (E_k, Delta E, E_x^GGA, E_c^LDA, v_xc)
+    with v_xc = v_nl + v_x + v_c^LDA (O15); arguments as energy_potential."""
+    parts = _evaluate(n, cell, table, n_min, grad_mode, semilocal=True)
+    if return_parts:
+        return parts
+    return parts["E_k"], parts["dE"], parts["E_x"], parts["E_c"], parts["v"]
+
+
+def _evaluate(n, cell, table, n_min, grad_mode, semilocal):
     n = np.asarray(n, dtype=np.float64)
     shape = n.shape
     N = n.size
@@ -352,12 +406,23 @@ def energy_potential(n, cell, table, n_min=N_MIN, return_parts=False, grad_mode=
     de = dvol * np.sum(loc["e_delta"])                         # O11
     v_loc = np.sum(u * loc["dtheta_dn"], axis=0) + loc["de_dn"]                  # O13
     gsc = np.sum(u * loc["g"], axis=0) + loc["ge"]
+    sl = {}
+    if semilocal:                                              # O15
+        ok = n >= n_min
+        ns = np.where(ok, n, 1.0)
+        sigma = np.where(ok, np.sum(grad * grad, axis=0), 0.0)
+        ex, dex_dn, dex_ds = exchange_gga(ns, sigma)
+        ec, dec_dn = correlation_lda(ns)
+        z = ~ok
+        for arr in (ex, dex_dn, dex_ds, ec, dec_dn):
+            arr[z] = 0.0
+        v_loc = v_loc + dex_dn + dec_dn
+        gsc = gsc + 2.0 * dex_ds                               # de/dgrad n = 2 de/dsigma grad n
+        sl = dict(E_x=dvol * np.sum(ex), E_c=dvol * np.sum(ec))
     wvec = gsc[None] * grad
     if grad_mode == 0:
         v = v_loc - divergence(wvec, cell)                     # O14
     else:
         v = v_loc - divergence_fd(wvec, cell, grad_mode)
-    if return_parts:
-        return dict(E_k=ek, dE=de, v=v, u=u, chat=chat, uhat=uhat, grad=grad, v_loc=v_loc,
-                    w=wvec, **loc)
-    return ek, de, v
+    return dict(E_k=ek, dE=de, v=v, u=u, chat=chat, uhat=uhat, grad=grad, v_loc=v_loc,
+                w=wvec, **sl, **loc)
