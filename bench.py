@@ -118,6 +118,9 @@ def main():
                     help="finite-difference half-width of the second leg (0: skip that leg)")
     ap.add_argument("--lattice-leg", type=int, default=1,
                     help="1: also time the batch in triclinic cells (general-cell path); 0: skip")
+    ap.add_argument("--xc-leg", type=int, default=1,
+                    help="1: also time the batch with the whole functional of Eq. (Exc) "
+                         "(semilocal terms added); 0: skip")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain device copy of 1 GiB (reference dispatch for "
                          "hardware byte counters)")
@@ -206,6 +209,32 @@ def main():
     dom_bytes = pass_bytes(dom, shapes, 4)
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
     path_bytes = sum(pass_bytes(k, shapes, 4) for k in passes)
+
+    # ---- the same batch with the whole functional of Eq. (Exc): revPBE
+    # exchange and LDA correlation added in the theta and assembly passes
+    xc = None
+    if args.xc_leg:
+        from paper_0812_0244_amd.binding import FUNCTIONAL_NONLOCAL, FUNCTIONAL_VDW_DF
+        lib.set_functional(FUNCTIONAL_VDW_DF)
+        for _ in range(args.warmup):
+            lib.energy_potential_batched(nptr, vptr, stream)
+        torch.cuda.synchronize()
+        xc_ms = []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ts = time.perf_counter()
+            Exc = lib.energy_potential_batched(nptr, vptr, stream)
+            xc_ms.append((time.perf_counter() - ts) * 1e3)
+        torch.cuda.synchronize()
+        xc_step = (time.perf_counter() - t0) * 1e3 / args.steps
+        sl = lib.semilocal_energies()
+        lib.set_functional(FUNCTIONAL_NONLOCAL)
+        log("fp32 batched, whole functional (graph replay): %.3f ms/step, median %.3f"
+            % (xc_step, float(np.median(xc_ms))))
+        xc = {"functional": "E_x^GGA (revPBE) + E_c^LDA (PW92) + E_c^nl, v_xc",
+              "ms_per_step": xc_step, "median_ms_per_step": float(np.median(xc_ms)),
+              "value": total / (xc_step * 1e-3), "unit": "grid-points/s",
+              "E_sum": float(Exc.sum()), "E_x_sum": float(sl[:, 0].sum()), "E_c_lda_sum": float(sl[:, 1].sum())}
 
     # ---- the same workload with the finite-difference gradient (the paper's
     # own choice; seven passes instead of fourteen), FP32 batched
@@ -371,6 +400,7 @@ def main():
                      "path_frac": path_bytes / (ms_step * 1e-3) / 1e9 / PEAK_HBM_GBS},
         "fd_gradient": fd,
         "triclinic_cells": tri,
+        "whole_functional": xc,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

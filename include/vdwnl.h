@@ -6,13 +6,15 @@
  *
  * Following the paper's statement of the problem (the paragraph after
  * Eq. (epsofk)), the library accepts the density n(r_i) on a uniform periodic
- * real-space grid and returns E_c^nl and v_nl(r_i) on the same grid.
+ * real-space grid and returns E_c^nl and v_nl(r_i) on the same grid (or, with
+ * vdwnl_set_functional, the whole E_xc of Eq. (Exc) and v_xc).
  *
  * Conventions
  *  - Hartree atomic units (bohr, Hartree).
- *  - Grids are orthorhombic: cell lengths L1, L2, L3 along the three axes;
- *    arrays are C order [N1][N2][N3] (N3 fastest); r_i = (i1 L1/N1, i2 L2/N2,
- *    i3 L3/N3).
+ *  - vdwnl_set_grid(s) take orthorhombic cells (lengths L1, L2, L3 along the
+ *    three axes), vdwnl_set_grids_lattice cells of any shape (three cell
+ *    vectors); arrays are C order [N1][N2][N3] (N3 fastest); r_i =
+ *    (i1/N1) a_1 + (i2/N2) a_2 + (i3/N3) a_3 for cell vectors a_c.
  *  - Precision 32 or 64 selects the arithmetic of every device array and
  *    kernel (float / double); global reductions are always FP64.
  *  - Every function returns VDWNL_OK (0) or a negative error code; nothing
@@ -136,6 +138,30 @@ int vdwnl_energy_potential(vdwnl_ctx *ctx, const void *n_dev, void *v_dev, doubl
 int vdwnl_energy_potential_batched(vdwnl_ctx *ctx, int32_t nb, const void *const *n_ptrs,
                                    void *const *v_ptrs, double *E_out, void *stream);
 
+/* Which functional an evaluation computes (Eq. (Exc) of the paper:
+ * E_xc = E_x^GGA + E_c^LDA + E_c^nl).
+ *   VDWNL_FUNCTIONAL_NONLOCAL (the default): v = v_nl, E_c^nl only.
+ *   VDWNL_FUNCTIONAL_VDW_DF: the whole functional.  v receives v_xc =
+ *     v_nl + v_x + v_c^LDA, where the semilocal terms are the revPBE GGA
+ *     exchange of Zhang and Yang (the PBE enhancement factor
+ *     F_x = 1 + kappa - kappa / (1 + mu s^2 / kappa), kappa = 1.245,
+ *     mu = 0.066725 pi^2 / 3) and the Perdew-Wang 1992 LDA correlation (the
+ *     LDA inside q0); their gradient parts go through the same adjoint of the
+ *     gradient as the nonlocal term (the paper's Sec. on the potential,
+ *     around Eq. (Vi)).  E_out still holds (E_k, Delta E); the semilocal
+ *     energies come from vdwnl_semilocal_energies.
+ * The setting applies from the next evaluation on (no re-planning; a
+ * captured graph reads it from the instance table).  VDWNL_E_ARG for any
+ * other value. */
+enum { VDWNL_FUNCTIONAL_NONLOCAL = 0, VDWNL_FUNCTIONAL_VDW_DF = 1 };
+int vdwnl_set_functional(vdwnl_ctx *ctx, int32_t functional);
+
+/* E_out[nb][2] (host): E_x^GGA and E_c^LDA (Hartree, FP64 sums) of every grid
+ * of the last evaluation, which must have run with VDWNL_FUNCTIONAL_VDW_DF
+ * (else VDWNL_E_STATE; also before any evaluation and after re-planning).
+ * nb must equal the planned number of grids (VDWNL_E_ARG). */
+int vdwnl_semilocal_energies(const vdwnl_ctx *ctx, int32_t nb, double *E_out);
+
 /* Copy an internal per-grid field of the last evaluation of grid `inst` to
  * the device buffer dst (for parity probes): which = 0: grad n [3][N] with
  * the spectral gradient; with finite differences the same buffer holds, after
@@ -143,7 +169,8 @@ int vdwnl_energy_potential_batched(vdwnl_ctx *ctx, int32_t nb, const void *const
  * N_c b_c,x / (2 pi), N_c / L_c on the diagonal of an orthorhombic cell) of
  * the vector field w = sum_a u_a dtheta_a/dgrad n + de/dgrad n of Eq. (Vi)
  * (grad n is overwritten in place); 1: v_loc [N] (the local
- * part of v, before the gradient term).  Arrays in the planned precision. */
+ * part of v, before the gradient term; with the whole functional it includes
+ * the semilocal terms' local parts).  Arrays in the planned precision. */
 int vdwnl_debug_field(vdwnl_ctx *ctx, int32_t inst, int32_t which, void *dst, void *stream);
 
 /* Per-pass timing.  vdwnl_set_timing(ctx, 1) clears the counters and makes

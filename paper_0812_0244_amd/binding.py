@@ -43,12 +43,17 @@ SIGNATURES = {
                                                 _i32, ctypes.c_double, _dp, _dp]),
     "vdwnl_kernel_phi": (ctypes.c_int, [ctypes.c_int, _i32, _dp, _dp, _dp]),
     "vdwnl_set_graph": (ctypes.c_int, [_vp, _i32]),
+    "vdwnl_set_functional": (ctypes.c_int, [_vp, _i32]),
+    "vdwnl_semilocal_energies": (ctypes.c_int, [_vp, _i32, _dp]),
     "vdwnl_autotune": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _i32, _vp]),
     "vdwnl_get_tiling": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(ctypes.c_int64)]),
     "vdwnl_set_tiling": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(ctypes.c_int64)]),
 }
 
 _lib = None
+
+FUNCTIONAL_NONLOCAL = 0
+FUNCTIONAL_VDW_DF = 1
 
 
 class VdwNlError(RuntimeError):
@@ -200,6 +205,18 @@ class VdwNl:
 
     def set_graph(self, on: bool = True):
         self._check(self.lib.vdwnl_set_graph(self.h, 1 if on else 0), "set_graph")
+
+    def set_functional(self, functional: int):
+        """FUNCTIONAL_NONLOCAL (E_c^nl, v_nl) or FUNCTIONAL_VDW_DF (the whole E_xc, v_xc)."""
+        self._check(self.lib.vdwnl_set_functional(self.h, int(functional)), "set_functional")
+
+    def semilocal_energies(self):
+        """[nb, 2]: E_x^GGA and E_c^LDA of every grid of the last evaluation."""
+        nb, _ = self.info()
+        E = np.zeros((nb, 2))
+        self._check(self.lib.vdwnl_semilocal_energies(self.h, nb, _as_ptr(E, ctypes.c_double)),
+                    "semilocal_energies")
+        return E
 
     def autotune(self, n_ptrs, v_ptrs, reps: int = 2, stream: int = 0):
         nb = len(n_ptrs)

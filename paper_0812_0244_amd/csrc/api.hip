@@ -133,7 +133,7 @@ struct Grid {
     int k3main, k3aux;       // k3 per fused axis-1 tile (20 comps), per grad/div tile
     int wy20, wy3, wy1;      // axis-2 tile widths
     int shell_key;           // index into Ctx::shells
-    size_t off_grad, off_vloc, off_spec, off_spec3, off_spec1, off_map, off_tab, off_ek, off_de;
+    size_t off_grad, off_vloc, off_spec, off_spec3, off_spec1, off_map, off_tab, off_ek, off_de, off_sl;
     int n_ek, n_de;
     size_t npts() const { return (size_t)s[0] * s[1] * s[2]; }
     size_t nhalf() const { return (size_t)s[0] * s[1] * (s[2] / 2 + 1); }
@@ -148,6 +148,8 @@ struct vdwnl_ctx {
     size_t lds_cap = kLdsCap;             // LDS bytes one workgroup may take on this device
     int precision = 32;
     int grad_mode = 0;
+    int functional = VDWNL_FUNCTIONAL_NONLOCAL;
+    int last_functional = -1;             // of the last finished evaluation (-1: none)
     std::string err;
     size_t pref[TG_COUNT] = {kLdsCap, kLdsCap, kLdsCap, kLdsCap, kLdsCap};   // LDS budget per pass group
     std::string plan_key;                 // identifies the batch for the tuned-budget cache
@@ -223,6 +225,7 @@ static void drop_graph(vdwnl_ctx *c) {
 }
 
 static void free_device(vdwnl_ctx *c) {
+    c->last_functional = -1;
     if (c->device < 0) return;
     (void)hipSetDevice(c->device);
     drop_graph(c);
@@ -634,6 +637,7 @@ static int prepare_device(vdwnl_ctx *c) {
         g.off_spec1 = off; off = align_up(off + aux * 16);
         g.off_ek = off; off = align_up(off + g.n_ek * sizeof(double));
         g.off_de = off; off = align_up(off + g.n_de * sizeof(double));
+        g.off_sl = off; off = align_up(off + 2 * g.n_de * sizeof(double));
     }
     // LDS of one tile of each pass for grid g
     auto lds_of = [&](int k, const Grid &g) -> size_t {
@@ -743,8 +747,9 @@ static int prepare_device(vdwnl_ctx *c) {
     if (!zcols.empty() &&
         (e = hipMemcpy(c->d_cols, zcols.data(), zcols.size() * sizeof(int2), hipMemcpyHostToDevice)) != hipSuccess)
         return hipfail(c, e, "upload columns");
-    if ((e = hipMalloc(&c->d_E, ng * 2 * sizeof(double))) != hipSuccess) return hipfail(c, e, "hipMalloc E");
-    if ((e = hipHostMalloc((void **)&c->h_E, ng * 2 * sizeof(double), hipHostMallocDefault)) != hipSuccess) return hipfail(c, e, "hipHostMalloc E");
+    // four energies per grid: E_k, Delta E, E_x, E_c^LDA
+    if ((e = hipMalloc(&c->d_E, ng * 4 * sizeof(double))) != hipSuccess) return hipfail(c, e, "hipMalloc E");
+    if ((e = hipHostMalloc((void **)&c->h_E, ng * 4 * sizeof(double), hipHostMallocDefault)) != hipSuccess) return hipfail(c, e, "hipHostMalloc E");
     // uploads
     char *w = (char *)c->work;
     for (size_t i = 0; i < c->shells.size(); ++i) {
@@ -807,6 +812,7 @@ static int prepare_device(vdwnl_ctx *c) {
         I.shellmap = (const int *)(w + c->map_off[g.shell_key]);
         I.shelltab = w + c->tab_off[g.shell_key];
         I.part_ek = (double *)(w + g.off_ek); I.part_de = (double *)(w + g.off_de);
+        I.part_sl = (double *)(w + g.off_sl);
         I.n_ek = g.n_ek; I.n_de = g.n_de;
     }
     c->device_ready = true;
@@ -857,7 +863,7 @@ static int enqueue(vdwnl_ctx *c, int nb, hipStream_t st, bool chains = false) {
     }
     if ((e = launch_reduce(c->d_inst, nb, c->d_E, st)) != hipSuccess) return hipfail(c, e, "reduce launch");
     if (c->timing) (void)hipEventRecord(c->ev[npass + 1], st);
-    if ((e = hipMemcpyAsync(c->h_E, c->d_E, nb * 2 * sizeof(double), hipMemcpyDeviceToHost, st)) != hipSuccess)
+    if ((e = hipMemcpyAsync(c->h_E, c->d_E, nb * 4 * sizeof(double), hipMemcpyDeviceToHost, st)) != hipSuccess)
         return hipfail(c, e, "copy energies");
     return VDWNL_OK;
 }
@@ -919,7 +925,9 @@ static int run(vdwnl_ctx *c, int nb, const void *const *n_ptrs, void *const *v_p
     for (int i = 0; i < nb; ++i) {
         c->h_inst[i].n = n_ptrs[i];
         c->h_inst[i].v = v_ptrs[i];
+        c->h_inst[i].semilocal = c->functional == VDWNL_FUNCTIONAL_VDW_DF;
     }
+    c->last_functional = -1;
     if (c->timing && !c->ev_made) {
         for (auto &ev : c->ev)
             if ((e = hipEventCreate(&ev)) != hipSuccess) return hipfail(c, e, "hipEventCreate");
@@ -933,7 +941,11 @@ static int run(vdwnl_ctx *c, int nb, const void *const *n_ptrs, void *const *v_p
         if ((rc = enqueue(c, nb, st)) != VDWNL_OK) return rc;
     }
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return hipfail(c, e, "stream synchronize");
-    std::memcpy(E_out, c->h_E, nb * 2 * sizeof(double));
+    for (int i = 0; i < nb; ++i) {
+        E_out[2 * i] = c->h_E[4 * i];
+        E_out[2 * i + 1] = c->h_E[4 * i + 1];
+    }
+    c->last_functional = c->functional;
     if (c->timing) {
         const int *order;
         const int npass = pass_order(c->grad_mode, &order);
@@ -1121,6 +1133,26 @@ int vdwnl_debug_field(vdwnl_ctx *ctx, int32_t inst, int32_t which, void *dst, vo
 int vdwnl_set_graph(vdwnl_ctx *ctx, int32_t on) {
     if (!ctx) return VDWNL_E_ARG;
     ctx->use_graph = on != 0;
+    return VDWNL_OK;
+}
+
+int vdwnl_set_functional(vdwnl_ctx *ctx, int32_t functional) {
+    if (!ctx) return VDWNL_E_ARG;
+    if (functional != VDWNL_FUNCTIONAL_NONLOCAL && functional != VDWNL_FUNCTIONAL_VDW_DF)
+        return fail(ctx, VDWNL_E_ARG, "functional must be VDWNL_FUNCTIONAL_NONLOCAL or VDWNL_FUNCTIONAL_VDW_DF");
+    ctx->functional = functional;
+    return VDWNL_OK;
+}
+
+int vdwnl_semilocal_energies(const vdwnl_ctx *ctx, int32_t nb, double *E_out) {
+    if (!ctx || !E_out) return VDWNL_E_ARG;
+    if (ctx->last_functional != VDWNL_FUNCTIONAL_VDW_DF || !ctx->h_E)
+        return VDWNL_E_STATE;
+    if (nb != (int32_t)ctx->grids.size()) return VDWNL_E_ARG;
+    for (int i = 0; i < nb; ++i) {
+        E_out[2 * i] = ctx->h_E[4 * i + 2];
+        E_out[2 * i + 1] = ctx->h_E[4 * i + 3];
+    }
     return VDWNL_OK;
 }
 

@@ -89,6 +89,7 @@ __device__ double block_sum(double v) {
 template <typename T, bool DERIV>
 struct LocalQ {
     T q0, Q, dqdn, dqds;
+    T kf, eps, deps_dn;      // k_F, the LDA eps_c and (DERIV) d eps_c/dn
 
     __device__ __forceinline__ void eval(T n, T sigma, double qc, double iqc, int mc, const T *invm) {
         const T pi = (T)3.14159265358979323846;
@@ -97,20 +98,20 @@ struct LocalQ {
         const T zg = (T)(0.8491 / 36.0);   // -Z_ab / 36
         // k_F = (3 pi^2 n)^(1/3), r_s = (3 / (4 pi n))^(1/3): one cube root
         const T cn = dev_cbrt<T>(n), icn = rcp<T>(cn), in = rcp<T>(n);
-        const T kf = (T)3.0936677262801355 * cn;          // (3 pi^2)^(1/3)
+        kf = (T)3.0936677262801355 * cn;                  // (3 pi^2)^(1/3)
         const T rs = (T)0.6203504908994001 * icn;         // (3 / (4 pi))^(1/3)
         const T srs = dev_sqrt<T>(rs);
         const T P = b1 * srs + b2 * rs + b3 * rs * srs + b4 * rs * rs;
         const T iP2A = rcp<T>((T)2 * A * P);
         const T L = dev_log1p<T>(iP2A);
-        const T eps = (T)-2 * A * ((T)1 + a1 * rs) * L;
+        eps = (T)-2 * A * ((T)1 + a1 * rs) * L;
         const T ikfn2 = rcp<T>(kf) * in * in;             // 1 / (k_F n^2)
         const T grad_term = zg * sigma * ikfn2;
         const T qraw = kf - ((T)4 * pi / (T)3) * eps + grad_term;
         if (DERIV) {
             const T dP = (T)0.5 * b1 * rcp<T>(srs) + b2 + (T)1.5 * b3 * srs + (T)2 * b4 * rs;
             const T deps_drs = (T)-2 * A * a1 * L + (T)2 * A * ((T)1 + a1 * rs) * dP * rcp<T>(P * ((T)2 * A * P + (T)1));
-            const T deps_dn = deps_drs * (-rs * in * ((T)1 / (T)3));
+            deps_dn = deps_drs * (-rs * in * ((T)1 / (T)3));
             dqdn = kf * in * ((T)1 / (T)3) - ((T)4 * pi / (T)3) * deps_dn - ((T)7 / (T)3) * grad_term * in;
             dqds = zg * ikfn2;
         }
@@ -135,6 +136,35 @@ struct LocalQ {
             } else {
                 Q = (T)0;
             }
+        }
+    }
+};
+
+// The semilocal terms of Eq. (Exc) at one point, from n, sigma = |grad n|^2
+// and the k_F, eps_c (and d eps_c/dn) of LocalQ.  Exchange: the revPBE GGA,
+// e_x = e_u F_x(s) with e_u = -3 k_F n / (4 pi), s^2 = sigma / (4 k_F^2 n^2),
+// F_x = 1 + kappa - kappa / (1 + mu s^2 / kappa), kappa = 1.245,
+// mu = 0.066725 pi^2 / 3; correlation: the LDA e_c = n eps_c.
+template <typename T>
+struct Semilocal {
+    T ex, ec;                // energies per volume
+    T dn, ds;                // d(e_x + e_c)/dn, d e_x/dsigma (DERIV)
+    template <bool DERIV>
+    __device__ __forceinline__ void eval(T n, T sigma, const LocalQ<T, DERIV> &lq) {
+        const T kappa = (T)1.245, mu = (T)(0.066725 * 3.14159265358979323846 * 3.14159265358979323846 / 3.0);
+        const T in = rcp<T>(n), ikf = rcp<T>(lq.kf);
+        const T eu = (T)(-3.0 / (4.0 * 3.14159265358979323846)) * lq.kf * n;
+        const T ds2 = (T)0.25 * ikf * ikf * in * in;        // d s^2 / d sigma
+        const T s2 = sigma * ds2;
+        const T iden = rcp<T>((T)1 + (mu / kappa) * s2);
+        const T fx = (T)1 + kappa - kappa * iden;
+        ex = eu * fx;
+        ec = n * lq.eps;
+        if (DERIV) {
+            const T dfx = mu * iden * iden;                  // dF_x / ds^2
+            // d e_u/dn = (4/3) e_u / n, d s^2/dn = -(8/3) s^2 / n
+            dn = ((T)(4.0 / 3.0) * fx - (T)(8.0 / 3.0) * dfx * s2) * eu * in + lq.eps + n * lq.deps_dn;
+            ds = eu * dfx * ds2;
         }
     }
 };
@@ -307,7 +337,8 @@ __global__ void __launch_bounds__(kThreads) k_x_theta(const InstDev *insts, cons
 
     const double c_qc = cst->qc, c_iqc = cst->iqc, c_cs = cst->cs, c_nmin = cst->nmin;
     const int c_mc = cst->mc;
-    double de = 0.0;
+    const bool semilocal = I.semilocal != 0;
+    double de = 0.0, dex = 0.0, dec = 0.0;
     for (int idx = threadIdx.x; idx < npt; idx += kThreads) {
         const int rb = idx / N3, k = idx - rb * N3;
         const bool first = idx == (int)threadIdx.x;
@@ -317,7 +348,14 @@ __global__ void __launch_bounds__(kThreads) k_x_theta(const InstDev *insts, cons
         T *th = reinterpret_cast<T *>(r2 + (size_t)(kNQ / 2 * rb) * ls);   // pair line m at th + 2 m ls
         if (nv >= (T)c_nmin) {
             LocalQ<T, false> lq;
-            lq.eval(nv, g01.x * g01.x + g01.y * g01.y + g2.x * g2.x, c_qc, c_iqc, c_mc, invm);
+            const T sigma = g01.x * g01.x + g01.y * g01.y + g2.x * g2.x;
+            lq.eval(nv, sigma, c_qc, c_iqc, c_mc, invm);
+            if (semilocal) {
+                Semilocal<T> sl;
+                sl.eval(nv, sigma, lq);
+                dex += (double)sl.ex;
+                dec += (double)sl.ec;
+            }
             SplineW<T> sw;
             sw.locate(lq.q0, qm, kNQ);
             const T *Mj = Mm + sw.j * kNQ;
@@ -355,7 +393,16 @@ __global__ void __launch_bounds__(kThreads) k_x_theta(const InstDev *insts, cons
         else { gst(o)[0] = mk<T>(ex, ey); gst(o)[1] = mk<T>(ox, oy); }
     }
     const double s = block_sum(de);
-    if (threadIdx.x == 0) I.part_de[t.slot] = s;
+    double sx = 0.0, sc = 0.0;
+    if (semilocal) {                 // (uniform over the workgroup)
+        sx = block_sum(dex);
+        sc = block_sum(dec);
+    }
+    if (threadIdx.x == 0) {
+        I.part_de[t.slot] = s;
+        I.part_sl[2 * t.slot] = sx;
+        I.part_sl[2 * t.slot + 1] = sc;
+    }
 }
 
 // C2R of the 20 u_a rows; v_loc = sum_a u_a dtheta_a/dn + de/dn;
@@ -427,6 +474,7 @@ __global__ void __launch_bounds__(kThreads) k_x_assemble(const InstDev *insts, c
 
     const double c_qc = cst->qc, c_iqc = cst->iqc, c_cs = cst->cs, c_nmin = cst->nmin;
     const int c_mc = cst->mc;
+    const bool semilocal = I.semilocal != 0;
     const gptr<T> vloc = gst(reinterpret_cast<T *>(I.vloc) + p0);
     for (int idx = threadIdx.x; idx < npt; idx += kThreads) {
         const int rb = idx / N3, k = idx - rb * N3;
@@ -436,7 +484,8 @@ __global__ void __launch_bounds__(kThreads) k_x_assemble(const InstDev *insts, c
         T vl = (T)0, gs = (T)0;
         if (nv >= (T)c_nmin) {
             LocalQ<T, true> lq;
-            lq.eval(nv, gx * gx + gy * gy + gz * gz, c_qc, c_iqc, c_mc, invm);
+            const T sigma = gx * gx + gy * gy + gz * gz;
+            lq.eval(nv, sigma, c_qc, c_iqc, c_mc, invm);
             SplineW<T> sw;
             sw.locate(lq.q0, qm, kNQ);
             const T *u = reinterpret_cast<const T *>(r2 + (size_t)(kNQ / 2 * rb) * ls);
@@ -459,6 +508,13 @@ __global__ void __launch_bounds__(kThreads) k_x_assemble(const InstDev *insts, c
             const T iq = rcp<T>(q0), iq3 = iq * iq * iq, iq4 = iq3 * iq;
             vl = su + cn * sdu + (T)2 * cs * nv * iq3 - (T)3 * cs * nv * nv * iq4 * lq.Q * lq.dqdn;
             gs = (T)2 * nv * lq.Q * lq.dqds * sdu - (T)6 * cs * nv * nv * iq4 * lq.Q * lq.dqds;
+            if (semilocal) {
+                // the semilocal terms: de/dgrad n = 2 de/dsigma grad n
+                Semilocal<T> sl;
+                sl.eval(nv, sigma, lq);
+                vl += sl.dn;
+                gs += (T)2 * sl.ds;
+            }
         }
         vloc[idx] = vl;
         if constexpr (FD) {
@@ -945,17 +1001,27 @@ __global__ void __launch_bounds__(kThreads) k_z_main(const InstDev *insts, const
 }
 
 // E_k = (Omega/2) sum of the axis-1 partials; Delta E = dOmega sum of the
-// theta partials.  One workgroup per grid, fixed summation order.
+// theta partials; E_x, E_c^LDA = dOmega sums of the semilocal partials (zero
+// unless the semilocal terms are on).  One workgroup per grid, fixed
+// summation order; E[4 g + 0..3].
 __global__ void __launch_bounds__(kThreads) k_reduce(const InstDev *insts, double *E) {
     const InstDev &I = insts[blockIdx.x];
-    double a = 0.0, b = 0.0;
+    double a = 0.0, b = 0.0, x = 0.0, c = 0.0;
     for (int i = threadIdx.x; i < I.n_ek; i += kThreads) a += I.part_ek[i];
-    for (int i = threadIdx.x; i < I.n_de; i += kThreads) b += I.part_de[i];
+    for (int i = threadIdx.x; i < I.n_de; i += kThreads) {
+        b += I.part_de[i];
+        x += I.part_sl[2 * i];
+        c += I.part_sl[2 * i + 1];
+    }
     a = block_sum(a);
     b = block_sum(b);
+    x = block_sum(x);
+    c = block_sum(c);
     if (threadIdx.x == 0) {
-        E[2 * blockIdx.x] = 0.5 * I.omega * a;
-        E[2 * blockIdx.x + 1] = I.dvol * b;
+        E[4 * blockIdx.x] = 0.5 * I.omega * a;
+        E[4 * blockIdx.x + 1] = I.dvol * b;
+        E[4 * blockIdx.x + 2] = I.dvol * x;
+        E[4 * blockIdx.x + 3] = I.dvol * c;
     }
 }
 

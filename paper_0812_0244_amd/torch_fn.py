@@ -1,4 +1,5 @@
-"""E_c^nl as a differentiable torch function whose backward is v_nl.
+"""E_c^nl (or the whole E_xc of Eq. (Exc)) as a differentiable torch
+function whose backward is v_nl (v_xc).
 
 Eq. (Vi) defines v_i = (1/dOmega) dE/dn_i, so the gradient of E with
 respect to the grid values n_i is dOmega * v_i.  The forward pass runs the
@@ -10,7 +11,7 @@ from __future__ import annotations
 import numpy as np
 import torch
 
-from .binding import VdwNl
+from .binding import FUNCTIONAL_VDW_DF, VdwNl
 
 
 class NonlocalCorrelation:
@@ -47,19 +48,45 @@ class NonlocalCorrelation:
         ek, de = self.lib.energy_potential(n.data_ptr(), v.data_ptr(), stream)
         return ek, de, v
 
+    def total(self, n: torch.Tensor):
+        """(E, v): the energy this engine's functional defines and its potential."""
+        ek, de, v = self.energy_potential(n)
+        return ek + de, v
+
     def __call__(self, n: torch.Tensor) -> torch.Tensor:
         return VdwNlEnergy.apply(n, self)
 
 
+class VdwDF(NonlocalCorrelation):
+    """The whole functional of Eq. (Exc), E_xc = E_x^GGA + E_c^LDA + E_c^nl
+    (revPBE exchange, Perdew-Wang 1992 LDA correlation), with v_xc; the
+    arguments are those of NonlocalCorrelation."""
+
+    def __init__(self, shape, cell, table, precision: int = 32, device: int = 0, grad_mode: int = 0):
+        super().__init__(shape, cell, table, precision, device, grad_mode)
+        self.lib.set_functional(FUNCTIONAL_VDW_DF)
+
+    def energy_potential(self, n: torch.Tensor, v: torch.Tensor | None = None):
+        """(E_k, Delta E, E_x, E_c^LDA, v_xc) for a device tensor n."""
+        ek, de, v = super().energy_potential(n, v)
+        ex, ec = self.lib.semilocal_energies()[0]
+        return ek, de, float(ex), float(ec), v
+
+    def total(self, n: torch.Tensor):
+        ek, de, ex, ec, v = self.energy_potential(n)
+        return ek + de + ex + ec, v
+
+
 class VdwNlEnergy(torch.autograd.Function):
-    """forward(n) = E_c^nl (FP64 scalar); backward(gE) = gE * dOmega * v_nl."""
+    """forward(n) = E (FP64 scalar: E_c^nl, or E_xc for a VdwDF engine);
+    backward(gE) = gE * dOmega * v."""
 
     @staticmethod
     def forward(ctx, n, engine: NonlocalCorrelation):
-        ek, de, v = engine.energy_potential(n.detach())
+        e, v = engine.total(n.detach())
         ctx.save_for_backward(v)
         ctx.dvol = engine.dvol
-        return torch.tensor(ek + de, dtype=torch.float64, device=n.device)
+        return torch.tensor(e, dtype=torch.float64, device=n.device)
 
     @staticmethod
     def backward(ctx, gE):

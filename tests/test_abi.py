@@ -158,3 +158,21 @@ def test_lattice_planning_checks():
     assert plan(nan) == E["ARG"]
     assert lib.vdwnl_set_grids_lattice(h, 1, s.ctypes.data_as(ip), None, 0, 32) == E["ARG"]
     lib.vdwnl_destroy(h)
+
+
+def test_functional_mode_checks():
+    """vdwnl_set_functional takes the two documented values only; the
+    semilocal energies exist only after an evaluation of the whole functional
+    (a host-only context never evaluates)."""
+    lib, h = _host_ctx()
+    assert lib.vdwnl_set_functional(h, B.FUNCTIONAL_VDW_DF) == 0
+    assert lib.vdwnl_set_functional(h, B.FUNCTIONAL_NONLOCAL) == 0
+    assert lib.vdwnl_set_functional(h, 2) == E["ARG"]
+    assert lib.vdwnl_set_functional(h, -1) == E["ARG"]
+    assert lib.vdwnl_set_functional(None, 1) == E["ARG"]
+    assert _set_grid(lib, h, (24, 24, 24)) == 0
+    out = np.zeros(2)
+    dp = ctypes.POINTER(ctypes.c_double)
+    assert lib.vdwnl_semilocal_energies(h, 1, out.ctypes.data_as(dp)) == E["STATE"]
+    assert lib.vdwnl_semilocal_energies(h, 1, None) == E["ARG"]
+    lib.vdwnl_destroy(h)

@@ -1,0 +1,172 @@
+"""Parity of the whole functional of Eq. (Exc) on the GPU (the nonlocal term
+plus revPBE exchange and LDA correlation, their gradient parts through the
+same adjoint) with the FP64 oracle, through the C ABI: FP64 to rounding with
+the spectral and the finite-difference gradient, orthorhombic and triclinic
+cells; FP32 at the method's accuracy; switching the functional on a planned
+context (graph replays included); a batch equals its single-grid
+evaluations; the autograd backward is dOmega v_xc."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import functional as F
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+FP64_REL = 1e-10
+FP32_EREL = 1e-6
+FP32_DV = 1e-5
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_xc(n, cell, table, precision, m=0, debug=False):
+    from paper_0812_0244_amd import VdwDF
+    say("  gpu vdW-DF shape=%s precision=%d grad_mode=%d" % (n.shape, precision, m))
+    eng = VdwDF(n.shape, cell, table, precision=precision, device=0, grad_mode=m)
+    dt = torch.float64 if precision == 64 else torch.float32
+    ek, de, ex, ec, v = eng.energy_potential(torch.from_numpy(n).to(device="cuda", dtype=dt))
+    out = dict(E_k=ek, dE=de, E_x=ex, E_c=ec, v=v.double().cpu().numpy())
+    if debug:
+        vl = torch.empty(n.shape, dtype=dt, device="cuda")
+        eng.lib.debug_field(0, 1, vl.data_ptr())
+        out["v_loc"] = vl.double().cpu().numpy()
+    return out
+
+
+def check(g, o, precision):
+    vmax = np.abs(o["v"]).max()
+    dv = np.abs(g["v"] - o["v"]).max()
+    say("  E_k %.15e / %.15e  dE %.15e / %.15e" % (g["E_k"], o["E_k"], g["dE"], o["dE"]))
+    say("  E_x %.15e / %.15e  E_c %.15e / %.15e  max|dv| %.2e (max|v| %.2e)"
+        % (g["E_x"], o["E_x"], g["E_c"], o["E_c"], dv, vmax))
+    keys = ("E_k", "dE", "E_x", "E_c")
+    if precision == 64:
+        for k in keys:
+            assert abs(g[k] - o[k]) <= FP64_REL * abs(o[k]), k
+        assert dv <= FP64_REL * vmax
+    else:
+        e_g = g["E_k"] + g["dE"]
+        e_o = o["E_k"] + o["dE"]
+        assert abs(e_g - e_o) <= FP32_EREL * abs(e_o)
+        for k in ("E_x", "E_c"):
+            assert abs(g[k] - o[k]) <= FP32_EREL * abs(o[k]), k
+        assert dv <= FP32_DV
+
+
+def test_c1_fp64_spectral_with_intermediates(table):
+    wl = W.config(1)
+    n = wl.density()
+    o = F.xc_energy_potential(n, wl.cell, table, return_parts=True)
+    g = gpu_xc(n, wl.cell, table, 64, debug=True)
+    np.testing.assert_allclose(g["v_loc"], o["v_loc"], rtol=0, atol=1e-10 * np.abs(o["v_loc"]).max())
+    check(g, o, 64)
+
+
+@pytest.mark.parametrize("m", [1, 3])
+def test_c1_fp64_finite_differences(table, m):
+    wl = W.config(1)
+    n = wl.density()
+    o = F.xc_energy_potential(n, wl.cell, table, return_parts=True, grad_mode=m)
+    check(gpu_xc(n, wl.cell, table, 64, m), o, 64)
+
+
+@pytest.mark.parametrize("shape,m", [((20, 18, 24), 0), ((16, 20, 15), 2)])
+def test_triclinic_fp64(table, shape, m):
+    L = W.triclinic_lattice((8.0, 7.5, 8.5), (78.0, 104.0, 66.0))
+    rng = np.random.default_rng(sum(shape))
+    n = W.density_on_lattice(shape, L, W.random_atoms_lattice(rng, 3, L))
+    o = F.xc_energy_potential(n, L, table, return_parts=True, grad_mode=m)
+    check(gpu_xc(n, L, table, 64, m), o, 64)
+
+
+@pytest.mark.parametrize("m", [0, 3])
+def test_c2_fp32(table, m):
+    wl = W.config(2)
+    n32 = wl.density().astype(np.float32).astype(np.float64)
+    o = F.xc_energy_potential(n32, wl.cell, table, return_parts=True, grad_mode=m)
+    check(gpu_xc(n32, wl.cell, table, 32, m), o, 32)
+
+
+@pytest.mark.parametrize("graph", [True, False])
+def test_switching_the_functional(table, graph):
+    """One planned context: the nonlocal evaluation, the whole functional,
+    the nonlocal one again.  E_k and Delta E never change; the nonlocal
+    results repeat bitwise; the semilocal energies exist only after an
+    evaluation of the whole functional."""
+    from paper_0812_0244_amd import VdwNl, VdwNlError
+    from paper_0812_0244_amd.binding import FUNCTIONAL_NONLOCAL, FUNCTIONAL_VDW_DF
+    wl = W.config(1)
+    lib = VdwNl(0)
+    lib.set_grid(wl.shape, wl.cell, 0, 64)
+    lib.set_kernel_table(table["qmesh"], table["qc"], 12, table["dk"], table["phi"], table["c_soft"])
+    lib.set_graph(graph)
+    n = torch.from_numpy(wl.density()).to("cuda")
+    v0, v1, v2 = (torch.full_like(n, float("nan")) for _ in range(3))
+    e0 = lib.energy_potential(n.data_ptr(), v0.data_ptr())
+    with pytest.raises(VdwNlError):
+        lib.semilocal_energies()
+    lib.set_functional(FUNCTIONAL_VDW_DF)
+    e1 = lib.energy_potential(n.data_ptr(), v1.data_ptr())
+    sl = lib.semilocal_energies()
+    lib.set_functional(FUNCTIONAL_NONLOCAL)
+    e2 = lib.energy_potential(n.data_ptr(), v2.data_ptr())
+    assert e0 == e1 == e2
+    assert torch.equal(v0, v2)
+    o = F.xc_energy_potential(wl.density(), wl.cell, table, return_parts=True)
+    assert abs(sl[0, 0] - o["E_x"]) <= FP64_REL * abs(o["E_x"])
+    assert abs(sl[0, 1] - o["E_c"]) <= FP64_REL * abs(o["E_c"])
+    np.testing.assert_allclose(v1.cpu().numpy(), o["v"], rtol=0, atol=FP64_REL * np.abs(o["v"]).max())
+    with pytest.raises(VdwNlError):
+        lib.semilocal_energies()
+
+
+def test_batch_equals_single(table):
+    from paper_0812_0244_amd import VdwNl
+    from paper_0812_0244_amd.binding import FUNCTIONAL_VDW_DF
+    L = W.triclinic_lattice((8.0, 7.5, 8.5), (78.0, 104.0, 66.0))
+    rng = np.random.default_rng(31)
+    n_tri = W.density_on_lattice((20, 18, 24), L, W.random_atoms_lattice(rng, 3, L))
+    wl1, wl4 = W.config(1), W.batch_instances(3)[2]
+    dens = [wl1.density(), n_tri, wl4.density()]
+    cells = [np.diag(wl1.cell), L, np.diag(wl4.cell)]
+    for prec in (64, 32):
+        dt = torch.float64 if prec == 64 else torch.float32
+        lib = VdwNl(0)
+        lib.set_grids([d.shape for d in dens], cells, 0, prec)
+        lib.set_kernel_table(table["qmesh"], table["qc"], 12, table["dk"], table["phi"], table["c_soft"])
+        lib.set_functional(FUNCTIONAL_VDW_DF)
+        n = [torch.from_numpy(d).to("cuda", dt) for d in dens]
+        v = [torch.empty_like(x) for x in n]
+        E = lib.energy_potential_batched([x.data_ptr() for x in n], [x.data_ptr() for x in v])
+        S = lib.semilocal_energies()
+        for i in range(3):
+            s = gpu_xc(dens[i].astype(np.float32).astype(np.float64) if prec == 32 else dens[i], cells[i],
+                       table, prec)
+            assert (s["E_k"], s["dE"]) == (E[i, 0], E[i, 1])
+            assert (s["E_x"], s["E_c"]) == (S[i, 0], S[i, 1])
+            assert np.array_equal(s["v"], v[i].double().cpu().numpy())
+
+
+def test_autograd_backward_is_dvol_v(table):
+    from paper_0812_0244_amd import VdwDF
+    wl = W.config(1)
+    eng = VdwDF(wl.shape, wl.cell, table, precision=64, device=0)
+    n = torch.from_numpy(wl.density()).to("cuda").requires_grad_(True)
+    E = eng(n)
+    E.backward()
+    ek, de, ex, ec, v = eng.energy_potential(n.detach())
+    assert float(E.detach()) == ek + de + ex + ec
+    assert torch.equal(n.grad, eng.dvol * v)
