@@ -216,19 +216,22 @@ def main():
     if args.xc_leg:
         from paper_0812_0244_amd.binding import FUNCTIONAL_NONLOCAL, FUNCTIONAL_VDW_DF
         lib.set_functional(FUNCTIONAL_VDW_DF)
+        vxc = [torch.empty_like(x) for x in n32]             # (v32 keeps v_nl for the comparison below)
+        vxptr = [x.data_ptr() for x in vxc]
         for _ in range(args.warmup):
-            lib.energy_potential_batched(nptr, vptr, stream)
+            lib.energy_potential_batched(nptr, vxptr, stream)
         torch.cuda.synchronize()
         xc_ms = []
         t0 = time.perf_counter()
         for _ in range(args.steps):
             ts = time.perf_counter()
-            Exc = lib.energy_potential_batched(nptr, vptr, stream)
+            Exc = lib.energy_potential_batched(nptr, vxptr, stream)
             xc_ms.append((time.perf_counter() - ts) * 1e3)
         torch.cuda.synchronize()
         xc_step = (time.perf_counter() - t0) * 1e3 / args.steps
         sl = lib.semilocal_energies()
         lib.set_functional(FUNCTIONAL_NONLOCAL)
+        del vxc
         log("fp32 batched, whole functional (graph replay): %.3f ms/step, median %.3f"
             % (xc_step, float(np.median(xc_ms))))
         xc = {"functional": "E_x^GGA (revPBE) + E_c^LDA (PW92) + E_c^nl, v_xc",
