@@ -23,11 +23,23 @@ namespace vdwnl {
 
 // ---------------------------------------------------------------- helpers
 
+// Elementary functions of the local chain.  FP64: the device library.  FP32
+// (arguments positive and normal there): built on the hardware base-2
+// logarithm and exponential (v_log_f32, v_exp_f32), square root and
+// reciprocal, each within about an ulp, in a few instructions where the
+// library's general versions (special values, denormals, extra-precise
+// arithmetic) take tens to a hundred.
+__device__ __forceinline__ float hw_log(float x) { return __builtin_amdgcn_logf(x) * 0.693147180559945309f; }
+__device__ __forceinline__ float hw_exp(float x) { return __builtin_amdgcn_exp2f(x * 1.44269504088896341f); }
 template <typename T> __device__ __forceinline__ T dev_cbrt(T x);
-template <> __device__ __forceinline__ float dev_cbrt(float x) { return cbrtf(x); }
+template <> __device__ __forceinline__ float dev_cbrt(float x) {
+    // 2^(log2(x)/3), then one Newton step for r^3 = x
+    const float r = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(x) * (1.0f / 3.0f));
+    return r + (x * __builtin_amdgcn_rcpf(r * r) - r) * (1.0f / 3.0f);
+}
 template <> __device__ __forceinline__ double dev_cbrt(double x) { return cbrt(x); }
 template <typename T> __device__ __forceinline__ T dev_sqrt(T x);
-template <> __device__ __forceinline__ float dev_sqrt(float x) { return sqrtf(x); }
+template <> __device__ __forceinline__ float dev_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 template <> __device__ __forceinline__ double dev_sqrt(double x) { return sqrt(x); }
 // 1/x: the hardware reciprocal in FP32 (within 1 ulp), a division in FP64
 template <typename T> __device__ __forceinline__ T rcp(T x);
@@ -41,13 +53,31 @@ template <> __device__ __forceinline__ double rcp(double x) {
     return fma(r, fma(-x, r, 1.0), r);
 }
 template <typename T> __device__ __forceinline__ T dev_log1p(T x);
-template <> __device__ __forceinline__ float dev_log1p(float x) { return log1pf(x); }
+template <> __device__ __forceinline__ float dev_log1p(float x) {
+    // log(u) x / (u - 1) with u = 1 + x as rounded: the quotient restores what
+    // the rounding of 1 + x lost (Goldberg 1991, Theorem 4); x itself when u = 1
+    const float u = 1.0f + x, d = u - 1.0f;
+    return d == 0.0f ? x : hw_log(u) * (x * __builtin_amdgcn_rcpf(d));
+}
 template <> __device__ __forceinline__ double dev_log1p(double x) { return log1p(x); }
 template <typename T> __device__ __forceinline__ T dev_exp(T x);
-template <> __device__ __forceinline__ float dev_exp(float x) { return expf(x); }
+template <> __device__ __forceinline__ float dev_exp(float x) { return hw_exp(x); }
 template <> __device__ __forceinline__ double dev_exp(double x) { return exp(x); }
 template <typename T> __device__ __forceinline__ T dev_expm1(T x);
-template <> __device__ __forceinline__ float dev_expm1(float x) { return expm1f(x); }
+template <> __device__ __forceinline__ float dev_expm1(float x) {
+    // |x| < 1/2: x (1 + x/2! + ... + x^8/9!) (Taylor; the rest is below 1e-9
+    // relative); elsewhere exp(x) - 1, where no cancellation can hurt
+    float p = 1.0f / 362880.0f;
+    p = p * x + 1.0f / 40320.0f;
+    p = p * x + 1.0f / 5040.0f;
+    p = p * x + 1.0f / 720.0f;
+    p = p * x + 1.0f / 120.0f;
+    p = p * x + 1.0f / 24.0f;
+    p = p * x + 1.0f / 6.0f;
+    p = p * x + 0.5f;
+    p = p * x + 1.0f;
+    return fabsf(x) < 0.5f ? x * p : hw_exp(x) - 1.0f;
+}
 template <> __device__ __forceinline__ double dev_expm1(double x) { return expm1(x); }
 
 // signed frequency index of position k on an axis of N points, 0 at Nyquist
