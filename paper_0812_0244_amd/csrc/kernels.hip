@@ -842,16 +842,12 @@ __global__ void __launch_bounds__(kThreads) k_z_main(const InstDev *insts, const
     const int W = K * kNQ, lp = N1 | 1;                      // W lines, contiguous, odd pitch
     const int cstride = kNQ * lp;                             // LDS elements per column
     __shared__ int colbase[kMaxCols];                         // offset of each column in a k1 plane
-    __shared__ int colk3[kMaxCols];
     C2<T> *twall = reinterpret_cast<C2<T> *>(smem);
     C2<T> *buf = twall + N1;
     int *sidx = reinterpret_cast<int *>(buf + W * lp);        // shell of every item
     {
         const int2 cw = cols[t.a + min((int)threadIdx.x, K - 1)];   // unconditional (clamped) load
-        if (threadIdx.x < K) {
-            colbase[threadIdx.x] = (cw.x * N3h + cw.y) * kNQ;
-            colk3[threadIdx.x] = cw.y;
-        }
+        if (threadIdx.x < K) colbase[threadIdx.x] = (cw.x * N3h + cw.y) * kNQ;
     }
     const int2 c0 = cols[t.a];
     __syncthreads();
@@ -978,18 +974,26 @@ __global__ void __launch_bounds__(kThreads) k_z_main(const InstDev *insts, const
     // lanes share one wave, so reads of theta and writes of u need wave-level
     // ordering only
     auto process = [&](const T *f) {
+        // the points +-m1 of each column of the item (lq = l for k1 = 0, the
+        // Nyquist plane and general cells: the second point is the first
+        // again, its energy masked and its u the same value written twice)
         const int l = m1;
         int lq = N1 - m1;
-        if (general || m1 == 0 || lq == m1) lq = -1;   // k1 = 0 and the Nyquist plane stand alone
+        const bool two = !(general || m1 == 0 || lq == m1);
+        if (!two) lq = l;
+        const T mask2 = two ? (T)1 : (T)0;
         const int w0 = __mul24(pr, CP);
+        const int k3 = k30 + pr;                               // the item's columns share k3
+        const bool edge = (k3 == 0) || ((N3 & 1) == 0 && 2 * k3 == N3);
+        const double wgt = edge ? wn : 2.0 * wn;
         m1 += dm;
         pr += dr;
         if (pr >= P) { pr -= P; ++m1; }
-        for (int w = w0; w < w0 + CP; ++w) {
+        auto column = [&](int w) {
             C2<T> u1 = mk<T>((T)0, (T)0), u2 = u1;
             C2<T> *xc = buf + __mul24(w, cstride);
             C2<T> *x1 = xc + l;                                   // component b at x1[b lp]
-            C2<T> *x2 = xc + (lq >= 0 ? lq : l);
+            C2<T> *x2 = xc + lq;
 #pragma unroll
             for (int b = 0; b < kNQ; ++b) {
                 const C2<T> t1 = x1[b * lp], t2 = x2[b * lp];
@@ -999,19 +1003,17 @@ __global__ void __launch_bounds__(kThreads) k_z_main(const InstDev *insts, const
                 u2.y += f[b] * t2.y;
             }
             const C2<T> own1 = x1[al * lp], own2 = x2[al * lp];
-            const int k3 = colk3[w];
-            const bool edge = (k3 == 0) || ((N3 & 1) == 0 && k3 == N3 / 2);
-            const double wgt = edge ? wn : 2.0 * wn;
-            e += wgt * (double)(own1.x * u1.x + own1.y * u1.y);
-            if (lq >= 0) e += wgt * (double)(own2.x * u2.x + own2.y * u2.y);
+            e += wgt * (double)(own1.x * u1.x + own1.y * u1.y + mask2 * (own2.x * u2.x + own2.y * u2.y));
             // every lane of the group has read theta at these points before
             // any lane overwrites its component with u; the next column or
             // item reads other points (each k point belongs to one item), so
             // no ordering is needed after the writes
             wave_sync();
             x1[al * lp] = cscale(u1, inv_n);
-            if (lq >= 0) x2[al * lp] = cscale(u2, inv_n);
-        }
+            x2[al * lp] = cscale(u2, inv_n);
+        };
+        column(w0);
+        if (CP == 2) column(w0 + 1);
     };
     for (int it = gid; lane_on && it < nitems;) {
         fetch(it + kGroups, fb);               // the next item's row (clamped past the end)
@@ -1027,7 +1029,6 @@ __global__ void __launch_bounds__(kThreads) k_z_main(const InstDev *insts, const
     io(false);
     const double sum = block_sum(e);
     if (threadIdx.x == 0) I.part_ek[t.slot] = sum;
-#undef VDWNL_FETCH_ROW
 }
 
 // E_k = (Omega/2) sum of the axis-1 partials; Delta E = dOmega sum of the
