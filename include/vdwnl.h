@@ -36,7 +36,8 @@ extern "C" {
 enum {
     VDWNL_OK = 0,
     VDWNL_E_ARG = -1,               /* null pointer, bad enum, non-positive size */
-    VDWNL_E_UNSUPPORTED_SIZE = -2,  /* grid edge with a prime factor > 5, or outside the limits */
+    VDWNL_E_UNSUPPORTED_SIZE = -2,  /* grid edge with a prime factor > 5, or outside the limits
+                                       (edges >= 4; at most 715827882 points) */
     VDWNL_E_NOMEM = -3,             /* device or host allocation failed */
     VDWNL_E_TABLE = -4,             /* kernel table invalid (mesh, symmetry, size) */
     VDWNL_E_KRANGE = -5,            /* radial table does not reach max |G| of a grid */

@@ -312,6 +312,8 @@ static int check_grid(vdwnl_ctx *c, const int32_t *shape, const double *lattice,
     const size_t N1 = g.s[0], N2 = g.s[1], N3 = g.s[2];
     if ((N1 * N2) % 2 != 0)
         return fail(c, VDWNL_E_UNSUPPORTED_SIZE, "N1 * N2 must be even (rows are transformed in pairs)");
+    if (3 * N1 * N2 * N3 >= ((size_t)1 << 31))   // (element offsets of three fields in 32 bits)
+        return fail(c, VDWNL_E_UNSUPPORTED_SIZE, "more than 715827882 grid points");
     // LDS of each pass as a function of its tile size (twiddles staged in LDS too)
     auto zmain = [&](size_t k3) { return (N1 + kNQ * k3 * (N1 | 1)) * cs + 16 + (N1 / 2 + 1) * k3 * sizeof(int); };
     auto zaux = [&](size_t k3) { return (N1 + 4 * k3 * (N1 | 1)) * 16; };

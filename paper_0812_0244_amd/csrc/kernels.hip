@@ -580,60 +580,60 @@ __global__ void __launch_bounds__(kThreads) k_x_assemble(const InstDev *insts, c
 
 // ---------------------------------------------------------------- finite-difference passes
 
-// Central differences on the periodic grid, FP64 arithmetic on values read in
-// T: d_c f_i = sum_s c_s (f_{i + s e_c} - f_{i - s e_c}), s = 1..M, along the
-// grid (lattice) axis c; grad n = sum_c W[c] d_c n with W[c][x] = N_c b_c,x / (2 pi).
+// Central differences on the periodic grid in the working precision:
+// d_c f_i = sum_s c_s (f_{i + s e_c} - f_{i - s e_c}), s = 1..M, along the grid
+// (lattice) axis c; grad n = sum_c W[c] d_c n with W[c][x] = N_c b_c,x / (2 pi).
 // Neighbour indices wrap once (M <= 4 <= every edge).  Tiles are runs of
-// whole axis-3 lines: a = first row (i1 N2 + i2), b = rows.
-struct FdIndex {
-    size_t p, b1, b2, b3;    // the point; the point with i1, i2, i3 set to 0
-    int i1, i2, i3;
-    __device__ __forceinline__ FdIndex(int row, int k, int N2, int N3) {
-        i1 = row / N2;
-        i2 = row - i1 * N2;
-        i3 = k;
-        p = (size_t)row * N3 + k;
-        b1 = p - (size_t)i1 * N2 * N3;
-        b2 = p - (size_t)i2 * N3;
-        b3 = p - (size_t)i3;
-    }
-};
+// whole axis-3 lines: a = first row (i1 N2 + i2), b = rows.  Offsets are
+// 32-bit (a grid and its three fields stay below 2^31 elements).
 
-__device__ __forceinline__ int wrap_up(int i, int n) { return i >= n ? i - n : i; }
-__device__ __forceinline__ int wrap_dn(int i, int n) { return i < 0 ? i + n : i; }
+// offset of the neighbour s steps up (down) an axis of n points with element
+// stride st from index i (one wrap at most)
+__device__ __forceinline__ int fd_up(int i, int s, int n, int st) { return i + s < n ? s * st : (s - n) * st; }
+__device__ __forceinline__ int fd_dn(int i, int s, int n, int st) { return i >= s ? -s * st : (n - s) * st; }
 
 template <typename T, int M>
-__device__ __forceinline__ double fd_diff(const gptr<const T> f, size_t base, size_t stride, int i, int n,
-                                          const double *c) {
-    double acc = 0.0;
+__device__ __forceinline__ T fd_diff(gptr<const T> f, int i, int n, int st, const T *c) {
+    T acc = (T)0;
 #pragma unroll
-    for (int s = 1; s <= M; ++s) {
-        const T a = f[base + (size_t)wrap_up(i + s, n) * stride];
-        const T b = f[base + (size_t)wrap_dn(i - s, n) * stride];
-        acc += c[s - 1] * ((double)a - (double)b);
-    }
+    for (int s = 1; s <= M; ++s) acc += c[s - 1] * (f[fd_up(i, s, n, st)] - f[fd_dn(i, s, n, st)]);
     return acc;
 }
 
 template <typename T, int M>
 __device__ __forceinline__ void fd_grad_tile(const InstDev &I, int row0, int B) {
     const int N1 = I.n1, N2 = I.n2, N3 = I.n3;
-    const size_t N = (size_t)N1 * N2 * N3, plane = (size_t)N2 * N3;
+    const int plane = N2 * N3, N = N1 * plane;
     const gptr<const T> n = gld(reinterpret_cast<const T *>(I.n));
     const gptr<T> g = gst(reinterpret_cast<T *>(I.grad));
-    double c[M];
+    T c[M];
 #pragma unroll
-    for (int s = 0; s < M; ++s) c[s] = I.fdc[s];
+    for (int s = 0; s < M; ++s) c[s] = (T)I.fdc[s];
+    T Wm[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int x = 0; x < 3; ++x) Wm[a][x] = (T)I.fdW[a][x];
     const int npt = B * N3;
-#pragma unroll 2
-    for (int idx = threadIdx.x; idx < npt; idx += kThreads) {
-        const int rb = idx / N3;
-        const FdIndex x(row0 + rb, idx - rb * N3, N2, N3);
-        const double d1 = fd_diff<T, M>(n, x.b1, plane, x.i1, N1, c);
-        const double d2 = fd_diff<T, M>(n, x.b2, (size_t)N3, x.i2, N2, c);
-        const double d3 = fd_diff<T, M>(n, x.b3, 1, x.i3, N3, c);
+    const int drow = kThreads / N3, dk = kThreads - drow * N3;
+    int idx = threadIdx.x;
+    if (idx >= npt) return;
+    int rb = idx / N3, i3 = idx - rb * N3, row = row0 + rb;
+    int i1 = row / N2, i2 = row - i1 * N2;
+    for (; idx < npt; idx += kThreads) {
+        const int p = row * N3 + i3;
+        const gptr<const T> f = n + p;
+        const T d1 = fd_diff<T, M>(f, i1, N1, plane, c);
+        const T d2 = fd_diff<T, M>(f, i2, N2, N3, c);
+        const T d3 = fd_diff<T, M>(f, i3, N3, 1, c);
 #pragma unroll
-        for (int a = 0; a < 3; ++a) g[a * N + x.p] = (T)(I.fdW[0][a] * d1 + I.fdW[1][a] * d2 + I.fdW[2][a] * d3);
+        for (int a = 0; a < 3; ++a) g[a * N + p] = Wm[0][a] * d1 + Wm[1][a] * d2 + Wm[2][a] * d3;
+        // next point: kThreads = drow N3 + dk further on
+        i3 += dk;
+        row += drow;
+        i2 += drow;
+        if (i3 >= N3) { i3 -= N3; ++row; ++i2; }
+        while (i2 >= N2) { i2 -= N2; ++i1; }
     }
 }
 
@@ -644,23 +644,30 @@ __device__ __forceinline__ void fd_grad_tile(const InstDev &I, int row0, int B) 
 template <typename T, int M>
 __device__ __forceinline__ void fd_div_tile(const InstDev &I, int row0, int B) {
     const int N1 = I.n1, N2 = I.n2, N3 = I.n3;
-    const size_t N = (size_t)N1 * N2 * N3, plane = (size_t)N2 * N3;
+    const int plane = N2 * N3, N = N1 * plane;
     const gptr<const T> w = gld(reinterpret_cast<const T *>(I.grad));
     const gptr<const T> vloc = gld(reinterpret_cast<const T *>(I.vloc));
     const gptr<T> v = gst(reinterpret_cast<T *>(I.v));
-    double c[M];
+    T c[M];
 #pragma unroll
-    for (int s = 0; s < M; ++s) c[s] = I.fdc[s];
+    for (int s = 0; s < M; ++s) c[s] = (T)I.fdc[s];
     const int npt = B * N3;
-#pragma unroll 2
-    for (int idx = threadIdx.x; idx < npt; idx += kThreads) {
-        const int rb = idx / N3;
-        const FdIndex x(row0 + rb, idx - rb * N3, N2, N3);
-        const double vl = (double)vloc[x.p];
-        const double d1 = fd_diff<T, M>(w, x.b1, plane, x.i1, N1, c);
-        const double d2 = fd_diff<T, M>(w + N, x.b2, (size_t)N3, x.i2, N2, c);
-        const double d3 = fd_diff<T, M>(w + 2 * N, x.b3, 1, x.i3, N3, c);
-        v[x.p] = (T)(vl - (d1 + d2 + d3));
+    const int drow = kThreads / N3, dk = kThreads - drow * N3;
+    int idx = threadIdx.x;
+    if (idx >= npt) return;
+    int rb = idx / N3, i3 = idx - rb * N3, row = row0 + rb;
+    int i1 = row / N2, i2 = row - i1 * N2;
+    for (; idx < npt; idx += kThreads) {
+        const int p = row * N3 + i3;
+        const T d1 = fd_diff<T, M>(w + p, i1, N1, plane, c);
+        const T d2 = fd_diff<T, M>(w + N + p, i2, N2, N3, c);
+        const T d3 = fd_diff<T, M>(w + 2 * N + p, i3, N3, 1, c);
+        v[p] = vloc[p] - (d1 + d2 + d3);
+        i3 += dk;
+        row += drow;
+        i2 += drow;
+        if (i3 >= N3) { i3 -= N3; ++row; ++i2; }
+        while (i2 >= N2) { i2 -= N2; ++i1; }
     }
 }
 
