@@ -586,7 +586,7 @@ static int prepare_device(vdwnl_ctx *c) {
         }
         // Fused axis-1 tiles: the columns k2 and N2 - k2 (the same |m2|, so
         // the same |G| shell at every (|m1|, k3)) over a run of consecutive
-        // k3; one staged kernel row then serves four k points.  Columns
+        // k3; one kernel row (loaded per lane) then serves four k points.  Columns
         // k2 = 0 and N2/2 stand alone.
         {
             const int K = std::min(g.k3main, kMaxCols);
