@@ -54,6 +54,7 @@ struct Shells {
     std::vector<int> map;       // [h1][h2][n3h] (orthorhombic) or [N1][N2][n3h] (general cell)
     std::vector<double> gmod;   // |G| per shell
     double gmax = 0.0;
+    bool general = false;       // table rows packed (upper triangle): one k point per shell
 };
 
 static Shells shells_from_keys(const std::vector<double> &key) {
@@ -177,6 +178,7 @@ struct vdwnl_ctx {
         int kind, lc, off, cnt;
         size_t lds;
         int group;
+        int general;          // grids of the group in non-orthogonal cells
     };
     // per pass: one launch per group of grids (grids whose three axes fall in
     // the same FFT length classes); the groups' chains of passes are
@@ -438,6 +440,7 @@ static int plan_grids(vdwnl_ctx *c, int nb, const int32_t *shapes, const double 
             found = (int)c->shells.size();
             double diag[3] = {g.A[0][0], g.A[1][1], g.A[2][2]};
             c->shells.push_back(g.general ? build_shells_general(g.s, g.B) : build_shells(g.s, diag));
+            c->shells.back().general = g.general;
             c->shell_keys.push_back({key, found});
         }
         g.shell_key = found;
@@ -447,9 +450,13 @@ static int plan_grids(vdwnl_ctx *c, int nb, const int32_t *shapes, const double 
 }
 
 // spline of the radial table at |G| for every pair: phi_ab(|G_s|), FP64,
-// stored as the full symmetric matrix of each shell
+// stored as the full symmetric matrix of each shell (orthorhombic cells: a
+// shell serves up to four k points) or as its packed upper triangle, pair
+// p = (r, q), r <= q, in row order (general cells: a shell per k point, so
+// the rows' bytes dominate the fused pass)
 static void shell_table(const vdwnl_ctx *c, const Shells &sh, std::vector<double> &out) {
-    out.assign(sh.gmod.size() * kTabRow, 0.0);
+    const size_t row = sh.general ? kTabPacked : kTabRow;
+    out.assign(sh.gmod.size() * row, 0.0);
     for (size_t s = 0; s < sh.gmod.size(); ++s) {
         const double k = sh.gmod[s];
         int j = (int)std::floor(k / c->dk);
@@ -463,8 +470,12 @@ static void shell_table(const vdwnl_ctx *c, const Shells &sh, std::vector<double
                 const double *f = c->phi.data() + (size_t)p * c->nk;
                 const double *m = c->d2.data() + (size_t)p * c->nk;
                 const double v = a * f[j] + b * f[j + 1] + ((a * a * a - a) * m[j] + (b * b * b - b) * m[j + 1]) * w;
-                out[s * kTabRow + r * kNQ + q] = v;
-                out[s * kTabRow + q * kNQ + r] = v;
+                if (sh.general) {
+                    out[s * row + p] = v;
+                } else {
+                    out[s * row + r * kNQ + q] = v;
+                    out[s * row + q * kNQ + r] = v;
+                }
             }
     }
 }
@@ -548,7 +559,7 @@ static int prepare_device(vdwnl_ctx *c) {
         c->map_off[i] = off;
         off = align_up(off + c->shells[i].map.size() * sizeof(int));
         c->tab_off[i] = off;
-        off = align_up(off + c->shells[i].gmod.size() * kTabRow * rs);
+        off = align_up(off + c->shells[i].gmod.size() * (c->shells[i].general ? kTabPacked : kTabRow) * rs);
     }
     std::vector<Tile> tiles[KIND_COUNT];
     std::vector<int2> zcols;              // columns of the fused axis-1 tiles
@@ -682,7 +693,9 @@ static int prepare_device(vdwnl_ctx *c) {
         std::vector<int> keys;
         for (size_t gi = 0; gi < c->grids.size(); ++gi) {
             const Grid &g = c->grids[gi];
-            const int key = (len_class(g.s[0]) * kNumLenClasses + len_class(g.s[1])) * kNumLenClasses + len_class(g.s[2]);
+            // (and the cell kind: general cells take the fused pass's packed-row variant)
+            const int key = ((len_class(g.s[0]) * kNumLenClasses + len_class(g.s[1])) * kNumLenClasses +
+                             len_class(g.s[2])) * 2 + (g.general ? 1 : 0);
             auto it = std::find(keys.begin(), keys.end(), key);
             group_of[gi] = (int)(it - keys.begin());
             if (it == keys.end()) keys.push_back(key);
@@ -693,10 +706,11 @@ static int prepare_device(vdwnl_ctx *c) {
     for (int k = 0; k < KIND_COUNT; ++k) {
         c->launches[k].clear();
         for (int grp = 0; grp < c->ngroups; ++grp) {
-            vdwnl_ctx::Launch L{k, 0, (int)all.size(), 0, 0, grp};
+            vdwnl_ctx::Launch L{k, 0, (int)all.size(), 0, 0, grp, 0};
             for (const Tile &tl : tiles[k]) {
                 if (group_of[tl.inst] != grp) continue;
                 const Grid &g = c->grids[tl.inst];
+                L.general = g.general ? 1 : 0;
                 // the stencil passes transform nothing (class 0 for any grid)
                 L.lc = (k == KF_GRAD || k == KF_DIV) ? 0 : len_class(axis_len(k, g));
                 all.push_back(tl);
@@ -710,7 +724,7 @@ static int prepare_device(vdwnl_ctx *c) {
     // at launch time: launches may be captured into a graph)
     for (int k = 0; k < KIND_COUNT; ++k)
         for (const auto &L : c->launches[k]) {
-            LaunchArgs a{nullptr, nullptr, 0, L.lds, nullptr, nullptr, nullptr, nullptr, nullptr};
+            LaunchArgs a{nullptr, nullptr, 0, L.lds, nullptr, nullptr, nullptr, nullptr, nullptr, L.general};
             if ((e = launch_kind(k, L.lc, c->precision, a)) != hipSuccess) return hipfail(c, e, "kernel LDS limit");
         }
     // twiddles
@@ -836,7 +850,8 @@ static int enqueue(vdwnl_ctx *c, int nb, hipStream_t st, bool chains = false) {
     const int *order;
     const int npass = pass_order(c->grad_mode, &order);
     auto launch = [&](const vdwnl_ctx::Launch &L, hipStream_t s) -> int {
-        LaunchArgs a{c->d_inst, c->d_tiles + L.off, L.cnt, L.lds, c->d_consts, c->d_tw, c->d_twd, s, c->d_cols};
+        LaunchArgs a{c->d_inst, c->d_tiles + L.off, L.cnt, L.lds, c->d_consts, c->d_tw, c->d_twd, s, c->d_cols,
+                     L.general};
         const hipError_t le = launch_kind(L.kind, L.lc, c->precision, a);
         return le == hipSuccess ? VDWNL_OK : hipfail(c, le, "kernel launch");
     };

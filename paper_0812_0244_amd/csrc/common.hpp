@@ -10,6 +10,7 @@ namespace vdwnl {
 constexpr int kNQ = 20;                          // interpolation points q_a (compile-time)
 constexpr int kNPair = kNQ * (kNQ + 1) / 2;      // distinct phi_ab (a <= b) per |G| shell
 constexpr int kTabRow = kNQ * kNQ;               // shell table entries per shell (full matrix)
+constexpr int kTabPacked = kNQ * (kNQ + 1) / 2;  // the same, packed upper triangle (general cells)
 constexpr int kThreads = 256;                    // threads per workgroup, every kernel
 constexpr int kTileCap = 4096;                   // complex elements of one LDS FFT tile
 constexpr int kLdsCap = 65536;                   // bytes of LDS one workgroup may take
@@ -120,6 +121,7 @@ struct LaunchArgs {
     const void *twd;         // FP64 twiddles (gradient and divergence chains)
     hipStream_t stream;
     const int2 *cols;        // (k2, k3) columns of the fused axis-1 tiles
+    int general;             // the launch's grids have non-orthogonal cells (packed shell rows)
 };
 
 hipError_t launch_kind(int kind, int len_class, int precision, const LaunchArgs &a);

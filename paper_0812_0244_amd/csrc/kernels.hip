@@ -837,7 +837,10 @@ __global__ void __launch_bounds__(kThreads) k_z_div(const InstDev *insts, const 
 // kernel matrix (kNQ contiguous values, 16-byte loads) into registers and
 // forms u_a at the pair's points (+-m1 of each column).  The rows of the
 // group's next item are loaded meanwhile (two register sets in turn).
-template <typename T, int LC>
+// GEN (grids in non-orthogonal cells): every item is one k point with its
+// own shell, whose table holds the packed upper triangle; lane a gathers its
+// row from it through offsets fixed per lane.
+template <typename T, int LC, bool GEN>
 __global__ void __launch_bounds__(kThreads) k_z_main(const InstDev *insts, const Tile *tiles, const int2 *cols,
                                                      const void *twv) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -928,7 +931,7 @@ __global__ void __launch_bounds__(kThreads) k_z_main(const InstDev *insts, const
     const T *tab = reinterpret_cast<const T *>(I.shelltab);
     // orthorhombic cell: item = |m1| P + pair, the +-m1 points share a shell;
     // general cell: item = k1 P + pair over the whole axis, a shell each
-    const bool general = I.general != 0;
+    constexpr bool general = GEN;
     const int k30 = c0.y;
     const int m2 = general ? c0.x : freq_abs(c0.x, N2);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -945,10 +948,25 @@ __global__ void __launch_bounds__(kThreads) k_z_main(const InstDev *insts, const
             sidx[i] = smap[m1 * smap_m1 + (i - m1 * P)];
         }
     }
+    // (packed rows: entry (r, q), r <= q, at r kNQ - r (r - 1)/2 + q - r)
+    int poff[GEN ? kNQ : 1];
+    if constexpr (GEN) {
+#pragma unroll
+        for (int b = 0; b < kNQ; ++b) {
+            const int r = min(al, b), q = max(al, b);
+            poff[b] = r * kNQ - ((r * (r - 1)) >> 1) + q - r;
+        }
+    }
     // row al of the shell matrix of an item (index clamped to the last item:
     // the loads stay unconditional)
     auto fetch = [&](int item, T *f) {
         const int sh = sidx[min(item, nitems - 1)];
+        if constexpr (GEN) {
+            const gptr<const T> src = gld(tab + (size_t)sh * kTabPacked);
+#pragma unroll
+            for (int b = 0; b < kNQ; ++b) f[b] = src[poff[b]];
+            return;
+        }
         const gptr<const T> src = gld(tab + (size_t)sh * kTabRow + al * kNQ);
         if constexpr (sizeof(T) == 4) {
             const gptr<const float4> s4 = (gptr<const float4>)src;
@@ -1089,7 +1107,10 @@ static hipError_t launch_lc(int kind, const LaunchArgs &a) {
         case KX_GRAD: VDWNL_LAUNCH((k_x_grad<T, LC>), a.twd); break;
         case KX_THETA: VDWNL_LAUNCH((k_x_theta<T, LC>), a.cst, a.tw); break;
         case KY_20F: VDWNL_LAUNCH((k_y<T, -1, LC>), a.tw, 0, kNQ); break;
-        case KZ_MAIN: VDWNL_LAUNCH((k_z_main<T, LC>), a.cols, a.tw); break;
+        case KZ_MAIN:
+            if (a.general) VDWNL_LAUNCH((k_z_main<T, LC, true>), a.cols, a.tw);
+            else VDWNL_LAUNCH((k_z_main<T, LC, false>), a.cols, a.tw);
+            break;
         case KY_20I: VDWNL_LAUNCH((k_y<T, 1, LC>), a.tw, 0, kNQ); break;
         case KX_ASSEMBLE: VDWNL_LAUNCH((k_x_assemble<T, LC, false>), a.cst, a.tw); break;
         case KX_ASSEMBLE_FD: VDWNL_LAUNCH((k_x_assemble<T, LC, true>), a.cst, a.tw); break;
