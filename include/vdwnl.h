@@ -139,6 +139,20 @@ int vdwnl_energy_potential(vdwnl_ctx *ctx, const void *n_dev, void *v_dev, doubl
 int vdwnl_energy_potential_batched(vdwnl_ctx *ctx, int32_t nb, const void *const *n_ptrs,
                                    void *const *v_ptrs, double *E_out, void *stream);
 
+/* As vdwnl_energy_potential_batched, without waiting for the result: the
+ * call returns once the evaluation is enqueued on `stream`, and E_dev, a
+ * device array double[nb][2], receives (E_k, Delta E) of every grid on that
+ * stream (the paper's E as a device value, for callers that keep the
+ * evaluation inside their own stream-ordered work).  The density and
+ * potential buffers must stay valid until the stream has passed the
+ * evaluation.  The next call on the context (any evaluation, re-planning,
+ * vdwnl_semilocal_energies, destroy) first waits on the host until this
+ * evaluation has finished, since it reads the context's pinned instance
+ * table.  VDWNL_E_ARG for a null E_dev; VDWNL_E_STATE while per-pass timing
+ * is on; otherwise the errors of the synchronous call. */
+int vdwnl_energy_potential_batched_async(vdwnl_ctx *ctx, int32_t nb, const void *const *n_ptrs,
+                                         void *const *v_ptrs, double *E_dev, void *stream);
+
 /* Which functional an evaluation computes (Eq. (Exc) of the paper:
  * E_xc = E_x^GGA + E_c^LDA + E_c^nl).
  *   VDWNL_FUNCTIONAL_NONLOCAL (the default): v = v_nl, E_c^nl only.

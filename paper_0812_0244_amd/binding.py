@@ -33,6 +33,8 @@ SIGNATURES = {
     "vdwnl_energy_potential": (ctypes.c_int, [_vp, _vp, _vp, _dp, _vp]),
     "vdwnl_energy_potential_batched": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(_vp),
                                                       ctypes.POINTER(_vp), _dp, _vp]),
+    "vdwnl_energy_potential_batched_async": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(_vp),
+                                                            ctypes.POINTER(_vp), _vp, _vp]),
     "vdwnl_debug_field": (ctypes.c_int, [_vp, _i32, _i32, _vp, _vp]),
     "vdwnl_info": (ctypes.c_int, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(ctypes.c_int64)]),
     "vdwnl_set_timing": (ctypes.c_int, [_vp, _i32]),
@@ -202,6 +204,15 @@ class VdwNl:
         self._check(self.lib.vdwnl_energy_potential_batched(self.h, nb, na, va, _as_ptr(E, ctypes.c_double),
                                                             _vp(stream)), "energy_potential_batched")
         return E
+
+    def energy_potential_batched_async(self, n_ptrs, v_ptrs, e_dev_ptr: int, stream: int = 0):
+        """Enqueue one evaluation; (E_k, Delta E) per grid land in the device
+        array at e_dev_ptr (double [nb, 2]) on the stream."""
+        nb = len(n_ptrs)
+        na = (_vp * nb)(*[_vp(p) for p in n_ptrs])
+        va = (_vp * nb)(*[_vp(p) for p in v_ptrs])
+        self._check(self.lib.vdwnl_energy_potential_batched_async(self.h, nb, na, va, _vp(e_dev_ptr), _vp(stream)),
+                    "energy_potential_batched_async")
 
     def set_graph(self, on: bool = True):
         self._check(self.lib.vdwnl_set_graph(self.h, 1 if on else 0), "set_graph")

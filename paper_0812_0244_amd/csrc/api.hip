@@ -151,6 +151,10 @@ struct vdwnl_ctx {
     int grad_mode = 0;
     int functional = VDWNL_FUNCTIONAL_NONLOCAL;
     int last_functional = -1;             // of the last finished evaluation (-1: none)
+    // an evaluation enqueued by the asynchronous call and not yet waited for
+    hipEvent_t done_ev = nullptr;
+    bool pending = false;
+    int pending_functional = -1;
     std::string err;
     size_t pref[TG_COUNT] = {kLdsCap, kLdsCap, kLdsCap, kLdsCap, kLdsCap};   // LDS budget per pass group
     std::string plan_key;                 // identifies the batch for the tuned-budget cache
@@ -219,6 +223,17 @@ static int hipfail(vdwnl_ctx *c, hipError_t e, const char *what) {
     return fail(c, VDWNL_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+// Wait (on the host) for the evaluation the asynchronous call left in
+// flight: it reads the pinned instance table and writes the pinned energies.
+static int wait_pending(vdwnl_ctx *c) {
+    if (!c->pending) return VDWNL_OK;
+    c->pending = false;
+    const hipError_t e = hipEventSynchronize(c->done_ev);
+    if (e != hipSuccess) return hipfail(c, e, "wait for the previous evaluation");
+    c->last_functional = c->pending_functional;
+    return VDWNL_OK;
+}
+
 static void drop_graph(vdwnl_ctx *c) {
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
@@ -227,9 +242,12 @@ static void drop_graph(vdwnl_ctx *c) {
 }
 
 static void free_device(vdwnl_ctx *c) {
+    if (c->device >= 0) (void)hipSetDevice(c->device);
+    (void)wait_pending(c);
     c->last_functional = -1;
     if (c->device < 0) return;
-    (void)hipSetDevice(c->device);
+    if (c->done_ev) (void)hipEventDestroy(c->done_ev);
+    c->done_ev = nullptr;
     drop_graph(c);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     c->cap_stream = nullptr;
@@ -925,9 +943,15 @@ static int capture(vdwnl_ctx *c, int nb) {
     return VDWNL_OK;
 }
 
-static int run(vdwnl_ctx *c, int nb, const void *const *n_ptrs, void *const *v_ptrs, double *E_out, void *stream) {
+// One evaluation of the planned batch on `stream`.  Synchronous (E_dev null):
+// returns after the stream has finished, energies in E_out (host).
+// Asynchronous (E_dev set): returns once the work is enqueued; (E_k, Delta E)
+// of each grid land in E_dev (device) on the stream.
+static int run(vdwnl_ctx *c, int nb, const void *const *n_ptrs, void *const *v_ptrs, double *E_out, void *stream,
+               double *E_dev = nullptr) {
     if (!c) return VDWNL_E_ARG;
-    if (!n_ptrs || !v_ptrs || !E_out) return fail(c, VDWNL_E_ARG, "null pointer");
+    if (!n_ptrs || !v_ptrs || (!E_out && !E_dev)) return fail(c, VDWNL_E_ARG, "null pointer");
+    if (E_dev && c->timing) return fail(c, VDWNL_E_STATE, "per-pass timing needs the synchronous calls");
     if (!c->have_grid || !c->have_table) return fail(c, VDWNL_E_STATE, "grid and kernel table must both be set");
     if (nb != (int)c->grids.size()) return fail(c, VDWNL_E_ARG, "batch size differs from the planned grids");
     for (int i = 0; i < nb; ++i)
@@ -938,7 +962,8 @@ static int run(vdwnl_ctx *c, int nb, const void *const *n_ptrs, void *const *v_p
     hipError_t e = hipSetDevice(c->device);
     if (e != hipSuccess) return hipfail(c, e, "hipSetDevice");
     hipStream_t st = (hipStream_t)stream;
-    // the previous call has synchronised: the pinned table is free to update
+    // the pinned table is free to update once the previous evaluation is done
+    if ((rc = wait_pending(c)) != VDWNL_OK) return rc;
     for (int i = 0; i < nb; ++i) {
         c->h_inst[i].n = n_ptrs[i];
         c->h_inst[i].v = v_ptrs[i];
@@ -956,6 +981,18 @@ static int run(vdwnl_ctx *c, int nb, const void *const *n_ptrs, void *const *v_p
     } else {
         // per-pass timing: eager launches bracketed by events
         if ((rc = enqueue(c, nb, st)) != VDWNL_OK) return rc;
+    }
+    if (E_dev) {
+        // (E_k, Delta E) of each grid: the first two of its four energies
+        if ((e = hipMemcpy2DAsync(E_dev, 2 * sizeof(double), c->d_E, 4 * sizeof(double), 2 * sizeof(double), nb,
+                                  hipMemcpyDeviceToDevice, st)) != hipSuccess)
+            return hipfail(c, e, "copy energies to the device buffer");
+        if (!c->done_ev && (e = hipEventCreateWithFlags(&c->done_ev, hipEventDisableTiming)) != hipSuccess)
+            return hipfail(c, e, "hipEventCreate");
+        if ((e = hipEventRecord(c->done_ev, st)) != hipSuccess) return hipfail(c, e, "hipEventRecord");
+        c->pending = true;
+        c->pending_functional = c->functional;
+        return VDWNL_OK;
     }
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return hipfail(c, e, "stream synchronize");
     for (int i = 0; i < nb; ++i) {
@@ -1132,6 +1169,13 @@ int vdwnl_energy_potential_batched(vdwnl_ctx *ctx, int32_t nb, const void *const
     return run(ctx, nb, n_ptrs, v_ptrs, E_out, stream);
 }
 
+int vdwnl_energy_potential_batched_async(vdwnl_ctx *ctx, int32_t nb, const void *const *n_ptrs,
+                                         void *const *v_ptrs, double *E_dev, void *stream) {
+    if (!ctx) return VDWNL_E_ARG;
+    if (!E_dev) return fail(ctx, VDWNL_E_ARG, "null energy buffer");
+    return run(ctx, nb, n_ptrs, v_ptrs, nullptr, stream, E_dev);
+}
+
 int vdwnl_debug_field(vdwnl_ctx *ctx, int32_t inst, int32_t which, void *dst, void *stream) {
     if (!ctx || !dst) return VDWNL_E_ARG;
     if (!ctx->device_ready || inst < 0 || inst >= (int32_t)ctx->grids.size())
@@ -1163,6 +1207,10 @@ int vdwnl_set_functional(vdwnl_ctx *ctx, int32_t functional) {
 
 int vdwnl_semilocal_energies(const vdwnl_ctx *ctx, int32_t nb, double *E_out) {
     if (!ctx || !E_out) return VDWNL_E_ARG;
+    // (an asynchronous evaluation in flight is waited for: its energies are
+    // the last evaluation's)
+    const int rc = wait_pending(const_cast<vdwnl_ctx *>(ctx));
+    if (rc != VDWNL_OK) return rc;
     if (ctx->last_functional != VDWNL_FUNCTIONAL_VDW_DF || !ctx->h_E)
         return VDWNL_E_STATE;
     if (nb != (int32_t)ctx->grids.size()) return VDWNL_E_ARG;

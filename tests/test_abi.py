@@ -176,3 +176,17 @@ def test_functional_mode_checks():
     assert lib.vdwnl_semilocal_energies(h, 1, out.ctypes.data_as(dp)) == E["STATE"]
     assert lib.vdwnl_semilocal_energies(h, 1, None) == E["ARG"]
     lib.vdwnl_destroy(h)
+
+
+def test_async_call_checks():
+    """The asynchronous batched call rejects a null energy buffer and, on a
+    host-only context, reports that there is no device."""
+    lib, h = _host_ctx()
+    assert _set_grid(lib, h, (24, 24, 24)) == 0
+    vp = ctypes.c_void_p
+    n = (vp * 1)(vp(16))
+    v = (vp * 1)(vp(32))
+    assert lib.vdwnl_energy_potential_batched_async(h, 1, n, v, None, None) == E["ARG"]
+    assert lib.vdwnl_energy_potential_batched_async(h, 1, n, v, vp(64), None) == E["STATE"]
+    assert lib.vdwnl_energy_potential_batched_async(None, 1, n, v, vp(64), None) == E["ARG"]
+    lib.vdwnl_destroy(h)
