@@ -58,7 +58,7 @@ def pass_bytes(name, shapes, s):
 def measured_traffic(kernel, lds_budget_z):
     """HBM bytes per evaluation of `kernel` from the committed counter summary
     (profiles/<kernel>_batched64_fp32.md), if it was taken on the kernel
-    sources as they are now and the same tile budget; else None."""
+    sources as they are now and at the tile budget of this run; else None."""
     import hashlib
     import re
     path = os.path.join(ROOT, "profiles", "%s_batched64_fp32.md" % kernel)
@@ -72,9 +72,10 @@ def measured_traffic(kernel, lds_budget_z):
     src = os.path.join(ROOT, "paper_0812_0244_amd", "csrc")
     for f in ("common.hpp", "fft_lds.hpp", "fft_fast.hpp", "tile_io.hpp", "kernels.hip"):
         h.update(open(os.path.join(src, f), "rb").read())
-    if rec.get("kernel_sources_sha256") != h.hexdigest() or rec.get("lds_budget_z") != lds_budget_z:
+    if rec.get("kernel_sources_sha256") != h.hexdigest():
         return None
-    return float(rec["hbm_bytes_per_evaluation"])
+    hit = rec.get("by_lds_budget_z", {}).get(str(lds_budget_z))
+    return None if hit is None else float(hit["hbm_bytes_per_evaluation"])
 
 
 def cpu_baseline(insts, dens, budget_s):
