@@ -55,6 +55,24 @@ def pass_bytes(name, shapes, s):
     return tot
 
 
+def z_main_flops(shapes):
+    """Algorithmic FP32 flops of one launch of the fused axis-1 pass over all
+    grids: per half-spectrum k point the contraction (20 x 20 real matrix on
+    a complex 20-vector: 1600 flops) and its share of the forward and inverse
+    axis-1 FFTs of the 20 spectra (5 N1 log2 N1 flops per complex line)."""
+    import math
+    tot = 0.0
+    for (n1, n2, n3) in shapes:
+        tot += n1 * n2 * (n3 // 2 + 1) * (1600.0 + 2 * 20 * 5 * math.log2(n1))
+    return tot
+
+
+# FP32 vector arithmetic of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2 flops
+# (FMA) x 2.4 GHz without packed FP32 (which this build does not use); the
+# published 157.3 TFLOP/s counts packed FP32
+PEAK_FP32_VALU_TFS = 78.6
+
+
 def measured_traffic(kernel, lds_budget_z):
     """HBM bytes per evaluation of `kernel` from the committed counter summary
     (profiles/<kernel>_batched64_fp32.md), if it was taken on the kernel
@@ -402,6 +420,13 @@ def main():
                      "algorithmic_bytes": dom_bytes,
                      "path_algorithmic_bytes_per_step": path_bytes,
                      "path_frac": path_bytes / (ms_step * 1e-3) / 1e9 / PEAK_HBM_GBS},
+        # the same pass against the vector-ALU roofline (its counters show it
+        # bound by instruction issue, not bandwidth)
+        "roofline_valu": None if dom != "z_main" else {
+            "bound": "alu", "kernel": dom, "unit": "TFLOP/s",
+            "achieved": z_main_flops(shapes) / (dom_ms * 1e-3) / 1e12, "peak": PEAK_FP32_VALU_TFS,
+            "frac": z_main_flops(shapes) / (dom_ms * 1e-3) / 1e12 / PEAK_FP32_VALU_TFS,
+            "algorithmic_flops": z_main_flops(shapes)},
         "fd_gradient": fd,
         "triclinic_cells": tri,
         "whole_functional": xc,
