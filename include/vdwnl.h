@@ -146,9 +146,9 @@ int vdwnl_energy_potential_batched(vdwnl_ctx *ctx, int32_t nb, const void *const
  * evaluation inside their own stream-ordered work).  The density and
  * potential buffers must stay valid until the stream has passed the
  * evaluation.  The next call on the context (any evaluation, re-planning,
- * vdwnl_semilocal_energies, destroy) first waits on the host until this
- * evaluation has finished, since it reads the context's pinned instance
- * table.  VDWNL_E_ARG for a null E_dev; VDWNL_E_STATE while per-pass timing
+ * vdwnl_semilocal_energies, vdwnl_debug_field, destroy) first waits on the
+ * host until this evaluation has finished, since it reads the context's
+ * pinned instance table.  VDWNL_E_ARG for a null E_dev; VDWNL_E_STATE while per-pass timing
  * is on; otherwise the errors of the synchronous call. */
 int vdwnl_energy_potential_batched_async(vdwnl_ctx *ctx, int32_t nb, const void *const *n_ptrs,
                                          void *const *v_ptrs, double *E_dev, void *stream);

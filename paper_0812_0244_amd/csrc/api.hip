@@ -1180,6 +1180,8 @@ int vdwnl_debug_field(vdwnl_ctx *ctx, int32_t inst, int32_t which, void *dst, vo
     if (!ctx || !dst) return VDWNL_E_ARG;
     if (!ctx->device_ready || inst < 0 || inst >= (int32_t)ctx->grids.size())
         return fail(ctx, VDWNL_E_STATE, "no evaluation of that grid yet");
+    const int rc = wait_pending(ctx);     // (the copy reads what that evaluation writes)
+    if (rc != VDWNL_OK) return rc;
     const Grid &g = ctx->grids[inst];
     const size_t rs = ctx->precision == 64 ? 8 : 4;
     size_t off, bytes;
