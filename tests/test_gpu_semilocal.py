@@ -100,6 +100,18 @@ def test_c2_fp32(table, m):
     check(gpu_xc(n32, wl.cell, table, 32, m), o, 32)
 
 
+@pytest.mark.parametrize("m", [0, 2])
+def test_triclinic_fp32(table, m):
+    """FP32 in a triclinic cell: the packed-row variant of the fused pass
+    with the semilocal terms."""
+    L = W.triclinic_lattice((12.0, 11.0, 13.0), (78.0, 104.0, 66.0))
+    rng = np.random.default_rng(7)
+    n = W.density_on_lattice((40, 36, 48), L, W.random_atoms_lattice(rng, 8, L))
+    n32 = n.astype(np.float32).astype(np.float64)
+    o = F.xc_energy_potential(n32, L, table, return_parts=True, grad_mode=m)
+    check(gpu_xc(n32, L, table, 32, m), o, 32)
+
+
 @pytest.mark.parametrize("graph", [True, False])
 def test_switching_the_functional(table, graph):
     """One planned context: the nonlocal evaluation, the whole functional,
