@@ -6,6 +6,7 @@ identity behind Eq. (Vi), v as the exact gradient of E, and the spectral
 derivative as the limit of growing stencils.
 """
 import math
+import os
 from fractions import Fraction
 
 import numpy as np
@@ -14,13 +15,21 @@ import pytest
 import workloads as W
 from oracle import functional as F
 
-# first-derivative central weights, Fornberg, Math. Comp. 51 (1988), Table 1
-FORNBERG = {
-    1: [Fraction(1, 2)],
-    2: [Fraction(2, 3), Fraction(-1, 12)],
-    3: [Fraction(3, 4), Fraction(-3, 20), Fraction(1, 60)],
-    4: [Fraction(4, 5), Fraction(-1, 5), Fraction(4, 105), Fraction(-1, 280)],
-}
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _fornberg():
+    """First-derivative central weights, Fornberg, Math. Comp. 51 (1988),
+    Table 1 (tests/golden/fd_central_weights.txt)."""
+    out = {}
+    for line in open(os.path.join(GOLDEN, "fd_central_weights.txt")):
+        if line.strip() and not line.startswith("#"):
+            m, *ws = line.split()
+            out[int(m)] = [Fraction(w) for w in ws]
+    return out
+
+
+FORNBERG = _fornberg()
 
 
 @pytest.mark.parametrize("m", [1, 2, 3, 4])

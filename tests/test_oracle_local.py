@@ -4,6 +4,7 @@ Each test checks the oracle against something other than itself: an
 identity the paper states, a closed form, a textbook value, or a finite
 difference.
 """
+import os
 from fractions import Fraction
 
 import numpy as np
@@ -116,10 +117,16 @@ def test_saturation_derivative_fd():
 
 
 # ---------------------------------------------------------------- P3 (q0)
-@pytest.mark.parametrize("rs,ref", [(1.0, -0.0598), (2.0, -0.0448), (5.0, -0.0282), (10.0, -0.0186)])
+def _golden_rows(name):
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name)
+    return [line.split() for line in open(path) if line.strip() and not line.startswith("#")]
+
+
+@pytest.mark.parametrize("rs,ref", [(float(a), float(b)) for a, b in _golden_rows("uniform_gas_correlation.txt")])
 def test_pw92_uniform_gas_values(rs, ref):
     """Correlation energy per electron of the uniform gas (Ceperley-Alder data
-    as parametrised by Perdew-Wang), Hartree, three significant digits."""
+    as parametrised by Perdew-Wang; tests/golden/uniform_gas_correlation.txt),
+    Hartree, three significant digits."""
     n = 3.0 / (4.0 * np.pi * rs ** 3)
     eps, _ = F.pw92(np.array([n]))
     np.testing.assert_allclose(eps, ref, rtol=2.5e-3)
@@ -183,3 +190,16 @@ def test_local_derivatives_fd(table):
         lm = F.theta_fields(n, gm, table)
         np.testing.assert_allclose(loc["g"] * g[c], (lp["theta"] - lm["theta"]) / (2 * h), rtol=1e-5, atol=1e-9)
         np.testing.assert_allclose(loc["ge"] * g[c], (lp["e_delta"] - lm["e_delta"]) / (2 * h), rtol=1e-5, atol=1e-12)
+
+
+def test_paper_parameters(table):
+    """The table and the saturation use the interpolation and saturation
+    parameters the paper prints (tests/golden/paper_parameters.txt)."""
+    from oracle import kernel_table as kt
+    par = {r[0]: float(r[1]) for r in _golden_rows("paper_parameters.txt")}
+    q = kt.log_qmesh()
+    assert len(q) == int(par["n_alpha"]) == table["qmesh"].size
+    assert q[-1] == par["q_c"] == table["qc"]
+    assert table["mc"] == int(par["m_c"])
+    d = np.diff(q)                       # a logarithmic mesh: spacings grow by a constant factor > 1
+    assert d[1] / d[0] > 1.0 and np.allclose(d[1:] / d[:-1], d[1] / d[0], rtol=1e-12)
