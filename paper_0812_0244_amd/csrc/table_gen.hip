@@ -49,6 +49,15 @@ __device__ inline double nu(double a, double d) {
     return a * a / (-2.0 * expm1(-kGamma * t * t));
 }
 
+// 1/x: the hardware estimate refined by two Newton-Raphson steps
+// r <- r + r (1 - x r), within an ulp or so of 1/x for normal x (a few
+// instructions against the division's fifteen-odd)
+__device__ __forceinline__ double rcp_nr(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+
 // mesh: node a, weight w_i a_i^2 (times the smooth cutoff), S = sin a / a, F = f3(a)
 struct MeshDev {
     const double *a, *wa, *S, *F;
@@ -61,7 +70,7 @@ __global__ void __launch_bounds__(kTile) k_phi(const double *d1, const double *d
     if (p >= npts) return;
     const MeshDev m = meshes[band[p]];
     const double x1 = d1[p], x2 = d2[p];
-    __shared__ double jn1[kTile], jn2[kTile], jw[kTile], jS[kTile], jF[kTile];
+    __shared__ double jn1[kTile], jn2[kTile], jw[kTile], jS[kTile], jF[kTile], js[kTile];
     __shared__ double red[kTile / 64];
     const int nt = (m.na + kTile - 1) / kTile;
     double acc = 0.0;
@@ -71,20 +80,23 @@ __global__ void __launch_bounds__(kTile) k_phi(const double *d1, const double *d
         const double ai = iv ? m.a[i] : 1.0;
         const double n1i = nu(ai, x1), n2i = nu(ai, x2);
         const double wi = iv ? m.wa[i] : 0.0, Si = iv ? m.S[i] : 0.0, Fi = iv ? m.F[i] : 0.0;
-        const double sii = 1.0 / (n1i + n2i);
+        const double sii = rcp_nr(n1i + n2i);
         for (int tj = ti; tj < nt; ++tj) {
             __syncthreads();
             const int j = tj * kTile + threadIdx.x;
             if (j < m.na) {
                 const double aj = m.a[j];
-                jn1[threadIdx.x] = nu(aj, x1);
-                jn2[threadIdx.x] = nu(aj, x2);
+                const double n1j = nu(aj, x1), n2j = nu(aj, x2);
+                jn1[threadIdx.x] = n1j;
+                jn2[threadIdx.x] = n2j;
+                js[threadIdx.x] = rcp_nr(n1j + n2j);
                 jw[threadIdx.x] = m.wa[j];
                 jS[threadIdx.x] = m.S[j];
                 jF[threadIdx.x] = m.F[j];
             } else {
                 jn1[threadIdx.x] = 1.0;
                 jn2[threadIdx.x] = 1.0;
+                js[threadIdx.x] = 0.5;
                 jw[threadIdx.x] = 0.0;
                 jS[threadIdx.x] = 0.0;
                 jF[threadIdx.x] = 0.0;
@@ -95,9 +107,12 @@ __global__ void __launch_bounds__(kTile) k_phi(const double *d1, const double *d
             for (int jj = j0; jj < kTile; ++jj) {
                 const double x = jn1[jj], z = jn2[jj];
                 const double W = 2.0 * (Si * jF[jj] + Fi * jS[jj] - 3.0 * Fi * jF[jj]);
-                const double sjj = 1.0 / (x + z);
-                const double T = 0.5 * (1.0 / (n1i + x) + 1.0 / (n2i + z)) *
-                                 (sii * sjj + 1.0 / ((n1i + z) * (n2i + x)));
+                // T = (1/2) [1/(w+x) + 1/(y+z)] [1/((w+y)(x+z)) + 1/((w+z)(y+x))]
+                // with w, y = nu(a_i) at d1, d2 and x, z = nu(a_j) at d1, d2:
+                // the first bracket as one quotient, 1/(x+z) per j from LDS
+                const double p1 = n1i + x, p2 = n2i + z;
+                const double T = 0.5 * (p1 + p2) * rcp_nr(p1 * p2) *
+                                 (sii * js[jj] + rcp_nr((n1i + z) * (n2i + x)));
                 const double term = jw[jj] * W * T;
                 row += (tj == ti && jj == (int)threadIdx.x) ? term : 2.0 * term;   // (i,j) and (j,i)
             }
