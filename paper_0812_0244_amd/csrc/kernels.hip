@@ -118,7 +118,7 @@ __device__ double block_sum(double v) {
 // Perdew-Wang 1992 correlation), then the saturation of Eq. (Sat).
 template <typename T, bool DERIV>
 struct LocalQ {
-    T q0, Q, dqdn, dqds;
+    T q0, Q, dqdn, ndqds;    // ndqds = n dq0/dsigma (dq0/dsigma alone overflows FP32 at small n)
     T kf, eps, deps_dn;      // k_F, the LDA eps_c and (DERIV) d eps_c/dn
 
     __device__ __forceinline__ void eval(T n, T sigma, double qc, double iqc, int mc, const T *invm) {
@@ -135,15 +135,17 @@ struct LocalQ {
         const T iP2A = rcp<T>((T)2 * A * P);
         const T L = dev_log1p<T>(iP2A);
         eps = (T)-2 * A * ((T)1 + a1 * rs) * L;
-        const T ikfn2 = rcp<T>(kf) * in * in;             // 1 / (k_F n^2)
-        const T grad_term = zg * sigma * ikfn2;
+        // sigma / (k_F n^2) as ((sigma / n) / n) / k_F: finite in FP32 wherever
+        // |grad n| / n is, down to n_min (1 / (k_F n^2) alone is not below 1e-17)
+        const T ikf = rcp<T>(kf);
+        const T grad_term = zg * ((sigma * in) * in) * ikf;
         const T qraw = kf - ((T)4 * pi / (T)3) * eps + grad_term;
         if (DERIV) {
             const T dP = (T)0.5 * b1 * rcp<T>(srs) + b2 + (T)1.5 * b3 * srs + (T)2 * b4 * rs;
             const T deps_drs = (T)-2 * A * a1 * L + (T)2 * A * ((T)1 + a1 * rs) * dP * rcp<T>(P * ((T)2 * A * P + (T)1));
             deps_dn = deps_drs * (-rs * in * ((T)1 / (T)3));
             dqdn = kf * in * ((T)1 / (T)3) - ((T)4 * pi / (T)3) * deps_dn - ((T)7 / (T)3) * grad_term * in;
-            dqds = zg * ikfn2;
+            ndqds = zg * ikf * in;
         }
         // h(x, x_c) = x_c (1 - exp(-S)), S = sum_{m<=m_c} (x/x_c)^m / m (Horner),
         // dh/dx = exp(-S) sum_{m<m_c} (x/x_c)^m.  1 - exp(-S) as -expm1(-S)
@@ -157,6 +159,7 @@ struct LocalQ {
         if (!(S < (T)80)) {
             q0 = (T)qc;
             Q = (T)0;
+            if (DERIV) { dqdn = (T)0; ndqds = (T)0; }   // (their products with Q vanish)
         } else {
             q0 = (T)(-qc) * dev_expm1<T>(-S);
             if (DERIV) {
@@ -184,17 +187,21 @@ struct Semilocal {
         const T kappa = (T)1.245, mu = (T)(0.066725 * 3.14159265358979323846 * 3.14159265358979323846 / 3.0);
         const T in = rcp<T>(n), ikf = rcp<T>(lq.kf);
         const T eu = (T)(-3.0 / (4.0 * 3.14159265358979323846)) * lq.kf * n;
-        const T ds2 = (T)0.25 * ikf * ikf * in * in;        // d s^2 / d sigma
-        const T s2 = sigma * ds2;
-        const T iden = rcp<T>((T)1 + (mu / kappa) * s2);
+        // s^2 = sigma / (4 k_F^2 n^2), ordered to stay finite at small n; where
+        // it still overflows (or is huge) F_x has reached 1 + kappa
+        const T s2 = ((sigma * in) * in) * ((T)0.25 * ikf * ikf);
+        const bool flat = !(s2 < (T)1e30);
+        const T iden = flat ? (T)0 : rcp<T>((T)1 + (mu / kappa) * s2);
         const T fx = (T)1 + kappa - kappa * iden;
         ex = eu * fx;
         ec = n * lq.eps;
         if (DERIV) {
             const T dfx = mu * iden * iden;                  // dF_x / ds^2
-            // d e_u/dn = (4/3) e_u / n, d s^2/dn = -(8/3) s^2 / n
-            dn = ((T)(4.0 / 3.0) * fx - (T)(8.0 / 3.0) * dfx * s2) * eu * in + lq.eps + n * lq.deps_dn;
-            ds = eu * dfx * ds2;
+            const T dfx_s2 = flat ? (T)0 : dfx * s2;
+            // d e_u/dn = (4/3) e_u / n, d s^2/dn = -(8/3) s^2 / n;
+            // d e_x/dsigma = e_u F_x' / (4 k_F^2 n^2) = -3 F_x' / (16 pi k_F n)
+            dn = ((T)(4.0 / 3.0) * fx - (T)(8.0 / 3.0) * dfx_s2) * eu * in + lq.eps + n * lq.deps_dn;
+            ds = (T)(-3.0 / (16.0 * 3.14159265358979323846)) * dfx * rcp<T>(lq.kf * n);
         }
     }
 };
@@ -537,7 +544,7 @@ __global__ void __launch_bounds__(kThreads) k_x_assemble(const InstDev *insts, c
             const T q0 = lq.q0, cs = (T)c_cs;
             const T iq = rcp<T>(q0), iq3 = iq * iq * iq, iq4 = iq3 * iq;
             vl = su + cn * sdu + (T)2 * cs * nv * iq3 - (T)3 * cs * nv * nv * iq4 * lq.Q * lq.dqdn;
-            gs = (T)2 * nv * lq.Q * lq.dqds * sdu - (T)6 * cs * nv * nv * iq4 * lq.Q * lq.dqds;
+            gs = (T)2 * lq.Q * lq.ndqds * sdu - (T)6 * cs * nv * iq4 * lq.Q * lq.ndqds;
             if (semilocal) {
                 // the semilocal terms: de/dgrad n = 2 de/dsigma grad n
                 Semilocal<T> sl;
