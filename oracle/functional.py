@@ -127,10 +127,11 @@ def saturate(q, qc, mc):
     S = np.zeros_like(y)
     dS = np.zeros_like(y)   # dS/dy = sum_{m=0}^{mc-1} y^m
     ym = np.ones_like(y)
-    for m in range(1, mc + 1):
-        dS += ym
-        ym = ym * y
-        S += ym / m
+    with np.errstate(over="ignore", invalid="ignore"):   # (huge y: S overflows and saturates below)
+        for m in range(1, mc + 1):
+            dS += ym
+            ym = ym * y
+            S += ym / m
     big = S > 700.0
     e = np.exp(-np.where(big, 0.0, S))
     h = np.where(big, qc, qc * (1.0 - e))
