@@ -190,3 +190,33 @@ def test_async_call_checks():
     assert lib.vdwnl_energy_potential_batched_async(h, 1, n, v, vp(64), None) == E["STATE"]
     assert lib.vdwnl_energy_potential_batched_async(None, 1, n, v, vp(64), None) == E["ARG"]
     lib.vdwnl_destroy(h)
+
+
+def test_pass_lists_and_tiling_on_host():
+    """Pass names, the pass order of each gradient mode, and the tile budgets
+    (set, read back, range-checked) on a host-only context."""
+    lib, h = _host_ctx()
+    i32 = ctypes.c_int32
+    names = [lib.vdwnl_pass_name(i).decode() for i in range(40)]
+    assert "z_main" in names and "x_theta" in names and "fd_grad" in names
+    assert lib.vdwnl_pass_name(-1) == b"" and lib.vdwnl_pass_name(1000) == b""
+    for gm, n_pass in ((0, 14), (3, 7)):
+        assert _set_grid(lib, h, (24, 24, 24), gm=gm) == 0
+        kinds = (i32 * 32)()
+        n = lib.vdwnl_pass_order(h, 32, kinds)
+        assert n == n_pass
+        order = [names[kinds[i]] for i in range(n)]
+        assert order[0] == ("x_nfwd" if gm == 0 else "fd_grad")
+        assert "z_main" in order and order[-1] == ("x_final" if gm == 0 else "fd_div")
+    b = (ctypes.c_int64 * 5)(32768, 32768, 16384, 49152, 24576)
+    assert lib.vdwnl_set_tiling(h, 5, b) == 0
+    out = (ctypes.c_int64 * 8)()
+    assert lib.vdwnl_get_tiling(h, 8, out) == 5
+    assert list(out)[:5] == [32768, 32768, 16384, 49152, 24576]
+    assert lib.vdwnl_set_tiling(h, 4, b) == E["ARG"]
+    bad = (ctypes.c_int64 * 5)(32768, 32768, 1024, 49152, 24576)
+    assert lib.vdwnl_set_tiling(h, 5, bad) == E["ARG"]
+    nb = ctypes.c_int32()
+    ws = ctypes.c_int64()
+    assert lib.vdwnl_info(h, ctypes.byref(nb), ctypes.byref(ws)) == 0 and nb.value == 1
+    lib.vdwnl_destroy(h)
