@@ -1,8 +1,9 @@
 """The full-size workloads, in the launch configuration the benchmark times.
 
-At these sizes the oracle cannot evaluate every output, so the checks are:
-the oracle on the members it can afford (the small grids of the batch),
-the FP32 path against the FP64 GPU path (same input), properties that hold
+At these sizes the oracle is not run on every output, so the checks are:
+the oracle on one member of every edge length of the batch (up to 128^3),
+every member's FP32 potential against the FP64 GPU path on the same
+FP32-rounded input, properties that hold
 at any size (v = dE/dn by central differences of FP64 energies, translation
 invariance), and the forces of the differentiation workload against central
 differences of the energy in the atom positions.
@@ -50,21 +51,35 @@ def test_batched_workload_against_fp64_plain_and_oracle(table):
     n32 = [torch.from_numpy(d).to("cuda", torch.float32) for d in dens]
     v32 = [torch.empty_like(x) for x in n32]
     E32 = lib.energy_potential_batched([x.data_ptr() for x in n32], [x.data_ptr() for x in v32])
-    worst = 0.0
+    worst, worst_dv = 0.0, 0.0
+    checked_edges = set()
     for i, w in enumerate(insts):
         eng = engine(w.shape, w.cell, table, 64)
-        e64, v64 = run(eng, torch.from_numpy(dens[i]).cuda())
+        e64, _ = run(eng, torch.from_numpy(dens[i]).cuda())
         rel = abs(E32[i].sum() - e64) / abs(e64)
         worst = max(worst, rel)
         assert rel <= 1e-6, (i, rel)
-        if w.shape[0] <= 32 and i < 24:
+        # v of every member against the FP64 path on the same FP32-rounded input
+        e64r, v64r = run(eng, n32[i].double())
+        dv = float((v32[i].double() - v64r).abs().max())
+        worst_dv = max(worst_dv, dv)
+        assert dv <= 1e-5, (i, w.shape, dv)
+        assert abs(E32[i].sum() - e64r) <= 1e-6 * abs(e64r)
+        # the first member of every edge length against the oracle (same input)
+        if w.shape[0] not in checked_edges:
+            checked_edges.add(w.shape[0])
             n32h = n32[i].double().cpu().numpy()
             ek, de, vo = F.energy_potential(n32h, w.cell, table)
-            say("  member %d (%d^3): E gpu32 %.12e oracle %.12e  max|dv| %.2e"
-                % (i, w.shape[0], E32[i].sum(), ek + de, np.abs(v32[i].double().cpu().numpy() - vo).max()))
+            dvo = np.abs(v32[i].double().cpu().numpy() - vo).max()
+            say("  member %d (%d^3): E gpu32 %.12e oracle %.12e  max|dv| %.2e (gpu64 same input %.2e)"
+                % (i, w.shape[0], E32[i].sum(), ek + de, dvo, dv))
             assert abs(E32[i].sum() - (ek + de)) <= 1e-6 * abs(ek + de)
-            assert np.abs(v32[i].double().cpu().numpy() - vo).max() <= 1e-5
-    say("  batched FP32 vs FP64 plain: worst relative energy difference %.2e" % worst)
+            assert dvo <= 1e-5
+            assert abs(e64r - (ek + de)) <= 1e-10 * abs(ek + de)
+            assert float(np.abs(v64r.cpu().numpy() - vo).max()) <= 1e-10 * np.abs(vo).max()
+    assert checked_edges == {32, 48, 64, 96, 128}
+    say("  batched FP32 vs FP64 plain: worst relative energy difference %.2e, worst max|dv| "
+        "(same input) %.2e Ha" % (worst, worst_dv))
 
 
 def _directional_check(eng, n, cell, centre, dvol, eps=1e-4, width=1.5):
@@ -149,3 +164,40 @@ def test_differentiation_workload_forces(table):
             fd = -(float(energy(pp, e64)) - float(energy(pm, e64))) / (2 * h)
         say("  F[%d,%d] autograd %.10e  FD %.10e" % (a, c, f64[a, c], fd))
         assert abs(fd - f64[a, c]) <= 1e-5 * fscale + 1e-9
+
+
+def test_forces_against_oracle_energy_differences(table):
+    """F_A = -dE/dR_A: the autograd forces of the HIP path (backward =
+    dOmega v, chained through the torch density builder) against central
+    differences (h = 1e-4 bohr) of the FP64 oracle's energies E_k + Delta E
+    on a 48^3 grid with six atoms, in FP64 (to 1e-6 of max|F|) and FP32 (to
+    1e-4 of max|F|)."""
+    from oracle import functional as F
+    shape, L = (48, 48, 48), 48 * W.BATCH_SPACING
+    cell = (L, L, L)
+    atoms = W.random_atoms(np.random.default_rng(4848), 6, cell)
+    pos = torch.tensor(atoms.pos, dtype=torch.float64, device="cuda")
+    forces = {}
+    for prec in (64, 32):
+        eng = engine(shape, cell, table, prec)
+        r = pos.clone().requires_grad_(True)
+        n = W.density_torch(shape, cell, atoms.amp, atoms.width, r)
+        if prec == 32:
+            n = n.float()
+        eng(n).backward()
+        forces[prec] = -r.grad.cpu().numpy()
+    fscale = np.abs(forces[64]).max()
+    h = 1e-4
+
+    def e_oracle(p):
+        ek, de, _ = F.energy_potential(W.density_on_grid(shape, cell, W.Atoms(atoms.amp, atoms.width, p)), cell, table)
+        return ek + de
+
+    for a, c in [(0, 0), (1, 2), (3, 1), (5, 0), (5, 2)]:
+        pp, pm = atoms.pos.copy(), atoms.pos.copy()
+        pp[a, c] += h
+        pm[a, c] -= h
+        fd = -(e_oracle(pp) - e_oracle(pm)) / (2 * h)
+        say("  F[%d,%d] oracle FD %.10e  gpu64 %.10e  gpu32 %.10e" % (a, c, fd, forces[64][a, c], forces[32][a, c]))
+        assert abs(forces[64][a, c] - fd) <= 1e-6 * fscale
+        assert abs(forces[32][a, c] - fd) <= 1e-4 * fscale
