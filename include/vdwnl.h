@@ -76,8 +76,10 @@ const char *vdwnl_last_error(const vdwnl_ctx *ctx);
  *   precision  32 or 64
  * Device workspace is allocated at the first evaluation after planning;
  * later evaluations allocate nothing.  Tile shapes follow one LDS budget per
- * pass group: a budget set tuned by vdwnl_autotune for the same grid list and
- * precision in this process is reused, else 64 KB each. */
+ * pass group: a budget set tuned by vdwnl_autotune for the same grid list,
+ * precision, gradient mode and device architecture is reused (from this
+ * process, or from the tuning file of an earlier one; see vdwnl_autotune),
+ * else 64 KB each. */
 int vdwnl_set_grid(vdwnl_ctx *ctx, const int32_t shape[3], const double cell[3],
                    int32_t grad_mode, int32_t precision);
 
@@ -188,6 +190,41 @@ int vdwnl_semilocal_energies(const vdwnl_ctx *ctx, int32_t nb, double *E_out);
  * the semilocal terms' local parts).  Arrays in the planned precision. */
 int vdwnl_debug_field(vdwnl_ctx *ctx, int32_t inst, int32_t which, void *dst, void *stream);
 
+/* Parity probe of one stage of the method for grid `inst` (0-based) of the
+ * planned batch.  The passes of the last evaluation run again, launched one
+ * by one on `stream`, up to the stage, with the same density buffers (they
+ * must still hold the density of that evaluation; the potential buffers are
+ * not written), and the stage's values are written to the caller's device
+ * buffer dst (planned precision, C order):
+ *   VDWNL_STAGE_THETA    theta_a(r_i) = n_i p_a(q0_i), the weighted densities
+ *                        of the factorised kernel (the text after
+ *                        Eq. (Eoffk)); real [20][N1][N2][N3]
+ *   VDWNL_STAGE_THETA_K  their transforms c_a(G) = FFT(theta_a)(G) / N
+ *                        (Eq. (Eoffk)) on the half spectrum m_3 = 0..N3/2;
+ *                        complex [N1][N2][N3/2+1][20] (re, im pairs; the 20
+ *                        components of a wave vector contiguous); index k_c
+ *                        of axes 1, 2 in FFT order (frequency k_c, or
+ *                        k_c - N_c above N_c/2)
+ *   VDWNL_STAGE_U_K      u_a(G) = sum_b phi_ab(|G|) c_b(G), the per-k
+ *                        contraction of Eqs. (epsofk); same layout
+ *   VDWNL_STAGE_U        u_a(r_i) = sum_G u_a(G) exp(i G . r_i)
+ *                        (Eq. (epsilon): u_ai = dOmega^-1 dE_k/dtheta_ai);
+ *                        real [20][N1][N2][N3]
+ * Returns after the stream has finished.  The workspace is left as the probe
+ * left it; the next evaluation recomputes everything.  VDWNL_E_ARG for a null
+ * pointer or an unknown stage; VDWNL_E_STATE before the first evaluation of
+ * the plan or for an index outside the batch. */
+enum { VDWNL_STAGE_THETA = 0, VDWNL_STAGE_THETA_K = 1, VDWNL_STAGE_U_K = 2, VDWNL_STAGE_U = 3 };
+int vdwnl_debug_stage(vdwnl_ctx *ctx, int32_t inst, int32_t stage, void *dst, void *stream);
+
+/* The logarithmic mesh of interpolation points of the factorisation (the
+ * paragraph before Eq. (qsat)): q_1 = q1, q_nq = q_c, and increments that grow
+ * by the factor lambda, (q_{a+1} - q_a) = lambda (q_a - q_{a-1}).  Host only
+ * (no device, no context).  q_out: host array [nq].  VDWNL_E_ARG unless
+ * 2 <= nq <= 4096, 0 < q1 < q_c, lambda >= 1 (1: a uniform mesh) and
+ * lambda^(nq-2) finite. */
+int vdwnl_log_qmesh(int32_t nq, double q1, double q_c, double lambda, double *q_out);
+
 /* Per-pass timing.  vdwnl_set_timing(ctx, 1) clears the counters and makes
  * every later evaluation record a HIP event after each of its passes (on the
  * evaluation's stream); vdwnl_pass_times copies the accumulated milliseconds
@@ -211,9 +248,15 @@ int vdwnl_set_graph(vdwnl_ctx *ctx, int32_t on);
  * v_ptrs[nb] as for vdwnl_energy_potential_batched; v is overwritten) once
  * plus `reps` timed times (1..100) for each candidate LDS budget, picks per
  * pass group the budget with the least time over the group's passes, plans
- * with it and remembers it for this grid list and precision for the rest of
- * the process.  Results do not depend on the tile shapes beyond rounding
- * order.  Returns an error code as the evaluation does. */
+ * with it and remembers it, keyed by the device architecture, its LDS size,
+ * the precision, the gradient mode and the exact grid list: for the rest of
+ * the process, and in the tuning file for later processes.  The file is a
+ * JSON object with one entry per line, "<arch>/<key hash>": [five budgets],
+ * at $VDWNL_TUNE_CACHE (an empty value: no file), else
+ * $XDG_CACHE_HOME/vdwnl/tuning.json or $HOME/.cache/vdwnl/tuning.json; a file
+ * that cannot be read or written is ignored.  Results do not depend on the
+ * tile shapes beyond rounding order.  Returns an error code as the
+ * evaluation does. */
 int vdwnl_autotune(vdwnl_ctx *ctx, int32_t nb, const void *const *n_ptrs, void *const *v_ptrs,
                    int32_t reps, void *stream);
 

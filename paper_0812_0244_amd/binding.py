@@ -36,6 +36,8 @@ SIGNATURES = {
     "vdwnl_energy_potential_batched_async": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(_vp),
                                                             ctypes.POINTER(_vp), _vp, _vp]),
     "vdwnl_debug_field": (ctypes.c_int, [_vp, _i32, _i32, _vp, _vp]),
+    "vdwnl_debug_stage": (ctypes.c_int, [_vp, _i32, _i32, _vp, _vp]),
+    "vdwnl_log_qmesh": (ctypes.c_int, [_i32, ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp]),
     "vdwnl_info": (ctypes.c_int, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(ctypes.c_int64)]),
     "vdwnl_set_timing": (ctypes.c_int, [_vp, _i32]),
     "vdwnl_pass_times": (ctypes.c_int, [_vp, _i32, _dp, ctypes.POINTER(ctypes.c_int64)]),
@@ -85,11 +87,17 @@ def load_library(path: str = LIB_PATH):
     return _lib
 
 
+STAGE_THETA, STAGE_THETA_K, STAGE_U_K, STAGE_U = 0, 1, 2, 3
+
+
 def log_qmesh(nq: int = 20, q1: float = 0.05, qc: float = 5.0, lam: float = 1.17):
-    """Logarithmic q mesh: (q_{a+1} - q_a) = lam (q_a - q_{a-1}), q_1 = q1, q_N = q_c."""
-    d = np.cumprod(np.concatenate([[1.0], np.full(nq - 2, lam)]))
-    q = q1 + np.concatenate([[0.0], np.cumsum(d * (qc - q1) / d.sum())])
-    q[-1] = qc
+    """Logarithmic q mesh built by the library: (q_{a+1} - q_a) = lam (q_a - q_{a-1}),
+    q_1 = q1, q_N = q_c."""
+    lib = load_library()
+    q = np.zeros(int(nq))
+    rc = lib.vdwnl_log_qmesh(int(nq), float(q1), float(qc), float(lam), _as_ptr(q, ctypes.c_double))
+    if rc != 0:
+        raise VdwNlError(rc, "vdwnl_log_qmesh")
     return q
 
 
@@ -252,6 +260,11 @@ class VdwNl:
 
     def debug_field(self, inst: int, which: int, dst_ptr: int, stream: int = 0):
         self._check(self.lib.vdwnl_debug_field(self.h, inst, which, _vp(dst_ptr), _vp(stream)), "debug_field")
+
+    def debug_stage(self, inst: int, stage: int, dst_ptr: int, stream: int = 0):
+        """One stage (STAGE_THETA, STAGE_THETA_K, STAGE_U_K, STAGE_U) of grid
+        inst, recomputed from the last evaluation's density, into dst."""
+        self._check(self.lib.vdwnl_debug_stage(self.h, inst, stage, _vp(dst_ptr), _vp(stream)), "debug_stage")
 
     def set_timing(self, on: bool = True):
         self._check(self.lib.vdwnl_set_timing(self.h, 1 if on else 0), "set_timing")

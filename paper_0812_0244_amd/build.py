@@ -1,4 +1,8 @@
-"""Compile libvdwnl.so (HIP, gfx950) in-tree with hipcc."""
+"""Compile libvdwnl.so (HIP, gfx950) in-tree with hipcc.
+
+Each translation unit is compiled to an object in its own hipcc process (in
+parallel), then the objects are linked into the shared library.
+"""
 from __future__ import annotations
 
 import os
@@ -9,10 +13,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT_DIR, "libvdwnl.so")
-SOURCES = ("api.hip", "kernels.hip", "table_gen.hip")
+SOURCES = ("api.hip", "kernels_f32.hip", "kernels_f64.hip", "table_gen.hip")
 
 HIPCC_FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # packed-FP32 instructions off: plain scalar/vector FP32 only
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
@@ -22,15 +26,35 @@ def build(verbose: bool = False) -> str:
     """Compile every HIP source into libvdwnl.so (always recompiles)."""
     os.makedirs(OUT_DIR, exist_ok=True)
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc] + HIPCC_FLAGS + ["-o", tmp] + [os.path.join(CSRC, s) for s in SOURCES]
-    res = subprocess.run(cmd, capture_output=True, text=True)
-    if res.returncode != 0:
-        sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building libvdwnl.so")
-    if verbose:
-        sys.stdout.write(res.stderr)
-    os.replace(tmp, LIB)
+    tag = ".%d" % os.getpid()
+    objs, procs = [], []
+    for src in SOURCES:
+        obj = os.path.join(OUT_DIR, os.path.splitext(src)[0] + tag + ".o")
+        cmd = [hipcc] + HIPCC_FLAGS + ["-c", "-o", obj, os.path.join(CSRC, src)]
+        procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)))
+        objs.append(obj)
+    failed = False
+    for src, p in procs:
+        out, err = p.communicate()
+        if p.returncode != 0:
+            sys.stderr.write(out + err)
+            failed = True
+        elif verbose:
+            sys.stdout.write(err)
+    try:
+        if failed:
+            raise RuntimeError("hipcc failed building libvdwnl.so")
+        tmp = LIB + ".tmp%d" % os.getpid()
+        res = subprocess.run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs,
+                             capture_output=True, text=True)
+        if res.returncode != 0:
+            sys.stderr.write(res.stdout + res.stderr)
+            raise RuntimeError("hipcc failed linking libvdwnl.so")
+        os.replace(tmp, LIB)
+    finally:
+        for o in objs:
+            if os.path.exists(o):
+                os.remove(o)
     return LIB
 
 

@@ -1,6 +1,10 @@
 // Host side of libvdwnl: contexts, argument checks, planning and the C ABI.
+#include <sys/stat.h>
+#include <unistd.h>
+
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -140,6 +144,34 @@ struct Grid {
     size_t nhalf() const { return (size_t)s[0] * s[1] * (s[2] / 2 + 1); }
 };
 
+// Host image of the device state of a plan: the layout of one device buffer
+// (per-grid fields, shell maps and kernel rows, then the tile list, the
+// columns of the fused axis-1 tiles, twiddles, method constants, the
+// instance table and the energies), the contents of its tables and the
+// launches of every pass.  Host work only (no HIP call); the kernel rows are
+// kept only when asked (they are recomputed at upload time otherwise).
+struct Image {
+    std::vector<Tile> tiles;
+    std::vector<int2> cols;
+    std::vector<double> twd;                  // FP64 twiddles, (re, im) pairs
+    std::vector<float> tw32;                  // the same in FP32 (FP32 plans)
+    std::vector<std::vector<char>> tabs;      // kernel rows per shells entry (working precision), if kept
+    size_t ws = 0;                            // per-grid fields, shell maps and rows
+    size_t off_tiles = 0, off_cols = 0, off_tw = 0, off_twd = 0, off_consts = 0, off_inst = 0, off_E = 0;
+    size_t total = 0;
+};
+
+// Device pointers into one buffer that holds an image.
+struct DevPtrs {
+    char *base = nullptr;
+    InstDev *inst = nullptr;
+    Tile *tiles = nullptr;
+    Consts *consts = nullptr;
+    void *tw = nullptr, *twd = nullptr;     // twiddles in the working precision, FP64 twiddles
+    int2 *cols = nullptr;                   // (k2, k3) columns of the fused axis-1 tiles
+    double *E = nullptr;
+};
+
 }  // namespace vdwnl
 
 using namespace vdwnl;
@@ -158,6 +190,7 @@ struct vdwnl_ctx {
     std::string err;
     size_t pref[TG_COUNT] = {kLdsCap, kLdsCap, kLdsCap, kLdsCap, kLdsCap};   // LDS budget per pass group
     std::string plan_key;                 // identifies the batch for the tuned-budget cache
+    std::string arch = "host";            // device architecture (gcnArchName)
     // plan
     std::vector<Grid> grids;
     std::vector<Shells> shells;
@@ -171,13 +204,18 @@ struct vdwnl_ctx {
     Consts consts;
     // device state
     bool device_ready = false;            // tables built for the current (grid, table)
+    bool evaluated = false;               // an evaluation has run on the current workspace
     void *work = nullptr;
     size_t work_bytes = 0;
     std::vector<size_t> tab_off;          // per shells entry: offset of map and table
     std::vector<size_t> map_off;
-    InstDev *d_inst = nullptr;
+    DevPtrs dp;                           // the image in the context's own buffer (work)
     InstDev *h_inst = nullptr;            // pinned
-    Tile *d_tiles = nullptr;
+    // the host image of the plan (with the kernel rows when it is small)
+    Image img;
+    bool img_valid = false;
+    size_t img_need = 0;                  // bytes of the plan's image (0: no plan)
+    uint64_t plan_stamp = 0;              // changes whenever the image does
     struct Launch {
         int kind, lc, off, cnt;
         size_t lds;
@@ -191,11 +229,7 @@ struct vdwnl_ctx {
     int ngroups = 0;
     std::vector<hipStream_t> chain_streams;   // one per group (graph capture)
     std::vector<hipEvent_t> chain_events;     // fork (index 0) and one join per group
-    void *d_tw = nullptr;                 // twiddles in the working precision
-    void *d_twd = nullptr;                // FP64 twiddles
-    Consts *d_consts = nullptr;
-    int2 *d_cols = nullptr;               // (k2, k3) columns of the fused axis-1 tiles
-    double *d_E = nullptr, *h_E = nullptr;
+    double *h_E = nullptr;                // pinned
     std::map<int, int> tw_off;            // length -> offset
     // the evaluation captured as a HIP graph (replayed on the caller's stream)
     bool use_graph = true;
@@ -218,6 +252,7 @@ static int fail(vdwnl_ctx *c, int code, const std::string &msg) {
 }
 
 static int check_krange(vdwnl_ctx *c);
+static void refresh_image(vdwnl_ctx *c);
 
 static int hipfail(vdwnl_ctx *c, hipError_t e, const char *what) {
     return fail(c, VDWNL_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
@@ -260,20 +295,13 @@ static void free_device(vdwnl_ctx *c) {
         c->ev_made = false;
     }
     if (c->work) (void)hipFree(c->work);
-    if (c->d_inst) (void)hipFree(c->d_inst);
     if (c->h_inst) (void)hipHostFree(c->h_inst);
-    if (c->d_tiles) (void)hipFree(c->d_tiles);
-    if (c->d_tw) (void)hipFree(c->d_tw);
-    if (c->d_twd) (void)hipFree(c->d_twd);
-    if (c->d_consts) (void)hipFree(c->d_consts);
-    if (c->d_cols) (void)hipFree(c->d_cols);
-    c->d_cols = nullptr;
-    if (c->d_E) (void)hipFree(c->d_E);
     if (c->h_E) (void)hipHostFree(c->h_E);
-    c->work = nullptr; c->d_inst = nullptr; c->h_inst = nullptr; c->d_tiles = nullptr;
-    c->d_tw = nullptr; c->d_twd = nullptr; c->d_consts = nullptr; c->d_E = nullptr; c->h_E = nullptr;
+    c->work = nullptr; c->h_inst = nullptr; c->h_E = nullptr;
+    c->dp = DevPtrs();
     c->work_bytes = 0;
     c->device_ready = false;
+    c->evaluated = false;
 }
 
 static bool smooth235(int n) {
@@ -393,8 +421,14 @@ static void size_tiles(const vdwnl_ctx *c, Grid &g) {
     g.wy1 = g.wy3;
 }
 
-// Tuned LDS budgets, per process, keyed by precision, gradient mode, LDS size
-// and the exact list of grid shapes and cells.
+// Tuned LDS budgets, keyed by the device architecture, LDS size, precision,
+// gradient mode and the exact list of grid shapes and cells: a map for the
+// process, backed by a file so that later processes reuse them.  The file is
+// a JSON object with one entry per line,
+//   "<arch>/<hash of the rest of the key>": [x, y20, yaux, z, zaux],
+// at $VDWNL_TUNE_CACHE (empty: no file), else $XDG_CACHE_HOME/vdwnl/tuning.json
+// or $HOME/.cache/vdwnl/tuning.json.  A file that cannot be read or written
+// is ignored (the process map still works).
 static std::mutex g_tuned_mu;
 static std::map<std::string, std::vector<size_t>> g_tuned;
 
@@ -409,13 +443,85 @@ static std::string plan_key(const vdwnl_ctx *c) {
             k += buf;
         }
     }
-    return k;
+    // FNV-1a of the whole key, behind the readable part
+    uint64_t h = 1469598103934665603ull;
+    for (unsigned char ch : k) { h ^= ch; h *= 1099511628211ull; }
+    std::snprintf(buf, sizeof(buf), "%s/p%d/g%d/l%zu/n%zu/%016llx", c->arch.c_str(), c->precision, c->grad_mode,
+                  c->lds_cap, c->grids.size(), (unsigned long long)h);
+    return buf;
 }
 
-static bool tuned_lookup(const std::string &key, size_t *pref) {
+static std::string tune_cache_path() {
+    if (const char *p = std::getenv("VDWNL_TUNE_CACHE")) return p;
+    if (const char *x = std::getenv("XDG_CACHE_HOME"); x && *x) return std::string(x) + "/vdwnl/tuning.json";
+    if (const char *h = std::getenv("HOME"); h && *h) return std::string(h) + "/.cache/vdwnl/tuning.json";
+    return "";
+}
+
+// Entries of the file: lines  "key": [n, n, n, n, n]  (anything else skipped).
+static std::map<std::string, std::vector<size_t>> read_tune_file(const std::string &path) {
+    std::map<std::string, std::vector<size_t>> out;
+    if (path.empty()) return out;
+    FILE *f = std::fopen(path.c_str(), "r");
+    if (!f) return out;
+    char line[1024];
+    while (std::fgets(line, sizeof(line), f)) {
+        const char *q0 = std::strchr(line, '"');
+        const char *q1 = q0 ? std::strchr(q0 + 1, '"') : nullptr;
+        const char *br = q1 ? std::strchr(q1, '[') : nullptr;
+        if (!br) continue;
+        std::vector<size_t> v;
+        const char *p = br + 1;
+        while (v.size() < (size_t)TG_COUNT) {
+            char *end = nullptr;
+            const unsigned long long x = std::strtoull(p, &end, 10);
+            if (end == p) break;
+            v.push_back((size_t)x);
+            p = end;
+            while (*p == ',' || *p == ' ') ++p;
+        }
+        if (v.size() == (size_t)TG_COUNT) out[std::string(q0 + 1, q1)] = v;
+    }
+    std::fclose(f);
+    return out;
+}
+
+static void write_tune_file(const std::string &path, const std::map<std::string, std::vector<size_t>> &m) {
+    if (path.empty()) return;
+    const size_t slash = path.rfind('/');
+    if (slash != std::string::npos && slash > 0) {
+        // (create the directory and its parents; errors show up at fopen)
+        std::string dir = path.substr(0, slash);
+        for (size_t i = 1; i <= dir.size(); ++i)
+            if (i == dir.size() || dir[i] == '/') (void)mkdir(dir.substr(0, i).c_str(), 0755);
+    }
+    const std::string tmp = path + ".tmp" + std::to_string((long)getpid());
+    FILE *f = std::fopen(tmp.c_str(), "w");
+    if (!f) return;
+    std::fprintf(f, "{\n");
+    size_t i = 0;
+    for (const auto &kv : m) {
+        std::fprintf(f, "  \"%s\": [", kv.first.c_str());
+        for (int g = 0; g < TG_COUNT; ++g) std::fprintf(f, g ? ", %zu" : "%zu", kv.second[g]);
+        std::fprintf(f, "]%s\n", ++i < m.size() ? "," : "");
+    }
+    std::fprintf(f, "}\n");
+    const bool ok = std::fclose(f) == 0;
+    if (ok) (void)std::rename(tmp.c_str(), path.c_str());
+    else (void)std::remove(tmp.c_str());
+}
+
+static bool tuned_lookup(const std::string &key, size_t *pref, size_t cap) {
     std::lock_guard<std::mutex> lk(g_tuned_mu);
     auto it = g_tuned.find(key);
-    if (it == g_tuned.end()) return false;
+    if (it == g_tuned.end()) {
+        auto file = read_tune_file(tune_cache_path());
+        auto ft = file.find(key);
+        if (ft == file.end()) return false;
+        for (size_t b : ft->second)
+            if (b < 4096 || b > cap) return false;    // (not a budget this device accepts)
+        it = g_tuned.insert(*ft).first;
+    }
     for (int i = 0; i < TG_COUNT; ++i) pref[i] = it->second[i];
     return true;
 }
@@ -423,6 +529,10 @@ static bool tuned_lookup(const std::string &key, size_t *pref) {
 static void tuned_store(const std::string &key, const size_t *pref) {
     std::lock_guard<std::mutex> lk(g_tuned_mu);
     g_tuned[key] = std::vector<size_t>(pref, pref + TG_COUNT);
+    const std::string path = tune_cache_path();
+    auto file = read_tune_file(path);
+    file[key] = g_tuned[key];
+    write_tune_file(path, file);
 }
 
 // cells: nb x 9 values (rows a_1, a_2, a_3 of each grid's cell)
@@ -443,7 +553,7 @@ static int plan_grids(vdwnl_ctx *c, int nb, const int32_t *shapes, const double 
     c->grad_mode = grad_mode;
     // tile budgets: a tuned set for this exact batch if one exists, else defaults
     c->plan_key = plan_key(c);
-    if (!tuned_lookup(c->plan_key, c->pref))
+    if (!tuned_lookup(c->plan_key, c->pref, c->lds_cap))
         for (auto &p : c->pref) p = std::min<size_t>(c->lds_cap, kLdsCap);
     for (auto &g : c->grids) size_tiles(c, g);
     c->shells.clear();
@@ -464,7 +574,9 @@ static int plan_grids(vdwnl_ctx *c, int nb, const int32_t *shapes, const double 
         g.shell_key = found;
     }
     c->have_grid = true;
-    return check_krange(c);
+    const int rc = check_krange(c);
+    refresh_image(c);
+    return rc;
 }
 
 // spline of the radial table at |G| for every pair: phi_ab(|G_s|), FP64,
@@ -556,16 +668,7 @@ static void xcd_blocks(std::vector<Tile> &t) {
     t.swap(out);
 }
 
-// Build every device structure for the current grids and table.
-static int prepare_device(vdwnl_ctx *c) {
-    if (c->device_ready) return VDWNL_OK;
-    if (!c->have_grid || !c->have_table) return fail(c, VDWNL_E_STATE, "grid and kernel table must both be set");
-    int krc = check_krange(c);
-    if (krc != VDWNL_OK) return krc;
-    if (c->device < 0) return fail(c, VDWNL_E_STATE, "host-only context");
-    hipError_t e = hipSetDevice(c->device);
-    if (e != hipSuccess) return hipfail(c, e, "hipSetDevice");
-    free_device(c);
+static int build_image(vdwnl_ctx *c, Image &im, bool keep_tables) {
     const bool dp = c->precision == 64;
     const size_t rs = dp ? 8 : 4, cs = 2 * rs;
 
@@ -738,13 +841,6 @@ static int prepare_device(vdwnl_ctx *c) {
             if (L.cnt > 0) c->launches[k].push_back(L);
         }
     }
-    // kernels whose tiles take more than 64 KB of LDS opt in to it now (not
-    // at launch time: launches may be captured into a graph)
-    for (int k = 0; k < KIND_COUNT; ++k)
-        for (const auto &L : c->launches[k]) {
-            LaunchArgs a{nullptr, nullptr, 0, L.lds, nullptr, nullptr, nullptr, nullptr, nullptr, L.general};
-            if ((e = launch_kind(k, L.lc, c->precision, a)) != hipSuccess) return hipfail(c, e, "kernel LDS limit");
-        }
     // twiddles
     c->tw_off.clear();
     std::vector<double> twd;
@@ -765,58 +861,133 @@ static int prepare_device(vdwnl_ctx *c) {
                 p->tw = it->second;
             }
         }
-    // allocations
-    c->work_bytes = off;
-    if ((e = hipMalloc(&c->work, std::max<size_t>(off, 256))) != hipSuccess) { c->work = nullptr; return hipfail(c, e, "hipMalloc workspace"); }
+    // the rest of the buffer
+    im.ws = off;
+    im.tiles.swap(all);
+    im.cols.swap(zcols);
+    im.twd.swap(twd);
+    im.tw32.assign(im.twd.begin(), im.twd.end());
     const size_t ng = c->grids.size();
-    if ((e = hipMalloc(&c->d_inst, ng * sizeof(InstDev))) != hipSuccess) return hipfail(c, e, "hipMalloc insts");
-    if ((e = hipHostMalloc((void **)&c->h_inst, ng * sizeof(InstDev), hipHostMallocDefault)) != hipSuccess) return hipfail(c, e, "hipHostMalloc insts");
-    if ((e = hipMalloc(&c->d_tiles, std::max<size_t>(all.size(), 1) * sizeof(Tile))) != hipSuccess) return hipfail(c, e, "hipMalloc tiles");
-    const size_t twbytes = (twd.size() / 2) * cs;
-    if ((e = hipMalloc(&c->d_tw, std::max<size_t>(twbytes, 16))) != hipSuccess) return hipfail(c, e, "hipMalloc twiddles");
-    if ((e = hipMalloc(&c->d_twd, std::max<size_t>((twd.size() / 2) * 16, 16))) != hipSuccess) return hipfail(c, e, "hipMalloc twiddles");
-    if ((e = hipMalloc(&c->d_consts, sizeof(Consts))) != hipSuccess) return hipfail(c, e, "hipMalloc consts");
-    if ((e = hipMalloc(&c->d_cols, std::max<size_t>(zcols.size(), 1) * sizeof(int2))) != hipSuccess)
-        return hipfail(c, e, "hipMalloc columns");
-    if (!zcols.empty() &&
-        (e = hipMemcpy(c->d_cols, zcols.data(), zcols.size() * sizeof(int2), hipMemcpyHostToDevice)) != hipSuccess)
-        return hipfail(c, e, "upload columns");
-    // four energies per grid: E_k, Delta E, E_x, E_c^LDA
-    if ((e = hipMalloc(&c->d_E, ng * 4 * sizeof(double))) != hipSuccess) return hipfail(c, e, "hipMalloc E");
-    if ((e = hipHostMalloc((void **)&c->h_E, ng * 4 * sizeof(double), hipHostMallocDefault)) != hipSuccess) return hipfail(c, e, "hipHostMalloc E");
-    // uploads
-    char *w = (char *)c->work;
+    im.off_tiles = align_up(off);
+    im.off_cols = align_up(im.off_tiles + std::max<size_t>(im.tiles.size(), 1) * sizeof(Tile));
+    im.off_tw = align_up(im.off_cols + std::max<size_t>(im.cols.size(), 1) * sizeof(int2));
+    im.off_twd = align_up(im.off_tw + std::max<size_t>(im.twd.size() / 2 * cs, 16));
+    im.off_consts = align_up(im.off_twd + std::max<size_t>(im.twd.size() / 2 * 16, 16));
+    im.off_inst = align_up(im.off_consts + sizeof(Consts));
+    im.off_E = align_up(im.off_inst + ng * sizeof(InstDev));
+    im.total = align_up(im.off_E + ng * 4 * sizeof(double));   // four energies per grid: E_k, Delta E, E_x, E_c^LDA
+    im.tabs.clear();
+    if (keep_tables)
+        for (const Shells &sh : c->shells) {
+            std::vector<double> tab;
+            shell_table(c, sh, tab);
+            std::vector<char> bytes(tab.size() * rs);
+            if (dp) {
+                std::memcpy(bytes.data(), tab.data(), bytes.size());
+            } else {
+                std::vector<float> tf(tab.begin(), tab.end());
+                std::memcpy(bytes.data(), tf.data(), bytes.size());
+            }
+            im.tabs.push_back(std::move(bytes));
+        }
+    return VDWNL_OK;
+}
+
+// Kernels whose tiles take more than 64 KB of LDS opt in to it (at planning:
+// launches may be captured into a graph).
+static int lds_optin(vdwnl_ctx *c) {
+    hipError_t e;
+    for (int k = 0; k < KIND_COUNT; ++k)
+        for (const auto &L : c->launches[k]) {
+            LaunchArgs a{nullptr, nullptr, 0, L.lds, nullptr, nullptr, nullptr, nullptr, nullptr, L.general};
+            if ((e = launch_kind(k, L.lc, c->precision, a)) != hipSuccess) return hipfail(c, e, "kernel LDS limit");
+            // (and the stage probes that stand in for the pass)
+            for (int pr : {PROBE_THETA_K, PROBE_U_K, PROBE_U}) {
+                const int pk = pr == PROBE_U ? (c->grad_mode ? KX_ASSEMBLE_FD : KX_ASSEMBLE) : KZ_MAIN;
+                if (k == pk && (e = launch_probe(pr, L.lc, c->precision, a, nullptr, 0)) != hipSuccess)
+                    return hipfail(c, e, "kernel LDS limit");
+            }
+        }
+    return VDWNL_OK;
+}
+
+// Device pointers of an image placed at base.
+static DevPtrs place(const Image &im, char *base) {
+    DevPtrs P;
+    P.base = base;
+    P.tiles = (Tile *)(base + im.off_tiles);
+    P.cols = (int2 *)(base + im.off_cols);
+    P.tw = base + im.off_tw;
+    P.twd = base + im.off_twd;
+    P.consts = (Consts *)(base + im.off_consts);
+    P.inst = (InstDev *)(base + im.off_inst);
+    P.E = (double *)(base + im.off_E);
+    return P;
+}
+
+// Copy an image's tables to the buffer at P.base (stream-ordered on st;
+// pageable host sources).  Kernel rows not kept in the image are computed
+// here, one shells entry at a time, and copied synchronously.
+static int upload_image(vdwnl_ctx *c, const Image &im, const DevPtrs &P, hipStream_t st) {
+    hipError_t e;
+    const bool dp = c->precision == 64;
+    const size_t rs = dp ? 8 : 4, cs = 2 * rs;
+    char *w = P.base;
     for (size_t i = 0; i < c->shells.size(); ++i) {
         const Shells &sh = c->shells[i];
-        if ((e = hipMemcpy(w + c->map_off[i], sh.map.data(), sh.map.size() * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess)
+        if ((e = hipMemcpyAsync(w + c->map_off[i], sh.map.data(), sh.map.size() * sizeof(int), hipMemcpyHostToDevice,
+                                st)) != hipSuccess)
             return hipfail(c, e, "upload shell map");
-        std::vector<double> tab;
-        shell_table(c, sh, tab);
-        if (dp) {
-            e = hipMemcpy(w + c->tab_off[i], tab.data(), tab.size() * 8, hipMemcpyHostToDevice);
+        if (i < im.tabs.size()) {
+            e = hipMemcpyAsync(w + c->tab_off[i], im.tabs[i].data(), im.tabs[i].size(), hipMemcpyHostToDevice, st);
         } else {
-            std::vector<float> tf(tab.begin(), tab.end());
-            e = hipMemcpy(w + c->tab_off[i], tf.data(), tf.size() * 4, hipMemcpyHostToDevice);
+            std::vector<double> tab;
+            shell_table(c, sh, tab);
+            if (dp) {
+                e = hipMemcpy(w + c->tab_off[i], tab.data(), tab.size() * 8, hipMemcpyHostToDevice);
+            } else {
+                std::vector<float> tf(tab.begin(), tab.end());
+                e = hipMemcpy(w + c->tab_off[i], tf.data(), tf.size() * 4, hipMemcpyHostToDevice);
+            }
         }
         if (e != hipSuccess) return hipfail(c, e, "upload shell table");
     }
+    const size_t twn = im.twd.size() / 2;
     if (dp) {
-        e = hipMemcpy(c->d_tw, twd.data(), twbytes, hipMemcpyHostToDevice);
+        e = hipMemcpyAsync(P.tw, im.twd.data(), twn * cs, hipMemcpyHostToDevice, st);
     } else {
-        std::vector<float> tf(twd.begin(), twd.end());
-        e = hipMemcpy(c->d_tw, tf.data(), twbytes, hipMemcpyHostToDevice);
+        e = hipMemcpyAsync(P.tw, im.tw32.data(), twn * cs, hipMemcpyHostToDevice, st);
     }
     if (e != hipSuccess) return hipfail(c, e, "upload twiddles");
-    if ((e = hipMemcpy(c->d_twd, twd.data(), twd.size() * 8, hipMemcpyHostToDevice)) != hipSuccess)
+    if ((e = hipMemcpyAsync(P.twd, im.twd.data(), twn * 16, hipMemcpyHostToDevice, st)) != hipSuccess)
         return hipfail(c, e, "upload twiddles");
-    if ((e = hipMemcpy(c->d_tiles, all.data(), all.size() * sizeof(Tile), hipMemcpyHostToDevice)) != hipSuccess)
+    if (!im.tiles.empty() &&
+        (e = hipMemcpyAsync(P.tiles, im.tiles.data(), im.tiles.size() * sizeof(Tile), hipMemcpyHostToDevice, st)) !=
+            hipSuccess)
         return hipfail(c, e, "upload tiles");
-    if ((e = hipMemcpy(c->d_consts, &c->consts, sizeof(Consts), hipMemcpyHostToDevice)) != hipSuccess)
+    if (!im.cols.empty() &&
+        (e = hipMemcpyAsync(P.cols, im.cols.data(), im.cols.size() * sizeof(int2), hipMemcpyHostToDevice, st)) !=
+            hipSuccess)
+        return hipfail(c, e, "upload columns");
+    if ((e = hipMemcpyAsync(P.consts, &c->consts, sizeof(Consts), hipMemcpyHostToDevice, st)) != hipSuccess)
         return hipfail(c, e, "upload consts");
+    return VDWNL_OK;
+}
+
+// The per-grid entries of the instance table for a buffer at base (the
+// density and potential pointers and the functional switch are kept).
+static void fill_insts(vdwnl_ctx *c, char *w, InstDev *out) {
+    const size_t ng = c->grids.size();
     for (size_t gi = 0; gi < ng; ++gi) {
         const Grid &g = c->grids[gi];
-        InstDev &I = c->h_inst[gi];
+        InstDev &I = out[gi];
+        const void *n_keep = I.n;
+        void *v_keep = I.v;
+        const int sl_keep = I.semilocal;
         std::memset(&I, 0, sizeof(I));
+        I.n = n_keep;
+        I.v = v_keep;
+        I.semilocal = sl_keep;
         I.n1 = g.s[0]; I.n2 = g.s[1]; I.n3 = g.s[2]; I.n3h = g.s[2] / 2 + 1;
         I.h1 = g.s[0] / 2 + 1; I.h2 = g.s[1] / 2 + 1;
         I.p1 = g.p1; I.p2 = g.p2; I.p3 = g.p3;
@@ -849,6 +1020,47 @@ static int prepare_device(vdwnl_ctx *c) {
         I.part_sl = (double *)(w + g.off_sl);
         I.n_ek = g.n_ek; I.n_de = g.n_de;
     }
+}
+
+// Build every device structure for the current grids and table in the
+// context's own allocation.
+static int prepare_device(vdwnl_ctx *c) {
+    if (c->device_ready) return VDWNL_OK;
+    if (!c->have_grid || !c->have_table) return fail(c, VDWNL_E_STATE, "grid and kernel table must both be set");
+    int krc = check_krange(c);
+    if (krc != VDWNL_OK) return krc;
+    if (c->device < 0) return fail(c, VDWNL_E_STATE, "host-only context");
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hipfail(c, e, "hipSetDevice");
+    free_device(c);
+    Image tmp;
+    const Image *im = &c->img;
+    if (!c->img_valid) {
+        int rc = build_image(c, tmp, false);
+        if (rc != VDWNL_OK) return rc;
+        im = &tmp;
+    }
+    int rc = lds_optin(c);
+    if (rc != VDWNL_OK) return rc;
+    const size_t ng = c->grids.size();
+    c->work_bytes = im->total;
+    if ((e = hipMalloc(&c->work, std::max<size_t>(im->total, 256))) != hipSuccess) {
+        c->work = nullptr;
+        return hipfail(c, e, "hipMalloc workspace");
+    }
+    if ((e = hipHostMalloc((void **)&c->h_inst, ng * sizeof(InstDev), hipHostMallocDefault)) != hipSuccess) {
+        c->h_inst = nullptr;
+        return hipfail(c, e, "hipHostMalloc insts");
+    }
+    if ((e = hipHostMalloc((void **)&c->h_E, ng * 4 * sizeof(double), hipHostMallocDefault)) != hipSuccess) {
+        c->h_E = nullptr;
+        return hipfail(c, e, "hipHostMalloc E");
+    }
+    c->dp = place(*im, (char *)c->work);
+    if ((rc = upload_image(c, *im, c->dp, 0)) != VDWNL_OK) return rc;
+    if ((e = hipStreamSynchronize(0)) != hipSuccess) return hipfail(c, e, "upload");
+    std::memset(c->h_inst, 0, ng * sizeof(InstDev));
+    fill_insts(c, (char *)c->work, c->h_inst);
     c->device_ready = true;
     return VDWNL_OK;
 }
@@ -860,16 +1072,16 @@ static int prepare_device(vdwnl_ctx *c) {
 // passes go to a stream of its own, forked from st and joined back before
 // the reduction: the groups' chains are independent, so a pass of one group
 // can run beside a pass of another.  Otherwise the passes go in order on st.
-static int enqueue(vdwnl_ctx *c, int nb, hipStream_t st, bool chains = false) {
+static int enqueue(vdwnl_ctx *c, const DevPtrs &P, const InstDev *hinst, double *hE, int nb, hipStream_t st,
+                   bool chains = false) {
     hipError_t e;
-    if ((e = hipMemcpyAsync(c->d_inst, c->h_inst, nb * sizeof(InstDev), hipMemcpyHostToDevice, st)) != hipSuccess)
+    if ((e = hipMemcpyAsync(P.inst, hinst, nb * sizeof(InstDev), hipMemcpyHostToDevice, st)) != hipSuccess)
         return hipfail(c, e, "upload instance table");
     if (c->timing) (void)hipEventRecord(c->ev[0], st);
     const int *order;
     const int npass = pass_order(c->grad_mode, &order);
     auto launch = [&](const vdwnl_ctx::Launch &L, hipStream_t s) -> int {
-        LaunchArgs a{c->d_inst, c->d_tiles + L.off, L.cnt, L.lds, c->d_consts, c->d_tw, c->d_twd, s, c->d_cols,
-                     L.general};
+        LaunchArgs a{P.inst, P.tiles + L.off, L.cnt, L.lds, P.consts, P.tw, P.twd, s, P.cols, L.general};
         const hipError_t le = launch_kind(L.kind, L.lc, c->precision, a);
         return le == hipSuccess ? VDWNL_OK : hipfail(c, le, "kernel launch");
     };
@@ -896,9 +1108,9 @@ static int enqueue(vdwnl_ctx *c, int nb, hipStream_t st, bool chains = false) {
             if (c->timing) (void)hipEventRecord(c->ev[i + 1], st);
         }
     }
-    if ((e = launch_reduce(c->d_inst, nb, c->d_E, st)) != hipSuccess) return hipfail(c, e, "reduce launch");
+    if ((e = launch_reduce(P.inst, nb, P.E, st)) != hipSuccess) return hipfail(c, e, "reduce launch");
     if (c->timing) (void)hipEventRecord(c->ev[npass + 1], st);
-    if ((e = hipMemcpyAsync(c->h_E, c->d_E, nb * 4 * sizeof(double), hipMemcpyDeviceToHost, st)) != hipSuccess)
+    if ((e = hipMemcpyAsync(hE, P.E, nb * 4 * sizeof(double), hipMemcpyDeviceToHost, st)) != hipSuccess)
         return hipfail(c, e, "copy energies");
     return VDWNL_OK;
 }
@@ -926,7 +1138,7 @@ static int capture(vdwnl_ctx *c, int nb) {
     }
     if ((e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed)) != hipSuccess)
         return hipfail(c, e, "hipStreamBeginCapture");
-    const int rc = enqueue(c, nb, c->cap_stream, chains);
+    const int rc = enqueue(c, c->dp, c->h_inst, c->h_E, nb, c->cap_stream, chains);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(c->cap_stream, &g);
     if (rc != VDWNL_OK) {
@@ -980,11 +1192,12 @@ static int run(vdwnl_ctx *c, int nb, const void *const *n_ptrs, void *const *v_p
         if ((e = hipGraphLaunch(c->gexec, st)) != hipSuccess) return hipfail(c, e, "hipGraphLaunch");
     } else {
         // per-pass timing: eager launches bracketed by events
-        if ((rc = enqueue(c, nb, st)) != VDWNL_OK) return rc;
+        if ((rc = enqueue(c, c->dp, c->h_inst, c->h_E, nb, st)) != VDWNL_OK) return rc;
     }
+    c->evaluated = true;
     if (E_dev) {
         // (E_k, Delta E) of each grid: the first two of its four energies
-        if ((e = hipMemcpy2DAsync(E_dev, 2 * sizeof(double), c->d_E, 4 * sizeof(double), 2 * sizeof(double), nb,
+        if ((e = hipMemcpy2DAsync(E_dev, 2 * sizeof(double), c->dp.E, 4 * sizeof(double), 2 * sizeof(double), nb,
                                   hipMemcpyDeviceToDevice, st)) != hipSuccess)
             return hipfail(c, e, "copy energies to the device buffer");
         if (!c->done_ev && (e = hipEventCreateWithFlags(&c->done_ev, hipEventDisableTiming)) != hipSuccess)
@@ -1011,6 +1224,91 @@ static int run(vdwnl_ctx *c, int nb, const void *const *n_ptrs, void *const *v_p
         c->timed_calls++;
     }
     return VDWNL_OK;
+}
+
+// Parity probe of one stage of grid `target`: the passes of the last
+// evaluation (its instance table: the same density buffers) up to the stage,
+// launched one by one on st, then the probe in place of the pass that holds
+// the stage (theta: the theta pass; the spectra c and u = phi c: the fused
+// axis-1 pass; u(r): the assembly pass).  Nothing after the probe runs: the
+// caller's potential buffers are not written.
+static int probe_stage(vdwnl_ctx *c, int stage, int target, void *dst, hipStream_t st) {
+    hipError_t e;
+    const int nb = (int)c->grids.size();
+    if ((e = hipMemcpyAsync(c->dp.inst, c->h_inst, nb * sizeof(InstDev), hipMemcpyHostToDevice, st)) != hipSuccess)
+        return hipfail(c, e, "upload instance table");
+    const int *order;
+    const int npass = pass_order(c->grad_mode, &order);
+    int stop;
+    switch (stage) {
+        case VDWNL_STAGE_THETA: stop = KX_THETA; break;
+        case VDWNL_STAGE_THETA_K: case VDWNL_STAGE_U_K: stop = KZ_MAIN; break;
+        default: stop = c->grad_mode ? KX_ASSEMBLE_FD : KX_ASSEMBLE; break;
+    }
+    auto args = [&](const vdwnl_ctx::Launch &L) {
+        return LaunchArgs{c->dp.inst, c->dp.tiles + L.off, L.cnt, L.lds, c->dp.consts, c->dp.tw, c->dp.twd, st, c->dp.cols,
+                          L.general};
+    };
+    for (int i = 0; i < npass && order[i] != stop; ++i)
+        for (const auto &L : c->launches[order[i]])
+            if ((e = launch_kind(L.kind, L.lc, c->precision, args(L))) != hipSuccess) return hipfail(c, e, "kernel launch");
+    const int probe = stage == VDWNL_STAGE_THETA ? PROBE_THETA
+                      : stage == VDWNL_STAGE_THETA_K ? PROBE_THETA_K
+                      : stage == VDWNL_STAGE_U_K ? PROBE_U_K : PROBE_U;
+    for (const auto &L : c->launches[stop])
+        if ((e = launch_probe(probe, L.lc, c->precision, args(L), dst, target)) != hipSuccess)
+            return hipfail(c, e, "probe launch");
+    if (stage == VDWNL_STAGE_THETA_K || stage == VDWNL_STAGE_U_K) {
+        const Grid &g = c->grids[target];
+        const size_t cs = c->precision == 64 ? 16 : 8;
+        if ((e = hipMemcpyAsync(dst, (char *)c->work + g.off_spec, g.nhalf() * kNQ * cs, hipMemcpyDeviceToDevice, st)) !=
+            hipSuccess)
+            return hipfail(c, e, "probe copy");
+    }
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return hipfail(c, e, "stream synchronize");
+    return VDWNL_OK;
+}
+
+// Plans whose whole device image stays below this keep their host image with
+// the kernel rows (the first evaluation then only copies it).
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static std::mutex g_stamp_mu;
+static uint64_t g_stamp = 0;
+
+// The plan's host image, rebuilt by every set-up call that changes the plan,
+// the table or the tiles; kept (with its kernel rows) only when it is small.
+static void refresh_image(vdwnl_ctx *c) {
+    c->img = Image();
+    c->img_valid = false;
+    c->img_need = 0;
+    {
+        std::lock_guard<std::mutex> lk(g_stamp_mu);
+        c->plan_stamp = ++g_stamp;
+    }
+    if (!c->have_grid || !c->have_table) return;
+    for (auto &sh : c->shells)
+        if (sh.gmax > (c->nk - 1) * c->dk * (1.0 + 1e-12)) return;
+    Image probe;
+    if (build_image(c, probe, false) != VDWNL_OK) return;
+    c->img_need = probe.total;
+    if (probe.total > kScratchBytes) return;
+    if (build_image(c, c->img, true) != VDWNL_OK) return;
+    c->img_valid = true;
+}
+
+// Logarithmic q mesh of the interpolation: q_1 = q1, q_nq = q_c, increments
+// growing by the factor lambda, (q_{a+1} - q_a) = lambda (q_a - q_{a-1}).
+static void log_qmesh(int nq, double q1, double qc, double lambda, double *q) {
+    std::vector<double> d(nq - 1);
+    double p = 1.0, tot = 0.0;
+    for (int i = 0; i < nq - 1; ++i) { d[i] = p; tot += p; p *= lambda; }
+    double acc = 0.0;
+    q[0] = q1;
+    for (int i = 1; i < nq - 1; ++i) {
+        acc += d[i - 1];
+        q[i] = q1 + (qc - q1) * (acc / tot);
+    }
+    q[nq - 1] = qc;
 }
 
 }  // namespace vdwnl
@@ -1058,8 +1356,10 @@ int vdwnl_create(vdwnl_ctx **out, int device) {
     c->device = device;
     if (device >= 0) {
         hipDeviceProp_t prop;
-        if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.sharedMemPerBlock > 0)
-            c->lds_cap = std::min<size_t>(prop.sharedMemPerBlock, 160 * 1024);
+        if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+            if (prop.sharedMemPerBlock > 0) c->lds_cap = std::min<size_t>(prop.sharedMemPerBlock, 160 * 1024);
+            c->arch = prop.gcnArchName;
+        }
     }
     std::memset(&c->consts, 0, sizeof(Consts));
     *out = c;
@@ -1152,7 +1452,9 @@ int vdwnl_set_kernel_table(vdwnl_ctx *ctx, int32_t nq, const double *qmesh, doub
     for (int m = 1; m <= kMaxMc; ++m) k.invm[m] = 1.0 / (double)m;
     ctx->have_table = true;
     free_device(ctx);
-    return check_krange(ctx);
+    const int rc = check_krange(ctx);
+    refresh_image(ctx);
+    return rc;
 }
 
 int vdwnl_energy_potential(vdwnl_ctx *ctx, const void *n_dev, void *v_dev, double *E_out, void *stream) {
@@ -1191,6 +1493,28 @@ int vdwnl_debug_field(vdwnl_ctx *ctx, int32_t inst, int32_t which, void *dst, vo
     hipError_t e = hipMemcpyAsync(dst, (char *)ctx->work + off, bytes, hipMemcpyDeviceToDevice, (hipStream_t)stream);
     if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
     return e == hipSuccess ? VDWNL_OK : hipfail(ctx, e, "debug copy");
+}
+
+int vdwnl_debug_stage(vdwnl_ctx *ctx, int32_t inst, int32_t stage, void *dst, void *stream) {
+    if (!ctx || !dst) return VDWNL_E_ARG;
+    if (stage < VDWNL_STAGE_THETA || stage > VDWNL_STAGE_U) return fail(ctx, VDWNL_E_ARG, "unknown stage");
+    int rc = wait_pending(ctx);
+    if (rc != VDWNL_OK) return rc;
+    if (!ctx->device_ready || !ctx->evaluated || inst < 0 || inst >= (int32_t)ctx->grids.size())
+        return fail(ctx, VDWNL_E_STATE, "no evaluation of that grid yet");
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hipfail(ctx, e, "hipSetDevice");
+    return probe_stage(ctx, stage, inst, dst, (hipStream_t)stream);
+}
+
+int vdwnl_log_qmesh(int32_t nq, double q1, double q_c, double lambda, double *q_out) {
+    if (!q_out || nq < 2 || nq > 4096) return VDWNL_E_ARG;
+    if (!(q1 > 0.0) || !(q_c > q1) || !std::isfinite(q_c) || !(lambda >= 1.0) || !std::isfinite(lambda))
+        return VDWNL_E_ARG;
+    // (lambda^(nq-2) must stay finite)
+    if ((nq - 2) * std::log(lambda) > 700.0) return VDWNL_E_ARG;
+    log_qmesh(nq, q1, q_c, lambda, q_out);
+    return VDWNL_OK;
 }
 
 int vdwnl_set_graph(vdwnl_ctx *ctx, int32_t on) {
@@ -1234,6 +1558,7 @@ int vdwnl_autotune(vdwnl_ctx *ctx, int32_t nb, const void *const *n_ptrs, void *
     for (size_t b : {16384, 24576, 32768, 49152, 65536, 98304, 131072})
         if (b <= ctx->lds_cap) cand.push_back(b);
     const bool timing0 = ctx->timing;
+    ctx->img_valid = false;     // (the candidates' tiles differ from the image's)
     std::vector<std::vector<double>> t(cand.size(), std::vector<double>(KIND_COUNT, 0.0));
     int rc = VDWNL_OK;
     std::vector<double> E((size_t)nb * 2);
@@ -1268,6 +1593,7 @@ int vdwnl_autotune(vdwnl_ctx *ctx, int32_t nb, const void *const *n_ptrs, void *
     for (int gi = 0; gi < TG_COUNT; ++gi) ctx->pref[gi] = best[gi];
     for (auto &g : ctx->grids) size_tiles(ctx, g);
     free_device(ctx);
+    refresh_image(ctx);
     vdwnl_set_timing(ctx, timing0 ? 1 : 0);
     if (rc != VDWNL_OK) return rc;
     tuned_store(ctx->plan_key, ctx->pref);
@@ -1284,6 +1610,7 @@ int vdwnl_set_tiling(vdwnl_ctx *ctx, int32_t ngroups, const int64_t *lds_budget)
     for (int i = 0; i < TG_COUNT; ++i) ctx->pref[i] = (size_t)lds_budget[i];
     for (auto &g : ctx->grids) size_tiles(ctx, g);
     free_device(ctx);
+    refresh_image(ctx);
     return VDWNL_OK;
 }
 

@@ -124,7 +124,14 @@ struct LaunchArgs {
     int general;             // the launch's grids have non-orthogonal cells (packed shell rows)
 };
 
+// Parity probes of the stages (the stage values of vdwnl_debug_stage): the
+// launch args of the pass the probe replaces (the theta pass for THETA, the
+// fused axis-1 pass for THETA_K and U_K, the assembly pass for U); dst the
+// probe's output (THETA, U), target the grid whose tiles run.
+enum ProbeKind { PROBE_THETA = 0, PROBE_THETA_K = 1, PROBE_U_K = 2, PROBE_U = 3 };
+
 hipError_t launch_kind(int kind, int len_class, int precision, const LaunchArgs &a);
+hipError_t launch_probe(int probe, int len_class, int precision, const LaunchArgs &a, void *dst, int target);
 hipError_t launch_reduce(const InstDev *insts, int ninst, double *E, hipStream_t stream);
 
 }  // namespace vdwnl

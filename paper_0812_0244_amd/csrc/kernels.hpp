@@ -1,0 +1,1270 @@
+// HIP kernels of libvdwnl (gfx950), as templates in the working precision T;
+// kernels_f32.hip and kernels_f64.hip instantiate them (compiled in parallel).  One evaluation of E_c^nl and v_nl is
+// fourteen passes over the grid with the spectral gradient, seven with finite
+// differences; each pass is one launch that covers every grid of the batch (a
+// workgroup reads its work item from a tile list).
+//
+// The 20 theta / u fields (the bulk of the traffic), the local chain and the
+// divergence of w are computed in the working precision T (float or double).
+// The spectral gradient of n always runs in FP64: the gradient term of v_nl
+// multiplies grad n by a factor that grows as 1/n, so FP32 rounding of a
+// spectral grad n in the low-density regions would dominate the error of v.
+//
+// Fields are transformed with three 1-D FFT passes: along axis 3 (the
+// contiguous one, real-to-complex by pairing two real lines into one complex
+// line), axis 2 and axis 1.  Spectra keep all components of one k point
+// together ([N1][N2][N3/2+1][V] complex), so the axis-1 pass of the 20 theta
+// spectra holds every component of its k points in LDS and can apply the
+// per-k kernel matrix between its forward and inverse FFTs.
+#pragma once
+
+#include "common.hpp"
+#include "fft_fast.hpp"
+#include "tile_io.hpp"
+
+namespace vdwnl {
+
+// ---------------------------------------------------------------- helpers
+
+// Elementary functions of the local chain.  FP64: the device library.  FP32
+// (arguments positive and normal there): built on the hardware base-2
+// logarithm and exponential (v_log_f32, v_exp_f32), square root and
+// reciprocal, each within about an ulp, in a few instructions where the
+// library's general versions (special values, denormals, extra-precise
+// arithmetic) take tens to a hundred.
+__device__ __forceinline__ float hw_log(float x) { return __builtin_amdgcn_logf(x) * 0.693147180559945309f; }
+__device__ __forceinline__ float hw_exp(float x) { return __builtin_amdgcn_exp2f(x * 1.44269504088896341f); }
+template <typename T> __device__ __forceinline__ T dev_cbrt(T x);
+template <> __device__ __forceinline__ float dev_cbrt(float x) {
+    // 2^(log2(x)/3), then one Newton step for r^3 = x
+    const float r = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(x) * (1.0f / 3.0f));
+    return r + (x * __builtin_amdgcn_rcpf(r * r) - r) * (1.0f / 3.0f);
+}
+template <> __device__ __forceinline__ double dev_cbrt(double x) { return cbrt(x); }
+template <typename T> __device__ __forceinline__ T dev_sqrt(T x);
+template <> __device__ __forceinline__ float dev_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+template <> __device__ __forceinline__ double dev_sqrt(double x) { return sqrt(x); }
+// 1/x: the hardware reciprocal in FP32 (within 1 ulp), a division in FP64
+template <typename T> __device__ __forceinline__ T rcp(T x);
+template <> __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+// FP64: the hardware estimate refined by two Newton-Raphson steps
+// r <- r + r (1 - x r) (each doubles the correct bits; within an ulp or so
+// of 1/x for normal x, against about fifteen instructions for a division)
+template <> __device__ __forceinline__ double rcp(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+template <typename T> __device__ __forceinline__ T dev_log1p(T x);
+template <> __device__ __forceinline__ float dev_log1p(float x) {
+    // log(u) x / (u - 1) with u = 1 + x as rounded: the quotient restores what
+    // the rounding of 1 + x lost (Goldberg 1991, Theorem 4); x itself when u = 1
+    const float u = 1.0f + x, d = u - 1.0f;
+    return d == 0.0f ? x : hw_log(u) * (x * __builtin_amdgcn_rcpf(d));
+}
+template <> __device__ __forceinline__ double dev_log1p(double x) { return log1p(x); }
+template <typename T> __device__ __forceinline__ T dev_exp(T x);
+template <> __device__ __forceinline__ float dev_exp(float x) { return hw_exp(x); }
+template <> __device__ __forceinline__ double dev_exp(double x) { return exp(x); }
+template <typename T> __device__ __forceinline__ T dev_expm1(T x);
+template <> __device__ __forceinline__ float dev_expm1(float x) {
+    // |x| < 1/2: x (1 + x/2! + ... + x^8/9!) (Taylor; the rest is below 1e-9
+    // relative); elsewhere exp(x) - 1, where no cancellation can hurt
+    float p = 1.0f / 362880.0f;
+    p = p * x + 1.0f / 40320.0f;
+    p = p * x + 1.0f / 5040.0f;
+    p = p * x + 1.0f / 720.0f;
+    p = p * x + 1.0f / 120.0f;
+    p = p * x + 1.0f / 24.0f;
+    p = p * x + 1.0f / 6.0f;
+    p = p * x + 0.5f;
+    p = p * x + 1.0f;
+    return fabsf(x) < 0.5f ? x * p : hw_exp(x) - 1.0f;
+}
+template <> __device__ __forceinline__ double dev_expm1(double x) { return expm1(x); }
+
+// signed frequency index of position k on an axis of N points, 0 at Nyquist
+__device__ __forceinline__ int freq_nz(int k, int N) {
+    int m = (k <= N / 2) ? k : k - N;
+    if ((N & 1) == 0 && k == N / 2) m = 0;
+    return m;
+}
+__device__ __forceinline__ int freq_abs(int k, int N) { return k <= N - k ? k : N - k; }
+
+// Cartesian components of G = m1 b_1 + m2 b_2 + m3 b_3 (the frequencies with
+// Nyquist taken as zero); in an orthorhombic cell the off-diagonal b_c,x are
+// zero and each component is the single product m_c b_c,c exactly.
+template <typename T>
+__device__ __forceinline__ void cart_g(const InstDev &I, double m1, double m2, double m3, T &gx, T &gy, T &gz) {
+    gx = (T)(m1 * I.B[0][0] + m2 * I.B[1][0] + m3 * I.B[2][0]);
+    gy = (T)(m1 * I.B[0][1] + m2 * I.B[1][1] + m3 * I.B[2][1]);
+    gz = (T)(m1 * I.B[0][2] + m2 * I.B[1][2] + m3 * I.B[2][2]);
+}
+
+// Sum over the workgroup in a fixed order; result valid in thread 0.
+__device__ __forceinline__ double block_sum(double v) {
+    __shared__ double red[kThreads / 64];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) red[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < kThreads / 64; ++w) s += red[w];
+    __syncthreads();
+    return s;
+}
+
+// ---------------------------------------------------------------- q0 and the spline basis
+
+// q0(n, |grad n|^2) before saturation and its partials (Dion et al. form,
+// Perdew-Wang 1992 correlation), then the saturation of Eq. (Sat).
+template <typename T, bool DERIV>
+struct LocalQ {
+    T q0, Q, dqdn, ndqds;    // ndqds = n dq0/dsigma (dq0/dsigma alone overflows FP32 at small n)
+    T kf, eps, deps_dn;      // k_F, the LDA eps_c and (DERIV) d eps_c/dn
+
+    __device__ __forceinline__ void eval(T n, T sigma, double qc, double iqc, int mc, const T *invm) {
+        const T pi = (T)3.14159265358979323846;
+        const T A = (T)0.031091, a1 = (T)0.21370;
+        const T b1 = (T)7.5957, b2 = (T)3.5876, b3 = (T)1.6382, b4 = (T)0.49294;
+        const T zg = (T)(0.8491 / 36.0);   // -Z_ab / 36
+        // k_F = (3 pi^2 n)^(1/3), r_s = (3 / (4 pi n))^(1/3): one cube root
+        const T cn = dev_cbrt<T>(n), icn = rcp<T>(cn), in = rcp<T>(n);
+        kf = (T)3.0936677262801355 * cn;                  // (3 pi^2)^(1/3)
+        const T rs = (T)0.6203504908994001 * icn;         // (3 / (4 pi))^(1/3)
+        const T srs = dev_sqrt<T>(rs);
+        const T P = b1 * srs + b2 * rs + b3 * rs * srs + b4 * rs * rs;
+        const T iP2A = rcp<T>((T)2 * A * P);
+        const T L = dev_log1p<T>(iP2A);
+        eps = (T)-2 * A * ((T)1 + a1 * rs) * L;
+        // sigma / (k_F n^2) as ((sigma / n) / n) / k_F: finite in FP32 wherever
+        // |grad n| / n is, down to n_min (1 / (k_F n^2) alone is not below 1e-17)
+        const T ikf = rcp<T>(kf);
+        const T grad_term = zg * ((sigma * in) * in) * ikf;
+        const T qraw = kf - ((T)4 * pi / (T)3) * eps + grad_term;
+        if (DERIV) {
+            const T dP = (T)0.5 * b1 * rcp<T>(srs) + b2 + (T)1.5 * b3 * srs + (T)2 * b4 * rs;
+            const T deps_drs = (T)-2 * A * a1 * L + (T)2 * A * ((T)1 + a1 * rs) * dP * rcp<T>(P * ((T)2 * A * P + (T)1));
+            deps_dn = deps_drs * (-rs * in * ((T)1 / (T)3));
+            dqdn = kf * in * ((T)1 / (T)3) - ((T)4 * pi / (T)3) * deps_dn - ((T)7 / (T)3) * grad_term * in;
+            ndqds = zg * ikf * in;
+        }
+        // h(x, x_c) = x_c (1 - exp(-S)), S = sum_{m<=m_c} (x/x_c)^m / m (Horner),
+        // dh/dx = exp(-S) sum_{m<m_c} (x/x_c)^m.  1 - exp(-S) as -expm1(-S)
+        // keeps its relative accuracy for small S.  S from 80 up (exp(-S) <
+        // 2e-35), or overflowing, saturates: h = x_c, dh/dx = 0.  Below that
+        // the derivative series stays under 80 m_c^2: no overflow in FP32.
+        const T y = qraw * (T)iqc;
+        T S = (T)0;
+        for (int m = mc; m >= 1; --m) S = S * y + invm[m];
+        S *= y;
+        if (!(S < (T)80)) {
+            q0 = (T)qc;
+            Q = (T)0;
+            if (DERIV) { dqdn = (T)0; ndqds = (T)0; }   // (their products with Q vanish)
+        } else {
+            q0 = (T)(-qc) * dev_expm1<T>(-S);
+            if (DERIV) {
+                T D = (T)0;
+                for (int m = mc - 1; m >= 0; --m) D = D * y + (T)1;
+                Q = dev_exp<T>(-S) * D;
+            } else {
+                Q = (T)0;
+            }
+        }
+    }
+};
+
+// The semilocal terms of Eq. (Exc) at one point, from n, sigma = |grad n|^2
+// and the k_F, eps_c (and d eps_c/dn) of LocalQ.  Exchange: the revPBE GGA,
+// e_x = e_u F_x(s) with e_u = -3 k_F n / (4 pi), s^2 = sigma / (4 k_F^2 n^2),
+// F_x = 1 + kappa - kappa / (1 + mu s^2 / kappa), kappa = 1.245,
+// mu = 0.066725 pi^2 / 3; correlation: the LDA e_c = n eps_c.
+template <typename T>
+struct Semilocal {
+    T ex, ec;                // energies per volume
+    T dn, ds;                // d(e_x + e_c)/dn, d e_x/dsigma (DERIV)
+    template <bool DERIV>
+    __device__ __forceinline__ void eval(T n, T sigma, const LocalQ<T, DERIV> &lq) {
+        const T kappa = (T)1.245, mu = (T)(0.066725 * 3.14159265358979323846 * 3.14159265358979323846 / 3.0);
+        const T in = rcp<T>(n), ikf = rcp<T>(lq.kf);
+        const T eu = (T)(-3.0 / (4.0 * 3.14159265358979323846)) * lq.kf * n;
+        // s^2 = sigma / (4 k_F^2 n^2), ordered to stay finite at small n; where
+        // it still overflows (or is huge) F_x has reached 1 + kappa
+        const T s2 = ((sigma * in) * in) * ((T)0.25 * ikf * ikf);
+        const bool flat = !(s2 < (T)1e30);
+        const T iden = flat ? (T)0 : rcp<T>((T)1 + (mu / kappa) * s2);
+        const T fx = (T)1 + kappa - kappa * iden;
+        ex = eu * fx;
+        ec = n * lq.eps;
+        if (DERIV) {
+            const T dfx = mu * iden * iden;                  // dF_x / ds^2
+            const T dfx_s2 = flat ? (T)0 : dfx * s2;
+            // d e_u/dn = (4/3) e_u / n, d s^2/dn = -(8/3) s^2 / n;
+            // d e_x/dsigma = e_u F_x' / (4 k_F^2 n^2) = -3 F_x' / (16 pi k_F n)
+            dn = ((T)(4.0 / 3.0) * fx - (T)(8.0 / 3.0) * dfx_s2) * eu * in + lq.eps + n * lq.deps_dn;
+            ds = (T)(-3.0 / (16.0 * 3.14159265358979323846)) * dfx * rcp<T>(lq.kf * n);
+        }
+    }
+};
+
+// Natural cubic cardinal splines p_a(q) on the q mesh (Eq. fofx and the text
+// after it), M[j][a] (second derivative at q_j of p_a) in LDS.  On the
+// interval j (a = (q_{j+1} - q)/h, b = 1 - a)
+//   p_a  = a d_aj + b d_a,j+1 + ((a^3 - a) M[j][a] + (b^3 - b) M[j+1][a]) h^2/6
+//   p_a' = (d_a,j+1 - d_aj)/h + ((1 - 3a^2) M[j][a] + (3b^2 - 1) M[j+1][a]) h/6
+// and below q_1 the linear continuation p_a(q_1) + (q - q_1) p_a'(q_1).  Both
+// are written p_a = A0 d_aj + A1 d_a,j+1 + C0 M[j][a] + C1 M[j+1][a] and
+// p_a' = B0 d_aj + B1 d_a,j+1 + D0 M[j][a] + D1 M[j+1][a] with per-point
+// scalars, so sums over a reduce to two dot products with rows of M.
+template <typename T>
+struct SplineW {
+    int j;
+    T A0, A1, C0, C1;
+    T B0, B1, D0, D1;
+
+    __device__ __forceinline__ void locate(T q0, const T *qm, int nq) {
+        // one path for every case (the struct then stays in registers)
+        const bool below = q0 < qm[0];
+        int lo = 0, hi = nq - 1;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (qm[mid] <= q0) lo = mid; else hi = mid;
+        }
+        j = lo;
+        const T ql = qm[lo], qh = qm[lo + 1];
+        const T h = qh - ql, ih = rcp<T>(h), h6 = h * (T)(1.0 / 6.0);
+        const T a = below ? (T)1 : (qh - q0) * ih;
+        const T b = (T)1 - a;
+        const T dq = below ? q0 - ql : (T)0;
+        B0 = -ih;
+        B1 = ih;
+        D0 = ((T)1 - (T)3 * a * a) * h6;
+        D1 = ((T)3 * b * b - (T)1) * h6;
+        A0 = a + dq * B0;
+        A1 = b + dq * B1;
+        C0 = (a * a * a - a) * h * h6 + dq * D0;
+        C1 = (b * b * b - b) * h * h6 + dq * D1;
+    }
+};
+
+// q mesh, spline second derivatives and 1/m into LDS (in T); all loads are
+// issued before any store (indices clamped, the stores guarded)
+template <typename T>
+__device__ __forceinline__ void load_consts(const Consts *cst, T *qm, T *Mm, T *invm) {
+    static_assert(kNQ * kNQ <= 2 * kThreads && kNQ <= kThreads && kMaxMc < kThreads, "one or two steps each");
+    const int i = threadIdx.x, i2 = threadIdx.x + kThreads;
+    const gptr<const double> q = gld(cst->q), M = gld(cst->M), im = gld(cst->invm);
+    const double a = q[min(i, kNQ - 1)], b = M[min(i, kNQ * kNQ - 1)], b2 = M[min(i2, kNQ * kNQ - 1)];
+    const double c = im[min(i, kMaxMc)];
+    if (i < kNQ) qm[i] = (T)a;
+    if (i < kNQ * kNQ) Mm[i] = (T)b;
+    if (i2 < kNQ * kNQ) Mm[i2] = (T)b2;
+    if (i <= kMaxMc) invm[i] = (T)c;
+}
+
+// ---------------------------------------------------------------- axis-3 passes
+
+// R2C of n (read in T, transformed in FP64): rows (2p, 2p+1) of a tile form
+// one complex line.  tile: a = first row (i1 N2 + i2), b = rows (even)
+template <typename T, int LC>
+__global__ void __launch_bounds__(kThreads) k_x_nfwd(const InstDev *insts, const Tile *tiles,
+                                                     const void *twdv) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const Tile t = tiles[blockIdx.x];
+    const InstDev &I = insts[t.inst];
+    const int N3 = axis_len<LC>(I.n3), N3h = N3 / 2 + 1, row0 = t.a, B = t.b, np = B / 2, ls = N3 + 1;
+    double2 *tw = reinterpret_cast<double2 *>(smem);
+    double2 *buf = tw + N3;
+    const T *n = reinterpret_cast<const T *>(I.n) + (size_t)row0 * N3;
+    batched<4>(np * N3, [&](int idx) {
+        const int pr = idx / N3, k = idx - pr * N3;
+        return mk<double>((double)gld(n)[(2 * pr) * N3 + k], (double)gld(n)[(2 * pr + 1) * N3 + k]);
+    }, [&](int idx, double2 z) {
+        const int pr = idx / N3, k = idx - pr * N3;
+        buf[pr * ls + k] = z;
+    });
+    load_twiddles<double>(tw, I.p3, reinterpret_cast<const double2 *>(twdv));
+    __syncthreads();
+    fft_lc<double, -1, LC>(buf, I.p3, np, 1, ls, tw);
+    double2 *out = reinterpret_cast<double2 *>(I.spec1) + (size_t)row0 * N3h;
+    for (int idx = threadIdx.x; idx < B * N3h; idx += kThreads) {
+        const int rb = idx / N3h, k = idx - rb * N3h;
+        const double2 *Z = buf + (rb >> 1) * ls;
+        const double2 z = Z[k], zc = cconj(Z[(N3 - k) % N3]);
+        double2 y;
+        if ((rb & 1) == 0) y = mk<double>((z.x + zc.x) * 0.5, (z.y + zc.y) * 0.5);
+        else y = mk<double>((z.y - zc.y) * 0.5, -(z.x - zc.x) * 0.5);
+        out[idx] = y;
+    }
+}
+
+// C2R of the three FP64 grad n spectra (axis 3), grad n stored in T.  Rows
+// (2p, 2p+1) of a tile make three complex lines: 3p and 3p+1 hold
+// d1 + i d2 of row 2p and of row 2p+1, 3p+2 holds d3 of row 2p + i d3 of row
+// 2p+1 (each real field has a Hermitian spectrum: the half spectrum at k and,
+// conjugated, at N3 - k).  tile: a = first row, b = rows (even).
+template <typename T, int LC>
+__global__ void __launch_bounds__(kThreads) k_x_grad(const InstDev *insts, const Tile *tiles,
+                                                     const void *twdv) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const Tile t = tiles[blockIdx.x];
+    const InstDev &I = insts[t.inst];
+    const int N3 = axis_len<LC>(I.n3), N3h = N3 / 2 + 1, row0 = t.a, B = t.b, np = B / 2, ls = N3 + 1;
+    const size_t N = (size_t)I.n1 * I.n2 * I.n3;
+    double2 *tw = reinterpret_cast<double2 *>(smem);
+    double2 *buf = tw + N3;
+    const double2 *s3 = reinterpret_cast<const double2 *>(I.spec3) + (size_t)row0 * N3h * 3;
+    struct Six { double2 a0, b0, c0, a1, b1, c1; };
+    batched<2>(np * N3, [&](int idx) {
+        const int pr = idx / N3, k = idx - pr * N3;
+        const int kk = k >= N3h ? N3 - k : k;
+        const gptr<const double2> g0 = gld(s3 + ((size_t)(2 * pr) * N3h + kk) * 3);
+        const gptr<const double2> g1 = gld(s3 + ((size_t)(2 * pr + 1) * N3h + kk) * 3);
+        return Six{g0[0], g0[1], g0[2], g1[0], g1[1], g1[2]};
+    }, [&](int idx, Six y) {
+        const int pr = idx / N3, k = idx - pr * N3;
+        if (k >= N3h) {
+            y.a0 = cconj(y.a0); y.b0 = cconj(y.b0); y.c0 = cconj(y.c0);
+            y.a1 = cconj(y.a1); y.b1 = cconj(y.b1); y.c1 = cconj(y.c1);
+        }
+        double2 *L = buf + 3 * pr * ls + k;
+        L[0] = mk<double>(y.a0.x - y.b0.y, y.a0.y + y.b0.x);
+        L[ls] = mk<double>(y.a1.x - y.b1.y, y.a1.y + y.b1.x);
+        L[2 * ls] = mk<double>(y.c0.x - y.c1.y, y.c0.y + y.c1.x);
+    });
+    load_twiddles<double>(tw, I.p3, reinterpret_cast<const double2 *>(twdv));
+    __syncthreads();
+    fft_lc<double, 1, LC>(buf, I.p3, 3 * np, 1, ls, tw);
+    const gptr<T> g = gst(reinterpret_cast<T *>(I.grad) + (size_t)row0 * N3);
+    for (int idx = threadIdx.x; idx < B * N3; idx += kThreads) {
+        const int rb = idx / N3, k = idx - rb * N3, pr = rb >> 1, odd = rb & 1;
+        const double2 z = buf[(3 * pr + odd) * ls + k], z3 = buf[(3 * pr + 2) * ls + k];
+        g[idx] = (T)z.x;
+        g[N + idx] = (T)z.y;
+        g[2 * N + idx] = (T)(odd ? z3.y : z3.x);
+    }
+}
+
+// theta_a = n p_a(q0) from n and the stored grad n, Delta E partials, R2C of
+// the 20 theta rows.  tile: a = first row, b = rows, slot = partial.
+template <typename T, int LC>
+__global__ void __launch_bounds__(kThreads) k_x_theta(const InstDev *insts, const Tile *tiles,
+                                                      const Consts *cst, const void *twv) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const Tile t = tiles[blockIdx.x];
+    const InstDev &I = insts[t.inst];
+    const int N3 = axis_len<LC>(I.n3), N3h = N3 / 2 + 1, row0 = t.a, B = t.b, ls = N3 + 1;
+    const size_t N = (size_t)I.n1 * I.n2 * I.n3;
+    C2<T> *r2 = reinterpret_cast<C2<T> *>(smem);              // 10 lines per row: theta pairs
+    C2<T> *tw = r2 + kNQ / 2 * B * ls;                       // twiddles in T
+    T *qm = reinterpret_cast<T *>(tw + N3);
+    T *Mm = qm + kNQ;
+    T *invm = Mm + kNQ * kNQ;
+    // density and grad n of this thread's first point, fetched first (used
+    // after the constants arrive); unconditional loads, clamped to the tile: a
+    // load under a branch would be waited for where the branch joins
+    const int npt = B * N3;
+    const size_t p0 = (size_t)row0 * N3;
+    const gptr<const T> nin = gld(reinterpret_cast<const T *>(I.n) + p0);
+    const gptr<const T> gin = gld(reinterpret_cast<const T *>(I.grad) + p0);
+    const int i_first = min((int)threadIdx.x, npt - 1);
+    const T n_first = nin[i_first], gx_f = gin[i_first], gy_f = gin[N + i_first], gz_f = gin[2 * N + i_first];
+    load_consts<T>(cst, qm, Mm, invm);
+    load_twiddles<T>(tw, I.p3, reinterpret_cast<const C2<T> *>(twv));
+    __syncthreads();
+
+    const double c_qc = cst->qc, c_iqc = cst->iqc, c_cs = cst->cs, c_nmin = cst->nmin;
+    const int c_mc = cst->mc;
+    const bool semilocal = I.semilocal != 0;
+    double de = 0.0, dex = 0.0, dec = 0.0;
+    for (int idx = threadIdx.x; idx < npt; idx += kThreads) {
+        const int rb = idx / N3, k = idx - rb * N3;
+        const bool first = idx == (int)threadIdx.x;
+        const T nv = first ? n_first : nin[idx];
+        const C2<T> g01 = mk<T>(first ? gx_f : gin[idx], first ? gy_f : gin[N + idx]);
+        const C2<T> g2 = mk<T>(first ? gz_f : gin[2 * N + idx], (T)0);
+        T *th = reinterpret_cast<T *>(r2 + (size_t)(kNQ / 2 * rb) * ls);   // pair line m at th + 2 m ls
+        if (nv >= (T)c_nmin) {
+            LocalQ<T, false> lq;
+            const T sigma = g01.x * g01.x + g01.y * g01.y + g2.x * g2.x;
+            lq.eval(nv, sigma, c_qc, c_iqc, c_mc, invm);
+            if (semilocal) {
+                Semilocal<T> sl;
+                sl.eval(nv, sigma, lq);
+                dex += (double)sl.ex;
+                dec += (double)sl.ec;
+            }
+            SplineW<T> sw;
+            sw.locate(lq.q0, qm, kNQ);
+            const T *Mj = Mm + sw.j * kNQ;
+            const T nC0 = nv * sw.C0, nC1 = nv * sw.C1;
+#pragma unroll
+            for (int al = 0; al < kNQ; ++al) th[2 * ((al >> 1) * ls + k) + (al & 1)] = nC0 * Mj[al] + nC1 * Mj[kNQ + al];
+            // the interpolating parts A0 d_aj + A1 d_a,j+1 touch two components:
+            // rewrite those two (same thread, so after the loop's stores)
+            const int j0 = sw.j, j1 = sw.j + 1;
+            th[2 * ((j0 >> 1) * ls + k) + (j0 & 1)] = nC0 * Mj[j0] + nC1 * Mj[kNQ + j0] + nv * sw.A0;
+            th[2 * ((j1 >> 1) * ls + k) + (j1 & 1)] = nC0 * Mj[j1] + nC1 * Mj[kNQ + j1] + nv * sw.A1;
+            const T iq = rcp<T>(lq.q0);
+            de += (double)((T)c_cs * nv * nv * iq * iq * iq);
+        } else {
+#pragma unroll 4
+            for (int al = 0; al < kNQ; ++al) th[2 * ((al >> 1) * ls + k) + (al & 1)] = (T)0;
+        }
+    }
+    __syncthreads();
+    fft_lc<T, -1, LC>(r2, I.p3, kNQ / 2 * B, 1, ls, tw);
+
+    // pair line m of row rb holds theta_{2m} + i theta_{2m+1}: its values at
+    // k and N3 - k give both spectra at k, written together (item idx =
+    // (rb N3h + k) 10 + m lands at spectrum element 2 idx)
+    C2<T> *out = reinterpret_cast<C2<T> *>(I.spec) + (size_t)row0 * N3h * kNQ;
+    Cursor3 cur(threadIdx.x, kNQ / 2, N3h);
+    for (int idx = threadIdx.x; idx < B * N3h * (kNQ / 2); idx += kThreads, cur.step()) {
+        const int m = cur.m, k = cur.k, rb = cur.r;
+        const C2<T> *Z = r2 + (kNQ / 2 * rb + m) * ls;
+        const C2<T> z = Z[k], zc = cconj(Z[k == 0 ? 0 : N3 - k]);
+        const T ex = (z.x + zc.x) * (T)0.5, ey = (z.y + zc.y) * (T)0.5;
+        const T ox = (z.y - zc.y) * (T)0.5, oy = -(z.x - zc.x) * (T)0.5;
+        C2<T> *o = out + 2 * (size_t)idx;
+        if constexpr (sizeof(T) == 4) gst(reinterpret_cast<float4 *>(o))[0] = make_float4(ex, ey, ox, oy);
+        else { gst(o)[0] = mk<T>(ex, ey); gst(o)[1] = mk<T>(ox, oy); }
+    }
+    const double s = block_sum(de);
+    double sx = 0.0, sc = 0.0;
+    if (semilocal) {                 // (uniform over the workgroup)
+        sx = block_sum(dex);
+        sc = block_sum(dec);
+    }
+    if (threadIdx.x == 0) {
+        I.part_de[t.slot] = s;
+        I.part_sl[2 * t.slot] = sx;
+        I.part_sl[2 * t.slot + 1] = sc;
+    }
+}
+
+// The u spectra of B rows (axis 3 half spectra, [B][N3h][kNQ] complex at sp)
+// into LDS pair lines ready for the inverse axis-3 FFT: u_{2m} + i u_{2m+1}
+// on pair line m of row rb (at r2 + (10 rb + m) ls), from the spectra at k
+// (< N3/2 + 1) both the value at k and, by Hermitian symmetry, at N3 - k.
+// Item idx = (rb N3h + k) 10 + m reads spectrum elements 2 idx, 2 idx + 1;
+// about five steps per thread for every length class: batches of six.
+template <typename T>
+__device__ __forceinline__ void u_lines_in(C2<T> *r2, int ls, const C2<T> *sp, int B, int N3, int N3h) {
+    constexpr int U = 6;
+    const int total = B * N3h * (kNQ / 2);
+    Cursor3 cur(threadIdx.x, kNQ / 2, N3h);
+    const gptr<const C2<T>> g = gld(sp);
+    for (int base = threadIdx.x; base < total; base += U * kThreads) {
+        C2<T> ya[U], yb[U];
+        int lo[U], kk[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int idx = base + u * kThreads;
+            const bool on = idx < total;
+            const size_t e = on ? 2 * (size_t)idx : 0;   // (unconditional loads)
+            ya[u] = g[e];
+            yb[u] = g[e + 1];
+            lo[u] = on ? (kNQ / 2 * cur.r + cur.m) * ls : -1;
+            kk[u] = cur.k;
+            cur.step();
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (lo[u] < 0) continue;
+            C2<T> *line = r2 + lo[u];
+            const int k = kk[u];
+            const C2<T> a = ya[u], b = yb[u];
+            line[k] = mk<T>(a.x - b.y, a.y + b.x);
+            if (k != 0 && 2 * k != N3) line[N3 - k] = mk<T>(a.x + b.y, -a.y + b.x);   // conj(a) + i conj(b)
+        }
+    }
+}
+
+// C2R of the 20 u_a rows; v_loc = sum_a u_a dtheta_a/dn + de/dn;
+// w = g grad n with g = sum_a u_a 2 n p'_a Q dq/dsigma + de/dsigma-part;
+// R2C of the three w rows (in T: the divergence chain runs in the working
+// precision), or (FD) w stored in place of grad n.  tile: a = first row, b = rows.
+template <typename T, int LC, bool FD>
+__global__ void __launch_bounds__(kThreads) k_x_assemble(const InstDev *insts, const Tile *tiles,
+                                                         const Consts *cst, const void *twv) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const Tile t = tiles[blockIdx.x];
+    const InstDev &I = insts[t.inst];
+    const int N3 = axis_len<LC>(I.n3), N3h = N3 / 2 + 1, row0 = t.a, B = t.b, ls = N3 + 1;
+    const size_t N = (size_t)I.n1 * I.n2 * I.n3;
+    C2<T> *r1 = reinterpret_cast<C2<T> *>(smem);              // 2 lines per row: w1 + i w2, w3
+    C2<T> *r2 = r1 + (FD ? 0 : 2 * B * ls);                   // 10 lines per row: u pairs
+    C2<T> *tw = r2 + kNQ / 2 * B * ls;                       // twiddles in T
+    T *qm = reinterpret_cast<T *>(tw + N3);
+    T *Mm = qm + kNQ;
+    T *invm = Mm + kNQ * kNQ;
+    // n and grad n of this thread's first point, fetched first (used after the FFT)
+    const int npt = B * N3;
+    const size_t p0 = (size_t)row0 * N3;
+    const gptr<const T> nin = gld(reinterpret_cast<const T *>(I.n) + p0);
+    const gptr<const T> grad = gld(reinterpret_cast<const T *>(I.grad) + p0);
+    // (unconditional loads, clamped to the tile: a load under a branch would
+    // be waited for where the branch joins)
+    const int i_first = min((int)threadIdx.x, npt - 1);
+    const T n_f = nin[i_first], gx_f = grad[i_first], gy_f = grad[N + i_first], gz_f = grad[2 * N + i_first];
+    u_lines_in<T>(r2, ls, reinterpret_cast<const C2<T> *>(I.spec) + (size_t)row0 * N3h * kNQ, B, N3, N3h);
+    load_consts<T>(cst, qm, Mm, invm);
+    load_twiddles<T>(tw, I.p3, reinterpret_cast<const C2<T> *>(twv));
+    __syncthreads();
+    fft_lc<T, 1, LC>(r2, I.p3, kNQ / 2 * B, 1, ls, tw);
+
+    const double c_qc = cst->qc, c_iqc = cst->iqc, c_cs = cst->cs, c_nmin = cst->nmin;
+    const int c_mc = cst->mc;
+    const bool semilocal = I.semilocal != 0;
+    const gptr<T> vloc = gst(reinterpret_cast<T *>(I.vloc) + p0);
+    for (int idx = threadIdx.x; idx < npt; idx += kThreads) {
+        const int rb = idx / N3, k = idx - rb * N3;
+        const bool first = idx == (int)threadIdx.x;
+        const T nv = first ? n_f : nin[idx];
+        const T gx = first ? gx_f : grad[idx], gy = first ? gy_f : grad[N + idx], gz = first ? gz_f : grad[2 * N + idx];
+        T vl = (T)0, gs = (T)0;
+        if (nv >= (T)c_nmin) {
+            LocalQ<T, true> lq;
+            const T sigma = gx * gx + gy * gy + gz * gz;
+            lq.eval(nv, sigma, c_qc, c_iqc, c_mc, invm);
+            SplineW<T> sw;
+            sw.locate(lq.q0, qm, kNQ);
+            const T *u = reinterpret_cast<const T *>(r2 + (size_t)(kNQ / 2 * rb) * ls);
+            const T cn = nv * lq.Q * lq.dqdn;
+            // sum_a u_a p_a and sum_a u_a p_a' through S0 = sum_a u_a M[j][a], S1 = sum_a u_a M[j+1][a]
+            const T *Mj = Mm + sw.j * kNQ;
+            T S0 = (T)0, S1 = (T)0;
+#pragma unroll
+            for (int al = 0; al < kNQ; ++al) {
+                const T ua = u[2 * ((al >> 1) * ls + k) + (al & 1)];
+                S0 += ua * Mj[al];
+                S1 += ua * Mj[kNQ + al];
+            }
+            const int j0 = sw.j, j1 = sw.j + 1;
+            const T uj = u[2 * ((j0 >> 1) * ls + k) + (j0 & 1)], uj1 = u[2 * ((j1 >> 1) * ls + k) + (j1 & 1)];
+            const T su = sw.A0 * uj + sw.A1 * uj1 + sw.C0 * S0 + sw.C1 * S1;
+            const T sdu = sw.B0 * uj + sw.B1 * uj1 + sw.D0 * S0 + sw.D1 * S1;
+            // dtheta_a/dn = p_a + n p'_a Q dq/dn ; dtheta_a/dgrad n = 2 n p'_a Q dq/dsigma grad n
+            const T q0 = lq.q0, cs = (T)c_cs;
+            const T iq = rcp<T>(q0), iq3 = iq * iq * iq, iq4 = iq3 * iq;
+            vl = su + cn * sdu + (T)2 * cs * nv * iq3 - (T)3 * cs * nv * nv * iq4 * lq.Q * lq.dqdn;
+            gs = (T)2 * lq.Q * lq.ndqds * sdu - (T)6 * cs * nv * iq4 * lq.Q * lq.ndqds;
+            if (semilocal) {
+                // the semilocal terms: de/dgrad n = 2 de/dsigma grad n
+                Semilocal<T> sl;
+                sl.eval(nv, sigma, lq);
+                vl += sl.dn;
+                gs += (T)2 * sl.ds;
+            }
+        }
+        vloc[idx] = vl;
+        if constexpr (FD) {
+            // the lattice components q_c = sum_x W[c][x] w_x of w in place of
+            // grad n (each point is read and written by its own thread)
+            const double gsd = (double)gs;
+            const double wx = gsd * (double)gx, wy = gsd * (double)gy, wz = gsd * (double)gz;
+            const gptr<T> wout = gst(reinterpret_cast<T *>(I.grad) + p0);
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                wout[c * N + idx] = (T)(I.fdW[c][0] * wx + I.fdW[c][1] * wy + I.fdW[c][2] * wz);
+        } else {
+            r1[(2 * rb) * ls + k] = mk<T>(gs * gx, gs * gy);
+            r1[(2 * rb + 1) * ls + k] = mk<T>(gs * gz, (T)0);
+        }
+    }
+    if constexpr (!FD) {
+        __syncthreads();
+        fft_lc<T, -1, LC>(r1, I.p3, 2 * B, 1, ls, tw);
+        C2<T> *out = reinterpret_cast<C2<T> *>(I.spec3) + (size_t)row0 * N3h * 3;
+        for (int idx = threadIdx.x; idx < B * N3h * 3; idx += kThreads) {
+            const int comp = idx % 3, rest = idx / 3;
+            const int k = rest % N3h, rb = rest / N3h;
+            const C2<T> *Z = r1 + (2 * rb + (comp >> 1)) * ls;
+            const C2<T> z = Z[k], zc = cconj(Z[(N3 - k) % N3]);
+            C2<T> y;
+            if (comp != 1) y = mk<T>((z.x + zc.x) * (T)0.5, (z.y + zc.y) * (T)0.5);
+            else y = mk<T>((z.y - zc.y) * (T)0.5, -(z.x - zc.x) * (T)0.5);
+            gst(out)[idx] = y;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- finite-difference passes
+
+// Central differences on the periodic grid in the working precision:
+// d_c f_i = sum_s c_s (f_{i + s e_c} - f_{i - s e_c}), s = 1..M, along the grid
+// (lattice) axis c; grad n = sum_c W[c] d_c n with W[c][x] = N_c b_c,x / (2 pi).
+// Neighbour indices wrap once (M <= 4 <= every edge).  Tiles are runs of
+// whole axis-3 lines: a = first row (i1 N2 + i2), b = rows.  Offsets are
+// 32-bit (a grid and its three fields stay below 2^31 elements).
+
+// offset of the neighbour s steps up (down) an axis of n points with element
+// stride st from index i (one wrap at most)
+__device__ __forceinline__ int fd_up(int i, int s, int n, int st) { return i + s < n ? s * st : (s - n) * st; }
+__device__ __forceinline__ int fd_dn(int i, int s, int n, int st) { return i >= s ? -s * st : (n - s) * st; }
+
+template <typename T, int M>
+__device__ __forceinline__ T fd_diff(gptr<const T> f, int i, int n, int st, const T *c) {
+    T acc = (T)0;
+#pragma unroll
+    for (int s = 1; s <= M; ++s) acc += c[s - 1] * (f[fd_up(i, s, n, st)] - f[fd_dn(i, s, n, st)]);
+    return acc;
+}
+
+template <typename T, int M>
+__device__ __forceinline__ void fd_grad_tile(const InstDev &I, int row0, int B) {
+    const int N1 = I.n1, N2 = I.n2, N3 = I.n3;
+    const int plane = N2 * N3, N = N1 * plane;
+    const gptr<const T> n = gld(reinterpret_cast<const T *>(I.n));
+    const gptr<T> g = gst(reinterpret_cast<T *>(I.grad));
+    T c[M];
+#pragma unroll
+    for (int s = 0; s < M; ++s) c[s] = (T)I.fdc[s];
+    T Wm[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int x = 0; x < 3; ++x) Wm[a][x] = (T)I.fdW[a][x];
+    const int npt = B * N3;
+    const int drow = kThreads / N3, dk = kThreads - drow * N3;
+    int idx = threadIdx.x;
+    if (idx >= npt) return;
+    int rb = idx / N3, i3 = idx - rb * N3, row = row0 + rb;
+    int i1 = row / N2, i2 = row - i1 * N2;
+    for (; idx < npt; idx += kThreads) {
+        const int p = row * N3 + i3;
+        const gptr<const T> f = n + p;
+        const T d1 = fd_diff<T, M>(f, i1, N1, plane, c);
+        const T d2 = fd_diff<T, M>(f, i2, N2, N3, c);
+        const T d3 = fd_diff<T, M>(f, i3, N3, 1, c);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) g[a * N + p] = Wm[0][a] * d1 + Wm[1][a] * d2 + Wm[2][a] * d3;
+        // next point: kThreads = drow N3 + dk further on
+        i3 += dk;
+        row += drow;
+        i2 += drow;
+        if (i3 >= N3) { i3 -= N3; ++row; ++i2; }
+        while (i2 >= N2) { i2 -= N2; ++i1; }
+    }
+}
+
+// v = v_loc - sum_c d_c q_c, q_c = sum_x W[c][x] w_x in the grad n buffer
+// (Eq. (Vi): the sum over j of w_j . d(grad n_j)/dn_i is the transpose of the
+// gradient operator applied to w, minus the same stencils since they are
+// antisymmetric).
+template <typename T, int M>
+__device__ __forceinline__ void fd_div_tile(const InstDev &I, int row0, int B) {
+    const int N1 = I.n1, N2 = I.n2, N3 = I.n3;
+    const int plane = N2 * N3, N = N1 * plane;
+    const gptr<const T> w = gld(reinterpret_cast<const T *>(I.grad));
+    const gptr<const T> vloc = gld(reinterpret_cast<const T *>(I.vloc));
+    const gptr<T> v = gst(reinterpret_cast<T *>(I.v));
+    T c[M];
+#pragma unroll
+    for (int s = 0; s < M; ++s) c[s] = (T)I.fdc[s];
+    const int npt = B * N3;
+    const int drow = kThreads / N3, dk = kThreads - drow * N3;
+    int idx = threadIdx.x;
+    if (idx >= npt) return;
+    int rb = idx / N3, i3 = idx - rb * N3, row = row0 + rb;
+    int i1 = row / N2, i2 = row - i1 * N2;
+    for (; idx < npt; idx += kThreads) {
+        const int p = row * N3 + i3;
+        const T d1 = fd_diff<T, M>(w + p, i1, N1, plane, c);
+        const T d2 = fd_diff<T, M>(w + N + p, i2, N2, N3, c);
+        const T d3 = fd_diff<T, M>(w + 2 * N + p, i3, N3, 1, c);
+        v[p] = vloc[p] - (d1 + d2 + d3);
+        i3 += dk;
+        row += drow;
+        i2 += drow;
+        if (i3 >= N3) { i3 -= N3; ++row; ++i2; }
+        while (i2 >= N2) { i2 -= N2; ++i1; }
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_fd_grad(const InstDev *insts, const Tile *tiles) {
+    const Tile t = tiles[blockIdx.x];
+    const InstDev &I = insts[t.inst];
+    switch (I.fdm) {
+        case 1: fd_grad_tile<T, 1>(I, t.a, t.b); break;
+        case 2: fd_grad_tile<T, 2>(I, t.a, t.b); break;
+        case 3: fd_grad_tile<T, 3>(I, t.a, t.b); break;
+        case 4: fd_grad_tile<T, 4>(I, t.a, t.b); break;
+        default: break;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_fd_div(const InstDev *insts, const Tile *tiles) {
+    const Tile t = tiles[blockIdx.x];
+    const InstDev &I = insts[t.inst];
+    switch (I.fdm) {
+        case 1: fd_div_tile<T, 1>(I, t.a, t.b); break;
+        case 2: fd_div_tile<T, 2>(I, t.a, t.b); break;
+        case 3: fd_div_tile<T, 3>(I, t.a, t.b); break;
+        case 4: fd_div_tile<T, 4>(I, t.a, t.b); break;
+        default: break;
+    }
+}
+
+// C2R of the divergence spectrum (row pairs, working precision), v = v_loc - div.
+template <typename T, int LC>
+__global__ void __launch_bounds__(kThreads) k_x_final(const InstDev *insts, const Tile *tiles,
+                                                      const void *twv) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const Tile t = tiles[blockIdx.x];
+    const InstDev &I = insts[t.inst];
+    const int N3 = axis_len<LC>(I.n3), N3h = N3 / 2 + 1, row0 = t.a, B = t.b, np = B / 2, ls = N3 + 1;
+    C2<T> *tw = reinterpret_cast<C2<T> *>(smem);
+    C2<T> *buf = tw + N3;
+    const C2<T> *s1 = reinterpret_cast<const C2<T> *>(I.spec1) + (size_t)row0 * N3h;
+    const int npt = B * N3;
+    const gptr<const T> vloc = gld(reinterpret_cast<const T *>(I.vloc) + (size_t)row0 * N3);
+    struct Two { C2<T> a, b; };
+    batched<4>(np * N3, [&](int idx) {
+        const int pr = idx / N3, k = idx - pr * N3;
+        const int kk = k >= N3h ? N3 - k : k;
+        return Two{gld(s1)[(2 * pr) * N3h + kk], gld(s1)[(2 * pr + 1) * N3h + kk]};
+    }, [&](int idx, Two y) {
+        const int pr = idx / N3, k = idx - pr * N3;
+        if (k >= N3h) { y.a = cconj(y.a); y.b = cconj(y.b); }
+        buf[pr * ls + k] = mk<T>(y.a.x - y.b.y, y.a.y + y.b.x);
+    });
+    load_twiddles<T>(tw, I.p3, reinterpret_cast<const C2<T> *>(twv));
+    __syncthreads();
+    fft_lc<T, 1, LC>(buf, I.p3, np, 1, ls, tw);
+    const gptr<T> v = gst(reinterpret_cast<T *>(I.v) + (size_t)row0 * N3);
+    batched<4>(npt, [&](int idx) { return vloc[idx]; }, [&](int idx, T vl) {
+        const int rb = idx / N3, k = idx - rb * N3;
+        const C2<T> z = buf[(rb >> 1) * ls + k];
+        v[idx] = vl - ((rb & 1) ? z.y : z.x);
+    });
+}
+
+// ---------------------------------------------------------------- axis-2 pass
+
+// tile: a = i1, b = first flattened (k3, component) index, c = width
+template <typename T, int S, int LC>
+__global__ void __launch_bounds__(kThreads) k_y(const InstDev *insts, const Tile *tiles,
+                                                const void *twv, int which, int V) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const Tile t = tiles[blockIdx.x];
+    const InstDev &I = insts[t.inst];
+    const int N2 = axis_len<LC>(I.n2), W = t.c, lp = N2 | 1;   // lines contiguous, odd pitch
+    C2<T> *tw = reinterpret_cast<C2<T> *>(smem);
+    C2<T> *buf = tw + N2;
+    const size_t rowlen = (size_t)I.n3h * V;
+    void *base = which == 0 ? I.spec : (which == 1 ? I.spec3 : I.spec1);
+    C2<T> *g = reinterpret_cast<C2<T> *>(base) + (size_t)t.a * N2 * rowlen + t.b;
+    rows_in_t(buf, lp, g, rowlen, N2, W);
+    load_twiddles<T>(tw, I.p2, reinterpret_cast<const C2<T> *>(twv));
+    __syncthreads();
+    fft_lc<T, S, LC>(buf, I.p2, W, 1, lp, tw);
+    rows_out_t(g, rowlen, buf, lp, N2, W);
+}
+
+// ---------------------------------------------------------------- axis-1 passes
+
+// n spectrum -> i G_c n / N, c = 1..3.  tile: a = k2, b = first k3, c = count
+template <typename T, int LC>
+__global__ void __launch_bounds__(kThreads) k_z_grad(const InstDev *insts, const Tile *tiles,
+                                                     const void *twv) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const Tile t = tiles[blockIdx.x];
+    const InstDev &I = insts[t.inst];
+    const int N1 = axis_len<LC>(I.n1), N2 = I.n2, N3 = I.n3, N3h = I.n3h, k2 = t.a, k30 = t.b, K3 = t.c;
+    const int lp = N1 | 1;                                   // lines contiguous, odd pitch
+    C2<T> *twall = reinterpret_cast<C2<T> *>(smem);
+    C2<T> *bin = twall + N1;                                 // K3 lines
+    C2<T> *bout = bin + K3 * lp;                             // 3 K3 lines: (w, c) at line 3 w + c
+    const C2<T> *gin = reinterpret_cast<const C2<T> *>(I.spec1) + (size_t)k2 * N3h + k30;
+    const size_t sin_ = (size_t)N2 * N3h;
+    rows_in_t(bin, lp, gin, sin_, N1, K3);
+    load_twiddles<T>(twall, I.p1, reinterpret_cast<const C2<T> *>(twv));
+    __syncthreads();
+    fft_lc<T, -1, LC>(bin, I.p1, K3, 1, lp, twall);
+    const double m2 = (double)freq_nz(k2, N2);
+    for (int idx = threadIdx.x; idx < N1 * K3; idx += kThreads) {
+        const int w = idx / N1, l = idx - w * N1;
+        const C2<T> nh = cscale(bin[w * lp + l], (T)I.inv_n);
+        T G1, G2, G3;
+        cart_g<T>(I, (double)freq_nz(l, N1), m2, (double)freq_nz(k30 + w, N3), G1, G2, G3);
+        C2<T> *o = bout + 3 * w * lp + l;
+        o[0] = mk<T>(-G1 * nh.y, G1 * nh.x);
+        o[lp] = mk<T>(-G2 * nh.y, G2 * nh.x);
+        o[2 * lp] = mk<T>(-G3 * nh.y, G3 * nh.x);
+    }
+    __syncthreads();
+    fft_lc<T, 1, LC>(bout, I.p1, 3 * K3, 1, lp, twall);
+    C2<T> *gout = reinterpret_cast<C2<T> *>(I.spec3) + ((size_t)k2 * N3h + k30) * 3;
+    rows_out_t(gout, sin_ * 3, bout, lp, N1, 3 * K3);
+}
+
+// sum_c i G_c w_c / N.  tile: a = k2, b = first k3, c = count
+template <typename T, int LC>
+__global__ void __launch_bounds__(kThreads) k_z_div(const InstDev *insts, const Tile *tiles,
+                                                    const void *twv) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const Tile t = tiles[blockIdx.x];
+    const InstDev &I = insts[t.inst];
+    const int N1 = axis_len<LC>(I.n1), N2 = I.n2, N3 = I.n3, N3h = I.n3h, k2 = t.a, k30 = t.b, K3 = t.c;
+    const int lp = N1 | 1;                                   // lines contiguous, odd pitch
+    C2<T> *twall = reinterpret_cast<C2<T> *>(smem);
+    C2<T> *bin = twall + N1;                                 // 3 K3 lines: (w, c) at line 3 w + c
+    C2<T> *bout = bin + 3 * K3 * lp;                         // K3 lines
+    const size_t sin_ = (size_t)N2 * N3h;
+    const C2<T> *gin = reinterpret_cast<const C2<T> *>(I.spec3) + ((size_t)k2 * N3h + k30) * 3;
+    rows_in_t(bin, lp, gin, sin_ * 3, N1, 3 * K3);
+    load_twiddles<T>(twall, I.p1, reinterpret_cast<const C2<T> *>(twv));
+    __syncthreads();
+    fft_lc<T, -1, LC>(bin, I.p1, 3 * K3, 1, lp, twall);
+    const double m2 = (double)freq_nz(k2, N2);
+    for (int idx = threadIdx.x; idx < N1 * K3; idx += kThreads) {
+        const int w = idx / N1, l = idx - w * N1;
+        const C2<T> *x = bin + 3 * w * lp + l;
+        T G1, G2, G3;
+        cart_g<T>(I, (double)freq_nz(l, N1), m2, (double)freq_nz(k30 + w, N3), G1, G2, G3);
+        const T sx = G1 * x[0].x + G2 * x[lp].x + G3 * x[2 * lp].x;
+        const T sy = G1 * x[0].y + G2 * x[lp].y + G3 * x[2 * lp].y;
+        bout[w * lp + l] = cscale(mk<T>(-sy, sx), (T)I.inv_n);
+    }
+    __syncthreads();
+    fft_lc<T, 1, LC>(bout, I.p1, K3, 1, lp, twall);
+    C2<T> *gout = reinterpret_cast<C2<T> *>(I.spec1) + (size_t)k2 * N3h + k30;
+    rows_out_t(gout, sin_, bout, lp, N1, K3);
+}
+
+// Forward axis-1 FFT of the 20 theta spectra, u_a(G) = sum_b phi_ab(|G|) c_b(G)
+// with c = Theta / N (Eq. Eoffk, Eq. epsofk), the energy sum
+// sum_G w_G sum_a Re(c_a^* u_a), inverse axis-1 FFT.
+// tile: a = first entry in the column list, b = number of column pairs P,
+// c = columns per pair (2: k2 and N2 - k2, which meet the same |G| shell at
+// every (|m1|, k3); 1: k2 = 0 or N2/2).  Pair i has k3 = k3_0 + i; the list
+// holds the columns pair by pair.
+//
+// Contraction layout: lanes form groups of kNQ (three per wave).  A group
+// takes one item, a |m1| and a pair; lane a loads row a of that shell's
+// kernel matrix (kNQ contiguous values, 16-byte loads) into registers and
+// forms u_a at the pair's points (+-m1 of each column).  The rows of the
+// group's next item are loaded meanwhile (two register sets in turn).
+// GEN (grids in non-orthogonal cells): every item is one k point with its
+// own shell, whose table holds the packed upper triangle; lane a gathers its
+// row from it through offsets fixed per lane.
+// PROBE (parity probes of the stages, never in an evaluation): 1 writes the
+// forward spectra c = FFT(theta)/N back in place of the tile (no contraction,
+// no inverse); 2 writes u = phi c (no inverse); 0 is the evaluation.
+template <typename T, int LC, bool GEN, int PROBE>
+__global__ void __launch_bounds__(kThreads) k_z_main(const InstDev *insts, const Tile *tiles, const int2 *cols,
+                                                     const void *twv) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int kGroups = (kThreads / 64) * (64 / kNQ);   // lane groups per workgroup
+    constexpr int kEpc = 16 / (int)sizeof(C2<T>);             // complex values per 16-byte chunk
+    const Tile t = tiles[blockIdx.x];
+    const InstDev &I = insts[t.inst];
+    const int N1 = axis_len<LC>(I.n1), N2 = I.n2, N3 = I.n3, N3h = I.n3h, P = t.b, CP = t.c, K = P * CP;
+    const int W = K * kNQ, lp = N1 | 1;                      // W lines, contiguous, odd pitch
+    const int cstride = kNQ * lp;                             // LDS elements per column
+    __shared__ int colbase[kMaxCols];                         // offset of each column in a k1 plane
+    C2<T> *twall = reinterpret_cast<C2<T> *>(smem);
+    C2<T> *buf = twall + N1;
+    int *sidx = reinterpret_cast<int *>(buf + W * lp);        // shell of every item
+    {
+        const int2 cw = cols[t.a + min((int)threadIdx.x, K - 1)];   // unconditional (clamped) load
+        if (threadIdx.x < K) colbase[threadIdx.x] = (cw.x * N3h + cw.y) * kNQ;
+    }
+    const int2 c0 = cols[t.a];
+    __syncthreads();
+    const size_t plane = (size_t)N2 * N3h * kNQ;
+    C2<T> *spec = reinterpret_cast<C2<T> *>(I.spec);
+    // 16-byte chunks (l, w, e): plane l, column w, chunk e of the column's 20 values
+    constexpr int kCpc = kNQ / kEpc;                          // chunks per column
+    // 16-byte chunks (l, w, e): plane l, column w, chunk e of the column's 20
+    // values.  Each thread keeps one chunk column (w, e) and steps through the
+    // planes; the loads of kUnroll planes are issued before their stores.
+    auto io = [&](bool in) {
+        const int C = K * kCpc;                               // chunks per plane
+        if (C > kThreads) {                                   // (only tiny N1 with many columns)
+            const int total = N1 * C;
+            for (int i = threadIdx.x; i < total; i += kThreads) {
+                const int l = i / C, c = i - l * C, w = c / kCpc, e = c - w * kCpc;
+                C2<T> *lb = buf + (w * kNQ + e * kEpc) * lp + l;
+                C2<T> *gb = spec + (size_t)l * plane + colbase[w] + e * kEpc;
+#pragma unroll
+                for (int q = 0; q < kEpc; ++q) {
+                    if (in) lb[q * lp] = gld(gb)[q];
+                    else gst(gb)[q] = lb[q * lp];
+                }
+            }
+            return;
+        }
+        const int rps = kThreads / C;                         // planes per step
+        if ((int)threadIdx.x >= rps * C) return;
+        const int r0 = threadIdx.x / C, c = threadIdx.x - r0 * C, w = c / kCpc, e = c - w * kCpc;
+        C2<T> *lb = buf + (w * kNQ + e * kEpc) * lp;
+        // this lane's chunk column; planes l = r0 + s rps, s = j kUnroll + u
+        char *cb = reinterpret_cast<char *>(spec + colbase[w] + e * kEpc);
+        const size_t plane_bytes = plane * sizeof(C2<T>);
+        for (int l0 = r0; l0 < N1; l0 += kUnroll * rps) {
+            T ra[kUnroll], rb[kUnroll], rc[kUnroll], rd[kUnroll];
+            if (in) {
+                // unconditional loads (a plane past N1 re-reads plane r0, valid here)
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
+                    const int l = l0 + u * rps;
+                    const char *src = cb + (size_t)(uint32_t)(l < N1 ? l : r0) * plane_bytes;
+                    if constexpr (kEpc == 2) {
+                        const float4 v = gld(reinterpret_cast<const float4 *>(src))[0];
+                        ra[u] = v.x; rb[u] = v.y; rc[u] = v.z; rd[u] = v.w;
+                    } else {
+                        const C2<T> v = gld(reinterpret_cast<const C2<T> *>(src))[0];
+                        ra[u] = v.x; rb[u] = v.y;
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const int l = l0 + u * rps;
+                if (l >= N1) continue;
+                char *dst = cb + (size_t)(uint32_t)l * plane_bytes;
+                if (in) {
+                    lb[l] = mk<T>(ra[u], rb[u]);
+                    if constexpr (kEpc == 2) lb[lp + l] = mk<T>(rc[u], rd[u]);
+                } else if constexpr (kEpc == 2) {
+                    const C2<T> p0 = lb[l], p1 = lb[lp + l];
+                    gst(reinterpret_cast<float4 *>(dst))[0] = make_float4(p0.x, p0.y, p1.x, p1.y);
+                } else {
+                    gst(reinterpret_cast<C2<T> *>(dst))[0] = lb[l];
+                }
+            }
+        }
+    };
+    io(true);
+    load_twiddles<T>(twall, I.p1, reinterpret_cast<const C2<T> *>(twv));
+
+    const T *tab = reinterpret_cast<const T *>(I.shelltab);
+    // orthorhombic cell: item = |m1| P + pair, the +-m1 points share a shell;
+    // general cell: item = k1 P + pair over the whole axis, a shell each
+    constexpr bool general = GEN;
+    const int k30 = c0.y;
+    const int m2 = general ? c0.x : freq_abs(c0.x, N2);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int grp = lane / kNQ, al = lane - grp * kNQ;
+    const bool lane_on = grp < 64 / kNQ;
+    const int gid = wave * (64 / kNQ) + grp;
+    const int nitems = (general ? N1 : N1 / 2 + 1) * P;
+    // shell of every item, into LDS (the loads overlap the forward FFT)
+    {
+        const gptr<const int> smap = gld(I.shellmap + (size_t)m2 * N3h + k30);
+        const size_t smap_m1 = (size_t)(general ? N2 : I.h2) * N3h;
+        for (int i = threadIdx.x; i < nitems; i += kThreads) {
+            const int m1 = i / P;
+            sidx[i] = smap[m1 * smap_m1 + (i - m1 * P)];
+        }
+    }
+    // (packed rows: entry (r, q), r <= q, at r kNQ - r (r - 1)/2 + q - r)
+    int poff[GEN ? kNQ : 1];
+    if constexpr (GEN) {
+#pragma unroll
+        for (int b = 0; b < kNQ; ++b) {
+            const int r = min(al, b), q = max(al, b);
+            poff[b] = r * kNQ - ((r * (r - 1)) >> 1) + q - r;
+        }
+    }
+    // row al of the shell matrix of an item (index clamped to the last item:
+    // the loads stay unconditional)
+    auto fetch = [&](int item, T *f) {
+        const int sh = sidx[min(item, nitems - 1)];
+        if constexpr (GEN) {
+            const gptr<const T> src = gld(tab + (size_t)sh * kTabPacked);
+#pragma unroll
+            for (int b = 0; b < kNQ; ++b) f[b] = src[poff[b]];
+            return;
+        }
+        const gptr<const T> src = gld(tab + (size_t)sh * kTabRow + al * kNQ);
+        if constexpr (sizeof(T) == 4) {
+            const gptr<const float4> s4 = (gptr<const float4>)src;
+#pragma unroll
+            for (int q = 0; q < kNQ / 4; ++q) {
+                const float4 v = s4[q];
+                f[4 * q] = v.x; f[4 * q + 1] = v.y; f[4 * q + 2] = v.z; f[4 * q + 3] = v.w;
+            }
+        } else {
+            const gptr<const double2> s2 = (gptr<const double2>)src;
+#pragma unroll
+            for (int q = 0; q < kNQ / 2; ++q) {
+                const double2 v = s2[q];
+                f[2 * q] = v.x; f[2 * q + 1] = v.y;
+            }
+        }
+    };
+    __syncthreads();
+    T fa[kNQ], fb[kNQ];
+    if (PROBE != 1 && lane_on) fetch(gid, fa);
+    fft_lc<T, -1, LC>(buf, I.p1, W, 1, lp, twall);
+    if constexpr (PROBE == 1) {
+        const T inv_n = (T)I.inv_n;
+        for (int i = threadIdx.x; i < W * lp; i += kThreads) buf[i] = cscale(buf[i], inv_n);
+        __syncthreads();
+        io(false);
+        if (threadIdx.x == 0) I.part_ek[t.slot] = 0.0;
+        return;
+    }
+
+    const T inv_n = (T)I.inv_n;
+    const double wn = (double)inv_n * (double)inv_n;
+    double e = 0.0;
+    // item it = m1 P + pr, stepped by kGroups without divisions
+    const int dm = kGroups / P, dr = kGroups - dm * P;
+    int m1 = gid / P, pr = gid - m1 * P;
+    // u at the points of the current item with the kernel row f; a group's
+    // lanes share one wave, so reads of theta and writes of u need wave-level
+    // ordering only
+    auto process = [&](const T *f) {
+        // the points +-m1 of each column of the item (lq = l for k1 = 0, the
+        // Nyquist plane and general cells: the second point is the first
+        // again, its energy masked and its u the same value written twice)
+        const int l = m1;
+        int lq = N1 - m1;
+        const bool two = !(general || m1 == 0 || lq == m1);
+        if (!two) lq = l;
+        const T mask2 = two ? (T)1 : (T)0;
+        const int w0 = __mul24(pr, CP);
+        const int k3 = k30 + pr;                               // the item's columns share k3
+        const bool edge = (k3 == 0) || ((N3 & 1) == 0 && 2 * k3 == N3);
+        const double wgt = edge ? wn : 2.0 * wn;
+        m1 += dm;
+        pr += dr;
+        if (pr >= P) { pr -= P; ++m1; }
+        auto column = [&](int w) {
+            C2<T> u1 = mk<T>((T)0, (T)0), u2 = u1;
+            C2<T> *xc = buf + __mul24(w, cstride);
+            C2<T> *x1 = xc + l;                                   // component b at x1[b lp]
+            C2<T> *x2 = xc + lq;
+#pragma unroll
+            for (int b = 0; b < kNQ; ++b) {
+                const C2<T> t1 = x1[b * lp], t2 = x2[b * lp];
+                u1.x += f[b] * t1.x;
+                u1.y += f[b] * t1.y;
+                u2.x += f[b] * t2.x;
+                u2.y += f[b] * t2.y;
+            }
+            const C2<T> own1 = x1[al * lp], own2 = x2[al * lp];
+            e += wgt * (double)(own1.x * u1.x + own1.y * u1.y + mask2 * (own2.x * u2.x + own2.y * u2.y));
+            // every lane of the group has read theta at these points before
+            // any lane overwrites its component with u; the next column or
+            // item reads other points (each k point belongs to one item), so
+            // no ordering is needed after the writes
+            wave_sync();
+            x1[al * lp] = cscale(u1, inv_n);
+            x2[al * lp] = cscale(u2, inv_n);
+        };
+        column(w0);
+        if (CP == 2) column(w0 + 1);
+    };
+    for (int it = gid; lane_on && it < nitems;) {
+        fetch(it + kGroups, fb);               // the next item's row (clamped past the end)
+        process(fa);
+        it += kGroups;
+        if (it >= nitems) break;
+        fetch(it + kGroups, fa);
+        process(fb);
+        it += kGroups;
+    }
+    __syncthreads();
+    if constexpr (PROBE == 0) fft_lc<T, 1, LC>(buf, I.p1, W, 1, lp, twall);
+    io(false);
+    const double sum = block_sum(e);
+    if (threadIdx.x == 0) I.part_ek[t.slot] = sum;
+}
+
+// ---------------------------------------------------------------- stage probes
+
+// Parity probes (never part of an evaluation): the launches cover the tiles of
+// a whole pass, and every workgroup whose tile belongs to another grid than
+// `target` returns at once (uniformly).
+
+// theta_a(r_i) = n_i p_a(q0_i) (the text after Eq. (Eoffk)) of the tile's
+// points into dst [kNQ][N] (working precision), from n and the stored grad n,
+// as the theta pass forms them.  tile: a = first row, b = rows.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_probe_theta(const InstDev *insts, const Tile *tiles,
+                                                          const Consts *cst, void *dstv, int target) {
+    __shared__ T qm[kNQ], Mm[kNQ * kNQ], invm[kMaxMc + 1];
+    const Tile t = tiles[blockIdx.x];
+    if (t.inst != target) return;
+    const InstDev &I = insts[t.inst];
+    load_consts<T>(cst, qm, Mm, invm);
+    __syncthreads();
+    const int N3 = I.n3;
+    const size_t N = (size_t)I.n1 * I.n2 * I.n3, p0 = (size_t)t.a * N3;
+    const T *nin = reinterpret_cast<const T *>(I.n) + p0;
+    const T *gin = reinterpret_cast<const T *>(I.grad) + p0;
+    T *dst = reinterpret_cast<T *>(dstv) + p0;
+    for (int idx = threadIdx.x; idx < t.b * N3; idx += kThreads) {
+        const T nv = nin[idx];
+        T th[kNQ];
+#pragma unroll
+        for (int a = 0; a < kNQ; ++a) th[a] = (T)0;
+        if (nv >= (T)cst->nmin) {
+            const T gx = gin[idx], gy = gin[N + idx], gz = gin[2 * N + idx];
+            LocalQ<T, false> lq;
+            lq.eval(nv, gx * gx + gy * gy + gz * gz, cst->qc, cst->iqc, cst->mc, invm);
+            SplineW<T> sw;
+            sw.locate(lq.q0, qm, kNQ);
+            const T *Mj = Mm + sw.j * kNQ;
+#pragma unroll
+            for (int a = 0; a < kNQ; ++a) {
+                T v = nv * sw.C0 * Mj[a] + nv * sw.C1 * Mj[kNQ + a];
+                if (a == sw.j) v += nv * sw.A0;
+                if (a == sw.j + 1) v += nv * sw.A1;
+                th[a] = v;
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < kNQ; ++a) dst[a * N + idx] = th[a];
+    }
+}
+
+// u_a(r_i) = sum_G u_a(G) exp(i G.r_i) (Eq. (epsilon)): the inverse axis-3
+// transform of the u spectra, as the assembly pass forms it, into dst
+// [kNQ][N] (working precision).  tile: a = first row, b = rows.
+template <typename T, int LC>
+__global__ void __launch_bounds__(kThreads) k_probe_u(const InstDev *insts, const Tile *tiles, const void *twv,
+                                                      void *dstv, int target) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const Tile t = tiles[blockIdx.x];
+    if (t.inst != target) return;
+    const InstDev &I = insts[t.inst];
+    const int N3 = axis_len<LC>(I.n3), N3h = N3 / 2 + 1, row0 = t.a, B = t.b, ls = N3 + 1;
+    const size_t N = (size_t)I.n1 * I.n2 * I.n3;
+    C2<T> *r2 = reinterpret_cast<C2<T> *>(smem);
+    C2<T> *tw = r2 + kNQ / 2 * B * ls;
+    u_lines_in<T>(r2, ls, reinterpret_cast<const C2<T> *>(I.spec) + (size_t)row0 * N3h * kNQ, B, N3, N3h);
+    load_twiddles<T>(tw, I.p3, reinterpret_cast<const C2<T> *>(twv));
+    __syncthreads();
+    fft_lc<T, 1, LC>(r2, I.p3, kNQ / 2 * B, 1, ls, tw);
+    T *dst = reinterpret_cast<T *>(dstv) + (size_t)row0 * N3;
+    for (int idx = threadIdx.x; idx < (kNQ / 2) * B * N3; idx += kThreads) {
+        const int m = idx / (B * N3), rest = idx - m * B * N3, rb = rest / N3, k = rest - rb * N3;
+        const C2<T> z = r2[(kNQ / 2 * rb + m) * ls + k];
+        dst[(size_t)(2 * m) * N + rest] = z.x;
+        dst[(size_t)(2 * m + 1) * N + rest] = z.y;
+    }
+}
+
+// ---------------------------------------------------------------- launchers
+
+// Kernels that take more than 64 KB of LDS opt in to the device's limit.
+template <typename K>
+static void allow_lds(K kernel, size_t bytes) {
+    if (bytes > 65536) (void)hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+// (launch_lc with ntiles == 0 only raises the kernel's LDS limit: done once
+// when the launches are planned, never while a stream is being captured)
+
+template <typename T, int LC>
+static hipError_t launch_lc(int kind, const LaunchArgs &a) {
+    dim3 grid(a.ntiles), block(kThreads);
+#define VDWNL_LAUNCH(kern, ...)                                                                  \
+    do {                                                                                         \
+        if (a.ntiles == 0) allow_lds(kern, a.lds);                                               \
+        else hipLaunchKernelGGL(kern, grid, block, a.lds, a.stream, a.insts, a.tiles, __VA_ARGS__); \
+    } while (0)
+    switch (kind) {
+        case KX_NFWD: VDWNL_LAUNCH((k_x_nfwd<T, LC>), a.twd); break;
+        case KY_1F: VDWNL_LAUNCH((k_y<double, -1, LC>), a.twd, 2, 1); break;
+        case KZ_GRAD: VDWNL_LAUNCH((k_z_grad<double, LC>), a.twd); break;
+        case KY_3I: VDWNL_LAUNCH((k_y<double, 1, LC>), a.twd, 1, 3); break;
+        case KX_GRAD: VDWNL_LAUNCH((k_x_grad<T, LC>), a.twd); break;
+        case KX_THETA: VDWNL_LAUNCH((k_x_theta<T, LC>), a.cst, a.tw); break;
+        case KY_20F: VDWNL_LAUNCH((k_y<T, -1, LC>), a.tw, 0, kNQ); break;
+        case KZ_MAIN:
+            if (a.general) VDWNL_LAUNCH((k_z_main<T, LC, true, 0>), a.cols, a.tw);
+            else VDWNL_LAUNCH((k_z_main<T, LC, false, 0>), a.cols, a.tw);
+            break;
+        case KY_20I: VDWNL_LAUNCH((k_y<T, 1, LC>), a.tw, 0, kNQ); break;
+        case KX_ASSEMBLE: VDWNL_LAUNCH((k_x_assemble<T, LC, false>), a.cst, a.tw); break;
+        case KX_ASSEMBLE_FD: VDWNL_LAUNCH((k_x_assemble<T, LC, true>), a.cst, a.tw); break;
+        case KY_3F: VDWNL_LAUNCH((k_y<T, -1, LC>), a.tw, 1, 3); break;
+        case KZ_DIV: VDWNL_LAUNCH((k_z_div<T, LC>), a.tw); break;
+        case KY_1I: VDWNL_LAUNCH((k_y<T, 1, LC>), a.tw, 2, 1); break;
+        case KX_FINAL: VDWNL_LAUNCH((k_x_final<T, LC>), a.tw); break;
+        default: return hipErrorInvalidValue;
+    }
+#undef VDWNL_LAUNCH
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_kind_t(int kind, int lc, const LaunchArgs &a) {
+    if (a.ntiles < 0) return hipErrorInvalidValue;
+    if (kind == KF_GRAD || kind == KF_DIV) {   // no FFT and no LDS: one launch for every grid
+        if (a.ntiles == 0) return hipSuccess;
+        if (kind == KF_GRAD) hipLaunchKernelGGL(k_fd_grad<T>, dim3(a.ntiles), dim3(kThreads), 0, a.stream, a.insts, a.tiles);
+        else hipLaunchKernelGGL(k_fd_div<T>, dim3(a.ntiles), dim3(kThreads), 0, a.stream, a.insts, a.tiles);
+        return hipGetLastError();
+    }
+    switch (lc) {
+        case 0: return launch_lc<T, 0>(kind, a);
+        case 1: return launch_lc<T, 1>(kind, a);
+        case 2: return launch_lc<T, 2>(kind, a);
+        case 3: return launch_lc<T, 3>(kind, a);
+        case 4: return launch_lc<T, 4>(kind, a);
+        case 5: return launch_lc<T, 5>(kind, a);
+        case 6: return launch_lc<T, 6>(kind, a);
+        case 7: return launch_lc<T, 7>(kind, a);
+        default: return launch_lc<T, kLenGeneric>(kind, a);
+    }
+}
+
+
+template <typename T, int LC>
+static hipError_t launch_probe_lc(int probe, const LaunchArgs &a, void *dst, int target) {
+    dim3 grid(a.ntiles), block(kThreads);
+#define VDWNL_PROBE(kern, ...)                                                                   \
+    do {                                                                                         \
+        if (a.ntiles == 0) allow_lds(kern, a.lds);                                               \
+        else hipLaunchKernelGGL(kern, grid, block, a.lds, a.stream, a.insts, a.tiles, __VA_ARGS__); \
+    } while (0)
+    switch (probe) {
+        case PROBE_THETA_K:
+            if (a.general) VDWNL_PROBE((k_z_main<T, LC, true, 1>), a.cols, a.tw);
+            else VDWNL_PROBE((k_z_main<T, LC, false, 1>), a.cols, a.tw);
+            break;
+        case PROBE_U_K:
+            if (a.general) VDWNL_PROBE((k_z_main<T, LC, true, 2>), a.cols, a.tw);
+            else VDWNL_PROBE((k_z_main<T, LC, false, 2>), a.cols, a.tw);
+            break;
+        case PROBE_U: VDWNL_PROBE((k_probe_u<T, LC>), a.tw, dst, target); break;
+        case PROBE_THETA:
+            if (a.ntiles > 0)
+                hipLaunchKernelGGL(k_probe_theta<T>, grid, block, 0, a.stream, a.insts, a.tiles, a.cst, dst, target);
+            break;
+        default: return hipErrorInvalidValue;
+    }
+#undef VDWNL_PROBE
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_probe_t(int probe, int lc, const LaunchArgs &a, void *dst, int target) {
+    switch (lc) {
+        case 0: return launch_probe_lc<T, 0>(probe, a, dst, target);
+        case 1: return launch_probe_lc<T, 1>(probe, a, dst, target);
+        case 2: return launch_probe_lc<T, 2>(probe, a, dst, target);
+        case 3: return launch_probe_lc<T, 3>(probe, a, dst, target);
+        case 4: return launch_probe_lc<T, 4>(probe, a, dst, target);
+        case 5: return launch_probe_lc<T, 5>(probe, a, dst, target);
+        case 6: return launch_probe_lc<T, 6>(probe, a, dst, target);
+        case 7: return launch_probe_lc<T, 7>(probe, a, dst, target);
+        default: return launch_probe_lc<T, kLenGeneric>(probe, a, dst, target);
+    }
+}
+
+
+
+}  // namespace vdwnl

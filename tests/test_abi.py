@@ -220,3 +220,35 @@ def test_pass_lists_and_tiling_on_host():
     ws = ctypes.c_int64()
     assert lib.vdwnl_info(h, ctypes.byref(nb), ctypes.byref(ws)) == 0 and nb.value == 1
     lib.vdwnl_destroy(h)
+
+
+def test_log_qmesh_built_by_the_library():
+    """The library's logarithmic q mesh: q_1 and q_c at the ends, increments
+    growing by lambda (the paragraph before Eq. (qsat)), equal to the
+    oracle's mesh; invalid arguments refused."""
+    from oracle import kernel_table as kt
+    for nq, q1, qc, lam in [(20, 0.05, 5.0, 1.17), (12, 0.1, 4.0, 1.3), (30, 0.02, 6.0, 1.05), (8, 0.5, 3.0, 1.0)]:
+        q = B.log_qmesh(nq, q1, qc, lam)
+        assert q[0] == q1 and q[-1] == qc and np.all(np.diff(q) > 0)
+        d = np.diff(q)
+        np.testing.assert_allclose(d[1:] / d[:-1], lam, rtol=1e-9)
+        np.testing.assert_allclose(q, kt.log_qmesh(nq, q1, qc, lam), rtol=1e-14, atol=0)
+    lib = B.load_library()
+    out = np.zeros(4)
+    p = out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    for args in [(1, 0.05, 5.0, 1.17), (4, 0.0, 5.0, 1.17), (4, 5.0, 5.0, 1.17), (4, 0.05, 5.0, 0.9),
+                 (4, 0.05, float("nan"), 1.17)]:
+        assert lib.vdwnl_log_qmesh(*args, p) == E["ARG"]
+    assert lib.vdwnl_log_qmesh(4, 0.05, 5.0, 1.17, None) == E["ARG"]
+
+
+def test_debug_stage_on_host_context():
+    lib, h = _host_ctx()
+    buf = np.zeros(16)
+    p = buf.ctypes.data_as(ctypes.c_void_p)
+    assert lib.vdwnl_debug_stage(None, 0, 0, p, None) == E["ARG"]
+    assert lib.vdwnl_debug_stage(h, 0, 0, None, None) == E["ARG"]
+    assert lib.vdwnl_debug_stage(h, 0, 7, p, None) == E["ARG"]
+    assert lib.vdwnl_debug_stage(h, 0, 0, p, None) == E["STATE"]   # nothing evaluated
+    lib.vdwnl_destroy(h)
+

@@ -96,3 +96,38 @@ def test_autotune_keeps_results_and_is_cached(table):
     v2 = [torch.empty_like(x) for x in n]
     E2 = run(lib2, n, v2)
     assert np.array_equal(E2, E1)
+
+
+def test_tuning_file_persists_across_processes(table, tmp_path, monkeypatch):
+    """Tuned budgets land in the tuning file (a JSON object keyed by device
+    architecture and plan) and a later process planning the same grid list
+    takes its budgets from there: the entry is edited here, and a fresh
+    process must plan with exactly the edited values."""
+    import json
+    import os
+    import subprocess
+    path = tmp_path / "tuning.json"
+    monkeypatch.setenv("VDWNL_TUNE_CACHE", str(path))
+    insts, n = small_batch(3, 32)
+    lib = make_ctx(insts, table, 32)
+    v = [torch.empty_like(x) for x in n]
+    lib.autotune([x.data_ptr() for x in n], [x.data_ptr() for x in v], reps=1)
+    entries = json.load(open(path))
+    say("  tuning file: %s" % entries)
+    assert len(entries) == 1
+    key = next(iter(entries))
+    assert key.startswith("gfx") and entries[key] == list(lib.get_tiling().values())
+    json.dump({key: [24576] * 5}, open(path, "w"))
+    code = ("import sys, json; sys.path.insert(0, %r)\n"
+            "import workloads as W\n"
+            "from paper_0812_0244_amd import VdwNl\n"
+            "insts = W.batch_instances(3)\n"
+            "lib = VdwNl(0)\n"
+            "lib.set_grids([w.shape for w in insts], [w.cell for w in insts], 0, 32)\n"
+            "print(json.dumps(lib.get_tiling()))\n" % os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120,
+                         env=dict(os.environ))
+    assert out.returncode == 0, out.stderr
+    got = json.loads(out.stdout.strip().splitlines()[-1])
+    say("  budgets in the new process: %s" % got)
+    assert list(got.values()) == [24576] * 5
