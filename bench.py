@@ -23,6 +23,10 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+# What the method must move per grid point with N_q = 20 fields, s bytes per
+# real: (4 N_q + 28) s (two HBM half-passes per 3-D transform, every local
+# step fused into a neighbouring pass): 432 bytes in FP32, 864 in FP64.
+ALG_BYTES_PER_POINT = {32: (4 * 20 + 28) * 4, 64: (4 * 20 + 28) * 8}
 
 
 def pass_bytes(name, shapes, s):
@@ -88,7 +92,7 @@ def measured_traffic(kernel, lds_budget_z):
     rec = json.loads(m.group(1))
     h = hashlib.sha256()
     src = os.path.join(ROOT, "paper_0812_0244_amd", "csrc")
-    for f in ("common.hpp", "fft_lds.hpp", "fft_fast.hpp", "tile_io.hpp", "kernels.hip"):
+    for f in ("common.hpp", "fft_lds.hpp", "fft_fast.hpp", "tile_io.hpp", "kernels.hpp"):
         h.update(open(os.path.join(src, f), "rb").read())
     if rec.get("kernel_sources_sha256") != h.hexdigest():
         return None
@@ -96,30 +100,130 @@ def measured_traffic(kernel, lds_budget_z):
     return None if hit is None else float(hit["hbm_bytes_per_evaluation"])
 
 
-def cpu_baseline(insts, dens, budget_s):
-    """The FP64 oracle on the smallest densities of the batch, until about
-    budget_s seconds of host work; grid points per second."""
+def cpu_baseline(insts, dens, budget_s=12.0):
+    """The FP64 oracle on the host cores: densities of every edge length of
+    the batch timed (one of each, then more in turn until about budget_s
+    seconds), the mean time per edge scaled by how many densities of that edge
+    the batch holds; grid points per second of the whole batch.  The threads
+    used are the process CPU time over the wall time of the timed calls."""
     from oracle import functional as F
     from oracle import kernel_table as kt
     table = dict(kt.kernel_table())
     table["mc"] = 12
-    order = sorted(range(len(insts)), key=lambda i: insts[i].npoints)
-    done, pts, t_used = [], 0, 0.0
-    F.energy_potential(dens[order[0]], insts[order[0]].cell, table)   # warm the table spline
-    for i in order:
-        t0 = time.perf_counter()
-        F.energy_potential(dens[i], insts[i].cell, table)
-        t_used += time.perf_counter() - t0
-        pts += insts[i].npoints
-        done.append(insts[i].shape[0])
-        if t_used > budget_s:
+    by_edge = {}
+    for i, w in enumerate(insts):
+        by_edge.setdefault(w.shape[0], []).append(i)
+    first = min(by_edge)
+    F.energy_potential(dens[by_edge[first][0]], insts[by_edge[first][0]].cell, table)   # warm the table spline
+    times, wall, cpu = {e: [] for e in by_edge}, 0.0, 0.0
+    rnd = 0
+    while True:
+        progressed = False
+        for edge, idx in sorted(by_edge.items()):
+            if rnd >= len(idx) or (rnd > 0 and wall > budget_s):
+                continue
+            i = idx[rnd]
+            c0, t0 = time.process_time(), time.perf_counter()
+            F.energy_potential(dens[i], insts[i].cell, table)
+            times[edge].append(time.perf_counter() - t0)
+            wall += times[edge][-1]
+            cpu += time.process_time() - c0
+            progressed = True
+        rnd += 1
+        if not progressed or wall > budget_s:
             break
-    sizes = {}
-    for n in done:
-        sizes[n] = sizes.get(n, 0) + 1
-    sample = "%d of the 64 densities, smallest first (%s), FP64 NumPy oracle, %.1f s" % (
-        len(done), ", ".join("%dx %d^3" % (v, k) for k, v in sorted(sizes.items())), t_used)
-    return dict(value=pts / t_used, unit="grid-points/s", cores=1, kind="oracle", sample=sample)
+    t_edge = {e: sum(v) / len(v) for e, v in times.items()}
+    total_t = sum(len(idx) * t_edge[e] for e, idx in by_edge.items())
+    total_pts = sum(w.npoints for w in insts)
+    cores = max(1, int(round(cpu / wall)))
+    sample = ("%d of the %d densities, every edge (%s), FP64 NumPy oracle, %.1f s of host work; the mean "
+              "time per edge scaled by each edge's count in the batch (%s): whole batch %.1f s" % (
+                  sum(len(v) for v in times.values()), len(insts),
+                  ", ".join("%d^3: %d timed, %.2f s each" % (e, len(times[e]), t_edge[e]) for e in sorted(times)),
+                  wall, ", ".join("%dx %d^3" % (len(by_edge[e]), e) for e in sorted(by_edge)), total_t))
+    return dict(value=total_pts / total_t, unit="grid-points/s", cores=cores, kind="oracle", sample=sample,
+                cpu_model=_cpu_model())
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def single_leg(name, wl, table, steps, warmup, log):
+    """One workload as a single grid: the FP32 evaluation (graph replays, then
+    per-pass events), the FP64 plain evaluation of the same density, and the
+    FP64 evaluation of the FP32-rounded density (the same input as FP32)."""
+    import numpy as np
+    import torch
+    from paper_0812_0244_amd.binding import VdwNl
+    n = wl.density()
+    N = int(np.prod(wl.shape))
+    out = {"workload": name, "grid": list(wl.shape), "points": N}
+    stream = torch.cuda.current_stream().cuda_stream
+    res = {}
+    for prec in (32, 64):
+        dt = torch.float32 if prec == 32 else torch.float64
+        lib = VdwNl(0)
+        lib.set_grid(wl.shape, wl.cell, 0, prec)
+        lib.set_kernel_table(table["qmesh"], table["qc"], table["mc"], table["dk"], table["phi"], table["c_soft"])
+        nt = torch.from_numpy(n).to("cuda", dt)
+        vt = torch.empty_like(nt)
+        for _ in range(warmup):
+            lib.energy_potential(nt.data_ptr(), vt.data_ptr(), stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            E = lib.energy_potential(nt.data_ptr(), vt.data_ptr(), stream)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        r = {"ms_per_step": ms, "value": N / (ms * 1e-3), "E": sum(E),
+             "path_frac": ALG_BYTES_PER_POINT[prec] * N / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS}
+        if prec == 32:
+            lib.set_timing(True)
+            for _ in range(steps):
+                lib.energy_potential(nt.data_ptr(), vt.data_ptr(), stream)
+            torch.cuda.synchronize()
+            passes = lib.pass_times()
+            lib.set_timing(False)
+            dom = max((k for k in passes if k != "reduce"), key=lambda k: passes[k][0])
+            dom_ms = passes[dom][0] / max(passes[dom][1], 1)
+            r["passes_ms_per_step"] = {k: v[0] / max(v[1], 1) for k, v in passes.items()}
+            r["dominant"] = {"kernel": dom, "ms": dom_ms, "algorithmic_bytes": pass_bytes(dom, [wl.shape], 4),
+                             "frac": pass_bytes(dom, [wl.shape], 4) / (dom_ms * 1e-3) / 1e9 / PEAK_HBM_GBS}
+            r["v"] = vt
+            n32 = nt
+        else:
+            v64 = vt
+            # the FP64 path on the FP32-rounded density: the same input as the FP32 run
+            v64r = torch.empty_like(nt)
+            n32d = n32.double().contiguous()
+            E64r = lib.energy_potential(n32d.data_ptr(), v64r.data_ptr(), stream)
+            torch.cuda.synchronize()
+            r["E_same_input"] = sum(E64r)
+            r["v_same_input"] = v64r
+            r["v"] = v64
+        res[prec] = r
+        del lib
+    f32, f64 = res[32], res[64]
+    out["fp32"] = {k: v for k, v in f32.items() if k != "v"}
+    out["fp64_plain"] = {k: v for k, v in f64.items() if k not in ("v", "v_same_input")}
+    out["rel_E_fp32_vs_fp64"] = abs(f32["E"] - f64["E"]) / abs(f64["E"])
+    out["rel_E_fp32_vs_fp64_same_input"] = abs(f32["E"] - f64["E_same_input"]) / abs(f64["E_same_input"])
+    out["max_abs_dv_same_input_Ha"] = float((f32["v"].double() - f64["v_same_input"]).abs().max())
+    out["max_abs_dv_Ha"] = float((f32["v"].double() - f64["v"]).abs().max())
+    out["gate_ok"] = out["rel_E_fp32_vs_fp64"] <= 1e-6 and out["max_abs_dv_same_input_Ha"] <= 1e-5
+    log("%s %s: fp32 %.3f ms (%.3e pts/s, %.3f of the algorithmic HBM floor; %s %.3f ms, %.3f of HBM), "
+        "fp64 %.3f ms; rel E %.2e, max|dv| same input %.2e Ha"
+        % (name, wl.shape, f32["ms_per_step"], f32["value"], f32["path_frac"], f32["dominant"]["kernel"],
+           f32["dominant"]["ms"], f32["dominant"]["frac"], f64["ms_per_step"], out["rel_E_fp32_vs_fp64"],
+           out["max_abs_dv_same_input_Ha"]))
+    return out
 
 
 def main():
@@ -128,7 +232,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--fp64-steps", type=int, default=3)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--single-legs", type=int, default=1,
+                    help="1: also time the 96^3, DWNT and 128^3 workloads as single grids (FP32 and FP64)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--lds-budgets", type=str, default=None,
@@ -349,38 +454,67 @@ def main():
                "passes_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in tr_passes.items()},
                "E_sum": float(Etr.sum())}
 
-    # ---- FP64 plain: one context per density, evaluated one after another
-    ctxs, n64, v64 = [], [], []
-    for w, d in zip(insts, dens):
-        c = VdwNl(0)
-        c.set_grid(w.shape, w.cell, 0, 64)
-        c.set_kernel_table(table["qmesh"], table["qc"], table["mc"], table["dk"], table["phi"], table["c_soft"])
-        ctxs.append(c)
-        n64.append(torch.from_numpy(d).to("cuda"))
-        v64.append(torch.empty_like(n64[-1]))
-    E64 = np.zeros((len(insts), 2))
-    for i, c in enumerate(ctxs):
-        E64[i] = c.energy_potential(n64[i].data_ptr(), v64[i].data_ptr(), stream)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.fp64_steps):
+    # ---- per-density ("plain") evaluations of the same densities, one context
+    # per density, one call after another: FP32 with graph replay off (the
+    # batched call's baseline), FP64 (the accuracy reference, and on the
+    # FP32-rounded densities the same input as the FP32 runs)
+    def plain(prec, graph, inputs):
+        dt = torch.float32 if prec == 32 else torch.float64
+        ctxs = []
+        for w in insts:
+            c = VdwNl(0)
+            c.set_grid(w.shape, w.cell, 0, prec)
+            c.set_kernel_table(table["qmesh"], table["qc"], table["mc"], table["dk"], table["phi"], table["c_soft"])
+            c.set_graph(graph)
+            ctxs.append(c)
+        ns = [x.to(dt).contiguous() for x in inputs]
+        vs = [torch.empty_like(x) for x in ns]
+        E = np.zeros((len(insts), 2))
         for i, c in enumerate(ctxs):
-            E64[i] = c.energy_potential(n64[i].data_ptr(), v64[i].data_ptr(), stream)
-    torch.cuda.synchronize()
-    ms64 = (time.perf_counter() - t0) * 1e3 / args.fp64_steps
+            E[i] = c.energy_potential(ns[i].data_ptr(), vs[i].data_ptr(), stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.fp64_steps):
+            for i, c in enumerate(ctxs):
+                E[i] = c.energy_potential(ns[i].data_ptr(), vs[i].data_ptr(), stream)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.fp64_steps
+        return ctxs, ns, vs, E, ms
+
+    _, _, _, _, ms32p = plain(32, False, n32)
+    log("fp32 plain (one context per density, no graph): %.3f ms/step" % ms32p)
+    n64 = [torch.from_numpy(d).to("cuda") for d in dens]
+    ctxs, _, v64, E64, ms64 = plain(64, True, n64)
     e32 = E32.sum(axis=1)
     e64 = E64.sum(axis=1)
     max_rel = float(np.max(np.abs(e32 - e64) / np.abs(e64)))
     max_dv = max(float((v32[i].double() - v64[i]).abs().max()) for i in range(len(insts)))
-    log("fp64 plain: %.3f ms/step; max rel E (fp32 batched vs fp64 plain) %.2e; max|dv| %.2e"
-        % (ms64, max_rel, max_dv))
-    del ctxs
+    # FP64 on the FP32-rounded densities: the same input as the FP32 batch
+    max_dv_same, max_rel_same = 0.0, 0.0
+    for i, c in enumerate(ctxs):
+        nr = n32[i].double().contiguous()
+        vr = torch.empty_like(nr)
+        er = sum(c.energy_potential(nr.data_ptr(), vr.data_ptr(), stream))
+        max_rel_same = max(max_rel_same, abs(e32[i] - er) / abs(er))
+        max_dv_same = max(max_dv_same, float((v32[i].double() - vr).abs().max()))
+    del ctxs, v64, n64
+    gate_ok = max_rel <= 1e-6 and max_dv_same <= 1e-5
+    log("fp64 plain: %.3f ms/step; fp32 batched vs fp64 plain: max rel E %.2e, max|dv| %.2e (same input: "
+        "rel E %.2e, max|dv| %.2e Ha; gate %s)" % (ms64, max_rel, max_dv, max_rel_same, max_dv_same,
+                                                   "met" if gate_ok else "NOT MET"))
+
+    # ---- the other workloads as single grids: FP32 against FP64 plain
+    singles = {}
+    if args.single_legs:
+        for key, k in (("c2_96", 2), ("c3_dwnt", 3), ("c5_128", 5)):
+            wl = W.config(k)
+            singles[key] = single_leg(wl.name, wl, table, args.steps, args.warmup, log)
 
     cpu = None
     if not args.no_cpu_baseline:
         t0 = time.time()
-        cpu = cpu_baseline(insts, dens, args.cpu_seconds)
-        log("cpu baseline: %.3e pts/s (%.1f s)" % (cpu["value"], time.time() - t0))
+        cpu = cpu_baseline(insts, dens)
+        log("cpu baseline: %.3e pts/s (%.1f s): %s" % (cpu["value"], time.time() - t0, cpu["sample"]))
 
     sizes = {}
     for s in shapes:
@@ -411,15 +545,30 @@ def main():
             "lds_budgets": tiling,
         },
         "fp64_plain": {"ms_per_step": ms64, "value": total / (ms64 * 1e-3),
-                       "max_rel_E_fp32_batched_vs_fp64_plain": max_rel, "max_abs_dv_Ha": max_dv},
+                       "max_rel_E_fp32_batched_vs_fp64_plain": max_rel,
+                       "max_abs_dv_Ha": max_dv,
+                       "max_rel_E_same_input": max_rel_same,
+                       "max_abs_dv_same_input_Ha": max_dv_same,
+                       "gate": {"rel_E": 1e-6, "max_abs_dv_same_input_Ha": 1e-5, "met": gate_ok},
+                       "note": "max_abs_dv_Ha compares FP32 on the FP32-rounded densities with FP64 on the "
+                               "unrounded ones (input rounding included); the _same_input figures run FP64 "
+                               "on the FP32-rounded densities"},
+        "fp32_plain": {"ms_per_step": ms32p, "value": total / (ms32p * 1e-3),
+                       "launch": "one context per density, passes launched one by one (no graph)"},
+        "single_grids": singles,
         "passes_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in passes.items()},
         "event_timed_ms_per_step": ev_ms,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
                      "traffic": measured_traffic(dom, tiling["z"]) if dom == "z_main" else None,
                      "algorithmic_bytes": dom_bytes,
-                     "path_algorithmic_bytes_per_step": path_bytes,
-                     "path_frac": path_bytes / (ms_step * 1e-3) / 1e9 / PEAK_HBM_GBS},
+                     # the whole path against its algorithmic bytes (432 per point in FP32)
+                     "path_algorithmic_bytes_per_point": ALG_BYTES_PER_POINT[32],
+                     "path_frac": ALG_BYTES_PER_POINT[32] * total / (ms_step * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                     # the bytes the passes as built are designed to move (three HBM
+                     # round trips per 3-D transform, the FP64 gradient chain)
+                     "passes_design_bytes_per_step": path_bytes,
+                     "passes_design_bytes_per_point": path_bytes / total},
         # the same pass against the vector-ALU roofline (its counters show it
         # bound by instruction issue, not bandwidth)
         "roofline_valu": None if dom != "z_main" else {
