@@ -132,6 +132,33 @@ int vdwnl_set_kernel_table(vdwnl_ctx *ctx, int32_t nq, const double *qmesh, doub
 int vdwnl_energy_potential(vdwnl_ctx *ctx, const void *n_dev, void *v_dev, double *E_out,
                            void *stream);
 
+/* As vdwnl_energy_potential, for callers that cannot allocate device memory
+ * (code under stream capture, tight serving loops, harnesses that forbid
+ * allocation): this call allocates nothing, neither device nor host memory,
+ * and calls no allocating library routine.  Every device structure of the
+ * evaluation (the per-grid fields and spectra, tile lists, twiddles, kernel
+ * rows, partial sums, instance table and energies) lives in one buffer of
+ * 64 MiB, a static device array of the library, one per GPU the library runs
+ * on (each held from the library's first use of that GPU until the process
+ * ends; its address is taken when a context is created).  A plan fits when
+ * its whole image does: about 64^3 points in FP32 or 48^3 in FP64 for cubic
+ * grids; larger plans return VDWNL_E_UNSUPPORTED_SIZE with the bytes they
+ * need in vdwnl_last_error.  Every call on a GPU shares that GPU's buffer and
+ * it keeps the last call's contents: nothing in it must start at zero (each
+ * evaluation writes every value before reading it), the tables of the plan
+ * are copied in when the buffer holds another plan's, and calls that overlap
+ * on one GPU (from other threads or on other streams) race.  The context must
+ * hold a single grid (vdwnl_set_grid); E_out is a host double[2] as in
+ * vdwnl_energy_potential; the passes are launched one by one on `stream` and
+ * the call returns after the stream has finished.  The semilocal energies of
+ * the whole functional are not kept (vdwnl_semilocal_energies returns
+ * VDWNL_E_STATE after this call).  Errors: VDWNL_E_ARG (null pointer),
+ * VDWNL_E_STATE (no grid or table, a batch plan, a host-only context,
+ * per-pass timing on), VDWNL_E_UNSUPPORTED_SIZE (the plan exceeds the
+ * buffer), VDWNL_E_KRANGE, VDWNL_E_HIP. */
+int vdwnl_energy_potential_noalloc(vdwnl_ctx *ctx, const void *n_dev, void *v_dev, double *E_out,
+                                   void *stream);
+
 /* The planned batch: n_ptrs[nb], v_ptrs[nb] device pointers, E_out[nb][2].
  * The first evaluation after planning captures the whole evaluation (every
  * pass of every grid, the reduction and the copy of the energies) into a HIP

@@ -31,6 +31,7 @@ SIGNATURES = {
     "vdwnl_set_kernel_table": (ctypes.c_int, [_vp, _i32, _dp, ctypes.c_double, _i32, _i32,
                                               ctypes.c_double, _dp, ctypes.c_double]),
     "vdwnl_energy_potential": (ctypes.c_int, [_vp, _vp, _vp, _dp, _vp]),
+    "vdwnl_energy_potential_noalloc": (ctypes.c_int, [_vp, _vp, _vp, _dp, _vp]),
     "vdwnl_energy_potential_batched": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(_vp),
                                                       ctypes.POINTER(_vp), _dp, _vp]),
     "vdwnl_energy_potential_batched_async": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(_vp),
@@ -202,6 +203,15 @@ class VdwNl:
         E = np.zeros(2)
         self._check(self.lib.vdwnl_energy_potential(self.h, _vp(n_ptr), _vp(v_ptr), _as_ptr(E, ctypes.c_double),
                                                     _vp(stream)), "energy_potential")
+        return float(E[0]), float(E[1])
+
+    def energy_potential_noalloc(self, n_ptr: int, v_ptr: int, stream: int = 0):
+        """As energy_potential, through the entry point that allocates nothing
+        (its device structures in the library's static scratch buffer)."""
+        E = np.zeros(2)
+        self._check(self.lib.vdwnl_energy_potential_noalloc(self.h, _vp(n_ptr), _vp(v_ptr),
+                                                            _as_ptr(E, ctypes.c_double), _vp(stream)),
+                    "energy_potential_noalloc")
         return float(E[0]), float(E[1])
 
     def energy_potential_batched(self, n_ptrs, v_ptrs, stream: int = 0):

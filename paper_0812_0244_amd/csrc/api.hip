@@ -211,11 +211,14 @@ struct vdwnl_ctx {
     std::vector<size_t> map_off;
     DevPtrs dp;                           // the image in the context's own buffer (work)
     InstDev *h_inst = nullptr;            // pinned
-    // the host image of the plan (with the kernel rows when it is small)
+    // the host image of the plan, kept for the no-allocation entry point
+    // when the plan fits its scratch buffer (with the kernel rows)
     Image img;
     bool img_valid = false;
     size_t img_need = 0;                  // bytes of the plan's image (0: no plan)
     uint64_t plan_stamp = 0;              // changes whenever the image does
+    std::vector<InstDev> na_inst;         // instance table of the no-allocation entry point
+    std::vector<double> na_E;             // its energies (host)
     struct Launch {
         int kind, lc, off, cnt;
         size_t lds;
@@ -1269,14 +1272,48 @@ static int probe_stage(vdwnl_ctx *c, int stage, int target, void *dst, hipStream
     return VDWNL_OK;
 }
 
-// Plans whose whole device image stays below this keep their host image with
-// the kernel rows (the first evaluation then only copies it).
+// ---------------------------------------------------------------- evaluation without allocation
+
+// The device buffer of vdwnl_energy_potential_noalloc: one per GPU the
+// library runs on (each device holds its own copy of this array, at its own
+// address, from the library's first use of the device until the process
+// ends).  Host code never uses the array's name as an address: the pointer
+// comes from hipGetSymbolAddress, once per device, with that device current.
 constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+struct ScratchSlot {
+    char *ptr = nullptr;       // the device's address of scratch
+    uint64_t owner = 0;        // plan stamp of the image it holds (0: none)
+    uint64_t optin = 0;        // plan stamp whose kernels have their LDS limits raised
+};
+static std::mutex g_scratch_mu;
+static ScratchSlot g_scratch[kMaxDevices];
 static std::mutex g_stamp_mu;
 static uint64_t g_stamp = 0;
 
-// The plan's host image, rebuilt by every set-up call that changes the plan,
-// the table or the tiles; kept (with its kernel rows) only when it is small.
+// Set-up: the address of scratch on `device` (made current for the call;
+// the caller's current device is restored).
+static hipError_t scratch_setup(int device) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch[device].ptr) return hipSuccess;
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    hipError_t e = hipSetDevice(device);
+    if (e == hipSuccess) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e == hipSuccess) g_scratch[device].ptr = (char *)p;
+    }
+    if (prev >= 0) (void)hipSetDevice(prev);
+    return e;
+}
+
+// The plan's host image for the entry point without allocation, rebuilt by
+// every set-up call that changes the plan, the table or the tiles; kept
+// (with its kernel rows) only when the whole image fits the scratch buffer.
 static void refresh_image(vdwnl_ctx *c) {
     c->img = Image();
     c->img_valid = false;
@@ -1293,7 +1330,46 @@ static void refresh_image(vdwnl_ctx *c) {
     c->img_need = probe.total;
     if (probe.total > kScratchBytes) return;
     if (build_image(c, c->img, true) != VDWNL_OK) return;
+    c->na_inst.assign(c->grids.size(), InstDev());
+    c->na_E.assign(4 * c->grids.size(), 0.0);
     c->img_valid = true;
+}
+
+// One evaluation of a single planned grid with every device structure in
+// this device's scratch: the image is copied in when the scratch holds
+// another one, then the instance table, the passes launched one by one, the
+// reduction and the energies, all on st; returns after st has finished.
+static int run_noalloc(vdwnl_ctx *c, const void *n_dev, void *v_dev, double *E_out, hipStream_t st) {
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hipfail(c, e, "hipSetDevice");
+    if ((e = scratch_setup(c->device)) != hipSuccess) return hipfail(c, e, "hipGetSymbolAddress(scratch)");
+    ScratchSlot &slot = g_scratch[c->device];
+    const DevPtrs P = place(c->img, slot.ptr);
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (slot.optin != c->plan_stamp) {
+            const int rc = lds_optin(c);
+            if (rc != VDWNL_OK) return rc;
+            slot.optin = c->plan_stamp;
+        }
+        if (slot.owner != c->plan_stamp) {
+            slot.owner = 0;
+            const int rc = upload_image(c, c->img, P, st);
+            if (rc != VDWNL_OK) return rc;
+            slot.owner = c->plan_stamp;
+        }
+    }
+    InstDev *hi = c->na_inst.data();
+    fill_insts(c, slot.ptr, hi);
+    hi[0].n = n_dev;
+    hi[0].v = v_dev;
+    hi[0].semilocal = c->functional == VDWNL_FUNCTIONAL_VDW_DF;
+    const int rc = enqueue(c, P, hi, c->na_E.data(), 1, st);
+    if (rc != VDWNL_OK) return rc;
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return hipfail(c, e, "stream synchronize");
+    E_out[0] = c->na_E[0];
+    E_out[1] = c->na_E[1];
+    return VDWNL_OK;
 }
 
 // Logarithmic q mesh of the interpolation: q_1 = q1, q_nq = q_c, increments
@@ -1362,6 +1438,15 @@ int vdwnl_create(vdwnl_ctx **out, int device) {
         }
     }
     std::memset(&c->consts, 0, sizeof(Consts));
+    if (device >= 0) {
+        // set-up of the no-allocation entry point's buffer on this device
+        const hipError_t e = scratch_setup(device);
+        if (e != hipSuccess) {
+            g_create_err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+            delete c;
+            return VDWNL_E_HIP;
+        }
+    }
     *out = c;
     return VDWNL_OK;
 }
@@ -1463,6 +1548,27 @@ int vdwnl_energy_potential(vdwnl_ctx *ctx, const void *n_dev, void *v_dev, doubl
     const void *np[1] = {n_dev};
     void *vp[1] = {v_dev};
     return run(ctx, 1, np, vp, E_out, stream);
+}
+
+int vdwnl_energy_potential_noalloc(vdwnl_ctx *ctx, const void *n_dev, void *v_dev, double *E_out, void *stream) {
+    if (!ctx) return VDWNL_E_ARG;
+    if (!n_dev || !v_dev || !E_out) return fail(ctx, VDWNL_E_ARG, "null pointer");
+    if (!ctx->have_grid || !ctx->have_table) return fail(ctx, VDWNL_E_STATE, "grid and kernel table must both be set");
+    if (ctx->grids.size() != 1) return fail(ctx, VDWNL_E_STATE, "context holds a batch plan");
+    if (ctx->device < 0) return fail(ctx, VDWNL_E_STATE, "host-only context");
+    if (ctx->timing) return fail(ctx, VDWNL_E_STATE, "per-pass timing needs vdwnl_energy_potential");
+    const int krc = check_krange(ctx);
+    if (krc != VDWNL_OK) return krc;
+    if (!ctx->img_valid) {
+        char msg[200];
+        std::snprintf(msg, sizeof(msg),
+                      "the plan needs %zu bytes of device scratch; vdwnl_energy_potential_noalloc has %zu",
+                      ctx->img_need, kScratchBytes);
+        return fail(ctx, VDWNL_E_UNSUPPORTED_SIZE, msg);
+    }
+    const int rc = run_noalloc(ctx, n_dev, v_dev, E_out, (hipStream_t)stream);
+    ctx->last_functional = -1;   // (its semilocal energies are not kept)
+    return rc;
 }
 
 int vdwnl_energy_potential_batched(vdwnl_ctx *ctx, int32_t nb, const void *const *n_ptrs, void *const *v_ptrs,

@@ -252,3 +252,16 @@ def test_debug_stage_on_host_context():
     assert lib.vdwnl_debug_stage(h, 0, 0, p, None) == E["STATE"]   # nothing evaluated
     lib.vdwnl_destroy(h)
 
+
+def test_noalloc_entry_point_on_host_context():
+    lib, h = _host_ctx()
+    Eo = np.zeros(2)
+    pe = Eo.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    buf = np.zeros(8)
+    p = buf.ctypes.data_as(ctypes.c_void_p)
+    assert lib.vdwnl_energy_potential_noalloc(None, p, p, pe, None) == E["ARG"]
+    assert lib.vdwnl_energy_potential_noalloc(h, None, p, pe, None) == E["ARG"]
+    assert lib.vdwnl_energy_potential_noalloc(h, p, p, pe, None) == E["STATE"]   # no plan
+    assert _set_grid(lib, h, (24, 24, 24)) == 0
+    assert lib.vdwnl_energy_potential_noalloc(h, p, p, pe, None) == E["STATE"]   # no table, host only
+    lib.vdwnl_destroy(h)
