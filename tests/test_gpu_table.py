@@ -2,7 +2,10 @@
 independent one (different quadratures, ray sampling and radial transform).
 Each is accurate to about 1e-7..1e-6 (the slope at d_s, the quadrature near
 the logarithmic divergence, the interpolation along the rays), which sets
-the tolerances."""
+the tolerances: 2e-5 of each pair's largest value for every pair, the most
+skewed rays (q_b/q_a = 100) included (measured 1.3e-6), on the default q mesh
+and on others (the mesh is the caller's choice, as the paper's construction
+allows: any increasing mesh ending at q_c)."""
 import sys
 import time
 
@@ -34,17 +37,64 @@ def test_tables_agree(gpu_table, table):
     a, b = gpu_table["phi"], table["phi"]
     assert np.array_equal(a, a.transpose(1, 0, 2))
     q = table["qmesh"]
-    worst = 0.0
-    for i in range(20):
-        for j in range(i, 20):
-            scale = np.abs(b[i, j]).max()
-            err = np.abs(a[i, j] - b[i, j]).max() / scale
-            ratio = max(q[i], q[j]) / min(q[i], q[j])
-            worst = max(worst, err) if ratio < 8 else worst
-            tol = 2e-5 if ratio < 8 else 2e-3
-            assert err < tol, (i, j, err)
-    print("  max relative table difference (q ratio < 8): %.2e" % worst, flush=True)
+    worst = _worst_pair(a, b)
+    print("  max relative table difference: %.2e (pair %s)" % worst, flush=True)
+    assert worst[0] < 2e-5
     np.testing.assert_allclose(np.diag(a[:, :, 0]), -2 * gpu_table["c_soft"] / q ** 3, rtol=1e-6)
+
+
+def _worst_pair(a, b):
+    nq = b.shape[0]
+    worst = (0.0, None)
+    for i in range(nq):
+        for j in range(i, nq):
+            err = np.abs(a[i, j] - b[i, j]).max() / np.abs(b[i, j]).max()
+            if err > worst[0]:
+                worst = (err, (i, j))
+    return worst
+
+
+@pytest.mark.parametrize("params", [dict(nq=6, q1=0.1, qc=4.0, lam=1.4, nk=1601, dk=0.02),
+                                    dict(nq=20, q1=0.08, qc=4.0, lam=1.15, nk=6401, dk=0.005)])
+def test_tables_agree_on_other_q_meshes(params):
+    """Other q meshes (fewer points, another q_1, q_c and growth factor) and
+    radial meshes: the two generators agree to the same 2e-5 on every pair."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from oracle import kernel_table as kt
+    from paper_0812_0244_amd.binding import build_kernel_table
+    o = kt.kernel_table(**params)
+    g = build_kernel_table(0, nq=params["nq"], q1=params["q1"], qc=params["qc"], lam=params["lam"],
+                           nk=params["nk"], dk=params["dk"])
+    np.testing.assert_allclose(g["qmesh"], o["qmesh"], rtol=1e-14)
+    np.testing.assert_allclose(g["c_soft"], o["c_soft"], rtol=1e-6)
+    worst = _worst_pair(g["phi"], o["phi"])
+    print("  %s: max relative table difference %.2e (pair %s)" % (params, worst[0], worst[1]), flush=True)
+    assert worst[0] < 2e-5
+
+
+def test_evaluation_on_another_q_mesh():
+    """The whole evaluation with a non-default mesh (q_1 = 0.08, q_c = 4,
+    lambda = 1.15, so the saturation of Eq. (Sat) differs too): FP64 against
+    the oracle with the oracle's table for that mesh."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import workloads as W
+    from oracle import functional as F
+    from oracle import kernel_table as kt
+    from paper_0812_0244_amd import NonlocalCorrelation
+    t = dict(kt.kernel_table(q1=0.08, qc=4.0, lam=1.15))
+    t["mc"] = 12
+    for wl in (W.config(1), W.batch_instances(3)[2]):
+        n = wl.density()
+        ek_o, de_o, v_o = F.energy_potential(n, wl.cell, t)
+        eng = NonlocalCorrelation(wl.shape, wl.cell, t, precision=64)
+        ek, de, v = eng.energy_potential(torch.from_numpy(n).cuda())
+        v = v.cpu().numpy()
+        print("  %s: E_k %.14e / %.14e  dE %.14e / %.14e  max|dv| %.2e"
+              % (wl.shape, ek, ek_o, de, de_o, np.abs(v - v_o).max()), flush=True)
+        assert abs(ek - ek_o) <= 1e-10 * abs(ek_o) and abs(de - de_o) <= 1e-10 * abs(de_o)
+        assert np.abs(v - v_o).max() <= 1e-10 * np.abs(v_o).max()
 
 
 def test_energy_with_either_table(gpu_table, table):
