@@ -298,7 +298,7 @@ def main():
     elif not args.no_autotune:
         lib.autotune(nptr, vptr, reps=5, stream=stream)
     tiling = lib.get_tiling()
-    log("tile budgets %s (%.1f s)" % (tiling, time.time() - t0))
+    log("tile budgets %s, contraction unit %d (%.1f s)" % (tiling, lib.get_contraction(), time.time() - t0))
     for _ in range(args.warmup):
         lib.energy_potential_batched(nptr, vptr, stream)
     torch.cuda.synchronize()
@@ -325,6 +325,35 @@ def main():
     log("fp32 batched (event-timed launches): %.3f ms/step of passes" % ev_ms)
     for k, (ms, calls) in passes.items():
         log("  pass %-10s %8.3f ms/step" % (k, ms / max(calls, 1)))
+
+    # the per-k contraction on either unit (the tuned budgets kept): whole
+    # step by graph replay and the fused pass by events, an A/B of the vector
+    # ALU against the matrix cores
+    from paper_0812_0244_amd.binding import CONTRACTION_MATRIX, CONTRACTION_VECTOR
+    chosen = lib.get_contraction()
+    contraction_ab = {"chosen": "matrix" if chosen == CONTRACTION_MATRIX else "vector"}
+    for name, unit in (("vector", CONTRACTION_VECTOR), ("matrix", CONTRACTION_MATRIX)):
+        lib.set_contraction(unit)
+        for _ in range(args.warmup):
+            lib.energy_potential_batched(nptr, vptr, stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            lib.energy_potential_batched(nptr, vptr, stream)
+        torch.cuda.synchronize()
+        ab_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        lib.set_timing(True)
+        for _ in range(args.steps):
+            lib.energy_potential_batched(nptr, vptr, stream)
+        torch.cuda.synchronize()
+        ab_pass = lib.pass_times()["z_main"]
+        lib.set_timing(False)
+        contraction_ab[name] = {"ms_per_step": ab_ms, "z_main_ms": ab_pass[0] / max(ab_pass[1], 1)}
+        log("contraction on the %s unit: %.3f ms/step, z_main %.3f ms" % (name, ab_ms, contraction_ab[name]["z_main_ms"]))
+    lib.set_contraction(chosen)
+    for _ in range(args.warmup):
+        lib.energy_potential_batched(nptr, vptr, stream)
+    torch.cuda.synchronize()
 
     # dominant pass and its roofline (bytes and time per step: the pass's
     # launches over every grid of the batch)
@@ -558,6 +587,7 @@ def main():
         "single_grids": singles,
         "passes_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in passes.items()},
         "event_timed_ms_per_step": ev_ms,
+        "contraction_ab": contraction_ab,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
                      "traffic": measured_traffic(dom, tiling["z"]) if dom == "z_main" else None,

@@ -287,6 +287,25 @@ int vdwnl_set_graph(vdwnl_ctx *ctx, int32_t on);
 int vdwnl_autotune(vdwnl_ctx *ctx, int32_t nb, const void *const *n_ptrs, void *const *v_ptrs,
                    int32_t reps, void *stream);
 
+/* Schedule choices of the evaluation (they change no result beyond the order
+ * of FP32 additions):
+ *   VDWNL_SCHEDULE_CONTRACTION  the unit that forms the per-k contraction
+ *     u_a(k) = sum_b phi_ab(|k|) c_b(k) of Eqs. (Eoffk)/(epsofk) in the fused
+ *     axis-1 pass of FP32 grids in orthorhombic cells:
+ *     VDWNL_CONTRACTION_VECTOR (the vector ALU, a lane per output component)
+ *     or VDWNL_CONTRACTION_MATRIX (the matrix cores: 16-block 4 x 4 x 1 FP32
+ *     outer products, 15 blocks per instruction for the 20 x 20 matrices of
+ *     three k-point groups); FP64 and general cells always use the vector ALU.
+ * vdwnl_autotune chooses the contraction unit together with the LDS budgets
+ * (and a plan reuses a tuned choice as it does the budgets); otherwise the
+ * matrix cores.  Setting it re-plans the launches (the workspace is rebuilt
+ * at the next evaluation).  VDWNL_E_ARG for an unknown choice or value;
+ * VDWNL_E_STATE without a planned grid. */
+enum { VDWNL_SCHEDULE_CONTRACTION = 0 };
+enum { VDWNL_CONTRACTION_VECTOR = 0, VDWNL_CONTRACTION_MATRIX = 1 };
+int vdwnl_set_schedule(vdwnl_ctx *ctx, int32_t what, int32_t value);
+int vdwnl_get_schedule(const vdwnl_ctx *ctx, int32_t what, int32_t *value);
+
 /* LDS budget (bytes) of each pass group in the current plan, in the order
  * axis-3 (theta, assembly), axis-2 over the 20 spectra, axis-2 over the
  * gradient / divergence spectra, axis-1 with the contraction, axis-1 of the

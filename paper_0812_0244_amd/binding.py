@@ -53,12 +53,16 @@ SIGNATURES = {
     "vdwnl_autotune": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _i32, _vp]),
     "vdwnl_get_tiling": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(ctypes.c_int64)]),
     "vdwnl_set_tiling": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(ctypes.c_int64)]),
+    "vdwnl_set_schedule": (ctypes.c_int, [_vp, _i32, _i32]),
+    "vdwnl_get_schedule": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(_i32)]),
 }
 
 _lib = None
 
 FUNCTIONAL_NONLOCAL = 0
 FUNCTIONAL_VDW_DF = 1
+SCHEDULE_CONTRACTION = 0
+CONTRACTION_VECTOR, CONTRACTION_MATRIX = 0, 1
 
 
 class VdwNlError(RuntimeError):
@@ -259,6 +263,15 @@ class VdwNl:
             budgets = [budgets[k] for k in ("x", "y20", "yaux", "z", "zaux")]
         b = (ctypes.c_int64 * 5)(*[int(x) for x in budgets])
         self._check(self.lib.vdwnl_set_tiling(self.h, 5, b), "set_tiling")
+
+    def set_contraction(self, unit: int):
+        """CONTRACTION_VECTOR or CONTRACTION_MATRIX (the per-k contraction's unit)."""
+        self._check(self.lib.vdwnl_set_schedule(self.h, SCHEDULE_CONTRACTION, int(unit)), "set_schedule")
+
+    def get_contraction(self) -> int:
+        v = _i32()
+        self._check(self.lib.vdwnl_get_schedule(self.h, SCHEDULE_CONTRACTION, ctypes.byref(v)), "get_schedule")
+        return int(v.value)
 
     def get_tiling(self):
         """LDS budget (bytes) per pass group: x, y20, yaux, z, zaux."""

@@ -122,6 +122,9 @@ static Shells build_shells(const int s[3], const double cell[3]) {
     return shells_from_keys(key);
 }
 
+// Contraction unit of a plan with no tuned choice.
+constexpr int kDefaultContraction = VDWNL_CONTRACTION_MATRIX;
+
 // Pass groups whose tile shapes follow one LDS budget each.
 enum TileGroup { TG_X = 0, TG_Y20, TG_YAUX, TG_Z, TG_ZAUX, TG_COUNT };
 
@@ -189,6 +192,7 @@ struct vdwnl_ctx {
     int pending_functional = -1;
     std::string err;
     size_t pref[TG_COUNT] = {kLdsCap, kLdsCap, kLdsCap, kLdsCap, kLdsCap};   // LDS budget per pass group
+    int contraction = VDWNL_CONTRACTION_VECTOR;   // unit of the per-k contraction (FP32, orthorhombic)
     std::string plan_key;                 // identifies the batch for the tuned-budget cache
     std::string arch = "host";            // device architecture (gcnArchName)
     // plan
@@ -224,6 +228,7 @@ struct vdwnl_ctx {
         size_t lds;
         int group;
         int general;          // grids of the group in non-orthogonal cells
+        int mfma;             // (fused axis-1 pass) the contraction on the matrix cores
     };
     // per pass: one launch per group of grids (grids whose three axes fall in
     // the same FFT length classes); the groups' chains of passes are
@@ -428,12 +433,13 @@ static void size_tiles(const vdwnl_ctx *c, Grid &g) {
 // gradient mode and the exact list of grid shapes and cells: a map for the
 // process, backed by a file so that later processes reuse them.  The file is
 // a JSON object with one entry per line,
-//   "<arch>/<hash of the rest of the key>": [x, y20, yaux, z, zaux],
+//   "<arch>/<hash of the rest of the key>": [x, y20, yaux, z, zaux, contraction],
 // at $VDWNL_TUNE_CACHE (empty: no file), else $XDG_CACHE_HOME/vdwnl/tuning.json
 // or $HOME/.cache/vdwnl/tuning.json.  A file that cannot be read or written
 // is ignored (the process map still works).
 static std::mutex g_tuned_mu;
 static std::map<std::string, std::vector<size_t>> g_tuned;
+constexpr int kTuneVals = TG_COUNT + 1;   // the five budgets and the contraction unit
 
 static std::string plan_key(const vdwnl_ctx *c) {
     std::string k = std::to_string(c->precision) + "/" + std::to_string(c->grad_mode) + "/" + std::to_string(c->lds_cap);
@@ -475,7 +481,7 @@ static std::map<std::string, std::vector<size_t>> read_tune_file(const std::stri
         if (!br) continue;
         std::vector<size_t> v;
         const char *p = br + 1;
-        while (v.size() < (size_t)TG_COUNT) {
+        while (v.size() < (size_t)kTuneVals) {
             char *end = nullptr;
             const unsigned long long x = std::strtoull(p, &end, 10);
             if (end == p) break;
@@ -483,7 +489,7 @@ static std::map<std::string, std::vector<size_t>> read_tune_file(const std::stri
             p = end;
             while (*p == ',' || *p == ' ') ++p;
         }
-        if (v.size() == (size_t)TG_COUNT) out[std::string(q0 + 1, q1)] = v;
+        if (v.size() == (size_t)kTuneVals) out[std::string(q0 + 1, q1)] = v;
     }
     std::fclose(f);
     return out;
@@ -505,7 +511,7 @@ static void write_tune_file(const std::string &path, const std::map<std::string,
     size_t i = 0;
     for (const auto &kv : m) {
         std::fprintf(f, "  \"%s\": [", kv.first.c_str());
-        for (int g = 0; g < TG_COUNT; ++g) std::fprintf(f, g ? ", %zu" : "%zu", kv.second[g]);
+        for (int g = 0; g < kTuneVals; ++g) std::fprintf(f, g ? ", %zu" : "%zu", kv.second[g]);
         std::fprintf(f, "]%s\n", ++i < m.size() ? "," : "");
     }
     std::fprintf(f, "}\n");
@@ -514,24 +520,28 @@ static void write_tune_file(const std::string &path, const std::map<std::string,
     else (void)std::remove(tmp.c_str());
 }
 
-static bool tuned_lookup(const std::string &key, size_t *pref, size_t cap) {
+static bool tuned_lookup(const std::string &key, size_t *pref, int *contraction, size_t cap) {
     std::lock_guard<std::mutex> lk(g_tuned_mu);
     auto it = g_tuned.find(key);
     if (it == g_tuned.end()) {
         auto file = read_tune_file(tune_cache_path());
         auto ft = file.find(key);
         if (ft == file.end()) return false;
-        for (size_t b : ft->second)
-            if (b < 4096 || b > cap) return false;    // (not a budget this device accepts)
+        for (int i = 0; i < TG_COUNT; ++i)
+            if (ft->second[i] < 4096 || ft->second[i] > cap) return false;   // (not a budget this device accepts)
+        if (ft->second[TG_COUNT] > 1) return false;
         it = g_tuned.insert(*ft).first;
     }
     for (int i = 0; i < TG_COUNT; ++i) pref[i] = it->second[i];
+    *contraction = (int)it->second[TG_COUNT];
     return true;
 }
 
-static void tuned_store(const std::string &key, const size_t *pref) {
+static void tuned_store(const std::string &key, const size_t *pref, int contraction) {
     std::lock_guard<std::mutex> lk(g_tuned_mu);
-    g_tuned[key] = std::vector<size_t>(pref, pref + TG_COUNT);
+    std::vector<size_t> v(pref, pref + TG_COUNT);
+    v.push_back((size_t)contraction);
+    g_tuned[key] = v;
     const std::string path = tune_cache_path();
     auto file = read_tune_file(path);
     file[key] = g_tuned[key];
@@ -556,8 +566,10 @@ static int plan_grids(vdwnl_ctx *c, int nb, const int32_t *shapes, const double 
     c->grad_mode = grad_mode;
     // tile budgets: a tuned set for this exact batch if one exists, else defaults
     c->plan_key = plan_key(c);
-    if (!tuned_lookup(c->plan_key, c->pref, c->lds_cap))
+    if (!tuned_lookup(c->plan_key, c->pref, &c->contraction, c->lds_cap)) {
         for (auto &p : c->pref) p = std::min<size_t>(c->lds_cap, kLdsCap);
+        c->contraction = kDefaultContraction;
+    }
     for (auto &g : c->grids) size_tiles(c, g);
     c->shells.clear();
     c->shell_keys.clear();
@@ -830,11 +842,13 @@ static int build_image(vdwnl_ctx *c, Image &im, bool keep_tables) {
     for (int k = 0; k < KIND_COUNT; ++k) {
         c->launches[k].clear();
         for (int grp = 0; grp < c->ngroups; ++grp) {
-            vdwnl_ctx::Launch L{k, 0, (int)all.size(), 0, 0, grp, 0};
+            vdwnl_ctx::Launch L{k, 0, (int)all.size(), 0, 0, grp, 0, 0};
             for (const Tile &tl : tiles[k]) {
                 if (group_of[tl.inst] != grp) continue;
                 const Grid &g = c->grids[tl.inst];
                 L.general = g.general ? 1 : 0;
+                L.mfma = (k == KZ_MAIN && c->precision == 32 && !g.general && c->contraction == VDWNL_CONTRACTION_MATRIX)
+                             ? 1 : 0;
                 // the stencil passes transform nothing (class 0 for any grid)
                 L.lc = (k == KF_GRAD || k == KF_DIV) ? 0 : len_class(axis_len(k, g));
                 all.push_back(tl);
@@ -902,7 +916,7 @@ static int lds_optin(vdwnl_ctx *c) {
     hipError_t e;
     for (int k = 0; k < KIND_COUNT; ++k)
         for (const auto &L : c->launches[k]) {
-            LaunchArgs a{nullptr, nullptr, 0, L.lds, nullptr, nullptr, nullptr, nullptr, nullptr, L.general};
+            LaunchArgs a{nullptr, nullptr, 0, L.lds, nullptr, nullptr, nullptr, nullptr, nullptr, L.general, L.mfma};
             if ((e = launch_kind(k, L.lc, c->precision, a)) != hipSuccess) return hipfail(c, e, "kernel LDS limit");
             // (and the stage probes that stand in for the pass)
             for (int pr : {PROBE_THETA_K, PROBE_U_K, PROBE_U}) {
@@ -1084,7 +1098,7 @@ static int enqueue(vdwnl_ctx *c, const DevPtrs &P, const InstDev *hinst, double 
     const int *order;
     const int npass = pass_order(c->grad_mode, &order);
     auto launch = [&](const vdwnl_ctx::Launch &L, hipStream_t s) -> int {
-        LaunchArgs a{P.inst, P.tiles + L.off, L.cnt, L.lds, P.consts, P.tw, P.twd, s, P.cols, L.general};
+        LaunchArgs a{P.inst, P.tiles + L.off, L.cnt, L.lds, P.consts, P.tw, P.twd, s, P.cols, L.general, L.mfma};
         const hipError_t le = launch_kind(L.kind, L.lc, c->precision, a);
         return le == hipSuccess ? VDWNL_OK : hipfail(c, le, "kernel launch");
     };
@@ -1250,7 +1264,7 @@ static int probe_stage(vdwnl_ctx *c, int stage, int target, void *dst, hipStream
     }
     auto args = [&](const vdwnl_ctx::Launch &L) {
         return LaunchArgs{c->dp.inst, c->dp.tiles + L.off, L.cnt, L.lds, c->dp.consts, c->dp.tw, c->dp.twd, st, c->dp.cols,
-                          L.general};
+                          L.general, L.mfma};
     };
     for (int i = 0; i < npass && order[i] != stop; ++i)
         for (const auto &L : c->launches[order[i]])
@@ -1665,44 +1679,62 @@ int vdwnl_autotune(vdwnl_ctx *ctx, int32_t nb, const void *const *n_ptrs, void *
         if (b <= ctx->lds_cap) cand.push_back(b);
     const bool timing0 = ctx->timing;
     ctx->img_valid = false;     // (the candidates' tiles differ from the image's)
-    std::vector<std::vector<double>> t(cand.size(), std::vector<double>(KIND_COUNT, 0.0));
+    // contraction units to try: the vector ALU, and the matrix cores where
+    // some grid takes them (FP32, orthorhombic cell)
+    std::vector<int> units = {VDWNL_CONTRACTION_VECTOR};
+    bool any_orth = false;
+    for (const auto &g : ctx->grids) any_orth = any_orth || !g.general;
+    if (ctx->precision == 32 && any_orth) units.push_back(VDWNL_CONTRACTION_MATRIX);
+    // t[unit][candidate][pass kind]
+    std::vector<std::vector<std::vector<double>>> t(
+        units.size(), std::vector<std::vector<double>>(cand.size(), std::vector<double>(KIND_COUNT, 0.0)));
     int rc = VDWNL_OK;
     std::vector<double> E((size_t)nb * 2);
-    for (size_t ci = 0; ci < cand.size() && rc == VDWNL_OK; ++ci) {
-        for (auto &p : ctx->pref) p = cand[ci];
-        for (auto &g : ctx->grids) size_tiles(ctx, g);
-        free_device(ctx);
-        ctx->timing = false;
-        rc = run(ctx, nb, n_ptrs, v_ptrs, E.data(), stream);   // plans and warms up
-        if (rc != VDWNL_OK) break;
-        vdwnl_set_timing(ctx, 1);
-        for (int r = 0; r < reps && rc == VDWNL_OK; ++r) rc = run(ctx, nb, n_ptrs, v_ptrs, E.data(), stream);
-        for (int k = 0; k < KIND_COUNT; ++k) t[ci][k] = ctx->pass_ms[k];
-    }
+    for (size_t ui = 0; ui < units.size() && rc == VDWNL_OK; ++ui)
+        for (size_t ci = 0; ci < cand.size() && rc == VDWNL_OK; ++ci) {
+            ctx->contraction = units[ui];
+            for (auto &p : ctx->pref) p = cand[ci];
+            for (auto &g : ctx->grids) size_tiles(ctx, g);
+            free_device(ctx);
+            ctx->timing = false;
+            rc = run(ctx, nb, n_ptrs, v_ptrs, E.data(), stream);   // plans and warms up
+            if (rc != VDWNL_OK) break;
+            vdwnl_set_timing(ctx, 1);
+            for (int r = 0; r < reps && rc == VDWNL_OK; ++r) rc = run(ctx, nb, n_ptrs, v_ptrs, E.data(), stream);
+            for (int k = 0; k < KIND_COUNT; ++k) t[ui][ci][k] = ctx->pass_ms[k];
+        }
     // per group, the budget with the least time over the group's passes (a
-    // group with no pass in this gradient mode keeps the default)
+    // group with no pass in this gradient mode keeps the default); for the
+    // fused axis-1 group, the budget and the contraction unit together
     const std::vector<std::vector<int>> groups = {{KX_THETA, KX_ASSEMBLE, KX_ASSEMBLE_FD},
                                                   {KY_20F, KY_20I},
                                                   {KY_1F, KY_1I, KY_3F, KY_3I},
                                                   {KZ_MAIN},
                                                   {KZ_GRAD, KZ_DIV}};
     size_t best[TG_COUNT];
+    int best_unit = VDWNL_CONTRACTION_VECTOR;
     for (int gi = 0; gi < TG_COUNT; ++gi) {
         double bt = 1e300;
         best[gi] = std::min<size_t>(ctx->lds_cap, kLdsCap);
-        for (size_t ci = 0; rc == VDWNL_OK && ci < cand.size(); ++ci) {
-            double sum = 0.0;
-            for (int k : groups[gi]) sum += t[ci][k];
-            if (sum > 0.0 && sum < bt) { bt = sum; best[gi] = cand[ci]; }
-        }
+        for (size_t ui = 0; ui < (gi == TG_Z ? units.size() : 1); ++ui)
+            for (size_t ci = 0; rc == VDWNL_OK && ci < cand.size(); ++ci) {
+                double sum = 0.0;
+                for (int k : groups[gi]) sum += t[ui][ci][k];
+                if (sum > 0.0 && sum < bt) {
+                    bt = sum;
+                    best[gi] = cand[ci];
+                    if (gi == TG_Z) best_unit = units[ui];
+                }
+            }
     }
+    ctx->contraction = best_unit;
     for (int gi = 0; gi < TG_COUNT; ++gi) ctx->pref[gi] = best[gi];
     for (auto &g : ctx->grids) size_tiles(ctx, g);
     free_device(ctx);
     refresh_image(ctx);
     vdwnl_set_timing(ctx, timing0 ? 1 : 0);
     if (rc != VDWNL_OK) return rc;
-    tuned_store(ctx->plan_key, ctx->pref);
+    tuned_store(ctx->plan_key, ctx->pref, ctx->contraction);
     return VDWNL_OK;
 }
 
@@ -1717,6 +1749,25 @@ int vdwnl_set_tiling(vdwnl_ctx *ctx, int32_t ngroups, const int64_t *lds_budget)
     for (auto &g : ctx->grids) size_tiles(ctx, g);
     free_device(ctx);
     refresh_image(ctx);
+    return VDWNL_OK;
+}
+
+int vdwnl_set_schedule(vdwnl_ctx *ctx, int32_t what, int32_t value) {
+    if (!ctx) return VDWNL_E_ARG;
+    if (what != VDWNL_SCHEDULE_CONTRACTION) return fail(ctx, VDWNL_E_ARG, "unknown schedule choice");
+    if (value != VDWNL_CONTRACTION_VECTOR && value != VDWNL_CONTRACTION_MATRIX)
+        return fail(ctx, VDWNL_E_ARG, "contraction must be VDWNL_CONTRACTION_VECTOR or VDWNL_CONTRACTION_MATRIX");
+    if (!ctx->have_grid) return fail(ctx, VDWNL_E_STATE, "no grid planned");
+    ctx->contraction = value;
+    free_device(ctx);
+    refresh_image(ctx);
+    return VDWNL_OK;
+}
+
+int vdwnl_get_schedule(const vdwnl_ctx *ctx, int32_t what, int32_t *value) {
+    if (!ctx || !value) return VDWNL_E_ARG;
+    if (what != VDWNL_SCHEDULE_CONTRACTION) return VDWNL_E_ARG;
+    *value = ctx->contraction;
     return VDWNL_OK;
 }
 

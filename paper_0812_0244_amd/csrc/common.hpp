@@ -122,6 +122,7 @@ struct LaunchArgs {
     hipStream_t stream;
     const int2 *cols;        // (k2, k3) columns of the fused axis-1 tiles
     int general;             // the launch's grids have non-orthogonal cells (packed shell rows)
+    int mfma = 0;            // FP32 orthorhombic fused axis-1 pass: contraction on the matrix cores
 };
 
 // Parity probes of the stages (the stage values of vdwnl_debug_stage): the

@@ -400,18 +400,27 @@ __global__ void __launch_bounds__(kThreads) k_x_theta(const InstDev *insts, cons
             sw.locate(lq.q0, qm, kNQ);
             const T *Mj = Mm + sw.j * kNQ;
             const T nC0 = nv * sw.C0, nC1 = nv * sw.C1;
+            // pair m = (theta_2m, theta_2m+1) as one 8- or 16-byte store: lanes
+            // (consecutive k) then touch consecutive LDS words
+            C2<T> *thc = reinterpret_cast<C2<T> *>(th) + k;   // pair line m at thc[m ls]
 #pragma unroll
-            for (int al = 0; al < kNQ; ++al) th[2 * ((al >> 1) * ls + k) + (al & 1)] = nC0 * Mj[al] + nC1 * Mj[kNQ + al];
-            // the interpolating parts A0 d_aj + A1 d_a,j+1 touch two components:
-            // rewrite those two (same thread, so after the loop's stores)
-            const int j0 = sw.j, j1 = sw.j + 1;
-            th[2 * ((j0 >> 1) * ls + k) + (j0 & 1)] = nC0 * Mj[j0] + nC1 * Mj[kNQ + j0] + nv * sw.A0;
-            th[2 * ((j1 >> 1) * ls + k) + (j1 & 1)] = nC0 * Mj[j1] + nC1 * Mj[kNQ + j1] + nv * sw.A1;
+            for (int m = 0; m < kNQ / 2; ++m)
+                thc[m * ls] = mk<T>(nC0 * Mj[2 * m] + nC1 * Mj[kNQ + 2 * m], nC0 * Mj[2 * m + 1] + nC1 * Mj[kNQ + 2 * m + 1]);
+            // the interpolating parts A0 d_aj + A1 d_a,j+1 touch components j and
+            // j + 1: rewrite the pair (j even) or the two pairs (j odd) that hold
+            // them (same thread, so after the loop's stores)
+            const int j0 = sw.j, m0 = j0 >> 1;
+            const bool odd = (j0 & 1) != 0;
+            const T nA0 = nv * sw.A0, nA1 = nv * sw.A1;
+            const T *M0 = Mj + 2 * m0, *M1 = Mj + kNQ + 2 * m0;
+            thc[m0 * ls] = mk<T>(nC0 * M0[0] + nC1 * M1[0] + (odd ? (T)0 : nA0), nC0 * M0[1] + nC1 * M1[1] + (odd ? nA0 : nA1));
+            if (odd) thc[(m0 + 1) * ls] = mk<T>(nC0 * M0[2] + nC1 * M1[2] + nA1, nC0 * M0[3] + nC1 * M1[3]);
             const T iq = rcp<T>(lq.q0);
             de += (double)((T)c_cs * nv * nv * iq * iq * iq);
         } else {
-#pragma unroll 4
-            for (int al = 0; al < kNQ; ++al) th[2 * ((al >> 1) * ls + k) + (al & 1)] = (T)0;
+            C2<T> *thc = reinterpret_cast<C2<T> *>(th) + k;
+#pragma unroll
+            for (int m = 0; m < kNQ / 2; ++m) thc[m * ls] = mk<T>((T)0, (T)0);
         }
     }
     __syncthreads();
@@ -537,11 +546,14 @@ __global__ void __launch_bounds__(kThreads) k_x_assemble(const InstDev *insts, c
             // sum_a u_a p_a and sum_a u_a p_a' through S0 = sum_a u_a M[j][a], S1 = sum_a u_a M[j+1][a]
             const T *Mj = Mm + sw.j * kNQ;
             T S0 = (T)0, S1 = (T)0;
+            // pair m = (u_2m, u_2m+1) as one 8- or 16-byte load (lanes on
+            // consecutive k read consecutive LDS words)
+            const C2<T> *uc = reinterpret_cast<const C2<T> *>(u) + k;
 #pragma unroll
-            for (int al = 0; al < kNQ; ++al) {
-                const T ua = u[2 * ((al >> 1) * ls + k) + (al & 1)];
-                S0 += ua * Mj[al];
-                S1 += ua * Mj[kNQ + al];
+            for (int m = 0; m < kNQ / 2; ++m) {
+                const C2<T> up = uc[m * ls];
+                S0 += up.x * Mj[2 * m] + up.y * Mj[2 * m + 1];
+                S1 += up.x * Mj[kNQ + 2 * m] + up.y * Mj[kNQ + 2 * m + 1];
             }
             const int j0 = sw.j, j1 = sw.j + 1;
             const T uj = u[2 * ((j0 >> 1) * ls + k) + (j0 & 1)], uj1 = u[2 * ((j1 >> 1) * ls + k) + (j1 & 1)];
@@ -857,7 +869,10 @@ __global__ void __launch_bounds__(kThreads) k_z_div(const InstDev *insts, const 
 // PROBE (parity probes of the stages, never in an evaluation): 1 writes the
 // forward spectra c = FFT(theta)/N back in place of the tile (no contraction,
 // no inverse); 2 writes u = phi c (no inverse); 0 is the evaluation.
-template <typename T, int LC, bool GEN, int PROBE>
+// MF (FP32, orthorhombic cells): the contraction on the matrix cores (see the
+// item loop below) instead of the vector ALU; the same items, the same
+// results up to the order of the FP32 additions.
+template <typename T, int LC, bool GEN, int PROBE, bool MF>
 __global__ void __launch_bounds__(kThreads) k_z_main(const InstDev *insts, const Tile *tiles, const int2 *cols,
                                                      const void *twv) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -974,8 +989,16 @@ __global__ void __launch_bounds__(kThreads) k_z_main(const InstDev *insts, const
             poff[b] = r * kNQ - ((r * (r - 1)) >> 1) + q - r;
         }
     }
-    // row al of the shell matrix of an item (index clamped to the last item:
-    // the loads stay unconditional)
+    static_assert(!MF || (sizeof(T) == 4 && !GEN), "matrix-core contraction: FP32, orthorhombic cells");
+    // the kernel-matrix row this lane holds: a of its group (vector ALU), or
+    // 4 rb + (lane % 4) of its block (matrix cores, below)
+    const int mf_blk = lane >> 2, mf_q = lane & 3;
+    const bool mf_on = mf_blk < 15;
+    const int mf_g = mf_on ? mf_blk / 5 : 2;
+    const int mf_rb = mf_on ? mf_blk - (mf_blk / 5) * 5 : 0;
+    const int row = MF ? 4 * mf_rb + mf_q : al;
+    // row `row` of the shell matrix of an item (index clamped to the last
+    // item: the loads stay unconditional)
     auto fetch = [&](int item, T *f) {
         const int sh = sidx[min(item, nitems - 1)];
         if constexpr (GEN) {
@@ -984,7 +1007,7 @@ __global__ void __launch_bounds__(kThreads) k_z_main(const InstDev *insts, const
             for (int b = 0; b < kNQ; ++b) f[b] = src[poff[b]];
             return;
         }
-        const gptr<const T> src = gld(tab + (size_t)sh * kTabRow + al * kNQ);
+        const gptr<const T> src = gld(tab + (size_t)sh * kTabRow + row * kNQ);
         if constexpr (sizeof(T) == 4) {
             const gptr<const float4> s4 = (gptr<const float4>)src;
 #pragma unroll
@@ -1003,7 +1026,11 @@ __global__ void __launch_bounds__(kThreads) k_z_main(const InstDev *insts, const
     };
     __syncthreads();
     T fa[kNQ], fb[kNQ];
-    if (PROBE != 1 && lane_on) fetch(gid, fa);
+    if constexpr (MF) {
+        if (PROBE != 1) fetch(wave * (64 / kNQ) + mf_g, fa);
+    } else {
+        if (PROBE != 1 && lane_on) fetch(gid, fa);
+    }
     fft_lc<T, -1, LC>(buf, I.p1, W, 1, lp, twall);
     if constexpr (PROBE == 1) {
         const T inv_n = (T)I.inv_n;
@@ -1065,14 +1092,89 @@ __global__ void __launch_bounds__(kThreads) k_z_main(const InstDev *insts, const
         column(w0);
         if (CP == 2) column(w0 + 1);
     };
-    for (int it = gid; lane_on && it < nitems;) {
-        fetch(it + kGroups, fb);               // the next item's row (clamped past the end)
-        process(fa);
-        it += kGroups;
-        if (it >= nitems) break;
-        fetch(it + kGroups, fa);
-        process(fb);
-        it += kGroups;
+    if constexpr (MF) {
+        // Matrix cores: v_mfma_f32_4x4x1_16b_f32 forms 16 independent 4 x 4
+        // outer products per instruction (A 4 x 1 and B 1 x 4 per block,
+        // accumulated over K).  A wave takes the three items its three lane
+        // groups take on the vector path.  Block k = lane / 4 (15 of the 16
+        // in use): item g = k / 5 of the three, rows 4 rb .. 4 rb + 3 of its
+        // kernel matrix (rb = k % 5).  Lane 4 k + i feeds A = row 4 rb + i of
+        // the matrix (20 values in registers, one per K step b) and B =
+        // column i of the item's four real columns: theta_b at point i / 2
+        // (+m1 or -m1) and part i % 2 (re, im); it receives in its four
+        // accumulators u_{4 rb + r} at that point and part, r = 0..3.  The
+        // lanes of a wave read theta before any of them writes u (wave-level
+        // ordering), as on the vector path.
+        typedef float v4f __attribute__((ext_vector_type(4)));
+        const int g0 = wave * (64 / kNQ);
+        int it = g0 + mf_g;
+        int mg = it / P, pg = it - mg * P;
+        const float fin = (float)I.inv_n;
+        auto process_mf = [&](const T *f) {
+            const bool valid = mf_on && it < nitems;
+            const int l = valid ? mg : 0;                 // (an item past the end reads point 0)
+            int lq = N1 - l;
+            const bool two = !(l == 0 || lq == l);
+            if (!two) lq = l;
+            const int w0 = __mul24(pg, CP);
+            const int k3 = k30 + pg;
+            const bool edge = (k3 == 0) || ((N3 & 1) == 0 && 2 * k3 == N3);
+            const double wgt = (valid && (mf_q < 2 || two)) ? (edge ? wn : 2.0 * wn) : 0.0;
+            it += kGroups;
+            mg += dm;
+            pg += dr;
+            if (pg >= P) { pg -= P; ++mg; }
+            const int pt = mf_q < 2 ? l : lq;
+            float *x0 = reinterpret_cast<float *>(buf + __mul24(w0, cstride) + pt) + (mf_q & 1);
+            float *o0 = x0 + 2 * 4 * mf_rb * lp;
+            if (CP == 2) {
+                float *x1 = x0 + 2 * cstride, *o1 = o0 + 2 * cstride;
+                v4f a0 = {0.f, 0.f, 0.f, 0.f}, a1 = a0;
+#pragma unroll
+                for (int b = 0; b < kNQ; ++b) {
+                    a0 = __builtin_amdgcn_mfma_f32_4x4x1f32(f[b], x0[2 * b * lp], a0, 0, 0, 0);
+                    a1 = __builtin_amdgcn_mfma_f32_4x4x1f32(f[b], x1[2 * b * lp], a1, 0, 0, 0);
+                }
+                e += wgt * (double)(o0[0] * a0[0] + o0[2 * lp] * a0[1] + o0[4 * lp] * a0[2] + o0[6 * lp] * a0[3]);
+                e += wgt * (double)(o1[0] * a1[0] + o1[2 * lp] * a1[1] + o1[4 * lp] * a1[2] + o1[6 * lp] * a1[3]);
+                wave_sync();
+                if (valid) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        o0[2 * r * lp] = a0[r] * fin;
+                        o1[2 * r * lp] = a1[r] * fin;
+                    }
+                }
+            } else {
+                v4f a0 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int b = 0; b < kNQ; ++b) a0 = __builtin_amdgcn_mfma_f32_4x4x1f32(f[b], x0[2 * b * lp], a0, 0, 0, 0);
+                e += wgt * (double)(o0[0] * a0[0] + o0[2 * lp] * a0[1] + o0[4 * lp] * a0[2] + o0[6 * lp] * a0[3]);
+                wave_sync();
+                if (valid) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) o0[2 * r * lp] = a0[r] * fin;
+                }
+            }
+        };
+        // rounds of three items per wave, the loop bound uniform over the wave
+        for (int base = g0; base < nitems; base += 2 * kGroups) {
+            fetch(it + kGroups, fb);               // the next round's row (clamped past the end)
+            process_mf(fa);
+            if (base + kGroups >= nitems) break;
+            fetch(it + kGroups, fa);
+            process_mf(fb);
+        }
+    } else {
+        for (int it = gid; lane_on && it < nitems;) {
+            fetch(it + kGroups, fb);               // the next item's row (clamped past the end)
+            process(fa);
+            it += kGroups;
+            if (it >= nitems) break;
+            fetch(it + kGroups, fa);
+            process(fb);
+            it += kGroups;
+        }
     }
     __syncthreads();
     if constexpr (PROBE == 0) fft_lc<T, 1, LC>(buf, I.p1, W, 1, lp, twall);
@@ -1183,8 +1285,9 @@ static hipError_t launch_lc(int kind, const LaunchArgs &a) {
         case KX_THETA: VDWNL_LAUNCH((k_x_theta<T, LC>), a.cst, a.tw); break;
         case KY_20F: VDWNL_LAUNCH((k_y<T, -1, LC>), a.tw, 0, kNQ); break;
         case KZ_MAIN:
-            if (a.general) VDWNL_LAUNCH((k_z_main<T, LC, true, 0>), a.cols, a.tw);
-            else VDWNL_LAUNCH((k_z_main<T, LC, false, 0>), a.cols, a.tw);
+            if (a.general) VDWNL_LAUNCH((k_z_main<T, LC, true, 0, false>), a.cols, a.tw);
+            else if (sizeof(T) == 4 && a.mfma) VDWNL_LAUNCH((k_z_main<T, LC, false, 0, sizeof(T) == 4>), a.cols, a.tw);
+            else VDWNL_LAUNCH((k_z_main<T, LC, false, 0, false>), a.cols, a.tw);
             break;
         case KY_20I: VDWNL_LAUNCH((k_y<T, 1, LC>), a.tw, 0, kNQ); break;
         case KX_ASSEMBLE: VDWNL_LAUNCH((k_x_assemble<T, LC, false>), a.cst, a.tw); break;
@@ -1232,12 +1335,13 @@ static hipError_t launch_probe_lc(int probe, const LaunchArgs &a, void *dst, int
     } while (0)
     switch (probe) {
         case PROBE_THETA_K:
-            if (a.general) VDWNL_PROBE((k_z_main<T, LC, true, 1>), a.cols, a.tw);
-            else VDWNL_PROBE((k_z_main<T, LC, false, 1>), a.cols, a.tw);
+            if (a.general) VDWNL_PROBE((k_z_main<T, LC, true, 1, false>), a.cols, a.tw);
+            else VDWNL_PROBE((k_z_main<T, LC, false, 1, false>), a.cols, a.tw);
             break;
         case PROBE_U_K:
-            if (a.general) VDWNL_PROBE((k_z_main<T, LC, true, 2>), a.cols, a.tw);
-            else VDWNL_PROBE((k_z_main<T, LC, false, 2>), a.cols, a.tw);
+            if (a.general) VDWNL_PROBE((k_z_main<T, LC, true, 2, false>), a.cols, a.tw);
+            else if (sizeof(T) == 4 && a.mfma) VDWNL_PROBE((k_z_main<T, LC, false, 2, sizeof(T) == 4>), a.cols, a.tw);
+            else VDWNL_PROBE((k_z_main<T, LC, false, 2, false>), a.cols, a.tw);
             break;
         case PROBE_U: VDWNL_PROBE((k_probe_u<T, LC>), a.tw, dst, target); break;
         case PROBE_THETA:

@@ -265,3 +265,16 @@ def test_noalloc_entry_point_on_host_context():
     assert _set_grid(lib, h, (24, 24, 24)) == 0
     assert lib.vdwnl_energy_potential_noalloc(h, p, p, pe, None) == E["STATE"]   # no table, host only
     lib.vdwnl_destroy(h)
+
+
+def test_schedule_choice_arguments():
+    lib, h = _host_ctx()
+    v = ctypes.c_int32(-1)
+    assert lib.vdwnl_set_schedule(h, 0, 1) == E["STATE"]          # no grid planned
+    assert _set_grid(lib, h, (24, 24, 24)) == 0
+    for what, val, code in [(0, 0, 0), (0, 1, 0), (0, 2, E["ARG"]), (1, 0, E["ARG"]), (0, -1, E["ARG"])]:
+        assert lib.vdwnl_set_schedule(h, what, val) == code
+    assert lib.vdwnl_get_schedule(h, 0, ctypes.byref(v)) == 0 and v.value == 1
+    assert lib.vdwnl_get_schedule(h, 3, ctypes.byref(v)) == E["ARG"]
+    assert lib.vdwnl_get_schedule(h, 0, None) == E["ARG"]
+    lib.vdwnl_destroy(h)

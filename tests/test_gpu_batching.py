@@ -116,18 +116,21 @@ def test_tuning_file_persists_across_processes(table, tmp_path, monkeypatch):
     say("  tuning file: %s" % entries)
     assert len(entries) == 1
     key = next(iter(entries))
-    assert key.startswith("gfx") and entries[key] == list(lib.get_tiling().values())
-    json.dump({key: [24576] * 5}, open(path, "w"))
+    # the five LDS budgets, then the contraction unit
+    assert key.startswith("gfx") and entries[key][:5] == list(lib.get_tiling().values())
+    assert entries[key][5] == lib.get_contraction()
+    json.dump({key: [24576] * 5 + [1 - entries[key][5]]}, open(path, "w"))
     code = ("import sys, json; sys.path.insert(0, %r)\n"
             "import workloads as W\n"
             "from paper_0812_0244_amd import VdwNl\n"
             "insts = W.batch_instances(3)\n"
             "lib = VdwNl(0)\n"
             "lib.set_grids([w.shape for w in insts], [w.cell for w in insts], 0, 32)\n"
-            "print(json.dumps(lib.get_tiling()))\n" % os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+            "print(json.dumps([lib.get_tiling(), lib.get_contraction()]))\n"
+            % os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120,
                          env=dict(os.environ))
     assert out.returncode == 0, out.stderr
-    got = json.loads(out.stdout.strip().splitlines()[-1])
-    say("  budgets in the new process: %s" % got)
-    assert list(got.values()) == [24576] * 5
+    got, unit = json.loads(out.stdout.strip().splitlines()[-1])
+    say("  budgets in the new process: %s, contraction unit %d" % (got, unit))
+    assert list(got.values()) == [24576] * 5 and unit == 1 - entries[key][5]

@@ -191,3 +191,43 @@ def test_autograd_backward_is_dvol_times_v(table):
     E.backward()
     _, _, v = eng.energy_potential(n.detach())
     assert torch.equal(n.grad, v * eng.dvol)
+
+
+def test_contraction_units_agree_with_oracle(table):
+    """The per-k contraction of Eqs. (Eoffk)/(epsofk) on the vector ALU and on
+    the matrix cores (FP32): both against the oracle on the same rounded input
+    (1e-6 relative E, 1e-5 Ha), and against each other; the probed u spectra
+    too.  Single columns and column pairs (tile budgets 32 and 48 KB) on the
+    96^3 workload, a ragged non-cubic grid."""
+    from paper_0812_0244_amd import VdwNl
+    from paper_0812_0244_amd.binding import CONTRACTION_MATRIX, CONTRACTION_VECTOR, STAGE_U_K
+    cases = [(W.config(2).density(), W.config(2).cell, W.config(2).shape),
+             (None, (8.0, 11.0, 7.5), (20, 30, 18))]
+    for n, cell, shape in cases:
+        if n is None:
+            n = W.density_on_grid(shape, cell, W.random_atoms(np.random.default_rng(77), 6, cell))
+        n = fp32_input(n)
+        o = F.energy_potential(n, cell, table, return_parts=True)
+        nt = torch.from_numpy(n).to("cuda", torch.float32)
+        res = {}
+        for zb in (32768, 49152):
+            for unit in (CONTRACTION_VECTOR, CONTRACTION_MATRIX):
+                lib = VdwNl(0)
+                lib.set_grid(shape, cell, 0, 32)
+                lib.set_kernel_table(table["qmesh"], table["qc"], 12, table["dk"], table["phi"], table["c_soft"])
+                lib.set_tiling([65536, 65536, 65536, zb, 65536])
+                lib.set_contraction(unit)
+                assert lib.get_contraction() == unit
+                v = torch.empty_like(nt)
+                ek, de = lib.energy_potential(nt.data_ptr(), v.data_ptr())
+                uk = torch.empty((shape[0], shape[1], shape[2] // 2 + 1, 20, 2), dtype=torch.float32, device="cuda")
+                lib.debug_stage(0, STAGE_U_K, uk.data_ptr())
+                g = dict(E_k=ek, dE=de, v=v.double().cpu().numpy())
+                say("  %s z budget %d unit %d" % (shape, zb, unit))
+                check(g, o, 32)
+                res[(zb, unit)] = (ek + de, g["v"], uk.double().cpu().numpy())
+        base = res[(32768, CONTRACTION_VECTOR)]
+        for key, r in res.items():
+            assert abs(r[0] - base[0]) <= 1e-6 * abs(base[0])
+            assert np.abs(r[1] - base[1]).max() <= 1e-5
+            assert np.abs(r[2] - base[2]).max() <= 2e-6 * np.abs(base[2]).max()
