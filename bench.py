@@ -258,7 +258,7 @@ def main():
     import torch
 
     import workloads as W
-    from paper_0812_0244_amd.binding import VdwNl, build_kernel_table
+    from paper_0812_0244_amd.binding import VdwNl, build_kernel_table, radix_order
 
     def log(msg):
         print("[bench] " + msg, file=sys.stderr, flush=True)
@@ -298,7 +298,9 @@ def main():
     elif not args.no_autotune:
         lib.autotune(nptr, vptr, reps=5, stream=stream)
     tiling = lib.get_tiling()
-    log("tile budgets %s, contraction unit %d (%.1f s)" % (tiling, lib.get_contraction(), time.time() - t0))
+    radix = lib.get_radix_orders()
+    log("tile budgets %s, contraction unit %d, radix orders %s (%.1f s)"
+        % (tiling, lib.get_contraction(), radix, time.time() - t0))
     for _ in range(args.warmup):
         lib.energy_potential_batched(nptr, vptr, stream)
     torch.cuda.synchronize()
@@ -572,6 +574,9 @@ def main():
             "launch": "one HIP graph per call (14 passes x FFT length classes), tile LDS budgets "
                       "tuned at setup",
             "lds_budgets": tiling,
+            "radix_orders": radix,
+            "radix_passes": {str(n): [radix_order(n, radix[g]) for g in ("x", "y20", "z")]
+                             for n in sorted({s[0] for s in shapes})},
         },
         "fp64_plain": {"ms_per_step": ms64, "value": total / (ms64 * 1e-3),
                        "max_rel_E_fp32_batched_vs_fp64_plain": max_rel,

@@ -271,14 +271,18 @@ int vdwnl_pass_order(const vdwnl_ctx *ctx, int32_t max_passes, int32_t *kinds);
  * passes one by one; results are identical). */
 int vdwnl_set_graph(vdwnl_ctx *ctx, int32_t on);
 
-/* Tile-shape tuning for the planned grids: evaluates the batch (n_ptrs[nb],
+/* Schedule tuning for the planned grids: evaluates the batch (n_ptrs[nb],
  * v_ptrs[nb] as for vdwnl_energy_potential_batched; v is overwritten) once
- * plus `reps` timed times (1..100) for each candidate LDS budget, picks per
- * pass group the budget with the least time over the group's passes, plans
- * with it and remembers it, keyed by the device architecture, its LDS size,
+ * plus `reps` timed times (1..100) for each candidate LDS budget (and, for
+ * FP32 orthorhombic grids, each contraction unit), picks per pass group the
+ * budget (and unit) with the least time over the group's passes, then times
+ * the radix orders 0..3 with those and picks one per group the same way,
+ * plans with the choices and remembers them, keyed by the device
+ * architecture, its LDS size,
  * the precision, the gradient mode and the exact grid list: for the rest of
  * the process, and in the tuning file for later processes.  The file is a
- * JSON object with one entry per line, "<arch>/<key hash>": [five budgets],
+ * JSON object with one entry per line, "<arch>/<key hash>": [five budgets,
+ * the contraction unit, five radix orders],
  * at $VDWNL_TUNE_CACHE (an empty value: no file), else
  * $XDG_CACHE_HOME/vdwnl/tuning.json or $HOME/.cache/vdwnl/tuning.json; a file
  * that cannot be read or written is ignored.  Results do not depend on the
@@ -296,15 +300,37 @@ int vdwnl_autotune(vdwnl_ctx *ctx, int32_t nb, const void *const *n_ptrs, void *
  *     or VDWNL_CONTRACTION_MATRIX (the matrix cores: 16-block 4 x 4 x 1 FP32
  *     outer products, 15 blocks per instruction for the 20 x 20 matrices of
  *     three k-point groups); FP64 and general cells always use the vector ALU.
- * vdwnl_autotune chooses the contraction unit together with the LDS budgets
- * (and a plan reuses a tuned choice as it does the budgets); otherwise the
- * matrix cores.  Setting it re-plans the launches (the workspace is rebuilt
- * at the next evaluation).  VDWNL_E_ARG for an unknown choice or value;
- * VDWNL_E_STATE without a planned grid. */
-enum { VDWNL_SCHEDULE_CONTRACTION = 0 };
+ *   VDWNL_SCHEDULE_RADIX_*  the radix order of a pass group's transforms.
+ * vdwnl_autotune chooses the contraction unit together with the LDS budgets,
+ * then the radix orders (and a plan reuses tuned choices as it does the
+ * budgets); untuned, the matrix cores and order 0.  Setting a choice
+ * re-plans the launches (the workspace is rebuilt at the next evaluation).
+ * VDWNL_E_ARG for an unknown choice or value; VDWNL_E_STATE without a planned
+ * grid. */
+enum {
+    VDWNL_SCHEDULE_CONTRACTION = 0,
+    /* radix order of the transforms of each pass group (0..3): every axis-3
+     * transform, the axis-2 transforms of the 20 spectra, the other axis-2
+     * transforms, the fused axis-1 pass, the other axis-1 passes.  Each length
+     * with a compile-time plan has one to four orders (vdwnl_radix_order),
+     * and a larger value takes its last; other lengths have one. */
+    VDWNL_SCHEDULE_RADIX_X = 1,
+    VDWNL_SCHEDULE_RADIX_Y20 = 2,
+    VDWNL_SCHEDULE_RADIX_YAUX = 3,
+    VDWNL_SCHEDULE_RADIX_Z = 4,
+    VDWNL_SCHEDULE_RADIX_ZAUX = 5
+};
 enum { VDWNL_CONTRACTION_VECTOR = 0, VDWNL_CONTRACTION_MATRIX = 1 };
 int vdwnl_set_schedule(vdwnl_ctx *ctx, int32_t what, int32_t value);
 int vdwnl_get_schedule(const vdwnl_ctx *ctx, int32_t what, int32_t *value);
+
+/* The radix passes (each 2, 3, 4, 5 or 8, in order) of the transform of
+ * length n in radix order `order` (0..3; a larger order than the length has
+ * takes its last): up to max_radices values into radices[] (host array).
+ * Returns their number, VDWNL_E_ARG for bad arguments, or
+ * VDWNL_E_UNSUPPORTED_SIZE for a length with a prime factor above 5.  Host
+ * only (no context, no device). */
+int vdwnl_radix_order(int32_t n, int32_t order, int32_t max_radices, int32_t *radices);
 
 /* LDS budget (bytes) of each pass group in the current plan, in the order
  * axis-3 (theta, assembly), axis-2 over the 20 spectra, axis-2 over the

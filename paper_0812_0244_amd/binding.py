@@ -55,6 +55,7 @@ SIGNATURES = {
     "vdwnl_set_tiling": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(ctypes.c_int64)]),
     "vdwnl_set_schedule": (ctypes.c_int, [_vp, _i32, _i32]),
     "vdwnl_get_schedule": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(_i32)]),
+    "vdwnl_radix_order": (ctypes.c_int, [_i32, _i32, _i32, ctypes.POINTER(_i32)]),
 }
 
 _lib = None
@@ -63,6 +64,17 @@ FUNCTIONAL_NONLOCAL = 0
 FUNCTIONAL_VDW_DF = 1
 SCHEDULE_CONTRACTION = 0
 CONTRACTION_VECTOR, CONTRACTION_MATRIX = 0, 1
+RADIX_GROUPS = ("x", "y20", "yaux", "z", "zaux")     # schedule choices 1..5
+
+
+def radix_order(n: int, order: int = 0):
+    """The radix passes of the length-n transform in radix order `order`."""
+    lib = load_library()
+    r = (_i32 * 16)()
+    k = lib.vdwnl_radix_order(int(n), int(order), 16, r)
+    if k < 0:
+        raise VdwNlError(k, "vdwnl_radix_order")
+    return [int(r[i]) for i in range(k)]
 
 
 class VdwNlError(RuntimeError):
@@ -272,6 +284,21 @@ class VdwNl:
         v = _i32()
         self._check(self.lib.vdwnl_get_schedule(self.h, SCHEDULE_CONTRACTION, ctypes.byref(v)), "get_schedule")
         return int(v.value)
+
+    def set_radix_orders(self, orders):
+        """orders: dict with keys x, y20, yaux, z, zaux (0..3), or a sequence of 5."""
+        if isinstance(orders, dict):
+            orders = [orders[k] for k in RADIX_GROUPS]
+        for i, v in enumerate(orders):
+            self._check(self.lib.vdwnl_set_schedule(self.h, 1 + i, int(v)), "set_schedule")
+
+    def get_radix_orders(self):
+        out = {}
+        for i, k in enumerate(RADIX_GROUPS):
+            v = _i32()
+            self._check(self.lib.vdwnl_get_schedule(self.h, 1 + i, ctypes.byref(v)), "get_schedule")
+            out[k] = int(v.value)
+        return out
 
     def get_tiling(self):
         """LDS budget (bytes) per pass group: x, y20, yaux, z, zaux."""

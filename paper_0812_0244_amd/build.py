@@ -13,7 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT_DIR, "libvdwnl.so")
-SOURCES = ("api.hip", "kernels_f32.hip", "kernels_f64.hip", "table_gen.hip")
+SOURCES = ("api.hip", "kernels_f32_z.hip", "kernels_f32_x.hip", "kernels_f32_y.hip", "kernels_f64_z.hip",
+           "kernels_f64_x.hip", "kernels_f64_y.hip", "kernels_dispatch.hip", "table_gen.hip")
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -128,6 +128,19 @@ constexpr int kDefaultContraction = VDWNL_CONTRACTION_MATRIX;
 // Pass groups whose tile shapes follow one LDS budget each.
 enum TileGroup { TG_X = 0, TG_Y20, TG_YAUX, TG_Z, TG_ZAUX, TG_COUNT };
 
+// The pass group whose radix order a pass takes: every axis-3 transform, the
+// axis-2 transforms of the 20 spectra, the other axis-2 transforms, the fused
+// axis-1 pass, the other axis-1 passes.
+static int variant_group(int kind) {
+    switch (kind) {
+        case KY_20F: case KY_20I: return TG_Y20;
+        case KY_1F: case KY_3I: case KY_3F: case KY_1I: return TG_YAUX;
+        case KZ_MAIN: return TG_Z;
+        case KZ_GRAD: case KZ_DIV: return TG_ZAUX;
+        default: return TG_X;
+    }
+}
+
 struct Grid {
     int s[3];
     double A[3][3];          // cell vectors a_c (rows, bohr)
@@ -193,6 +206,7 @@ struct vdwnl_ctx {
     std::string err;
     size_t pref[TG_COUNT] = {kLdsCap, kLdsCap, kLdsCap, kLdsCap, kLdsCap};   // LDS budget per pass group
     int contraction = VDWNL_CONTRACTION_VECTOR;   // unit of the per-k contraction (FP32, orthorhombic)
+    int variant[TG_COUNT] = {0, 0, 0, 0, 0};        // radix order per pass group
     std::string plan_key;                 // identifies the batch for the tuned-budget cache
     std::string arch = "host";            // device architecture (gcnArchName)
     // plan
@@ -229,6 +243,7 @@ struct vdwnl_ctx {
         int group;
         int general;          // grids of the group in non-orthogonal cells
         int mfma;             // (fused axis-1 pass) the contraction on the matrix cores
+        int var;              // radix order of the transform (its length class's variant)
     };
     // per pass: one launch per group of grids (grids whose three axes fall in
     // the same FFT length classes); the groups' chains of passes are
@@ -433,13 +448,14 @@ static void size_tiles(const vdwnl_ctx *c, Grid &g) {
 // gradient mode and the exact list of grid shapes and cells: a map for the
 // process, backed by a file so that later processes reuse them.  The file is
 // a JSON object with one entry per line,
-//   "<arch>/<hash of the rest of the key>": [x, y20, yaux, z, zaux, contraction],
+//   "<arch>/<hash of the rest of the key>": [x, y20, yaux, z, zaux, contraction,
+//                                              five radix orders in the same group order],
 // at $VDWNL_TUNE_CACHE (empty: no file), else $XDG_CACHE_HOME/vdwnl/tuning.json
 // or $HOME/.cache/vdwnl/tuning.json.  A file that cannot be read or written
 // is ignored (the process map still works).
 static std::mutex g_tuned_mu;
 static std::map<std::string, std::vector<size_t>> g_tuned;
-constexpr int kTuneVals = TG_COUNT + 1;   // the five budgets and the contraction unit
+constexpr int kTuneVals = 2 * TG_COUNT + 1;   // the five budgets, the contraction unit, five radix orders
 
 static std::string plan_key(const vdwnl_ctx *c) {
     std::string k = std::to_string(c->precision) + "/" + std::to_string(c->grad_mode) + "/" + std::to_string(c->lds_cap);
@@ -520,7 +536,7 @@ static void write_tune_file(const std::string &path, const std::map<std::string,
     else (void)std::remove(tmp.c_str());
 }
 
-static bool tuned_lookup(const std::string &key, size_t *pref, int *contraction, size_t cap) {
+static bool tuned_lookup(const std::string &key, size_t *pref, int *contraction, int *variant, size_t cap) {
     std::lock_guard<std::mutex> lk(g_tuned_mu);
     auto it = g_tuned.find(key);
     if (it == g_tuned.end()) {
@@ -530,17 +546,21 @@ static bool tuned_lookup(const std::string &key, size_t *pref, int *contraction,
         for (int i = 0; i < TG_COUNT; ++i)
             if (ft->second[i] < 4096 || ft->second[i] > cap) return false;   // (not a budget this device accepts)
         if (ft->second[TG_COUNT] > 1) return false;
+        for (int i = 0; i < TG_COUNT; ++i)
+            if (ft->second[TG_COUNT + 1 + i] > 3) return false;
         it = g_tuned.insert(*ft).first;
     }
     for (int i = 0; i < TG_COUNT; ++i) pref[i] = it->second[i];
     *contraction = (int)it->second[TG_COUNT];
+    for (int i = 0; i < TG_COUNT; ++i) variant[i] = (int)it->second[TG_COUNT + 1 + i];
     return true;
 }
 
-static void tuned_store(const std::string &key, const size_t *pref, int contraction) {
+static void tuned_store(const std::string &key, const size_t *pref, int contraction, const int *variant) {
     std::lock_guard<std::mutex> lk(g_tuned_mu);
     std::vector<size_t> v(pref, pref + TG_COUNT);
     v.push_back((size_t)contraction);
+    for (int i = 0; i < TG_COUNT; ++i) v.push_back((size_t)variant[i]);
     g_tuned[key] = v;
     const std::string path = tune_cache_path();
     auto file = read_tune_file(path);
@@ -566,9 +586,10 @@ static int plan_grids(vdwnl_ctx *c, int nb, const int32_t *shapes, const double 
     c->grad_mode = grad_mode;
     // tile budgets: a tuned set for this exact batch if one exists, else defaults
     c->plan_key = plan_key(c);
-    if (!tuned_lookup(c->plan_key, c->pref, &c->contraction, c->lds_cap)) {
+    if (!tuned_lookup(c->plan_key, c->pref, &c->contraction, c->variant, c->lds_cap)) {
         for (auto &p : c->pref) p = std::min<size_t>(c->lds_cap, kLdsCap);
         c->contraction = kDefaultContraction;
+        for (auto &v : c->variant) v = 0;
     }
     for (auto &g : c->grids) size_tiles(c, g);
     c->shells.clear();
@@ -842,7 +863,7 @@ static int build_image(vdwnl_ctx *c, Image &im, bool keep_tables) {
     for (int k = 0; k < KIND_COUNT; ++k) {
         c->launches[k].clear();
         for (int grp = 0; grp < c->ngroups; ++grp) {
-            vdwnl_ctx::Launch L{k, 0, (int)all.size(), 0, 0, grp, 0, 0};
+            vdwnl_ctx::Launch L{k, 0, (int)all.size(), 0, 0, grp, 0, 0, 0};
             for (const Tile &tl : tiles[k]) {
                 if (group_of[tl.inst] != grp) continue;
                 const Grid &g = c->grids[tl.inst];
@@ -851,6 +872,7 @@ static int build_image(vdwnl_ctx *c, Image &im, bool keep_tables) {
                              ? 1 : 0;
                 // the stencil passes transform nothing (class 0 for any grid)
                 L.lc = (k == KF_GRAD || k == KF_DIV) ? 0 : len_class(axis_len(k, g));
+                L.var = (k == KF_GRAD || k == KF_DIV) ? 0 : std::min(c->variant[variant_group(k)], kNumVariants[L.lc] - 1);
                 all.push_back(tl);
                 L.lds = std::max(L.lds, lds_of(k, g));
             }
@@ -916,7 +938,7 @@ static int lds_optin(vdwnl_ctx *c) {
     hipError_t e;
     for (int k = 0; k < KIND_COUNT; ++k)
         for (const auto &L : c->launches[k]) {
-            LaunchArgs a{nullptr, nullptr, 0, L.lds, nullptr, nullptr, nullptr, nullptr, nullptr, L.general, L.mfma};
+            LaunchArgs a{nullptr, nullptr, 0, L.lds, nullptr, nullptr, nullptr, nullptr, nullptr, L.general, L.mfma, L.var};
             if ((e = launch_kind(k, L.lc, c->precision, a)) != hipSuccess) return hipfail(c, e, "kernel LDS limit");
             // (and the stage probes that stand in for the pass)
             for (int pr : {PROBE_THETA_K, PROBE_U_K, PROBE_U}) {
@@ -1098,7 +1120,7 @@ static int enqueue(vdwnl_ctx *c, const DevPtrs &P, const InstDev *hinst, double 
     const int *order;
     const int npass = pass_order(c->grad_mode, &order);
     auto launch = [&](const vdwnl_ctx::Launch &L, hipStream_t s) -> int {
-        LaunchArgs a{P.inst, P.tiles + L.off, L.cnt, L.lds, P.consts, P.tw, P.twd, s, P.cols, L.general, L.mfma};
+        LaunchArgs a{P.inst, P.tiles + L.off, L.cnt, L.lds, P.consts, P.tw, P.twd, s, P.cols, L.general, L.mfma, L.var};
         const hipError_t le = launch_kind(L.kind, L.lc, c->precision, a);
         return le == hipSuccess ? VDWNL_OK : hipfail(c, le, "kernel launch");
     };
@@ -1264,7 +1286,7 @@ static int probe_stage(vdwnl_ctx *c, int stage, int target, void *dst, hipStream
     }
     auto args = [&](const vdwnl_ctx::Launch &L) {
         return LaunchArgs{c->dp.inst, c->dp.tiles + L.off, L.cnt, L.lds, c->dp.consts, c->dp.tw, c->dp.twd, st, c->dp.cols,
-                          L.general, L.mfma};
+                          L.general, L.mfma, L.var};
     };
     for (int i = 0; i < npass && order[i] != stop; ++i)
         for (const auto &L : c->launches[order[i]])
@@ -1679,6 +1701,7 @@ int vdwnl_autotune(vdwnl_ctx *ctx, int32_t nb, const void *const *n_ptrs, void *
         if (b <= ctx->lds_cap) cand.push_back(b);
     const bool timing0 = ctx->timing;
     ctx->img_valid = false;     // (the candidates' tiles differ from the image's)
+    for (auto &x : ctx->variant) x = 0;   // (the budgets are tuned with the first radix orders)
     // contraction units to try: the vector ALU, and the matrix cores where
     // some grid takes them (FP32, orthorhombic cell)
     std::vector<int> units = {VDWNL_CONTRACTION_VECTOR};
@@ -1729,12 +1752,40 @@ int vdwnl_autotune(vdwnl_ctx *ctx, int32_t nb, const void *const *n_ptrs, void *
     }
     ctx->contraction = best_unit;
     for (int gi = 0; gi < TG_COUNT; ++gi) ctx->pref[gi] = best[gi];
+    // radix orders, with the chosen budgets and unit: every group at order v
+    // (each length class clamps v to its last variant), v = 0..3, and per
+    // group the order with the least time over the group's transforms
+    {
+        std::vector<std::vector<double>> tv(4, std::vector<double>(KIND_COUNT, 0.0));
+        for (int v = 0; v < 4 && rc == VDWNL_OK; ++v) {
+            for (auto &x : ctx->variant) x = v;
+            for (auto &g : ctx->grids) size_tiles(ctx, g);
+            free_device(ctx);
+            ctx->timing = false;
+            rc = run(ctx, nb, n_ptrs, v_ptrs, E.data(), stream);
+            if (rc != VDWNL_OK) break;
+            vdwnl_set_timing(ctx, 1);
+            for (int r = 0; r < reps && rc == VDWNL_OK; ++r) rc = run(ctx, nb, n_ptrs, v_ptrs, E.data(), stream);
+            for (int k = 0; k < KIND_COUNT; ++k) tv[v][k] = ctx->pass_ms[k];
+        }
+        for (int gi = 0; gi < TG_COUNT; ++gi) {
+            double bt = 1e300;
+            int bv = 0;
+            for (int v = 0; rc == VDWNL_OK && v < 4; ++v) {
+                double sum = 0.0;
+                for (int k = 0; k < KIND_COUNT; ++k)
+                    if (k != KF_GRAD && k != KF_DIV && variant_group(k) == gi) sum += tv[v][k];
+                if (sum > 0.0 && sum < bt) { bt = sum; bv = v; }
+            }
+            ctx->variant[gi] = bv;
+        }
+    }
     for (auto &g : ctx->grids) size_tiles(ctx, g);
     free_device(ctx);
     refresh_image(ctx);
     vdwnl_set_timing(ctx, timing0 ? 1 : 0);
     if (rc != VDWNL_OK) return rc;
-    tuned_store(ctx->plan_key, ctx->pref, ctx->contraction);
+    tuned_store(ctx->plan_key, ctx->pref, ctx->contraction, ctx->variant);
     return VDWNL_OK;
 }
 
@@ -1754,11 +1805,17 @@ int vdwnl_set_tiling(vdwnl_ctx *ctx, int32_t ngroups, const int64_t *lds_budget)
 
 int vdwnl_set_schedule(vdwnl_ctx *ctx, int32_t what, int32_t value) {
     if (!ctx) return VDWNL_E_ARG;
-    if (what != VDWNL_SCHEDULE_CONTRACTION) return fail(ctx, VDWNL_E_ARG, "unknown schedule choice");
-    if (value != VDWNL_CONTRACTION_VECTOR && value != VDWNL_CONTRACTION_MATRIX)
-        return fail(ctx, VDWNL_E_ARG, "contraction must be VDWNL_CONTRACTION_VECTOR or VDWNL_CONTRACTION_MATRIX");
+    if (what == VDWNL_SCHEDULE_CONTRACTION) {
+        if (value != VDWNL_CONTRACTION_VECTOR && value != VDWNL_CONTRACTION_MATRIX)
+            return fail(ctx, VDWNL_E_ARG, "contraction must be VDWNL_CONTRACTION_VECTOR or VDWNL_CONTRACTION_MATRIX");
+    } else if (what >= VDWNL_SCHEDULE_RADIX_X && what <= VDWNL_SCHEDULE_RADIX_ZAUX) {
+        if (value < 0 || value > 3) return fail(ctx, VDWNL_E_ARG, "radix order must be 0..3");
+    } else {
+        return fail(ctx, VDWNL_E_ARG, "unknown schedule choice");
+    }
     if (!ctx->have_grid) return fail(ctx, VDWNL_E_STATE, "no grid planned");
-    ctx->contraction = value;
+    if (what == VDWNL_SCHEDULE_CONTRACTION) ctx->contraction = value;
+    else ctx->variant[what - VDWNL_SCHEDULE_RADIX_X] = value;
     free_device(ctx);
     refresh_image(ctx);
     return VDWNL_OK;
@@ -1766,9 +1823,25 @@ int vdwnl_set_schedule(vdwnl_ctx *ctx, int32_t what, int32_t value) {
 
 int vdwnl_get_schedule(const vdwnl_ctx *ctx, int32_t what, int32_t *value) {
     if (!ctx || !value) return VDWNL_E_ARG;
-    if (what != VDWNL_SCHEDULE_CONTRACTION) return VDWNL_E_ARG;
-    *value = ctx->contraction;
+    if (what == VDWNL_SCHEDULE_CONTRACTION) *value = ctx->contraction;
+    else if (what >= VDWNL_SCHEDULE_RADIX_X && what <= VDWNL_SCHEDULE_RADIX_ZAUX) *value = ctx->variant[what - VDWNL_SCHEDULE_RADIX_X];
+    else return VDWNL_E_ARG;
     return VDWNL_OK;
+}
+
+int vdwnl_radix_order(int32_t n, int32_t order, int32_t max_radices, int32_t *radices) {
+    if (max_radices < 0 || (max_radices > 0 && !radices) || order < 0 || order > 3) return VDWNL_E_ARG;
+    const int lc = len_class(n);
+    int r[kMaxStages], nr = 0;
+    if (lc == kLenGeneric) {
+        FftPlan p;
+        if (n < 1 || !radix_plan(n, p)) return VDWNL_E_UNSUPPORTED_SIZE;
+        for (int i = 0; i < p.nstage; ++i) r[nr++] = p.radix[i];
+    } else {
+        nr = radix_order_of(lc, std::min<int>(order, kNumVariants[lc] - 1), r);
+    }
+    for (int i = 0; i < std::min<int>(nr, max_radices); ++i) radices[i] = r[i];
+    return nr;
 }
 
 int vdwnl_get_tiling(const vdwnl_ctx *ctx, int32_t max_groups, int64_t *lds_budget) {

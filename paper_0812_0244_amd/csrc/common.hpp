@@ -123,6 +123,9 @@ struct LaunchArgs {
     const int2 *cols;        // (k2, k3) columns of the fused axis-1 tiles
     int general;             // the launch's grids have non-orthogonal cells (packed shell rows)
     int mfma = 0;            // FP32 orthorhombic fused axis-1 pass: contraction on the matrix cores
+    int var = 0;             // radix order of the pass's transform length (0 .. its variants - 1)
+    void *dst = nullptr;     // (stage probes) the probe's output
+    int target = 0;          // (stage probes) the grid whose tiles run
 };
 
 // Parity probes of the stages (the stage values of vdwnl_debug_stage): the
@@ -130,9 +133,18 @@ struct LaunchArgs {
 // fused axis-1 pass for THETA_K and U_K, the assembly pass for U); dst the
 // probe's output (THETA, U), target the grid whose tiles run.
 enum ProbeKind { PROBE_THETA = 0, PROBE_THETA_K = 1, PROBE_U_K = 2, PROBE_U = 3 };
+// the probes as launch kinds of their families
+enum ProbeLaunch { KP_THETA = KIND_COUNT + 1, KP_THETA_K, KP_U_K, KP_U };
 
 hipError_t launch_kind(int kind, int len_class, int precision, const LaunchArgs &a);
 hipError_t launch_probe(int probe, int len_class, int precision, const LaunchArgs &a, void *dst, int target);
+// family launchers (kernels_f32_x.hip ...): kind, length class, radix order
+hipError_t launch_x_f32(int kind, int lc, int var, const LaunchArgs &a);
+hipError_t launch_y_f32(int kind, int lc, int var, const LaunchArgs &a);
+hipError_t launch_z_f32(int kind, int lc, int var, const LaunchArgs &a);
+hipError_t launch_x_f64(int kind, int lc, int var, const LaunchArgs &a);
+hipError_t launch_y_f64(int kind, int lc, int var, const LaunchArgs &a);
+hipError_t launch_z_f64(int kind, int lc, int var, const LaunchArgs &a);
 hipError_t launch_reduce(const InstDev *insts, int ninst, double *E, hipStream_t stream);
 
 }  // namespace vdwnl

@@ -7,6 +7,8 @@
 // compile-time twiddles.  Lengths without a specialisation use fft_lines.
 #pragma once
 
+#include <utility>
+
 #include "fft_lds.hpp"
 
 namespace vdwnl {
@@ -186,20 +188,60 @@ __host__ __device__ constexpr int len_class(int n) {
     return kLenGeneric;
 }
 
-// Unnormalised DFT (sign S) of nl lines of length p.n, for a length of class LC.
-template <typename T, int S, int LC>
+// Radix orders of each length class, variant V (chosen per pass group by
+// the autotuner): the passes' order changes the LDS access strides and the
+// twiddle pattern, not the result beyond rounding.  Lanes per line =
+// gcd(L / R_i) (within one wave), elements per lane <= 20.  Entries end at
+// the first zero; the last class (other lengths) uses the runtime plan.
+constexpr int kRadixOrders[kNumLenClasses][4][5] = {
+    {{4, 3, 2}},                                          // 24: 2 lanes, 12 each
+    {{8, 4}, {4, 8}},                                     // 32: 4 lanes, 8 each
+    {{4, 4, 3}, {3, 4, 4}},                               // 48: 4 lanes, 12 each
+    {{8, 8}, {4, 4, 4}},                                  // 64: 8 lanes, 8 each; 16 lanes, 4 each
+    {{4, 4, 2, 3}, {2, 4, 4, 3}, {3, 4, 4, 2}},          // 96: 8 lanes, 12 each
+    {{8, 4, 4}, {4, 4, 8}, {2, 8, 8}, {4, 8, 4}},        // 128: 16 lanes, 8 each
+    {{4, 4, 2, 5}, {5, 4, 4, 2}},                         // 160: 8 lanes, 20 each
+    {{4, 4, 4, 5}, {5, 4, 4, 4}},                         // 320: 16 lanes, 20 each
+    {},
+};
+
+__host__ __device__ constexpr int num_radices(int lc, int v) {
+    int n = 0;
+    while (n < 5 && kRadixOrders[lc][v][n] != 0) ++n;
+    return n;
+}
+
+__host__ __device__ constexpr int num_variants(int lc) {
+    int v = 0;
+    while (v < 4 && num_radices(lc, v) > 0) ++v;
+    return v;
+}
+
+constexpr int kNumVariants[kNumLenClasses] = {num_variants(0), num_variants(1), num_variants(2), num_variants(3),
+                                              num_variants(4), num_variants(5), num_variants(6), num_variants(7),
+                                              1};
+
+template <typename T, int S, int LC, int V, int... I>
+__device__ __forceinline__ void fft_ordered(C2<T> *buf, int nl, int es, int ls, const C2<T> *__restrict__ tw,
+                                            std::integer_sequence<int, I...>) {
+    fft_fast<T, S, kFastLens[LC], kRadixOrders[LC][V][I]...>(buf, nl, es, ls, tw);
+}
+
+// Unnormalised DFT (sign S) of nl lines of length p.n, for a length of class
+// LC, radix order V.
+template <typename T, int S, int LC, int V>
 __device__ __forceinline__ void fft_lc(C2<T> *buf, const FftPlan &p, int nl, int es, int ls,
                                        const C2<T> *__restrict__ tw) {
-    // radix sequences: lanes per line = gcd(L / R_i), elements per lane <= 20
-    if constexpr (LC == 0) fft_fast<T, S, 24, 4, 3, 2>(buf, nl, es, ls, tw);          // 2 lanes, 12 each
-    else if constexpr (LC == 1) fft_fast<T, S, 32, 8, 4>(buf, nl, es, ls, tw);        // 4 lanes, 8 each
-    else if constexpr (LC == 2) fft_fast<T, S, 48, 4, 4, 3>(buf, nl, es, ls, tw);     // 4 lanes, 12 each
-    else if constexpr (LC == 3) fft_fast<T, S, 64, 8, 8>(buf, nl, es, ls, tw);        // 8 lanes, 8 each
-    else if constexpr (LC == 4) fft_fast<T, S, 96, 4, 4, 2, 3>(buf, nl, es, ls, tw);  // 8 lanes, 12 each
-    else if constexpr (LC == 5) fft_fast<T, S, 128, 8, 4, 4>(buf, nl, es, ls, tw);    // 16 lanes, 8 each
-    else if constexpr (LC == 6) fft_fast<T, S, 160, 4, 4, 2, 5>(buf, nl, es, ls, tw); // 8 lanes, 20 each
-    else if constexpr (LC == 7) fft_fast<T, S, 320, 4, 4, 4, 5>(buf, nl, es, ls, tw); // 16 lanes, 20 each
-    else fft_lines<T>(buf, p, nl, es, ls, tw, S);
+    static_assert(V < kNumVariants[LC], "radix order out of range");
+    if constexpr (LC == kLenGeneric) fft_lines<T>(buf, p, nl, es, ls, tw, S);
+    else fft_ordered<T, S, LC, V>(buf, nl, es, ls, tw, std::make_integer_sequence<int, num_radices(LC, V)>{});
+}
+
+// The radix sequence of class lc, order v (host side), into r[]; its length.
+inline int radix_order_of(int lc, int v, int *r) {
+    const int n = num_radices(lc, v);
+    for (int i = 0; i < n; ++i) r[i] = kRadixOrders[lc][v][i];
+    return n;
 }
 
 }  // namespace vdwnl

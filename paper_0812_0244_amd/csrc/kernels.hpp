@@ -268,7 +268,7 @@ __device__ __forceinline__ void load_consts(const Consts *cst, T *qm, T *Mm, T *
 
 // R2C of n (read in T, transformed in FP64): rows (2p, 2p+1) of a tile form
 // one complex line.  tile: a = first row (i1 N2 + i2), b = rows (even)
-template <typename T, int LC>
+template <typename T, int LC, int V>
 __global__ void __launch_bounds__(kThreads) k_x_nfwd(const InstDev *insts, const Tile *tiles,
                                                      const void *twdv) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -287,7 +287,7 @@ __global__ void __launch_bounds__(kThreads) k_x_nfwd(const InstDev *insts, const
     });
     load_twiddles<double>(tw, I.p3, reinterpret_cast<const double2 *>(twdv));
     __syncthreads();
-    fft_lc<double, -1, LC>(buf, I.p3, np, 1, ls, tw);
+    fft_lc<double, -1, LC, V>(buf, I.p3, np, 1, ls, tw);
     double2 *out = reinterpret_cast<double2 *>(I.spec1) + (size_t)row0 * N3h;
     for (int idx = threadIdx.x; idx < B * N3h; idx += kThreads) {
         const int rb = idx / N3h, k = idx - rb * N3h;
@@ -305,7 +305,7 @@ __global__ void __launch_bounds__(kThreads) k_x_nfwd(const InstDev *insts, const
 // d1 + i d2 of row 2p and of row 2p+1, 3p+2 holds d3 of row 2p + i d3 of row
 // 2p+1 (each real field has a Hermitian spectrum: the half spectrum at k and,
 // conjugated, at N3 - k).  tile: a = first row, b = rows (even).
-template <typename T, int LC>
+template <typename T, int LC, int V>
 __global__ void __launch_bounds__(kThreads) k_x_grad(const InstDev *insts, const Tile *tiles,
                                                      const void *twdv) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -336,7 +336,7 @@ __global__ void __launch_bounds__(kThreads) k_x_grad(const InstDev *insts, const
     });
     load_twiddles<double>(tw, I.p3, reinterpret_cast<const double2 *>(twdv));
     __syncthreads();
-    fft_lc<double, 1, LC>(buf, I.p3, 3 * np, 1, ls, tw);
+    fft_lc<double, 1, LC, V>(buf, I.p3, 3 * np, 1, ls, tw);
     const gptr<T> g = gst(reinterpret_cast<T *>(I.grad) + (size_t)row0 * N3);
     for (int idx = threadIdx.x; idx < B * N3; idx += kThreads) {
         const int rb = idx / N3, k = idx - rb * N3, pr = rb >> 1, odd = rb & 1;
@@ -349,7 +349,7 @@ __global__ void __launch_bounds__(kThreads) k_x_grad(const InstDev *insts, const
 
 // theta_a = n p_a(q0) from n and the stored grad n, Delta E partials, R2C of
 // the 20 theta rows.  tile: a = first row, b = rows, slot = partial.
-template <typename T, int LC>
+template <typename T, int LC, int V>
 __global__ void __launch_bounds__(kThreads) k_x_theta(const InstDev *insts, const Tile *tiles,
                                                       const Consts *cst, const void *twv) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -424,7 +424,7 @@ __global__ void __launch_bounds__(kThreads) k_x_theta(const InstDev *insts, cons
         }
     }
     __syncthreads();
-    fft_lc<T, -1, LC>(r2, I.p3, kNQ / 2 * B, 1, ls, tw);
+    fft_lc<T, -1, LC, V>(r2, I.p3, kNQ / 2 * B, 1, ls, tw);
 
     // pair line m of row rb holds theta_{2m} + i theta_{2m+1}: its values at
     // k and N3 - k give both spectra at k, written together (item idx =
@@ -496,7 +496,7 @@ __device__ __forceinline__ void u_lines_in(C2<T> *r2, int ls, const C2<T> *sp, i
 // w = g grad n with g = sum_a u_a 2 n p'_a Q dq/dsigma + de/dsigma-part;
 // R2C of the three w rows (in T: the divergence chain runs in the working
 // precision), or (FD) w stored in place of grad n.  tile: a = first row, b = rows.
-template <typename T, int LC, bool FD>
+template <typename T, int LC, int V, bool FD>
 __global__ void __launch_bounds__(kThreads) k_x_assemble(const InstDev *insts, const Tile *tiles,
                                                          const Consts *cst, const void *twv) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -523,7 +523,7 @@ __global__ void __launch_bounds__(kThreads) k_x_assemble(const InstDev *insts, c
     load_consts<T>(cst, qm, Mm, invm);
     load_twiddles<T>(tw, I.p3, reinterpret_cast<const C2<T> *>(twv));
     __syncthreads();
-    fft_lc<T, 1, LC>(r2, I.p3, kNQ / 2 * B, 1, ls, tw);
+    fft_lc<T, 1, LC, V>(r2, I.p3, kNQ / 2 * B, 1, ls, tw);
 
     const double c_qc = cst->qc, c_iqc = cst->iqc, c_cs = cst->cs, c_nmin = cst->nmin;
     const int c_mc = cst->mc;
@@ -589,7 +589,7 @@ __global__ void __launch_bounds__(kThreads) k_x_assemble(const InstDev *insts, c
     }
     if constexpr (!FD) {
         __syncthreads();
-        fft_lc<T, -1, LC>(r1, I.p3, 2 * B, 1, ls, tw);
+        fft_lc<T, -1, LC, V>(r1, I.p3, 2 * B, 1, ls, tw);
         C2<T> *out = reinterpret_cast<C2<T> *>(I.spec3) + (size_t)row0 * N3h * 3;
         for (int idx = threadIdx.x; idx < B * N3h * 3; idx += kThreads) {
             const int comp = idx % 3, rest = idx / 3;
@@ -724,7 +724,7 @@ __global__ void __launch_bounds__(kThreads) k_fd_div(const InstDev *insts, const
 }
 
 // C2R of the divergence spectrum (row pairs, working precision), v = v_loc - div.
-template <typename T, int LC>
+template <typename T, int LC, int V>
 __global__ void __launch_bounds__(kThreads) k_x_final(const InstDev *insts, const Tile *tiles,
                                                       const void *twv) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -748,7 +748,7 @@ __global__ void __launch_bounds__(kThreads) k_x_final(const InstDev *insts, cons
     });
     load_twiddles<T>(tw, I.p3, reinterpret_cast<const C2<T> *>(twv));
     __syncthreads();
-    fft_lc<T, 1, LC>(buf, I.p3, np, 1, ls, tw);
+    fft_lc<T, 1, LC, V>(buf, I.p3, np, 1, ls, tw);
     const gptr<T> v = gst(reinterpret_cast<T *>(I.v) + (size_t)row0 * N3);
     batched<4>(npt, [&](int idx) { return vloc[idx]; }, [&](int idx, T vl) {
         const int rb = idx / N3, k = idx - rb * N3;
@@ -759,30 +759,31 @@ __global__ void __launch_bounds__(kThreads) k_x_final(const InstDev *insts, cons
 
 // ---------------------------------------------------------------- axis-2 pass
 
-// tile: a = i1, b = first flattened (k3, component) index, c = width
-template <typename T, int S, int LC>
+// tile: a = i1, b = first flattened (k3, component) index, c = width;
+// ncomp components per k point
+template <typename T, int S, int LC, int V>
 __global__ void __launch_bounds__(kThreads) k_y(const InstDev *insts, const Tile *tiles,
-                                                const void *twv, int which, int V) {
+                                                const void *twv, int which, int ncomp) {
     extern __shared__ __align__(16) unsigned char smem[];
     const Tile t = tiles[blockIdx.x];
     const InstDev &I = insts[t.inst];
     const int N2 = axis_len<LC>(I.n2), W = t.c, lp = N2 | 1;   // lines contiguous, odd pitch
     C2<T> *tw = reinterpret_cast<C2<T> *>(smem);
     C2<T> *buf = tw + N2;
-    const size_t rowlen = (size_t)I.n3h * V;
+    const size_t rowlen = (size_t)I.n3h * ncomp;
     void *base = which == 0 ? I.spec : (which == 1 ? I.spec3 : I.spec1);
     C2<T> *g = reinterpret_cast<C2<T> *>(base) + (size_t)t.a * N2 * rowlen + t.b;
     rows_in_t(buf, lp, g, rowlen, N2, W);
     load_twiddles<T>(tw, I.p2, reinterpret_cast<const C2<T> *>(twv));
     __syncthreads();
-    fft_lc<T, S, LC>(buf, I.p2, W, 1, lp, tw);
+    fft_lc<T, S, LC, V>(buf, I.p2, W, 1, lp, tw);
     rows_out_t(g, rowlen, buf, lp, N2, W);
 }
 
 // ---------------------------------------------------------------- axis-1 passes
 
 // n spectrum -> i G_c n / N, c = 1..3.  tile: a = k2, b = first k3, c = count
-template <typename T, int LC>
+template <typename T, int LC, int V>
 __global__ void __launch_bounds__(kThreads) k_z_grad(const InstDev *insts, const Tile *tiles,
                                                      const void *twv) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -798,7 +799,7 @@ __global__ void __launch_bounds__(kThreads) k_z_grad(const InstDev *insts, const
     rows_in_t(bin, lp, gin, sin_, N1, K3);
     load_twiddles<T>(twall, I.p1, reinterpret_cast<const C2<T> *>(twv));
     __syncthreads();
-    fft_lc<T, -1, LC>(bin, I.p1, K3, 1, lp, twall);
+    fft_lc<T, -1, LC, V>(bin, I.p1, K3, 1, lp, twall);
     const double m2 = (double)freq_nz(k2, N2);
     for (int idx = threadIdx.x; idx < N1 * K3; idx += kThreads) {
         const int w = idx / N1, l = idx - w * N1;
@@ -811,13 +812,13 @@ __global__ void __launch_bounds__(kThreads) k_z_grad(const InstDev *insts, const
         o[2 * lp] = mk<T>(-G3 * nh.y, G3 * nh.x);
     }
     __syncthreads();
-    fft_lc<T, 1, LC>(bout, I.p1, 3 * K3, 1, lp, twall);
+    fft_lc<T, 1, LC, V>(bout, I.p1, 3 * K3, 1, lp, twall);
     C2<T> *gout = reinterpret_cast<C2<T> *>(I.spec3) + ((size_t)k2 * N3h + k30) * 3;
     rows_out_t(gout, sin_ * 3, bout, lp, N1, 3 * K3);
 }
 
 // sum_c i G_c w_c / N.  tile: a = k2, b = first k3, c = count
-template <typename T, int LC>
+template <typename T, int LC, int V>
 __global__ void __launch_bounds__(kThreads) k_z_div(const InstDev *insts, const Tile *tiles,
                                                     const void *twv) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -833,7 +834,7 @@ __global__ void __launch_bounds__(kThreads) k_z_div(const InstDev *insts, const 
     rows_in_t(bin, lp, gin, sin_ * 3, N1, 3 * K3);
     load_twiddles<T>(twall, I.p1, reinterpret_cast<const C2<T> *>(twv));
     __syncthreads();
-    fft_lc<T, -1, LC>(bin, I.p1, 3 * K3, 1, lp, twall);
+    fft_lc<T, -1, LC, V>(bin, I.p1, 3 * K3, 1, lp, twall);
     const double m2 = (double)freq_nz(k2, N2);
     for (int idx = threadIdx.x; idx < N1 * K3; idx += kThreads) {
         const int w = idx / N1, l = idx - w * N1;
@@ -845,7 +846,7 @@ __global__ void __launch_bounds__(kThreads) k_z_div(const InstDev *insts, const 
         bout[w * lp + l] = cscale(mk<T>(-sy, sx), (T)I.inv_n);
     }
     __syncthreads();
-    fft_lc<T, 1, LC>(bout, I.p1, K3, 1, lp, twall);
+    fft_lc<T, 1, LC, V>(bout, I.p1, K3, 1, lp, twall);
     C2<T> *gout = reinterpret_cast<C2<T> *>(I.spec1) + (size_t)k2 * N3h + k30;
     rows_out_t(gout, sin_, bout, lp, N1, K3);
 }
@@ -872,7 +873,7 @@ __global__ void __launch_bounds__(kThreads) k_z_div(const InstDev *insts, const 
 // MF (FP32, orthorhombic cells): the contraction on the matrix cores (see the
 // item loop below) instead of the vector ALU; the same items, the same
 // results up to the order of the FP32 additions.
-template <typename T, int LC, bool GEN, int PROBE, bool MF>
+template <typename T, int LC, int V, bool GEN, int PROBE, bool MF>
 __global__ void __launch_bounds__(kThreads) k_z_main(const InstDev *insts, const Tile *tiles, const int2 *cols,
                                                      const void *twv) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -1031,7 +1032,7 @@ __global__ void __launch_bounds__(kThreads) k_z_main(const InstDev *insts, const
     } else {
         if (PROBE != 1 && lane_on) fetch(gid, fa);
     }
-    fft_lc<T, -1, LC>(buf, I.p1, W, 1, lp, twall);
+    fft_lc<T, -1, LC, V>(buf, I.p1, W, 1, lp, twall);
     if constexpr (PROBE == 1) {
         const T inv_n = (T)I.inv_n;
         for (int i = threadIdx.x; i < W * lp; i += kThreads) buf[i] = cscale(buf[i], inv_n);
@@ -1177,7 +1178,7 @@ __global__ void __launch_bounds__(kThreads) k_z_main(const InstDev *insts, const
         }
     }
     __syncthreads();
-    if constexpr (PROBE == 0) fft_lc<T, 1, LC>(buf, I.p1, W, 1, lp, twall);
+    if constexpr (PROBE == 0) fft_lc<T, 1, LC, V>(buf, I.p1, W, 1, lp, twall);
     io(false);
     const double sum = block_sum(e);
     if (threadIdx.x == 0) I.part_ek[t.slot] = sum;
@@ -1234,7 +1235,7 @@ __global__ void __launch_bounds__(kThreads) k_probe_theta(const InstDev *insts, 
 // u_a(r_i) = sum_G u_a(G) exp(i G.r_i) (Eq. (epsilon)): the inverse axis-3
 // transform of the u spectra, as the assembly pass forms it, into dst
 // [kNQ][N] (working precision).  tile: a = first row, b = rows.
-template <typename T, int LC>
+template <typename T, int LC, int V>
 __global__ void __launch_bounds__(kThreads) k_probe_u(const InstDev *insts, const Tile *tiles, const void *twv,
                                                       void *dstv, int target) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -1248,7 +1249,7 @@ __global__ void __launch_bounds__(kThreads) k_probe_u(const InstDev *insts, cons
     u_lines_in<T>(r2, ls, reinterpret_cast<const C2<T> *>(I.spec) + (size_t)row0 * N3h * kNQ, B, N3, N3h);
     load_twiddles<T>(tw, I.p3, reinterpret_cast<const C2<T> *>(twv));
     __syncthreads();
-    fft_lc<T, 1, LC>(r2, I.p3, kNQ / 2 * B, 1, ls, tw);
+    fft_lc<T, 1, LC, V>(r2, I.p3, kNQ / 2 * B, 1, ls, tw);
     T *dst = reinterpret_cast<T *>(dstv) + (size_t)row0 * N3;
     for (int idx = threadIdx.x; idx < (kNQ / 2) * B * N3; idx += kThreads) {
         const int m = idx / (B * N3), rest = idx - m * B * N3, rb = rest / N3, k = rest - rb * N3;
@@ -1260,115 +1261,99 @@ __global__ void __launch_bounds__(kThreads) k_probe_u(const InstDev *insts, cons
 
 // ---------------------------------------------------------------- launchers
 
+// The passes launch by family (the axis they transform): axis 3 (x), axis 2
+// (y), axis 1 (z); each family's launcher is compiled in a translation unit
+// of its own per precision (kernels_f32_x.hip ...), so the build runs them in
+// parallel.  A launch with ntiles == 0 only raises the kernel's LDS limit
+// (done once when the launches are planned, never while a stream is being
+// captured).
+
 // Kernels that take more than 64 KB of LDS opt in to the device's limit.
 template <typename K>
 static void allow_lds(K kernel, size_t bytes) {
     if (bytes > 65536) (void)hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
-// (launch_lc with ntiles == 0 only raises the kernel's LDS limit: done once
-// when the launches are planned, never while a stream is being captured)
 
-template <typename T, int LC>
-static hipError_t launch_lc(int kind, const LaunchArgs &a) {
-    dim3 grid(a.ntiles), block(kThreads);
-#define VDWNL_LAUNCH(kern, ...)                                                                  \
-    do {                                                                                         \
-        if (a.ntiles == 0) allow_lds(kern, a.lds);                                               \
-        else hipLaunchKernelGGL(kern, grid, block, a.lds, a.stream, a.insts, a.tiles, __VA_ARGS__); \
+#define VDWNL_LAUNCH(kern, ...)                                                                      \
+    do {                                                                                             \
+        if (a.ntiles == 0) allow_lds(kern, a.lds);                                                   \
+        else hipLaunchKernelGGL(kern, dim3(a.ntiles), dim3(kThreads), a.lds, a.stream, a.insts, a.tiles, \
+                                __VA_ARGS__);                                                        \
     } while (0)
+
+template <typename T, int LC, int V>
+hipError_t launch_x_lc(int kind, const LaunchArgs &a) {
     switch (kind) {
-        case KX_NFWD: VDWNL_LAUNCH((k_x_nfwd<T, LC>), a.twd); break;
-        case KY_1F: VDWNL_LAUNCH((k_y<double, -1, LC>), a.twd, 2, 1); break;
-        case KZ_GRAD: VDWNL_LAUNCH((k_z_grad<double, LC>), a.twd); break;
-        case KY_3I: VDWNL_LAUNCH((k_y<double, 1, LC>), a.twd, 1, 3); break;
-        case KX_GRAD: VDWNL_LAUNCH((k_x_grad<T, LC>), a.twd); break;
-        case KX_THETA: VDWNL_LAUNCH((k_x_theta<T, LC>), a.cst, a.tw); break;
-        case KY_20F: VDWNL_LAUNCH((k_y<T, -1, LC>), a.tw, 0, kNQ); break;
+        case KX_NFWD: VDWNL_LAUNCH((k_x_nfwd<T, LC, V>), a.twd); break;
+        case KX_GRAD: VDWNL_LAUNCH((k_x_grad<T, LC, V>), a.twd); break;
+        case KX_THETA: VDWNL_LAUNCH((k_x_theta<T, LC, V>), a.cst, a.tw); break;
+        case KX_ASSEMBLE: VDWNL_LAUNCH((k_x_assemble<T, LC, V, false>), a.cst, a.tw); break;
+        case KX_ASSEMBLE_FD: VDWNL_LAUNCH((k_x_assemble<T, LC, V, true>), a.cst, a.tw); break;
+        case KX_FINAL: VDWNL_LAUNCH((k_x_final<T, LC, V>), a.tw); break;
+        case KP_U: VDWNL_LAUNCH((k_probe_u<T, LC, V>), a.tw, a.dst, a.target); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T, int LC, int V>
+hipError_t launch_y_lc(int kind, const LaunchArgs &a) {
+    switch (kind) {
+        // (the gradient chain in FP64)
+        case KY_1F: VDWNL_LAUNCH((k_y<double, -1, LC, V>), a.twd, 2, 1); break;
+        case KY_3I: VDWNL_LAUNCH((k_y<double, 1, LC, V>), a.twd, 1, 3); break;
+        case KY_20F: VDWNL_LAUNCH((k_y<T, -1, LC, V>), a.tw, 0, kNQ); break;
+        case KY_20I: VDWNL_LAUNCH((k_y<T, 1, LC, V>), a.tw, 0, kNQ); break;
+        case KY_3F: VDWNL_LAUNCH((k_y<T, -1, LC, V>), a.tw, 1, 3); break;
+        case KY_1I: VDWNL_LAUNCH((k_y<T, 1, LC, V>), a.tw, 2, 1); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T, int LC, int V>
+hipError_t launch_z_lc(int kind, const LaunchArgs &a) {
+    constexpr bool F32 = sizeof(T) == 4;
+    switch (kind) {
+        case KZ_GRAD: VDWNL_LAUNCH((k_z_grad<double, LC, V>), a.twd); break;
+        case KZ_DIV: VDWNL_LAUNCH((k_z_div<T, LC, V>), a.tw); break;
         case KZ_MAIN:
-            if (a.general) VDWNL_LAUNCH((k_z_main<T, LC, true, 0, false>), a.cols, a.tw);
-            else if (sizeof(T) == 4 && a.mfma) VDWNL_LAUNCH((k_z_main<T, LC, false, 0, sizeof(T) == 4>), a.cols, a.tw);
-            else VDWNL_LAUNCH((k_z_main<T, LC, false, 0, false>), a.cols, a.tw);
+            if (a.general) VDWNL_LAUNCH((k_z_main<T, LC, V, true, 0, false>), a.cols, a.tw);
+            else if (F32 && a.mfma) VDWNL_LAUNCH((k_z_main<T, LC, V, false, 0, F32>), a.cols, a.tw);
+            else VDWNL_LAUNCH((k_z_main<T, LC, V, false, 0, false>), a.cols, a.tw);
             break;
-        case KY_20I: VDWNL_LAUNCH((k_y<T, 1, LC>), a.tw, 0, kNQ); break;
-        case KX_ASSEMBLE: VDWNL_LAUNCH((k_x_assemble<T, LC, false>), a.cst, a.tw); break;
-        case KX_ASSEMBLE_FD: VDWNL_LAUNCH((k_x_assemble<T, LC, true>), a.cst, a.tw); break;
-        case KY_3F: VDWNL_LAUNCH((k_y<T, -1, LC>), a.tw, 1, 3); break;
-        case KZ_DIV: VDWNL_LAUNCH((k_z_div<T, LC>), a.tw); break;
-        case KY_1I: VDWNL_LAUNCH((k_y<T, 1, LC>), a.tw, 2, 1); break;
-        case KX_FINAL: VDWNL_LAUNCH((k_x_final<T, LC>), a.tw); break;
+        case KP_THETA_K:
+            if (a.general) VDWNL_LAUNCH((k_z_main<T, LC, V, true, 1, false>), a.cols, a.tw);
+            else VDWNL_LAUNCH((k_z_main<T, LC, V, false, 1, false>), a.cols, a.tw);
+            break;
+        case KP_U_K:
+            if (a.general) VDWNL_LAUNCH((k_z_main<T, LC, V, true, 2, false>), a.cols, a.tw);
+            else if (F32 && a.mfma) VDWNL_LAUNCH((k_z_main<T, LC, V, false, 2, F32>), a.cols, a.tw);
+            else VDWNL_LAUNCH((k_z_main<T, LC, V, false, 2, false>), a.cols, a.tw);
+            break;
         default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
 #undef VDWNL_LAUNCH
-    return hipGetLastError();
-}
 
-template <typename T>
-static hipError_t launch_kind_t(int kind, int lc, const LaunchArgs &a) {
-    if (a.ntiles < 0) return hipErrorInvalidValue;
-    if (kind == KF_GRAD || kind == KF_DIV) {   // no FFT and no LDS: one launch for every grid
-        if (a.ntiles == 0) return hipSuccess;
-        if (kind == KF_GRAD) hipLaunchKernelGGL(k_fd_grad<T>, dim3(a.ntiles), dim3(kThreads), 0, a.stream, a.insts, a.tiles);
-        else hipLaunchKernelGGL(k_fd_div<T>, dim3(a.ntiles), dim3(kThreads), 0, a.stream, a.insts, a.tiles);
-        return hipGetLastError();
+// (length class, radix order) at run time -> the compiled instance; an order
+// beyond the class's variants takes its last one
+#define VDWNL_LC_VARIANTS(FN, T, kind, lc, var, a)                                                        \
+    switch (lc) {                                                                                         \
+        case 0: return FN<T, 0, 0>(kind, a);                                                              \
+        case 1: return (var) >= 1 ? FN<T, 1, 1>(kind, a) : FN<T, 1, 0>(kind, a);                          \
+        case 2: return (var) >= 1 ? FN<T, 2, 1>(kind, a) : FN<T, 2, 0>(kind, a);                          \
+        case 3: return (var) >= 1 ? FN<T, 3, 1>(kind, a) : FN<T, 3, 0>(kind, a);                          \
+        case 4: return (var) >= 2 ? FN<T, 4, 2>(kind, a) : (var) == 1 ? FN<T, 4, 1>(kind, a) : FN<T, 4, 0>(kind, a); \
+        case 5:                                                                                           \
+            return (var) >= 3 ? FN<T, 5, 3>(kind, a)                                                      \
+                   : (var) == 2 ? FN<T, 5, 2>(kind, a)                                                    \
+                   : (var) == 1 ? FN<T, 5, 1>(kind, a) : FN<T, 5, 0>(kind, a);                            \
+        case 6: return (var) >= 1 ? FN<T, 6, 1>(kind, a) : FN<T, 6, 0>(kind, a);                          \
+        case 7: return (var) >= 1 ? FN<T, 7, 1>(kind, a) : FN<T, 7, 0>(kind, a);                          \
+        default: return FN<T, kLenGeneric, 0>(kind, a);                                                   \
     }
-    switch (lc) {
-        case 0: return launch_lc<T, 0>(kind, a);
-        case 1: return launch_lc<T, 1>(kind, a);
-        case 2: return launch_lc<T, 2>(kind, a);
-        case 3: return launch_lc<T, 3>(kind, a);
-        case 4: return launch_lc<T, 4>(kind, a);
-        case 5: return launch_lc<T, 5>(kind, a);
-        case 6: return launch_lc<T, 6>(kind, a);
-        case 7: return launch_lc<T, 7>(kind, a);
-        default: return launch_lc<T, kLenGeneric>(kind, a);
-    }
-}
-
-
-template <typename T, int LC>
-static hipError_t launch_probe_lc(int probe, const LaunchArgs &a, void *dst, int target) {
-    dim3 grid(a.ntiles), block(kThreads);
-#define VDWNL_PROBE(kern, ...)                                                                   \
-    do {                                                                                         \
-        if (a.ntiles == 0) allow_lds(kern, a.lds);                                               \
-        else hipLaunchKernelGGL(kern, grid, block, a.lds, a.stream, a.insts, a.tiles, __VA_ARGS__); \
-    } while (0)
-    switch (probe) {
-        case PROBE_THETA_K:
-            if (a.general) VDWNL_PROBE((k_z_main<T, LC, true, 1, false>), a.cols, a.tw);
-            else VDWNL_PROBE((k_z_main<T, LC, false, 1, false>), a.cols, a.tw);
-            break;
-        case PROBE_U_K:
-            if (a.general) VDWNL_PROBE((k_z_main<T, LC, true, 2, false>), a.cols, a.tw);
-            else if (sizeof(T) == 4 && a.mfma) VDWNL_PROBE((k_z_main<T, LC, false, 2, sizeof(T) == 4>), a.cols, a.tw);
-            else VDWNL_PROBE((k_z_main<T, LC, false, 2, false>), a.cols, a.tw);
-            break;
-        case PROBE_U: VDWNL_PROBE((k_probe_u<T, LC>), a.tw, dst, target); break;
-        case PROBE_THETA:
-            if (a.ntiles > 0)
-                hipLaunchKernelGGL(k_probe_theta<T>, grid, block, 0, a.stream, a.insts, a.tiles, a.cst, dst, target);
-            break;
-        default: return hipErrorInvalidValue;
-    }
-#undef VDWNL_PROBE
-    return hipGetLastError();
-}
-
-template <typename T>
-static hipError_t launch_probe_t(int probe, int lc, const LaunchArgs &a, void *dst, int target) {
-    switch (lc) {
-        case 0: return launch_probe_lc<T, 0>(probe, a, dst, target);
-        case 1: return launch_probe_lc<T, 1>(probe, a, dst, target);
-        case 2: return launch_probe_lc<T, 2>(probe, a, dst, target);
-        case 3: return launch_probe_lc<T, 3>(probe, a, dst, target);
-        case 4: return launch_probe_lc<T, 4>(probe, a, dst, target);
-        case 5: return launch_probe_lc<T, 5>(probe, a, dst, target);
-        case 6: return launch_probe_lc<T, 6>(probe, a, dst, target);
-        case 7: return launch_probe_lc<T, 7>(probe, a, dst, target);
-        default: return launch_probe_lc<T, kLenGeneric>(probe, a, dst, target);
-    }
-}
-
-
 
 }  // namespace vdwnl

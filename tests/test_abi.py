@@ -272,9 +272,44 @@ def test_schedule_choice_arguments():
     v = ctypes.c_int32(-1)
     assert lib.vdwnl_set_schedule(h, 0, 1) == E["STATE"]          # no grid planned
     assert _set_grid(lib, h, (24, 24, 24)) == 0
-    for what, val, code in [(0, 0, 0), (0, 1, 0), (0, 2, E["ARG"]), (1, 0, E["ARG"]), (0, -1, E["ARG"])]:
+    for what, val, code in [(0, 0, 0), (0, 1, 0), (0, 2, E["ARG"]), (7, 0, E["ARG"]), (0, -1, E["ARG"])]:
         assert lib.vdwnl_set_schedule(h, what, val) == code
     assert lib.vdwnl_get_schedule(h, 0, ctypes.byref(v)) == 0 and v.value == 1
-    assert lib.vdwnl_get_schedule(h, 3, ctypes.byref(v)) == E["ARG"]
+    assert lib.vdwnl_get_schedule(h, 9, ctypes.byref(v)) == E["ARG"]
     assert lib.vdwnl_get_schedule(h, 0, None) == E["ARG"]
+    lib.vdwnl_destroy(h)
+
+
+def test_radix_orders_multiply_to_their_length():
+    """Every radix order of every compile-time length class (and the runtime
+    plan of other lengths) is a factorisation of the length into passes of
+    2, 3, 4, 5 and 8; the orders of a length are distinct; an order past a
+    length's last takes its last."""
+    for n, count in [(24, 1), (32, 2), (48, 2), (64, 2), (96, 3), (128, 4), (160, 2), (320, 2), (36, 1), (250, 1)]:
+        seen = []
+        for v in range(4):
+            r = B.radix_order(n, v)
+            assert np.prod(r) == n and all(x in (2, 3, 4, 5, 8) for x in r), (n, v, r)
+            if v < count:
+                assert r not in seen
+                seen.append(r)
+            else:
+                assert r == seen[-1]
+    lib = B.load_library()
+    out = (ctypes.c_int32 * 8)()
+    assert lib.vdwnl_radix_order(14, 0, 8, out) == E["SIZE"]
+    assert lib.vdwnl_radix_order(128, 4, 8, out) == E["ARG"]
+    assert lib.vdwnl_radix_order(128, 0, 8, None) == E["ARG"]
+    assert lib.vdwnl_radix_order(128, 2, 1, out) == 3 and out[0] == 2     # (count returned, one written)
+
+
+def test_radix_schedule_arguments():
+    lib, h = _host_ctx()
+    v = ctypes.c_int32(-1)
+    assert _set_grid(lib, h, (24, 24, 24)) == 0
+    for what in range(1, 6):
+        assert lib.vdwnl_set_schedule(h, what, 3) == 0
+        assert lib.vdwnl_get_schedule(h, what, ctypes.byref(v)) == 0 and v.value == 3
+        assert lib.vdwnl_set_schedule(h, what, 4) == E["ARG"]
+    assert lib.vdwnl_set_schedule(h, 6, 0) == E["ARG"]
     lib.vdwnl_destroy(h)
