@@ -238,6 +238,10 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--lds-budgets", type=str, default=None,
                     help="x,y20,yaux,z,zaux LDS budgets in bytes (fixes the tiles; no tuning)")
+    ap.add_argument("--radix-orders", type=str, default=None,
+                    help="x,y20,yaux,z,zaux radix orders 0..3 (with --lds-budgets; no tuning)")
+    ap.add_argument("--contraction", type=int, default=None,
+                    help="0: vector ALU, 1: matrix cores (with --lds-budgets; no tuning)")
     ap.add_argument("--fd-mode", type=int, default=3,
                     help="finite-difference half-width of the second leg (0: skip that leg)")
     ap.add_argument("--lattice-leg", type=int, default=1,
@@ -295,6 +299,10 @@ def main():
     t0 = time.time()
     if args.lds_budgets:
         lib.set_tiling([int(x) for x in args.lds_budgets.split(",")])
+        if args.radix_orders:
+            lib.set_radix_orders([int(x) for x in args.radix_orders.split(",")])
+        if args.contraction is not None:
+            lib.set_contraction(args.contraction)
     elif not args.no_autotune:
         lib.autotune(nptr, vptr, reps=5, stream=stream)
     tiling = lib.get_tiling()

@@ -32,9 +32,12 @@ feeds the same table to both sides):
   because the integrand settles into its oscillatory tail only for a >> d.
 * along each ray, phi is sampled at log-spaced D in [d_s, X] and splined in
   log D (phi itself up to D = 10, log(-phi) beyond, where phi < 0); beyond
-  X = min(20/min(cos, sin), 400) the r^-6 asymptote -C/(d1^2 d2^2 (d1^2+d2^2)),
+  X = min(20/min(cos, sin), 2000) the r^-6 asymptote -C/(d1^2 d2^2 (d1^2+d2^2)),
   C = 12 (4 pi/9)^3, is used and its transform is added in closed form
-  (sine/cosine integrals).
+  (sine/cosine integrals).  The asymptote needs both d1 and d2 large: on the
+  most skewed ray of the default mesh (q_b/q_a = 100) phi/asymptote is 1.038
+  at d1 = 4, 1.0000 from d1 = 12 on, so X reaches d1 = 20 there (an end at
+  D = 400 had left 1.2e-4 of that pair's largest table value at k = 0).
 * radial transform: trapezoid rule on a uniform D mesh (step d_s/200, the
   soft-region boundary is a node).
 """
@@ -190,7 +193,7 @@ class Ray:
         self.c, self.s = float(cos_t), float(sin_t)
         self.ds, self.phi0 = float(ds), float(phi0)
         cmin = min(self.c, self.s)
-        self.X = min(20.0 / cmin, 400.0)
+        self.X = min(20.0 / cmin, 2000.0)
         # value and slope at d_s (slope by a centred difference of the exact kernel)
         h = 1e-3 * ds
         p = phi(np.array([ds - h, ds, ds + h]) * self.c, np.array([ds - h, ds, ds + h]) * self.s)
@@ -327,7 +330,7 @@ def kernel_table(nq=20, q1=0.05, qc=5.0, lam=1.17, nk=6401, dk=0.005, ds=1.0, ph
     Returns a dict with ``qmesh`` [nq], ``phi`` [nq, nq, nk] (symmetric in a, b),
     ``dk``, ``nk``, ``c_soft``, ``ds``, ``phi0``.
     """
-    params = dict(nq=nq, q1=q1, qc=qc, lam=lam, nk=nk, dk=dk, ds=ds, phi0=phi0, version=3)
+    params = dict(nq=nq, q1=q1, qc=qc, lam=lam, nk=nk, dk=dk, ds=ds, phi0=phi0, version=4)
     key = hashlib.sha256(json.dumps(params, sort_keys=True).encode()).hexdigest()[:16]
     path = os.path.join(_CACHE, "table_%s.npz" % key)
     if cache and os.path.exists(path):

@@ -316,7 +316,10 @@ extern "C" int vdwnl_build_kernel_table(int device, int32_t nq, const double *qm
             r.Q = std::hypot(qmesh[a], qmesh[b]);
             r.c = qmesh[a] / r.Q;
             r.s = qmesh[b] / r.Q;
-            r.X = std::min(24.0 / std::min(r.c, r.s), 400.0);
+            // the r^-6 asymptote needs both d1 and d2 large: samples reach
+            // min(d1, d2) = 24 (phi/asymptote is 1.04 at min(d) = 4, 1.00000
+            // from 12 on; D up to 2400 on the most skewed rays)
+            r.X = std::min(24.0 / std::min(r.c, r.s), 2400.0);
             for (int i = 0; d_s + i * h1 < 10.0 - 1e-9; ++i) r.D.push_back(d_s + i * h1);
             for (int i = 0; 10.0 + i * 0.02 < std::min(40.0, r.X) - 1e-9; ++i) r.D.push_back(10.0 + i * 0.02);
             for (double D = 40.0; D < r.X - 1e-9; D *= 1.004) r.D.push_back(D);
