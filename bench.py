@@ -239,7 +239,7 @@ def main():
     ap.add_argument("--lds-budgets", type=str, default=None,
                     help="x,y20,yaux,z,zaux LDS budgets in bytes (fixes the tiles; no tuning)")
     ap.add_argument("--radix-orders", type=str, default=None,
-                    help="x,y20,yaux,z,zaux radix orders 0..3 (with --lds-budgets; no tuning)")
+                    help="x,y20,yaux,z,zaux radix orders 0..5 (with --lds-budgets; no tuning)")
     ap.add_argument("--contraction", type=int, default=None,
                     help="0: vector ALU, 1: matrix cores (with --lds-budgets; no tuning)")
     ap.add_argument("--fd-mode", type=int, default=3,

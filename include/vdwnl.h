@@ -276,7 +276,7 @@ int vdwnl_set_graph(vdwnl_ctx *ctx, int32_t on);
  * plus `reps` timed times (1..100) for each candidate LDS budget (and, for
  * FP32 orthorhombic grids, each contraction unit), picks per pass group the
  * budget (and unit) with the least time over the group's passes, then times
- * the radix orders 0..3 with those and picks one per group the same way,
+ * the radix orders 0..5 with those and picks one per group the same way,
  * plans with the choices and remembers them, keyed by the device
  * architecture, its LDS size,
  * the precision, the gradient mode and the exact grid list: for the rest of
@@ -309,10 +309,10 @@ int vdwnl_autotune(vdwnl_ctx *ctx, int32_t nb, const void *const *n_ptrs, void *
  * grid. */
 enum {
     VDWNL_SCHEDULE_CONTRACTION = 0,
-    /* radix order of the transforms of each pass group (0..3): every axis-3
+    /* radix order of the transforms of each pass group (0..5): every axis-3
      * transform, the axis-2 transforms of the 20 spectra, the other axis-2
      * transforms, the fused axis-1 pass, the other axis-1 passes.  Each length
-     * with a compile-time plan has one to four orders (vdwnl_radix_order),
+     * with a compile-time plan has one to six orders (vdwnl_radix_order),
      * and a larger value takes its last; other lengths have one. */
     VDWNL_SCHEDULE_RADIX_X = 1,
     VDWNL_SCHEDULE_RADIX_Y20 = 2,
@@ -324,8 +324,8 @@ enum { VDWNL_CONTRACTION_VECTOR = 0, VDWNL_CONTRACTION_MATRIX = 1 };
 int vdwnl_set_schedule(vdwnl_ctx *ctx, int32_t what, int32_t value);
 int vdwnl_get_schedule(const vdwnl_ctx *ctx, int32_t what, int32_t *value);
 
-/* The radix passes (each 2, 3, 4, 5 or 8, in order) of the transform of
- * length n in radix order `order` (0..3; a larger order than the length has
+/* The radix passes (each 2, 3, 4, 5, 8 or 16, in order) of the transform of
+ * length n in radix order `order` (0..5; a larger order than the length has
  * takes its last): up to max_radices values into radices[] (host array).
  * Returns their number, VDWNL_E_ARG for bad arguments, or
  * VDWNL_E_UNSUPPORTED_SIZE for a length with a prime factor above 5.  Host

@@ -286,7 +286,7 @@ class VdwNl:
         return int(v.value)
 
     def set_radix_orders(self, orders):
-        """orders: dict with keys x, y20, yaux, z, zaux (0..3), or a sequence of 5."""
+        """orders: dict with keys x, y20, yaux, z, zaux (0..5), or a sequence of 5."""
         if isinstance(orders, dict):
             orders = [orders[k] for k in RADIX_GROUPS]
         for i, v in enumerate(orders):

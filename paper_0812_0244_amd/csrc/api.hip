@@ -1753,11 +1753,11 @@ int vdwnl_autotune(vdwnl_ctx *ctx, int32_t nb, const void *const *n_ptrs, void *
     ctx->contraction = best_unit;
     for (int gi = 0; gi < TG_COUNT; ++gi) ctx->pref[gi] = best[gi];
     // radix orders, with the chosen budgets and unit: every group at order v
-    // (each length class clamps v to its last variant), v = 0..3, and per
-    // group the order with the least time over the group's transforms
+    // (each length class clamps v to its last variant), v = 0 .. kMaxVariants - 1,
+    // and per group the order with the least time over the group's transforms
     {
-        std::vector<std::vector<double>> tv(4, std::vector<double>(KIND_COUNT, 0.0));
-        for (int v = 0; v < 4 && rc == VDWNL_OK; ++v) {
+        std::vector<std::vector<double>> tv(kMaxVariants, std::vector<double>(KIND_COUNT, 0.0));
+        for (int v = 0; v < kMaxVariants && rc == VDWNL_OK; ++v) {
             for (auto &x : ctx->variant) x = v;
             for (auto &g : ctx->grids) size_tiles(ctx, g);
             free_device(ctx);
@@ -1771,7 +1771,7 @@ int vdwnl_autotune(vdwnl_ctx *ctx, int32_t nb, const void *const *n_ptrs, void *
         for (int gi = 0; gi < TG_COUNT; ++gi) {
             double bt = 1e300;
             int bv = 0;
-            for (int v = 0; rc == VDWNL_OK && v < 4; ++v) {
+            for (int v = 0; rc == VDWNL_OK && v < kMaxVariants; ++v) {
                 double sum = 0.0;
                 for (int k = 0; k < KIND_COUNT; ++k)
                     if (k != KF_GRAD && k != KF_DIV && variant_group(k) == gi) sum += tv[v][k];
@@ -1809,7 +1809,7 @@ int vdwnl_set_schedule(vdwnl_ctx *ctx, int32_t what, int32_t value) {
         if (value != VDWNL_CONTRACTION_VECTOR && value != VDWNL_CONTRACTION_MATRIX)
             return fail(ctx, VDWNL_E_ARG, "contraction must be VDWNL_CONTRACTION_VECTOR or VDWNL_CONTRACTION_MATRIX");
     } else if (what >= VDWNL_SCHEDULE_RADIX_X && what <= VDWNL_SCHEDULE_RADIX_ZAUX) {
-        if (value < 0 || value > 3) return fail(ctx, VDWNL_E_ARG, "radix order must be 0..3");
+        if (value < 0 || value >= kMaxVariants) return fail(ctx, VDWNL_E_ARG, "radix order must be 0..5");
     } else {
         return fail(ctx, VDWNL_E_ARG, "unknown schedule choice");
     }
@@ -1830,7 +1830,7 @@ int vdwnl_get_schedule(const vdwnl_ctx *ctx, int32_t what, int32_t *value) {
 }
 
 int vdwnl_radix_order(int32_t n, int32_t order, int32_t max_radices, int32_t *radices) {
-    if (max_radices < 0 || (max_radices > 0 && !radices) || order < 0 || order > 3) return VDWNL_E_ARG;
+    if (max_radices < 0 || (max_radices > 0 && !radices) || order < 0 || order >= kMaxVariants) return VDWNL_E_ARG;
     const int lc = len_class(n);
     int r[kMaxStages], nr = 0;
     if (lc == kLenGeneric) {

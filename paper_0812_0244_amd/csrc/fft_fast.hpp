@@ -128,11 +128,42 @@ struct FastPlan {
     static constexpr int TPL = gcd_all();
 };
 
+// Twiddles a lane applies in the passes from the one after NS combined
+// points on (the first pass, NS = 1, needs none): NB (R - 1) per pass.
+template <int L, int TPL, int NS, int... RS>
+struct TwCount {
+    static constexpr int value = 0;
+};
+template <int L, int TPL, int NS, int R, int... RS>
+struct TwCount<L, TPL, NS, R, RS...> {
+    static constexpr int value = (NS > 1 ? (L / R / TPL) * (R - 1) : 0) + TwCount<L, TPL, NS * R, RS...>::value;
+};
+
+// The lane's twiddles of every pass, in pass order, (m, r) within a pass:
+// W_{NS R}^{r (j % NS)} for butterfly j = t + m TPL, r = 1 .. R-1 (forward
+// sign; the inverse conjugates them where they are applied).
+template <typename T, int L, int TPL, int NS, int R, int... RS>
+__device__ __forceinline__ void tw_gather(C2<T> *w, const C2<T> *__restrict__ tw, int t) {
+    constexpr int NB = L / R / TPL;
+    if constexpr (NS > 1) {
+#pragma unroll
+        for (int m = 0; m < NB; ++m) {
+            const int kk = (t + m * TPL) % NS;
+#pragma unroll
+            for (int r = 1; r < R; ++r) w[m * (R - 1) + r - 1] = tw[r * kk * (L / (NS * R))];
+        }
+    }
+    if constexpr (sizeof...(RS) > 0) tw_gather<T, L, TPL, NS * R, RS...>(w + (NS > 1 ? NB * (R - 1) : 0), tw, t);
+}
+
 // Pass of radix R after NS points have been combined; lane t of the group
 // owns butterflies j = t + m TPL.  Reads e = j + r L/R, twiddles by
-// W_{NS R}^{r (j % NS)}, writes e = (j - j%NS) R + j%NS + r NS.
-template <typename T, int L, int S, int TPL, int NS, int R, int... RS>
-__device__ __forceinline__ void fast_passes(C2<T> *line, int es, const C2<T> *__restrict__ tw, int t) {
+// W_{NS R}^{r (j % NS)}, writes e = (j - j%NS) R + j%NS + r NS.  The
+// twiddles come from the lane's registers (wr, tw_gather's order) when REG,
+// else from the LDS table.
+template <typename T, int L, int S, int TPL, bool REG, int NS, int R, int... RS>
+__device__ __forceinline__ void fast_passes(C2<T> *line, int es, const C2<T> *__restrict__ tw, const C2<T> *wr,
+                                            int t) {
     constexpr int NB = L / R / TPL;
     C2<T> v[NB][R];
 #pragma unroll
@@ -143,7 +174,9 @@ __device__ __forceinline__ void fast_passes(C2<T> *line, int es, const C2<T> *__
         for (int r = 0; r < R; ++r) {
             C2<T> a = line[(j + r * (L / R)) * es];
             if (NS > 1 && r > 0) {
-                C2<T> w = tw[r * kk * (L / (NS * R))];
+                C2<T> w;
+                if constexpr (REG) w = wr[m * (R - 1) + r - 1];
+                else w = tw[r * kk * (L / (NS * R))];
                 if (S > 0) w.y = -w.y;
                 a = cmul(a, w);
             }
@@ -160,7 +193,8 @@ __device__ __forceinline__ void fast_passes(C2<T> *line, int es, const C2<T> *__
         for (int r = 0; r < R; ++r) line[((j - kk) * R + kk + r * NS) * es] = v[m][r];
     }
     wave_sync();
-    if constexpr (sizeof...(RS) > 0) fast_passes<T, L, S, TPL, NS * R, RS...>(line, es, tw, t);
+    if constexpr (sizeof...(RS) > 0)
+        fast_passes<T, L, S, TPL, REG, NS * R, RS...>(line, es, tw, wr + (NS > 1 ? NB * (R - 1) : 0), t);
 }
 
 template <typename T, int S, int L, int... RS>
@@ -169,9 +203,15 @@ __device__ __forceinline__ void fft_fast(C2<T> *buf, int nl, int es, int ls, con
     static_assert(64 % TPL == 0, "a line's lanes must sit in one wave");
     constexpr int G = kThreads / TPL;
     const int grp = threadIdx.x / TPL, t = threadIdx.x - grp * TPL;
+    // the lane's twiddles are the same for every line it transforms: read
+    // once into registers when they take at most 64 VGPRs
+    constexpr int NTW = TwCount<L, TPL, 1, RS...>::value;
+    constexpr bool REG = NTW > 0 && NTW * (int)sizeof(C2<T>) <= 64 * 4;
+    C2<T> wr[REG ? NTW : 1];
+    if constexpr (REG) tw_gather<T, L, TPL, 1, RS...>(wr, tw, t);
     for (int l0 = 0; l0 < nl; l0 += G) {
         const int line = l0 + grp;
-        if (line < nl) fast_passes<T, L, S, TPL, 1, RS...>(buf + line * ls, es, tw, t);
+        if (line < nl) fast_passes<T, L, S, TPL, REG, 1, RS...>(buf + line * ls, es, tw, wr, t);
     }
     __syncthreads();
 }
@@ -189,17 +229,20 @@ __host__ __device__ constexpr int len_class(int n) {
 }
 
 // Radix orders of each length class, variant V (chosen per pass group by
-// the autotuner): the passes' order changes the LDS access strides and the
-// twiddle pattern, not the result beyond rounding.  Lanes per line =
+// the autotuner): the passes' order and number change the LDS access
+// strides, the LDS round trips and the twiddle pattern, not the result
+// beyond rounding.  Lanes per line =
 // gcd(L / R_i) (within one wave), elements per lane <= 20.  Entries end at
 // the first zero; the last class (other lengths) uses the runtime plan.
-constexpr int kRadixOrders[kNumLenClasses][4][5] = {
+constexpr int kMaxVariants = 6;
+constexpr int kRadixOrders[kNumLenClasses][kMaxVariants][5] = {
     {{4, 3, 2}},                                          // 24: 2 lanes, 12 each
     {{8, 4}, {4, 8}},                                     // 32: 4 lanes, 8 each
     {{4, 4, 3}, {3, 4, 4}},                               // 48: 4 lanes, 12 each
-    {{8, 8}, {4, 4, 4}},                                  // 64: 8 lanes, 8 each; 16 lanes, 4 each
+    {{8, 8}, {4, 4, 4}, {16, 4}, {4, 16}},                // 64: 8 lanes, 8 each; 16 lanes, 4 each; 4 lanes, 16 each
     {{4, 4, 2, 3}, {2, 4, 4, 3}, {3, 4, 4, 2}},          // 96: 8 lanes, 12 each
-    {{8, 4, 4}, {4, 4, 8}, {2, 8, 8}, {4, 8, 4}},        // 128: 16 lanes, 8 each
+    {{8, 4, 4}, {4, 4, 8}, {2, 8, 8}, {4, 8, 4},         // 128: 16 lanes, 8 each
+     {16, 8}, {8, 16}},                                   //      8 lanes, 16 each (two passes)
     {{4, 4, 2, 5}, {5, 4, 4, 2}},                         // 160: 8 lanes, 20 each
     {{4, 4, 4, 5}, {5, 4, 4, 4}},                         // 320: 16 lanes, 20 each
     {},
@@ -213,7 +256,7 @@ __host__ __device__ constexpr int num_radices(int lc, int v) {
 
 __host__ __device__ constexpr int num_variants(int lc) {
     int v = 0;
-    while (v < 4 && num_radices(lc, v) > 0) ++v;
+    while (v < kMaxVariants && num_radices(lc, v) > 0) ++v;
     return v;
 }
 

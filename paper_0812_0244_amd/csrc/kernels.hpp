@@ -1103,9 +1103,13 @@ __global__ void __launch_bounds__(kThreads) k_z_main(const InstDev *insts, const
         // the matrix (20 values in registers, one per K step b) and B =
         // column i of the item's four real columns: theta_b at point i / 2
         // (+m1 or -m1) and part i % 2 (re, im); it receives in its four
-        // accumulators u_{4 rb + r} at that point and part, r = 0..3.  The
-        // lanes of a wave read theta before any of them writes u (wave-level
-        // ordering), as on the vector path.
+        // accumulators u_{4 rb + r} at that point and part, r = 0..3.  Items
+        // of a column pair (two columns sharing every shell) instead use
+        // B column i = theta_b at column i % 2 and point i / 2, both parts
+        // from one 8-byte LDS read, in two chains (real and imaginary parts:
+        // the kernel is real); the accumulators hold u_{4 rb + r} at that
+        // column and point.  The lanes of a wave read theta before any of
+        // them writes u (wave-level ordering), as on the vector path.
         typedef float v4f __attribute__((ext_vector_type(4)));
         const int g0 = wave * (64 / kNQ);
         int it = g0 + mf_g;
@@ -1125,28 +1129,33 @@ __global__ void __launch_bounds__(kThreads) k_z_main(const InstDev *insts, const
             mg += dm;
             pg += dr;
             if (pg >= P) { pg -= P; ++mg; }
-            const int pt = mf_q < 2 ? l : lq;
-            float *x0 = reinterpret_cast<float *>(buf + __mul24(w0, cstride) + pt) + (mf_q & 1);
-            float *o0 = x0 + 2 * 4 * mf_rb * lp;
             if (CP == 2) {
-                float *x1 = x0 + 2 * cstride, *o1 = o0 + 2 * cstride;
-                v4f a0 = {0.f, 0.f, 0.f, 0.f}, a1 = a0;
+                // lane column: column mf_q % 2 of the pair, point +m1 (mf_q < 2) or -m1
+                C2<T> *xc = buf + __mul24(w0 + (mf_q & 1), cstride) + (mf_q < 2 ? l : lq);
+                C2<T> *oc = xc + 4 * mf_rb * lp;
+                v4f are = {0.f, 0.f, 0.f, 0.f}, aim = are;
 #pragma unroll
                 for (int b = 0; b < kNQ; ++b) {
-                    a0 = __builtin_amdgcn_mfma_f32_4x4x1f32(f[b], x0[2 * b * lp], a0, 0, 0, 0);
-                    a1 = __builtin_amdgcn_mfma_f32_4x4x1f32(f[b], x1[2 * b * lp], a1, 0, 0, 0);
+                    const C2<T> th = xc[b * lp];
+                    are = __builtin_amdgcn_mfma_f32_4x4x1f32(f[b], th.x, are, 0, 0, 0);
+                    aim = __builtin_amdgcn_mfma_f32_4x4x1f32(f[b], th.y, aim, 0, 0, 0);
                 }
-                e += wgt * (double)(o0[0] * a0[0] + o0[2 * lp] * a0[1] + o0[4 * lp] * a0[2] + o0[6 * lp] * a0[3]);
-                e += wgt * (double)(o1[0] * a1[0] + o1[2 * lp] * a1[1] + o1[4 * lp] * a1[2] + o1[6 * lp] * a1[3]);
+                float es = 0.f;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const C2<T> own = oc[r * lp];
+                    es += own.x * are[r] + own.y * aim[r];
+                }
+                e += wgt * (double)es;
                 wave_sync();
                 if (valid) {
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        o0[2 * r * lp] = a0[r] * fin;
-                        o1[2 * r * lp] = a1[r] * fin;
-                    }
+                    for (int r = 0; r < 4; ++r) oc[r * lp] = mk<T>(are[r] * fin, aim[r] * fin);
                 }
             } else {
+                const int pt = mf_q < 2 ? l : lq;
+                float *x0 = reinterpret_cast<float *>(buf + __mul24(w0, cstride) + pt) + (mf_q & 1);
+                float *o0 = x0 + 2 * 4 * mf_rb * lp;
                 v4f a0 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int b = 0; b < kNQ; ++b) a0 = __builtin_amdgcn_mfma_f32_4x4x1f32(f[b], x0[2 * b * lp], a0, 0, 0, 0);
@@ -1345,10 +1354,15 @@ hipError_t launch_z_lc(int kind, const LaunchArgs &a) {
         case 0: return FN<T, 0, 0>(kind, a);                                                              \
         case 1: return (var) >= 1 ? FN<T, 1, 1>(kind, a) : FN<T, 1, 0>(kind, a);                          \
         case 2: return (var) >= 1 ? FN<T, 2, 1>(kind, a) : FN<T, 2, 0>(kind, a);                          \
-        case 3: return (var) >= 1 ? FN<T, 3, 1>(kind, a) : FN<T, 3, 0>(kind, a);                          \
+        case 3:                                                                                           \
+            return (var) >= 3 ? FN<T, 3, 3>(kind, a)                                                      \
+                   : (var) == 2 ? FN<T, 3, 2>(kind, a)                                                    \
+                   : (var) == 1 ? FN<T, 3, 1>(kind, a) : FN<T, 3, 0>(kind, a);                            \
         case 4: return (var) >= 2 ? FN<T, 4, 2>(kind, a) : (var) == 1 ? FN<T, 4, 1>(kind, a) : FN<T, 4, 0>(kind, a); \
         case 5:                                                                                           \
-            return (var) >= 3 ? FN<T, 5, 3>(kind, a)                                                      \
+            return (var) >= 5 ? FN<T, 5, 5>(kind, a)                                                      \
+                   : (var) == 4 ? FN<T, 5, 4>(kind, a)                                                    \
+                   : (var) == 3 ? FN<T, 5, 3>(kind, a)                                                    \
                    : (var) == 2 ? FN<T, 5, 2>(kind, a)                                                    \
                    : (var) == 1 ? FN<T, 5, 1>(kind, a) : FN<T, 5, 0>(kind, a);                            \
         case 6: return (var) >= 1 ? FN<T, 6, 1>(kind, a) : FN<T, 6, 0>(kind, a);                          \

@@ -283,13 +283,13 @@ def test_schedule_choice_arguments():
 def test_radix_orders_multiply_to_their_length():
     """Every radix order of every compile-time length class (and the runtime
     plan of other lengths) is a factorisation of the length into passes of
-    2, 3, 4, 5 and 8; the orders of a length are distinct; an order past a
-    length's last takes its last."""
-    for n, count in [(24, 1), (32, 2), (48, 2), (64, 2), (96, 3), (128, 4), (160, 2), (320, 2), (36, 1), (250, 1)]:
+    2, 3, 4, 5, 8 and 16; the orders of a length are distinct; an order past
+    a length's last takes its last."""
+    for n, count in [(24, 1), (32, 2), (48, 2), (64, 4), (96, 3), (128, 6), (160, 2), (320, 2), (36, 1), (250, 1)]:
         seen = []
-        for v in range(4):
+        for v in range(6):
             r = B.radix_order(n, v)
-            assert np.prod(r) == n and all(x in (2, 3, 4, 5, 8) for x in r), (n, v, r)
+            assert np.prod(r) == n and all(x in (2, 3, 4, 5, 8, 16) for x in r), (n, v, r)
             if v < count:
                 assert r not in seen
                 seen.append(r)
@@ -298,7 +298,8 @@ def test_radix_orders_multiply_to_their_length():
     lib = B.load_library()
     out = (ctypes.c_int32 * 8)()
     assert lib.vdwnl_radix_order(14, 0, 8, out) == E["SIZE"]
-    assert lib.vdwnl_radix_order(128, 4, 8, out) == E["ARG"]
+    assert lib.vdwnl_radix_order(128, 6, 8, out) == E["ARG"]
+    assert lib.vdwnl_radix_order(128, 4, 8, out) == 2 and list(out[:2]) == [16, 8]
     assert lib.vdwnl_radix_order(128, 0, 8, None) == E["ARG"]
     assert lib.vdwnl_radix_order(128, 2, 1, out) == 3 and out[0] == 2     # (count returned, one written)
 
@@ -310,6 +311,7 @@ def test_radix_schedule_arguments():
     for what in range(1, 6):
         assert lib.vdwnl_set_schedule(h, what, 3) == 0
         assert lib.vdwnl_get_schedule(h, what, ctypes.byref(v)) == 0 and v.value == 3
-        assert lib.vdwnl_set_schedule(h, what, 4) == E["ARG"]
+        assert lib.vdwnl_set_schedule(h, what, 5) == 0
+        assert lib.vdwnl_set_schedule(h, what, 6) == E["ARG"]
     assert lib.vdwnl_set_schedule(h, 6, 0) == E["ARG"]
     lib.vdwnl_destroy(h)

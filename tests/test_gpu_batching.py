@@ -167,7 +167,7 @@ def test_every_radix_order_against_oracle(table):
         lib.set_grids(shapes, cells, 0, prec)
         lib.set_kernel_table(table["qmesh"], table["qc"], 12, table["dk"], table["phi"], table["c_soft"])
         ns = [torch.from_numpy(d).to("cuda", dt) for d in ins]
-        for order in range(4):
+        for order in range(6):
             lib.set_radix_orders([order] * 5)
             vs = [torch.empty_like(x) for x in ns]
             E = lib.energy_potential_batched([x.data_ptr() for x in ns], [x.data_ptr() for x in vs])
