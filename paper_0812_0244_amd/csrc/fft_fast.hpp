@@ -156,15 +156,29 @@ __device__ __forceinline__ void tw_gather(C2<T> *w, const C2<T> *__restrict__ tw
     if constexpr (sizeof...(RS) > 0) tw_gather<T, L, TPL, NS * R, RS...>(w + (NS > 1 ? NB * (R - 1) : 0), tw, t);
 }
 
+// Element slots of the passes' intermediate results (between the first
+// pass's reads and the last pass's writes, which keep the line in natural
+// order) for the lengths 64 and 128: element e at e ^ ((e / 16) % 8), a
+// permutation within aligned groups of 8.  The writes of the early passes
+// go at stride R or in runs of NS < 16; the XOR moves the 16-element (128
+// byte) blocks they share onto different LDS banks.
+template <int L>
+struct PassSwizzle {
+    static constexpr bool on = (L == 64 || L == 128);
+};
+__device__ __forceinline__ int swizzle16(int e) { return e ^ ((e >> 4) & 7); }
+
 // Pass of radix R after NS points have been combined; lane t of the group
 // owns butterflies j = t + m TPL.  Reads e = j + r L/R, twiddles by
-// W_{NS R}^{r (j % NS)}, writes e = (j - j%NS) R + j%NS + r NS.  The
-// twiddles come from the lane's registers (wr, tw_gather's order) when REG,
-// else from the LDS table.
+// W_{NS R}^{r (j % NS)}, writes e = (j - j%NS) R + j%NS + r NS (at their
+// swizzled slots between passes).  The twiddles come from the lane's
+// registers (wr, tw_gather's order) when REG, else from the LDS table.
 template <typename T, int L, int S, int TPL, bool REG, int NS, int R, int... RS>
 __device__ __forceinline__ void fast_passes(C2<T> *line, int es, const C2<T> *__restrict__ tw, const C2<T> *wr,
                                             int t) {
     constexpr int NB = L / R / TPL;
+    constexpr bool SWZ_IN = PassSwizzle<L>::on && NS > 1;                 // not the first pass
+    constexpr bool SWZ_OUT = PassSwizzle<L>::on && sizeof...(RS) > 0;     // not the last pass
     C2<T> v[NB][R];
 #pragma unroll
     for (int m = 0; m < NB; ++m) {
@@ -172,7 +186,8 @@ __device__ __forceinline__ void fast_passes(C2<T> *line, int es, const C2<T> *__
         const int kk = j % NS;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            C2<T> a = line[(j + r * (L / R)) * es];
+            const int e = j + r * (L / R);
+            C2<T> a = line[(SWZ_IN ? swizzle16(e) : e) * es];
             if (NS > 1 && r > 0) {
                 C2<T> w;
                 if constexpr (REG) w = wr[m * (R - 1) + r - 1];
@@ -190,7 +205,10 @@ __device__ __forceinline__ void fast_passes(C2<T> *line, int es, const C2<T> *__
         const int j = t + m * TPL;
         const int kk = j % NS;
 #pragma unroll
-        for (int r = 0; r < R; ++r) line[((j - kk) * R + kk + r * NS) * es] = v[m][r];
+        for (int r = 0; r < R; ++r) {
+            const int e = (j - kk) * R + kk + r * NS;
+            line[(SWZ_OUT ? swizzle16(e) : e) * es] = v[m][r];
+        }
     }
     wave_sync();
     if constexpr (sizeof...(RS) > 0)
