@@ -896,11 +896,52 @@ __global__ void __launch_bounds__(kThreads) k_z_main(const InstDev *insts, const
     __syncthreads();
     const size_t plane = (size_t)N2 * N3h * kNQ;
     C2<T> *spec = reinterpret_cast<C2<T> *>(I.spec);
-    // 16-byte chunks (l, w, e): plane l, column w, chunk e of the column's 20 values
-    constexpr int kCpc = kNQ / kEpc;                          // chunks per column
     // 16-byte chunks (l, w, e): plane l, column w, chunk e of the column's 20
     // values.  Each thread keeps one chunk column (w, e) and steps through the
-    // planes; the loads of kUnroll planes are issued before their stores.
+    // planes; the loads of U planes are issued before their LDS writes (U at
+    // least the planes per lane where that is at most 12: one batch).
+    constexpr int kCpc = kNQ / kEpc;                          // chunks per column
+    auto io_batch = [&](bool in, int C, int rps, auto Uc) {
+        constexpr int U = decltype(Uc)::value;
+        const int r0 = threadIdx.x / C, c = threadIdx.x - r0 * C, w = c / kCpc, e = c - w * kCpc;
+        C2<T> *lb = buf + (w * kNQ + e * kEpc) * lp;
+        // this lane's chunk column; planes l = r0 + s rps, s = j U + u
+        char *cb = reinterpret_cast<char *>(spec + colbase[w] + e * kEpc);
+        const size_t plane_bytes = plane * sizeof(C2<T>);
+        for (int l0 = r0; l0 < N1; l0 += U * rps) {
+            T ra[U], rb[U], rc[U], rd[U];
+            if (in) {
+                // unconditional loads (a plane past N1 re-reads plane r0, valid here)
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int l = l0 + u * rps;
+                    const char *src = cb + (size_t)(uint32_t)(l < N1 ? l : r0) * plane_bytes;
+                    if constexpr (kEpc == 2) {
+                        const float4 v = gld(reinterpret_cast<const float4 *>(src))[0];
+                        ra[u] = v.x; rb[u] = v.y; rc[u] = v.z; rd[u] = v.w;
+                    } else {
+                        const C2<T> v = gld(reinterpret_cast<const C2<T> *>(src))[0];
+                        ra[u] = v.x; rb[u] = v.y;
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int l = l0 + u * rps;
+                if (l >= N1) continue;
+                char *dst = cb + (size_t)(uint32_t)l * plane_bytes;
+                if (in) {
+                    lb[l] = mk<T>(ra[u], rb[u]);
+                    if constexpr (kEpc == 2) lb[lp + l] = mk<T>(rc[u], rd[u]);
+                } else if constexpr (kEpc == 2) {
+                    const C2<T> p0 = lb[l], p1 = lb[lp + l];
+                    gst(reinterpret_cast<float4 *>(dst))[0] = make_float4(p0.x, p0.y, p1.x, p1.y);
+                } else {
+                    gst(reinterpret_cast<C2<T> *>(dst))[0] = lb[l];
+                }
+            }
+        }
+    };
     auto io = [&](bool in) {
         const int C = K * kCpc;                               // chunks per plane
         if (C > kThreads) {                                   // (only tiny N1 with many columns)
@@ -919,48 +960,10 @@ __global__ void __launch_bounds__(kThreads) k_z_main(const InstDev *insts, const
         }
         const int rps = kThreads / C;                         // planes per step
         if ((int)threadIdx.x >= rps * C) return;
-        const int r0 = threadIdx.x / C, c = threadIdx.x - r0 * C, w = c / kCpc, e = c - w * kCpc;
-        C2<T> *lb = buf + (w * kNQ + e * kEpc) * lp;
-        // this lane's chunk column; planes l = r0 + s rps, s = j kUnroll + u
-        char *cb = reinterpret_cast<char *>(spec + colbase[w] + e * kEpc);
-        const size_t plane_bytes = plane * sizeof(C2<T>);
-        for (int l0 = r0; l0 < N1; l0 += kUnroll * rps) {
-            T ra[kUnroll], rb[kUnroll], rc[kUnroll], rd[kUnroll];
-            if (in) {
-                // unconditional loads (a plane past N1 re-reads plane r0, valid here)
-#pragma unroll
-                for (int u = 0; u < kUnroll; ++u) {
-                    const int l = l0 + u * rps;
-                    const char *src = cb + (size_t)(uint32_t)(l < N1 ? l : r0) * plane_bytes;
-                    if constexpr (kEpc == 2) {
-                        const float4 v = gld(reinterpret_cast<const float4 *>(src))[0];
-                        ra[u] = v.x; rb[u] = v.y; rc[u] = v.z; rd[u] = v.w;
-                    } else {
-                        const C2<T> v = gld(reinterpret_cast<const C2<T> *>(src))[0];
-                        ra[u] = v.x; rb[u] = v.y;
-                    }
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
-                const int l = l0 + u * rps;
-                if (l >= N1) continue;
-                char *dst = cb + (size_t)(uint32_t)l * plane_bytes;
-                if (in) {
-                    lb[l] = mk<T>(ra[u], rb[u]);
-                    if constexpr (kEpc == 2) lb[lp + l] = mk<T>(rc[u], rd[u]);
-                } else if constexpr (kEpc == 2) {
-                    const C2<T> p0 = lb[l], p1 = lb[lp + l];
-                    gst(reinterpret_cast<float4 *>(dst))[0] = make_float4(p0.x, p0.y, p1.x, p1.y);
-                } else {
-                    gst(reinterpret_cast<C2<T> *>(dst))[0] = lb[l];
-                }
-            }
-        }
+        const int steps = (N1 + rps - 1) / rps;               // planes per lane
+        if (steps > kUnroll && steps <= 12) io_batch(in, C, rps, std::integral_constant<int, 12>{});
+        else io_batch(in, C, rps, std::integral_constant<int, kUnroll>{});
     };
-    io(true);
-    load_twiddles<T>(twall, I.p1, reinterpret_cast<const C2<T> *>(twv));
-
     const T *tab = reinterpret_cast<const T *>(I.shelltab);
     // orthorhombic cell: item = |m1| P + pair, the +-m1 points share a shell;
     // general cell: item = k1 P + pair over the whole axis, a shell each
@@ -972,15 +975,20 @@ __global__ void __launch_bounds__(kThreads) k_z_main(const InstDev *insts, const
     const bool lane_on = grp < 64 / kNQ;
     const int gid = wave * (64 / kNQ) + grp;
     const int nitems = (general ? N1 : N1 / 2 + 1) * P;
-    // shell of every item, into LDS (the loads overlap the forward FFT)
-    {
-        const gptr<const int> smap = gld(I.shellmap + (size_t)m2 * N3h + k30);
-        const size_t smap_m1 = (size_t)(general ? N2 : I.h2) * N3h;
-        for (int i = threadIdx.x; i < nitems; i += kThreads) {
-            const int m1 = i / P;
-            sidx[i] = smap[m1 * smap_m1 + (i - m1 * P)];
-        }
-    }
+    // shell of every item, into LDS; the thread's first item is loaded
+    // before the tile (unconditionally, index clamped), so that its latency
+    // overlaps the tile's loads
+    const gptr<const int> smap = gld(I.shellmap + (size_t)m2 * N3h + k30);
+    const size_t smap_m1 = (size_t)(general ? N2 : I.h2) * N3h;
+    auto smap_at = [&](int i) {
+        const int m1 = i / P;
+        return smap[m1 * smap_m1 + (i - m1 * P)];
+    };
+    const int sh_first = smap_at(min((int)threadIdx.x, nitems - 1));
+    io(true);
+    load_twiddles<T>(twall, I.p1, reinterpret_cast<const C2<T> *>(twv));
+    if ((int)threadIdx.x < nitems) sidx[threadIdx.x] = sh_first;
+    for (int i = threadIdx.x + kThreads; i < nitems; i += kThreads) sidx[i] = smap_at(i);
     // (packed rows: entry (r, q), r <= q, at r kNQ - r (r - 1)/2 + q - r)
     int poff[GEN ? kNQ : 1];
     if constexpr (GEN) {
@@ -1026,12 +1034,11 @@ __global__ void __launch_bounds__(kThreads) k_z_main(const InstDev *insts, const
         }
     };
     __syncthreads();
+    // kernel rows in flight: one item (vector ALU) or round (matrix cores)
+    // ahead, the first before the forward FFT
     T fa[kNQ], fb[kNQ];
-    if constexpr (MF) {
-        if (PROBE != 1) fetch(wave * (64 / kNQ) + mf_g, fa);
-    } else {
-        if (PROBE != 1 && lane_on) fetch(gid, fa);
-    }
+    const int it0 = MF ? wave * (64 / kNQ) + mf_g : gid;
+    if (PROBE != 1 && (MF || lane_on)) fetch(it0, fa);
     fft_lc<T, -1, LC, V>(buf, I.p1, W, 1, lp, twall);
     if constexpr (PROBE == 1) {
         const T inv_n = (T)I.inv_n;
@@ -1133,19 +1140,23 @@ __global__ void __launch_bounds__(kThreads) k_z_main(const InstDev *insts, const
                 // lane column: column mf_q % 2 of the pair, point +m1 (mf_q < 2) or -m1
                 C2<T> *xc = buf + __mul24(w0 + (mf_q & 1), cstride) + (mf_q < 2 ? l : lq);
                 C2<T> *oc = xc + 4 * mf_rb * lp;
+                // every LDS read of the round before the first product (one
+                // wait instead of one per K step)
+                C2<T> th[kNQ], own[4];
+#pragma unroll
+                for (int b = 0; b < kNQ; ++b) th[b] = xc[b * lp];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) own[r] = oc[r * lp];
+                __builtin_amdgcn_sched_barrier(0);
                 v4f are = {0.f, 0.f, 0.f, 0.f}, aim = are;
 #pragma unroll
                 for (int b = 0; b < kNQ; ++b) {
-                    const C2<T> th = xc[b * lp];
-                    are = __builtin_amdgcn_mfma_f32_4x4x1f32(f[b], th.x, are, 0, 0, 0);
-                    aim = __builtin_amdgcn_mfma_f32_4x4x1f32(f[b], th.y, aim, 0, 0, 0);
+                    are = __builtin_amdgcn_mfma_f32_4x4x1f32(f[b], th[b].x, are, 0, 0, 0);
+                    aim = __builtin_amdgcn_mfma_f32_4x4x1f32(f[b], th[b].y, aim, 0, 0, 0);
                 }
                 float es = 0.f;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const C2<T> own = oc[r * lp];
-                    es += own.x * are[r] + own.y * aim[r];
-                }
+                for (int r = 0; r < 4; ++r) es += own[r].x * are[r] + own[r].y * aim[r];
                 e += wgt * (double)es;
                 wave_sync();
                 if (valid) {
