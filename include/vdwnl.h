@@ -43,7 +43,8 @@ enum {
     VDWNL_E_KRANGE = -5,            /* radial table does not reach max |G| of a grid */
     VDWNL_E_STATE = -6,             /* grid or table missing, or no device */
     VDWNL_E_HIP = -7,               /* a HIP runtime call failed */
-    VDWNL_E_BAD_DENSITY = -8        /* reserved */
+    VDWNL_E_BAD_DENSITY = -8        /* a density value is negative, NaN or infinite (the method
+                                       is defined for n >= 0); E and v of that grid are not valid */
 };
 
 typedef struct vdwnl_ctx vdwnl_ctx;
@@ -128,7 +129,13 @@ int vdwnl_set_kernel_table(vdwnl_ctx *ctx, int32_t nq, const double *qmesh, doub
  *   E_out   host double[2]: E_k (the FFT part, Eq. Eoffk) and Delta E (the
  *           local correction, Eq. DEnl); E_c^nl = E_out[0] + E_out[1]
  *   stream  hipStream_t to run on (0: the null stream); the call returns
- *           after the stream has finished the evaluation. */
+ *           after the stream has finished the evaluation.
+ * The theta pass checks every density value as it reads it (no extra pass):
+ * a negative, NaN or infinite value makes both energies NaN and the call
+ * return VDWNL_E_BAD_DENSITY (v is then not valid either); the next
+ * evaluation starts clean.  The batched calls do the same per grid (the
+ * other grids' results stay valid; the asynchronous call reports it only
+ * through the NaN energies in E_dev). */
 int vdwnl_energy_potential(vdwnl_ctx *ctx, const void *n_dev, void *v_dev, double *E_out,
                            void *stream);
 
@@ -155,7 +162,8 @@ int vdwnl_energy_potential(vdwnl_ctx *ctx, const void *n_dev, void *v_dev, doubl
  * VDWNL_E_STATE after this call).  Errors: VDWNL_E_ARG (null pointer),
  * VDWNL_E_STATE (no grid or table, a batch plan, a host-only context,
  * per-pass timing on), VDWNL_E_UNSUPPORTED_SIZE (the plan exceeds the
- * buffer), VDWNL_E_KRANGE, VDWNL_E_HIP. */
+ * buffer), VDWNL_E_KRANGE, VDWNL_E_HIP, VDWNL_E_BAD_DENSITY (as
+ * vdwnl_energy_potential). */
 int vdwnl_energy_potential_noalloc(vdwnl_ctx *ctx, const void *n_dev, void *v_dev, double *E_out,
                                    void *stream);
 

@@ -154,7 +154,7 @@ struct Grid {
     int k3main, k3aux;       // k3 per fused axis-1 tile (20 comps), per grad/div tile
     int wy20, wy3, wy1;      // axis-2 tile widths
     int shell_key;           // index into Ctx::shells
-    size_t off_grad, off_vloc, off_spec, off_spec3, off_spec1, off_map, off_tab, off_ek, off_de, off_sl;
+    size_t off_grad, off_vloc, off_spec, off_spec3, off_spec1, off_map, off_tab, off_ek, off_de, off_sl, off_bad;
     int n_ek, n_de;
     size_t npts() const { return (size_t)s[0] * s[1] * s[2]; }
     size_t nhalf() const { return (size_t)s[0] * s[1] * (s[2] / 2 + 1); }
@@ -275,6 +275,16 @@ static int fail(vdwnl_ctx *c, int code, const std::string &msg) {
 }
 
 static int check_krange(vdwnl_ctx *c);
+
+// The theta pass flags a grid whose density holds a negative, NaN or
+// infinite value; the reduction then makes all its energies NaN.
+static int check_density_flags(vdwnl_ctx *c, const double *E4, int nb) {
+    for (int i = 0; i < nb; ++i)
+        if (E4[4 * i] != E4[4 * i])
+            return fail(c, VDWNL_E_BAD_DENSITY,
+                        "grid " + std::to_string(i) + ": a density value is negative, NaN or infinite");
+    return VDWNL_OK;
+}
 static void refresh_image(vdwnl_ctx *c);
 
 static int hipfail(vdwnl_ctx *c, hipError_t e, const char *what) {
@@ -808,6 +818,7 @@ static int build_image(vdwnl_ctx *c, Image &im, bool keep_tables) {
         g.off_ek = off; off = align_up(off + g.n_ek * sizeof(double));
         g.off_de = off; off = align_up(off + g.n_de * sizeof(double));
         g.off_sl = off; off = align_up(off + 2 * g.n_de * sizeof(double));
+        g.off_bad = off; off = align_up(off + sizeof(int));
     }
     // LDS of one tile of each pass for grid g
     auto lds_of = [&](int k, const Grid &g) -> size_t {
@@ -1057,6 +1068,7 @@ static void fill_insts(vdwnl_ctx *c, char *w, InstDev *out) {
         I.shelltab = w + c->tab_off[g.shell_key];
         I.part_ek = (double *)(w + g.off_ek); I.part_de = (double *)(w + g.off_de);
         I.part_sl = (double *)(w + g.off_sl);
+        I.bad = (int *)(w + g.off_bad);
         I.n_ek = g.n_ek; I.n_de = g.n_de;
     }
 }
@@ -1262,7 +1274,7 @@ static int run(vdwnl_ctx *c, int nb, const void *const *n_ptrs, void *const *v_p
         }
         c->timed_calls++;
     }
-    return VDWNL_OK;
+    return check_density_flags(c, c->h_E, nb);
 }
 
 // Parity probe of one stage of grid `target`: the passes of the last
@@ -1405,7 +1417,7 @@ static int run_noalloc(vdwnl_ctx *c, const void *n_dev, void *v_dev, double *E_o
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return hipfail(c, e, "stream synchronize");
     E_out[0] = c->na_E[0];
     E_out[1] = c->na_E[1];
-    return VDWNL_OK;
+    return check_density_flags(c, c->na_E.data(), 1);
 }
 
 // Logarithmic q mesh of the interpolation: q_1 = q1, q_nq = q_c, increments
@@ -1439,7 +1451,7 @@ const char *vdwnl_strerror(int code) {
         case VDWNL_E_KRANGE: return "kernel table does not cover the grid's wave vectors";
         case VDWNL_E_STATE: return "grid or kernel table missing, or no device";
         case VDWNL_E_HIP: return "HIP runtime error";
-        case VDWNL_E_BAD_DENSITY: return "invalid density";
+        case VDWNL_E_BAD_DENSITY: return "invalid density (negative, NaN or infinite)";
         default: return "unknown error";
     }
 }

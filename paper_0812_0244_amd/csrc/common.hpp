@@ -60,6 +60,7 @@ struct InstDev {
     double *part_ek;         // one partial per fused axis-1 tile
     double *part_de;         // one partial per theta tile
     double *part_sl;         // two per theta tile: E_x and E_c^LDA partials
+    int *bad;                // set when a density value is negative, NaN or infinite
     int n_ek, n_de;
     int semilocal;           // add the semilocal terms of Eq. (Exc) (per call)
     const void *n;           // per call

@@ -176,6 +176,13 @@ struct LocalQ {
     }
 };
 
+// Largest finite value of T.
+template <typename T>
+__device__ __forceinline__ constexpr T finite_max() {
+    if constexpr (sizeof(T) == 4) return __FLT_MAX__;
+    else return __DBL_MAX__;
+}
+
 // The semilocal terms of Eq. (Exc) at one point, from n, sigma = |grad n|^2
 // and the k_F, eps_c (and d eps_c/dn) of LocalQ.  Exchange: the revPBE GGA,
 // e_x = e_u F_x(s) with e_u = -3 k_F n / (4 pi), s^2 = sigma / (4 k_F^2 n^2),
@@ -275,6 +282,8 @@ __global__ void __launch_bounds__(kThreads) k_x_nfwd(const InstDev *insts, const
     const Tile t = tiles[blockIdx.x];
     const InstDev &I = insts[t.inst];
     const int N3 = axis_len<LC>(I.n3), N3h = N3 / 2 + 1, row0 = t.a, B = t.b, np = B / 2, ls = N3 + 1;
+    // (the grid's first pass: clear its bad-density flag before the theta pass)
+    if (row0 == 0 && threadIdx.x == 0) gst(I.bad)[0] = 0;
     double2 *tw = reinterpret_cast<double2 *>(smem);
     double2 *buf = tw + N3;
     const T *n = reinterpret_cast<const T *>(I.n) + (size_t)row0 * N3;
@@ -386,6 +395,9 @@ __global__ void __launch_bounds__(kThreads) k_x_theta(const InstDev *insts, cons
         const C2<T> g01 = mk<T>(first ? gx_f : gin[idx], first ? gy_f : gin[N + idx]);
         const C2<T> g2 = mk<T>(first ? gz_f : gin[2 * N + idx], (T)0);
         T *th = reinterpret_cast<T *>(r2 + (size_t)(kNQ / 2 * rb) * ls);   // pair line m at th + 2 m ls
+        // a density the method is not defined for (negative, NaN, infinite):
+        // flag the grid (its energies come out NaN, the call reports it)
+        if (!(nv >= (T)0 && nv <= finite_max<T>())) gst(I.bad)[0] = 1;
         if (nv >= (T)c_nmin) {
             LocalQ<T, false> lq;
             const T sigma = g01.x * g01.x + g01.y * g01.y + g2.x * g2.x;
@@ -701,6 +713,8 @@ template <typename T>
 __global__ void __launch_bounds__(kThreads) k_fd_grad(const InstDev *insts, const Tile *tiles) {
     const Tile t = tiles[blockIdx.x];
     const InstDev &I = insts[t.inst];
+    // (the grid's first pass: clear its bad-density flag before the theta pass)
+    if (t.a == 0 && threadIdx.x == 0) gst(I.bad)[0] = 0;
     switch (I.fdm) {
         case 1: fd_grad_tile<T, 1>(I, t.a, t.b); break;
         case 2: fd_grad_tile<T, 2>(I, t.a, t.b); break;

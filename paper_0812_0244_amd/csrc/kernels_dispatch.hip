@@ -23,10 +23,13 @@ __global__ void __launch_bounds__(kThreads) k_reduce(const InstDev *insts, doubl
     x = block_sum(x);
     c = block_sum(c);
     if (threadIdx.x == 0) {
-        E[4 * blockIdx.x] = 0.5 * I.omega * a;
-        E[4 * blockIdx.x + 1] = I.dvol * b;
-        E[4 * blockIdx.x + 2] = I.dvol * x;
-        E[4 * blockIdx.x + 3] = I.dvol * c;
+        // a density the theta pass flagged: every energy of the grid NaN
+        const double nan = __builtin_nan("");
+        const bool bad = gld(I.bad)[0] != 0;
+        E[4 * blockIdx.x] = bad ? nan : 0.5 * I.omega * a;
+        E[4 * blockIdx.x + 1] = bad ? nan : I.dvol * b;
+        E[4 * blockIdx.x + 2] = bad ? nan : I.dvol * x;
+        E[4 * blockIdx.x + 3] = bad ? nan : I.dvol * c;
     }
 }
 

@@ -40,6 +40,7 @@ def test_error_codes_match_header():
     lib = B.load_library()
     assert lib.vdwnl_strerror(0) == b"ok"
     assert lib.vdwnl_strerror(-2) == b"unsupported grid size"
+    assert lib.vdwnl_strerror(-8) == b"invalid density (negative, NaN or infinite)"
 
 
 def _host_ctx():
