@@ -557,7 +557,7 @@ static bool tuned_lookup(const std::string &key, size_t *pref, int *contraction,
             if (ft->second[i] < 4096 || ft->second[i] > cap) return false;   // (not a budget this device accepts)
         if (ft->second[TG_COUNT] > 1) return false;
         for (int i = 0; i < TG_COUNT; ++i)
-            if (ft->second[TG_COUNT + 1 + i] > 3) return false;
+            if (ft->second[TG_COUNT + 1 + i] >= (size_t)kMaxVariants) return false;
         it = g_tuned.insert(*ft).first;
     }
     for (int i = 0; i < TG_COUNT; ++i) pref[i] = it->second[i];
