@@ -32,26 +32,22 @@ ALG_BYTES_PER_POINT = {32: (4 * 20 + 28) * 4, 64: (4 * 20 + 28) * 8}
 def pass_bytes(name, shapes, s):
     """Algorithmic bytes one launch of a pass moves over all grids: what it
     must read and write given its inputs and outputs (spectra as N1 N2
-    (N3/2+1) complex values; the gradient chain's spectra are FP64, the
-    divergence chain's in the working precision)."""
+    (N3/2+1) complex values; reals in the working precision; orthorhombic
+    cells)."""
     tot = 0
     for (n1, n2, n3) in shapes:
         N = n1 * n2 * n3
         NH = n1 * n2 * (n3 // 2 + 1)
-        c, d = 2 * s, 16
+        c = 2 * s
         b = {
-            "x_nfwd": N * s + NH * d,
-            "y_1f": 2 * NH * d, "y_1i": 2 * NH * c,
-            "z_grad": 4 * NH * d, "z_div": 4 * NH * c,
-            "y_3i": 6 * NH * d, "y_3f": 6 * NH * c,
-            "x_grad": 3 * NH * d + 3 * N * s,
+            # spectral gradient and divergence, one pass per axis
+            "x_deriv": 2 * N * s, "y_deriv": 2 * N * s, "z_deriv": 2 * N * s,
+            "x_div": 3 * N * s, "y_div": 3 * N * s, "z_div": 3 * N * s,
             "x_theta": 4 * N * s + 20 * NH * c,
             "y_20f": 40 * NH * c, "z_main": 40 * NH * c, "y_20i": 40 * NH * c,
-            "x_assemble": 20 * NH * c + 5 * N * s + 3 * NH * c,
-            "x_final": NH * c + 2 * N * s,
+            "x_assemble": 20 * NH * c + 8 * N * s,
             # finite-difference gradient mode
             "fd_grad": 4 * N * s,
-            "x_assemble_fd": 20 * NH * c + 8 * N * s,
             "fd_div": 5 * N * s,
             "reduce": 0,
         }[name]

@@ -215,12 +215,12 @@ int vdwnl_set_functional(vdwnl_ctx *ctx, int32_t functional);
 int vdwnl_semilocal_energies(const vdwnl_ctx *ctx, int32_t nb, double *E_out);
 
 /* Copy an internal per-grid field of the last evaluation of grid `inst` to
- * the device buffer dst (for parity probes): which = 0: grad n [3][N] with
- * the spectral gradient; with finite differences the same buffer holds, after
- * an evaluation, the components q_c = sum_x W[c][x] w_x (W[c][x] =
- * N_c b_c,x / (2 pi), N_c / L_c on the diagonal of an orthorhombic cell) of
- * the vector field w = sum_a u_a dtheta_a/dgrad n + de/dgrad n of Eq. (Vi)
- * (grad n is overwritten in place); 1: v_loc [N] (the local
+ * the device buffer dst (for parity probes): which = 0: the components
+ * q_c = sum_x W[c][x] w_x (W[c][x] = N_c b_c,x / (2 pi), N_c / L_c on the
+ * diagonal of an orthorhombic cell) of the vector field
+ * w = sum_a u_a dtheta_a/dgrad n + de/dgrad n of Eq. (Vi), [3][N] (they
+ * overwrite grad n in place; grad n itself: vdwnl_debug_stage with
+ * VDWNL_STAGE_GRAD); 1: v_loc [N] (the local
  * part of v, before the gradient term; with the whole functional it includes
  * the semilocal terms' local parts).  Arrays in the planned precision. */
 int vdwnl_debug_field(vdwnl_ctx *ctx, int32_t inst, int32_t which, void *dst, void *stream);
@@ -245,11 +245,14 @@ int vdwnl_debug_field(vdwnl_ctx *ctx, int32_t inst, int32_t which, void *dst, vo
  *   VDWNL_STAGE_U        u_a(r_i) = sum_G u_a(G) exp(i G . r_i)
  *                        (Eq. (epsilon): u_ai = dOmega^-1 dE_k/dtheta_ai);
  *                        real [20][N1][N2][N3]
+ *   VDWNL_STAGE_GRAD     grad n as the theta pass takes it (the gradient of
+ *                        q0's argument, Eq. (q0)), Cartesian components;
+ *                        real [3][N1][N2][N3]
  * Returns after the stream has finished.  The workspace is left as the probe
  * left it; the next evaluation recomputes everything.  VDWNL_E_ARG for a null
  * pointer or an unknown stage; VDWNL_E_STATE before the first evaluation of
  * the plan or for an index outside the batch. */
-enum { VDWNL_STAGE_THETA = 0, VDWNL_STAGE_THETA_K = 1, VDWNL_STAGE_U_K = 2, VDWNL_STAGE_U = 3 };
+enum { VDWNL_STAGE_THETA = 0, VDWNL_STAGE_THETA_K = 1, VDWNL_STAGE_U_K = 2, VDWNL_STAGE_U = 3, VDWNL_STAGE_GRAD = 4 };
 int vdwnl_debug_stage(vdwnl_ctx *ctx, int32_t inst, int32_t stage, void *dst, void *stream);
 
 /* The logarithmic mesh of interpolation points of the factorisation (the

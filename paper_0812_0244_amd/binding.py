@@ -104,7 +104,7 @@ def load_library(path: str = LIB_PATH):
     return _lib
 
 
-STAGE_THETA, STAGE_THETA_K, STAGE_U_K, STAGE_U = 0, 1, 2, 3
+STAGE_THETA, STAGE_THETA_K, STAGE_U_K, STAGE_U, STAGE_GRAD = 0, 1, 2, 3, 4
 
 
 def log_qmesh(nq: int = 20, q1: float = 0.05, qc: float = 5.0, lam: float = 1.17):
@@ -312,7 +312,7 @@ class VdwNl:
         self._check(self.lib.vdwnl_debug_field(self.h, inst, which, _vp(dst_ptr), _vp(stream)), "debug_field")
 
     def debug_stage(self, inst: int, stage: int, dst_ptr: int, stream: int = 0):
-        """One stage (STAGE_THETA, STAGE_THETA_K, STAGE_U_K, STAGE_U) of grid
+        """One stage (STAGE_THETA, STAGE_THETA_K, STAGE_U_K, STAGE_U, STAGE_GRAD) of grid
         inst, recomputed from the last evaluation's density, into dst."""
         self._check(self.lib.vdwnl_debug_stage(self.h, inst, stage, _vp(dst_ptr), _vp(stream)), "debug_stage")
 

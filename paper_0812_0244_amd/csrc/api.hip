@@ -129,14 +129,14 @@ constexpr int kDefaultContraction = VDWNL_CONTRACTION_MATRIX;
 enum TileGroup { TG_X = 0, TG_Y20, TG_YAUX, TG_Z, TG_ZAUX, TG_COUNT };
 
 // The pass group whose radix order a pass takes: every axis-3 transform, the
-// axis-2 transforms of the 20 spectra, the other axis-2 transforms, the fused
-// axis-1 pass, the other axis-1 passes.
+// axis-2 transforms of the 20 spectra, the other axis-2 transforms (the
+// gradient and divergence), the fused axis-1 pass, the other axis-1 passes.
 static int variant_group(int kind) {
     switch (kind) {
         case KY_20F: case KY_20I: return TG_Y20;
-        case KY_1F: case KY_3I: case KY_3F: case KY_1I: return TG_YAUX;
+        case KG_Y: case KD_Y: return TG_YAUX;
         case KZ_MAIN: return TG_Z;
-        case KZ_GRAD: case KZ_DIV: return TG_ZAUX;
+        case KG_Z: case KD_Z: return TG_ZAUX;
         default: return TG_X;
     }
 }
@@ -149,12 +149,12 @@ struct Grid {
     double cell[3];          // |a_c| (the orthorhombic lengths when !general)
     FftPlan p1, p2, p3;
     int bmain;               // rows per theta / assemble tile
-    int bnf;                 // rows per n-forward / final tile (even)
-    int bgr;                 // rows per grad n C2R tile (even)
-    int k3main, k3aux;       // k3 per fused axis-1 tile (20 comps), per grad/div tile
-    int wy20, wy3, wy1;      // axis-2 tile widths
+    int bnf;                 // rows per axis-3 derivative tile (and stencil tile; even)
+    int k3main;              // k3 per fused axis-1 tile (20 comps)
+    int wy20;                // axis-2 tile width of the 20 spectra
+    int wdy, wdz;            // i3 per axis-2 / axis-1 derivative tile
     int shell_key;           // index into Ctx::shells
-    size_t off_grad, off_vloc, off_spec, off_spec3, off_spec1, off_map, off_tab, off_ek, off_de, off_sl, off_bad;
+    size_t off_grad, off_vloc, off_spec, off_map, off_tab, off_ek, off_de, off_sl, off_bad;
     int n_ek, n_de;
     size_t npts() const { return (size_t)s[0] * s[1] * s[2]; }
     size_t nhalf() const { return (size_t)s[0] * s[1] * (s[2] / 2 + 1); }
@@ -344,18 +344,18 @@ static bool smooth235(int n) {
 }
 
 // LDS of one theta / assembly tile of b rows: the 20 fields' pair lines,
-// twiddles and method constants; the spectral assembly pass also holds two
-// lines per row of w (XL_ASSEMBLE).
-enum XLayout { XL_PLAIN = 0, XL_ASSEMBLE };
-static size_t xpass_lds(int layout, size_t b, size_t N3, size_t rs) {
+// twiddles and method constants.
+static size_t xpass_lds(size_t b, size_t N3, size_t rs) {
     const size_t cs = 2 * rs;
-    const size_t base = b * (N3 + 1) * (kNQ / 2) * cs + N3 * cs + (kNQ + kNQ * kNQ) * rs + (kMaxMc + 1) * 8;
-    return layout == XL_ASSEMBLE ? base + b * (N3 + 1) * 2 * cs : base;
+    return b * (N3 + 1) * (kNQ / 2) * cs + N3 * cs + (kNQ + kNQ * kNQ) * rs + (kMaxMc + 1) * 8;
 }
 
-// LDS of one grad n C2R tile of b rows (even): 3 FP64 lines per row pair and
-// FP64 twiddles.
-static size_t xgrad_lds(size_t b, size_t N3) { return (N3 + 3 * (b / 2) * (N3 + 1)) * 16; }
+// LDS of one derivative tile of a one-axis pass: twiddles and np lines of
+// length L, complex elements of ce bytes (16: the gradient's FP64, or the
+// working precision's for the divergence); lines at pitch L | 1 along axes
+// 2 and 1, at pitch N3 + 1 along axis 3 (the rows).
+static size_t deriv_lds(size_t L, size_t np, size_t ce) { return (L + np * (L | 1)) * ce; }
+static size_t drow_lds(size_t N3, size_t np, size_t ce) { return (N3 + np * (N3 + 1)) * ce; }
 
 // lattice: 9 values, rows a_1, a_2, a_3 (bohr)
 static int check_grid(vdwnl_ctx *c, const int32_t *shape, const double *lattice, int precision, Grid &g) {
@@ -397,13 +397,12 @@ static int check_grid(vdwnl_ctx *c, const int32_t *shape, const double *lattice,
         return fail(c, VDWNL_E_UNSUPPORTED_SIZE, "more than 715827882 grid points");
     // LDS of each pass as a function of its tile size (twiddles staged in LDS too)
     auto zmain = [&](size_t k3) { return (N1 + kNQ * k3 * (N1 | 1)) * cs + 16 + (N1 / 2 + 1) * k3 * sizeof(int); };
-    auto zaux = [&](size_t k3) { return (N1 + 4 * k3 * (N1 | 1)) * 16; };
-    auto xmain = [&](size_t b) { return xpass_lds(XL_ASSEMBLE, b, N3, rs); };   // the larger layout
+    auto xmain = [&](size_t b) { return xpass_lds(b, N3, rs); };
     auto ypass = [&](size_t w, size_t c2) { return (N2 + (N2 | 1) * w) * c2; };
     const size_t cap = c->lds_cap;
-    if (N1 > (size_t)kMaxN1 || zmain(1) > cap)
+    if (N1 > (size_t)kMaxN1 || zmain(1) > cap || deriv_lds(N1, 1, 16) > cap)
         return fail(c, VDWNL_E_UNSUPPORTED_SIZE, "N1 too large for the fused axis-1 pass");
-    if (N2 > (size_t)kTileCap || ypass(1, cs) > cap || ypass(1, 16) > cap)
+    if (N2 > (size_t)kTileCap || ypass(1, cs) > cap || deriv_lds(N2, 1, 16) > cap)
         return fail(c, VDWNL_E_UNSUPPORTED_SIZE, "N2 too large");
     if ((size_t)kNQ / 2 * N3 > (size_t)kTileCap || xmain(1) > cap)
         return fail(c, VDWNL_E_UNSUPPORTED_SIZE, "N3 too large for the axis-3 pass");
@@ -418,40 +417,39 @@ static void size_tiles(const vdwnl_ctx *c, Grid &g) {
     const size_t cs = c->precision == 64 ? 16 : 8, rs = c->precision == 64 ? 8 : 4;
     const size_t N1 = g.s[0], N2 = g.s[1], N3 = g.s[2];
     auto zmain = [&](size_t k3) { return (N1 + kNQ * k3 * (N1 | 1)) * cs + 16 + (N1 / 2 + 1) * k3 * sizeof(int); };
-    auto zaux = [&](size_t k3) { return (N1 + 4 * k3 * (N1 | 1)) * 16; };
-    auto xmain = [&](size_t b) { return xpass_lds(c->grad_mode ? XL_PLAIN : XL_ASSEMBLE, b, N3, rs); };
+    auto xmain = [&](size_t b) { return xpass_lds(b, N3, rs); };
     auto ypass = [&](size_t w, size_t c2) { return (N2 + (N2 | 1) * w) * c2; };
     // complex elements per LDS FFT tile: bounded for the runtime-radix FFT
     // (its per-thread register arrays), not for the compile-time plans
     auto cap = [](size_t n) { return len_class((int)n) == kLenGeneric ? (size_t)kTileCap : (size_t)1 << 30; };
     // axis-3 tiles of the theta / assembly passes: at most one grid point
     // per thread (two measured slower: the local chain needs the VGPRs);
-    // of the n-forward / final passes (FP64, one line per row pair): about
-    // 4096 points, enough lines to occupy every lane
+    // of the derivative passes (FP64 lines, one per row pair): about 4096
+    // points, enough lines to occupy every lane
     g.bmain = 1;
     while ((size_t)(g.bmain + 1) * N3 <= (size_t)kThreads && (kNQ / 2) * (g.bmain + 1) * N3 <= cap(N3) &&
            xmain(g.bmain + 1) <= c->pref[TG_X])
         ++g.bmain;
     g.bnf = 2;
     while ((size_t)(g.bnf + 2) * N3 <= 4096 && (size_t)(g.bnf / 2 + 1) * N3 <= cap(N3) &&
-           (N3 + (size_t)(g.bnf / 2 + 1) * (N3 + 1)) * 16 <= kLdsCap)
+           drow_lds(N3, g.bnf / 2 + 1, 16) <= kLdsCap)
         g.bnf += 2;
-    // grad n C2R tiles: up to 4096 points in at most 32 KB of FP64 lines
-    g.bgr = 2;
-    while ((size_t)(g.bgr + 2) * N3 <= 4096 && (size_t)3 * (g.bgr / 2 + 1) * N3 <= cap(N3) &&
-           xgrad_lds(g.bgr + 2, N3) <= 32768)
-        g.bgr += 2;
     g.k3main = 1;
     while (g.k3main < kMaxCols && (size_t)kNQ * (g.k3main + 1) * N1 <= cap(N1) && zmain(g.k3main + 1) <= c->pref[TG_Z])
         ++g.k3main;
-    g.k3aux = 1;
-    while (3 * (size_t)(g.k3aux + 1) * N1 <= cap(N1) && zaux(g.k3aux + 1) <= c->pref[TG_ZAUX]) ++g.k3aux;
     g.wy20 = 1;
     while ((size_t)(g.wy20 + 1) * N2 <= cap(N2) && ypass(g.wy20 + 1, cs) <= c->pref[TG_Y20]) ++g.wy20;
     if (g.wy20 > 1) g.wy20 &= ~1;   // even widths: 16-byte aligned FP32 rows
-    g.wy3 = 1;
-    while ((size_t)(g.wy3 + 1) * N2 <= cap(N2) && ypass(g.wy3 + 1, 16) <= c->pref[TG_YAUX]) ++g.wy3;
-    g.wy1 = g.wy3;
+    // derivative tiles along axes 2 and 1: i3 columns in pairs (one FP64
+    // line each), within the group's budget
+    auto dwidth = [&](size_t L, size_t budget) {
+        int w = 2;
+        while ((size_t)(w + 2) <= N3 && (size_t)(w / 2 + 1) * L <= cap(L) && deriv_lds(L, w / 2 + 1, 16) <= budget)
+            w += 2;
+        return std::min<int>(w, (int)N3);
+    };
+    g.wdy = dwidth(N2, c->pref[TG_YAUX]);
+    g.wdz = dwidth(N1, c->pref[TG_ZAUX]);
 }
 
 // Tuned LDS budgets, keyed by the device architecture, LDS size, precision,
@@ -666,13 +664,14 @@ static int check_krange(vdwnl_ctx *c) {
 }
 
 // Launch order of the passes of one evaluation (the final reduction follows):
-// spectral gradient (fourteen passes) or finite differences (seven).
-static const int kOrderSpectral[] = {KX_NFWD, KY_1F, KZ_GRAD, KY_3I, KX_GRAD, KX_THETA, KY_20F,
-                                     KZ_MAIN, KY_20I, KX_ASSEMBLE, KY_3F, KZ_DIV, KY_1I, KX_FINAL};
-static const int kOrderFd[] = {KF_GRAD, KX_THETA, KY_20F, KZ_MAIN, KY_20I, KX_ASSEMBLE_FD, KF_DIV};
+// spectral gradient (eleven passes: one per axis for the gradient and for
+// the divergence) or finite differences (seven).
+static const int kOrderSpectral[] = {KG_X, KG_Y, KG_Z, KX_THETA, KY_20F, KZ_MAIN, KY_20I, KX_ASSEMBLE,
+                                     KD_X, KD_Y, KD_Z};
+static const int kOrderFd[] = {KF_GRAD, KX_THETA, KY_20F, KZ_MAIN, KY_20I, KX_ASSEMBLE, KF_DIV};
 static const char *kPassName[KIND_COUNT + 1] = {
-    "x_nfwd", "y_1f", "z_grad", "y_3i", "x_theta", "y_20f", "z_main", "y_20i", "x_assemble", "y_3f", "z_div",
-    "y_1i", "x_final", "fd_grad", "x_grad", "x_assemble_fd", "fd_div", "reduce"};
+    "x_deriv", "y_deriv", "z_deriv", "x_theta", "y_20f", "z_main", "y_20i", "x_assemble", "x_div", "y_div",
+    "z_div", "fd_grad", "fd_div", "reduce"};
 
 static int pass_order(int grad_mode, const int **order) {
     if (grad_mode == 0) {
@@ -741,26 +740,34 @@ static int build_image(vdwnl_ctx *c, Image &im, bool keep_tables) {
         const bool fd = c->grad_mode > 0;
         for (int r = 0; r < rows; r += g.bnf) {
             const int b = std::min(g.bnf, rows - r);   // even: rows and bnf are
-            tiles[fd ? KF_GRAD : KX_NFWD].push_back({inst, r, b, 0, -1});
-            tiles[fd ? KF_DIV : KX_FINAL].push_back({inst, r, b, 0, -1});
+            tiles[fd ? KF_GRAD : KG_X].push_back({inst, r, b, 0, -1});
+            tiles[fd ? KF_DIV : KD_X].push_back({inst, r, b, 0, -1});
         }
         int slot = 0;
         for (int r = 0; r < rows; r += g.bmain) {
             const int b = std::min(g.bmain, rows - r);
             tiles[KX_THETA].push_back({inst, r, b, 0, slot++});
-            tiles[fd ? KX_ASSEMBLE_FD : KX_ASSEMBLE].push_back({inst, r, b, 0, -1});
+            tiles[KX_ASSEMBLE].push_back({inst, r, b, 0, -1});
         }
         g.n_de = slot;
-        if (!fd)
-            for (int r = 0; r < rows; r += g.bgr) tiles[KX_GRAD].push_back({inst, r, std::min(g.bgr, rows - r), 0, -1});
-        // axis-2 tiles
-        const int kinds_y[6] = {KY_20F, KY_20I, KY_1F, KY_1I, KY_3F, KY_3I};
-        const int vs[6] = {kNQ, kNQ, 1, 1, 3, 3};
-        for (int q = 0; q < (fd ? 2 : 6); ++q) {
-            const int ftot = N3h * vs[q];
-            const int w = vs[q] == kNQ ? g.wy20 : (vs[q] == 3 ? g.wy3 : g.wy1);
+        // axis-2 tiles of the 20 spectra
+        for (int i1 = 0; i1 < N1; ++i1)
+            for (int f = 0; f < N3h * kNQ; f += g.wy20) {
+                tiles[KY_20F].push_back({inst, i1, f, std::min(g.wy20, N3h * kNQ - f), -1});
+                tiles[KY_20I].push_back({inst, i1, f, std::min(g.wy20, N3h * kNQ - f), -1});
+            }
+        // derivative tiles along axes 2 (a = i1) and 1 (a = i2): runs of i3
+        if (!fd) {
             for (int i1 = 0; i1 < N1; ++i1)
-                for (int f = 0; f < ftot; f += w) tiles[kinds_y[q]].push_back({inst, i1, f, std::min(w, ftot - f), -1});
+                for (int i3 = 0; i3 < N3; i3 += g.wdy) {
+                    tiles[KG_Y].push_back({inst, i1, i3, std::min(g.wdy, N3 - i3), -1});
+                    tiles[KD_Y].push_back({inst, i1, i3, std::min(g.wdy, N3 - i3), -1});
+                }
+            for (int i2 = 0; i2 < N2; ++i2)
+                for (int i3 = 0; i3 < N3; i3 += g.wdz) {
+                    tiles[KG_Z].push_back({inst, i2, i3, std::min(g.wdz, N3 - i3), -1});
+                    tiles[KD_Z].push_back({inst, i2, i3, std::min(g.wdz, N3 - i3), -1});
+                }
         }
         // Fused axis-1 tiles: the columns k2 and N2 - k2 (the same |m2|, so
         // the same |G| shell at every (|m1|, k3)) over a run of consecutive
@@ -795,11 +802,6 @@ static int build_image(vdwnl_ctx *c, Image &im, bool keep_tables) {
                 tiles[KZ_MAIN].push_back(tl);
             }
         }
-        for (int k2 = 0; k2 < (fd ? 0 : N2); ++k2)
-            for (int k3 = 0; k3 < N3h; k3 += g.k3aux) {
-                tiles[KZ_GRAD].push_back({inst, k2, k3, std::min(g.k3aux, N3h - k3), -1});
-                tiles[KZ_DIV].push_back({inst, k2, k3, std::min(g.k3aux, N3h - k3), -1});
-            }
         g.n_ek = slot;
         // XCD-contiguous order for this grid's tiles of the other passes
         for (int k = 0; k < KIND_COUNT; ++k) {
@@ -812,9 +814,6 @@ static int build_image(vdwnl_ctx *c, Image &im, bool keep_tables) {
         g.off_grad = off; off = align_up(off + 3 * g.npts() * rs);
         g.off_vloc = off; off = align_up(off + g.npts() * rs);
         g.off_spec = off; off = align_up(off + g.nhalf() * kNQ * cs);
-        const size_t aux = fd ? 0 : g.nhalf();   // FP64 gradient / divergence spectra
-        g.off_spec3 = off; off = align_up(off + aux * 3 * 16);
-        g.off_spec1 = off; off = align_up(off + aux * 16);
         g.off_ek = off; off = align_up(off + g.n_ek * sizeof(double));
         g.off_de = off; off = align_up(off + g.n_de * sizeof(double));
         g.off_sl = off; off = align_up(off + 2 * g.n_de * sizeof(double));
@@ -824,32 +823,27 @@ static int build_image(vdwnl_ctx *c, Image &im, bool keep_tables) {
     auto lds_of = [&](int k, const Grid &g) -> size_t {
         const size_t N1 = g.s[0], N2 = g.s[1], N3 = g.s[2];
         switch (k) {
-            // the gradient chain in FP64, the divergence chain in the working precision
-            case KX_NFWD: return (N3 + (g.bnf / 2) * (N3 + 1)) * 16;
-            case KX_FINAL: return (N3 + (g.bnf / 2) * (N3 + 1)) * cs;
+            // the gradient's derivatives in FP64, the divergence's in the working precision
+            case KG_X: return drow_lds(N3, g.bnf / 2, 16);
+            case KD_X: return drow_lds(N3, g.bnf / 2, cs);
+            case KG_Y: return deriv_lds(N2, (g.wdy + 1) / 2, 16);
+            case KD_Y: return deriv_lds(N2, (g.wdy + 1) / 2, cs);
+            case KG_Z: return deriv_lds(N1, (g.wdz + 1) / 2, 16);
+            case KD_Z: return deriv_lds(N1, (g.wdz + 1) / 2, cs);
             case KF_GRAD: case KF_DIV: return 0;
-            case KX_GRAD: return xgrad_lds(g.bgr, N3);
-            case KX_THETA: case KX_ASSEMBLE_FD: return xpass_lds(XL_PLAIN, g.bmain, N3, rs);
-            case KX_ASSEMBLE: return xpass_lds(XL_ASSEMBLE, g.bmain, N3, rs);
-            case KY_1F: return (N2 + (N2 | 1) * g.wy1) * 16;
-            case KY_1I: return (N2 + (N2 | 1) * g.wy1) * cs;
-            case KY_3I: return (N2 + (N2 | 1) * g.wy3) * 16;
-            case KY_3F: return (N2 + (N2 | 1) * g.wy3) * cs;
+            case KX_THETA: case KX_ASSEMBLE: return xpass_lds(g.bmain, N3, rs);
             case KY_20F: case KY_20I: return (N2 + (N2 | 1) * g.wy20) * cs;
-            case KZ_MAIN: {
+            default: {   // KZ_MAIN
                 const size_t K = std::min(g.k3main, kMaxCols);
                 return (N1 + (size_t)kNQ * K * (N1 | 1)) * cs + 16 + (g.general ? N1 : N1 / 2 + 1) * K * sizeof(int);
             }
-            case KZ_DIV: return (N1 + 4 * g.k3aux * (N1 | 1)) * cs;
-            default: return (N1 + 4 * g.k3aux * (N1 | 1)) * 16;   // KZ_GRAD
         }
     };
     // the axis whose FFT a pass performs: 3 for the axis-3 passes, 2, 1
     auto axis_len = [&](int k, const Grid &g) -> int {
         switch (k) {
-            case KX_NFWD: case KX_THETA: case KX_ASSEMBLE: case KX_FINAL: case KX_GRAD: case KX_ASSEMBLE_FD:
-                return g.s[2];
-            case KY_1F: case KY_1I: case KY_3F: case KY_3I: case KY_20F: case KY_20I: return g.s[1];
+            case KG_X: case KD_X: case KX_THETA: case KX_ASSEMBLE: return g.s[2];
+            case KG_Y: case KD_Y: case KY_20F: case KY_20I: return g.s[1];
             default: return g.s[0];
         }
     };
@@ -953,7 +947,7 @@ static int lds_optin(vdwnl_ctx *c) {
             if ((e = launch_kind(k, L.lc, c->precision, a)) != hipSuccess) return hipfail(c, e, "kernel LDS limit");
             // (and the stage probes that stand in for the pass)
             for (int pr : {PROBE_THETA_K, PROBE_U_K, PROBE_U}) {
-                const int pk = pr == PROBE_U ? (c->grad_mode ? KX_ASSEMBLE_FD : KX_ASSEMBLE) : KZ_MAIN;
+                const int pk = pr == PROBE_U ? KX_ASSEMBLE : KZ_MAIN;
                 if (k == pk && (e = launch_probe(pr, L.lc, c->precision, a, nullptr, 0)) != hipSuccess)
                     return hipfail(c, e, "kernel LDS limit");
             }
@@ -1054,16 +1048,14 @@ static void fill_insts(vdwnl_ctx *c, char *w, InstDev *out) {
         }
         I.dvol = I.omega / (double)g.npts();
         I.fdm = c->grad_mode;
-        if (c->grad_mode > 0) {
-            central_weights(c->grad_mode, I.fdc);
-            // W[c][x] = N_c b_c,x / (2 pi) (orthorhombic: N_c / L_c on the diagonal)
-            for (int cc = 0; cc < 3; ++cc)
-                for (int x = 0; x < 3; ++x)
-                    I.fdW[cc][x] = g.general ? (double)g.s[cc] * g.B[cc][x] / (2.0 * M_PI)
-                                             : (cc == x ? (double)g.s[cc] / g.A[cc][cc] : 0.0);
-        }
+        if (c->grad_mode > 0) central_weights(c->grad_mode, I.fdc);
+        // W[c][x] = N_c b_c,x / (2 pi) (orthorhombic: N_c / L_c on the diagonal):
+        // grad n = sum_c W[c] d_c n, the chain rule from grid index to Cartesian
+        for (int cc = 0; cc < 3; ++cc)
+            for (int x = 0; x < 3; ++x)
+                I.fdW[cc][x] = g.general ? (double)g.s[cc] * g.B[cc][x] / (2.0 * M_PI)
+                                         : (cc == x ? (double)g.s[cc] / g.A[cc][cc] : 0.0);
         I.grad = w + g.off_grad; I.vloc = w + g.off_vloc; I.spec = w + g.off_spec;
-        I.spec3 = w + g.off_spec3; I.spec1 = w + g.off_spec1;
         I.shellmap = (const int *)(w + c->map_off[g.shell_key]);
         I.shelltab = w + c->tab_off[g.shell_key];
         I.part_ek = (double *)(w + g.off_ek); I.part_de = (double *)(w + g.off_de);
@@ -1292,9 +1284,9 @@ static int probe_stage(vdwnl_ctx *c, int stage, int target, void *dst, hipStream
     const int npass = pass_order(c->grad_mode, &order);
     int stop;
     switch (stage) {
-        case VDWNL_STAGE_THETA: stop = KX_THETA; break;
+        case VDWNL_STAGE_GRAD: case VDWNL_STAGE_THETA: stop = KX_THETA; break;
         case VDWNL_STAGE_THETA_K: case VDWNL_STAGE_U_K: stop = KZ_MAIN; break;
-        default: stop = c->grad_mode ? KX_ASSEMBLE_FD : KX_ASSEMBLE; break;
+        default: stop = KX_ASSEMBLE; break;
     }
     auto args = [&](const vdwnl_ctx::Launch &L) {
         return LaunchArgs{c->dp.inst, c->dp.tiles + L.off, L.cnt, L.lds, c->dp.consts, c->dp.tw, c->dp.twd, st, c->dp.cols,
@@ -1303,6 +1295,16 @@ static int probe_stage(vdwnl_ctx *c, int stage, int target, void *dst, hipStream
     for (int i = 0; i < npass && order[i] != stop; ++i)
         for (const auto &L : c->launches[order[i]])
             if ((e = launch_kind(L.kind, L.lc, c->precision, args(L))) != hipSuccess) return hipfail(c, e, "kernel launch");
+    if (stage == VDWNL_STAGE_GRAD) {
+        // grad n as the theta pass takes it: the gradient passes' result
+        const Grid &g = c->grids[target];
+        const size_t rs = c->precision == 64 ? 8 : 4;
+        if ((e = hipMemcpyAsync(dst, (char *)c->work + g.off_grad, 3 * g.npts() * rs, hipMemcpyDeviceToDevice, st)) !=
+            hipSuccess)
+            return hipfail(c, e, "probe copy");
+        if ((e = hipStreamSynchronize(st)) != hipSuccess) return hipfail(c, e, "stream synchronize");
+        return VDWNL_OK;
+    }
     const int probe = stage == VDWNL_STAGE_THETA ? PROBE_THETA
                       : stage == VDWNL_STAGE_THETA_K ? PROBE_THETA_K
                       : stage == VDWNL_STAGE_U_K ? PROBE_U_K : PROBE_U;
@@ -1651,7 +1653,7 @@ int vdwnl_debug_field(vdwnl_ctx *ctx, int32_t inst, int32_t which, void *dst, vo
 
 int vdwnl_debug_stage(vdwnl_ctx *ctx, int32_t inst, int32_t stage, void *dst, void *stream) {
     if (!ctx || !dst) return VDWNL_E_ARG;
-    if (stage < VDWNL_STAGE_THETA || stage > VDWNL_STAGE_U) return fail(ctx, VDWNL_E_ARG, "unknown stage");
+    if (stage < VDWNL_STAGE_THETA || stage > VDWNL_STAGE_GRAD) return fail(ctx, VDWNL_E_ARG, "unknown stage");
     int rc = wait_pending(ctx);
     if (rc != VDWNL_OK) return rc;
     if (!ctx->device_ready || !ctx->evaluated || inst < 0 || inst >= (int32_t)ctx->grids.size())
@@ -1741,11 +1743,11 @@ int vdwnl_autotune(vdwnl_ctx *ctx, int32_t nb, const void *const *n_ptrs, void *
     // per group, the budget with the least time over the group's passes (a
     // group with no pass in this gradient mode keeps the default); for the
     // fused axis-1 group, the budget and the contraction unit together
-    const std::vector<std::vector<int>> groups = {{KX_THETA, KX_ASSEMBLE, KX_ASSEMBLE_FD},
+    const std::vector<std::vector<int>> groups = {{KX_THETA, KX_ASSEMBLE},
                                                   {KY_20F, KY_20I},
-                                                  {KY_1F, KY_1I, KY_3F, KY_3I},
+                                                  {KG_Y, KD_Y},
                                                   {KZ_MAIN},
-                                                  {KZ_GRAD, KZ_DIV}};
+                                                  {KG_Z, KD_Z}};
     size_t best[TG_COUNT];
     int best_unit = VDWNL_CONTRACTION_VECTOR;
     for (int gi = 0; gi < TG_COUNT; ++gi) {

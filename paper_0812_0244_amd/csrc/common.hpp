@@ -32,14 +32,11 @@ struct FftPlan {
 
 // Per-grid state seen by the kernels.  Field layouts (C order):
 //   n, v, vloc      [N1][N2][N3] real
-//   grad            [3][N1][N2][N3] real  (grad n, Cartesian components; in the
-//                   finite-difference mode overwritten in place by the lattice
-//                   components q_c = sum_x W[c][x] w_x of the assembly's vector field)
+//   grad            [3][N1][N2][N3] real  (grad n, Cartesian components, after the
+//                   gradient passes (general cells: d_3 n, d_2 n in slots 2, 1
+//                   between them); overwritten in place by the assembly with the
+//                   lattice components q_c = sum_x W[c][x] w_x of its vector field)
 //   spec            [N1][N2][N3h][kNQ] complex  (20 theta / u spectra, component fastest)
-//   spec3           [N1][N2][N3h][3] complex        (grad n spectra in FP64; later the
-//                   w spectra in the working precision)
-//   spec1           [N1][N2][N3h] complex           (n spectrum in FP64; later the
-//                   divergence spectrum in the working precision)
 //   shellmap        [N1/2+1][N2/2+1][N3h] int   (|G| shell of (|m1|, |m2|, m3)); in a
 //                   general (non-orthogonal) cell [N1][N2][N3h] over the whole half spectrum
 //   shelltab        [nshell][kNQ][kNQ] real     (phi_ab(|G_s|), the full symmetric matrix:
@@ -54,7 +51,7 @@ struct InstDev {
     int fdm;                 // finite-difference half-width m (0: spectral gradient)
     double fdc[kMaxFd];      // weights c_s of the central formula (unit spacing)
     double fdW[3][3];        // W[c][x] = N_c b_c,x / (2 pi): grad n = sum_c W[c] d_c n
-    void *grad, *vloc, *spec, *spec3, *spec1;
+    void *grad, *vloc, *spec;
     const int *shellmap;
     const void *shelltab;
     double *part_ek;         // one partial per fused axis-1 tile
@@ -88,25 +85,22 @@ struct Tile {
 };
 
 enum KernelKind {
-    KX_NFWD = 0,   // R2C of n along axis 3
-    KY_1F,         // axis-2 forward, 1 component
-    KZ_GRAD,       // axis 1: n -> i G_c n / N (3 components)
-    KY_3I,         // axis-2 inverse, 3 components
+    // spectral gradient: one pass per grid axis (one-axis FFTs in FP64)
+    KG_X = 0,      // axis 3: d_3 n
+    KG_Y,          // axis 2: d_2 n
+    KG_Z,          // axis 1: d_1 n, grad n complete (Cartesian components)
     KX_THETA,      // theta_a from n and the stored grad n, R2C theta along axis 3
     KY_20F,        // axis-2 forward, 20 components
     KZ_MAIN,       // axis 1 forward, u = phi c, energy, axis 1 inverse
     KY_20I,        // axis-2 inverse, 20 components
-    KX_ASSEMBLE,   // C2R u_a, v_loc and w = g grad n, R2C w along axis 3 (working precision from here)
-    KY_3F,         // axis-2 forward, 3 components
-    KZ_DIV,        // axis 1: sum_c i G_c w_c / N (1 component)
-    KY_1I,         // axis-2 inverse, 1 component
-    KX_FINAL,      // C2R divergence, v = v_loc - div
-    // finite-difference gradient mode: the stencils replace the gradient and
-    // divergence FFT chains
+    KX_ASSEMBLE,   // C2R u_a, v_loc, the lattice components q_c of w in place of grad n
+    // spectral divergence: v = v_loc - sum_c d_c q_c, one pass per axis
+    KD_X,          // axis 3: v = v_loc - d_3 q_3
+    KD_Y,          // axis 2: v -= d_2 q_2
+    KD_Z,          // axis 1: v -= d_1 q_1
+    // finite-difference gradient mode: the stencils replace the per-axis passes
     KF_GRAD,       // grad n by central differences
-    KX_GRAD,       // (spectral) C2R of the FP64 grad n spectra along axis 3, grad n stored
-    KX_ASSEMBLE_FD,// C2R u_a, v_loc and w (stored in place of grad n)
-    KF_DIV,        // v = v_loc - sum_c D_c w_c
+    KF_DIV,        // v = v_loc - sum_c D_c q_c
     KIND_COUNT
 };
 

@@ -273,89 +273,6 @@ __device__ __forceinline__ void load_consts(const Consts *cst, T *qm, T *Mm, T *
 
 // ---------------------------------------------------------------- axis-3 passes
 
-// R2C of n (read in T, transformed in FP64): rows (2p, 2p+1) of a tile form
-// one complex line.  tile: a = first row (i1 N2 + i2), b = rows (even)
-template <typename T, int LC, int V>
-__global__ void __launch_bounds__(kThreads) k_x_nfwd(const InstDev *insts, const Tile *tiles,
-                                                     const void *twdv) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    const Tile t = tiles[blockIdx.x];
-    const InstDev &I = insts[t.inst];
-    const int N3 = axis_len<LC>(I.n3), N3h = N3 / 2 + 1, row0 = t.a, B = t.b, np = B / 2, ls = N3 + 1;
-    // (the grid's first pass: clear its bad-density flag before the theta pass)
-    if (row0 == 0 && threadIdx.x == 0) gst(I.bad)[0] = 0;
-    double2 *tw = reinterpret_cast<double2 *>(smem);
-    double2 *buf = tw + N3;
-    const T *n = reinterpret_cast<const T *>(I.n) + (size_t)row0 * N3;
-    batched<4>(np * N3, [&](int idx) {
-        const int pr = idx / N3, k = idx - pr * N3;
-        return mk<double>((double)gld(n)[(2 * pr) * N3 + k], (double)gld(n)[(2 * pr + 1) * N3 + k]);
-    }, [&](int idx, double2 z) {
-        const int pr = idx / N3, k = idx - pr * N3;
-        buf[pr * ls + k] = z;
-    });
-    load_twiddles<double>(tw, I.p3, reinterpret_cast<const double2 *>(twdv));
-    __syncthreads();
-    fft_lc<double, -1, LC, V>(buf, I.p3, np, 1, ls, tw);
-    double2 *out = reinterpret_cast<double2 *>(I.spec1) + (size_t)row0 * N3h;
-    for (int idx = threadIdx.x; idx < B * N3h; idx += kThreads) {
-        const int rb = idx / N3h, k = idx - rb * N3h;
-        const double2 *Z = buf + (rb >> 1) * ls;
-        const double2 z = Z[k], zc = cconj(Z[(N3 - k) % N3]);
-        double2 y;
-        if ((rb & 1) == 0) y = mk<double>((z.x + zc.x) * 0.5, (z.y + zc.y) * 0.5);
-        else y = mk<double>((z.y - zc.y) * 0.5, -(z.x - zc.x) * 0.5);
-        out[idx] = y;
-    }
-}
-
-// C2R of the three FP64 grad n spectra (axis 3), grad n stored in T.  Rows
-// (2p, 2p+1) of a tile make three complex lines: 3p and 3p+1 hold
-// d1 + i d2 of row 2p and of row 2p+1, 3p+2 holds d3 of row 2p + i d3 of row
-// 2p+1 (each real field has a Hermitian spectrum: the half spectrum at k and,
-// conjugated, at N3 - k).  tile: a = first row, b = rows (even).
-template <typename T, int LC, int V>
-__global__ void __launch_bounds__(kThreads) k_x_grad(const InstDev *insts, const Tile *tiles,
-                                                     const void *twdv) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    const Tile t = tiles[blockIdx.x];
-    const InstDev &I = insts[t.inst];
-    const int N3 = axis_len<LC>(I.n3), N3h = N3 / 2 + 1, row0 = t.a, B = t.b, np = B / 2, ls = N3 + 1;
-    const size_t N = (size_t)I.n1 * I.n2 * I.n3;
-    double2 *tw = reinterpret_cast<double2 *>(smem);
-    double2 *buf = tw + N3;
-    const double2 *s3 = reinterpret_cast<const double2 *>(I.spec3) + (size_t)row0 * N3h * 3;
-    struct Six { double2 a0, b0, c0, a1, b1, c1; };
-    batched<2>(np * N3, [&](int idx) {
-        const int pr = idx / N3, k = idx - pr * N3;
-        const int kk = k >= N3h ? N3 - k : k;
-        const gptr<const double2> g0 = gld(s3 + ((size_t)(2 * pr) * N3h + kk) * 3);
-        const gptr<const double2> g1 = gld(s3 + ((size_t)(2 * pr + 1) * N3h + kk) * 3);
-        return Six{g0[0], g0[1], g0[2], g1[0], g1[1], g1[2]};
-    }, [&](int idx, Six y) {
-        const int pr = idx / N3, k = idx - pr * N3;
-        if (k >= N3h) {
-            y.a0 = cconj(y.a0); y.b0 = cconj(y.b0); y.c0 = cconj(y.c0);
-            y.a1 = cconj(y.a1); y.b1 = cconj(y.b1); y.c1 = cconj(y.c1);
-        }
-        double2 *L = buf + 3 * pr * ls + k;
-        L[0] = mk<double>(y.a0.x - y.b0.y, y.a0.y + y.b0.x);
-        L[ls] = mk<double>(y.a1.x - y.b1.y, y.a1.y + y.b1.x);
-        L[2 * ls] = mk<double>(y.c0.x - y.c1.y, y.c0.y + y.c1.x);
-    });
-    load_twiddles<double>(tw, I.p3, reinterpret_cast<const double2 *>(twdv));
-    __syncthreads();
-    fft_lc<double, 1, LC, V>(buf, I.p3, 3 * np, 1, ls, tw);
-    const gptr<T> g = gst(reinterpret_cast<T *>(I.grad) + (size_t)row0 * N3);
-    for (int idx = threadIdx.x; idx < B * N3; idx += kThreads) {
-        const int rb = idx / N3, k = idx - rb * N3, pr = rb >> 1, odd = rb & 1;
-        const double2 z = buf[(3 * pr + odd) * ls + k], z3 = buf[(3 * pr + 2) * ls + k];
-        g[idx] = (T)z.x;
-        g[N + idx] = (T)z.y;
-        g[2 * N + idx] = (T)(odd ? z3.y : z3.x);
-    }
-}
-
 // theta_a = n p_a(q0) from n and the stored grad n, Delta E partials, R2C of
 // the 20 theta rows.  tile: a = first row, b = rows, slot = partial.
 template <typename T, int LC, int V>
@@ -505,10 +422,10 @@ __device__ __forceinline__ void u_lines_in(C2<T> *r2, int ls, const C2<T> *sp, i
 }
 
 // C2R of the 20 u_a rows; v_loc = sum_a u_a dtheta_a/dn + de/dn;
-// w = g grad n with g = sum_a u_a 2 n p'_a Q dq/dsigma + de/dsigma-part;
-// R2C of the three w rows (in T: the divergence chain runs in the working
-// precision), or (FD) w stored in place of grad n.  tile: a = first row, b = rows.
-template <typename T, int LC, int V, bool FD>
+// w = g grad n with g = sum_a u_a 2 n p'_a Q dq/dsigma + de/dsigma-part,
+// stored in place of grad n as its lattice components q_c (the divergence
+// passes take them).  tile: a = first row, b = rows.
+template <typename T, int LC, int V>
 __global__ void __launch_bounds__(kThreads) k_x_assemble(const InstDev *insts, const Tile *tiles,
                                                          const Consts *cst, const void *twv) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -516,8 +433,7 @@ __global__ void __launch_bounds__(kThreads) k_x_assemble(const InstDev *insts, c
     const InstDev &I = insts[t.inst];
     const int N3 = axis_len<LC>(I.n3), N3h = N3 / 2 + 1, row0 = t.a, B = t.b, ls = N3 + 1;
     const size_t N = (size_t)I.n1 * I.n2 * I.n3;
-    C2<T> *r1 = reinterpret_cast<C2<T> *>(smem);              // 2 lines per row: w1 + i w2, w3
-    C2<T> *r2 = r1 + (FD ? 0 : 2 * B * ls);                   // 10 lines per row: u pairs
+    C2<T> *r2 = reinterpret_cast<C2<T> *>(smem);              // 10 lines per row: u pairs
     C2<T> *tw = r2 + kNQ / 2 * B * ls;                       // twiddles in T
     T *qm = reinterpret_cast<T *>(tw + N3);
     T *Mm = qm + kNQ;
@@ -585,34 +501,14 @@ __global__ void __launch_bounds__(kThreads) k_x_assemble(const InstDev *insts, c
             }
         }
         vloc[idx] = vl;
-        if constexpr (FD) {
-            // the lattice components q_c = sum_x W[c][x] w_x of w in place of
-            // grad n (each point is read and written by its own thread)
-            const double gsd = (double)gs;
-            const double wx = gsd * (double)gx, wy = gsd * (double)gy, wz = gsd * (double)gz;
-            const gptr<T> wout = gst(reinterpret_cast<T *>(I.grad) + p0);
+        // the lattice components q_c = sum_x W[c][x] w_x of w in place of
+        // grad n (each point is read and written by its own thread)
+        const double gsd = (double)gs;
+        const double wx = gsd * (double)gx, wy = gsd * (double)gy, wz = gsd * (double)gz;
+        const gptr<T> wout = gst(reinterpret_cast<T *>(I.grad) + p0);
 #pragma unroll
-            for (int c = 0; c < 3; ++c)
-                wout[c * N + idx] = (T)(I.fdW[c][0] * wx + I.fdW[c][1] * wy + I.fdW[c][2] * wz);
-        } else {
-            r1[(2 * rb) * ls + k] = mk<T>(gs * gx, gs * gy);
-            r1[(2 * rb + 1) * ls + k] = mk<T>(gs * gz, (T)0);
-        }
-    }
-    if constexpr (!FD) {
-        __syncthreads();
-        fft_lc<T, -1, LC, V>(r1, I.p3, 2 * B, 1, ls, tw);
-        C2<T> *out = reinterpret_cast<C2<T> *>(I.spec3) + (size_t)row0 * N3h * 3;
-        for (int idx = threadIdx.x; idx < B * N3h * 3; idx += kThreads) {
-            const int comp = idx % 3, rest = idx / 3;
-            const int k = rest % N3h, rb = rest / N3h;
-            const C2<T> *Z = r1 + (2 * rb + (comp >> 1)) * ls;
-            const C2<T> z = Z[k], zc = cconj(Z[(N3 - k) % N3]);
-            C2<T> y;
-            if (comp != 1) y = mk<T>((z.x + zc.x) * (T)0.5, (z.y + zc.y) * (T)0.5);
-            else y = mk<T>((z.y - zc.y) * (T)0.5, -(z.x - zc.x) * (T)0.5);
-            gst(out)[idx] = y;
-        }
+        for (int c = 0; c < 3; ++c)
+            wout[c * N + idx] = (T)(I.fdW[c][0] * wx + I.fdW[c][1] * wy + I.fdW[c][2] * wz);
     }
 }
 
@@ -737,56 +633,161 @@ __global__ void __launch_bounds__(kThreads) k_fd_div(const InstDev *insts, const
     }
 }
 
-// C2R of the divergence spectrum (row pairs, working precision), v = v_loc - div.
-template <typename T, int LC, int V>
-__global__ void __launch_bounds__(kThreads) k_x_final(const InstDev *insts, const Tile *tiles,
-                                                      const void *twv) {
+// ---------------------------------------------------------------- per-axis spectral derivatives
+
+// The spectral gradient of Eq. (Vi) multiplies the transform of n by i G_x,
+// G = sum_c m_c b_c with the Nyquist index m_c = N_c/2 taken as zero: a sum
+// of one-axis multipliers, so grad n = sum_c W[c] d_c n exactly, with d_c n
+// = F_c^-1[i (2 pi m_c / N_c) F_c n] the derivative along grid axis c alone
+// (in grid-index units; W[c][x] = N_c b_c,x / (2 pi)) and F_c the 1-D DFT
+// along that axis; the divergence of the gradient term of v is likewise
+// sum_c d_c q_c with q_c = sum_x W[c][x] w_x.  One pass per axis: pairs of
+// real lines as one complex line (the one-axis operator is real), forward
+// DFT, i kappa_m (Nyquist zero; the inverse's 1/N folded in), inverse DFT.
+// MODE 0 (gradient, FP64 lines): n -> d_c n; MODE 1 (divergence, lines in
+// the working precision): q_c -> the potential, v = v_loc - sum_c d_c q_c.
+
+// spectra of nl lines (length L, pitch ls) times i s 2 pi m / L^2
+template <typename C>
+__device__ __forceinline__ void deriv_multiply(C2<C> *buf, int nl, int L, int ls, double s) {
+    const double k0 = 2.0 * 3.14159265358979323846 / ((double)L * (double)L) * s;
+    for (int idx = threadIdx.x; idx < nl * L; idx += kThreads) {
+        const int l = idx / L, m0 = idx - l * L;
+        const int m = 2 * m0 == L ? 0 : (2 * m0 < L ? m0 : m0 - L);
+        const C kap = (C)(k0 * (double)m);
+        C2<C> &z = buf[l * ls + m0];
+        z = mk<C>(-kap * z.y, kap * z.x);
+    }
+    __syncthreads();
+}
+
+// Axis 3 (rows, contiguous).  tile: a = first row (i1 N2 + i2), b = rows
+// (even: rows 2p, 2p+1 form line p).  MODE 0: grad[2] = W[2][2] d_3 n
+// (orthorhombic) or d_3 n (general cells: the axis-1 pass combines); the
+// grid's first pass, it also clears the bad-density flag.  MODE 1: v =
+// v_loc - d_3 q_3 (q_3 in grad[2]).
+template <typename T, typename C, int LC, int V, int MODE>
+__global__ void __launch_bounds__(kThreads) k_drow(const InstDev *insts, const Tile *tiles, const void *twv) {
     extern __shared__ __align__(16) unsigned char smem[];
     const Tile t = tiles[blockIdx.x];
     const InstDev &I = insts[t.inst];
-    const int N3 = axis_len<LC>(I.n3), N3h = N3 / 2 + 1, row0 = t.a, B = t.b, np = B / 2, ls = N3 + 1;
-    C2<T> *tw = reinterpret_cast<C2<T> *>(smem);
-    C2<T> *buf = tw + N3;
-    const C2<T> *s1 = reinterpret_cast<const C2<T> *>(I.spec1) + (size_t)row0 * N3h;
-    const int npt = B * N3;
-    const gptr<const T> vloc = gld(reinterpret_cast<const T *>(I.vloc) + (size_t)row0 * N3);
-    struct Two { C2<T> a, b; };
+    const int N3 = axis_len<LC>(I.n3), row0 = t.a, B = t.b, np = B / 2, ls = N3 + 1;
+    const size_t N = (size_t)I.n1 * I.n2 * I.n3;
+    if (MODE == 0 && row0 == 0 && threadIdx.x == 0) gst(I.bad)[0] = 0;
+    C2<C> *tw = reinterpret_cast<C2<C> *>(smem);
+    C2<C> *buf = tw + N3;
+    const T *f = MODE == 0 ? reinterpret_cast<const T *>(I.n) + (size_t)row0 * N3
+                           : reinterpret_cast<const T *>(I.grad) + 2 * N + (size_t)row0 * N3;
     batched<4>(np * N3, [&](int idx) {
         const int pr = idx / N3, k = idx - pr * N3;
-        const int kk = k >= N3h ? N3 - k : k;
-        return Two{gld(s1)[(2 * pr) * N3h + kk], gld(s1)[(2 * pr + 1) * N3h + kk]};
-    }, [&](int idx, Two y) {
+        return mk<C>((C)gld(f)[(2 * pr) * N3 + k], (C)gld(f)[(2 * pr + 1) * N3 + k]);
+    }, [&](int idx, C2<C> z) {
         const int pr = idx / N3, k = idx - pr * N3;
-        if (k >= N3h) { y.a = cconj(y.a); y.b = cconj(y.b); }
-        buf[pr * ls + k] = mk<T>(y.a.x - y.b.y, y.a.y + y.b.x);
+        buf[pr * ls + k] = z;
     });
-    load_twiddles<T>(tw, I.p3, reinterpret_cast<const C2<T> *>(twv));
+    load_twiddles<C>(tw, I.p3, reinterpret_cast<const C2<C> *>(twv));
     __syncthreads();
-    fft_lc<T, 1, LC, V>(buf, I.p3, np, 1, ls, tw);
-    const gptr<T> v = gst(reinterpret_cast<T *>(I.v) + (size_t)row0 * N3);
-    batched<4>(npt, [&](int idx) { return vloc[idx]; }, [&](int idx, T vl) {
-        const int rb = idx / N3, k = idx - rb * N3;
-        const C2<T> z = buf[(rb >> 1) * ls + k];
-        v[idx] = vl - ((rb & 1) ? z.y : z.x);
+    fft_lc<C, -1, LC, V>(buf, I.p3, np, 1, ls, tw);
+    deriv_multiply<C>(buf, np, N3, ls, (MODE == 0 && !I.general) ? I.fdW[2][2] : 1.0);
+    fft_lc<C, 1, LC, V>(buf, I.p3, np, 1, ls, tw);
+    const int npt = B * N3;
+    if constexpr (MODE == 0) {
+        const gptr<T> g = gst(reinterpret_cast<T *>(I.grad) + 2 * N + (size_t)row0 * N3);
+        for (int idx = threadIdx.x; idx < npt; idx += kThreads) {
+            const int rb = idx / N3, k = idx - rb * N3;
+            const C2<C> z = buf[(rb >> 1) * ls + k];
+            g[idx] = (T)((rb & 1) ? z.y : z.x);
+        }
+    } else {
+        const gptr<const T> vl = gld(reinterpret_cast<const T *>(I.vloc) + (size_t)row0 * N3);
+        const gptr<T> v = gst(reinterpret_cast<T *>(I.v) + (size_t)row0 * N3);
+        batched<4>(npt, [&](int idx) { return vl[idx]; }, [&](int idx, T x) {
+            const int rb = idx / N3, k = idx - rb * N3;
+            const C2<C> z = buf[(rb >> 1) * ls + k];
+            v[idx] = x - (T)((rb & 1) ? z.y : z.x);
+        });
+    }
+}
+
+// Axes 2 (AX = 2: lines along i2, element stride N3) and 1 (AX = 1: along
+// i1, stride N2 N3).  tile: a = the other outer index (i1, or i2), b = first
+// i3, c = number W of consecutive i3 (pairs form one complex line; an odd
+// W's last line has a zero imaginary part).  MODE 0, AX = 2: grad[1] =
+// W[1][1] d_2 n (orthorhombic) or d_2 n (general).  MODE 0, AX = 1 (the last
+// gradient pass): grad[0] = W[0][0] d_1 n (orthorhombic); general cells: grad n
+// = sum_c W[c] d_c n from d_1 n and the stored d_2 n, d_3 n, all three
+// Cartesian components written.  MODE 1: v -= d_c q_c (q_c in grad[AX-1]).
+template <typename T, typename C, int LC, int V, int MODE, int AX>
+__global__ void __launch_bounds__(kThreads) k_dcol(const InstDev *insts, const Tile *tiles, const void *twv) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const Tile t = tiles[blockIdx.x];
+    const InstDev &I = insts[t.inst];
+    constexpr int c = AX - 1;                                  // lattice axis (0-based)
+    const int L = axis_len<LC>(AX == 2 ? I.n2 : I.n1), lp = L | 1, Wc = t.c, np = (Wc + 1) / 2;
+    const size_t N = (size_t)I.n1 * I.n2 * I.n3;
+    const int stride = AX == 2 ? I.n3 : I.n2 * I.n3;           // (32-bit offsets: 3 N < 2^31)
+    const size_t base = (AX == 2 ? (size_t)t.a * I.n2 * I.n3 : (size_t)t.a * I.n3) + t.b;
+    C2<C> *tw = reinterpret_cast<C2<C> *>(smem);
+    C2<C> *buf = tw + L;
+    C *bc = reinterpret_cast<C *>(buf);                        // (re, im) of element e of line j / 2 at 2 ((j/2) lp + e) + j % 2
+    const gptr<const T> f = gld(MODE == 0 ? reinterpret_cast<const T *>(I.n) + base
+                                          : reinterpret_cast<const T *>(I.grad) + c * N + base);
+    batched<8>(L * Wc, [&](int idx) {
+        const int e = idx / Wc, j = idx - e * Wc;
+        return (C)f[e * stride + j];
+    }, [&](int idx, C x) {
+        const int e = idx / Wc, j = idx - e * Wc;
+        bc[2 * ((j >> 1) * lp + e) + (j & 1)] = x;
     });
+    if (Wc & 1)
+        for (int e = threadIdx.x; e < L; e += kThreads) bc[2 * ((np - 1) * lp + e) + 1] = (C)0;
+    load_twiddles<C>(tw, AX == 2 ? I.p2 : I.p1, reinterpret_cast<const C2<C> *>(twv));
+    __syncthreads();
+    fft_lc<C, -1, LC, V>(buf, AX == 2 ? I.p2 : I.p1, np, 1, lp, tw);
+    deriv_multiply<C>(buf, np, L, lp, (MODE == 0 && !I.general) ? I.fdW[c][c] : 1.0);
+    fft_lc<C, 1, LC, V>(buf, AX == 2 ? I.p2 : I.p1, np, 1, lp, tw);
+    T *gbase = reinterpret_cast<T *>(I.grad) + base;
+    if constexpr (MODE == 0) {
+        const bool combine = AX == 1 && I.general;
+        for (int idx = threadIdx.x; idx < L * Wc; idx += kThreads) {
+            const int e = idx / Wc, j = idx - e * Wc;
+            const size_t o = (size_t)e * stride + j;
+            const C d = bc[2 * ((j >> 1) * lp + e) + (j & 1)];
+            if (!combine) {
+                gst(gbase)[c * N + o] = (T)d;
+            } else {
+                const double d1 = (double)d, d2 = (double)gld(gbase)[N + o], d3 = (double)gld(gbase)[2 * N + o];
+#pragma unroll
+                for (int x = 0; x < 3; ++x)
+                    gst(gbase)[x * N + o] = (T)(I.fdW[0][x] * d1 + I.fdW[1][x] * d2 + I.fdW[2][x] * d3);
+            }
+        }
+    } else {
+        const gptr<T> v = gst(reinterpret_cast<T *>(I.v) + base);
+        batched<4>(L * Wc, [&](int idx) {
+            const int e = idx / Wc, j = idx - e * Wc;
+            return v[e * stride + j];
+        }, [&](int idx, T x) {
+            const int e = idx / Wc, j = idx - e * Wc;
+            v[e * stride + j] = x - (T)bc[2 * ((j >> 1) * lp + e) + (j & 1)];
+        });
+    }
 }
 
 // ---------------------------------------------------------------- axis-2 pass
 
-// tile: a = i1, b = first flattened (k3, component) index, c = width;
-// ncomp components per k point
+// The 20 spectra along axis 2.  tile: a = i1, b = first flattened (k3,
+// component) index, c = width
 template <typename T, int S, int LC, int V>
-__global__ void __launch_bounds__(kThreads) k_y(const InstDev *insts, const Tile *tiles,
-                                                const void *twv, int which, int ncomp) {
+__global__ void __launch_bounds__(kThreads) k_y(const InstDev *insts, const Tile *tiles, const void *twv) {
     extern __shared__ __align__(16) unsigned char smem[];
     const Tile t = tiles[blockIdx.x];
     const InstDev &I = insts[t.inst];
     const int N2 = axis_len<LC>(I.n2), W = t.c, lp = N2 | 1;   // lines contiguous, odd pitch
     C2<T> *tw = reinterpret_cast<C2<T> *>(smem);
     C2<T> *buf = tw + N2;
-    const size_t rowlen = (size_t)I.n3h * ncomp;
-    void *base = which == 0 ? I.spec : (which == 1 ? I.spec3 : I.spec1);
-    C2<T> *g = reinterpret_cast<C2<T> *>(base) + (size_t)t.a * N2 * rowlen + t.b;
+    const size_t rowlen = (size_t)I.n3h * kNQ;
+    C2<T> *g = reinterpret_cast<C2<T> *>(I.spec) + (size_t)t.a * N2 * rowlen + t.b;
     rows_in_t(buf, lp, g, rowlen, N2, W);
     load_twiddles<T>(tw, I.p2, reinterpret_cast<const C2<T> *>(twv));
     __syncthreads();
@@ -795,75 +796,6 @@ __global__ void __launch_bounds__(kThreads) k_y(const InstDev *insts, const Tile
 }
 
 // ---------------------------------------------------------------- axis-1 passes
-
-// n spectrum -> i G_c n / N, c = 1..3.  tile: a = k2, b = first k3, c = count
-template <typename T, int LC, int V>
-__global__ void __launch_bounds__(kThreads) k_z_grad(const InstDev *insts, const Tile *tiles,
-                                                     const void *twv) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    const Tile t = tiles[blockIdx.x];
-    const InstDev &I = insts[t.inst];
-    const int N1 = axis_len<LC>(I.n1), N2 = I.n2, N3 = I.n3, N3h = I.n3h, k2 = t.a, k30 = t.b, K3 = t.c;
-    const int lp = N1 | 1;                                   // lines contiguous, odd pitch
-    C2<T> *twall = reinterpret_cast<C2<T> *>(smem);
-    C2<T> *bin = twall + N1;                                 // K3 lines
-    C2<T> *bout = bin + K3 * lp;                             // 3 K3 lines: (w, c) at line 3 w + c
-    const C2<T> *gin = reinterpret_cast<const C2<T> *>(I.spec1) + (size_t)k2 * N3h + k30;
-    const size_t sin_ = (size_t)N2 * N3h;
-    rows_in_t(bin, lp, gin, sin_, N1, K3);
-    load_twiddles<T>(twall, I.p1, reinterpret_cast<const C2<T> *>(twv));
-    __syncthreads();
-    fft_lc<T, -1, LC, V>(bin, I.p1, K3, 1, lp, twall);
-    const double m2 = (double)freq_nz(k2, N2);
-    for (int idx = threadIdx.x; idx < N1 * K3; idx += kThreads) {
-        const int w = idx / N1, l = idx - w * N1;
-        const C2<T> nh = cscale(bin[w * lp + l], (T)I.inv_n);
-        T G1, G2, G3;
-        cart_g<T>(I, (double)freq_nz(l, N1), m2, (double)freq_nz(k30 + w, N3), G1, G2, G3);
-        C2<T> *o = bout + 3 * w * lp + l;
-        o[0] = mk<T>(-G1 * nh.y, G1 * nh.x);
-        o[lp] = mk<T>(-G2 * nh.y, G2 * nh.x);
-        o[2 * lp] = mk<T>(-G3 * nh.y, G3 * nh.x);
-    }
-    __syncthreads();
-    fft_lc<T, 1, LC, V>(bout, I.p1, 3 * K3, 1, lp, twall);
-    C2<T> *gout = reinterpret_cast<C2<T> *>(I.spec3) + ((size_t)k2 * N3h + k30) * 3;
-    rows_out_t(gout, sin_ * 3, bout, lp, N1, 3 * K3);
-}
-
-// sum_c i G_c w_c / N.  tile: a = k2, b = first k3, c = count
-template <typename T, int LC, int V>
-__global__ void __launch_bounds__(kThreads) k_z_div(const InstDev *insts, const Tile *tiles,
-                                                    const void *twv) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    const Tile t = tiles[blockIdx.x];
-    const InstDev &I = insts[t.inst];
-    const int N1 = axis_len<LC>(I.n1), N2 = I.n2, N3 = I.n3, N3h = I.n3h, k2 = t.a, k30 = t.b, K3 = t.c;
-    const int lp = N1 | 1;                                   // lines contiguous, odd pitch
-    C2<T> *twall = reinterpret_cast<C2<T> *>(smem);
-    C2<T> *bin = twall + N1;                                 // 3 K3 lines: (w, c) at line 3 w + c
-    C2<T> *bout = bin + 3 * K3 * lp;                         // K3 lines
-    const size_t sin_ = (size_t)N2 * N3h;
-    const C2<T> *gin = reinterpret_cast<const C2<T> *>(I.spec3) + ((size_t)k2 * N3h + k30) * 3;
-    rows_in_t(bin, lp, gin, sin_ * 3, N1, 3 * K3);
-    load_twiddles<T>(twall, I.p1, reinterpret_cast<const C2<T> *>(twv));
-    __syncthreads();
-    fft_lc<T, -1, LC, V>(bin, I.p1, 3 * K3, 1, lp, twall);
-    const double m2 = (double)freq_nz(k2, N2);
-    for (int idx = threadIdx.x; idx < N1 * K3; idx += kThreads) {
-        const int w = idx / N1, l = idx - w * N1;
-        const C2<T> *x = bin + 3 * w * lp + l;
-        T G1, G2, G3;
-        cart_g<T>(I, (double)freq_nz(l, N1), m2, (double)freq_nz(k30 + w, N3), G1, G2, G3);
-        const T sx = G1 * x[0].x + G2 * x[lp].x + G3 * x[2 * lp].x;
-        const T sy = G1 * x[0].y + G2 * x[lp].y + G3 * x[2 * lp].y;
-        bout[w * lp + l] = cscale(mk<T>(-sy, sx), (T)I.inv_n);
-    }
-    __syncthreads();
-    fft_lc<T, 1, LC, V>(bout, I.p1, K3, 1, lp, twall);
-    C2<T> *gout = reinterpret_cast<C2<T> *>(I.spec1) + (size_t)k2 * N3h + k30;
-    rows_out_t(gout, sin_, bout, lp, N1, K3);
-}
 
 // Forward axis-1 FFT of the 20 theta spectra, u_a(G) = sum_b phi_ab(|G|) c_b(G)
 // with c = Theta / N (Eq. Eoffk, Eq. epsofk), the energy sum
@@ -1318,12 +1250,11 @@ static void allow_lds(K kernel, size_t bytes) {
 template <typename T, int LC, int V>
 hipError_t launch_x_lc(int kind, const LaunchArgs &a) {
     switch (kind) {
-        case KX_NFWD: VDWNL_LAUNCH((k_x_nfwd<T, LC, V>), a.twd); break;
-        case KX_GRAD: VDWNL_LAUNCH((k_x_grad<T, LC, V>), a.twd); break;
+        // (the gradient's one-axis transforms in FP64, the divergence's in T)
+        case KG_X: VDWNL_LAUNCH((k_drow<T, double, LC, V, 0>), a.twd); break;
+        case KD_X: VDWNL_LAUNCH((k_drow<T, T, LC, V, 1>), a.tw); break;
         case KX_THETA: VDWNL_LAUNCH((k_x_theta<T, LC, V>), a.cst, a.tw); break;
-        case KX_ASSEMBLE: VDWNL_LAUNCH((k_x_assemble<T, LC, V, false>), a.cst, a.tw); break;
-        case KX_ASSEMBLE_FD: VDWNL_LAUNCH((k_x_assemble<T, LC, V, true>), a.cst, a.tw); break;
-        case KX_FINAL: VDWNL_LAUNCH((k_x_final<T, LC, V>), a.tw); break;
+        case KX_ASSEMBLE: VDWNL_LAUNCH((k_x_assemble<T, LC, V>), a.cst, a.tw); break;
         case KP_U: VDWNL_LAUNCH((k_probe_u<T, LC, V>), a.tw, a.dst, a.target); break;
         default: return hipErrorInvalidValue;
     }
@@ -1333,13 +1264,10 @@ hipError_t launch_x_lc(int kind, const LaunchArgs &a) {
 template <typename T, int LC, int V>
 hipError_t launch_y_lc(int kind, const LaunchArgs &a) {
     switch (kind) {
-        // (the gradient chain in FP64)
-        case KY_1F: VDWNL_LAUNCH((k_y<double, -1, LC, V>), a.twd, 2, 1); break;
-        case KY_3I: VDWNL_LAUNCH((k_y<double, 1, LC, V>), a.twd, 1, 3); break;
-        case KY_20F: VDWNL_LAUNCH((k_y<T, -1, LC, V>), a.tw, 0, kNQ); break;
-        case KY_20I: VDWNL_LAUNCH((k_y<T, 1, LC, V>), a.tw, 0, kNQ); break;
-        case KY_3F: VDWNL_LAUNCH((k_y<T, -1, LC, V>), a.tw, 1, 3); break;
-        case KY_1I: VDWNL_LAUNCH((k_y<T, 1, LC, V>), a.tw, 2, 1); break;
+        case KG_Y: VDWNL_LAUNCH((k_dcol<T, double, LC, V, 0, 2>), a.twd); break;
+        case KD_Y: VDWNL_LAUNCH((k_dcol<T, T, LC, V, 1, 2>), a.tw); break;
+        case KY_20F: VDWNL_LAUNCH((k_y<T, -1, LC, V>), a.tw); break;
+        case KY_20I: VDWNL_LAUNCH((k_y<T, 1, LC, V>), a.tw); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1349,8 +1277,8 @@ template <typename T, int LC, int V>
 hipError_t launch_z_lc(int kind, const LaunchArgs &a) {
     constexpr bool F32 = sizeof(T) == 4;
     switch (kind) {
-        case KZ_GRAD: VDWNL_LAUNCH((k_z_grad<double, LC, V>), a.twd); break;
-        case KZ_DIV: VDWNL_LAUNCH((k_z_div<T, LC, V>), a.tw); break;
+        case KG_Z: VDWNL_LAUNCH((k_dcol<T, double, LC, V, 0, 1>), a.twd); break;
+        case KD_Z: VDWNL_LAUNCH((k_dcol<T, T, LC, V, 1, 1>), a.tw); break;
         case KZ_MAIN:
             if (a.general) VDWNL_LAUNCH((k_z_main<T, LC, V, true, 0, false>), a.cols, a.tw);
             else if (F32 && a.mfma) VDWNL_LAUNCH((k_z_main<T, LC, V, false, 0, F32>), a.cols, a.tw);

@@ -54,11 +54,11 @@ hipError_t launch_kind(int kind, int lc, int precision, const LaunchArgs &a) {
     switch (kind) {
         case KF_GRAD: case KF_DIV: case KP_THETA:
             return dp ? launch_plain<double>(kind, a) : launch_plain<float>(kind, a);
-        case KX_NFWD: case KX_GRAD: case KX_THETA: case KX_ASSEMBLE: case KX_ASSEMBLE_FD: case KX_FINAL: case KP_U:
+        case KG_X: case KD_X: case KX_THETA: case KX_ASSEMBLE: case KP_U:
             return dp ? launch_x_f64(kind, lc, a.var, a) : launch_x_f32(kind, lc, a.var, a);
-        case KY_1F: case KY_3I: case KY_20F: case KY_20I: case KY_3F: case KY_1I:
+        case KG_Y: case KD_Y: case KY_20F: case KY_20I:
             return dp ? launch_y_f64(kind, lc, a.var, a) : launch_y_f32(kind, lc, a.var, a);
-        case KZ_GRAD: case KZ_DIV: case KZ_MAIN: case KP_THETA_K: case KP_U_K:
+        case KG_Z: case KD_Z: case KZ_MAIN: case KP_THETA_K: case KP_U_K:
             return dp ? launch_z_f64(kind, lc, a.var, a) : launch_z_f32(kind, lc, a.var, a);
         default: return hipErrorInvalidValue;
     }

@@ -201,14 +201,14 @@ def test_pass_lists_and_tiling_on_host():
     names = [lib.vdwnl_pass_name(i).decode() for i in range(40)]
     assert "z_main" in names and "x_theta" in names and "fd_grad" in names
     assert lib.vdwnl_pass_name(-1) == b"" and lib.vdwnl_pass_name(1000) == b""
-    for gm, n_pass in ((0, 14), (3, 7)):
+    for gm, n_pass in ((0, 11), (3, 7)):
         assert _set_grid(lib, h, (24, 24, 24), gm=gm) == 0
         kinds = (i32 * 32)()
         n = lib.vdwnl_pass_order(h, 32, kinds)
         assert n == n_pass
         order = [names[kinds[i]] for i in range(n)]
-        assert order[0] == ("x_nfwd" if gm == 0 else "fd_grad")
-        assert "z_main" in order and order[-1] == ("x_final" if gm == 0 else "fd_div")
+        assert order[0] == ("x_deriv" if gm == 0 else "fd_grad")
+        assert "z_main" in order and order[-1] == ("z_div" if gm == 0 else "fd_div")
     b = (ctypes.c_int64 * 5)(32768, 32768, 16384, 49152, 24576)
     assert lib.vdwnl_set_tiling(h, 5, b) == 0
     out = (ctypes.c_int64 * 8)()

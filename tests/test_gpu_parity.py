@@ -45,10 +45,16 @@ def gpu_eval(n, cell, table, precision, debug=False):
     ek, de, v = eng.energy_potential(nt)
     out = dict(E_k=ek, dE=de, v=v.double().cpu().numpy())
     if debug:
-        g = torch.empty((3,) + n.shape, dtype=dt, device="cuda")
-        eng.lib.debug_field(0, 0, g.data_ptr())
+        from paper_0812_0244_amd.binding import STAGE_GRAD
+        # after the evaluation: the lattice components q_c of w, and v_loc;
+        # then the gradient passes again for grad n itself
+        q = torch.empty((3,) + n.shape, dtype=dt, device="cuda")
+        eng.lib.debug_field(0, 0, q.data_ptr())
         vl = torch.empty(n.shape, dtype=dt, device="cuda")
         eng.lib.debug_field(0, 1, vl.data_ptr())
+        g = torch.empty((3,) + n.shape, dtype=dt, device="cuda")
+        eng.lib.debug_stage(0, STAGE_GRAD, g.data_ptr())
+        out["q"] = q.double().cpu().numpy()
         out["grad"] = g.double().cpu().numpy()
         out["v_loc"] = vl.double().cpu().numpy()
     return out
@@ -76,6 +82,9 @@ def test_c1_fp64_parity_with_intermediates(table):
     g = gpu_eval(n, wl.cell, table, 64, debug=True)
     np.testing.assert_allclose(g["grad"], o["grad"], rtol=0, atol=1e-12 * np.abs(o["grad"]).max())
     np.testing.assert_allclose(g["v_loc"], o["v_loc"], rtol=0, atol=1e-10 * np.abs(o["v_loc"]).max())
+    # the divergence passes' input: q_c = sum_x W[c][x] w_x of the vector field of Eq. (Vi)
+    q = np.einsum("cx,x...->c...", F.fd_metric(n.shape, wl.cell), o["w"])
+    np.testing.assert_allclose(g["q"], q, rtol=0, atol=1e-10 * np.abs(q).max())
     check(g, o, 64)
 
 
@@ -96,6 +105,8 @@ def test_c1_fp32_parity(table):
     ((32, 16, 48), (6.0, 3.0, 9.0), 5),
     ((40, 36, 50), (9.0, 8.0, 10.0), 9),
     ((6, 8, 10), (3.0, 4.0, 5.0), 2),
+    ((16, 20, 15), (7.0, 8.0, 6.0), 4),       # odd N3: rows of odd length, odd i3 runs
+    ((10, 12, 25), (5.0, 6.0, 9.0), 3),
 ])
 def test_fp64_parity_ragged_shapes(table, shape, cell, natoms):
     rng = np.random.default_rng(sum(shape))

@@ -176,7 +176,36 @@ def test_stage_probe_errors(table):
     n = torch.full((12, 12, 12), 0.01, dtype=torch.float64, device="cuda")
     v = torch.empty_like(n)
     lib.energy_potential(n.data_ptr(), v.data_ptr())
-    for inst, stage, code in [(1, 0, -6), (-1, 0, -6), (0, 4, -1), (0, -1, -1)]:
+    for inst, stage, code in [(1, 0, -6), (-1, 0, -6), (0, 5, -1), (0, -1, -1)]:
         with pytest.raises(VdwNlError) as ex:
             lib.debug_stage(inst, stage, buf.data_ptr())
         assert ex.value.code == code
+
+
+@pytest.mark.parametrize("shape,cell,m", [((20, 18, 24), (9.0, 8.0, 10.0), 0), ((16, 20, 15), (7.0, 8.0, 6.0), 0),
+                                          ((12, 10, 9), (6.0, 5.0, 4.5), 0), ((16, 20, 15), (7.0, 8.0, 6.0), 2)])
+def test_gradient_stage_against_oracle(table, shape, cell, m):
+    """grad n as the theta pass takes it: the spectral gradient (one-axis
+    passes along the three grid axes, each multiplier i 2 pi m_c / N_c with
+    the Nyquist index zero) or the central differences of order 2m, against
+    the oracle's 3-D spectral gradient or its stencils; FP64 to 1e-12 of
+    max |grad n|, FP32 (same rounded input) to 1e-6."""
+    from paper_0812_0244_amd import VdwNl
+    from paper_0812_0244_amd.binding import STAGE_GRAD
+    rng = np.random.default_rng(sum(shape) + m)
+    n = W.density_on_grid(shape, cell, W.random_atoms(rng, 5, cell))
+    for prec in (64, 32):
+        dt = torch.float64 if prec == 64 else torch.float32
+        nin = n if prec == 64 else n.astype(np.float32).astype(np.float64)
+        ref = F.gradient(nin, cell) if m == 0 else F.gradient_fd(nin, cell, m)
+        lib = VdwNl(0)
+        lib.set_grid(shape, cell, m, prec)
+        lib.set_kernel_table(table["qmesh"], table["qc"], 12, table["dk"], table["phi"], table["c_soft"])
+        nt = torch.from_numpy(nin).to("cuda", dt)
+        v = torch.empty_like(nt)
+        lib.energy_potential(nt.data_ptr(), v.data_ptr())
+        g = torch.empty((3,) + shape, dtype=dt, device="cuda")
+        lib.debug_stage(0, STAGE_GRAD, g.data_ptr())
+        err = np.abs(g.double().cpu().numpy() - ref).max() / np.abs(ref).max()
+        say("  %s m=%d FP%d: max |d grad| / max |grad| = %.2e" % (shape, m, prec, err))
+        assert err <= (1e-12 if prec == 64 else 1e-6)
