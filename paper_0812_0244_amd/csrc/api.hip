@@ -442,11 +442,15 @@ static void size_tiles(const vdwnl_ctx *c, Grid &g) {
     if (g.wy20 > 1) g.wy20 &= ~1;   // even widths: 16-byte aligned FP32 rows
     // derivative tiles along axes 2 and 1: i3 columns in pairs (one FP64
     // line each), within the group's budget
+    // (a width short of the whole row: a multiple of 32 once it reaches 32,
+    // so that the runs of i3 start and end on 128-byte boundaries)
     auto dwidth = [&](size_t L, size_t budget) {
         int w = 2;
         while ((size_t)(w + 2) <= N3 && (size_t)(w / 2 + 1) * L <= cap(L) && deriv_lds(L, w / 2 + 1, 16) <= budget)
             w += 2;
-        return std::min<int>(w, (int)N3);
+        w = std::min<int>(w, (int)N3);
+        if (w < (int)N3 && w >= 32) w &= ~31;
+        return w;
     };
     g.wdy = dwidth(N2, c->pref[TG_YAUX]);
     g.wdz = dwidth(N1, c->pref[TG_ZAUX]);
