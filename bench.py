@@ -76,7 +76,8 @@ PEAK_FP32_VALU_TFS = 78.6
 def measured_traffic(kernel, lds_budget_z):
     """HBM bytes per evaluation of `kernel` from the committed counter summary
     (profiles/<kernel>_batched64_fp32.md), if it was taken on the kernel
-    sources as they are now and at the tile budget of this run; else None."""
+    sources and the planner (the tile order sets what stays in L2) as they
+    are now and at the tile budget of this run; else None."""
     import hashlib
     import re
     path = os.path.join(ROOT, "profiles", "%s_batched64_fp32.md" % kernel)
@@ -88,7 +89,7 @@ def measured_traffic(kernel, lds_budget_z):
     rec = json.loads(m.group(1))
     h = hashlib.sha256()
     src = os.path.join(ROOT, "paper_0812_0244_amd", "csrc")
-    for f in ("common.hpp", "fft_lds.hpp", "fft_fast.hpp", "tile_io.hpp", "kernels.hpp"):
+    for f in ("common.hpp", "fft_lds.hpp", "fft_fast.hpp", "tile_io.hpp", "kernels.hpp", "api.hip"):
         h.update(open(os.path.join(src, f), "rb").read())
     if rec.get("kernel_sources_sha256") != h.hexdigest():
         return None
@@ -575,8 +576,8 @@ def main():
             "total_points": total,
             "precision": "theta/u FFTs, contraction and divergence chain FP32; grad n chain and "
                          "reductions FP64",
-            "launch": "one HIP graph per call (14 passes x FFT length classes), tile LDS budgets "
-                      "tuned at setup",
+            "launch": "one HIP graph per call (%d passes, the energy reduction included, x FFT length "
+                      "classes), tile LDS budgets tuned at setup" % len(passes),
             "lds_budgets": tiling,
             "radix_orders": radix,
             "radix_passes": {str(n): [radix_order(n, radix[g]) for g in ("x", "y20", "z")]

@@ -799,7 +799,6 @@ static int build_image(vdwnl_ctx *c, Image &im, bool keep_tables) {
                     }
                 }
             }
-            xcd_blocks(zt);
             slot = 0;
             for (Tile &tl : zt) {
                 tl.slot = slot++;
@@ -867,6 +866,34 @@ static int build_image(vdwnl_ctx *c, Image &im, bool keep_tables) {
             if (it == keys.end()) keys.push_back(key);
         }
         c->ngroups = (int)keys.size();
+    }
+    // The fused axis-1 pass: grids that share a kernel-row table (the same
+    // shape and cell, so the same tiles) take turns, tile j of each such grid
+    // one after another, and the XCD blocks are cut from that order: the rows
+    // one tile loads into its XCD's L2 serve the same tile of the other grids.
+    {
+        std::vector<std::vector<Tile>> per(c->grids.size());
+        for (const Tile &tl : tiles[KZ_MAIN]) per[tl.inst].push_back(tl);
+        std::vector<Tile> out;
+        for (int grp = 0; grp < c->ngroups; ++grp) {
+            std::vector<Tile> mine;
+            std::vector<bool> done(c->grids.size(), false);
+            for (size_t gi = 0; gi < c->grids.size(); ++gi) {
+                if (group_of[gi] != grp || done[gi]) continue;
+                std::vector<size_t> share;
+                for (size_t gj = gi; gj < c->grids.size(); ++gj)
+                    if (group_of[gj] == grp && !done[gj] && c->grids[gj].shell_key == c->grids[gi].shell_key &&
+                        per[gj].size() == per[gi].size()) {
+                        share.push_back(gj);
+                        done[gj] = true;
+                    }
+                for (size_t j = 0; j < per[gi].size(); ++j)
+                    for (size_t gj : share) mine.push_back(per[gj][j]);
+            }
+            xcd_blocks(mine);
+            out.insert(out.end(), mine.begin(), mine.end());
+        }
+        tiles[KZ_MAIN].swap(out);
     }
     std::vector<Tile> all;
     for (int k = 0; k < KIND_COUNT; ++k) {
