@@ -732,13 +732,27 @@ __global__ void __launch_bounds__(kThreads) k_dcol(const InstDev *insts, const T
     C *bc = reinterpret_cast<C *>(buf);                        // (re, im) of element e of line j / 2 at 2 ((j/2) lp + e) + j % 2
     const gptr<const T> f = gld(MODE == 0 ? reinterpret_cast<const T *>(I.n) + base
                                           : reinterpret_cast<const T *>(I.grad) + c * N + base);
-    batched<8>(L * Wc, [&](int idx) {
-        const int e = idx / Wc, j = idx - e * Wc;
-        return (C)f[e * stride + j];
-    }, [&](int idx, C x) {
-        const int e = idx / Wc, j = idx - e * Wc;
-        bc[2 * ((j >> 1) * lp + e) + (j & 1)] = x;
-    });
+    // element e of tile column j at f[e stride + j], flat index e Wc + j
+    // (positions advanced without divisions: Wc is a runtime width); eight
+    // unconditional loads in flight per lane
+    const int total = L * Wc;
+    {
+        RowCursor cur(threadIdx.x, Wc);
+        for (int base = threadIdx.x; base < total; base += 8 * kThreads) {
+            C r[8];
+            int o[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const bool on = base + u * kThreads < total;
+                r[u] = (C)f[on ? cur.l * stride + cur.w : 0];
+                o[u] = on ? 2 * ((cur.w >> 1) * lp + cur.l) + (cur.w & 1) : -1;
+                cur.step();
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (o[u] >= 0) bc[o[u]] = r[u];
+        }
+    }
     if (Wc & 1)
         for (int e = threadIdx.x; e < L; e += kThreads) bc[2 * ((np - 1) * lp + e) + 1] = (C)0;
     load_twiddles<C>(tw, AX == 2 ? I.p2 : I.p1, reinterpret_cast<const C2<C> *>(twv));
@@ -749,8 +763,9 @@ __global__ void __launch_bounds__(kThreads) k_dcol(const InstDev *insts, const T
     T *gbase = reinterpret_cast<T *>(I.grad) + base;
     if constexpr (MODE == 0) {
         const bool combine = AX == 1 && I.general;
-        for (int idx = threadIdx.x; idx < L * Wc; idx += kThreads) {
-            const int e = idx / Wc, j = idx - e * Wc;
+        RowCursor cur(threadIdx.x, Wc);
+        for (int idx = threadIdx.x; idx < total; idx += kThreads, cur.step()) {
+            const int e = cur.l, j = cur.w;
             const size_t o = (size_t)e * stride + j;
             const C d = bc[2 * ((j >> 1) * lp + e) + (j & 1)];
             if (!combine) {
@@ -764,13 +779,22 @@ __global__ void __launch_bounds__(kThreads) k_dcol(const InstDev *insts, const T
         }
     } else {
         const gptr<T> v = gst(reinterpret_cast<T *>(I.v) + base);
-        batched<4>(L * Wc, [&](int idx) {
-            const int e = idx / Wc, j = idx - e * Wc;
-            return v[e * stride + j];
-        }, [&](int idx, T x) {
-            const int e = idx / Wc, j = idx - e * Wc;
-            v[e * stride + j] = x - (T)bc[2 * ((j >> 1) * lp + e) + (j & 1)];
-        });
+        RowCursor cur(threadIdx.x, Wc);
+        for (int b0 = threadIdx.x; b0 < total; b0 += 4 * kThreads) {
+            T r[4];
+            int go[4], lo[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const bool on = b0 + u * kThreads < total;
+                go[u] = on ? cur.l * stride + cur.w : -1;
+                lo[u] = 2 * ((cur.w >> 1) * lp + cur.l) + (cur.w & 1);
+                r[u] = v[on ? go[u] : 0];
+                cur.step();
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (go[u] >= 0) v[go[u]] = r[u] - (T)bc[lo[u]];
+        }
     }
 }
 
