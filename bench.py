@@ -400,7 +400,7 @@ def main():
               "E_sum": float(Exc.sum()), "E_x_sum": float(sl[:, 0].sum()), "E_c_lda_sum": float(sl[:, 1].sum())}
 
     # ---- the same workload with the finite-difference gradient (the paper's
-    # own choice; seven passes instead of fourteen), FP32 batched
+    # own choice; seven passes instead of eleven), FP32 batched
     del lib
     fd = None
     if args.fd_mode > 0:

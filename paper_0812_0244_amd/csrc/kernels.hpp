@@ -1,13 +1,15 @@
 // HIP kernels of libvdwnl (gfx950), as templates in the working precision T;
-// kernels_f32.hip and kernels_f64.hip instantiate them (compiled in parallel).  One evaluation of E_c^nl and v_nl is
-// fourteen passes over the grid with the spectral gradient, seven with finite
-// differences; each pass is one launch that covers every grid of the batch (a
-// workgroup reads its work item from a tile list).
+// kernels_f32_{x,y,z}.hip and kernels_f64_{x,y,z}.hip instantiate them per pass
+// family (compiled in parallel).  One evaluation of E_c^nl and v_nl is eleven
+// passes over the grid with the spectral gradient (its gradient and
+// divergence one pass per grid axis each), seven with finite differences;
+// each pass is one launch per FFT length class that covers every grid of the
+// batch (a workgroup reads its work item from a tile list).
 //
 // The 20 theta / u fields (the bulk of the traffic), the local chain and the
 // divergence of w are computed in the working precision T (float or double).
-// The spectral gradient of n always runs in FP64: the gradient term of v_nl
-// multiplies grad n by a factor that grows as 1/n, so FP32 rounding of a
+// The spectral gradient of n always transforms in FP64: the gradient term of
+// v_nl multiplies grad n by a factor that grows as 1/n, so FP32 rounding of a
 // spectral grad n in the low-density regions would dominate the error of v.
 //
 // Fields are transformed with three 1-D FFT passes: along axis 3 (the
