@@ -58,7 +58,8 @@ struct Shells {
     std::vector<int> map;       // [h1][h2][n3h] (orthorhombic) or [N1][N2][n3h] (general cell)
     std::vector<double> gmod;   // |G| per shell
     double gmax = 0.0;
-    bool general = false;       // table rows packed (upper triangle): one k point per shell
+    bool general = false;       // non-orthogonal cell: one k point per shell
+    bool packed = false;        // table rows as the packed upper triangle (else the full matrix)
 };
 
 static Shells shells_from_keys(const std::vector<double> &key) {
@@ -244,6 +245,7 @@ struct vdwnl_ctx {
         int general;          // grids of the group in non-orthogonal cells
         int mfma;             // (fused axis-1 pass) the contraction on the matrix cores
         int var;              // radix order of the transform (its length class's variant)
+        int packed;           // (general cells) shell tables of packed upper triangles
     };
     // per pass: one launch per group of grids (grids whose three axes fall in
     // the same FFT length classes); the groups' chains of passes are
@@ -621,6 +623,21 @@ static int plan_grids(vdwnl_ctx *c, int nb, const int32_t *shapes, const double 
         }
         g.shell_key = found;
     }
+    // Row layout of each shell table.  Orthorhombic cells: the full matrix
+    // (row a contiguous for the lane that forms u_a).  General cells, where
+    // every k point has a shell of its own: the full matrix too when two or
+    // more grids share the table (a tile's rows, loaded into its XCD's L2,
+    // then serve the same tile of the other grids) or when it fits in the
+    // Infinity Cache; else the packed upper triangle, half the bytes.
+    {
+        const size_t rs = precision == 64 ? 8 : 4;
+        std::vector<int> users(c->shells.size(), 0);
+        for (auto &g : c->grids) ++users[g.shell_key];
+        for (size_t i = 0; i < c->shells.size(); ++i) {
+            Shells &sh = c->shells[i];
+            sh.packed = sh.general && users[i] < 2 && sh.gmod.size() * kTabRow * rs > kFullRowCacheBytes;
+        }
+    }
     c->have_grid = true;
     const int rc = check_krange(c);
     refresh_image(c);
@@ -628,12 +645,10 @@ static int plan_grids(vdwnl_ctx *c, int nb, const int32_t *shapes, const double 
 }
 
 // spline of the radial table at |G| for every pair: phi_ab(|G_s|), FP64,
-// stored as the full symmetric matrix of each shell (orthorhombic cells: a
-// shell serves up to four k points) or as its packed upper triangle, pair
-// p = (r, q), r <= q, in row order (general cells: a shell per k point, so
-// the rows' bytes dominate the fused pass)
+// stored as the full symmetric matrix of each shell or as its packed upper
+// triangle, pair p = (r, q), r <= q, in row order (Shells::packed)
 static void shell_table(const vdwnl_ctx *c, const Shells &sh, std::vector<double> &out) {
-    const size_t row = sh.general ? kTabPacked : kTabRow;
+    const size_t row = sh.packed ? kTabPacked : kTabRow;
     out.assign(sh.gmod.size() * row, 0.0);
     for (size_t s = 0; s < sh.gmod.size(); ++s) {
         const double k = sh.gmod[s];
@@ -648,7 +663,7 @@ static void shell_table(const vdwnl_ctx *c, const Shells &sh, std::vector<double
                 const double *f = c->phi.data() + (size_t)p * c->nk;
                 const double *m = c->d2.data() + (size_t)p * c->nk;
                 const double v = a * f[j] + b * f[j + 1] + ((a * a * a - a) * m[j] + (b * b * b - b) * m[j + 1]) * w;
-                if (sh.general) {
+                if (sh.packed) {
                     out[s * row + p] = v;
                 } else {
                     out[s * row + r * kNQ + q] = v;
@@ -729,7 +744,7 @@ static int build_image(vdwnl_ctx *c, Image &im, bool keep_tables) {
         c->map_off[i] = off;
         off = align_up(off + c->shells[i].map.size() * sizeof(int));
         c->tab_off[i] = off;
-        off = align_up(off + c->shells[i].gmod.size() * (c->shells[i].general ? kTabPacked : kTabRow) * rs);
+        off = align_up(off + c->shells[i].gmod.size() * (c->shells[i].packed ? kTabPacked : kTabRow) * rs);
     }
     std::vector<Tile> tiles[KIND_COUNT];
     std::vector<int2> zcols;              // columns of the fused axis-1 tiles
@@ -858,9 +873,10 @@ static int build_image(vdwnl_ctx *c, Image &im, bool keep_tables) {
         std::vector<int> keys;
         for (size_t gi = 0; gi < c->grids.size(); ++gi) {
             const Grid &g = c->grids[gi];
-            // (and the cell kind: general cells take the fused pass's packed-row variant)
+            // (and the cell kind and kernel-row layout: general cells take the
+            // fused pass's general variant, full or packed rows)
             const int key = ((len_class(g.s[0]) * kNumLenClasses + len_class(g.s[1])) * kNumLenClasses +
-                             len_class(g.s[2])) * 2 + (g.general ? 1 : 0);
+                             len_class(g.s[2])) * 4 + (g.general ? 1 : 0) + (c->shells[g.shell_key].packed ? 2 : 0);
             auto it = std::find(keys.begin(), keys.end(), key);
             group_of[gi] = (int)(it - keys.begin());
             if (it == keys.end()) keys.push_back(key);
@@ -899,11 +915,12 @@ static int build_image(vdwnl_ctx *c, Image &im, bool keep_tables) {
     for (int k = 0; k < KIND_COUNT; ++k) {
         c->launches[k].clear();
         for (int grp = 0; grp < c->ngroups; ++grp) {
-            vdwnl_ctx::Launch L{k, 0, (int)all.size(), 0, 0, grp, 0, 0, 0};
+            vdwnl_ctx::Launch L{k, 0, (int)all.size(), 0, 0, grp, 0, 0, 0, 0};
             for (const Tile &tl : tiles[k]) {
                 if (group_of[tl.inst] != grp) continue;
                 const Grid &g = c->grids[tl.inst];
                 L.general = g.general ? 1 : 0;
+                L.packed = c->shells[g.shell_key].packed ? 1 : 0;
                 L.mfma = (k == KZ_MAIN && c->precision == 32 && !g.general && c->contraction == VDWNL_CONTRACTION_MATRIX)
                              ? 1 : 0;
                 // the stencil passes transform nothing (class 0 for any grid)
@@ -974,7 +991,7 @@ static int lds_optin(vdwnl_ctx *c) {
     hipError_t e;
     for (int k = 0; k < KIND_COUNT; ++k)
         for (const auto &L : c->launches[k]) {
-            LaunchArgs a{nullptr, nullptr, 0, L.lds, nullptr, nullptr, nullptr, nullptr, nullptr, L.general, L.mfma, L.var};
+            LaunchArgs a{nullptr, nullptr, 0, L.lds, nullptr, nullptr, nullptr, nullptr, nullptr, L.general, L.mfma, L.var, L.packed};
             if ((e = launch_kind(k, L.lc, c->precision, a)) != hipSuccess) return hipfail(c, e, "kernel LDS limit");
             // (and the stage probes that stand in for the pass)
             for (int pr : {PROBE_THETA_K, PROBE_U_K, PROBE_U}) {
@@ -1155,7 +1172,7 @@ static int enqueue(vdwnl_ctx *c, const DevPtrs &P, const InstDev *hinst, double 
     const int *order;
     const int npass = pass_order(c->grad_mode, &order);
     auto launch = [&](const vdwnl_ctx::Launch &L, hipStream_t s) -> int {
-        LaunchArgs a{P.inst, P.tiles + L.off, L.cnt, L.lds, P.consts, P.tw, P.twd, s, P.cols, L.general, L.mfma, L.var};
+        LaunchArgs a{P.inst, P.tiles + L.off, L.cnt, L.lds, P.consts, P.tw, P.twd, s, P.cols, L.general, L.mfma, L.var, L.packed};
         const hipError_t le = launch_kind(L.kind, L.lc, c->precision, a);
         return le == hipSuccess ? VDWNL_OK : hipfail(c, le, "kernel launch");
     };
@@ -1321,7 +1338,7 @@ static int probe_stage(vdwnl_ctx *c, int stage, int target, void *dst, hipStream
     }
     auto args = [&](const vdwnl_ctx::Launch &L) {
         return LaunchArgs{c->dp.inst, c->dp.tiles + L.off, L.cnt, L.lds, c->dp.consts, c->dp.tw, c->dp.twd, st, c->dp.cols,
-                          L.general, L.mfma, L.var};
+                          L.general, L.mfma, L.var, L.packed};
     };
     for (int i = 0; i < npass && order[i] != stop; ++i)
         for (const auto &L : c->launches[order[i]])

@@ -10,7 +10,8 @@ namespace vdwnl {
 constexpr int kNQ = 20;                          // interpolation points q_a (compile-time)
 constexpr int kNPair = kNQ * (kNQ + 1) / 2;      // distinct phi_ab (a <= b) per |G| shell
 constexpr int kTabRow = kNQ * kNQ;               // shell table entries per shell (full matrix)
-constexpr int kTabPacked = kNQ * (kNQ + 1) / 2;  // the same, packed upper triangle (general cells)
+constexpr int kTabPacked = kNQ * (kNQ + 1) / 2;  // the same, packed upper triangle (some general-cell tables)
+constexpr size_t kFullRowCacheBytes = (size_t)256 << 20;   // a general-cell table this small keeps full rows
 constexpr int kThreads = 256;                    // threads per workgroup, every kernel
 constexpr int kTileCap = 4096;                   // complex elements of one LDS FFT tile
 constexpr int kLdsCap = 65536;                   // bytes of LDS one workgroup may take
@@ -40,7 +41,8 @@ struct FftPlan {
 //   shellmap        [N1/2+1][N2/2+1][N3h] int   (|G| shell of (|m1|, |m2|, m3)); in a
 //                   general (non-orthogonal) cell [N1][N2][N3h] over the whole half spectrum
 //   shelltab        [nshell][kNQ][kNQ] real     (phi_ab(|G_s|), the full symmetric matrix:
-//                   row a of a shell is contiguous for the lane that forms u_a)
+//                   row a of a shell is contiguous for the lane that forms u_a), or
+//                   [nshell][kNQ (kNQ + 1) / 2] (packed upper triangle; some general-cell tables)
 struct InstDev {
     int n1, n2, n3, n3h, h1, h2;
     FftPlan p1, p2, p3;
@@ -119,6 +121,7 @@ struct LaunchArgs {
     int general;             // the launch's grids have non-orthogonal cells (packed shell rows)
     int mfma = 0;            // FP32 orthorhombic fused axis-1 pass: contraction on the matrix cores
     int var = 0;             // radix order of the pass's transform length (0 .. its variants - 1)
+    int packed = 0;          // (general cells) the launch's shell tables hold packed upper triangles
     void *dst = nullptr;     // (stage probes) the probe's output
     int target = 0;          // (stage probes) the grid whose tiles run
 };

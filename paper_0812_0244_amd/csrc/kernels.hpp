@@ -837,15 +837,16 @@ __global__ void __launch_bounds__(kThreads) k_y(const InstDev *insts, const Tile
 // forms u_a at the pair's points (+-m1 of each column).  The rows of the
 // group's next item are loaded meanwhile (two register sets in turn).
 // GEN (grids in non-orthogonal cells): every item is one k point with its
-// own shell, whose table holds the packed upper triangle; lane a gathers its
-// row from it through offsets fixed per lane.
+// own shell; lane a loads row a of its full matrix, or (PK: the launch's
+// tables hold packed upper triangles) gathers the row from it through
+// offsets fixed per lane.
 // PROBE (parity probes of the stages, never in an evaluation): 1 writes the
 // forward spectra c = FFT(theta)/N back in place of the tile (no contraction,
 // no inverse); 2 writes u = phi c (no inverse); 0 is the evaluation.
 // MF (FP32, orthorhombic cells): the contraction on the matrix cores (see the
 // item loop below) instead of the vector ALU; the same items, the same
 // results up to the order of the FP32 additions.
-template <typename T, int LC, int V, bool GEN, int PROBE, bool MF>
+template <typename T, int LC, int V, bool GEN, int PROBE, bool MF, bool PK>
 __global__ void __launch_bounds__(kThreads) k_z_main(const InstDev *insts, const Tile *tiles, const int2 *cols,
                                                      const void *twv) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -962,8 +963,8 @@ __global__ void __launch_bounds__(kThreads) k_z_main(const InstDev *insts, const
     if ((int)threadIdx.x < nitems) sidx[threadIdx.x] = sh_first;
     for (int i = threadIdx.x + kThreads; i < nitems; i += kThreads) sidx[i] = smap_at(i);
     // (packed rows: entry (r, q), r <= q, at r kNQ - r (r - 1)/2 + q - r)
-    int poff[GEN ? kNQ : 1];
-    if constexpr (GEN) {
+    int poff[GEN && PK ? kNQ : 1];
+    if constexpr (GEN && PK) {
 #pragma unroll
         for (int b = 0; b < kNQ; ++b) {
             const int r = min(al, b), q = max(al, b);
@@ -982,7 +983,7 @@ __global__ void __launch_bounds__(kThreads) k_z_main(const InstDev *insts, const
     // item: the loads stay unconditional)
     auto fetch = [&](int item, T *f) {
         const int sh = sidx[min(item, nitems - 1)];
-        if constexpr (GEN) {
+        if constexpr (GEN && PK) {
             const gptr<const T> src = gld(tab + (size_t)sh * kTabPacked);
 #pragma unroll
             for (int b = 0; b < kNQ; ++b) f[b] = src[poff[b]];
@@ -1306,18 +1307,21 @@ hipError_t launch_z_lc(int kind, const LaunchArgs &a) {
         case KG_Z: VDWNL_LAUNCH((k_dcol<T, double, LC, V, 0, 1>), a.twd); break;
         case KD_Z: VDWNL_LAUNCH((k_dcol<T, T, LC, V, 1, 1>), a.tw); break;
         case KZ_MAIN:
-            if (a.general) VDWNL_LAUNCH((k_z_main<T, LC, V, true, 0, false>), a.cols, a.tw);
-            else if (F32 && a.mfma) VDWNL_LAUNCH((k_z_main<T, LC, V, false, 0, F32>), a.cols, a.tw);
-            else VDWNL_LAUNCH((k_z_main<T, LC, V, false, 0, false>), a.cols, a.tw);
+            if (a.general && a.packed) VDWNL_LAUNCH((k_z_main<T, LC, V, true, 0, false, true>), a.cols, a.tw);
+            else if (a.general) VDWNL_LAUNCH((k_z_main<T, LC, V, true, 0, false, false>), a.cols, a.tw);
+            else if (F32 && a.mfma) VDWNL_LAUNCH((k_z_main<T, LC, V, false, 0, F32, false>), a.cols, a.tw);
+            else VDWNL_LAUNCH((k_z_main<T, LC, V, false, 0, false, false>), a.cols, a.tw);
             break;
         case KP_THETA_K:
-            if (a.general) VDWNL_LAUNCH((k_z_main<T, LC, V, true, 1, false>), a.cols, a.tw);
-            else VDWNL_LAUNCH((k_z_main<T, LC, V, false, 1, false>), a.cols, a.tw);
+            // (the forward spectra alone: no kernel rows read)
+            if (a.general) VDWNL_LAUNCH((k_z_main<T, LC, V, true, 1, false, false>), a.cols, a.tw);
+            else VDWNL_LAUNCH((k_z_main<T, LC, V, false, 1, false, false>), a.cols, a.tw);
             break;
         case KP_U_K:
-            if (a.general) VDWNL_LAUNCH((k_z_main<T, LC, V, true, 2, false>), a.cols, a.tw);
-            else if (F32 && a.mfma) VDWNL_LAUNCH((k_z_main<T, LC, V, false, 2, F32>), a.cols, a.tw);
-            else VDWNL_LAUNCH((k_z_main<T, LC, V, false, 2, false>), a.cols, a.tw);
+            if (a.general && a.packed) VDWNL_LAUNCH((k_z_main<T, LC, V, true, 2, false, true>), a.cols, a.tw);
+            else if (a.general) VDWNL_LAUNCH((k_z_main<T, LC, V, true, 2, false, false>), a.cols, a.tw);
+            else if (F32 && a.mfma) VDWNL_LAUNCH((k_z_main<T, LC, V, false, 2, F32, false>), a.cols, a.tw);
+            else VDWNL_LAUNCH((k_z_main<T, LC, V, false, 2, false, false>), a.cols, a.tw);
             break;
         default: return hipErrorInvalidValue;
     }
