@@ -149,8 +149,10 @@ int vdwnl_energy_potential(vdwnl_ctx *ctx, const void *n_dev, void *v_dev, doubl
  * on (each held from the library's first use of that GPU until the process
  * ends; its address is taken when a context is created).  A plan fits when
  * its whole image does: about 64^3 points in FP32 or 48^3 in FP64 for cubic
- * grids; larger plans return VDWNL_E_UNSUPPORTED_SIZE with the bytes they
- * need in vdwnl_last_error.  Every call on a GPU shares that GPU's buffer and
+ * grids in orthorhombic cells, about 48^3 in FP32 in general cells (whose
+ * kernel rows, one set per k point, are then kept as packed upper
+ * triangles); larger plans return VDWNL_E_UNSUPPORTED_SIZE with the bytes
+ * they need in vdwnl_last_error.  Every call on a GPU shares that GPU's buffer and
  * it keeps the last call's contents: nothing in it must start at zero (each
  * evaluation writes every value before reading it), the tables of the plan
  * are copied in when the buffer holds another plan's, and calls that overlap

@@ -1425,6 +1425,22 @@ static void refresh_image(vdwnl_ctx *c) {
         if (sh.gmax > (c->nk - 1) * c->dk * (1.0 + 1e-12)) return;
     Image probe;
     if (build_image(c, probe, false) != VDWNL_OK) return;
+    // a lone grid in a general cell whose full kernel matrices keep the
+    // image beyond the scratch array: its table packed (half the row
+    // bytes) when that fits, for both entry points
+    if (probe.total > kScratchBytes && c->grids.size() == 1) {
+        Shells &sh = c->shells[c->grids[0].shell_key];
+        if (sh.general && !sh.packed) {
+            sh.packed = true;
+            Image packed;
+            if (build_image(c, packed, false) == VDWNL_OK && packed.total <= kScratchBytes) {
+                probe = packed;
+            } else {
+                sh.packed = false;
+                if (build_image(c, probe, false) != VDWNL_OK) return;
+            }
+        }
+    }
     c->img_need = probe.total;
     if (probe.total > kScratchBytes) return;
     if (build_image(c, c->img, true) != VDWNL_OK) return;

@@ -79,6 +79,19 @@ def test_noalloc_finite_differences_and_triclinic(table):
     _check(*_both(_context(shape, lat, table, 64), torch.from_numpy(d).cuda()), "triclinic 20x18x24")
 
 
+def test_noalloc_triclinic_packs_rows_to_fit(table):
+    """A lone grid in a general cell whose full-matrix kernel rows would not
+    fit the scratch array (48 x 45 x 45 FP32, edges 14.4, 14.2, 12.6 bohr,
+    angles 78, 104, 66 degrees: about 48,600 shells, 74 MiB as full
+    matrices, 39 MiB packed) keeps packed rows: the no-allocation call runs
+    it and equals the allocating call bitwise."""
+    shape = (48, 45, 45)
+    lat = W.triclinic_lattice((14.4, 14.2, 12.6), (78.0, 104.0, 66.0))
+    d = W.density_on_lattice(shape, lat, W.random_atoms_lattice(np.random.default_rng(7), 5, lat))
+    n = torch.from_numpy(d.astype(np.float32)).cuda()
+    _check(*_both(_context(shape, lat, table, 32), n), "triclinic 48x45x45 FP32")
+
+
 def test_noalloc_allocates_no_device_memory(table):
     wl = W.config(1)
     n = torch.from_numpy(wl.density()).cuda()
