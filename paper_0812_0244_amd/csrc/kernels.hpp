@@ -863,7 +863,7 @@ __global__ void __launch_bounds__(kThreads) k_z_main(const InstDev *insts, const
     int *sidx = reinterpret_cast<int *>(buf + W * lp);        // shell of every item
     {
         const int2 cw = cols[t.a + min((int)threadIdx.x, K - 1)];   // unconditional (clamped) load
-        if (threadIdx.x < K) colbase[threadIdx.x] = (cw.x * N3h + cw.y) * kNQ;
+        if ((int)threadIdx.x < K) colbase[threadIdx.x] = (cw.x * N3h + cw.y) * kNQ;
     }
     const int2 c0 = cols[t.a];
     __syncthreads();
