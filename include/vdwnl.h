@@ -75,8 +75,10 @@ const char *vdwnl_last_error(const vdwnl_ctx *ctx);
  *              divergence.  An edge shorter than 2m + 1 folds coinciding
  *              neighbours' weights together.
  *   precision  32 or 64
- * Device workspace is allocated at the first evaluation after planning;
- * later evaluations allocate nothing.  Tile shapes follow one LDS budget per
+ * Device workspace is allocated at the first evaluation after planning
+ * (one allocation, kept across later plans of the context while it is large
+ * enough, freed by vdwnl_destroy); later evaluations allocate nothing.  Tile
+ * shapes follow one LDS budget per
  * pass group: a budget set tuned by vdwnl_autotune for the same grid list,
  * precision, gradient mode and device architecture is reused (from this
  * process, or from the tuning file of an earlier one; see vdwnl_autotune),
@@ -287,10 +289,11 @@ int vdwnl_set_graph(vdwnl_ctx *ctx, int32_t on);
 /* Schedule tuning for the planned grids: evaluates the batch (n_ptrs[nb],
  * v_ptrs[nb] as for vdwnl_energy_potential_batched; v is overwritten) once
  * plus `reps` timed times (1..100) for each candidate LDS budget (and, for
- * FP32 orthorhombic grids, each contraction unit), picks per pass group the
- * budget (and unit) with the least time over the group's passes, then times
- * the radix orders 0..5 with those and picks one per group the same way,
- * plans with the choices and remembers them, keyed by the device
+ * FP32 orthorhombic grids, each contraction unit) at radix order 0, keeps
+ * the unit of the fused axis-1 pass with the least time over that pass, then
+ * times every candidate budget at the radix orders 1..5 with that unit and
+ * picks per pass group the (budget, order) pair with the least time over the
+ * group's passes, plans with the choices and remembers them, keyed by the device
  * architecture, its LDS size,
  * the precision, the gradient mode and the exact grid list: for the rest of
  * the process, and in the tuning file for later processes.  The file is a

@@ -226,6 +226,7 @@ struct vdwnl_ctx {
     bool evaluated = false;               // an evaluation has run on the current workspace
     void *work = nullptr;
     size_t work_bytes = 0;
+    size_t work_cap = 0;                  // bytes of the allocation at work (kept across re-plans)
     std::vector<size_t> tab_off;          // per shells entry: offset of map and table
     std::vector<size_t> map_off;
     DevPtrs dp;                           // the image in the context's own buffer (work)
@@ -311,7 +312,13 @@ static void drop_graph(vdwnl_ctx *c) {
     c->graph = nullptr;
 }
 
-static void free_device(vdwnl_ctx *c) {
+// Drop the device state of the plan.  The workspace allocation itself is
+// kept for the next plan (re-allocated only when a plan needs more) and
+// released with release_work (context destruction): device memory freed
+// while the context still held captured graphs was not returned to the
+// device on this runtime (each re-plan with graph replay lost one
+// workspace; only the last free, at destruction, came back).
+static void free_device(vdwnl_ctx *c, bool release_work = false) {
     if (c->device >= 0) (void)hipSetDevice(c->device);
     (void)wait_pending(c);
     c->last_functional = -1;
@@ -329,10 +336,14 @@ static void free_device(vdwnl_ctx *c) {
         for (auto &e : c->ev) (void)hipEventDestroy(e);
         c->ev_made = false;
     }
-    if (c->work) (void)hipFree(c->work);
+    if (release_work && c->work) {
+        (void)hipFree(c->work);
+        c->work = nullptr;
+        c->work_cap = 0;
+    }
     if (c->h_inst) (void)hipHostFree(c->h_inst);
     if (c->h_E) (void)hipHostFree(c->h_E);
-    c->work = nullptr; c->h_inst = nullptr; c->h_E = nullptr;
+    c->h_inst = nullptr; c->h_E = nullptr;
     c->dp = DevPtrs();
     c->work_bytes = 0;
     c->device_ready = false;
@@ -1135,9 +1146,18 @@ static int prepare_device(vdwnl_ctx *c) {
     if (rc != VDWNL_OK) return rc;
     const size_t ng = c->grids.size();
     c->work_bytes = im->total;
-    if ((e = hipMalloc(&c->work, std::max<size_t>(im->total, 256))) != hipSuccess) {
+    const size_t need = std::max<size_t>(im->total, 256);
+    if (c->work && c->work_cap < need) {
+        (void)hipFree(c->work);
         c->work = nullptr;
-        return hipfail(c, e, "hipMalloc workspace");
+        c->work_cap = 0;
+    }
+    if (!c->work) {
+        if ((e = hipMalloc(&c->work, need)) != hipSuccess) {
+            c->work = nullptr;
+            return hipfail(c, e, "hipMalloc workspace");
+        }
+        c->work_cap = need;
     }
     if ((e = hipHostMalloc((void **)&c->h_inst, ng * sizeof(InstDev), hipHostMallocDefault)) != hipSuccess) {
         c->h_inst = nullptr;
@@ -1567,7 +1587,7 @@ int vdwnl_create(vdwnl_ctx **out, int device) {
 
 int vdwnl_destroy(vdwnl_ctx *ctx) {
     if (!ctx) return VDWNL_E_ARG;
-    free_device(ctx);
+    free_device(ctx, true);
     delete ctx;
     return VDWNL_OK;
 }
@@ -1830,32 +1850,50 @@ int vdwnl_autotune(vdwnl_ctx *ctx, int32_t nb, const void *const *n_ptrs, void *
     }
     ctx->contraction = best_unit;
     for (int gi = 0; gi < TG_COUNT; ++gi) ctx->pref[gi] = best[gi];
-    // radix orders, with the chosen budgets and unit: every group at order v
-    // (each length class clamps v to its last variant), v = 0 .. kMaxVariants - 1,
-    // and per group the order with the least time over the group's transforms
+    // budgets and radix orders together, with the chosen unit: every group at
+    // budget b and order v (each length class clamps v to its last variant)
+    // for v = 1 .. kMaxVariants - 1 and every candidate b (order 0: the
+    // measurements above), and per group the pair with the least time over
+    // the group's passes (a radix order changes the lanes per line, so the
+    // best tile width can move with it)
     {
-        std::vector<std::vector<double>> tv(kMaxVariants, std::vector<double>(KIND_COUNT, 0.0));
-        for (int v = 0; v < kMaxVariants && rc == VDWNL_OK; ++v) {
-            for (auto &x : ctx->variant) x = v;
-            for (auto &g : ctx->grids) size_tiles(ctx, g);
-            free_device(ctx);
-            ctx->timing = false;
-            rc = run(ctx, nb, n_ptrs, v_ptrs, E.data(), stream);
-            if (rc != VDWNL_OK) break;
-            vdwnl_set_timing(ctx, 1);
-            for (int r = 0; r < reps && rc == VDWNL_OK; ++r) rc = run(ctx, nb, n_ptrs, v_ptrs, E.data(), stream);
-            for (int k = 0; k < KIND_COUNT; ++k) tv[v][k] = ctx->pass_ms[k];
-        }
+        const size_t ub = std::find(units.begin(), units.end(), best_unit) - units.begin();
+        // tv[v][candidate][pass kind]
+        std::vector<std::vector<std::vector<double>>> tv(
+            kMaxVariants, std::vector<std::vector<double>>(cand.size(), std::vector<double>(KIND_COUNT, 0.0)));
+        tv[0] = t[ub];
+        for (int v = 1; v < kMaxVariants && rc == VDWNL_OK; ++v)
+            for (size_t ci = 0; ci < cand.size() && rc == VDWNL_OK; ++ci) {
+                for (auto &x : ctx->variant) x = v;
+                for (auto &p : ctx->pref) p = cand[ci];
+                for (auto &g : ctx->grids) size_tiles(ctx, g);
+                free_device(ctx);
+                ctx->timing = false;
+                rc = run(ctx, nb, n_ptrs, v_ptrs, E.data(), stream);
+                if (rc != VDWNL_OK) break;
+                vdwnl_set_timing(ctx, 1);
+                for (int r = 0; r < reps && rc == VDWNL_OK; ++r) rc = run(ctx, nb, n_ptrs, v_ptrs, E.data(), stream);
+                for (int k = 0; k < KIND_COUNT; ++k) tv[v][ci][k] = ctx->pass_ms[k];
+            }
         for (int gi = 0; gi < TG_COUNT; ++gi) {
             double bt = 1e300;
             int bv = 0;
-            for (int v = 0; rc == VDWNL_OK && v < kMaxVariants; ++v) {
-                double sum = 0.0;
-                for (int k = 0; k < KIND_COUNT; ++k)
-                    if (k != KF_GRAD && k != KF_DIV && variant_group(k) == gi) sum += tv[v][k];
-                if (sum > 0.0 && sum < bt) { bt = sum; bv = v; }
-            }
+            size_t bb = best[gi];
+            for (int v = 0; rc == VDWNL_OK && v < kMaxVariants; ++v)
+                for (size_t ci = 0; ci < cand.size(); ++ci) {
+                    // (every pass whose transforms take the group's order: the
+                    // axis-3 group's FP64 derivative passes too)
+                    double sum = 0.0;
+                    for (int k = 0; k < KIND_COUNT; ++k)
+                        if (k != KF_GRAD && k != KF_DIV && variant_group(k) == gi) sum += tv[v][ci][k];
+                    if (sum > 0.0 && sum < bt) {
+                        bt = sum;
+                        bv = v;
+                        bb = cand[ci];
+                    }
+                }
             ctx->variant[gi] = bv;
+            ctx->pref[gi] = bb;
         }
     }
     for (auto &g : ctx->grids) size_tiles(ctx, g);
