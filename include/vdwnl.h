@@ -76,8 +76,10 @@ const char *vdwnl_last_error(const vdwnl_ctx *ctx);
  *              neighbours' weights together.
  *   precision  32 or 64
  * Device workspace is allocated at the first evaluation after planning
- * (one allocation, kept across later plans of the context while it is large
- * enough, freed by vdwnl_destroy); later evaluations allocate nothing.  Tile
+ * (one block, kept across later plans of the context while it is large
+ * enough; vdwnl_destroy hands it to the library's per-device pool, from
+ * which later contexts take blocks before they allocate, and the pool is
+ * held until the process ends); later evaluations allocate nothing.  Tile
  * shapes follow one LDS budget per
  * pass group: a budget set tuned by vdwnl_autotune for the same grid list,
  * precision, gradient mode and device architecture is reused (from this

@@ -312,12 +312,58 @@ static void drop_graph(vdwnl_ctx *c) {
     c->graph = nullptr;
 }
 
-// Drop the device state of the plan.  The workspace allocation itself is
-// kept for the next plan (re-allocated only when a plan needs more) and
-// released with release_work (context destruction): device memory freed
-// while the context still held captured graphs was not returned to the
-// device on this runtime (each re-plan with graph replay lost one
-// workspace; only the last free, at destruction, came back).
+// Workspace allocations of the process, per device: device memory that the
+// kernels of a captured graph had used was not returned to the device when
+// freed on this runtime (measured: one workspace lost per re-plan or per
+// destroyed context with graph replay), so workspaces are never freed.  A
+// context keeps its allocation across re-plans while it is large enough;
+// a destroyed context (or one that needs a larger block) hands it to this
+// pool, and a context takes the smallest pooled block that is large enough
+// before it allocates.  Memory held: the peak of the workspaces in use at
+// once (plus the blocks' slack).
+struct WorkBlock {
+    int device;
+    void *ptr;
+    size_t bytes;
+};
+static std::mutex g_pool_mu;
+static std::vector<WorkBlock> g_pool;
+
+static void pool_put(int device, void *ptr, size_t bytes) {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    g_pool.push_back({device, ptr, bytes});
+}
+
+// free every pooled block of this device (the allocation's last resort:
+// blocks that no graph used do come back)
+static void pool_release(int device) {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    std::vector<WorkBlock> keep;
+    for (auto &b : g_pool) {
+        if (b.device == device) (void)hipFree(b.ptr);
+        else keep.push_back(b);
+    }
+    g_pool.swap(keep);
+}
+
+// the smallest pooled block of this device with at least `need` bytes, or null
+static void *pool_take(int device, size_t need, size_t *bytes) {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    size_t best = g_pool.size();
+    for (size_t i = 0; i < g_pool.size(); ++i)
+        if (g_pool[i].device == device && g_pool[i].bytes >= need &&
+            (best == g_pool.size() || g_pool[i].bytes < g_pool[best].bytes))
+            best = i;
+    if (best == g_pool.size()) return nullptr;
+    void *p = g_pool[best].ptr;
+    *bytes = g_pool[best].bytes;
+    g_pool.erase(g_pool.begin() + (long)best);
+    return p;
+}
+
+// Drop the device state of the plan.  The workspace allocation is kept for
+// the next plan of the context; release_work (context destruction) hands it
+// to the process's pool.
 static void free_device(vdwnl_ctx *c, bool release_work = false) {
     if (c->device >= 0) (void)hipSetDevice(c->device);
     (void)wait_pending(c);
@@ -337,7 +383,7 @@ static void free_device(vdwnl_ctx *c, bool release_work = false) {
         c->ev_made = false;
     }
     if (release_work && c->work) {
-        (void)hipFree(c->work);
+        pool_put(c->device, c->work, c->work_cap);
         c->work = nullptr;
         c->work_cap = 0;
     }
@@ -1146,18 +1192,30 @@ static int prepare_device(vdwnl_ctx *c) {
     if (rc != VDWNL_OK) return rc;
     const size_t ng = c->grids.size();
     c->work_bytes = im->total;
-    const size_t need = std::max<size_t>(im->total, 256);
+    // (blocks rounded up, 4 MiB or 64 MiB above 512 MiB, so that plans that
+    // differ a little, such as tuning candidates, fit the same block)
+    const size_t gran = im->total > ((size_t)512 << 20) ? ((size_t)64 << 20) : ((size_t)4 << 20);
+    const size_t need = (std::max<size_t>(im->total, 256) + gran - 1) / gran * gran;
     if (c->work && c->work_cap < need) {
-        (void)hipFree(c->work);
+        pool_put(c->device, c->work, c->work_cap);
         c->work = nullptr;
         c->work_cap = 0;
     }
     if (!c->work) {
-        if ((e = hipMalloc(&c->work, need)) != hipSuccess) {
-            c->work = nullptr;
-            return hipfail(c, e, "hipMalloc workspace");
+        size_t got = 0;
+        if ((c->work = pool_take(c->device, need, &got)) != nullptr) {
+            c->work_cap = got;
+        } else {
+            if ((e = hipMalloc(&c->work, need)) != hipSuccess) {
+                (void)hipGetLastError();
+                pool_release(c->device);
+                if ((e = hipMalloc(&c->work, need)) != hipSuccess) {
+                    c->work = nullptr;
+                    return hipfail(c, e, "hipMalloc workspace");
+                }
+            }
+            c->work_cap = need;
         }
-        c->work_cap = need;
     }
     if ((e = hipHostMalloc((void **)&c->h_inst, ng * sizeof(InstDev), hipHostMallocDefault)) != hipSuccess) {
         c->h_inst = nullptr;
