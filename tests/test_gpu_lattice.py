@@ -177,30 +177,40 @@ def test_mixed_batch_equals_single(table):
             check(s, o, 64)
 
 
-def test_packed_and_full_kernel_rows_agree(table):
+@pytest.mark.parametrize("precision", [64, 32])
+def test_packed_and_full_kernel_rows_agree(table, precision):
     """General cells keep each shell's kernel rows as full 20 x 20 matrices
     unless a single grid uses the table and its full matrices would not fit
     in the 256 MB Infinity Cache; then the packed upper triangle (half the
-    bytes).  A 60^3 triclinic grid in FP64 (edges 18.0, 18.9, 16.8 bohr,
-    angles 78, 104, 66 degrees) has about 1.08e5 shells (330 MB as full
-    matrices): alone it takes packed rows, twice in a batch full rows.
-    Both against the oracle at the FP64 bars, and bitwise equal to each
-    other (the same FP64 row values, only loaded differently)."""
+    bytes).  FP64: a 60^3 triclinic grid (edges 18.0, 18.9, 16.8 bohr, angles
+    78, 104, 66 degrees) has about 1.08e5 shells (330 MB as full FP64
+    matrices); FP32: a 72^3 grid (edges 21.6, 22.7, 20.2 bohr) about 1.87e5
+    (285 MB as full FP32 matrices).  Alone each takes packed rows, twice in a
+    batch full rows.  Both against the oracle at the bars of the precision
+    (FP32 on the FP32-rounded input), and bitwise equal to each other (the
+    same row values, only loaded differently)."""
     from paper_0812_0244_amd import VdwNl
-    L, n = _lattice_density((60, 60, 60), seed=31, natoms=6, lengths=(18.0, 18.9, 16.8))
+    if precision == 64:
+        L, n = _lattice_density((60, 60, 60), seed=31, natoms=6, lengths=(18.0, 18.9, 16.8))
+        row_bytes = 3200
+    else:
+        L, n = _lattice_density((72, 72, 72), seed=32, natoms=8, lengths=(21.6, 22.7, 20.2))
+        n = n.astype(np.float32).astype(np.float64)
+        row_bytes = 1600
     nshell = len(np.unique(F.gmod_half(n.shape, L)))
-    say("  distinct |G| shells: %d (full FP64 matrices %.0f MB)" % (nshell, nshell * 3200 / 2 ** 20))
-    assert nshell * 3200 > 256 * 2 ** 20          # (the single-grid plan packs its rows)
+    say("  distinct |G| shells: %d (full matrices %.0f MB)" % (nshell, nshell * row_bytes / 2 ** 20))
+    assert nshell * row_bytes > 256 * 2 ** 20     # (the single-grid plan packs its rows)
     o = F.energy_potential(n, L, table, return_parts=True)
-    single = gpu_eval(n, L, table, 64)
-    check(single, o, 64)
+    single = gpu_eval(n, L, table, precision)
+    check(single, o, precision)
+    dt = torch.float64 if precision == 64 else torch.float32
     lib = VdwNl(0)
-    lib.set_grids([n.shape, n.shape], [L, L], 0, 64)
+    lib.set_grids([n.shape, n.shape], [L, L], 0, precision)
     lib.set_kernel_table(table["qmesh"], table["qc"], 12, table["dk"], table["phi"], table["c_soft"])
-    nt = [torch.from_numpy(n).to("cuda"), torch.from_numpy(n).to("cuda")]
+    nt = [torch.from_numpy(n).to("cuda", dt), torch.from_numpy(n).to("cuda", dt)]
     v = [torch.empty_like(x) for x in nt]
     E = lib.energy_potential_batched([x.data_ptr() for x in nt], [x.data_ptr() for x in v])
     for i in range(2):
         say("  batch member %d: E_k %.15e dE %.15e (single %.15e %.15e)" % (i, E[i, 0], E[i, 1], single["E_k"], single["dE"]))
         assert (E[i, 0], E[i, 1]) == (single["E_k"], single["dE"])
-        assert np.array_equal(v[i].cpu().numpy(), single["v"])
+        assert np.array_equal(v[i].double().cpu().numpy(), single["v"])
