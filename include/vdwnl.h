@@ -291,9 +291,11 @@ int vdwnl_set_graph(vdwnl_ctx *ctx, int32_t on);
 /* Schedule tuning for the planned grids: evaluates the batch (n_ptrs[nb],
  * v_ptrs[nb] as for vdwnl_energy_potential_batched; v is overwritten) once
  * plus `reps` timed times (1..100) for each candidate LDS budget (and, for
- * FP32 orthorhombic grids, each contraction unit) at radix order 0, keeps
+ * FP32 orthorhombic grids, each contraction unit) at radix order 0, the first
+ * candidate after some 300 ms of untimed evaluations so that the device's
+ * clocks have risen before any timing, keeps
  * the unit of the fused axis-1 pass with the least time over that pass, then
- * times every candidate budget at the radix orders 1..5 with that unit and
+ * times every candidate budget at every radix order (0..5) with that unit and
  * picks per pass group the (budget, order) pair with the least time over the
  * group's passes, plans with the choices and remembers them, keyed by the device
  * architecture, its LDS size,

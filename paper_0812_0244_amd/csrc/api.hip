@@ -3,6 +3,7 @@
 #include <unistd.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdlib>
 #include <cstdio>
@@ -1877,6 +1878,13 @@ int vdwnl_autotune(vdwnl_ctx *ctx, int32_t nb, const void *const *n_ptrs, void *
             free_device(ctx);
             ctx->timing = false;
             rc = run(ctx, nb, n_ptrs, v_ptrs, E.data(), stream);   // plans and warms up
+            // the first candidate: untimed evaluations for a few hundred
+            // milliseconds more (an idle device's clocks rise over its first
+            // work, which would favour the candidates timed later)
+            for (auto w0 = std::chrono::steady_clock::now();
+                 ui == 0 && ci == 0 && rc == VDWNL_OK &&
+                 std::chrono::steady_clock::now() - w0 < std::chrono::milliseconds(300);)
+                rc = run(ctx, nb, n_ptrs, v_ptrs, E.data(), stream);
             if (rc != VDWNL_OK) break;
             vdwnl_set_timing(ctx, 1);
             for (int r = 0; r < reps && rc == VDWNL_OK; ++r) rc = run(ctx, nb, n_ptrs, v_ptrs, E.data(), stream);
@@ -1910,17 +1918,16 @@ int vdwnl_autotune(vdwnl_ctx *ctx, int32_t nb, const void *const *n_ptrs, void *
     for (int gi = 0; gi < TG_COUNT; ++gi) ctx->pref[gi] = best[gi];
     // budgets and radix orders together, with the chosen unit: every group at
     // budget b and order v (each length class clamps v to its last variant)
-    // for v = 1 .. kMaxVariants - 1 and every candidate b (order 0: the
-    // measurements above), and per group the pair with the least time over
-    // the group's passes (a radix order changes the lanes per line, so the
-    // best tile width can move with it)
+    // for v = 0 .. kMaxVariants - 1 and every candidate b (order 0 timed
+    // again, so that the pairs compared come from one stretch of runs), and
+    // per group the pair with the least time over the group's passes (a
+    // radix order changes the lanes per line, so the best tile width can
+    // move with it)
     {
-        const size_t ub = std::find(units.begin(), units.end(), best_unit) - units.begin();
         // tv[v][candidate][pass kind]
         std::vector<std::vector<std::vector<double>>> tv(
             kMaxVariants, std::vector<std::vector<double>>(cand.size(), std::vector<double>(KIND_COUNT, 0.0)));
-        tv[0] = t[ub];
-        for (int v = 1; v < kMaxVariants && rc == VDWNL_OK; ++v)
+        for (int v = 0; v < kMaxVariants && rc == VDWNL_OK; ++v)
             for (size_t ci = 0; ci < cand.size() && rc == VDWNL_OK; ++ci) {
                 for (auto &x : ctx->variant) x = v;
                 for (auto &p : ctx->pref) p = cand[ci];
