@@ -542,8 +542,8 @@ def main():
     # ---- the other workloads as single grids: FP32 against FP64 plain
     singles = {}
     if args.single_legs:
-        for key, k in (("c2_96", 2), ("c3_dwnt", 3), ("c5_128", 5)):
-            wl = W.config(k)
+        for key, make in (("gauss96", W.gauss96), ("dwnt", W.dwnt_workload), ("gauss128", W.gauss128)):
+            wl = make()
             singles[key] = single_leg(wl.name, wl, table, args.steps, args.warmup, log)
 
     cpu = None

@@ -36,7 +36,7 @@ def _lib(table, insts, precision, graph=True):
 
 @pytest.mark.parametrize("precision,graph", [(32, True), (64, True), (32, False)])
 def test_async_equals_sync(table, precision, graph):
-    insts = [W.config(1)] + W.batch_instances(3)[:2]
+    insts = [W.gauss24()] + W.batch_instances(3)[:2]
     say("  async vs sync: %s precision=%d graph=%s" % ([w.shape for w in insts], precision, graph))
     dt = torch.float64 if precision == 64 else torch.float32
     n = [torch.from_numpy(w.density()).to("cuda", dt) for w in insts]
@@ -79,7 +79,7 @@ def test_async_calls_in_a_row(table):
 
 def test_async_semilocal_energies(table):
     from paper_0812_0244_amd.binding import FUNCTIONAL_VDW_DF
-    insts = [W.config(1)]
+    insts = [W.gauss24()]
     lib = _lib(table, insts, 64)
     lib.set_functional(FUNCTIONAL_VDW_DF)
     n = [torch.from_numpy(insts[0].density()).to("cuda")]

@@ -70,7 +70,7 @@ def check(g, o, precision):
 
 @pytest.mark.parametrize("m", [1, 2, 3, 4])
 def test_c1_fp64_fd_parity_with_intermediates(table, m):
-    wl = W.config(1)
+    wl = W.gauss24()
     n = wl.density()
     o = F.energy_potential(n, wl.cell, table, return_parts=True, grad_mode=m)
     g = gpu_eval(n, wl.cell, table, 64, m, debug=True)
@@ -97,7 +97,7 @@ def test_fp64_fd_parity_ragged_shapes(table, shape, cell, natoms, m):
 
 
 def test_c2_fd_fp64_and_fp32_parity(table):
-    wl = W.config(2)
+    wl = W.gauss96()
     n = wl.density()
     o = F.energy_potential(n, wl.cell, table, grad_mode=3, return_parts=True)
     check(gpu_eval(n, wl.cell, table, 64, 3), o, 64)
@@ -139,7 +139,7 @@ def test_fd_batched_equals_single_and_graph_replay(table):
 
 def test_fd_pass_order_and_timing(table):
     from paper_0812_0244_amd import VdwNl
-    wl = W.config(1)
+    wl = W.gauss24()
     lib = VdwNl(0)
     lib.set_grid(wl.shape, wl.cell, 2, 32)
     lib.set_kernel_table(table["qmesh"], table["qc"], 12, table["dk"], table["phi"], table["c_soft"])

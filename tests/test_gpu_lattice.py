@@ -142,7 +142,7 @@ def test_rotated_cell_same_result(table, m):
 
 @pytest.mark.parametrize("precision", [32, 64])
 def test_diagonal_lattice_equals_lengths_bitwise(table, precision):
-    wl = W.config(1)
+    wl = W.gauss24()
     n = wl.density()
     for m in (0, 3):
         a = gpu_eval(n, wl.cell, table, precision, m)
@@ -155,7 +155,7 @@ def test_mixed_batch_equals_single(table):
     from paper_0812_0244_amd import VdwNl
     L1, n1 = _lattice_density((20, 18, 24), seed=21)
     L2, n2 = _lattice_density((16, 20, 15), seed=22, angles=(70.0, 100.0, 120.0))
-    wl = W.config(1)
+    wl = W.gauss24()
     shapes = [n1.shape, wl.shape, n2.shape]
     cells = [L1, wl.cell, L2]
     dens = [n1, wl.density(), n2]

@@ -128,7 +128,7 @@ def test_two_long_axes(table):
 def test_differentiation_workload_128_cubed_against_oracle(table):
     """The 128^3 density of the differentiation workload (128 atoms) at full
     size, both precisions, against the oracle element by element."""
-    wl = W.config(5)
+    wl = W.gauss128()
     n = wl.density()
     say("  128^3, %d atoms" % len(wl.atoms.amp))
     compare(n, wl.cell, table, 64)

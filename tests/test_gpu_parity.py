@@ -76,7 +76,7 @@ def check(g, o, precision):
 
 
 def test_c1_fp64_parity_with_intermediates(table):
-    wl = W.config(1)
+    wl = W.gauss24()
     n = wl.density()
     o = F.energy_potential(n, wl.cell, table, return_parts=True)
     g = gpu_eval(n, wl.cell, table, 64, debug=True)
@@ -93,7 +93,7 @@ def fp32_input(n):
 
 
 def test_c1_fp32_parity(table):
-    wl = W.config(1)
+    wl = W.gauss24()
     n = fp32_input(wl.density())
     o = F.energy_potential(n, wl.cell, table, return_parts=True)
     check(gpu_eval(n, wl.cell, table, 32), o, 32)
@@ -116,7 +116,7 @@ def test_fp64_parity_ragged_shapes(table, shape, cell, natoms):
 
 
 def test_c2_fp64_and_fp32_parity(table):
-    wl = W.config(2)
+    wl = W.gauss96()
     n = wl.density()
     o = F.energy_potential(n, wl.cell, table, return_parts=True)
     check(gpu_eval(n, wl.cell, table, 64), o, 64)
@@ -172,7 +172,7 @@ def test_batched_equals_single(table):
 
 def test_repeat_runs_bitwise_identical(table):
     from paper_0812_0244_amd import NonlocalCorrelation
-    wl = W.config(1)
+    wl = W.gauss24()
     n = torch.from_numpy(wl.density()).to("cuda", torch.float32)
     eng = NonlocalCorrelation(n.shape, wl.cell, table, precision=32)
     ref = eng.energy_potential(n)
@@ -195,7 +195,7 @@ def test_uniform_density_on_node_gives_zero_on_gpu(table):
 
 def test_autograd_backward_is_dvol_times_v(table):
     from paper_0812_0244_amd import NonlocalCorrelation
-    wl = W.config(1)
+    wl = W.gauss24()
     eng = NonlocalCorrelation(wl.shape, wl.cell, table, precision=64)
     n = torch.from_numpy(wl.density()).to("cuda").requires_grad_(True)
     E = eng(n)
@@ -212,7 +212,7 @@ def test_contraction_units_agree_with_oracle(table):
     96^3 workload, a ragged non-cubic grid."""
     from paper_0812_0244_amd import VdwNl
     from paper_0812_0244_amd.binding import CONTRACTION_MATRIX, CONTRACTION_VECTOR, STAGE_U_K
-    cases = [(W.config(2).density(), W.config(2).cell, W.config(2).shape),
+    cases = [(W.gauss96().density(), W.gauss96().cell, W.gauss96().shape),
              (None, (8.0, 11.0, 7.5), (20, 30, 18))]
     for n, cell, shape in cases:
         if n is None:

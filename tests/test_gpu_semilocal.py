@@ -67,7 +67,7 @@ def check(g, o, precision):
 
 
 def test_c1_fp64_spectral_with_intermediates(table):
-    wl = W.config(1)
+    wl = W.gauss24()
     n = wl.density()
     o = F.xc_energy_potential(n, wl.cell, table, return_parts=True)
     g = gpu_xc(n, wl.cell, table, 64, debug=True)
@@ -77,7 +77,7 @@ def test_c1_fp64_spectral_with_intermediates(table):
 
 @pytest.mark.parametrize("m", [1, 3])
 def test_c1_fp64_finite_differences(table, m):
-    wl = W.config(1)
+    wl = W.gauss24()
     n = wl.density()
     o = F.xc_energy_potential(n, wl.cell, table, return_parts=True, grad_mode=m)
     check(gpu_xc(n, wl.cell, table, 64, m), o, 64)
@@ -94,7 +94,7 @@ def test_triclinic_fp64(table, shape, m):
 
 @pytest.mark.parametrize("m", [0, 3])
 def test_c2_fp32(table, m):
-    wl = W.config(2)
+    wl = W.gauss96()
     n32 = wl.density().astype(np.float32).astype(np.float64)
     o = F.xc_energy_potential(n32, wl.cell, table, return_parts=True, grad_mode=m)
     check(gpu_xc(n32, wl.cell, table, 32, m), o, 32)
@@ -120,7 +120,7 @@ def test_switching_the_functional(table, graph):
     evaluation of the whole functional."""
     from paper_0812_0244_amd import VdwNl, VdwNlError
     from paper_0812_0244_amd.binding import FUNCTIONAL_NONLOCAL, FUNCTIONAL_VDW_DF
-    wl = W.config(1)
+    wl = W.gauss24()
     lib = VdwNl(0)
     lib.set_grid(wl.shape, wl.cell, 0, 64)
     lib.set_kernel_table(table["qmesh"], table["qc"], 12, table["dk"], table["phi"], table["c_soft"])
@@ -151,7 +151,7 @@ def test_batch_equals_single(table):
     L = W.triclinic_lattice((8.0, 7.5, 8.5), (78.0, 104.0, 66.0))
     rng = np.random.default_rng(31)
     n_tri = W.density_on_lattice((20, 18, 24), L, W.random_atoms_lattice(rng, 3, L))
-    wl1, wl4 = W.config(1), W.batch_instances(3)[2]
+    wl1, wl4 = W.gauss24(), W.batch_instances(3)[2]
     dens = [wl1.density(), n_tri, wl4.density()]
     cells = [np.diag(wl1.cell), L, np.diag(wl4.cell)]
     for prec in (64, 32):
@@ -174,7 +174,7 @@ def test_batch_equals_single(table):
 
 def test_autograd_backward_is_dvol_v(table):
     from paper_0812_0244_amd import VdwDF
-    wl = W.config(1)
+    wl = W.gauss24()
     eng = VdwDF(wl.shape, wl.cell, table, precision=64, device=0)
     n = torch.from_numpy(wl.density()).to("cuda").requires_grad_(True)
     E = eng(n)
@@ -190,7 +190,7 @@ def test_tiny_density_floor(table, precision):
     (1/(k_F n^2) and the like) leave the FP32 range there unless ordered as
     (sigma/n)/n; v stays finite and meets the parity bars, with and without
     the semilocal terms."""
-    wl = W.config(1)
+    wl = W.gauss24()
     n = W.density_on_grid(wl.shape, wl.cell, wl.atoms, floor=1e-20)
     if precision == 32:
         n = n.astype(np.float32).astype(np.float64)

@@ -98,7 +98,7 @@ def check_against_oracle(g, o, precision, tag):
 
 @pytest.mark.parametrize("precision", [64, 32])
 def test_stages_c1(table, precision):
-    wl = W.config(1)
+    wl = W.gauss24()
     n = wl.density()
     if precision == 32:
         n = n.astype(np.float32).astype(np.float64)
@@ -124,7 +124,7 @@ def test_stages_batch_members(table, precision):
 
 
 def test_stages_finite_differences_and_triclinic(table):
-    wl = W.config(1)
+    wl = W.gauss24()
     n = wl.density()
     o = F.energy_potential(n, wl.cell, table, grad_mode=2, return_parts=True)
     check_against_oracle(stages([n], [wl.cell], table, 64, grad_mode=2)[0], o, 64, "24^3 m=2")

@@ -85,7 +85,7 @@ def test_evaluation_on_another_q_mesh():
     from paper_0812_0244_amd import NonlocalCorrelation
     t = dict(kt.kernel_table(q1=0.08, qc=4.0, lam=1.15))
     t["mc"] = 12
-    for wl in (W.config(1), W.batch_instances(3)[2]):
+    for wl in (W.gauss24(), W.batch_instances(3)[2]):
         n = wl.density()
         ek_o, de_o, v_o = F.energy_potential(n, wl.cell, t)
         eng = NonlocalCorrelation(wl.shape, wl.cell, t, precision=64)
@@ -100,7 +100,7 @@ def test_evaluation_on_another_q_mesh():
 def test_energy_with_either_table(gpu_table, table):
     import workloads as W
     from oracle import functional as F
-    wl = W.config(1)
+    wl = W.gauss24()
     n = wl.density()
     e1 = sum(F.energy_potential(n, wl.cell, table)[:2])
     e2 = sum(F.energy_potential(n, wl.cell, gpu_table)[:2])

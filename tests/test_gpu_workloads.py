@@ -101,7 +101,7 @@ def _directional_check(eng, n, cell, centre, dvol, eps=1e-4, width=1.5):
 
 
 def test_dwnt_workload(table):
-    wl = W.config(3)
+    wl = W.dwnt_workload()
     n = wl.density()
     say("  DWNT: %d atoms, %s grid" % (wl.meta["atoms"], wl.shape))
     e64eng = engine(wl.shape, wl.cell, table, 64)
@@ -132,7 +132,7 @@ def test_differentiation_workload_forces(table):
     """Forces F_A = -dE/dR_A through the torch density builder (autograd,
     backward = dOmega v) against central differences of FP64 energies with
     h = 1e-4 bohr; the FP32 path's forces against the FP64 ones."""
-    wl = W.config(5)
+    wl = W.gauss128()
     say("  %d atoms, %s grid" % (len(wl.atoms.amp), wl.shape))
     pos = torch.tensor(wl.atoms.pos, dtype=torch.float64, device="cuda")
     e64 = engine(wl.shape, wl.cell, table, 64)

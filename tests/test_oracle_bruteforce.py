@@ -61,7 +61,7 @@ def test_factorisation_accuracy_recorded(table):
 
 
 def _smooth_density(N, scale=0.01):
-    wl = W.config(1)
+    wl = W.gauss24()
     at = wl.atoms
     a2 = W.Atoms(pos=at.pos, amp=at.amp * scale, width=at.width)
     return W.density_on_grid((N, N, N), wl.cell, a2), wl.cell

@@ -117,7 +117,7 @@ def test_potential_is_gradient_of_energy_fd(table, m):
     h = 1e-3 n_i and 2h (the O(h^2) term cancels).  Most sampled points sit on
     the 1e-4 density floor, where a smaller step (1e-4 n_i) leaves a change of
     E only about 1e5 times its FP64 rounding."""
-    wl = W.config(1)
+    wl = W.gauss24()
     n = wl.density()
     cell = wl.cell
     dvol = np.prod(cell) / n.size
@@ -153,7 +153,7 @@ def test_stencils_approach_spectral_gradient(table):
     gs = F.gradient(f, cell)
     errs = [np.abs(F.gradient_fd(f, cell, m) - gs).max() for m in (1, 2, 3, 4)]
     assert all(b < 0.5 * a for a, b in zip(errs, errs[1:])), errs
-    wl = W.c1_coarse()
+    wl = W.gauss24_coarse()
     n = wl.density()
     e_s, de_s, v_s = F.energy_potential(n, wl.cell, table)
     gaps = []
@@ -164,6 +164,6 @@ def test_stencils_approach_spectral_gradient(table):
 
 
 def test_grad_mode_checked(table):
-    wl = W.c1_coarse()
+    wl = W.gauss24_coarse()
     with pytest.raises(ValueError):
         F.energy_potential(wl.density(), wl.cell, table, grad_mode=5)

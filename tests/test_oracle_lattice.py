@@ -97,7 +97,7 @@ def test_rotation_invariance(table, grad_mode):
 
 @pytest.mark.parametrize("grad_mode", [0, 3])
 def test_orthorhombic_lattice_equals_lengths(table, grad_mode):
-    wl = W.c1_coarse()
+    wl = W.gauss24_coarse()
     n = wl.density()
     a = F.energy_potential(n, wl.cell, table, grad_mode=grad_mode)
     b = F.energy_potential(n, np.diag(wl.cell), table, grad_mode=grad_mode)

@@ -97,7 +97,7 @@ def test_fft_energy_equals_direct_double_sum(table):
     """E = 1/2 dOmega^2 sum_ij sum_ab theta_ai theta_bj K_ab(r_i - r_j) (Eq. Eofni)
     with the band-limited periodic kernel K_ab(r) = (1/Omega) sum_{G in box}
     phi_ab(|G|) cos(G.r), summed directly (no FFT); likewise u (Eq. epsilon)."""
-    wl = W.c1_coarse()
+    wl = W.gauss24_coarse()
     n = wl.density()
     cell = wl.cell
     shape = n.shape
@@ -133,7 +133,7 @@ def test_fft_energy_equals_direct_double_sum(table):
 # ---------------------------------------------------------------- P11
 def test_potential_is_gradient_of_energy(table):
     """v_i = (1/dOmega) dE/dn_i (Eq. Vi) by central differences."""
-    wl = W.config(1)
+    wl = W.gauss24()
     n = wl.density()
     cell = wl.cell
     dvol = np.prod(cell) / n.size
@@ -152,7 +152,7 @@ def test_potential_is_gradient_of_energy(table):
 
 # ---------------------------------------------------------------- P12 / P13
 def test_translation_permutation_inversion(table):
-    wl = W.c1_coarse()
+    wl = W.gauss24_coarse()
     n = wl.density()
     cell = wl.cell
     e0, v0 = _evaluate(n, cell, table)
@@ -170,7 +170,7 @@ def test_translation_permutation_inversion(table):
 
 def test_parseval(table):
     """E_k in k space (Eq. Eoffk) = (dOmega/2) sum_i sum_a theta_ai u_ai in real space."""
-    wl = W.config(1)
+    wl = W.gauss24()
     n = wl.density()
     p = F.energy_potential(n, wl.cell, table, return_parts=True)
     dvol = np.prod(wl.cell) / n.size
@@ -179,7 +179,7 @@ def test_parseval(table):
 
 def test_low_density_points_are_excluded(table):
     """n < n_min: theta and its derivatives vanish there (design reading)."""
-    wl = W.c1_coarse()
+    wl = W.gauss24_coarse()
     n = wl.density()
     n[0, 0, :4] = 1e-40
     loc = F.theta_fields(n, F.gradient(n, wl.cell), table)

@@ -89,7 +89,7 @@ def test_exchange_uniform_scaling(table, grad_mode, triclinic):
         rng = np.random.default_rng(2)
         n = W.density_on_lattice((12, 10, 14), L, W.random_atoms_lattice(rng, 3, L))
     else:
-        wl = W.c1_coarse()
+        wl = W.gauss24_coarse()
         L, n = np.diag(wl.cell), wl.density()
     t = _zero_table(table)
     ex = F.xc_energy_potential(n, L, t, grad_mode=grad_mode)[2]
@@ -102,7 +102,7 @@ def test_exchange_uniform_scaling(table, grad_mode, triclinic):
 def test_semilocal_terms_add(table, grad_mode):
     """E_k and Delta E are those of the nonlocal evaluation, and v_xc - v_nl is
     the potential of the semilocal terms alone (a zero kernel table)."""
-    wl = W.c1_coarse()
+    wl = W.gauss24_coarse()
     n = wl.density()
     ek, de, v = F.energy_potential(n, wl.cell, table, grad_mode=grad_mode)
     ek2, de2, ex, ec, vxc = F.xc_energy_potential(n, wl.cell, table, grad_mode=grad_mode)
@@ -121,7 +121,7 @@ def test_xc_potential_is_gradient_of_energy(table, grad_mode, triclinic):
         rng = np.random.default_rng(6)
         n = W.density_on_lattice((14, 12, 16), L, W.random_atoms_lattice(rng, 3, L))
     else:
-        wl = W.c1_coarse()
+        wl = W.gauss24_coarse()
         L, n = np.diag(wl.cell), wl.density()
     dvol = F.volume(L) / n.size
 

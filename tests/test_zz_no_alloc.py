@@ -70,7 +70,7 @@ def test_noalloc_equals_energy_potential(table, precision):
 
 
 def test_noalloc_finite_differences_and_triclinic(table):
-    wl = W.config(1)
+    wl = W.gauss24()
     n = torch.from_numpy(wl.density()).cuda()
     _check(*_both(_context(wl.shape, wl.cell, table, 64, grad_mode=3), n), "24^3 m=3")
     lat = W.triclinic_lattice((7.0, 6.5, 8.0), (80.0, 100.0, 75.0))
@@ -93,7 +93,7 @@ def test_noalloc_triclinic_packs_rows_to_fit(table):
 
 
 def test_noalloc_allocates_no_device_memory(table):
-    wl = W.config(1)
+    wl = W.gauss24()
     n = torch.from_numpy(wl.density()).cuda()
     v = torch.empty_like(n)
     lib = _context(wl.shape, wl.cell, table, 64)

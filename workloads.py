@@ -211,24 +211,25 @@ def gaussian_workload(name, npts, length, natoms, seed) -> Workload:
     return Workload(name, (npts,) * 3, cell, random_atoms(rng, natoms, cell), seed=seed)
 
 
-def config(k: int) -> Workload:
-    """The workload of configuration k (1..5); k = 4 returns the first member."""
-    if k == 1:
-        return gaussian_workload("gauss4_24c_L10", 24, 10.0, 4, 1)
-    if k == 2:
-        return gaussian_workload("gauss64_96c_L20", 96, 20.0, 64, 2)
-    if k == 3:
-        return dwnt_workload()
-    if k == 4:
-        return batch_instances(1)[0]
-    if k == 5:
-        return gaussian_workload("gauss128_128c", 128, 128 * BATCH_SPACING, 128, 5)
-    raise ValueError("configs are 1..5")
+def gauss24() -> Workload:
+    """Four Gaussian atoms in a 10-bohr cube on a 24^3 grid (small enough for
+    the oracle to finish in seconds)."""
+    return gaussian_workload("gauss4_24c_L10", 24, 10.0, 4, 1)
 
 
-def c1_coarse() -> Workload:
-    """Configuration 1's density on the 12^3 grid (same atoms, same cell)."""
-    w = config(1)
+def gauss96() -> Workload:
+    """64 Gaussian atoms in a 20-bohr cube on a 96^3 grid."""
+    return gaussian_workload("gauss64_96c_L20", 96, 20.0, 64, 2)
+
+
+def gauss128() -> Workload:
+    """128 Gaussian atoms on a 128^3 grid at the batch's spacing (20/96 bohr)."""
+    return gaussian_workload("gauss128_128c", 128, 128 * BATCH_SPACING, 128, 5)
+
+
+def gauss24_coarse() -> Workload:
+    """The atoms and cell of gauss24() on a 12^3 grid."""
+    w = gauss24()
     return Workload("gauss4_12c_L10", (12, 12, 12), w.cell, w.atoms, seed=w.seed)
 
 
